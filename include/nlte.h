@@ -1,0 +1,214 @@
+/*
+ * nlte.h - C ABI of the MI355X library for the residual, Jacobian-vector
+ * product and Jacobian-free Newton-Krylov (JFNK) solve of multilevel NLTE
+ * statistical equilibrium in a plane-parallel atmosphere.
+ *
+ * The operations follow Arramy, de la Cruz Rodriguez & Leenaarts,
+ * "Jacobian-free Newton-Krylov method for multilevel nonlocal thermal
+ * equilibrium radiative transfer problems":
+ *   - the problem (atmosphere, model atom, frequency and angle grids): Sect. 2.1;
+ *   - the residual F(n): Algorithm 1 with Eqs. chi, eta (opacity/emissivity),
+ *     Iplus/Iminus (formal solution), Rij/Rji (rates), residuals_1/residuals_2;
+ *   - the Jacobian-vector product: Eq. fordif (forward difference);
+ *   - the block-Jacobi preconditioner: Sect. 2.5.2 (first solution), App. A.2;
+ *   - the solve: Algorithm 2 with the Krylov solver of Sect. 2.3 (GMRES) and the
+ *     damping and positivity safeguards of Sect. 2.2.2.
+ *
+ * Conventions
+ *   Units are CGS.  Depth index k = 0 is the top; z increases downwards.
+ *   Population-shaped arrays (n, F, v, Jv) are row-major [nz][nlev] doubles,
+ *   depth-major as in Sect. 2.1.1.  Mean intensities are [nz][nnu] doubles.
+ *   Transition t < nline are bound-bound lines, t >= nline bound-free edges.
+ *
+ *   Pointers named *_dev are device memory owned by the caller and used on
+ *   the given stream; outputs are valid once that stream has been
+ *   synchronised.  Descriptor arrays (host) are owned by the caller and are
+ *   deep-copied during nlte_column_create; they may be freed afterwards.
+ *
+ *   Every call returns an nlte_status and never throws; on failure
+ *   nlte_last_error() gives a message (thread-local).  Inputs are validated:
+ *   non-finite values, n_tot <= 0, T <= 0, non-monotonic z or nu, mu outside
+ *   (0, 1), windows outside the grid, level indices out of range.
+ */
+#ifndef NLTE_H
+#define NLTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NLTE_OK = 0,
+  NLTE_E_INVALID = -1,    /* bad argument or descriptor                        */
+  NLTE_E_NOMEM = -2,      /* device or host allocation failed                  */
+  NLTE_E_DEVICE = -3,     /* HIP runtime error                                 */
+  NLTE_E_NOCONV = -4,     /* solve stopped at maxiter; best iterate returned   */
+  NLTE_E_NONFINITE = -5,  /* NaN/Inf met in inputs or in the iteration         */
+  NLTE_E_BUSY = -6        /* request does not fit the server's memory budget   */
+} nlte_status;
+
+/* Precision of the formal solution and of the angle/frequency quadratures.
+ * Opacity assembly, rates, the residual, the rate-matrix solve and the
+ * finite-difference product are FP64 in both forms. */
+typedef enum { NLTE_FP64 = 0, NLTE_FP32_FORM = 1 } nlte_precision;
+
+typedef struct nlte_ctx nlte_ctx;
+typedef struct nlte_column nlte_column;
+typedef struct nlte_server nlte_server;
+
+/* Model atmosphere, Sect. 2.1.1 (Eqs. chi/eta background terms). */
+typedef struct {
+  int32_t nz;              /* depth points, >= 3                               */
+  const double *z;         /* [nz] cm, strictly increasing (downwards)          */
+  const double *T;         /* [nz] K                                            */
+  const double *ne;        /* [nz] electron density, cm^-3                      */
+  const double *ntot;      /* [nz] total density of the active atom, cm^-3      */
+  const double *chi_c;     /* [nz] gray background opacity, cm^-1; the
+                              background emissivity is chi_c B_nu(T)           */
+  const double *chi_sca;   /* [nz] background scattering opacity or NULL (0)   */
+} nlte_atmos_desc;
+
+/* Model atom, Sect. 2.1.1.  If nbf > 0 the last level is the continuum
+ * (stage 1) and every edge ends there. */
+typedef struct {
+  int32_t nlev;            /* levels incl. continuum, 2..16                     */
+  const double *E;         /* [nlev] erg                                        */
+  const double *g;         /* [nlev] statistical weights                        */
+  const int32_t *stage;    /* [nlev] 0 bound, 1 continuum                       */
+  int32_t nline;
+  const int32_t *line_lo;  /* [nline] lower level                               */
+  const int32_t *line_up;  /* [nline] upper level (> lower, bound)              */
+  const double *A_ul;      /* [nline] Einstein A, s^-1                          */
+  const double *a_damp;    /* [nline] Voigt damping parameter, 0 <= a <= 0.1    */
+  double mass_amu;         /* atomic mass for the Doppler width                 */
+  double vturb;            /* microturbulent velocity, cm/s                     */
+  int32_t nbf;
+  const int32_t *bf_lo;    /* [nbf] lower level of each edge                    */
+  const int32_t *bf_ptr;   /* [nbf+1] offsets into bf_nu / bf_alpha             */
+  const double *bf_nu;     /* tabulation frequencies of each edge, increasing   */
+  const double *bf_alpha;  /* photo-ionisation cross-section there, cm^2;
+                              linearly interpolated onto the union grid         */
+} nlte_atom_desc;
+
+/* Frequency and angle grids, Sect. 2.1.2. */
+typedef struct {
+  int32_t nnu;
+  const double *nu;        /* [nnu] Hz, strictly increasing union grid          */
+  const int32_t *win_lo;   /* [ntr] first grid index of each transition window  */
+  const int32_t *win_hi;   /* [ntr] one past the last index (>= win_lo + 2)     */
+  int32_t nmu;             /* 1..8 angles; two rays (+-mu) each                 */
+  const double *mu;        /* [nmu] Gauss-Legendre nodes on (0, 1)              */
+  const double *w_mu;      /* [nmu] weights, summing to 1                        */
+} nlte_grid_desc;
+
+typedef struct {
+  double ftol;         /* stop when max |F|/gross-rate <= ftol (default 1e-8)   */
+  double rtol;         /* Krylov relative tolerance (default 1e-3)              */
+  int32_t maxiter;     /* Newton iterations (default 50)                        */
+  int32_t max_krylov;  /* Krylov iterations per Newton iteration (default 200)  */
+  int32_t restart;     /* GMRES restart length m, 1..64 (default 30)            */
+  int32_t max_halvings;/* line-search halvings (default 8)                      */
+  int32_t init;        /* 0: n0 given, 1: LTE, 2: zero radiation                */
+  double eps_scale;    /* multiplies the difference step (default 1)            */
+} nlte_solve_opts;
+
+typedef struct {
+  int32_t status;        /* nlte_status of this column                          */
+  int32_t newton_iters;
+  int32_t krylov_iters;  /* total over the solve                                */
+  int32_t f_calls;       /* residual evaluations (formal solutions)             */
+  int32_t stalls;        /* line searches that found no decrease                */
+  double rho_inf;        /* final max |F|/gross rate                            */
+  double dn_inf;         /* last 0.5 max|(n - n_prev)/(n + n_prev)|             */
+} nlte_solve_stats;
+
+/* Fills opts with the defaults listed above. */
+void nlte_solve_opts_default(nlte_solve_opts *opts);
+
+/* Context bound to one HIP device (made current by every call that uses it). */
+nlte_status nlte_ctx_create(int hip_device, nlte_ctx **out);
+void nlte_ctx_destroy(nlte_ctx *ctx);
+
+/* Builds a column: validates and deep-copies the descriptors and runs the
+ * n-independent setup (Sect. 2.1.1: LTE populations, Planck function, Voigt
+ * profiles normalised on each line window, the unified transition
+ * coefficients V and g, collision rates in both directions by detailed
+ * balance, quadrature weights) on the device.  C_up is [nz][ntr] upward
+ * collision rates (lower -> upper), s^-1.  The column owns its device
+ * tables and solver state until nlte_column_destroy.  The lagged mean
+ * intensity J-dagger of Sect. 2.1.1 starts as B_nu(T). */
+nlte_status nlte_column_create(nlte_ctx *ctx, const nlte_atmos_desc *atmos,
+                               const nlte_atom_desc *atom, const nlte_grid_desc *grid,
+                               const double *C_up, nlte_precision precision,
+                               hipStream_t stream, nlte_column **out);
+void nlte_column_destroy(nlte_column *col);
+
+/* dims = {nz, nlev, ntr, nline, nbf, nnu, nmu, precision} */
+nlte_status nlte_column_dims(const nlte_column *col, int32_t dims[8]);
+
+/* LTE (Saha-Boltzmann) populations n* [nz][nlev] (Sect. 2.2.1 initial guess). */
+nlte_status nlte_lte_populations(nlte_column *col, double *n_dev, hipStream_t stream);
+
+/* Radiation-free populations (Sect. 2.2.1): per depth the rate equations with
+ * J = 0 and particle conservation. */
+nlte_status nlte_zero_radiation_populations(nlte_column *col, double *n_dev,
+                                            hipStream_t stream);
+
+/* Residual F(n) of Algorithm 1.
+ *   n_dev    [nz][nlev] populations (positive, finite);
+ *   F_dev    [nz][nlev] output;
+ *   J_dev    [nz][nnu] output mean intensity, or NULL;
+ *   R_dev    [nz][ntr][2] output radiative rates (R_lu, R_ul), or NULL;
+ *   Jbar_dev [nz][nline] output profile-averaged line intensity, or NULL;
+ *   P_dev    [nz][nlev][nlev] output block-Jacobi preconditioner (Sect. 2.5.2
+ *            first solution, conservation rows -1), or NULL (cheaper);
+ *   update_J nonzero: the computed J becomes the column's lagged J-dagger.
+ * The conservation row of each depth is the most populated level of n. */
+nlte_status nlte_residual(nlte_column *col, const double *n_dev, double *F_dev,
+                          double *J_dev, double *R_dev, double *Jbar_dev,
+                          double *P_dev, int update_J, hipStream_t stream);
+
+/* Forward-difference Jacobian-vector product (Eq. fordif):
+ * Jv = (F(n + eps v) - F(n)) / eps with the conservation rows and J-dagger
+ * of n.  Costs two residual evaluations (F(n) is recomputed). */
+nlte_status nlte_jvp(nlte_column *col, const double *n_dev, const double *v_dev,
+                     double eps, double *Jv_dev, hipStream_t stream);
+
+/* JFNK solve (Algorithm 2) of one column, entirely on the device.
+ *   n0_dev   [nz][nlev] initial populations when opts->init == 0 (else unused);
+ *   n_out_dev[nz][nlev] converged (or best) populations;
+ *   J_out_dev[nz][nnu] final mean intensity or NULL;
+ *   stats    host struct or NULL.
+ * Returns NLTE_E_NOCONV when maxiter is reached (n_out holds the last
+ * iterate).  Blocks until the solve has finished on `stream`. */
+nlte_status nlte_solve(nlte_column *col, const double *n0_dev, const nlte_solve_opts *opts,
+                       double *n_out_dev, double *J_out_dev, nlte_solve_stats *stats,
+                       hipStream_t stream);
+
+/* Solves ncol independent columns (any sizes, any precision) together: every
+ * step evaluates one residual per active column in the same launches, with
+ * per-column Krylov/Newton state on the device.  Arrays are indexed by
+ * column; n0_dev may be NULL when opts->init != 0; stats is [ncol] or NULL.
+ * Returns NLTE_OK if every column converged, else NLTE_E_NOCONV (per-column
+ * status in stats). */
+nlte_status nlte_solve_batch(nlte_ctx *ctx, nlte_column *const *cols, int32_t ncol,
+                             const double *const *n0_dev, const nlte_solve_opts *opts,
+                             double *const *n_out_dev, nlte_solve_stats *stats,
+                             hipStream_t stream);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char *nlte_last_error(void);
+
+/* Voigt function H(a, v) evaluated on the host with the same routine the
+ * device setup uses (Taylor expansion about the real axis with Rybicki's
+ * Dawson series for |v| < 8, asymptotic series beyond).  For tests. */
+nlte_status nlte_voigt_host(double a, const double *v, int32_t n, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NLTE_H */

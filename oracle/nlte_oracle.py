@@ -303,7 +303,7 @@ def residual(tb, n, Jdag=None, rows=None, want_P=False, I_override=None):
         Ip = Im = co = None
     R_lu, R_ul = rates_from_J(tb, J)
     F, G = assemble_F(tb, n, R_lu, R_ul, rows)
-    out = SimpleNamespace(F=F, rho=np.abs(F) / G, J=J, R_lu=R_lu, R_ul=R_ul,
+    out = SimpleNamespace(F=F, G=G, rho=np.abs(F) / G, J=J, R_lu=R_lu, R_ul=R_ul,
                           Jbar=mean_line_intensity(tb, J), rows=rows,
                           chi=chi, S=S)
     if want_P:

@@ -1,0 +1,745 @@
+// C ABI of the library: contexts, columns (validation, device layout and the
+// n-independent setup of Sect. 2.1.1), residual and Jacobian-vector product.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "nlte_internal.h"
+#include "voigt.h"
+
+using namespace nlte;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+nlte_status set_err(nlte_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+extern "C" const char* nlte_last_error(void) { return g_err.c_str(); }
+
+#define HIP_TRY(x)                                                                     \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      return set_err(NLTE_E_DEVICE, "%s failed: %s", #x, hipGetErrorString(e_));       \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// context and column objects
+// ---------------------------------------------------------------------------
+struct nlte_ctx {
+  int device;
+};
+
+struct nlte_column {
+  nlte_ctx* ctx = nullptr;
+  ColDev h{};                 // device pointers, host copy
+  ColDev* d = nullptr;        // device copy (one-element batch)
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  Tile* tiles = nullptr;      // device, chunk list with col = 0
+  int ntiles = 0;
+  int restart_cap = 0;
+  std::vector<double> Blu;    // host copy of line B_lu (profile-averaged J)
+  double* stage_buf = nullptr;
+};
+
+namespace nlte {
+hipError_t launch_residual(const ColDev* cols_dev, int ncol, const Tile* tiles_dev, int ntiles,
+                           int any_fp64, int any_fp32, int any_newton, int maxL, hipStream_t s);
+const ColDev& column_dev(const nlte_column* c) { return c->h; }
+ColDev* column_dev_ptr(const nlte_column* c) { return c->d; }
+int column_restart_cap(const nlte_column* c) { return c->restart_cap; }
+nlte_ctx* column_ctx(const nlte_column* c) { return c->ctx; }
+}  // namespace nlte
+
+extern "C" nlte_status nlte_ctx_create(int hip_device, nlte_ctx** out) {
+  if (!out) return set_err(NLTE_E_INVALID, "out is NULL");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (hip_device < 0 || hip_device >= ndev)
+    return set_err(NLTE_E_INVALID, "device %d out of range (%d devices)", hip_device, ndev);
+  HIP_TRY(hipSetDevice(hip_device));
+  *out = new nlte_ctx{hip_device};
+  return NLTE_OK;
+}
+
+extern "C" void nlte_ctx_destroy(nlte_ctx* ctx) { delete ctx; }
+
+extern "C" void nlte_solve_opts_default(nlte_solve_opts* o) {
+  if (!o) return;
+  o->ftol = 1e-8;
+  o->rtol = 1e-3;
+  o->maxiter = 50;
+  o->max_krylov = 200;
+  o->restart = 30;
+  o->max_halvings = 8;
+  o->init = 1;
+  o->eps_scale = 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// arena layout
+// ---------------------------------------------------------------------------
+namespace {
+struct Layout {
+  char* base;
+  size_t off = 0;
+  explicit Layout(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// raw inputs that only the setup kernels read
+struct SetupIn {
+  const double *E, *g, *A_ul, *a_damp, *bf_nu, *bf_alpha, *C_up;
+  const int *stage, *bf_ptr;
+  double mass_amu, vturb;
+};
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!isfinite(p[i])) return false;
+  return true;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// setup kernels (n-independent tables, Sect. 2.1.1)
+// ---------------------------------------------------------------------------
+// Per depth: LTE populations (Saha-Boltzmann), n*_l/n*_c of each edge,
+// downward collision rates by detailed balance, depth steps.
+__global__ void k_setup_depth(ColDev C, SetupIn in) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= C.nz) return;
+  const int L = C.L;
+  const double T = C.T[k];
+  const double saha = log(2.0 * pow(2.0 * kPi * kMe * kK * T / (kH * kH), 1.5) / C.ne[k]);
+  double lw[kMaxLev];
+  double mx = -1e300;
+  for (int i = 0; i < L; ++i) {
+    lw[i] = log(in.g[i]) - in.E[i] / (kK * T) + in.stage[i] * saha;
+    mx = fmax(mx, lw[i]);
+  }
+  double s = 0.0;
+  for (int i = 0; i < L; ++i) {
+    lw[i] = exp(lw[i] - mx);
+    s += lw[i];
+  }
+  double* ns = (double*)C.nstar + k * L;
+  for (int i = 0; i < L; ++i) ns[i] = C.ntot[k] * lw[i] / s;
+  for (int e = 0; e < C.nbf; ++e) {
+    const TrDev T_ = C.tr[C.nline + e];
+    ((double*)C.rho_bf)[k * C.nbf + e] = ns[T_.lo] / ns[T_.up];
+  }
+  for (int t = 0; t < C.ntr; ++t) {
+    const TrDev T_ = C.tr[t];
+    const double cu = in.C_up[k * C.ntr + t];
+    ((double*)C.C_lu)[k * C.ntr + t] = cu;
+    ((double*)C.C_ul)[k * C.ntr + t] = cu * ns[T_.lo] / ns[T_.up];
+  }
+  if (k + 1 < C.nz) ((double*)C.dz)[k] = fabs(C.z[k + 1] - C.z[k]);
+}
+
+// Per (k, f): Planck function, exp(-h nu/kT), and 2 h nu^3 / c^2.
+__global__ void k_setup_freq(ColDev C) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)C.nz * C.nnu) return;
+  const int k = (int)(i / C.nnu), f = (int)(i % C.nnu);
+  const double nu = C.nu[f];
+  const double x = kH * nu / (kK * C.T[k]);
+  const double gam = 2.0 * kH * nu * nu * nu / (kC * kC);
+  ((double*)C.Bnu)[i] = gam / expm1(x);
+  if (C.nbf) ((double*)C.Ebf)[i] = exp(-x);
+  if (k == 0) ((double*)C.gam)[f] = gam;
+  C.Jdag[i] = gam / expm1(x);
+}
+
+// Per (t, window point): rate weight 4 pi w/(h nu) with trapezoid weights
+// over the transition's own window; edges: cross-section interpolated
+// linearly onto the union grid (their V table).
+__global__ void k_setup_window(ColDev C, SetupIn in, const int* __restrict__ wbase, int wtotal) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= wtotal) return;
+  int t = 0;
+  while (t + 1 < C.ntr && wbase[t + 1] <= i) ++t;
+  const TrDev T = C.tr[t];
+  const int fl = i - wbase[t];
+  const int f = T.wlo + fl;
+  const int fm = max(f - 1, T.wlo), fp = min(f + 1, T.whi - 1);
+  const double w = 0.5 * (C.nu[fp] - C.nu[fm]);
+  ((double*)C.cw)[T.cwoff + fl] = 4.0 * kPi * w / (kH * C.nu[f]);
+  if (t >= C.nline) {
+    const int e = t - C.nline;
+    const int p0 = in.bf_ptr[e], p1 = in.bf_ptr[e + 1];
+    const double nu = C.nu[f];
+    double a;
+    if (nu <= in.bf_nu[p0]) a = in.bf_alpha[p0];
+    else if (nu >= in.bf_nu[p1 - 1]) a = in.bf_alpha[p1 - 1];
+    else {
+      int lo = p0, hi = p1 - 1;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (in.bf_nu[mid] <= nu) lo = mid; else hi = mid;
+      }
+      const double s = (nu - in.bf_nu[lo]) / (in.bf_nu[hi] - in.bf_nu[lo]);
+      a = in.bf_alpha[lo] + s * (in.bf_alpha[hi] - in.bf_alpha[lo]);
+    }
+    ((double*)C.V)[T.voff + fl] = a;
+  }
+}
+
+// Per (line, k, window point): raw Voigt profile value H(a, v).
+__global__ void k_setup_voigt(ColDev C, SetupIn in, const int* __restrict__ lbase, int ltotal) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)ltotal * C.nz) return;
+  const int k = (int)(i / ltotal);
+  const int j = (int)(i % ltotal);
+  int t = 0;
+  while (t + 1 < C.nline && lbase[t + 1] <= j) ++t;
+  const TrDev T = C.tr[t];
+  const int fl = j - lbase[t];
+  const int wl = T.whi - T.wlo;
+  const double nu0 = (in.E[T.up] - in.E[T.lo]) / kH;
+  const double dnuD = nu0 / kC * sqrt(2.0 * kK * C.T[k] / (in.mass_amu * kAmu) + in.vturb * in.vturb);
+  const double v = (C.nu[T.wlo + fl] - nu0) / dnuD;
+  ((double*)C.V)[T.voff + (size_t)k * wl + fl] = voigt_H(in.a_damp[t], v);
+}
+
+// Per (transition, k): profile normalisation on the window (lines),
+// V = (h nu / 4 pi) B_lu phi, and the n-independent part of R_ul:
+//   lines: sum_f cw V 2hnu^3/c^2;  edges: sum_f cw alpha exp(-h nu/kT) 2hnu^3/c^2.
+__global__ void k_setup_norm(ColDev C, SetupIn in) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= C.ntr * C.nz) return;
+  const int t = i / C.nz, k = i % C.nz;
+  const TrDev T = C.tr[t];
+  const int wl = T.whi - T.wlo;
+  double rsp = 0.0;
+  if (t < C.nline) {
+    double* phi = (double*)C.V + T.voff + (size_t)k * wl;
+    double s = 0.0;
+    for (int fl = 0; fl < wl; ++fl) {
+      const int f = T.wlo + fl;
+      const int fm = max(f - 1, T.wlo), fp = min(f + 1, T.whi - 1);
+      s += 0.5 * (C.nu[fp] - C.nu[fm]) * phi[fl];
+    }
+    for (int fl = 0; fl < wl; ++fl) {
+      const int f = T.wlo + fl;
+      const double V = kH * C.nu[f] / (4.0 * kPi) * T.Blu * (phi[fl] / s);
+      phi[fl] = V;
+      rsp += C.cw[T.cwoff + fl] * V * C.gam[f];
+    }
+  } else {
+    for (int fl = 0; fl < wl; ++fl) {
+      const int f = T.wlo + fl;
+      rsp += C.cw[T.cwoff + fl] * C.V[T.voff + fl] * C.Ebf[(size_t)k * C.nnu + f] * C.gam[f];
+    }
+  }
+  ((double*)C.Rsp)[k * C.ntr + t] = rsp;
+}
+
+// ---------------------------------------------------------------------------
+// column creation
+// ---------------------------------------------------------------------------
+static nlte_status validate(const nlte_atmos_desc* A, const nlte_atom_desc* M,
+                            const nlte_grid_desc* G, const double* C_up) {
+  if (!A || !M || !G || !C_up) return set_err(NLTE_E_INVALID, "NULL descriptor");
+  const int nz = A->nz, L = M->nlev, nnu = G->nnu, nmu = G->nmu;
+  if (nz < 3) return set_err(NLTE_E_INVALID, "nz = %d < 3", nz);
+  if (L < 2 || L > kMaxLev) return set_err(NLTE_E_INVALID, "nlev = %d outside 2..%d", L, kMaxLev);
+  if (nmu < 1 || nmu > kMaxMu) return set_err(NLTE_E_INVALID, "nmu = %d outside 1..%d", nmu, kMaxMu);
+  if (nnu < 2) return set_err(NLTE_E_INVALID, "nnu = %d < 2", nnu);
+  if (M->nline < 0 || M->nbf < 0 || M->nline + M->nbf < 1)
+    return set_err(NLTE_E_INVALID, "need at least one transition");
+  if (!A->z || !A->T || !A->ne || !A->ntot || !A->chi_c || !M->E || !M->g || !M->stage ||
+      !G->nu || !G->win_lo || !G->win_hi || !G->mu || !G->w_mu)
+    return set_err(NLTE_E_INVALID, "NULL array in descriptor");
+  const double* zs[] = {A->z, A->T, A->ne, A->ntot, A->chi_c};
+  for (auto p : zs)
+    if (!finite_all(p, nz)) return set_err(NLTE_E_NONFINITE, "non-finite atmosphere value");
+  if (A->chi_sca && !finite_all(A->chi_sca, nz)) return set_err(NLTE_E_NONFINITE, "non-finite chi_sca");
+  for (int k = 0; k < nz; ++k) {
+    if (A->ntot[k] <= 0) return set_err(NLTE_E_INVALID, "ntot[%d] <= 0", k);
+    if (A->T[k] <= 0) return set_err(NLTE_E_INVALID, "T[%d] <= 0", k);
+    if (A->ne[k] <= 0) return set_err(NLTE_E_INVALID, "ne[%d] <= 0", k);
+    if (A->chi_c[k] < 0 || (A->chi_sca && A->chi_sca[k] < 0))
+      return set_err(NLTE_E_INVALID, "negative background opacity at %d", k);
+    if (k + 1 < nz && !(A->z[k + 1] > A->z[k])) return set_err(NLTE_E_INVALID, "z not increasing at %d", k);
+  }
+  if (!finite_all(G->nu, nnu)) return set_err(NLTE_E_NONFINITE, "non-finite nu");
+  for (int f = 0; f + 1 < nnu; ++f)
+    if (!(G->nu[f + 1] > G->nu[f]) || G->nu[f] <= 0) return set_err(NLTE_E_INVALID, "nu not increasing at %d", f);
+  double ws = 0;
+  for (int m = 0; m < nmu; ++m) {
+    if (!(G->mu[m] > 0 && G->mu[m] < 1)) return set_err(NLTE_E_INVALID, "mu[%d] outside (0,1)", m);
+    if (!(G->w_mu[m] > 0)) return set_err(NLTE_E_INVALID, "w_mu[%d] <= 0", m);
+    ws += G->w_mu[m];
+  }
+  if (fabs(ws - 1.0) > 1e-10) return set_err(NLTE_E_INVALID, "angle weights sum to %g, not 1", ws);
+  if (!finite_all(M->E, L) || !finite_all(M->g, L)) return set_err(NLTE_E_NONFINITE, "non-finite level data");
+  int ncont = 0;
+  for (int i = 0; i < L; ++i) {
+    if (M->g[i] <= 0) return set_err(NLTE_E_INVALID, "g[%d] <= 0", i);
+    if (M->stage[i] != 0 && M->stage[i] != 1) return set_err(NLTE_E_INVALID, "stage[%d] not 0/1", i);
+    ncont += M->stage[i];
+  }
+  const int ntr = M->nline + M->nbf;
+  for (int t = 0; t < M->nline; ++t) {
+    const int lo = M->line_lo[t], up = M->line_up[t];
+    if (lo < 0 || up >= L || lo >= up || M->stage[lo] || M->stage[up])
+      return set_err(NLTE_E_INVALID, "line %d levels (%d,%d) invalid", t, lo, up);
+    if (!(M->E[up] > M->E[lo])) return set_err(NLTE_E_INVALID, "line %d has E_up <= E_lo", t);
+    if (!(M->A_ul[t] > 0) || !isfinite(M->A_ul[t])) return set_err(NLTE_E_INVALID, "A_ul[%d] invalid", t);
+    if (!(M->a_damp[t] >= 0 && M->a_damp[t] <= 0.1)) return set_err(NLTE_E_INVALID, "a_damp[%d] outside [0, 0.1]", t);
+  }
+  if (M->nline && !(M->mass_amu > 0)) return set_err(NLTE_E_INVALID, "mass_amu <= 0");
+  if (M->nbf) {
+    if (ncont != 1 || M->stage[L - 1] != 1)
+      return set_err(NLTE_E_INVALID, "edges need exactly one continuum level, the last");
+    for (int e = 0; e < M->nbf; ++e) {
+      const int lo = M->bf_lo[e];
+      if (lo < 0 || lo >= L - 1) return set_err(NLTE_E_INVALID, "edge %d lower level invalid", e);
+      const int p0 = M->bf_ptr[e], p1 = M->bf_ptr[e + 1];
+      if (p1 - p0 < 1 || p0 < 0) return set_err(NLTE_E_INVALID, "edge %d tabulation empty", e);
+      for (int p = p0; p < p1; ++p) {
+        if (!isfinite(M->bf_nu[p]) || !isfinite(M->bf_alpha[p]) || M->bf_alpha[p] < 0)
+          return set_err(NLTE_E_INVALID, "edge %d cross-section invalid", e);
+        if (p > p0 && !(M->bf_nu[p] > M->bf_nu[p - 1])) return set_err(NLTE_E_INVALID, "edge %d nu not increasing", e);
+      }
+    }
+  }
+  for (int t = 0; t < ntr; ++t) {
+    if (G->win_lo[t] < 0 || G->win_hi[t] > nnu || G->win_hi[t] - G->win_lo[t] < 2)
+      return set_err(NLTE_E_INVALID, "window of transition %d invalid", t);
+  }
+  if (!finite_all(C_up, (size_t)nz * ntr)) return set_err(NLTE_E_NONFINITE, "non-finite collision rate");
+  for (size_t i = 0; i < (size_t)nz * ntr; ++i)
+    if (C_up[i] < 0) return set_err(NLTE_E_INVALID, "negative collision rate");
+  return NLTE_OK;
+}
+
+static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, int nline_tab,
+                          int nbf_tot, int nentries, int m_cap, TrDev** tr_out, int** wbase,
+                          int** lbase, Tile** tiles, int** stage, int** bf_ptr, double** raw) {
+  const int nz = C.nz, L = C.L, ntr = C.ntr, nnu = C.nnu, N = C.N;
+  const size_t kf = (size_t)nz * nnu;
+  C.st = Lo.take<ColState>(1);
+  C.z = Lo.take<double>(nz);
+  C.dz = Lo.take<double>(nz);
+  C.T = Lo.take<double>(nz);
+  C.ne = Lo.take<double>(nz);
+  C.ntot = Lo.take<double>(nz);
+  C.chi_c = Lo.take<double>(nz);
+  C.chi_sca = Lo.take<double>(nz);
+  C.nu = Lo.take<double>(nnu);
+  C.gam = Lo.take<double>(nnu);
+  C.Bnu = Lo.take<double>(kf);
+  C.Ebf = C.nbf ? Lo.take<double>(kf) : nullptr;
+  *tr_out = Lo.take<TrDev>(ntr);
+  C.tr = *tr_out;
+  C.V = Lo.take<double>((size_t)nline_tab * nz + (nwin_total - nline_tab));
+  C.cw = Lo.take<double>(nwin_total);
+  C.rho_bf = Lo.take<double>((size_t)nz * std::max(C.nbf, 1));
+  C.Rsp = Lo.take<double>((size_t)nz * ntr);
+  C.C_lu = Lo.take<double>((size_t)nz * ntr);
+  C.C_ul = Lo.take<double>((size_t)nz * ntr);
+  C.nstar = Lo.take<double>((size_t)nz * L);
+  C.ch_ptr = Lo.take<int>(C.nchunk + 1);
+  C.ch_tr = Lo.take<int>(nentries);
+  C.ch_slot = Lo.take<int>(nentries);
+  C.eval_n = Lo.take<double>(N);
+  C.F = Lo.take<double>(N);
+  C.G = Lo.take<double>(N);
+  C.Jdag = Lo.take<double>(kf);
+  C.Jeval = Lo.take<double>(kf);
+  C.Jm = Lo.take<double>(kf);
+  C.Dchi = Lo.take<double>(kf);
+  C.Deta = Lo.take<double>(kf);
+  C.part = Lo.take<double>((size_t)C.nslot * nz * 2);
+  C.Ppart = Lo.take<double>((size_t)C.nchunk * nz * L * L);
+  C.P = Lo.take<double>((size_t)nz * L * L);
+  C.R = Lo.take<double>((size_t)nz * ntr * 2);
+  C.rho_k = Lo.take<double>(nz);
+  C.rows = Lo.take<int>(nz);
+  C.rows_frozen = Lo.take<int>(nz);
+  C.piv = Lo.take<int>((size_t)nz * L);
+  C.n = Lo.take<double>(N);
+  C.Fn = Lo.take<double>(N);
+  C.Vk = Lo.take<double>((size_t)(m_cap + 1) * N);
+  C.H = Lo.take<double>((size_t)(m_cap + 1) * m_cap);
+  C.cs = Lo.take<double>(m_cap + 1);
+  C.sn = Lo.take<double>(m_cap + 1);
+  C.gv = Lo.take<double>(m_cap + 1);
+  C.xk = Lo.take<double>(N);
+  C.w = Lo.take<double>(N);
+  C.lam = Lo.take<double>(nz);
+  C.dots = Lo.take<double>(2 * (m_cap + 1));
+  *wbase = Lo.take<int>(ntr + 1);
+  *lbase = Lo.take<int>(std::max(C.nline, 1) + 1);
+  *tiles = Lo.take<Tile>(C.nchunk);
+  *stage = Lo.take<int>(L);
+  *bf_ptr = Lo.take<int>(C.nbf + 1);
+  // raw setup inputs (doubles): E, g, A_ul, a_damp, bf_nu, bf_alpha, C_up
+  *raw = Lo.take<double>(2 * L + 2 * std::max(C.nline, 1) + 2 * std::max(nbf_tot, 1) + (size_t)nz * ntr);
+  (void)in;
+}
+
+extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* A,
+                                          const nlte_atom_desc* M, const nlte_grid_desc* G,
+                                          const double* C_up, nlte_precision prec,
+                                          hipStream_t stream, nlte_column** out) {
+  if (!ctx || !out) return set_err(NLTE_E_INVALID, "NULL ctx/out");
+  if (prec != NLTE_FP64 && prec != NLTE_FP32_FORM) return set_err(NLTE_E_INVALID, "bad precision");
+  nlte_status vs = validate(A, M, G, C_up);
+  if (vs != NLTE_OK) return vs;
+  HIP_TRY(hipSetDevice(ctx->device));
+
+  const int nz = A->nz, L = M->nlev, nline = M->nline, nbf = M->nbf, ntr = nline + nbf;
+  const int nnu = G->nnu, nmu = G->nmu;
+  ColDev C{};
+  C.nz = nz; C.L = L; C.ntr = ntr; C.nline = nline; C.nbf = nbf; C.nnu = nnu; C.nmu = nmu;
+  C.prec = prec; C.N = nz * L;
+  C.nchunk = (nnu + kWave - 1) / kWave;
+  C.has_sca = 0;
+  if (A->chi_sca)
+    for (int k = 0; k < nz; ++k)
+      if (A->chi_sca[k] != 0.0) C.has_sca = 1;
+  for (int m = 0; m < kMaxMu; ++m) {
+    C.wm2[m] = m < nmu ? 0.5 * G->w_mu[m] : 0.0;
+    C.inv2mu[m] = m < nmu ? 0.5 / G->mu[m] : 0.0;
+  }
+  // transitions, windows, chunk lists
+  std::vector<TrDev> tr(ntr);
+  std::vector<int> wbase(ntr + 1, 0), lbase(std::max(nline, 1) + 1, 0);
+  int nline_tab = 0, slot = 0;
+  std::vector<double> Blu(nline);
+  for (int t = 0; t < ntr; ++t) {
+    TrDev& T = tr[t];
+    T.lo = t < nline ? M->line_lo[t] : M->bf_lo[t - nline];
+    T.up = t < nline ? M->line_up[t] : L - 1;
+    T.wlo = G->win_lo[t];
+    T.whi = G->win_hi[t];
+    const int wl = T.whi - T.wlo;
+    wbase[t + 1] = wbase[t] + wl;
+    T.cwoff = wbase[t];
+    T.c0 = chunk_of(T.wlo);
+    T.slot = slot;
+    slot += chunk_of(T.whi - 1) - T.c0 + 1;
+    if (t < nline) {
+      const double nu0 = (M->E[T.up] - M->E[T.lo]) / kH;
+      const double Bul = M->A_ul[t] * kC * kC / (2.0 * kH * nu0 * nu0 * nu0);
+      T.Blu = M->g[T.up] / M->g[T.lo] * Bul;
+      T.g = M->g[T.lo] / M->g[T.up];
+      Blu[t] = T.Blu;
+      lbase[t + 1] = lbase[t] + wl;
+      nline_tab += wl;
+    } else {
+      T.Blu = 0;
+      T.g = 0;
+    }
+  }
+  // V offsets: line tables first ([nz][wl] each), then edge tables ([wl])
+  {
+    size_t off = 0;
+    for (int t = 0; t < nline; ++t) {
+      tr[t].voff = (int)off;
+      off += (size_t)nz * (tr[t].whi - tr[t].wlo);
+    }
+    for (int t = nline; t < ntr; ++t) {
+      tr[t].voff = (int)off;
+      off += tr[t].whi - tr[t].wlo;
+    }
+    if (off > 0x7fffffff) return set_err(NLTE_E_INVALID, "profile tables too large");
+  }
+  C.nslot = slot;
+  std::vector<int> ch_ptr(C.nchunk + 1, 0), ch_tr, ch_slot;
+  for (int c = 0; c < C.nchunk; ++c) {
+    const int f0 = c * kWave, f1 = std::min(nnu, f0 + kWave);
+    for (int t = 0; t < ntr; ++t) {
+      if (tr[t].wlo < f1 && tr[t].whi > f0) {
+        ch_tr.push_back(t);
+        ch_slot.push_back(tr[t].slot + (c - tr[t].c0));
+      }
+    }
+    ch_ptr[c + 1] = (int)ch_tr.size();
+  }
+  const int nentries = std::max<int>(1, (int)ch_tr.size());
+  int nbf_tot = nbf ? M->bf_ptr[nbf] : 0;
+  const int m_cap = 32;
+
+  // layout
+  SetupIn in{};
+  TrDev* tr_d;
+  int *wbase_d, *lbase_d, *stage_d, *bfptr_d;
+  Tile* tiles_d;
+  double* raw_d;
+  Layout sizer(nullptr);
+  {
+    ColDev tmp = C;
+    layout_column(sizer, tmp, in, wbase[ntr], nline_tab, nbf_tot, nentries, m_cap, &tr_d,
+                  &wbase_d, &lbase_d, &tiles_d, &stage_d, &bfptr_d, &raw_d);
+  }
+  nlte_column* col = new nlte_column();
+  col->ctx = ctx;
+  col->arena_bytes = sizer.off + 256;
+  hipError_t he = hipMalloc(&col->arena, col->arena_bytes);
+  if (he != hipSuccess) {
+    delete col;
+    return set_err(NLTE_E_NOMEM, "hipMalloc(%zu) failed: %s", sizer.off, hipGetErrorString(he));
+  }
+  Layout lay(col->arena);
+  layout_column(lay, C, in, wbase[ntr], nline_tab, nbf_tot, nentries, m_cap, &tr_d, &wbase_d,
+                &lbase_d, &tiles_d, &stage_d, &bfptr_d, &raw_d);
+  col->restart_cap = m_cap;
+  col->Blu = Blu;
+
+  // upload
+  auto up = [&](const void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!bytes) return hipSuccess;
+    return hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, stream);
+  };
+  std::vector<double> zeros(nz, 0.0);
+  std::vector<Tile> tiles(C.nchunk);
+  for (int c = 0; c < C.nchunk; ++c) tiles[c] = Tile{0, c};
+  double* rE = raw_d;
+  double* rg = rE + L;
+  double* rA = rg + L;
+  double* ra = rA + std::max(nline, 1);
+  double* rbn = ra + std::max(nline, 1);
+  double* rba = rbn + std::max(nbf_tot, 1);
+  double* rC = rba + std::max(nbf_tot, 1);
+  hipError_t e = hipSuccess;
+#define UP(d, s, b) if (e == hipSuccess) e = up(d, s, b)
+  UP(C.z, A->z, nz * 8);
+  UP(C.T, A->T, nz * 8);
+  UP(C.ne, A->ne, nz * 8);
+  UP(C.ntot, A->ntot, nz * 8);
+  UP(C.chi_c, A->chi_c, nz * 8);
+  UP(C.chi_sca, A->chi_sca ? A->chi_sca : zeros.data(), nz * 8);
+  UP(C.nu, G->nu, nnu * 8);
+  UP(tr_d, tr.data(), ntr * sizeof(TrDev));
+  UP(C.ch_ptr, ch_ptr.data(), ch_ptr.size() * 4);
+  UP(C.ch_tr, ch_tr.data(), ch_tr.size() * 4);
+  UP(C.ch_slot, ch_slot.data(), ch_slot.size() * 4);
+  UP(wbase_d, wbase.data(), wbase.size() * 4);
+  UP(lbase_d, lbase.data(), lbase.size() * 4);
+  UP(tiles_d, tiles.data(), tiles.size() * sizeof(Tile));
+  UP(stage_d, M->stage, L * 4);
+  if (nbf) UP(bfptr_d, M->bf_ptr, (nbf + 1) * 4);
+  UP(rE, M->E, L * 8);
+  UP(rg, M->g, L * 8);
+  if (nline) {
+    UP(rA, M->A_ul, nline * 8);
+    UP(ra, M->a_damp, nline * 8);
+  }
+  if (nbf_tot) {
+    UP(rbn, M->bf_nu, nbf_tot * 8);
+    UP(rba, M->bf_alpha, nbf_tot * 8);
+  }
+  UP(rC, C_up, (size_t)nz * ntr * 8);
+#undef UP
+  if (e == hipSuccess) e = hipMemsetAsync(C.st, 0, sizeof(ColState), stream);
+  if (e != hipSuccess) {
+    hipFree(col->arena);
+    delete col;
+    return set_err(NLTE_E_DEVICE, "upload failed: %s", hipGetErrorString(e));
+  }
+  in.E = rE; in.g = rg; in.A_ul = rA; in.a_damp = ra; in.bf_nu = rbn; in.bf_alpha = rba; in.C_up = rC;
+  in.stage = stage_d; in.bf_ptr = bfptr_d; in.mass_amu = M->mass_amu; in.vturb = M->vturb;
+
+  // setup kernels
+  k_setup_depth<<<(nz + 63) / 64, 64, 0, stream>>>(C, in);
+  {
+    const size_t n = (size_t)nz * nnu;
+    k_setup_freq<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C);
+  }
+  k_setup_window<<<(wbase[ntr] + 255) / 256, 256, 0, stream>>>(C, in, wbase_d, wbase[ntr]);
+  if (nline) {
+    const size_t n = (size_t)lbase[nline] * nz;
+    k_setup_voigt<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C, in, lbase_d, lbase[nline]);
+  }
+  k_setup_norm<<<(ntr * nz + 63) / 64, 64, 0, stream>>>(C, in);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMalloc(&col->d, sizeof(ColDev));
+  if (e == hipSuccess) e = hipMemcpyAsync(col->d, &C, sizeof(ColDev), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    if (col->d) hipFree(col->d);
+    hipFree(col->arena);
+    delete col;
+    return set_err(NLTE_E_DEVICE, "column setup failed: %s", hipGetErrorString(e));
+  }
+  col->h = C;
+  col->tiles = tiles_d;
+  col->ntiles = C.nchunk;
+  *out = col;
+  return NLTE_OK;
+}
+
+extern "C" void nlte_column_destroy(nlte_column* col) {
+  if (!col) return;
+  hipSetDevice(col->ctx->device);
+  if (col->d) hipFree(col->d);
+  if (col->arena) hipFree(col->arena);
+  delete col;
+}
+
+extern "C" nlte_status nlte_column_dims(const nlte_column* col, int32_t dims[8]) {
+  if (!col || !dims) return set_err(NLTE_E_INVALID, "NULL argument");
+  const ColDev& C = col->h;
+  dims[0] = C.nz; dims[1] = C.L; dims[2] = C.ntr; dims[3] = C.nline;
+  dims[4] = C.nbf; dims[5] = C.nnu; dims[6] = C.nmu; dims[7] = C.prec;
+  return NLTE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// small vector kernels for the API entry points
+// ---------------------------------------------------------------------------
+__global__ void k_axpy_into(double* __restrict__ y, const double* __restrict__ x,
+                            const double* __restrict__ v, double a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i] + a * v[i];
+}
+
+__global__ void k_diff_scaled(double* __restrict__ out, const double* __restrict__ F1,
+                              const double* __restrict__ F0, double inv_eps, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (F1[i] - F0[i]) * inv_eps;
+}
+
+__global__ void k_jbar(double* __restrict__ out, const double* __restrict__ R,
+                       const TrDev* __restrict__ tr, int nz, int ntr, int nline) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nz * nline) return;
+  const int k = i / nline, t = i % nline;
+  out[i] = R[((size_t)k * ntr + t) * 2] / tr[t].Blu;
+}
+
+__global__ void k_check_finite_pos(const double* __restrict__ n, int N, int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) {
+    const double v = n[i];
+    if (!(v > 0.0) || !isfinite(v)) atomicOr(flag, 1);
+  }
+}
+
+__global__ void k_set_eval(ColState* st, int mode, int want_J, int rows_own) {
+  st->mode = mode;
+  st->want_J = want_J;
+  st->rows_own = rows_own;
+}
+
+namespace nlte {
+hipError_t set_state_eval(nlte_column* col, int mode, int want_J, int rows_own, hipStream_t s) {
+  k_set_eval<<<1, 1, 0, s>>>(col->h.st, mode, want_J, rows_own);
+  return hipGetLastError();
+}
+}  // namespace nlte
+
+static nlte_status run_single(nlte_column* col, hipStream_t s) {
+  const ColDev& C = col->h;
+  HIP_TRY(launch_residual(col->d, 1, col->tiles, col->ntiles, C.prec == NLTE_FP64,
+                          C.prec == NLTE_FP32_FORM, 1, C.L, s));
+  return NLTE_OK;
+}
+
+static nlte_status check_populations(nlte_column* col, const double* n_dev, hipStream_t s) {
+  int* flag = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&flag, sizeof(int), s));
+  int h = 0;
+  hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
+  if (e == hipSuccess) {
+    k_check_finite_pos<<<(col->h.N + 255) / 256, 256, 0, s>>>(n_dev, col->h.N, flag);
+    e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFreeAsync(flag, s);
+  if (e != hipSuccess) return set_err(NLTE_E_DEVICE, "population check failed: %s", hipGetErrorString(e));
+  if (h) return set_err(NLTE_E_NONFINITE, "populations must be finite and positive");
+  return NLTE_OK;
+}
+
+extern "C" nlte_status nlte_lte_populations(nlte_column* col, double* n_dev, hipStream_t s) {
+  if (!col || !n_dev) return set_err(NLTE_E_INVALID, "NULL argument");
+  HIP_TRY(hipSetDevice(col->ctx->device));
+  HIP_TRY(hipMemcpyAsync(n_dev, col->h.nstar, col->h.N * 8, hipMemcpyDeviceToDevice, s));
+  return NLTE_OK;
+}
+
+extern "C" nlte_status nlte_residual(nlte_column* col, const double* n_dev, double* F_dev,
+                                     double* J_dev, double* R_dev, double* Jbar_dev,
+                                     double* P_dev, int update_J, hipStream_t s) {
+  if (!col || !n_dev || !F_dev) return set_err(NLTE_E_INVALID, "NULL argument");
+  HIP_TRY(hipSetDevice(col->ctx->device));
+  nlte_status st = check_populations(col, n_dev, s);
+  if (st != NLTE_OK) return st;
+  const ColDev& C = col->h;
+  const int newton = P_dev != nullptr;
+  const int wantJ = (J_dev != nullptr) || update_J;
+  HIP_TRY(hipMemcpyAsync(C.eval_n, n_dev, C.N * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(set_state_eval(col, newton ? kModeNewton : kModeF, wantJ, 1, s));
+  st = run_single(col, s);
+  if (st != NLTE_OK) return st;
+  HIP_TRY(hipMemcpyAsync(F_dev, C.F, C.N * 8, hipMemcpyDeviceToDevice, s));
+  const size_t kf = (size_t)C.nz * C.nnu * 8;
+  if (J_dev) HIP_TRY(hipMemcpyAsync(J_dev, C.Jeval, kf, hipMemcpyDeviceToDevice, s));
+  if (update_J) HIP_TRY(hipMemcpyAsync(C.Jdag, C.Jeval, kf, hipMemcpyDeviceToDevice, s));
+  if (R_dev) HIP_TRY(hipMemcpyAsync(R_dev, C.R, (size_t)C.nz * C.ntr * 16, hipMemcpyDeviceToDevice, s));
+  if (Jbar_dev && C.nline)
+    k_jbar<<<(C.nz * C.nline + 255) / 256, 256, 0, s>>>(Jbar_dev, C.R, C.tr, C.nz, C.ntr, C.nline);
+  if (P_dev) HIP_TRY(hipMemcpyAsync(P_dev, C.P, (size_t)C.nz * C.L * C.L * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(set_state_eval(col, kModeIdle, 0, 0, s));
+  HIP_TRY(hipGetLastError());
+  return NLTE_OK;
+}
+
+extern "C" nlte_status nlte_jvp(nlte_column* col, const double* n_dev, const double* v_dev,
+                                double eps, double* Jv_dev, hipStream_t s) {
+  if (!col || !n_dev || !v_dev || !Jv_dev) return set_err(NLTE_E_INVALID, "NULL argument");
+  if (!(eps != 0.0) || !isfinite(eps)) return set_err(NLTE_E_INVALID, "eps must be finite and nonzero");
+  HIP_TRY(hipSetDevice(col->ctx->device));
+  nlte_status st = check_populations(col, n_dev, s);
+  if (st != NLTE_OK) return st;
+  const ColDev& C = col->h;
+  // F(n) with its own rows, kept in Fn; rows frozen for the perturbed call
+  HIP_TRY(hipMemcpyAsync(C.eval_n, n_dev, C.N * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(set_state_eval(col, kModeF, 0, 1, s));
+  st = run_single(col, s);
+  if (st != NLTE_OK) return st;
+  HIP_TRY(hipMemcpyAsync(C.Fn, C.F, C.N * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(C.rows_frozen, C.rows, C.nz * 4, hipMemcpyDeviceToDevice, s));
+  k_axpy_into<<<(C.N + 255) / 256, 256, 0, s>>>(C.eval_n, n_dev, v_dev, eps, C.N);
+  HIP_TRY(set_state_eval(col, kModeF, 0, 0, s));
+  st = run_single(col, s);
+  if (st != NLTE_OK) return st;
+  k_diff_scaled<<<(C.N + 255) / 256, 256, 0, s>>>(Jv_dev, C.F, C.Fn, 1.0 / eps, C.N);
+  HIP_TRY(set_state_eval(col, kModeIdle, 0, 0, s));
+  HIP_TRY(hipGetLastError());
+  return NLTE_OK;
+}
+
+extern "C" nlte_status nlte_voigt_host(double a, const double* v, int32_t n, double* out) {
+  if (!v || !out || n < 0) return set_err(NLTE_E_INVALID, "NULL argument");
+  for (int i = 0; i < n; ++i) out[i] = voigt_H(a, v[i]);
+  return NLTE_OK;
+}

@@ -1,0 +1,284 @@
+"""Python binding of the C ABI in include/nlte.h (ctypes).
+
+Argument marshalling only: every step of the residual, the Jacobian-vector
+product and the solve runs in the HIP library.  Device memory and streams come
+from PyTorch tensors (``torch.float64`` on a HIP device).  The library must
+have been built (``python -m paper_2406_17234_amd.build``); loading fails
+loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnlte.so")
+
+NLTE_OK, NLTE_E_INVALID, NLTE_E_NOMEM, NLTE_E_DEVICE = 0, -1, -2, -3
+NLTE_E_NOCONV, NLTE_E_NONFINITE, NLTE_E_BUSY = -4, -5, -6
+FP64, FP32_FORM = 0, 1
+STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "DEVICE", -4: "NOCONV",
+                -5: "NONFINITE", -6: "BUSY"}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class NLTEError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class AtmosDesc(C.Structure):
+    _fields_ = [("nz", C.c_int32), ("z", _dp), ("T", _dp), ("ne", _dp), ("ntot", _dp),
+                ("chi_c", _dp), ("chi_sca", _dp)]
+
+
+class AtomDesc(C.Structure):
+    _fields_ = [("nlev", C.c_int32), ("E", _dp), ("g", _dp), ("stage", _ip),
+                ("nline", C.c_int32), ("line_lo", _ip), ("line_up", _ip), ("A_ul", _dp),
+                ("a_damp", _dp), ("mass_amu", C.c_double), ("vturb", C.c_double),
+                ("nbf", C.c_int32), ("bf_lo", _ip), ("bf_ptr", _ip), ("bf_nu", _dp),
+                ("bf_alpha", _dp)]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nnu", C.c_int32), ("nu", _dp), ("win_lo", _ip), ("win_hi", _ip),
+                ("nmu", C.c_int32), ("mu", _dp), ("w_mu", _dp)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("ftol", C.c_double), ("rtol", C.c_double), ("maxiter", C.c_int32),
+                ("max_krylov", C.c_int32), ("restart", C.c_int32),
+                ("max_halvings", C.c_int32), ("init", C.c_int32), ("eps_scale", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("newton_iters", C.c_int32),
+                ("krylov_iters", C.c_int32), ("f_calls", C.c_int32), ("stalls", C.c_int32),
+                ("rho_inf", C.c_double), ("dn_inf", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libnlte.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} missing: run `python -m paper_2406_17234_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.nlte_last_error.restype = C.c_char_p
+        L.nlte_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.nlte_ctx_destroy.argtypes = [vp]
+        L.nlte_ctx_destroy.restype = None
+        L.nlte_column_create.argtypes = [vp, C.POINTER(AtmosDesc), C.POINTER(AtomDesc),
+                                         C.POINTER(GridDesc), _dp, C.c_int, vp, C.POINTER(vp)]
+        L.nlte_column_destroy.argtypes = [vp]
+        L.nlte_column_destroy.restype = None
+        L.nlte_column_dims.argtypes = [vp, _ip]
+        L.nlte_lte_populations.argtypes = [vp, vp, vp]
+        L.nlte_zero_radiation_populations.argtypes = [vp, vp, vp]
+        L.nlte_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
+        L.nlte_jvp.argtypes = [vp, vp, vp, C.c_double, vp, vp]
+        L.nlte_solve.argtypes = [vp, vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveStats), vp]
+        L.nlte_solve_batch.argtypes = [vp, C.POINTER(vp), C.c_int32, C.POINTER(vp),
+                                       C.POINTER(SolveOpts), C.POINTER(vp),
+                                       C.POINTER(SolveStats), vp]
+        L.nlte_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
+        L.nlte_solve_opts_default.restype = None
+        L.nlte_voigt_host.argtypes = [C.c_double, _dp, C.c_int32, _dp]
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != NLTE_OK:
+        raise NLTEError(st, lib().nlte_last_error().decode())
+    return st
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_ip)
+
+
+def voigt_host(a, v):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.empty_like(v)
+    _check(lib().nlte_voigt_host(float(a), v.ctypes.data_as(_dp), v.size, out.ctypes.data_as(_dp)))
+    return out
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    lib().nlte_solve_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().nlte_ctx_create(device, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().nlte_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Column:
+    """One column: model atmosphere + model atom + grids (+ collision rates).
+
+    ``problem`` is any object with ``atom``, ``atmos``, ``grid`` and ``C_up``
+    attributes shaped like the synthetic generator's ``Problem``.
+    """
+
+    def __init__(self, ctx: Context, problem, precision: int = FP64, stream=None):
+        import torch
+        self.ctx = ctx
+        a, m, g = problem.atmos, problem.atom, problem.grid
+        keep = []
+
+        def D(x):
+            arr, p = _d(x)
+            keep.append(arr)
+            return p
+
+        def I(x):
+            arr, p = _i(x)
+            keep.append(arr)
+            return p
+
+        atm = AtmosDesc(len(a.z), D(a.z), D(a.T), D(a.ne), D(a.ntot), D(a.chi_c),
+                        D(a.chi_sca) if a.chi_sca is not None else None)
+        bf_ptr = np.concatenate([[0], np.cumsum([len(x) for x in g.bf_nu])]).astype(np.int32)
+        bf_nu = np.concatenate(g.bf_nu) if len(g.bf_nu) else np.zeros(1)
+        bf_al = np.concatenate(g.bf_alpha) if len(g.bf_alpha) else np.zeros(1)
+        atom = AtomDesc(m.nlev, D(m.E), D(m.g), I(m.stage), m.nline, I(m.line_lo), I(m.line_up),
+                        D(m.A_ul), D(m.a_damp), float(m.mass_amu), float(m.vturb), m.nbf,
+                        I(m.bf_lo), I(bf_ptr), D(bf_nu), D(bf_al))
+        grid = GridDesc(len(g.nu), D(g.nu), I(g.win_lo), I(g.win_hi), len(g.mu), D(g.mu), D(g.w_mu))
+        h = C.c_void_p()
+        torch.cuda.set_device(ctx.device)
+        _check(lib().nlte_column_create(ctx.h, C.byref(atm), C.byref(atom), C.byref(grid),
+                                        D(np.ascontiguousarray(problem.C_up)), int(precision),
+                                        _stream(stream), C.byref(h)))
+        self.h = h
+        dims = (C.c_int32 * 8)()
+        _check(lib().nlte_column_dims(h, dims))
+        self.nz, self.nlev, self.ntr, self.nline, self.nbf, self.nnu, self.nmu, self.precision = list(dims)
+        self.device = torch.device("cuda", ctx.device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nlte_column_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _empty(self, *shape):
+        import torch
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def lte(self, stream=None):
+        n = self._empty(self.nz, self.nlev)
+        _check(lib().nlte_lte_populations(self.h, _ptr(n), _stream(stream)))
+        return n
+
+    def zero_radiation(self, stream=None):
+        n = self._empty(self.nz, self.nlev)
+        _check(lib().nlte_zero_radiation_populations(self.h, _ptr(n), _stream(stream)))
+        return n
+
+    def residual(self, n, want_J=False, want_R=False, want_Jbar=False, want_P=False,
+                 update_J=False, stream=None):
+        n = n.contiguous()
+        out = {"F": self._empty(self.nz, self.nlev)}
+        if want_J:
+            out["J"] = self._empty(self.nz, self.nnu)
+        if want_R:
+            out["R"] = self._empty(self.nz, self.ntr, 2)
+        if want_Jbar:
+            out["Jbar"] = self._empty(self.nz, max(self.nline, 1))
+        if want_P:
+            out["P"] = self._empty(self.nz, self.nlev, self.nlev)
+        _check(lib().nlte_residual(self.h, _ptr(n), _ptr(out["F"]), _ptr(out.get("J")),
+                                   _ptr(out.get("R")), _ptr(out.get("Jbar")), _ptr(out.get("P")),
+                                   int(update_J), _stream(stream)))
+        return out
+
+    def jvp(self, n, v, eps, stream=None):
+        out = self._empty(self.nz, self.nlev)
+        _check(lib().nlte_jvp(self.h, _ptr(n.contiguous()), _ptr(v.contiguous()), float(eps),
+                              _ptr(out), _stream(stream)))
+        return out
+
+    def solve(self, n0=None, opts: SolveOpts | None = None, want_J=False, stream=None, **kw):
+        if opts is None:
+            opts = default_opts(**kw)
+        n = self._empty(self.nz, self.nlev)
+        J = self._empty(self.nz, self.nnu) if want_J else None
+        st = SolveStats()
+        rc = lib().nlte_solve(self.h, _ptr(n0), C.byref(opts), _ptr(n), _ptr(J), C.byref(st),
+                              _stream(stream))
+        if rc not in (NLTE_OK, NLTE_E_NOCONV):
+            _check(rc)
+        return n, J, st.as_dict(), rc
+
+
+def solve_batch(ctx: Context, columns, opts: SolveOpts | None = None, n0=None, stream=None, **kw):
+    """Solve many columns in shared launches; returns (list of n, stats list, status)."""
+    import torch
+    if opts is None:
+        opts = default_opts(**kw)
+    nc = len(columns)
+    outs = [torch.empty(c.nz, c.nlev, dtype=torch.float64, device=c.device) for c in columns]
+    cols = (C.c_void_p * nc)(*[c.h for c in columns])
+    outp = (C.c_void_p * nc)(*[o.data_ptr() for o in outs])
+    n0p = None
+    if n0 is not None:
+        n0p = (C.c_void_p * nc)(*[x.data_ptr() for x in n0])
+    stats = (SolveStats * nc)()
+    rc = lib().nlte_solve_batch(ctx.h, cols, nc, n0p, C.byref(opts), outp, stats, _stream(stream))
+    if rc not in (NLTE_OK, NLTE_E_NOCONV):
+        _check(rc)
+    return outs, [s.as_dict() for s in stats], rc

@@ -1,0 +1,52 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+declared in include/nlte.h, and its host Voigt routine (the one the device
+setup uses) matches the Faddeeva function to 1e-13."""
+import ctypes
+import os
+import re
+
+import numpy as np
+from scipy.special import wofz
+
+from paper_2406_17234_amd import nlte
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "nlte.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(nlte_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    lib = ctypes.CDLL(nlte.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 12
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_loads():
+    assert nlte.lib() is not None
+
+
+def test_voigt_matches_faddeeva():
+    v = np.linspace(-80, 80, 160001)
+    for a in [0.0, 1e-4, 1e-3, 1e-2, 0.1]:
+        h = nlte.voigt_host(a, v)
+        ref = wofz(v + 1j * a).real
+        m = ref > 1e-300
+        assert np.max(np.abs(h[m] / ref[m] - 1)) < 2e-13, a
+
+
+def test_invalid_device_is_reported():
+    ctx = ctypes.c_void_p()
+    st = nlte.lib().nlte_ctx_create(10_000, ctypes.byref(ctx))
+    assert st != 0
+    assert len(nlte.lib().nlte_last_error()) > 0
+
+
+def test_default_options():
+    o = nlte.default_opts()
+    assert o.ftol == 1e-8 and o.rtol == 1e-3 and o.restart == 30 and o.maxiter == 50
