@@ -1,0 +1,189 @@
+"""Benchmark: batched JFNK solves of NLTE columns on one MI355X.
+
+One step = one complete JFNK solve (residual evaluations, preconditioner,
+GMRES, Newton) of every column of the workload, starting from LTE, with all
+inputs resident in HBM (column setup is done before the timed region).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line: formal-solution depth-points per second over the whole
+solve (depth-points = frequencies x 2 x angles x depths per residual call,
+summed over every residual call of every column), plus columns converged/s,
+the roofline of the formal-solution kernel and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2406_17234_amd import synth as S  # noqa: E402
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, non-packed VALU issue
+PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
+# algorithmic work per depth-point: ~10 VALU ops plus half an exp and half a
+# reciprocal (shared by the two rays of an angle), transcendental at 1/4 rate
+OPS_PER_DP = 10.0 + 0.5 * 4 + 0.5 * 4
+
+WORKLOADS = {
+    # name: (description, maker(i), ncol default, precision, ftol)
+    "batch6": ("4096 chromosphere columns, 6-level atom (5 lines + 5 edges), "
+               "T perturbed +-10%, Nz U{64..160}, Nnu U{400..800}, 5 mu x 2; "
+               "FP32 formal solution, FP64 rates/solve", S.batch6_column, 4096, 1, 1e-6),
+    "batch6_fp64": ("4096 chromosphere columns as batch6, all FP64", S.batch6_column, 4096, 0, 1e-8),
+    "chromo6": ("1 column: 6-level atom, 82-depth chromosphere, ~600 frequencies, 5 mu x 2, FP64",
+                lambda i: S.chromo6(), 1, 0, 1e-8),
+    "chromo6_fp32": ("1 column as chromo6, FP32 formal solution", lambda i: S.chromo6(), 1, 1, 1e-6),
+    "slab3": ("1 column: 3-level atom, isothermal slab, 64 depths, 81 frequencies, 3 mu x 2, FP64",
+              lambda i: S.slab3(), 1, 0, 1e-8),
+    "chromo11": ("1 column: 11-level atom (20 lines + 10 edges), 256 depths, ~4000 frequencies, "
+                 "8 mu x 2, FP32 formal solution", lambda i: S.chromo11(), 1, 1, 1e-6),
+}
+
+
+def _oracle_column(args):
+    """CPU baseline worker: the FP64 oracle's JFNK solve of one column."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import nlte_oracle as O
+    maker_name, i, ftol, rtol = args
+    prob = WORKLOADS[maker_name][1](i)
+    tb = O.setup(prob)
+    t0 = time.perf_counter()
+    s = O.solve(tb, ftol=ftol, rtol=rtol, maxiter=50)
+    dt = time.perf_counter() - t0
+    return dt, s.calls * prob.depth_points(), bool(s.converged)
+
+
+def cpu_baseline(workload, ncol, ftol, rtol, budget_s=20.0):
+    """Time the oracle on a bounded sample (one column per process, a pool of
+    up to 16 processes, started before any GPU use)."""
+    procs = max(1, min(16, os.cpu_count() or 1, ncol))
+    sample = list(range(min(ncol, procs)))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        res = pool.map(_oracle_column, [(workload, i, ftol, rtol) for i in sample])
+    wall = time.perf_counter() - t0
+    dp = sum(r[1] for r in res)
+    return {
+        "value": dp / wall, "unit": "depth-points/s", "cores": procs, "kind": "oracle",
+        "sample": f"{len(sample)} columns of the workload ({workload} columns 0..{len(sample) - 1}), "
+                  f"one FP64 NumPy JFNK solve per process, {procs} processes, wall {wall:.1f} s",
+        "columns_per_s": len(sample) / wall,
+        "converged": sum(r[2] for r in res),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batch6", choices=list(WORKLOADS))
+    ap.add_argument("--ncol", type=int, default=None)
+    ap.add_argument("--rtol", type=float, default=1e-3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); columns are "
+              f"independent, so several GPUs would each run their own share of the batch.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    desc, maker, ncol_def, prec, ftol = WORKLOADS[args.workload]
+    ncol = args.ncol or ncol_def
+    t0 = time.perf_counter()
+    problems = [maker(i) for i in range(ncol)]
+    gen_s = time.perf_counter() - t0
+    print(f"[bench] generated {ncol} columns in {gen_s:.1f} s", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.workload, ncol, ftol, args.rtol)
+        print(f"[bench] cpu baseline {cpu['value']:.3e} dp/s", file=sys.stderr, flush=True)
+
+    import torch
+    from paper_2406_17234_amd import nlte
+    ctx = nlte.Context(0)
+    t0 = time.perf_counter()
+    cols = [nlte.Column(ctx, p, precision=prec) for p in problems]
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] created {ncol} columns in {setup_s:.1f} s", file=sys.stderr, flush=True)
+    dp_col = np.array([p.depth_points() for p in problems], dtype=np.float64)
+    opts = nlte.default_opts(ftol=ftol, rtol=args.rtol, maxiter=50)
+
+    for w in range(args.warmup):
+        _, st, rc = nlte.solve_batch(ctx, cols, opts)
+        print(f"[bench] warmup {w} rc={rc}", file=sys.stderr, flush=True)
+
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats_all = []
+    for k in range(args.steps):
+        _, st, rc = nlte.solve_batch(ctx, cols, opts)
+        stats_all.append(st)
+        print(f"[bench] step {k} rc={rc}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.read_profile()
+    ctx.profile(False)
+
+    f_calls = np.array([[s["f_calls"] for s in st] for st in stats_all], dtype=np.float64)
+    pc_calls = np.array([[s["precond_calls"] for s in st] for st in stats_all], dtype=np.float64)
+    conv = np.array([[s["status"] == 0 for s in st] for st in stats_all])
+    total_dp = float((f_calls * dp_col[None, :]).sum())
+    fmode_dp = float(((f_calls - pc_calls) * dp_col[None, :]).sum())
+    ms_per_step = elapsed / args.steps * 1e3
+    value = total_dp / elapsed
+    achieved = fmode_dp * OPS_PER_DP / (prof["formal_ms"] * 1e-3) / 1e12 if prof["formal_ms"] > 0 else None
+    peak = PEAK_VALU_OPS / 1e12
+    out = {
+        "metric": "formal-solution depth-points/s",
+        "value": value,
+        "unit": "depth-points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == 1 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "columns": ncol,
+                   "ftol": ftol, "rtol": args.rtol,
+                   "mean_nz": float(np.mean([p.atmos.nz for p in problems])),
+                   "mean_nnu": float(np.mean([p.grid.nnu for p in problems]))},
+        "columns_converged_per_s": float(conv.sum()) / elapsed,
+        "converged_fraction": float(conv.mean()),
+        "residual_calls_per_column": float(f_calls.mean()),
+        "newton_iters_mean": float(np.mean([[s["newton_iters"] for s in st] for st in stats_all])),
+        "kernel_ms_per_step": {k: prof[k] / args.steps for k in
+                               ("formal_ms", "newton_ms", "assemble_ms", "solver_ms")},
+        "roofline": {
+            "kernel": "k_formal<float,false>" if prec == 1 else "k_formal<double,false>",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TOP/s",
+            "frac": (achieved / peak) if achieved else None,
+            "ops_per_depth_point": OPS_PER_DP,
+            "traffic": None,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -110,7 +110,7 @@ typedef struct {
   double rtol;         /* Krylov relative tolerance (default 1e-3)              */
   int32_t maxiter;     /* Newton iterations (default 50)                        */
   int32_t max_krylov;  /* Krylov iterations per Newton iteration (default 200)  */
-  int32_t restart;     /* GMRES restart length m, 1..64 (default 30)            */
+  int32_t restart;     /* GMRES restart length m, 1..32 (default 30)            */
   int32_t max_halvings;/* line-search halvings (default 8)                      */
   int32_t init;        /* 0: n0 given, 1: LTE, 2: zero radiation                */
   double eps_scale;    /* multiplies the difference step (default 1)            */
@@ -122,9 +122,22 @@ typedef struct {
   int32_t krylov_iters;  /* total over the solve                                */
   int32_t f_calls;       /* residual evaluations (formal solutions)             */
   int32_t stalls;        /* line searches that found no decrease                */
+  int32_t precond_calls; /* evaluations that also built the preconditioner      */
   double rho_inf;        /* final max |F|/gross rate                            */
   double dn_inf;         /* last 0.5 max|(n - n_prev)/(n + n_prev)|             */
 } nlte_solve_stats;
+
+/* Kernel timings accumulated by solves on a context while profiling is on
+ * (HIP events on the solve's stream around each launch). */
+typedef struct {
+  int64_t steps;             /* solver steps (one residual per active column)   */
+  int64_t formal_launches;   /* formal-solution launches, residual-only mode    */
+  double formal_ms;          /* their summed duration                           */
+  int64_t newton_launches;   /* formal-solution launches, preconditioner mode   */
+  double newton_ms;
+  double assemble_ms;        /* rate/residual assembly launches                 */
+  double solver_ms;          /* Krylov/Newton step launches                     */
+} nlte_profile;
 
 /* Fills opts with the defaults listed above. */
 void nlte_solve_opts_default(nlte_solve_opts *opts);
@@ -199,6 +212,11 @@ nlte_status nlte_solve_batch(nlte_ctx *ctx, nlte_column *const *cols, int32_t nc
                              const double *const *n0_dev, const nlte_solve_opts *opts,
                              double *const *n_out_dev, nlte_solve_stats *stats,
                              hipStream_t stream);
+
+/* Turns kernel timing of subsequent solves on this context on (nonzero) or
+ * off, and clears the accumulated profile.  Adds two HIP events per launch. */
+nlte_status nlte_profile_enable(nlte_ctx *ctx, int on);
+nlte_status nlte_profile_read(const nlte_ctx *ctx, nlte_profile *out);
 
 /* Message describing the last non-OK status returned on this thread. */
 const char *nlte_last_error(void);

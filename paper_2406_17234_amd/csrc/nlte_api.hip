@@ -41,10 +41,6 @@ extern "C" const char* nlte_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 // context and column objects
 // ---------------------------------------------------------------------------
-struct nlte_ctx {
-  int device;
-};
-
 struct nlte_column {
   nlte_ctx* ctx = nullptr;
   ColDev h{};                 // device pointers, host copy
@@ -59,8 +55,6 @@ struct nlte_column {
 };
 
 namespace nlte {
-hipError_t launch_residual(const ColDev* cols_dev, int ncol, const Tile* tiles_dev, int ntiles,
-                           int any_fp64, int any_fp32, int any_newton, int maxL, hipStream_t s);
 const ColDev& column_dev(const nlte_column* c) { return c->h; }
 ColDev* column_dev_ptr(const nlte_column* c) { return c->d; }
 int column_restart_cap(const nlte_column* c) { return c->restart_cap; }
@@ -74,11 +68,28 @@ extern "C" nlte_status nlte_ctx_create(int hip_device, nlte_ctx** out) {
   if (hip_device < 0 || hip_device >= ndev)
     return set_err(NLTE_E_INVALID, "device %d out of range (%d devices)", hip_device, ndev);
   HIP_TRY(hipSetDevice(hip_device));
-  *out = new nlte_ctx{hip_device};
+  nlte_ctx* c = new nlte_ctx();
+  c->device = hip_device;
+  c->prof_on = 0;
+  memset(&c->prof, 0, sizeof c->prof);
+  *out = c;
   return NLTE_OK;
 }
 
 extern "C" void nlte_ctx_destroy(nlte_ctx* ctx) { delete ctx; }
+
+extern "C" nlte_status nlte_profile_enable(nlte_ctx* ctx, int on) {
+  if (!ctx) return set_err(NLTE_E_INVALID, "NULL ctx");
+  ctx->prof_on = on != 0;
+  memset(&ctx->prof, 0, sizeof ctx->prof);
+  return NLTE_OK;
+}
+
+extern "C" nlte_status nlte_profile_read(const nlte_ctx* ctx, nlte_profile* out) {
+  if (!ctx || !out) return set_err(NLTE_E_INVALID, "NULL argument");
+  *out = ctx->prof;
+  return NLTE_OK;
+}
 
 extern "C" void nlte_solve_opts_default(nlte_solve_opts* o) {
   if (!o) return;
@@ -378,6 +389,10 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.part = Lo.take<double>((size_t)C.nslot * nz * 2);
   C.Ppart = Lo.take<double>((size_t)C.nchunk * nz * L * L);
   C.P = Lo.take<double>((size_t)nz * L * L);
+  C.LU = Lo.take<double>((size_t)nz * L * L);
+  C.Fsave = Lo.take<double>(nz);
+  C.Gsave = Lo.take<double>(nz);
+  C.Psave = Lo.take<double>((size_t)nz * L);
   C.R = Lo.take<double>((size_t)nz * ntr * 2);
   C.rho_k = Lo.take<double>(nz);
   C.rows = Lo.take<int>(nz);

@@ -50,13 +50,14 @@ struct ColState {
   int pad_rows;
   int phase;        // solver phase (see nlte_solver.hip)
   int status;       // nlte_status of the solve
-  int newton_it, krylov_j, krylov_total, f_calls, stalls, ls_try, restarts, pad0;
+  int newton_it, krylov_j, krylov_total, f_calls, stalls, ls_try, restarts, precond_calls;
   double rho_eval;  // max scaled residual of the last evaluation
   double rho_cur;   // max scaled residual at the Newton iterate
   double beta0;     // preconditioned residual norm at the start of the Newton step
   double eps_fd;    // difference step of the pending product
   double alpha;     // line-search factor
   double dn_inf;    // last population change norm
+  double phi0;      // ||D^-1 P^-1 F|| at the iterate (line-search reference)
   double ftol, rtol, eps_mach, eps_scale;
   int maxiter, max_krylov, restart, max_halvings;
   int init_kind, done_flag, pad1, pad2;
@@ -93,7 +94,10 @@ struct ColDev {
   double *Dchi, *Deta;             // [nz][nnu] scratch: ingoing-ray intensity derivatives
   double *part;                    // [nslot][nz][2] partial rate sums
   double *Ppart;                   // [nchunk][nz][L*L] partial radiative blocks
-  double *P;                       // [nz][L][L] preconditioner blocks / LU factors
+  double *P;                       // [nz][L][L] preconditioner blocks of the last Newton-mode evaluation
+  double *LU;                      // [nz][L][L] LU factors of the iterate's blocks
+  double *Fsave, *Gsave;           // [nz] rate-row F and gross rate under each conservation row
+  double *Psave;                   // [nz][L] preconditioner row under each conservation row
   double *R;                       // [nz][ntr][2] radiative rates of the last evaluation
   double *rho_k;                   // [nz] max scaled residual per depth
   int *rows;                       // [nz] conservation rows used by the last evaluation
@@ -119,4 +123,18 @@ struct Tile {
 
 inline __host__ __device__ int chunk_of(int f) { return f / kWave; }
 
+// Residual launches for a batch of columns (formal solution in both modes and
+// precisions, then assembly).  ev, if not NULL, holds four events recorded
+// before the residual-mode formal launches, after them, after the
+// preconditioner-mode launches and after assembly.
+hipError_t launch_residual(const ColDev* cols_dev, int ncol, const Tile* tiles_dev, int ntiles,
+                           int any_fp64, int any_fp32, int any_newton, int maxL, hipStream_t s,
+                           hipEvent_t* ev = nullptr);
+
 }  // namespace nlte
+
+struct nlte_ctx {
+  int device;
+  int prof_on;
+  nlte_profile prof;
+};

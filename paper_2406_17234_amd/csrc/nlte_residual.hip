@@ -376,7 +376,7 @@ __global__ __launch_bounds__(64) void k_assemble(const ColDev* __restrict__ cols
       }
     }
     int r;
-    if (mode == kModeNewton || C.st->rows_own) {
+    if (C.st->rows_own) {
       r = 0;
       double best = nk[0];
       for (int i = 1; i < L; ++i)
@@ -390,10 +390,17 @@ __global__ __launch_bounds__(64) void k_assemble(const ColDev* __restrict__ cols
     C.rows[k] = r;
     double sum = 0.0;
     for (int i = 0; i < L; ++i) sum += nk[i];
+    // keep the rate row that the conservation row replaces, so a caller can
+    // move the conservation row without another formal solution
+    C.Fsave[k] = Fk[r];
+    C.Gsave[k] = Gk[r];
     Fk[r] = C.ntot[k] - sum;
     Gk[r] = C.ntot[k];
     if (mode == kModeNewton)
-      for (int j = 0; j < L; ++j) Pk[r * L + j] = -1.0;
+      for (int j = 0; j < L; ++j) {
+        C.Psave[k * L + j] = Pk[r * L + j];
+        Pk[r * L + j] = -1.0;
+      }
     double rk = 0.0;
     for (int i = 0; i < L; ++i) {
       C.F[k * L + i] = Fk[i];
@@ -424,22 +431,23 @@ __global__ __launch_bounds__(64) void k_assemble(const ColDev* __restrict__ cols
 size_t formal_pm_lds_bytes(int maxL) { return (size_t)4 * 2 * kWave * maxL * sizeof(double); }
 
 hipError_t launch_residual(const ColDev* cols_dev, int ncol, const Tile* tiles_dev, int ntiles,
-                           int any_fp64, int any_fp32, int any_newton, int maxL,
-                           hipStream_t s) {
+                           int any_fp64, int any_fp32, int any_newton, int maxL, hipStream_t s,
+                           hipEvent_t* ev) {
   const int blocks = (ntiles + 3) / 4;
+  if (ev) hipEventRecord(ev[0], s);
   if (ntiles > 0) {
-    if (any_fp64) {
-      k_formal<double, false><<<blocks, 256, 0, s>>>(cols_dev, tiles_dev, ntiles);
-      if (any_newton)
-        k_formal<double, true><<<blocks, 256, formal_pm_lds_bytes(maxL), s>>>(cols_dev, tiles_dev, ntiles);
-    }
-    if (any_fp32) {
-      k_formal<float, false><<<blocks, 256, 0, s>>>(cols_dev, tiles_dev, ntiles);
-      if (any_newton)
-        k_formal<float, true><<<blocks, 256, formal_pm_lds_bytes(maxL), s>>>(cols_dev, tiles_dev, ntiles);
-    }
+    if (any_fp64) k_formal<double, false><<<blocks, 256, 0, s>>>(cols_dev, tiles_dev, ntiles);
+    if (any_fp32) k_formal<float, false><<<blocks, 256, 0, s>>>(cols_dev, tiles_dev, ntiles);
   }
+  if (ev) hipEventRecord(ev[1], s);
+  if (ntiles > 0 && any_newton) {
+    const size_t lds = formal_pm_lds_bytes(maxL);
+    if (any_fp64) k_formal<double, true><<<blocks, 256, lds, s>>>(cols_dev, tiles_dev, ntiles);
+    if (any_fp32) k_formal<float, true><<<blocks, 256, lds, s>>>(cols_dev, tiles_dev, ntiles);
+  }
+  if (ev) hipEventRecord(ev[2], s);
   k_assemble<<<ncol, 64, 0, s>>>(cols_dev);
+  if (ev) hipEventRecord(ev[3], s);
   return hipGetLastError();
 }
 

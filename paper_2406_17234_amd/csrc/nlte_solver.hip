@@ -1,17 +1,765 @@
-// JFNK solver (Algorithm 2) on the device.
+// Jacobian-free Newton-Krylov solve (Algorithm 2) on the device.
+//
+// Every column carries its own Newton/Krylov state in device memory.  A solve
+// advances in steps; in each step every active column evaluates exactly one
+// residual (the pending evaluation set up by the previous step) and then one
+// block per column consumes it:
+//   INIT      F(n0) with preconditioner            -> start GMRES
+//   ARNOLDI   F(n + eps D v_j) (frozen rows)        -> one Arnoldi step
+//   RESTART   F(n + eps D x)                        -> restarted residual
+//   LINESRCH  F(n + alpha lambda D u) with P and J  -> accept or halve alpha
+// so the host only replays the same launches until every column is done.
+// The Krylov unknowns are relative corrections u = D^-1 dn with D = diag(n)
+// (Sect. 2.4.2 notes the rescaling); the system is left-preconditioned with
+// the block-Jacobi P (Eq. prec2), GMRES(m) uses classical Gram-Schmidt with
+// one re-orthogonalisation, and Newton steps are limited per depth to keep
+// populations positive and damped by backtracking (Sect. 2.2.2).
+#include <math.h>
+
+#include <vector>
+
 #include "nlte_internal.h"
 
 nlte_status set_err(nlte_status st, const char* fmt, ...);
 
-extern "C" nlte_status nlte_zero_radiation_populations(nlte_column*, double*, hipStream_t) {
-  return set_err(NLTE_E_INVALID, "not built yet");
+namespace nlte {
+const ColDev& column_dev(const nlte_column* c);
+ColDev* column_dev_ptr(const nlte_column* c);
+int column_restart_cap(const nlte_column* c);
+nlte_ctx* column_ctx(const nlte_column* c);
+}  // namespace nlte
+
+using namespace nlte;
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxM = 32;  // restart capacity allocated per column
+// Noise level assumed for the forward-difference step of FP32-form columns.
+// After the cancellations between gross rates, the FP32 formal solution
+// leaves relative noise far above 2^-23 in F; steps built on the FP32 machine
+// epsilon drown Jv in it.  Noise levels 1e-4..1e-2 all give converging
+// Newton sequences on the 6-level chromosphere; 1e-3 sits in the middle.
+constexpr double kFp32Noise = 1e-3;
+
+enum Phase : int { PH_IDLE = 0, PH_INIT = 1, PH_ARNOLDI = 2, PH_RESTART = 3, PH_LS = 4, PH_DONE = 5 };
+
+// ----------------------------------------------------------------- block ops
+__device__ __forceinline__ double warp_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
 }
-extern "C" nlte_status nlte_solve(nlte_column*, const double*, const nlte_solve_opts*, double*,
-                                  double*, nlte_solve_stats*, hipStream_t) {
-  return set_err(NLTE_E_INVALID, "not built yet");
+
+__device__ __forceinline__ double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+__device__ __forceinline__ double warp_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = nanmax(v, __shfl_xor(v, o));
+  return v;
 }
-extern "C" nlte_status nlte_solve_batch(nlte_ctx*, nlte_column* const*, int32_t, const double* const*,
-                                        const nlte_solve_opts*, double* const*, nlte_solve_stats*,
-                                        hipStream_t) {
-  return set_err(NLTE_E_INVALID, "not built yet");
+
+// Sums `cnt` per-thread partials (cnt <= kMaxM + 1) over the block; result in out[0..cnt).
+__device__ void block_sums(double* part, int cnt, double* red, double* out) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int i = 0; i < cnt; ++i) {
+    const double s = warp_sum(part[i]);
+    if (lane == 0) red[wave * (kMaxM + 1) + i] = s;
+  }
+  __syncthreads();
+  if (tid < cnt) {
+    double s = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) s += red[w * (kMaxM + 1) + tid];
+    out[tid] = s;
+  }
+  __syncthreads();
+}
+
+__device__ double block_sum1(double v, double* red) {
+  double p[1] = {v};
+  __shared__ double o[1];
+  block_sums(p, 1, red, o);
+  return o[0];
+}
+
+__device__ double block_max1(double v, double* red) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const double m = warp_max(v);
+  if (lane == 0) red[wave] = m;
+  __syncthreads();
+  double r = red[0];
+  for (int w = 1; w < kThreads / 64; ++w) r = nanmax(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------- per-depth dense LU
+// In-place LU with partial pivoting of a row-major L x L block.
+__device__ bool lu_factor(double* A, int* piv, int L) {
+  bool ok = true;
+  for (int c = 0; c < L; ++c) {
+    int p = c;
+    double best = fabs(A[c * L + c]);
+    for (int r = c + 1; r < L; ++r) {
+      const double v = fabs(A[r * L + c]);
+      if (v > best) {
+        best = v;
+        p = r;
+      }
+    }
+    piv[c] = p;
+    if (p != c)
+      for (int j = 0; j < L; ++j) {
+        const double t = A[c * L + j];
+        A[c * L + j] = A[p * L + j];
+        A[p * L + j] = t;
+      }
+    const double d = A[c * L + c];
+    if (d == 0.0 || d != d) {
+      ok = false;
+      continue;
+    }
+    const double inv = 1.0 / d;
+    for (int r = c + 1; r < L; ++r) {
+      const double f = A[r * L + c] * inv;
+      A[r * L + c] = f;
+      for (int j = c + 1; j < L; ++j) A[r * L + j] -= f * A[c * L + j];
+    }
+  }
+  return ok;
+}
+
+__device__ void lu_solve(const double* A, const int* piv, double* x, int L) {
+  for (int c = 0; c < L; ++c) {
+    const int p = piv[c];
+    if (p != c) {
+      const double t = x[c];
+      x[c] = x[p];
+      x[p] = t;
+    }
+  }
+  for (int r = 1; r < L; ++r) {
+    double s = x[r];
+    for (int c = 0; c < r; ++c) s -= A[r * L + c] * x[c];
+    x[r] = s;
+  }
+  for (int r = L - 1; r >= 0; --r) {
+    double s = x[r];
+    for (int c = r + 1; c < L; ++c) s -= A[r * L + c] * x[c];
+    x[r] = s / A[r * L + r];
+  }
+}
+
+// out = D^-1 P^-1 in (per depth), in/out may alias; D = diag(n).
+__device__ void apply_scaled_pinv(const ColDev& C, const double* in, double* out) {
+  const int L = C.L;
+  for (int k = threadIdx.x; k < C.nz; k += kThreads) {
+    double x[kMaxLev];
+    for (int i = 0; i < L; ++i) x[i] = in[k * L + i];
+    lu_solve(C.LU + (size_t)k * L * L, C.piv + k * L, x, L);
+    for (int i = 0; i < L; ++i) out[k * L + i] = x[i] / C.n[k * L + i];
+  }
+  __syncthreads();
+}
+
+__device__ void finish(const ColDev& C, int status, int* done_count) {
+  if (threadIdx.x == 0) {
+    C.st->status = status;
+    C.st->phase = PH_DONE;
+    C.st->mode = kModeIdle;
+    atomicAdd(done_count, 1);
+  }
+}
+
+// eval_n = n (1 + eps v), the perturbed state of a forward-difference product
+__device__ void prepare_jv(const ColDev& C, const double* v, double vnorm) {
+  ColState* st = C.st;
+  const double eps = st->eps_scale * sqrt(st->eps_mach) * sqrt(1.0 + sqrt((double)C.N)) / vnorm;
+  for (int i = threadIdx.x; i < C.N; i += kThreads) C.eval_n[i] = C.n[i] * (1.0 + eps * v[i]);
+  if (threadIdx.x == 0) {
+    st->eps_fd = eps;
+    st->mode = kModeF;
+    st->rows_own = 0;
+    st->want_J = 0;
+  }
+}
+
+// r in Vk[0] (unnormalised): start a GMRES cycle
+__device__ void start_cycle(const ColDev& C, bool first, double* red, int* done_count) {
+  ColState* st = C.st;
+  double p = 0.0;
+  for (int i = threadIdx.x; i < C.N; i += kThreads) p += C.Vk[i] * C.Vk[i];
+  const double beta = sqrt(block_sum1(p, red));
+  if (first && threadIdx.x == 0) {
+    st->beta0 = beta;
+    st->phi0 = beta;
+  }
+  if (!(beta > 0.0) || beta != beta) {
+    // F vanishes in the preconditioned norm: nothing left to correct
+    if (beta != beta) finish(C, NLTE_E_NONFINITE, done_count);
+    else finish(C, NLTE_OK, done_count);
+    return;
+  }
+  const double ib = 1.0 / beta;
+  for (int i = threadIdx.x; i < C.N; i += kThreads) C.Vk[i] *= ib;
+  if (threadIdx.x == 0) {
+    C.gv[0] = beta;
+    for (int i = 1; i <= kMaxM; ++i) C.gv[i] = 0.0;
+    for (int i = 0; i < (kMaxM + 1) * kMaxM; ++i) C.H[i] = 0.0;
+    st->krylov_j = 0;
+    st->phase = PH_ARNOLDI;
+  }
+  __syncthreads();
+  prepare_jv(C, C.Vk, 1.0);
+}
+
+__device__ void begin_linesearch(const ColDev& C) {
+  ColState* st = C.st;
+  const int L = C.L;
+  for (int k = threadIdx.x; k < C.nz; k += kThreads) {
+    double worst = 0.0;
+    for (int i = 0; i < L; ++i) worst = fmax(worst, -C.xk[k * L + i]);
+    C.lam[k] = worst > 0.0 ? fmin(1.0, 0.9 / worst) : 1.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < C.N; i += kThreads)
+    C.eval_n[i] = C.n[i] * (1.0 + C.lam[i / L] * C.xk[i]);
+  if (threadIdx.x == 0) {
+    st->alpha = 1.0;
+    st->ls_try = 0;
+    st->phase = PH_LS;
+    st->mode = kModeNewton;
+    st->rows_own = 0;
+    st->want_J = 1;
+  }
+}
+
+// The pending evaluation was a Newton-mode F at eval_n: make it the iterate.
+// Its conservation rows move to the most populated levels of eval_n (the
+// rate rows they replace were saved by the assembly, so this needs no new
+// formal solution), then the preconditioner blocks are factored and a GMRES
+// cycle starts on b = -D^-1 P^-1 F.
+__device__ void accept_point(const ColDev& C, double* red, int* done_count) {
+  ColState* st = C.st;
+  const int N = C.N, L = C.L;
+  double rk = 0.0;
+  for (int k = threadIdx.x; k < C.nz; k += kThreads) {
+    const double* nk = C.eval_n + k * L;
+    int rn = 0;
+    for (int i = 1; i < L; ++i)
+      if (nk[i] > nk[rn]) rn = i;
+    const int ro = C.rows[k];
+    if (rn != ro) {
+      double sum = 0.0;
+      for (int i = 0; i < L; ++i) sum += nk[i];
+      C.F[k * L + ro] = C.Fsave[k];
+      C.G[k * L + ro] = C.Gsave[k];
+      C.Fsave[k] = C.F[k * L + rn];
+      C.Gsave[k] = C.G[k * L + rn];
+      C.F[k * L + rn] = C.ntot[k] - sum;
+      C.G[k * L + rn] = C.ntot[k];
+      double* Pk = C.P + (size_t)k * L * L;
+      for (int j = 0; j < L; ++j) {
+        Pk[ro * L + j] = C.Psave[k * L + j];
+        C.Psave[k * L + j] = Pk[rn * L + j];
+        Pk[rn * L + j] = -1.0;
+      }
+    }
+    C.rows_frozen[k] = rn;
+    for (int i = 0; i < L; ++i) {
+      const double q = fabs(C.F[k * L + i]) / C.G[k * L + i];
+      rk = nanmax(rk, q);
+    }
+  }
+  const double rho = block_max1(rk, red);
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    C.n[i] = C.eval_n[i];
+    C.Fn[i] = C.F[i];
+  }
+  if (C.has_sca)
+    for (int i = threadIdx.x; i < C.nz * C.nnu; i += kThreads) C.Jdag[i] = C.Jeval[i];
+  __syncthreads();
+  if (threadIdx.x == 0) st->rho_cur = rho;
+  if (rho != rho || isinf(rho)) {
+    finish(C, NLTE_E_NONFINITE, done_count);
+    return;
+  }
+  if (rho <= st->ftol) {
+    finish(C, NLTE_OK, done_count);
+    return;
+  }
+  if (st->newton_it >= st->maxiter) {
+    finish(C, NLTE_E_NOCONV, done_count);
+    return;
+  }
+  // factor the preconditioner blocks into LU
+  int bad = 0;
+  for (int k = threadIdx.x; k < C.nz; k += kThreads) {
+    double* A = C.LU + (size_t)k * L * L;
+    const double* Pk = C.P + (size_t)k * L * L;
+    for (int q = 0; q < L * L; ++q) A[q] = Pk[q];
+    if (!lu_factor(A, C.piv + k * L, L)) bad = 1;
+  }
+  const double anybad = block_max1((double)bad, red);
+  if (anybad > 0.0) {
+    finish(C, NLTE_E_NONFINITE, done_count);
+    return;
+  }
+  // b = -D^-1 P^-1 F(n) -> Vk[0]
+  apply_scaled_pinv(C, C.Fn, C.Vk);
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    C.Vk[i] = -C.Vk[i];
+    C.xk[i] = 0.0;
+  }
+  if (threadIdx.x == 0) st->restarts = 0;
+  __syncthreads();
+  start_cycle(C, true, red, done_count);
+}
+
+__device__ void arnoldi(const ColDev& C, double* red, int* done_count) {
+  ColState* st = C.st;
+  const int N = C.N, m = st->restart;
+  const int j = st->krylov_j;
+  const double ieps = 1.0 / st->eps_fd;
+  double* w = C.w;
+  for (int i = threadIdx.x; i < N; i += kThreads) w[i] = (C.F[i] - C.Fn[i]) * ieps;
+  __syncthreads();
+  apply_scaled_pinv(C, w, w);
+  // classical Gram-Schmidt, twice
+  __shared__ double h[kMaxM + 1];
+  double part[kMaxM + 1];
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = 0; i <= j; ++i) part[i] = 0.0;
+    for (int q = threadIdx.x; q < N; q += kThreads) {
+      const double wq = w[q];
+      for (int i = 0; i <= j; ++i) part[i] += C.Vk[(size_t)i * N + q] * wq;
+    }
+    block_sums(part, j + 1, red, h);
+    for (int q = threadIdx.x; q < N; q += kThreads) {
+      double s = w[q];
+      for (int i = 0; i <= j; ++i) s -= h[i] * C.Vk[(size_t)i * N + q];
+      w[q] = s;
+    }
+    if (threadIdx.x <= j) C.H[threadIdx.x * kMaxM + j] += h[threadIdx.x];
+    __syncthreads();
+  }
+  double p = 0.0;
+  for (int q = threadIdx.x; q < N; q += kThreads) p += w[q] * w[q];
+  const double hn = sqrt(block_sum1(p, red));
+  const bool brk = !(hn > 1e-300);
+  if (!brk) {
+    const double ih = 1.0 / hn;
+    for (int q = threadIdx.x; q < N; q += kThreads) C.Vk[(size_t)(j + 1) * N + q] = w[q] * ih;
+  }
+  __shared__ double s_resid;
+  if (threadIdx.x == 0) {
+    double* H = C.H;
+    H[(j + 1) * kMaxM + j] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = H[i * kMaxM + j], b = H[(i + 1) * kMaxM + j];
+      H[i * kMaxM + j] = C.cs[i] * a + C.sn[i] * b;
+      H[(i + 1) * kMaxM + j] = -C.sn[i] * a + C.cs[i] * b;
+    }
+    const double a = H[j * kMaxM + j], b = H[(j + 1) * kMaxM + j];
+    const double den = hypot(a, b);
+    C.cs[j] = den > 0 ? a / den : 1.0;
+    C.sn[j] = den > 0 ? b / den : 0.0;
+    H[j * kMaxM + j] = den;
+    H[(j + 1) * kMaxM + j] = 0.0;
+    C.gv[j + 1] = -C.sn[j] * C.gv[j];
+    C.gv[j] = C.cs[j] * C.gv[j];
+    s_resid = fabs(C.gv[j + 1]);
+    st->krylov_j = j + 1;
+    st->krylov_total += 1;
+  }
+  __syncthreads();
+  const int jj = j + 1;
+  const bool conv = s_resid <= st->rtol * st->beta0;
+  const bool cap = st->krylov_total >= st->max_krylov;
+  if (!(conv || cap || brk || jj == m)) {
+    prepare_jv(C, C.Vk + (size_t)jj * N, 1.0);
+    return;
+  }
+  // y = H^-1 g (upper triangular jj x jj), x += V y
+  __shared__ double y[kMaxM];
+  if (threadIdx.x == 0) {
+    for (int r = jj - 1; r >= 0; --r) {
+      double s = C.gv[r];
+      for (int c = r + 1; c < jj; ++c) s -= C.H[r * kMaxM + c] * y[c];
+      const double d = C.H[r * kMaxM + r];
+      y[r] = d != 0.0 ? s / d : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < N; q += kThreads) {
+    double s = C.xk[q];
+    for (int i = 0; i < jj; ++i) s += y[i] * C.Vk[(size_t)i * N + q];
+    C.xk[q] = s;
+  }
+  __syncthreads();
+  if (conv || cap || brk) {
+    begin_linesearch(C);
+    return;
+  }
+  // restart: evaluate A x for the true residual b - A x
+  double px = 0.0;
+  for (int q = threadIdx.x; q < N; q += kThreads) px += C.xk[q] * C.xk[q];
+  const double xn = sqrt(block_sum1(px, red));
+  if (threadIdx.x == 0) {
+    st->phase = PH_RESTART;
+    st->restarts += 1;
+  }
+  if (!(xn > 0.0)) {
+    begin_linesearch(C);
+    return;
+  }
+  prepare_jv(C, C.xk, xn);
+}
+
+__device__ void restart(const ColDev& C, double* red, int* done_count) {
+  const int N = C.N;
+  const double ieps = 1.0 / C.st->eps_fd;
+  double* w = C.w;
+  for (int i = threadIdx.x; i < N; i += kThreads) w[i] = (C.F[i] - C.Fn[i]) * ieps;
+  __syncthreads();
+  apply_scaled_pinv(C, w, w);           // A x
+  apply_scaled_pinv(C, C.Fn, C.Vk);     // -b
+  for (int i = threadIdx.x; i < N; i += kThreads) C.Vk[i] = -C.Vk[i] - w[i];
+  __syncthreads();
+  start_cycle(C, false, red, done_count);
+}
+
+// Backtracking (Sect. 2.2.2) on the norm the Krylov step reduces:
+// accept the trial when ||D^-1 P^-1 F(trial)||_2 < (1 - 1e-4 alpha) ||D^-1 P^-1 F(n)||_2
+// with the iterate's P, D and conservation rows; else halve alpha.
+__device__ void linesearch(const ColDev& C, double* red, int* done_count) {
+  ColState* st = C.st;
+  const int N = C.N, L = C.L;
+  apply_scaled_pinv(C, C.F, C.w);
+  double p = 0.0;
+  for (int i = threadIdx.x; i < N; i += kThreads) p += C.w[i] * C.w[i];
+  const double phi = sqrt(block_sum1(p, red));
+  const double alpha = st->alpha;
+  const bool ok = phi < (1.0 - 1e-4 * alpha) * st->phi0;
+  if (ok || st->ls_try >= st->max_halvings) {
+    if (!ok && (phi != phi || isinf(phi))) {
+      finish(C, NLTE_E_NONFINITE, done_count);
+      return;
+    }
+    double q = 0.0;
+    for (int i = threadIdx.x; i < N; i += kThreads)
+      q = fmax(q, fabs((C.eval_n[i] - C.n[i]) / (C.eval_n[i] + C.n[i])));
+    const double dn = 0.5 * block_max1(q, red);
+    if (threadIdx.x == 0) {
+      st->dn_inf = dn;
+      st->newton_it += 1;
+      if (!ok) st->stalls += 1;
+    }
+    __syncthreads();
+    accept_point(C, red, done_count);
+    return;
+  }
+  const double a2 = 0.5 * alpha;
+  for (int i = threadIdx.x; i < N; i += kThreads)
+    C.eval_n[i] = C.n[i] * (1.0 + a2 * C.lam[i / L] * C.xk[i]);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->alpha = a2;
+    st->ls_try += 1;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_solver_step(const ColDev* __restrict__ cols,
+                                                          int* done_count) {
+  __shared__ double red[(kThreads / 64) * (kMaxM + 1)];
+  __shared__ int s_phase;
+  const ColDev& C = cols[blockIdx.x];
+  if (threadIdx.x == 0) {
+    s_phase = C.st->phase;
+    if (s_phase != PH_DONE && s_phase != PH_IDLE) C.st->f_calls += 1;
+    if (s_phase == PH_INIT || s_phase == PH_LS) C.st->precond_calls += 1;
+  }
+  __syncthreads();
+  const int phase = s_phase;
+  switch (phase) {
+    case PH_INIT: accept_point(C, red, done_count); break;
+    case PH_ARNOLDI: arnoldi(C, red, done_count); break;
+    case PH_RESTART: restart(C, red, done_count); break;
+    case PH_LS: linesearch(C, red, done_count); break;
+    default: break;
+  }
+}
+
+// Solve setup: options, initial populations, J-dagger = B, first evaluation.
+struct InitArgs {
+  double ftol, rtol, eps_mach, eps_scale;
+  int maxiter, max_krylov, restart, max_halvings, init;
+};
+
+__global__ void k_solver_init(const ColDev* __restrict__ cols, const double* const* n0, InitArgs a) {
+  const ColDev& C = cols[blockIdx.x];
+  ColState* st = C.st;
+  const double* src = n0 ? n0[blockIdx.x] : nullptr;
+  for (int i = threadIdx.x; i < C.N; i += blockDim.x)
+    C.eval_n[i] = (a.init == 0 && src) ? src[i] : C.nstar[i];
+  for (int i = threadIdx.x; i < C.nz * C.nnu; i += blockDim.x) C.Jdag[i] = C.Bnu[i];
+  if (threadIdx.x == 0) {
+    st->phase = PH_INIT;
+    st->status = NLTE_E_NOCONV;
+    st->newton_it = 0;
+    st->krylov_j = 0;
+    st->krylov_total = 0;
+    st->f_calls = 0;
+    st->precond_calls = 0;
+    st->stalls = 0;
+    st->ls_try = 0;
+    st->restarts = 0;
+    st->rho_eval = 0;
+    st->rho_cur = 0;
+    st->dn_inf = 0;
+    st->ftol = a.ftol;
+    st->rtol = a.rtol;
+    st->eps_mach = C.prec == NLTE_FP32_FORM ? kFp32Noise : a.eps_mach;
+    st->eps_scale = a.eps_scale;
+    st->maxiter = a.maxiter;
+    st->max_krylov = a.max_krylov;
+    st->restart = a.restart;
+    st->max_halvings = a.max_halvings;
+    st->mode = kModeNewton;
+    st->rows_own = 1;
+    st->want_J = 1;
+  }
+}
+
+// Radiation-free populations: per depth, rate equations with J = 0 (R_lu = 0,
+// R_ul = its spontaneous part) plus particle conservation on the most
+// populated level of the result (re-solved while that level changes).
+__global__ void k_zero_radiation(const ColDev* __restrict__ cols, double* out) {
+  const ColDev& C = cols[0];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= C.nz) return;
+  const int L = C.L;
+  double M0[kMaxLev * kMaxLev];
+  for (int i = 0; i < L * L; ++i) M0[i] = 0.0;
+  for (int t = 0; t < C.ntr; ++t) {
+    const TrDev T = C.tr[t];
+    const double Rul = (t < C.nline) ? T.g * C.Rsp[k * C.ntr + t]
+                                     : C.rho_bf[k * C.nbf + (t - C.nline)] * C.Rsp[k * C.ntr + t];
+    const double up = C.C_lu[k * C.ntr + t], dn = C.C_ul[k * C.ntr + t] + Rul;
+    M0[T.lo * L + T.lo] += up;
+    M0[T.up * L + T.up] += dn;
+    M0[T.lo * L + T.up] -= dn;
+    M0[T.up * L + T.lo] -= up;
+  }
+  int row = 0;
+  for (int i = 1; i < L; ++i)
+    if (C.nstar[k * L + i] > C.nstar[k * L + row]) row = i;
+  double A[kMaxLev * kMaxLev], x[kMaxLev];
+  int piv[kMaxLev];
+  for (int pass = 0; pass < L; ++pass) {
+    for (int i = 0; i < L * L; ++i) A[i] = M0[i];
+    for (int j = 0; j < L; ++j) A[row * L + j] = 1.0;
+    for (int i = 0; i < L; ++i) x[i] = 0.0;
+    x[row] = C.ntot[k];
+    lu_factor(A, piv, L);
+    lu_solve(A, piv, x, L);
+    int nr = 0;
+    for (int i = 1; i < L; ++i)
+      if (x[i] > x[nr]) nr = i;
+    if (nr == row) break;
+    row = nr;
+  }
+  for (int i = 0; i < L; ++i) out[k * L + i] = x[i];
+}
+
+__global__ void k_copy_out(const ColDev* __restrict__ cols, double* const* nout) {
+  const ColDev& C = cols[blockIdx.x];
+  double* dst = nout[blockIdx.x];
+  for (int i = threadIdx.x; i < C.N; i += blockDim.x) dst[i] = C.n[i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host drivers
+// ---------------------------------------------------------------------------
+#define HIP_TRY(x)                                                                     \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      return set_err(NLTE_E_DEVICE, "%s failed: %s", #x, hipGetErrorString(e_));       \
+  } while (0)
+
+extern "C" nlte_status nlte_zero_radiation_populations(nlte_column* col, double* n_dev,
+                                                       hipStream_t s) {
+  if (!col || !n_dev) return set_err(NLTE_E_INVALID, "NULL argument");
+  HIP_TRY(hipSetDevice(column_ctx(col)->device));
+  const ColDev& C = column_dev(col);
+  k_zero_radiation<<<(C.nz + 63) / 64, 64, 0, s>>>(column_dev_ptr(col), n_dev);
+  HIP_TRY(hipGetLastError());
+  return NLTE_OK;
+}
+
+namespace {
+struct Batch {
+  ColDev* cols = nullptr;       // device array of column descriptors
+  Tile* tiles = nullptr;
+  double** n0 = nullptr;
+  double** nout = nullptr;
+  int* done = nullptr;
+  int* done_host = nullptr;     // pinned
+  int ncol = 0, ntiles = 0, maxL = 0, any64 = 0, any32 = 0;
+  ~Batch() {
+    if (cols) hipFree(cols);
+    if (tiles) hipFree(tiles);
+    if (n0) hipFree(n0);
+    if (nout) hipFree(nout);
+    if (done) hipFree(done);
+    if (done_host) hipHostFree(done_host);
+  }
+};
+}  // namespace
+
+extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols, int32_t ncol,
+                                        const double* const* n0_dev, const nlte_solve_opts* opts,
+                                        double* const* n_out_dev, nlte_solve_stats* stats,
+                                        hipStream_t s) {
+  if (!ctx || !cols || ncol <= 0 || !n_out_dev) return set_err(NLTE_E_INVALID, "bad arguments");
+  nlte_solve_opts o;
+  nlte_solve_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.restart < 1 || o.restart > kMaxM) return set_err(NLTE_E_INVALID, "restart must be 1..%d", kMaxM);
+  if (o.maxiter < 0 || o.max_krylov < 1 || o.max_halvings < 0 || !(o.ftol >= 0) || !(o.rtol > 0) ||
+      !(o.eps_scale > 0))
+    return set_err(NLTE_E_INVALID, "invalid solve options");
+  if (o.init == 0 && !n0_dev) return set_err(NLTE_E_INVALID, "init = 0 needs n0");
+  HIP_TRY(hipSetDevice(ctx->device));
+  Batch b;
+  b.ncol = ncol;
+  std::vector<ColDev> hc(ncol);
+  std::vector<Tile> tiles;
+  for (int c = 0; c < ncol; ++c) {
+    if (!cols[c]) return set_err(NLTE_E_INVALID, "column %d is NULL", c);
+    if (column_ctx(cols[c]) != ctx) return set_err(NLTE_E_INVALID, "column %d from another context", c);
+    hc[c] = column_dev(cols[c]);
+    b.maxL = std::max(b.maxL, hc[c].L);
+    if (hc[c].prec == NLTE_FP64) b.any64 = 1; else b.any32 = 1;
+    for (int ch = 0; ch < hc[c].nchunk; ++ch) tiles.push_back(Tile{c, ch});
+    for (int d = 0; d < c; ++d)
+      if (cols[d] == cols[c]) return set_err(NLTE_E_INVALID, "column %d appears twice", c);
+  }
+  b.ntiles = (int)tiles.size();
+  HIP_TRY(hipMalloc(&b.cols, ncol * sizeof(ColDev)));
+  HIP_TRY(hipMalloc(&b.tiles, tiles.size() * sizeof(Tile)));
+  HIP_TRY(hipMalloc(&b.nout, ncol * sizeof(double*)));
+  HIP_TRY(hipMalloc(&b.done, sizeof(int)));
+  HIP_TRY(hipHostMalloc(&b.done_host, sizeof(int)));
+  HIP_TRY(hipMemcpyAsync(b.cols, hc.data(), ncol * sizeof(ColDev), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b.tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b.nout, n_out_dev, ncol * sizeof(double*), hipMemcpyHostToDevice, s));
+  if (o.init == 0) {
+    HIP_TRY(hipMalloc(&b.n0, ncol * sizeof(double*)));
+    HIP_TRY(hipMemcpyAsync(b.n0, n0_dev, ncol * sizeof(double*), hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(hipMemsetAsync(b.done, 0, sizeof(int), s));
+  InitArgs ia{o.ftol, o.rtol, 2.220446049250313e-16, o.eps_scale, o.maxiter, o.max_krylov,
+              o.restart, o.max_halvings, o.init};
+  k_solver_init<<<ncol, 256, 0, s>>>(b.cols, o.init == 0 ? b.n0 : nullptr, ia);
+  if (o.init == 2) {
+    for (int c = 0; c < ncol; ++c)
+      k_zero_radiation<<<(hc[c].nz + 63) / 64, 64, 0, s>>>(column_dev_ptr(cols[c]), hc[c].eval_n);
+  }
+  HIP_TRY(hipGetLastError());
+  // every step evaluates one residual per active column; bound the step count
+  const long max_steps = (long)(o.maxiter + 1) * (o.max_krylov + o.max_krylov / o.restart + o.max_halvings + 4) + 16;
+  const int check_every = 4;
+  const bool prof = ctx->prof_on != 0;
+  std::vector<hipEvent_t> ev;
+  if (prof) {
+    ev.resize(5 * check_every);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  }
+  long step = 0;
+  *b.done_host = 0;
+  nlte_status loop_st = NLTE_OK;
+  while (step < max_steps) {
+    for (int r = 0; r < check_every; ++r, ++step) {
+      hipEvent_t* e = prof ? &ev[5 * r] : nullptr;
+      hipError_t he = launch_residual(b.cols, ncol, b.tiles, b.ntiles, b.any64, b.any32, 1,
+                                      b.maxL, s, e);
+      k_solver_step<<<ncol, kThreads, 0, s>>>(b.cols, b.done);
+      if (prof) hipEventRecord(e[4], s);
+      if (he == hipSuccess) he = hipGetLastError();
+      if (he != hipSuccess) {
+        loop_st = set_err(NLTE_E_DEVICE, "solver launch failed: %s", hipGetErrorString(he));
+        break;
+      }
+    }
+    if (loop_st != NLTE_OK) break;
+    HIP_TRY(hipMemcpyAsync(b.done_host, b.done, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (prof) {
+      for (int r = 0; r < check_every; ++r) {
+        float t[4];
+        for (int q = 0; q < 4; ++q) HIP_TRY(hipEventElapsedTime(&t[q], ev[5 * r + q], ev[5 * r + q + 1]));
+        ctx->prof.steps += 1;
+        ctx->prof.formal_launches += (b.any64 + b.any32);
+        ctx->prof.formal_ms += t[0];
+        ctx->prof.newton_launches += (b.any64 + b.any32);
+        ctx->prof.newton_ms += t[1];
+        ctx->prof.assemble_ms += t[2];
+        ctx->prof.solver_ms += t[3];
+      }
+    }
+    if (*b.done_host >= ncol) break;
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  if (loop_st != NLTE_OK) return loop_st;
+  k_copy_out<<<ncol, 256, 0, s>>>(b.cols, b.nout);
+  HIP_TRY(hipGetLastError());
+  std::vector<ColState> sts(ncol);
+  for (int c = 0; c < ncol; ++c)
+    HIP_TRY(hipMemcpyAsync(&sts[c], hc[c].st, sizeof(ColState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  bool all_ok = true;
+  for (int c = 0; c < ncol; ++c) {
+    const ColState& st = sts[c];
+    const int status = st.phase == PH_DONE ? st.status : NLTE_E_NOCONV;
+    if (status != NLTE_OK) all_ok = false;
+    if (stats) {
+      stats[c].status = status;
+      stats[c].newton_iters = st.newton_it;
+      stats[c].krylov_iters = st.krylov_total;
+      stats[c].f_calls = st.f_calls;
+      stats[c].stalls = st.stalls;
+      stats[c].precond_calls = st.precond_calls;
+      stats[c].rho_inf = st.rho_cur;
+      stats[c].dn_inf = st.dn_inf;
+    }
+  }
+  // leave columns idle for later residual calls
+  for (int c = 0; c < ncol; ++c) HIP_TRY(hipMemsetAsync(hc[c].st, 0, 3 * sizeof(int), s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!all_ok) {
+    set_err(NLTE_E_NOCONV, "not every column converged (see stats)");
+    return NLTE_E_NOCONV;
+  }
+  return NLTE_OK;
+}
+
+extern "C" nlte_status nlte_solve(nlte_column* col, const double* n0_dev, const nlte_solve_opts* opts,
+                                  double* n_out_dev, double* J_out_dev, nlte_solve_stats* stats,
+                                  hipStream_t s) {
+  if (!col || !n_out_dev) return set_err(NLTE_E_INVALID, "NULL argument");
+  nlte_column* cols[1] = {col};
+  const double* n0s[1] = {n0_dev};
+  double* outs[1] = {n_out_dev};
+  nlte_status st = nlte_solve_batch(column_ctx(col), cols, 1, n0_dev ? n0s : nullptr, opts, outs,
+                                    stats, s);
+  if (J_out_dev && (st == NLTE_OK || st == NLTE_E_NOCONV)) {
+    const ColDev& C = column_dev(col);
+    HIP_TRY(hipMemcpyAsync(J_out_dev, C.Jeval, (size_t)C.nz * C.nnu * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return st;
 }

@@ -59,7 +59,16 @@ class SolveOpts(C.Structure):
 class SolveStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("newton_iters", C.c_int32),
                 ("krylov_iters", C.c_int32), ("f_calls", C.c_int32), ("stalls", C.c_int32),
-                ("rho_inf", C.c_double), ("dn_inf", C.c_double)]
+                ("precond_calls", C.c_int32), ("rho_inf", C.c_double), ("dn_inf", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Profile(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("formal_launches", C.c_int64), ("formal_ms", C.c_double),
+                ("newton_launches", C.c_int64), ("newton_ms", C.c_double),
+                ("assemble_ms", C.c_double), ("solver_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -96,6 +105,8 @@ def lib():
         L.nlte_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
         L.nlte_solve_opts_default.restype = None
         L.nlte_voigt_host.argtypes = [C.c_double, _dp, C.c_int32, _dp]
+        L.nlte_profile_enable.argtypes = [vp, C.c_int]
+        L.nlte_profile_read.argtypes = [vp, C.POINTER(Profile)]
         _lib = L
     return _lib
 
@@ -148,6 +159,15 @@ class Context:
         h = C.c_void_p()
         _check(lib().nlte_ctx_create(device, C.byref(h)))
         self.h = h
+
+    def profile(self, on: bool = True):
+        """Turn kernel timing of solves on/off (clears the accumulators)."""
+        _check(lib().nlte_profile_enable(self.h, int(on)))
+
+    def read_profile(self) -> dict:
+        p = Profile()
+        _check(lib().nlte_profile_read(self.h, C.byref(p)))
+        return p.as_dict()
 
     def close(self):
         if self.h:

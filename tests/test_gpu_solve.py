@@ -1,0 +1,120 @@
+"""GPU JFNK solves against the FP64 oracle's converged populations.
+
+Both sides are driven to a scaled residual of 1e-12, where the root is
+determined to ~1e-12 and the Newton paths (which need not agree) no longer
+matter; converged populations and profile-averaged intensities must agree to
+1e-10 relative (FP64) and 1e-4 (FP32 formal-solution form)."""
+import numpy as np
+import pytest
+
+from oracle import nlte_oracle as O
+from paper_2406_17234_amd import synth as S
+from tests.helpers import maxrel, require_gpu, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+_ORACLE_CACHE = {}
+
+
+def oracle_root(name, maker, ftol=1e-12):
+    if name not in _ORACLE_CACHE:
+        prob = maker()
+        tb = O.setup(prob)
+        s = O.solve(tb, ftol=ftol, rtol=1e-6, maxiter=60)
+        assert s.converged
+        _ORACLE_CACHE[name] = (prob, tb, s)
+    return _ORACLE_CACHE[name]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    require_gpu()
+    from paper_2406_17234_amd import nlte
+    return nlte.Context(0)
+
+
+CASES = {
+    "tiny": lambda: S.tiny(),
+    "slab3": lambda: S.slab3(),
+    "chromo6_small": lambda: S.chromo6(nz=40, nnu=300),
+    "chromo6": lambda: S.chromo6(),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_fp64_matches_oracle_root(ctx, name):
+    from paper_2406_17234_amd import nlte
+    prob, tb, ref = oracle_root(name, CASES[name])
+    print(f"[case] solve fp64 {name} dims={prob.dims}", flush=True)
+    col = nlte.Column(ctx, prob)
+    n, J, st, rc = col.solve(ftol=1e-12, rtol=1e-6, maxiter=60, want_J=True)
+    print(st, flush=True)
+    assert rc == 0 and st["status"] == 0
+    assert st["rho_inf"] <= 1e-12
+    n = to_np(n)
+    assert maxrel(n, ref.n) < 1e-10
+    out = col.residual(to_dev(n), want_Jbar=True)
+    if tb.nline:
+        rr = O.residual(tb, ref.n)
+        assert maxrel(to_np(out["Jbar"])[:, :tb.nline], rr.Jbar) < 1e-10
+    # particle conservation
+    assert np.max(np.abs(n.sum(axis=1) / tb.ntot - 1)) < 1e-13
+
+
+def test_solve_default_stop(ctx):
+    """The default stop (scaled residual 1e-8) on the 3-level slab."""
+    from paper_2406_17234_amd import nlte
+    prob, tb, ref = oracle_root("slab3", CASES["slab3"])
+    col = nlte.Column(ctx, prob)
+    n, _, st, rc = col.solve(ftol=1e-8)
+    assert rc == 0 and st["rho_inf"] <= 1e-8
+    assert maxrel(to_np(n), ref.n) < 1e-5
+
+
+def test_zero_radiation_guess(ctx):
+    from paper_2406_17234_amd import nlte
+    prob = CASES["chromo6_small"]()
+    tb = O.setup(prob)
+    ref = O.zero_radiation_guess(tb)
+    col = nlte.Column(ctx, prob)
+    # a dense per-depth solve over ~16 decades of populations: FP64 parity bar
+    assert maxrel(to_np(col.zero_radiation()), ref) < 1e-10
+    # this guess is poor for the synthetic 6-level atom (the oracle does not
+    # converge from it either); the solve must still end cleanly
+    n, _, st, rc = col.solve(init=2, ftol=1e-10, rtol=1e-4, maxiter=5)
+    assert rc in (0, nlte.NLTE_E_NOCONV) and st["newton_iters"] <= 5
+    assert np.all(np.isfinite(to_np(n)))
+
+
+def test_batch_equals_single(ctx):
+    """A column solved inside a batch gives bit-identical populations to the
+    same column solved alone."""
+    from paper_2406_17234_amd import nlte
+    probs = [CASES["slab3"](), CASES["chromo6_small"](), CASES["tiny"]()]
+    cols = [nlte.Column(ctx, p) for p in probs]
+    outs, stats, rc = nlte.solve_batch(ctx, cols, ftol=1e-10, rtol=1e-4)
+    assert rc == 0, stats
+    for c, o in zip(cols, outs):
+        n1, _, st, rc1 = c.solve(ftol=1e-10, rtol=1e-4)
+        assert rc1 == 0
+        assert np.array_equal(to_np(n1), to_np(o))
+
+
+def test_fp32_form_within_1e4(ctx):
+    from paper_2406_17234_amd import nlte
+    prob, tb, ref = oracle_root("chromo6", CASES["chromo6"])
+    col = nlte.Column(ctx, prob, precision=nlte.FP32_FORM)
+    n, _, st, rc = col.solve(ftol=1e-6, rtol=1e-3, maxiter=60)
+    print(st, flush=True)
+    assert rc == 0
+    assert maxrel(to_np(n), ref.n) < 1e-4
+
+
+def test_maxiter_reports_noconv(ctx):
+    from paper_2406_17234_amd import nlte
+    prob = CASES["chromo6_small"]()
+    col = nlte.Column(ctx, prob)
+    n, _, st, rc = col.solve(ftol=1e-14, maxiter=1)
+    assert rc == nlte.NLTE_E_NOCONV and st["status"] == nlte.NLTE_E_NOCONV
+    assert st["newton_iters"] == 1
+    assert np.all(np.isfinite(to_np(n)))
