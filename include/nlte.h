@@ -131,11 +131,10 @@ typedef struct {
  * (HIP events on the solve's stream around each launch). */
 typedef struct {
   int64_t steps;             /* solver steps (one residual per active column)   */
-  int64_t formal_launches;   /* formal-solution launches, residual-only mode    */
+  int64_t formal_launches;   /* formal-solution launches                        */
   double formal_ms;          /* their summed duration                           */
-  int64_t newton_launches;   /* formal-solution launches, preconditioner mode   */
-  double newton_ms;
-  double assemble_ms;        /* rate/residual assembly launches                 */
+  double depth_ms;           /* rate integrals + preconditioner pair sums       */
+  double assemble_ms;        /* residual/preconditioner assembly                */
   double solver_ms;          /* Krylov/Newton step launches                     */
 } nlte_profile;
 

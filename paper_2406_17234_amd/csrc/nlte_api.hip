@@ -47,8 +47,7 @@ struct nlte_column {
   ColDev* d = nullptr;        // device copy (one-element batch)
   void* arena = nullptr;
   size_t arena_bytes = 0;
-  Tile* tiles = nullptr;      // device, chunk list with col = 0
-  int ntiles = 0;
+  BatchWork bw;               // single-column work lists (col index 0)
   int restart_cap = 0;
   std::vector<double> Blu;    // host copy of line B_lu (profile-averaged J)
   double* stage_buf = nullptr;
@@ -269,6 +268,41 @@ __global__ void k_setup_norm(ColDev C, SetupIn in) {
   ((double*)C.Rsp)[k * C.ntr + t] = rsp;
 }
 
+// Depth-contiguous copies for the kernels that run one lane per depth.
+__global__ void k_setup_transpose(ColDev C, int nline_tab_total) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t kf = (size_t)C.nz * C.nnu;
+  if (C.nbf && i < kf) {
+    const int k = (int)(i / C.nnu), f = (int)(i % C.nnu);
+    ((double*)C.EbfT)[(size_t)f * C.nz + k] = C.Ebf[i];
+  }
+  if (i < (size_t)nline_tab_total) {
+    // find the line owning element i of the packed [nz][wl] tables
+    int t = 0;
+    while (t + 1 < C.nline && (size_t)C.tr[t + 1].voff <= i) ++t;
+    const TrDev T = C.tr[t];
+    const int wl = T.whi - T.wlo;
+    const size_t loc = i - T.voff;
+    const int k = (int)(loc / wl), q = (int)(loc % wl);
+    ((double*)C.VT)[T.voff + (size_t)q * C.nz + k] = C.V[i];
+  }
+}
+
+// J [nnu][nz] -> [nz][nnu]
+__global__ void k_transpose_J(const double* __restrict__ JT, double* __restrict__ out, int nz, int nnu) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)nz * nnu) return;
+  const int k = (int)(i / nnu), f = (int)(i % nnu);
+  out[i] = JT[(size_t)f * nz + k];
+}
+
+namespace nlte {
+void transpose_J(const ColDev& C, double* out, hipStream_t s) {
+  const size_t n = (size_t)C.nz * C.nnu;
+  k_transpose_J<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(C.JT, out, C.nz, C.nnu);
+}
+}  // namespace nlte
+
 // ---------------------------------------------------------------------------
 // column creation
 // ---------------------------------------------------------------------------
@@ -349,9 +383,16 @@ static nlte_status validate(const nlte_atmos_desc* A, const nlte_atom_desc* M,
   return NLTE_OK;
 }
 
+struct WorkPtrs {
+  Tile* tiles;
+  int4* rate;
+  int4* prec;
+};
+
 static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, int nline_tab,
                           int nbf_tot, int nentries, int m_cap, TrDev** tr_out, int** wbase,
-                          int** lbase, Tile** tiles, int** stage, int** bf_ptr, double** raw) {
+                          int** lbase, WorkPtrs* wp, const int* wsz, int** stage, int** bf_ptr,
+                          double** raw) {
   const int nz = C.nz, L = C.L, ntr = C.ntr, nnu = C.nnu, N = C.N;
   const size_t kf = (size_t)nz * nnu;
   C.st = Lo.take<ColState>(1);
@@ -366,28 +407,33 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.gam = Lo.take<double>(nnu);
   C.Bnu = Lo.take<double>(kf);
   C.Ebf = C.nbf ? Lo.take<double>(kf) : nullptr;
+  C.EbfT = C.nbf ? Lo.take<double>(kf) : nullptr;
   *tr_out = Lo.take<TrDev>(ntr);
   C.tr = *tr_out;
   C.V = Lo.take<double>((size_t)nline_tab * nz + (nwin_total - nline_tab));
+  C.VT = Lo.take<double>((size_t)nline_tab * nz + 1);
   C.cw = Lo.take<double>(nwin_total);
   C.rho_bf = Lo.take<double>((size_t)nz * std::max(C.nbf, 1));
   C.Rsp = Lo.take<double>((size_t)nz * ntr);
   C.C_lu = Lo.take<double>((size_t)nz * ntr);
   C.C_ul = Lo.take<double>((size_t)nz * ntr);
   C.nstar = Lo.take<double>((size_t)nz * L);
-  C.ch_ptr = Lo.take<int>(C.nchunk + 1);
-  C.ch_tr = Lo.take<int>(nentries);
-  C.ch_slot = Lo.take<int>(nentries);
+  C.ch_lptr = Lo.take<int>(C.nchunk + 1);
+  C.ch_line = Lo.take<int>(nentries);
+  C.pairs = Lo.take<int4>(std::max(C.npair, 1));
   C.eval_n = Lo.take<double>(N);
   C.F = Lo.take<double>(N);
   C.G = Lo.take<double>(N);
   C.Jdag = Lo.take<double>(kf);
-  C.Jeval = Lo.take<double>(kf);
+  C.JT = Lo.take<double>(kf);
   C.Jm = Lo.take<double>(kf);
+  C.XS = Lo.take<double>(2 * kf);
   C.Dchi = Lo.take<double>(kf);
   C.Deta = Lo.take<double>(kf);
-  C.part = Lo.take<double>((size_t)C.nslot * nz * 2);
-  C.Ppart = Lo.take<double>((size_t)C.nchunk * nz * L * L);
+  C.DchiT = Lo.take<double>(kf);
+  C.DetaT = Lo.take<double>(kf);
+  C.RJ = Lo.take<double>((size_t)nz * ntr * 2);
+  C.M = Lo.take<double>((size_t)nz * std::max(C.npair, 1) * 2);
   C.P = Lo.take<double>((size_t)nz * L * L);
   C.LU = Lo.take<double>((size_t)nz * L * L);
   C.Fsave = Lo.take<double>(nz);
@@ -411,7 +457,9 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.dots = Lo.take<double>(2 * (m_cap + 1));
   *wbase = Lo.take<int>(ntr + 1);
   *lbase = Lo.take<int>(std::max(C.nline, 1) + 1);
-  *tiles = Lo.take<Tile>(C.nchunk);
+  wp->tiles = Lo.take<Tile>(wsz[0]);
+  wp->rate = Lo.take<int4>(wsz[1]);
+  wp->prec = Lo.take<int4>(wsz[2]);
   *stage = Lo.take<int>(L);
   *bf_ptr = Lo.take<int>(C.nbf + 1);
   // raw setup inputs (doubles): E, g, A_ul, a_damp, bf_nu, bf_alpha, C_up
@@ -446,7 +494,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   // transitions, windows, chunk lists
   std::vector<TrDev> tr(ntr);
   std::vector<int> wbase(ntr + 1, 0), lbase(std::max(nline, 1) + 1, 0);
-  int nline_tab = 0, slot = 0;
+  int nline_tab = 0;
   std::vector<double> Blu(nline);
   for (int t = 0; t < ntr; ++t) {
     TrDev& T = tr[t];
@@ -457,9 +505,6 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     const int wl = T.whi - T.wlo;
     wbase[t + 1] = wbase[t] + wl;
     T.cwoff = wbase[t];
-    T.c0 = chunk_of(T.wlo);
-    T.slot = slot;
-    slot += chunk_of(T.whi - 1) - T.c0 + 1;
     if (t < nline) {
       const double nu0 = (M->E[T.up] - M->E[T.lo]) / kH;
       const double Bul = M->A_ul[t] * kC * kC / (2.0 * kH * nu0 * nu0 * nu0);
@@ -486,33 +531,46 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     }
     if (off > 0x7fffffff) return set_err(NLTE_E_INVALID, "profile tables too large");
   }
-  C.nslot = slot;
-  std::vector<int> ch_ptr(C.nchunk + 1, 0), ch_tr, ch_slot;
+
+  std::vector<int> ch_ptr(C.nchunk + 1, 0), ch_tr;
   for (int c = 0; c < C.nchunk; ++c) {
     const int f0 = c * kWave, f1 = std::min(nnu, f0 + kWave);
-    for (int t = 0; t < ntr; ++t) {
-      if (tr[t].wlo < f1 && tr[t].whi > f0) {
-        ch_tr.push_back(t);
-        ch_slot.push_back(tr[t].slot + (c - tr[t].c0));
-      }
-    }
+    for (int t = 0; t < nline; ++t)
+      if (tr[t].wlo < f1 && tr[t].whi > f0) ch_tr.push_back(t);
     ch_ptr[c + 1] = (int)ch_tr.size();
+    if (ch_ptr[c + 1] - ch_ptr[c] > kMaxChunkLines)
+      return set_err(NLTE_E_INVALID, "more than %d line windows overlap frequencies %d..%d",
+                     kMaxChunkLines, f0, f1 - 1);
   }
+  std::vector<int4> pairs;
+  for (int t = 0; t < ntr; ++t)
+    for (int u = 0; u < ntr; ++u) {
+      const int a = std::max(tr[t].wlo, tr[u].wlo), b = std::min(tr[t].whi, tr[u].whi);
+      if (b > a) pairs.push_back(make_int4(t, u, a, b));
+    }
+  C.npair = (int)pairs.size();
   const int nentries = std::max<int>(1, (int)ch_tr.size());
   int nbf_tot = nbf ? M->bf_ptr[nbf] : 0;
   const int m_cap = 32;
+
+  // single-column work lists
+  std::vector<Tile> tiles;
+  std::vector<int4> rate_w, prec_w;
+  int maxL_w = 0;
+  build_work_lists(&C, 1, tiles, rate_w, prec_w, maxL_w);
+  const int wsz[3] = {(int)tiles.size(), (int)rate_w.size(), (int)prec_w.size()};
 
   // layout
   SetupIn in{};
   TrDev* tr_d;
   int *wbase_d, *lbase_d, *stage_d, *bfptr_d;
-  Tile* tiles_d;
+  WorkPtrs wp{};
   double* raw_d;
   Layout sizer(nullptr);
   {
     ColDev tmp = C;
     layout_column(sizer, tmp, in, wbase[ntr], nline_tab, nbf_tot, nentries, m_cap, &tr_d,
-                  &wbase_d, &lbase_d, &tiles_d, &stage_d, &bfptr_d, &raw_d);
+                  &wbase_d, &lbase_d, &wp, wsz, &stage_d, &bfptr_d, &raw_d);
   }
   nlte_column* col = new nlte_column();
   col->ctx = ctx;
@@ -524,7 +582,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   }
   Layout lay(col->arena);
   layout_column(lay, C, in, wbase[ntr], nline_tab, nbf_tot, nentries, m_cap, &tr_d, &wbase_d,
-                &lbase_d, &tiles_d, &stage_d, &bfptr_d, &raw_d);
+                &lbase_d, &wp, wsz, &stage_d, &bfptr_d, &raw_d);
   col->restart_cap = m_cap;
   col->Blu = Blu;
 
@@ -534,8 +592,6 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     return hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, stream);
   };
   std::vector<double> zeros(nz, 0.0);
-  std::vector<Tile> tiles(C.nchunk);
-  for (int c = 0; c < C.nchunk; ++c) tiles[c] = Tile{0, c};
   double* rE = raw_d;
   double* rg = rE + L;
   double* rA = rg + L;
@@ -553,12 +609,14 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   UP(C.chi_sca, A->chi_sca ? A->chi_sca : zeros.data(), nz * 8);
   UP(C.nu, G->nu, nnu * 8);
   UP(tr_d, tr.data(), ntr * sizeof(TrDev));
-  UP(C.ch_ptr, ch_ptr.data(), ch_ptr.size() * 4);
-  UP(C.ch_tr, ch_tr.data(), ch_tr.size() * 4);
-  UP(C.ch_slot, ch_slot.data(), ch_slot.size() * 4);
+  UP(C.ch_lptr, ch_ptr.data(), ch_ptr.size() * 4);
+  UP(C.ch_line, ch_tr.data(), ch_tr.size() * 4);
+  UP(C.pairs, pairs.data(), pairs.size() * sizeof(int4));
+  UP(wp.rate, rate_w.data(), rate_w.size() * sizeof(int4));
+  UP(wp.prec, prec_w.data(), prec_w.size() * sizeof(int4));
   UP(wbase_d, wbase.data(), wbase.size() * 4);
   UP(lbase_d, lbase.data(), lbase.size() * 4);
-  UP(tiles_d, tiles.data(), tiles.size() * sizeof(Tile));
+  UP(wp.tiles, tiles.data(), tiles.size() * sizeof(Tile));
   UP(stage_d, M->stage, L * 4);
   if (nbf) UP(bfptr_d, M->bf_ptr, (nbf + 1) * 4);
   UP(rE, M->E, L * 8);
@@ -594,6 +652,10 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     k_setup_voigt<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C, in, lbase_d, lbase[nline]);
   }
   k_setup_norm<<<(ntr * nz + 63) / 64, 64, 0, stream>>>(C, in);
+  {
+    const size_t n = std::max((size_t)nz * nnu, (size_t)nline_tab * nz);
+    k_setup_transpose<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C, nline_tab * nz);
+  }
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMalloc(&col->d, sizeof(ColDev));
   if (e == hipSuccess) e = hipMemcpyAsync(col->d, &C, sizeof(ColDev), hipMemcpyHostToDevice, stream);
@@ -605,8 +667,18 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     return set_err(NLTE_E_DEVICE, "column setup failed: %s", hipGetErrorString(e));
   }
   col->h = C;
-  col->tiles = tiles_d;
-  col->ntiles = C.nchunk;
+  col->bw.cols = col->d;
+  col->bw.tiles = wp.tiles;
+  col->bw.rate_work = wp.rate;
+  col->bw.prec_work = wp.prec;
+  col->bw.ncol = 1;
+  col->bw.ntiles = wsz[0];
+  col->bw.nrate = wsz[1];
+  col->bw.nprec = wsz[2];
+  col->bw.any64 = prec == NLTE_FP64;
+  col->bw.any32 = prec == NLTE_FP32_FORM;
+  col->bw.any_newton = 1;
+
   *out = col;
   return NLTE_OK;
 }
@@ -673,8 +745,8 @@ hipError_t set_state_eval(nlte_column* col, int mode, int want_J, int rows_own, 
 
 static nlte_status run_single(nlte_column* col, hipStream_t s) {
   const ColDev& C = col->h;
-  HIP_TRY(launch_residual(col->d, 1, col->tiles, col->ntiles, C.prec == NLTE_FP64,
-                          C.prec == NLTE_FP32_FORM, 1, C.L, s));
+  (void)C;
+  HIP_TRY(launch_residual(col->bw, s));
   return NLTE_OK;
 }
 
@@ -717,8 +789,9 @@ extern "C" nlte_status nlte_residual(nlte_column* col, const double* n_dev, doub
   if (st != NLTE_OK) return st;
   HIP_TRY(hipMemcpyAsync(F_dev, C.F, C.N * 8, hipMemcpyDeviceToDevice, s));
   const size_t kf = (size_t)C.nz * C.nnu * 8;
-  if (J_dev) HIP_TRY(hipMemcpyAsync(J_dev, C.Jeval, kf, hipMemcpyDeviceToDevice, s));
-  if (update_J) HIP_TRY(hipMemcpyAsync(C.Jdag, C.Jeval, kf, hipMemcpyDeviceToDevice, s));
+  (void)kf;
+  if (J_dev) transpose_J(C, J_dev, s);
+  if (update_J) transpose_J(C, C.Jdag, s);
   if (R_dev) HIP_TRY(hipMemcpyAsync(R_dev, C.R, (size_t)C.nz * C.ntr * 16, hipMemcpyDeviceToDevice, s));
   if (Jbar_dev && C.nline)
     k_jbar<<<(C.nz * C.nline + 255) / 256, 256, 0, s>>>(Jbar_dev, C.R, C.tr, C.nz, C.ntr, C.nline);

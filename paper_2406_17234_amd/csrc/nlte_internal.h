@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "nlte.h"
 
 namespace nlte {
@@ -22,6 +24,37 @@ constexpr int kWave = 64;       // lanes per wavefront (CDNA)
 constexpr int kMaxMu = 8;       // angles per hemisphere held in registers
 constexpr int kMaxLev = 16;     // levels per atom
 constexpr int kMaxRestart = 64; // GMRES restart length
+constexpr int kMaxChunkLines = 4;  // line windows overlapping one 64-frequency chunk
+constexpr int kMaxEdges = kMaxLev - 1;
+
+// Loads and stores through the global address space (the pointers live in
+// column descriptors, so the compiler cannot infer it and would emit flat
+// accesses).
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
+// Wave-uniform loads of data no kernel writes while it runs (populations of
+// the evaluation, per-depth tables): through the constant address space, so
+// they use the scalar data cache.
+template <typename T>
+__device__ __forceinline__ T ldc(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)p;
+}
+
+// Values the compiler cannot prove wave-uniform, moved to scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
 
 // Evaluation modes of one residual call.
 enum EvalMode : int {
@@ -36,8 +69,6 @@ struct TrDev {
   int wlo, whi;     // window on the union grid [wlo, whi)
   int voff;         // offset of its V table (lines: [nz][wlen]; edges: [wlen])
   int cwoff;        // offset of its rate weights 4 pi w / (h nu) [wlen]
-  int slot;         // first partial-sum slot (one per 64-frequency chunk)
-  int c0;           // first chunk it touches
   double g;         // lines: g_l / g_u
   double Blu;       // lines: Einstein B_lu (for the profile-averaged intensity)
 };
@@ -65,7 +96,7 @@ struct ColState {
 
 struct ColDev {
   int nz, L, ntr, nline, nbf, nnu, nmu, prec;
-  int nchunk, nslot, has_sca, N;   // N = nz * L
+  int nchunk, npair, has_sca, N;   // N = nz * L; npair = overlapping transition pairs
   // angles (inline: at most kMaxMu)
   double wm2[kMaxMu];     // w_m / 2
   double inv2mu[kMaxMu];  // 1 / (2 mu_m)
@@ -74,26 +105,31 @@ struct ColDev {
   // frequency grid and per-(k, f) tables [nz][nnu]
   const double *nu, *gam;          // gam = 2 h nu^3 / c^2
   const double *Bnu, *Ebf;         // Planck function, exp(-h nu / kT)
+  const double *EbfT;              // [nnu][nz] exp(-h nu / kT), depth-contiguous
   // transitions
   const TrDev *tr;
   const double *V;                 // per-transition V tables
+  const double *VT;                // line V tables depth-contiguous ([wlen][nz] at the same offsets)
   const double *cw;                // per-transition rate weights
   const double *rho_bf;            // [nz][nbf] n*_l / n*_c
   const double *Rsp;               // [nz][ntr] n-independent part of R_ul
   const double *C_lu, *C_ul;       // [nz][ntr]
   const double *nstar;             // [nz][L]
-  // chunk -> transition lists
-  const int *ch_ptr, *ch_tr, *ch_slot;
+  // chunk -> overlapping line windows; overlapping transition pairs
+  const int *ch_lptr, *ch_line;
+  const int4 *pairs;               // (t, t', first, last + 1) of each window intersection
   // evaluation buffers
   ColState *st;
   double *eval_n;                  // [nz][L] populations to evaluate F at
   double *F, *G;                   // [nz][L] residual and gross rates
   double *Jdag;                    // [nz][nnu] lagged mean intensity
-  double *Jeval;                   // [nz][nnu] J of the last Newton-mode evaluation
+  double *JT;                      // [nnu][nz] J of the last evaluation (depth-contiguous)
   double *Jm;                      // [nz][nnu] scratch: ingoing-ray part of J
+  double *XS;                      // [nz][nnu][2] scratch: chi and S of the first sweep
   double *Dchi, *Deta;             // [nz][nnu] scratch: ingoing-ray intensity derivatives
-  double *part;                    // [nslot][nz][2] partial rate sums
-  double *Ppart;                   // [nchunk][nz][L*L] partial radiative blocks
+  double *DchiT, *DetaT;           // [nnu][nz] angle-averaged local intensity derivatives
+  double *RJ;                      // [nz][ntr][2] rate integrals over J
+  double *M;                       // [nz][npair][2] pair sums of the radiative blocks
   double *P;                       // [nz][L][L] preconditioner blocks of the last Newton-mode evaluation
   double *LU;                      // [nz][L][L] LU factors of the iterate's blocks
   double *Fsave, *Gsave;           // [nz] rate-row F and gross rate under each conservation row
@@ -123,13 +159,24 @@ struct Tile {
 
 inline __host__ __device__ int chunk_of(int f) { return f / kWave; }
 
-// Residual launches for a batch of columns (formal solution in both modes and
-// precisions, then assembly).  ev, if not NULL, holds four events recorded
-// before the residual-mode formal launches, after them, after the
-// preconditioner-mode launches and after assembly.
-hipError_t launch_residual(const ColDev* cols_dev, int ncol, const Tile* tiles_dev, int ntiles,
-                           int any_fp64, int any_fp32, int any_newton, int maxL, hipStream_t s,
-                           hipEvent_t* ev = nullptr);
+// Device work lists of a batch of columns.
+struct BatchWork {
+  const ColDev* cols = nullptr;   // device array [ncol]
+  const Tile* tiles = nullptr;    // formal-solution chunks
+  const int4* rate_work = nullptr;  // (col, transition, first depth, -)
+  const int4* prec_work = nullptr;  // (col, pair, first depth, -)
+  int ncol = 0, ntiles = 0, nrate = 0, nprec = 0;
+  int any64 = 0, any32 = 0, any_newton = 1;
+};
+
+// Residual launches for a batch (formal solution of every tile, rate
+// integrals and preconditioner pair sums, assembly).  ev, if not NULL, holds
+// four events: before the formal-solution launch, after it, after the
+// lane-per-depth work and after assembly.
+hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev = nullptr);
+
+void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
+                      std::vector<int4>& rate, std::vector<int4>& prec, int& maxL);
 
 }  // namespace nlte
 

@@ -6,16 +6,23 @@
 // (Eqs. residuals_1, residuals_2) and, in Newton mode, the block-Jacobi
 // preconditioner (Sect. 2.5.2 first solution, App. A.2).
 //
-// Work decomposition.  One wavefront owns a chunk of 64 consecutive
-// frequencies of one column; each lane owns one frequency and carries all
-// 2 x nmu rays of it through the depth recursion in registers.  The first
-// sweep runs top -> bottom for the ingoing rays and parks their share of J
-// in a per-(k, nu) scratch row; the second sweep runs bottom -> top for the
-// outgoing rays, completes J at each depth and immediately folds it into the
-// chunk's partial rate sums (wave reductions), so J never has to be re-read
-// from memory to form the rates.  The assembly kernel adds the partial sums of
-// every chunk in a fixed order (results do not depend on how columns are
-// batched) and builds F.
+// Work decomposition.
+//   k_formal : one wavefront per chunk of 64 consecutive frequencies of one
+//              column, one lane per frequency carrying all 2 x nmu rays
+//              through the depth recursion in registers.  The first sweep
+//              runs top -> bottom (ingoing rays) and parks their share of J
+//              in a [k][nu] scratch row; the second runs bottom -> top
+//              (outgoing rays) and writes J.  In Newton mode it also writes
+//              the angle-averaged local intensity derivatives.
+//   k_rates  : one lane per depth, one wavefront per (column, transition,
+//              64 depths): each lane sums its transition window in frequency
+//              order, so rate integrals need no cross-lane reductions and do
+//              not depend on how columns are batched.
+//   k_precond: Newton mode only; one lane per depth accumulates the
+//              radiative part of the diagonal Jacobian blocks over a segment
+//              of frequencies.
+//   k_assemble: rates, rate-equation residual, conservation rows, scaled
+//              residual, preconditioner blocks; one block per column.
 #include "nlte_internal.h"
 
 namespace nlte {
@@ -82,67 +89,133 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// opacity and emissivity at one (k, f), Eqs. chi and eta (FP64)
+// opacity and emissivity, Eqs. chi and eta (FP64)
 // ---------------------------------------------------------------------------
+// Per wave: the line windows overlapping its chunk (uniform, scalar
+// registers) and, per lane, the edges' cross-sections at its frequency
+// (depth independent, registers).  Per depth and lane: the table values that
+// change with depth, loaded one depth ahead of their use.
+struct LineMeta {
+  int lo, up, voff, wl;
+  double g;
+};
+
+struct DepthVals {
+  double B, E, Jd;
+  double v[kMaxChunkLines];
+};
+
+struct WaveOpac {
+  LineMeta lm[kMaxChunkLines];
+  int loff[kMaxChunkLines];   // f - window start (per lane)
+  unsigned amask;             // lane inside line window j
+  int nl;
+  int elo[kMaxEdges];         // edge lower levels (uniform)
+  double alpha[kMaxEdges];    // edge cross-sections at f (0 outside the window)
+  double gam;
+};
+
+__device__ __forceinline__ void wave_opac_init(WaveOpac& w, const ColDev& C, int chunk, int f) {
+  const int l0 = uni(C.ch_lptr[chunk]);
+  w.nl = uni(C.ch_lptr[chunk + 1]) - l0;
+  w.amask = 0;
+#pragma unroll
+  for (int j = 0; j < kMaxChunkLines; ++j) {
+    w.lm[j] = LineMeta{0, 0, 0, 0, 0.0};
+    w.loff[j] = 0;
+    if (j < w.nl) {
+      const int t = uni(C.ch_line[l0 + j]);
+      const TrDev& T = C.tr[t];
+      const int wlo = uni(T.wlo), whi = uni(T.whi);
+      w.lm[j] = LineMeta{uni(T.lo), uni(T.up), uni(T.voff), whi - wlo, uni(T.g)};
+      w.loff[j] = f - wlo;
+      if (f >= wlo && f < whi) w.amask |= 1u << j;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kMaxEdges; ++e) {
+    w.elo[e] = 0;
+    w.alpha[e] = 0.0;
+    if (e < C.nbf) {
+      const TrDev& T = C.tr[C.nline + e];
+      const int wlo = uni(T.wlo), whi = uni(T.whi);
+      w.elo[e] = uni(T.lo);
+      if (f >= wlo && f < whi) w.alpha[e] = ldg(C.V + uni(T.voff) + (f - wlo));
+    }
+  }
+  w.gam = ldg(C.gam + f);
+}
+
+__device__ __forceinline__ void load_depth(DepthVals& d, const WaveOpac& w, const ColDev& C,
+                                           int k, int f) {
+  const size_t kf = (size_t)k * C.nnu + f;
+  d.B = ldg(C.Bnu + kf);
+  d.E = C.nbf ? ldg(C.Ebf + kf) : 0.0;
+  d.Jd = C.has_sca ? ldg(C.Jdag + kf) : 0.0;
+#pragma unroll
+  for (int j = 0; j < kMaxChunkLines; ++j) {
+    d.v[j] = 0.0;
+    if (j < w.nl && ((w.amask >> j) & 1u))
+      d.v[j] = ldg(C.V + w.lm[j].voff + (size_t)k * w.lm[j].wl + w.loff[j]);
+  }
+}
+
 struct Opac {
   double chi, eta;
 };
 
-__device__ __forceinline__ Opac opacity_at(const ColDev& C, const double* __restrict__ n,
-                                           int k, int f, int e0, int e1) {
-  const int nnu = C.nnu, L = C.L;
-  const size_t kf = (size_t)k * nnu + f;
+__device__ __forceinline__ Opac opacity(const WaveOpac& w, const DepthVals& d, const ColDev& C,
+                                        const double* __restrict__ n, int k) {
+  const int L = C.L;
+  const double* nk = n + k * L;
+  const double cc = ldc(C.chi_c + k), cs = ldc(C.chi_sca + k);
   Opac o;
-  o.chi = C.chi_c[k] + C.chi_sca[k];
-  o.eta = C.chi_c[k] * C.Bnu[kf];
-  if (C.has_sca) o.eta += C.chi_sca[k] * C.Jdag[kf];
-  const double Ekf = C.nbf ? C.Ebf[kf] : 0.0;
-  const double gam = C.gam[f];
-  for (int e = e0; e < e1; ++e) {
-    const TrDev T = C.tr[C.ch_tr[e]];
-    if (f < T.wlo || f >= T.whi) continue;
-    const int t = C.ch_tr[e];
-    const double nl = n[k * L + T.lo], nu_ = n[k * L + T.up];
-    double V, g;
-    if (t < C.nline) {
-      V = C.V[T.voff + (size_t)k * (T.whi - T.wlo) + (f - T.wlo)];
-      g = T.g;
-    } else {
-      V = C.V[T.voff + (f - T.wlo)];
-      g = C.rho_bf[k * C.nbf + (t - C.nline)] * Ekf;
+  o.chi = cc + cs;
+  o.eta = cc * d.B + cs * d.Jd;
+  if (C.nbf) {
+    // edges: V = alpha, g = (n*_l/n*_c) exp(-h nu/kT); sum_e alpha (n_l - g n_c)
+    const double* rho = C.rho_bf + k * C.nbf;
+    double A1 = 0.0, A2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < kMaxEdges; ++e) {
+      if (e < C.nbf) {
+        A1 += w.alpha[e] * ldc(nk + w.elo[e]);
+        A2 += w.alpha[e] * ldc(rho + e);
+      }
     }
-    o.chi += V * (nl - g * nu_);
-    o.eta += gam * g * V * nu_;
+    const double nc = ldc(nk + L - 1);
+    o.chi += A1 - d.E * nc * A2;
+    o.eta += w.gam * d.E * nc * A2;
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxChunkLines; ++j) {
+    if (j < w.nl) {
+      const double nl_ = ldc(nk + w.lm[j].lo), nu_ = ldc(nk + w.lm[j].up);
+      o.chi += d.v[j] * (nl_ - w.lm[j].g * nu_);
+      o.eta += w.gam * w.lm[j].g * d.v[j] * nu_;
+    }
   }
   return o;
 }
 
 // ---------------------------------------------------------------------------
-// fused formal-solution kernel
+// formal solution kernel
 // ---------------------------------------------------------------------------
 // R: arithmetic of the depth recursion (double, or float for the FP32 form).
-// PM: Newton mode (also the preconditioner's radiative blocks and J output).
+// PM: Newton mode (also the local intensity derivatives of App. A.2).
+// The first sweep assembles chi and S at every depth and keeps them in a
+// [k][nu] scratch row for the second sweep, which only reloads them.
 template <typename R, bool PM>
-__global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
-                                                const Tile* __restrict__ tiles, int ntiles) {
-  extern __shared__ double lds[];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int tid = blockIdx.x * (blockDim.x >> 6) + wave;
-  if (tid >= ntiles) return;
-  const Tile tl = tiles[tid];
-  const ColDev& C = cols[tl.col];
-  const int mode = C.st->mode;
-  if (mode == kModeIdle || (mode == kModeNewton) != PM) return;
-  if ((C.prec == NLTE_FP32_FORM) != (sizeof(R) == sizeof(float))) return;
-  const bool wantJ = PM || C.st->want_J;
-
-  const int nz = C.nz, nnu = C.nnu, nmu = C.nmu, L = C.L;
-  const int f = tl.chunk * kWave + lane;
+__device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane) {
+  const int nz = C.nz, nnu = C.nnu, nmu = C.nmu;
+  const int f = chunk * kWave + lane;
   const bool fin = f < nnu;
   const int fc = fin ? f : nnu - 1;
   const double* __restrict__ n = C.eval_n;
-  const int e0 = C.ch_ptr[tl.chunk], e1 = C.ch_ptr[tl.chunk + 1];
+  R* __restrict__ xs = reinterpret_cast<R*>(C.XS);  // [nz][nnu][2]: chi, S
+
+  WaveOpac w;
+  wave_opac_init(w, C, chunk, fc);
 
   R wm2[kMaxMu], i2mu[kMaxMu];
 #pragma unroll
@@ -156,12 +229,15 @@ __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
 #pragma unroll
   for (int m = 0; m < kMaxMu; ++m) I[m] = (R)0;
   R chi_p = 0, S_p = 0;
+  DepthVals cur, nxt;
+  load_depth(cur, w, C, 0, fc);
   for (int k = 0; k < nz; ++k) {
-    const Opac o = opacity_at(C, n, k, fc, e0, e1);
+    if (k + 1 < nz) load_depth(nxt, w, C, k + 1, fc);
+    const Opac o = opacity(w, cur, C, n, k);
     const R chi = (R)o.chi, S = (R)(o.eta / o.chi);
     double Jm = 0.0, dX = 0.0, dE = 0.0;
     if (k > 0) {
-      const R dz = (R)C.dz[k - 1];
+      const R dz = (R)ldc(C.dz + k - 1);
       const R base = dz * (chi_p + chi);
 #pragma unroll
       for (int m = 0; m < kMaxMu; ++m) {
@@ -183,139 +259,244 @@ __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
       }
     }
     if (fin) {
-      C.Jm[(size_t)k * nnu + f] = Jm;
+      const size_t kf = (size_t)k * nnu + f;
+      stg(C.Jm + kf, Jm);
+      stg(xs + 2 * kf, chi);
+      stg(xs + 2 * kf + 1, S);
       if (PM) {
-        C.Dchi[(size_t)k * nnu + f] = dX;
-        C.Deta[(size_t)k * nnu + f] = dE;
+        stg(C.Dchi + kf, dX);
+        stg(C.Deta + kf, dE);
       }
     }
     chi_p = chi;
     S_p = S;
+    cur = nxt;
   }
 
   // ---- sweep 2: outgoing rays, bottom -> top (I+ = B at the bottom) ----
-  double* sA = nullptr;
-  double* sX = nullptr;
-  if (PM) {
-    sA = lds + (size_t)wave * 2 * kWave * L;
-    sX = sA + (size_t)kWave * L;
-  }
-  R chi_n = 0, S_n = 0;
-  for (int k = nz - 1; k >= 0; --k) {
-    const Opac o = opacity_at(C, n, k, fc, e0, e1);
-    const R chi = (R)o.chi, S = (R)(o.eta / o.chi);
-    const size_t kf = (size_t)k * nnu + fc;
-    double Jp = 0.0, dX = 0.0, dE = 0.0;
-    if (k == nz - 1) {
-      const R Bb = (R)C.Bnu[kf];
+  R chi_n = chi_p, S_n = S_p;
+  {
+    const size_t kf = (size_t)(nz - 1) * nnu + fc;
+    const R Bb = (R)ldg(C.Bnu + kf);
+    double Jp = 0.0;
 #pragma unroll
-      for (int m = 0; m < kMaxMu; ++m) {
-        I[m] = Bb;
-        if (m < nmu) Jp += (double)wm2[m] * (double)Bb;
+    for (int m = 0; m < kMaxMu; ++m) {
+      I[m] = Bb;
+      if (m < nmu) Jp += (double)wm2[m] * (double)Bb;
+    }
+    if (fin) {
+      const size_t fk = (size_t)f * nz + (nz - 1);
+      stg(C.JT + fk, ldg(C.Jm + kf) + Jp);
+      if (PM) {  // bottom: ingoing-ray derivatives only
+        stg(C.DchiT + fk, ldg(C.Dchi + kf));
+        stg(C.DetaT + fk, ldg(C.Deta + kf));
       }
-    } else {
-      const R dz = (R)C.dz[k];
-      const R base = dz * (chi + chi_n);
+    }
+  }
+  // prefetched: chi, S, Jm (and the ingoing derivatives) of the next depth up
+  R chi_c = 0, S_c = 0;
+  double Jm_c = 0.0, dX_c = 0.0, dE_c = 0.0;
+  if (nz >= 2) {
+    const size_t kf = (size_t)(nz - 2) * nnu + fc;
+    chi_c = ldg(xs + 2 * kf);
+    S_c = ldg(xs + 2 * kf + 1);
+    Jm_c = ldg(C.Jm + kf);
+    if (PM) {
+      dX_c = ldg(C.Dchi + kf);
+      dE_c = ldg(C.Deta + kf);
+    }
+  }
+  for (int k = nz - 2; k >= 0; --k) {
+    R chi_x = 0, S_x = 0;
+    double Jm_x = 0.0, dX_x = 0.0, dE_x = 0.0;
+    if (k > 0) {
+      const size_t kf = (size_t)(k - 1) * nnu + fc;
+      chi_x = ldg(xs + 2 * kf);
+      S_x = ldg(xs + 2 * kf + 1);
+      Jm_x = ldg(C.Jm + kf);
+      if (PM) {
+        dX_x = ldg(C.Dchi + kf);
+        dE_x = ldg(C.Deta + kf);
+      }
+    }
+    const R chi = chi_c, S = S_c;
+    const R dz = (R)ldc(C.dz + k);
+    const R base = dz * (chi + chi_n);
+    double Jp = 0.0, dX = 0.0, dE = 0.0;
 #pragma unroll
-      for (int m = 0; m < kMaxMu; ++m) {
-        if (m < nmu) {
-          const R dt = base * i2mu[m];
-          R e, a, b;
-          pl_coef(dt, e, a, b);
-          const R Iup = I[m];
-          I[m] = Iup + a * (S - Iup) + b * (S_n - Iup);
-          Jp += (double)wm2[m] * (double)I[m];
-          if (PM) {
-            // a_chi, a_eta of App. A.2 (outgoing ray, segment k+1 -> k)
-            const R achi = -(S / chi) * a +
-                           dz * i2mu[m] * (e * (S_n - Iup) - (S_n - S) * b / dt);
-            dX += (double)wm2[m] * (double)achi;
-            dE += (double)wm2[m] * (double)(a / chi);
-          }
+    for (int m = 0; m < kMaxMu; ++m) {
+      if (m < nmu) {
+        const R dt = base * i2mu[m];
+        R e, a, b;
+        pl_coef(dt, e, a, b);
+        const R Iup = I[m];
+        I[m] = Iup + a * (S - Iup) + b * (S_n - Iup);
+        Jp += (double)wm2[m] * (double)I[m];
+        if (PM) {
+          // a_chi, a_eta of App. A.2 (outgoing ray, segment k+1 -> k)
+          const R achi = -(S / chi) * a +
+                         dz * i2mu[m] * (e * (S_n - Iup) - (S_n - S) * b / dt);
+          dX += (double)wm2[m] * (double)achi;
+          dE += (double)wm2[m] * (double)(a / chi);
         }
+      }
+    }
+    if (fin) {
+      const size_t fk = (size_t)f * nz + k;
+      stg(C.JT + fk, Jm_c + Jp);
+      if (PM) {
+        stg(C.DchiT + fk, dX_c + dX);
+        stg(C.DetaT + fk, dE_c + dE);
       }
     }
     chi_n = chi;
     S_n = S;
-    const double J = C.Jm[kf] + Jp;
-    if (wantJ && fin) C.Jeval[kf] = J;
+    chi_c = chi_x;
+    S_c = S_x;
+    Jm_c = Jm_x;
+    dX_c = dX_x;
+    dE_c = dE_x;
+  }
+}
 
-    // frequency quadrature: partial rate sums of this chunk
-    const double Ekf = C.nbf ? C.Ebf[kf] : 0.0;
-    for (int e = e0; e < e1; ++e) {
-      const int t = C.ch_tr[e];
-      const TrDev T = C.tr[t];
-      const bool act = fin && f >= T.wlo && f < T.whi;
-      double v1 = 0.0;
-      if (act) {
-        const double V = (t < C.nline) ? C.V[T.voff + (size_t)k * (T.whi - T.wlo) + (f - T.wlo)]
-                                       : C.V[T.voff + (f - T.wlo)];
-        v1 = C.cw[T.cwoff + (f - T.wlo)] * V * J;
-      }
-      const double s1 = wave_sum(v1);
-      double* dst = C.part + ((size_t)C.ch_slot[e] * nz + k) * 2;
-      if (t < C.nline) {
-        if (lane == 0) dst[0] = s1;
-      } else {
-        const double s2 = wave_sum(v1 * Ekf);
-        if (lane == 0) {
-          dst[0] = s1;
-          dst[1] = s2;
-        }
-      }
-    }
+// One launch covers every tile of a step; each wave takes the mode of its
+// column (residual only, or residual + preconditioner derivatives).
+template <typename R>
+__global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
+                                                const Tile* __restrict__ tiles, int ntiles) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int tid = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (tid >= ntiles) return;
+  const int col = uni(tiles[tid].col);
+  const int chunk = uni(tiles[tid].chunk);
+  const ColDev& C = cols[col];
+  const int mode = uni(C.st->mode);
+  if (mode == kModeIdle) return;
+  if ((C.prec == NLTE_FP32_FORM) != (sizeof(R) == sizeof(float))) return;
+  if (mode == kModeNewton)
+    formal_tile<R, true>(C, chunk, lane);
+  else
+    formal_tile<R, false>(C, chunk, lane);
+}
 
-    if (PM) {
-      // Radiative block sum_f alpha_i (beta_j Dchi + gamma_j Deta) of this chunk.
-      const double DX = (fin ? C.Dchi[kf] : 0.0) + dX;
-      const double DE = (fin ? C.Deta[kf] : 0.0) + dE;
-      double* a_l = sA + lane * L;
-      double* x_l = sX + lane * L;
-      for (int i = 0; i < L; ++i) {
-        a_l[i] = 0.0;
-        x_l[i] = 0.0;
-      }
-      if (fin) {
-        const double gam = C.gam[f];
-        for (int e = e0; e < e1; ++e) {
-          const int t = C.ch_tr[e];
-          const TrDev T = C.tr[t];
-          if (f < T.wlo || f >= T.whi) continue;
-          double V, g;
-          if (t < C.nline) {
-            V = C.V[T.voff + (size_t)k * (T.whi - T.wlo) + (f - T.wlo)];
-            g = T.g;
-          } else {
-            V = C.V[T.voff + (f - T.wlo)];
-            g = C.rho_bf[k * C.nbf + (t - C.nline)] * Ekf;
-          }
-          const double cA = C.cw[T.cwoff + (f - T.wlo)] * V * (n[k * L + T.lo] - g * n[k * L + T.up]);
-          a_l[T.lo] += cA;
-          a_l[T.up] -= cA;
-          x_l[T.lo] += V * DX;
-          x_l[T.up] += g * V * (gam * DE - DX);
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      double* dstP = C.Ppart + ((size_t)tl.chunk * nz + k) * L * L;
-      for (int p = lane; p < L * L; p += kWave) {
-        const int i = p / L, j = p - i * L;
-        double s = 0.0;
-        for (int q = 0; q < kWave; ++q) s += sA[q * L + i] * sX[q * L + j];
-        dstP[p] = s;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// ---------------------------------------------------------------------------
+// rate integrals (Eqs. Rij, Rji): one lane per depth, sequential sums over
+// each transition window (depth-contiguous operands, so every load of a
+// wave is one contiguous run).  Lines: sum cw V J.  Edges: sum cw alpha J and
+// sum cw alpha exp(-h nu/kT) J (the J part of R_ul without its depth factor).
+// Compensated (Neumaier) sums: windows run to thousands of points and the
+// residual cancels gross rates, so plain sequential sums would set its floor.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void neumaier(double& s, double& c, double x) {
+  const double u = s + x;
+  c += (fabs(s) >= fabs(x)) ? (s - u) + x : (x - u) + s;
+  s = u;
+}
+
+__device__ __forceinline__ void rates_item(const ColDev& C, int t, int k0) {
+  if (uni(C.st->mode) == kModeIdle) return;
+  const int nz = C.nz;
+  const int k = k0 + threadIdx.x;
+  if (k >= nz) return;
+  const TrDev& T = C.tr[t];
+  const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
+  const double* __restrict__ J = C.JT + (size_t)wlo * nz + k;
+  const double* __restrict__ cw = C.cw + uni(T.cwoff);
+  double* dst = C.RJ + ((size_t)k * C.ntr + t) * 2;
+  if (t < C.nline) {
+    const double* __restrict__ V = C.VT + uni(T.voff) + k;
+    double s = 0.0, c = 0.0;
+#pragma unroll 4
+    for (int q = 0; q < wl; ++q)
+      neumaier(s, c, cw[q] * ldg(V + (size_t)q * nz) * ldg(J + (size_t)q * nz));
+    stg(dst, s + c);
+    stg(dst + 1, 0.0);
+  } else {
+    const double* __restrict__ A = C.V + uni(T.voff);
+    const double* __restrict__ E = C.EbfT + (size_t)wlo * nz + k;
+    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+#pragma unroll 4
+    for (int q = 0; q < wl; ++q) {
+      const double x = cw[q] * A[q] * ldg(J + (size_t)q * nz);
+      neumaier(s1, c1, x);
+      neumaier(s2, c2, x * ldg(E + (size_t)q * nz));
     }
+    stg(dst, s1 + c1);
+    stg(dst + 1, s2 + c2);
   }
 }
 
 // ---------------------------------------------------------------------------
-// assembly: rates from the partial sums, F rows, conservation rows, rho,
-// preconditioner blocks (Gamma + radiative part)
+// radiative part of the diagonal Jacobian blocks (Sect. 2.5.1, 2.5.2 first
+// solution):  P_ij += sum_nu alpha_i (beta_j D_chi + gamma_j D_eta).
+// alpha_i, beta_j and gamma_j are sums over the transitions touching a level,
+// so the block is a sum over pairs of transitions (t, t') of
+//   M1 = sum_nu cw_t A_t V_t' D_chi,
+//   M2 = sum_nu cw_t A_t g_t' V_t' (2 h nu^3/c^2 D_eta - D_chi),
+// over the intersection of their windows, A_t = V_t (n_l - g_t n_u); the
+// assembly scatters M1, M2 to the levels.  One lane per depth.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void tr_vg(const ColDev& C, int t, int voff, int wlo, double gline,
+                                      int kk, int q, double E, double& V, double& g) {
+  if (t < C.nline) {
+    V = ldg(C.VT + voff + (size_t)(q - wlo) * C.nz + kk);
+    g = gline;
+  } else {
+    V = C.V[voff + (q - wlo)];
+    g = C.rho_bf[kk * C.nbf + (t - C.nline)] * E;
+  }
+}
+
+__device__ __forceinline__ void precond_item(const ColDev& C, int p, int k0) {
+  const int nz = C.nz, L = C.L;
+  const int k = k0 + threadIdx.x;
+  if (k >= nz) return;
+  const int4 pr = C.pairs[p];
+  const int t = uni(pr.x), u = uni(pr.y), f0 = uni(pr.z), f1 = uni(pr.w);
+  const TrDev& Tt = C.tr[t];
+  const TrDev& Tu = C.tr[u];
+  const int tw = uni(Tt.wlo), uw = uni(Tu.wlo), tv = uni(Tt.voff), uv = uni(Tu.voff);
+  const double tg = uni(Tt.g), ug = uni(Tu.g);
+  const double* cwt = C.cw + uni(Tt.cwoff) - tw;
+  const double nl = C.eval_n[k * L + uni(Tt.lo)], nu_ = C.eval_n[k * L + uni(Tt.up)];
+  const bool edge = t >= C.nline || u >= C.nline;
+  double m1 = 0.0, m2 = 0.0;
+  for (int q = f0; q < f1; ++q) {
+    const size_t fk = (size_t)q * nz + k;
+    const double E = edge ? ldg(C.EbfT + fk) : 0.0;
+    double Vt, gt, Vu, gu;
+    tr_vg(C, t, tv, tw, tg, k, q, E, Vt, gt);
+    tr_vg(C, u, uv, uw, ug, k, q, E, Vu, gu);
+    const double DX = ldg(C.DchiT + fk), DE = ldg(C.DetaT + fk);
+    const double cA = cwt[q] * Vt * (nl - gt * nu_);
+    m1 += cA * Vu * DX;
+    m2 += cA * gu * Vu * (C.gam[q] * DE - DX);
+  }
+  double* dst = C.M + ((size_t)k * C.npair + p) * 2;
+  stg(dst, m1);
+  stg(dst + 1, m2);
+}
+
+// Lane-per-depth work of a step: rate integrals (kind 0) of every active
+// column and, for columns in Newton mode, preconditioner pair sums (kind 1).
+__global__ __launch_bounds__(64) void k_depthwork(const ColDev* __restrict__ cols,
+                                                  const int4* __restrict__ work, int nwork) {
+  const int w = blockIdx.x;
+  if (w >= nwork) return;
+  const int4 it = work[w];
+  const int col = uni(it.x), idx = uni(it.y), k0 = uni(it.z), kind = uni(it.w);
+  const ColDev& C = cols[col];
+  const int mode = uni(C.st->mode);
+  if (kind == 0) {
+    if (mode != kModeIdle) rates_item(C, idx, k0);
+  } else {
+    if (mode == kModeNewton) precond_item(C, idx, k0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// assembly: rates, F rows, conservation rows, rho, preconditioner blocks
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_assemble(const ColDev* __restrict__ cols) {
   __shared__ double sF[kWave][kMaxLev + 1];
@@ -336,25 +517,26 @@ __global__ __launch_bounds__(64) void k_assemble(const ColDev* __restrict__ cols
     }
     double* Pk = C.P + (size_t)k * L * L;
     if (mode == kModeNewton) {
-      for (int p = 0; p < L * L; ++p) {
-        double s = 0.0;
-        for (int c = 0; c < C.nchunk; ++c) s += C.Ppart[((size_t)c * nz + k) * L * L + p];
-        Pk[p] = s;
+      for (int p = 0; p < L * L; ++p) Pk[p] = 0.0;
+      for (int p = 0; p < C.npair; ++p) {
+        const int4 pr = C.pairs[p];
+        const TrDev& Tt = C.tr[pr.x];
+        const TrDev& Tu = C.tr[pr.y];
+        const double m1 = C.M[((size_t)k * C.npair + p) * 2];
+        const double m2 = C.M[((size_t)k * C.npair + p) * 2 + 1];
+        Pk[Tt.lo * L + Tu.lo] += m1;
+        Pk[Tt.up * L + Tu.lo] -= m1;
+        Pk[Tt.lo * L + Tu.up] += m2;
+        Pk[Tt.up * L + Tu.up] -= m2;
       }
     }
     for (int t = 0; t < ntr; ++t) {
       const TrDev T = C.tr[t];
-      const int nch = chunk_of(T.whi - 1) - T.c0 + 1;
-      double s1 = 0.0, s2 = 0.0;
-      for (int s = 0; s < nch; ++s) {
-        const double* src = C.part + ((size_t)(T.slot + s) * nz + k) * 2;
-        s1 += src[0];
-        if (t >= nline) s2 += src[1];
-      }
-      const double Rlu = s1;
+      const double* rj = C.RJ + ((size_t)k * ntr + t) * 2;
+      const double Rlu = rj[0];
       const double Rsp = C.Rsp[k * ntr + t];
       const double Rul = (t < nline) ? T.g * (Rsp + Rlu)
-                                     : C.rho_bf[k * C.nbf + (t - nline)] * (Rsp + s2);
+                                     : C.rho_bf[k * C.nbf + (t - nline)] * (Rsp + rj[1]);
       C.R[((size_t)k * ntr + t) * 2 + 0] = Rlu;
       C.R[((size_t)k * ntr + t) * 2 + 1] = Rul;
       const double up_rate = C.C_lu[k * ntr + t] + Rlu;
@@ -428,27 +610,38 @@ __global__ __launch_bounds__(64) void k_assemble(const ColDev* __restrict__ cols
 // ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
-size_t formal_pm_lds_bytes(int maxL) { return (size_t)4 * 2 * kWave * maxL * sizeof(double); }
-
-hipError_t launch_residual(const ColDev* cols_dev, int ncol, const Tile* tiles_dev, int ntiles,
-                           int any_fp64, int any_fp32, int any_newton, int maxL, hipStream_t s,
-                           hipEvent_t* ev) {
-  const int blocks = (ntiles + 3) / 4;
+hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
+  const int blocks = (bw.ntiles + 3) / 4;
   if (ev) hipEventRecord(ev[0], s);
-  if (ntiles > 0) {
-    if (any_fp64) k_formal<double, false><<<blocks, 256, 0, s>>>(cols_dev, tiles_dev, ntiles);
-    if (any_fp32) k_formal<float, false><<<blocks, 256, 0, s>>>(cols_dev, tiles_dev, ntiles);
+  if (bw.ntiles > 0) {
+    if (bw.any64) k_formal<double><<<blocks, 256, 0, s>>>(bw.cols, bw.tiles, bw.ntiles);
+    if (bw.any32) k_formal<float><<<blocks, 256, 0, s>>>(bw.cols, bw.tiles, bw.ntiles);
   }
   if (ev) hipEventRecord(ev[1], s);
-  if (ntiles > 0 && any_newton) {
-    const size_t lds = formal_pm_lds_bytes(maxL);
-    if (any_fp64) k_formal<double, true><<<blocks, 256, lds, s>>>(cols_dev, tiles_dev, ntiles);
-    if (any_fp32) k_formal<float, true><<<blocks, 256, lds, s>>>(cols_dev, tiles_dev, ntiles);
-  }
+  if (bw.nrate > 0) k_depthwork<<<bw.nrate, 64, 0, s>>>(bw.cols, bw.rate_work, bw.nrate);
   if (ev) hipEventRecord(ev[2], s);
-  k_assemble<<<ncol, 64, 0, s>>>(cols_dev);
+  k_assemble<<<bw.ncol, 64, 0, s>>>(bw.cols);
   if (ev) hipEventRecord(ev[3], s);
   return hipGetLastError();
+}
+
+// Work lists of a batch (host side): formal-solution tiles, rate items and
+// preconditioner items for every column.
+void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
+                      std::vector<int4>& rate, std::vector<int4>& prec, int& maxL) {
+  // rate items (kind 0) and preconditioner items (kind 1) share one list;
+  // prec stays empty
+  maxL = 0;
+  (void)prec;
+  for (int c = 0; c < ncol; ++c) {
+    const ColDev& C = hc[c];
+    maxL = std::max(maxL, C.L);
+    for (int ch = 0; ch < C.nchunk; ++ch) tiles.push_back(Tile{c, ch});
+    for (int t = 0; t < C.ntr; ++t)
+      for (int k0 = 0; k0 < C.nz; k0 += kWave) rate.push_back(make_int4(c, t, k0, 0));
+    for (int p = 0; p < C.npair; ++p)
+      for (int k0 = 0; k0 < C.nz; k0 += kWave) rate.push_back(make_int4(c, p, k0, 1));
+  }
 }
 
 }  // namespace nlte

@@ -27,6 +27,7 @@ const ColDev& column_dev(const nlte_column* c);
 ColDev* column_dev_ptr(const nlte_column* c);
 int column_restart_cap(const nlte_column* c);
 nlte_ctx* column_ctx(const nlte_column* c);
+void transpose_J(const ColDev& C, double* out, hipStream_t s);
 }  // namespace nlte
 
 using namespace nlte;
@@ -277,7 +278,10 @@ __device__ void accept_point(const ColDev& C, double* red, int* done_count) {
     C.Fn[i] = C.F[i];
   }
   if (C.has_sca)
-    for (int i = threadIdx.x; i < C.nz * C.nnu; i += kThreads) C.Jdag[i] = C.Jeval[i];
+    for (int i = threadIdx.x; i < C.nz * C.nnu; i += kThreads) {
+      const int k = i / C.nnu, f = i - k * C.nnu;
+      C.Jdag[i] = C.JT[(size_t)f * C.nz + k];
+    }
   __syncthreads();
   if (threadIdx.x == 0) st->rho_cur = rho;
   if (rho != rho || isinf(rho)) {
@@ -604,6 +608,8 @@ namespace {
 struct Batch {
   ColDev* cols = nullptr;       // device array of column descriptors
   Tile* tiles = nullptr;
+  int4* rate = nullptr;
+  int4* prec = nullptr;
   double** n0 = nullptr;
   double** nout = nullptr;
   int* done = nullptr;
@@ -612,6 +618,8 @@ struct Batch {
   ~Batch() {
     if (cols) hipFree(cols);
     if (tiles) hipFree(tiles);
+    if (rate) hipFree(rate);
+    if (prec) hipFree(prec);
     if (n0) hipFree(n0);
     if (nout) hipFree(nout);
     if (done) hipFree(done);
@@ -638,19 +646,37 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   b.ncol = ncol;
   std::vector<ColDev> hc(ncol);
   std::vector<Tile> tiles;
+  std::vector<int4> rate_w, prec_w;
   for (int c = 0; c < ncol; ++c) {
     if (!cols[c]) return set_err(NLTE_E_INVALID, "column %d is NULL", c);
     if (column_ctx(cols[c]) != ctx) return set_err(NLTE_E_INVALID, "column %d from another context", c);
     hc[c] = column_dev(cols[c]);
     b.maxL = std::max(b.maxL, hc[c].L);
     if (hc[c].prec == NLTE_FP64) b.any64 = 1; else b.any32 = 1;
-    for (int ch = 0; ch < hc[c].nchunk; ++ch) tiles.push_back(Tile{c, ch});
     for (int d = 0; d < c; ++d)
       if (cols[d] == cols[c]) return set_err(NLTE_E_INVALID, "column %d appears twice", c);
   }
+  build_work_lists(hc.data(), ncol, tiles, rate_w, prec_w, b.maxL);
   b.ntiles = (int)tiles.size();
   HIP_TRY(hipMalloc(&b.cols, ncol * sizeof(ColDev)));
   HIP_TRY(hipMalloc(&b.tiles, tiles.size() * sizeof(Tile)));
+  HIP_TRY(hipMalloc(&b.rate, std::max<size_t>(1, rate_w.size()) * sizeof(int4)));
+  HIP_TRY(hipMalloc(&b.prec, std::max<size_t>(1, prec_w.size()) * sizeof(int4)));
+  HIP_TRY(hipMemcpyAsync(b.rate, rate_w.data(), rate_w.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b.prec, prec_w.data(), prec_w.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  BatchWork bw;
+  bw.cols = b.cols;
+  bw.tiles = b.tiles;
+  bw.rate_work = b.rate;
+  bw.prec_work = b.prec;
+  bw.ncol = ncol;
+  bw.ntiles = b.ntiles;
+  bw.nrate = (int)rate_w.size();
+  bw.nprec = (int)prec_w.size();
+  bw.any64 = b.any64;
+  bw.any32 = b.any32;
+  bw.any_newton = 1;
+
   HIP_TRY(hipMalloc(&b.nout, ncol * sizeof(double*)));
   HIP_TRY(hipMalloc(&b.done, sizeof(int)));
   HIP_TRY(hipHostMalloc(&b.done_host, sizeof(int)));
@@ -685,8 +711,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   while (step < max_steps) {
     for (int r = 0; r < check_every; ++r, ++step) {
       hipEvent_t* e = prof ? &ev[5 * r] : nullptr;
-      hipError_t he = launch_residual(b.cols, ncol, b.tiles, b.ntiles, b.any64, b.any32, 1,
-                                      b.maxL, s, e);
+      hipError_t he = launch_residual(bw, s, e);
       k_solver_step<<<ncol, kThreads, 0, s>>>(b.cols, b.done);
       if (prof) hipEventRecord(e[4], s);
       if (he == hipSuccess) he = hipGetLastError();
@@ -705,8 +730,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
         ctx->prof.steps += 1;
         ctx->prof.formal_launches += (b.any64 + b.any32);
         ctx->prof.formal_ms += t[0];
-        ctx->prof.newton_launches += (b.any64 + b.any32);
-        ctx->prof.newton_ms += t[1];
+        ctx->prof.depth_ms += t[1];
         ctx->prof.assemble_ms += t[2];
         ctx->prof.solver_ms += t[3];
       }
@@ -758,7 +782,8 @@ extern "C" nlte_status nlte_solve(nlte_column* col, const double* n0_dev, const 
                                     stats, s);
   if (J_out_dev && (st == NLTE_OK || st == NLTE_E_NOCONV)) {
     const ColDev& C = column_dev(col);
-    HIP_TRY(hipMemcpyAsync(J_out_dev, C.Jeval, (size_t)C.nz * C.nnu * 8, hipMemcpyDeviceToDevice, s));
+    transpose_J(C, J_out_dev, s);
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
   }
   return st;
