@@ -386,7 +386,7 @@ static nlte_status validate(const nlte_atmos_desc* A, const nlte_atom_desc* M,
 struct WorkPtrs {
   Tile* tiles;
   int4* rate;
-  int4* prec;
+  int2* pb;
 };
 
 static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, int nline_tab,
@@ -421,6 +421,8 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.ch_lptr = Lo.take<int>(C.nchunk + 1);
   C.ch_line = Lo.take<int>(nentries);
   C.pairs = Lo.take<int4>(std::max(C.npair, 1));
+  C.pg_ptr = Lo.take<int>(L * L + 1);
+  C.pg_code = Lo.take<int>(4 * ntr + 4 * std::max(C.npair, 1));
   C.eval_n = Lo.take<double>(N);
   C.F = Lo.take<double>(N);
   C.G = Lo.take<double>(N);
@@ -440,6 +442,7 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.Gsave = Lo.take<double>(nz);
   C.Psave = Lo.take<double>((size_t)nz * L);
   C.R = Lo.take<double>((size_t)nz * ntr * 2);
+  C.Rtot = Lo.take<double>((size_t)nz * ntr * 2);
   C.rho_k = Lo.take<double>(nz);
   C.rows = Lo.take<int>(nz);
   C.rows_frozen = Lo.take<int>(nz);
@@ -459,7 +462,7 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   *lbase = Lo.take<int>(std::max(C.nline, 1) + 1);
   wp->tiles = Lo.take<Tile>(wsz[0]);
   wp->rate = Lo.take<int4>(wsz[1]);
-  wp->prec = Lo.take<int4>(wsz[2]);
+  wp->pb = Lo.take<int2>(std::max(wsz[2], 1));
   *stage = Lo.take<int>(L);
   *bf_ptr = Lo.take<int>(C.nbf + 1);
   // raw setup inputs (doubles): E, g, A_ul, a_damp, bf_nu, bf_alpha, C_up
@@ -549,13 +552,39 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
       if (b > a) pairs.push_back(make_int4(t, u, a, b));
     }
   C.npair = (int)pairs.size();
+  // gather lists of the preconditioner blocks: entry (i, j) sums
+  //   Gamma: (lo,lo) += C_lu+R_lu, (up,up) += C_ul+R_ul, (lo,up) -= C_ul+R_ul, (up,lo) -= C_lu+R_lu
+  //   pairs: (lo_t,lo_u) += M1, (up_t,lo_u) -= M1, (lo_t,up_u) += M2, (up_t,up_u) -= M2
+  // code = (index << 3) | (kind << 1) | negate; kind 0/1: total up/down rate, 2/3: M1/M2
+  std::vector<std::vector<int>> gl(L * L);
+  for (int t = 0; t < ntr; ++t) {
+    const int lo = tr[t].lo, up = tr[t].up;
+    gl[lo * L + lo].push_back((t << 3) | (0 << 1) | 0);
+    gl[up * L + up].push_back((t << 3) | (1 << 1) | 0);
+    gl[lo * L + up].push_back((t << 3) | (1 << 1) | 1);
+    gl[up * L + lo].push_back((t << 3) | (0 << 1) | 1);
+  }
+  for (int q = 0; q < C.npair; ++q) {
+    const TrDev& Tt = tr[pairs[q].x];
+    const TrDev& Tu = tr[pairs[q].y];
+    gl[Tt.lo * L + Tu.lo].push_back((q << 3) | (2 << 1) | 0);
+    gl[Tt.up * L + Tu.lo].push_back((q << 3) | (2 << 1) | 1);
+    gl[Tt.lo * L + Tu.up].push_back((q << 3) | (3 << 1) | 0);
+    gl[Tt.up * L + Tu.up].push_back((q << 3) | (3 << 1) | 1);
+  }
+  std::vector<int> pg_ptr(L * L + 1, 0), pg_code;
+  for (int e = 0; e < L * L; ++e) {
+    pg_code.insert(pg_code.end(), gl[e].begin(), gl[e].end());
+    pg_ptr[e + 1] = (int)pg_code.size();
+  }
   const int nentries = std::max<int>(1, (int)ch_tr.size());
   int nbf_tot = nbf ? M->bf_ptr[nbf] : 0;
   const int m_cap = 32;
 
   // single-column work lists
   std::vector<Tile> tiles;
-  std::vector<int4> rate_w, prec_w;
+  std::vector<int4> rate_w;
+  std::vector<int2> prec_w;
   int maxL_w = 0;
   build_work_lists(&C, 1, tiles, rate_w, prec_w, maxL_w);
   const int wsz[3] = {(int)tiles.size(), (int)rate_w.size(), (int)prec_w.size()};
@@ -613,7 +642,9 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   UP(C.ch_line, ch_tr.data(), ch_tr.size() * 4);
   UP(C.pairs, pairs.data(), pairs.size() * sizeof(int4));
   UP(wp.rate, rate_w.data(), rate_w.size() * sizeof(int4));
-  UP(wp.prec, prec_w.data(), prec_w.size() * sizeof(int4));
+  UP(wp.pb, prec_w.data(), prec_w.size() * sizeof(int2));
+  UP(C.pg_ptr, pg_ptr.data(), pg_ptr.size() * 4);
+  UP(C.pg_code, pg_code.data(), pg_code.size() * 4);
   UP(wbase_d, wbase.data(), wbase.size() * 4);
   UP(lbase_d, lbase.data(), lbase.size() * 4);
   UP(wp.tiles, tiles.data(), tiles.size() * sizeof(Tile));
@@ -670,11 +701,11 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   col->bw.cols = col->d;
   col->bw.tiles = wp.tiles;
   col->bw.rate_work = wp.rate;
-  col->bw.prec_work = wp.prec;
+  col->bw.pb_work = wp.pb;
   col->bw.ncol = 1;
   col->bw.ntiles = wsz[0];
   col->bw.nrate = wsz[1];
-  col->bw.nprec = wsz[2];
+  col->bw.npb = wsz[2];
   col->bw.any64 = prec == NLTE_FP64;
   col->bw.any32 = prec == NLTE_FP32_FORM;
   col->bw.any_newton = 1;

@@ -118,6 +118,7 @@ struct ColDev {
   // chunk -> overlapping line windows; overlapping transition pairs
   const int *ch_lptr, *ch_line;
   const int4 *pairs;               // (t, t', first, last + 1) of each window intersection
+  const int *pg_ptr, *pg_code;     // per block entry (i, j): contributions, see k_pblock
   // evaluation buffers
   ColState *st;
   double *eval_n;                  // [nz][L] populations to evaluate F at
@@ -135,6 +136,7 @@ struct ColDev {
   double *Fsave, *Gsave;           // [nz] rate-row F and gross rate under each conservation row
   double *Psave;                   // [nz][L] preconditioner row under each conservation row
   double *R;                       // [nz][ntr][2] radiative rates of the last evaluation
+  double *Rtot;                    // [nz][ntr][2] C_lu + R_lu, C_ul + R_ul
   double *rho_k;                   // [nz] max scaled residual per depth
   int *rows;                       // [nz] conservation rows used by the last evaluation
   int *rows_frozen;                // [nz] rows for kModeF evaluations
@@ -164,8 +166,8 @@ struct BatchWork {
   const ColDev* cols = nullptr;   // device array [ncol]
   const Tile* tiles = nullptr;    // formal-solution chunks
   const int4* rate_work = nullptr;  // (col, transition, first depth, -)
-  const int4* prec_work = nullptr;  // (col, pair, first depth, -)
-  int ncol = 0, ntiles = 0, nrate = 0, nprec = 0;
+  const int2* pb_work = nullptr;  // (col, first depth-entry index)
+  int ncol = 0, ntiles = 0, nrate = 0, npb = 0;
   int any64 = 0, any32 = 0, any_newton = 1;
 };
 
@@ -176,7 +178,7 @@ struct BatchWork {
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev = nullptr);
 
 void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
-                      std::vector<int4>& rate, std::vector<int4>& prec, int& maxL);
+                      std::vector<int4>& rate, std::vector<int2>& pblock, int& maxL);
 
 }  // namespace nlte
 

@@ -462,6 +462,7 @@ __device__ __forceinline__ void precond_item(const ColDev& C, int p, int k0) {
   const double nl = C.eval_n[k * L + uni(Tt.lo)], nu_ = C.eval_n[k * L + uni(Tt.up)];
   const bool edge = t >= C.nline || u >= C.nline;
   double m1 = 0.0, m2 = 0.0;
+#pragma unroll 4
   for (int q = f0; q < f1; ++q) {
     const size_t fk = (size_t)q * nz + k;
     const double E = edge ? ldg(C.EbfT + fk) : 0.0;
@@ -498,11 +499,13 @@ __global__ __launch_bounds__(64) void k_depthwork(const ColDev* __restrict__ col
 // ---------------------------------------------------------------------------
 // assembly: rates, F rows, conservation rows, rho, preconditioner blocks
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_assemble(const ColDev* __restrict__ cols) {
-  __shared__ double sF[kWave][kMaxLev + 1];
-  __shared__ double sG[kWave][kMaxLev + 1];
+constexpr int kAsmThreads = 128;
+
+__global__ __launch_bounds__(kAsmThreads) void k_assemble(const ColDev* __restrict__ cols) {
+  __shared__ double sF[kAsmThreads][kMaxLev + 1];
+  __shared__ double sG[kAsmThreads][kMaxLev + 1];
   const ColDev& C = cols[blockIdx.x];
-  const int mode = C.st->mode;
+  const int mode = uni(C.st->mode);
   if (mode == kModeIdle) return;
   const int nz = C.nz, L = C.L, ntr = C.ntr, nline = C.nline;
   const int tx = threadIdx.x;
@@ -515,47 +518,30 @@ __global__ __launch_bounds__(64) void k_assemble(const ColDev* __restrict__ cols
       Fk[i] = 0.0;
       Gk[i] = 0.0;
     }
-    double* Pk = C.P + (size_t)k * L * L;
-    if (mode == kModeNewton) {
-      for (int p = 0; p < L * L; ++p) Pk[p] = 0.0;
-      for (int p = 0; p < C.npair; ++p) {
-        const int4 pr = C.pairs[p];
-        const TrDev& Tt = C.tr[pr.x];
-        const TrDev& Tu = C.tr[pr.y];
-        const double m1 = C.M[((size_t)k * C.npair + p) * 2];
-        const double m2 = C.M[((size_t)k * C.npair + p) * 2 + 1];
-        Pk[Tt.lo * L + Tu.lo] += m1;
-        Pk[Tt.up * L + Tu.lo] -= m1;
-        Pk[Tt.lo * L + Tu.up] += m2;
-        Pk[Tt.up * L + Tu.up] -= m2;
-      }
-    }
     for (int t = 0; t < ntr; ++t) {
-      const TrDev T = C.tr[t];
+      const TrDev& T = C.tr[t];
+      const int lo = uni(T.lo), up = uni(T.up);
       const double* rj = C.RJ + ((size_t)k * ntr + t) * 2;
       const double Rlu = rj[0];
       const double Rsp = C.Rsp[k * ntr + t];
-      const double Rul = (t < nline) ? T.g * (Rsp + Rlu)
+      const double Rul = (t < nline) ? uni(T.g) * (Rsp + Rlu)
                                      : C.rho_bf[k * C.nbf + (t - nline)] * (Rsp + rj[1]);
-      C.R[((size_t)k * ntr + t) * 2 + 0] = Rlu;
-      C.R[((size_t)k * ntr + t) * 2 + 1] = Rul;
+      double* R = C.R + ((size_t)k * ntr + t) * 2;
+      R[0] = Rlu;
+      R[1] = Rul;
       const double up_rate = C.C_lu[k * ntr + t] + Rlu;
       const double dn_rate = C.C_ul[k * ntr + t] + Rul;
-      const double out_l = nk[T.lo] * up_rate;
-      const double out_u = nk[T.up] * dn_rate;
+      double* Rt = C.Rtot + ((size_t)k * ntr + t) * 2;
+      Rt[0] = up_rate;
+      Rt[1] = dn_rate;
+      const double out_l = nk[lo] * up_rate;
+      const double out_u = nk[up] * dn_rate;
       const double kap = out_l - out_u;
-      Fk[T.lo] += kap;
-      Fk[T.up] -= kap;
+      Fk[lo] += kap;
+      Fk[up] -= kap;
       const double gross = fabs(out_l) + fabs(out_u);
-      Gk[T.lo] += gross;
-      Gk[T.up] += gross;
-      if (mode == kModeNewton) {
-        // Gamma_ij = delta_ij sum_p (C_ip + R_ip) - (C_ji + R_ji)
-        Pk[T.lo * L + T.lo] += up_rate;
-        Pk[T.up * L + T.up] += dn_rate;
-        Pk[T.lo * L + T.up] -= dn_rate;
-        Pk[T.up * L + T.lo] -= up_rate;
-      }
+      Gk[lo] += gross;
+      Gk[up] += gross;
     }
     int r;
     if (C.st->rows_own) {
@@ -578,11 +564,6 @@ __global__ __launch_bounds__(64) void k_assemble(const ColDev* __restrict__ cols
     C.Gsave[k] = Gk[r];
     Fk[r] = C.ntot[k] - sum;
     Gk[r] = C.ntot[k];
-    if (mode == kModeNewton)
-      for (int j = 0; j < L; ++j) {
-        C.Psave[k * L + j] = Pk[r * L + j];
-        Pk[r * L + j] = -1.0;
-      }
     double rk = 0.0;
     for (int i = 0; i < L; ++i) {
       C.F[k * L + i] = Fk[i];
@@ -594,10 +575,10 @@ __global__ __launch_bounds__(64) void k_assemble(const ColDev* __restrict__ cols
     rmax = (rk > rmax || rk != rk) ? rk : rmax;
   }
   // block max (NaN-propagating)
-  __shared__ double sm[64];
+  __shared__ double sm[kAsmThreads];
   sm[tx] = rmax;
   __syncthreads();
-  for (int o = 32; o > 0; o >>= 1) {
+  for (int o = kAsmThreads / 2; o > 0; o >>= 1) {
     if (tx < o) {
       const double a = sm[tx], b = sm[tx + o];
       sm[tx] = (b > a || b != b) ? b : a;
@@ -605,6 +586,39 @@ __global__ __launch_bounds__(64) void k_assemble(const ColDev* __restrict__ cols
     __syncthreads();
   }
   if (tx == 0) C.st->rho_eval = sm[0];
+}
+
+// Preconditioner blocks of Newton-mode columns: one thread per (depth, entry)
+// gathers its contributions (Gamma from the total rates, the radiative part
+// from the pair sums) from a per-column list, then the conservation row of
+// the depth becomes -1 (the original row is kept in Psave).
+__global__ __launch_bounds__(256) void k_pblock(const ColDev* __restrict__ cols,
+                                                const int2* __restrict__ work, int nwork) {
+  const int w = blockIdx.x;
+  if (w >= nwork) return;
+  const int col = uni(work[w].x), base = uni(work[w].y);
+  const ColDev& C = cols[col];
+  if (uni(C.st->mode) != kModeNewton) return;
+  const int L = C.L, LL = L * L;
+  const int id = base + threadIdx.x;
+  if (id >= C.nz * LL) return;
+  const int k = id / LL, ij = id - k * LL;
+  const int i = ij / L, j = ij - i * L;
+  const double* Rt = C.Rtot + (size_t)k * C.ntr * 2;
+  const double* Mk = C.M + (size_t)k * C.npair * 2;
+  double s = 0.0;
+  for (int e = C.pg_ptr[ij]; e < C.pg_ptr[ij + 1]; ++e) {
+    const int code = C.pg_code[e];
+    const int kind = (code >> 1) & 3, idx = code >> 3;
+    const double v = kind < 2 ? Rt[idx * 2 + kind] : Mk[idx * 2 + (kind - 2)];
+    s += (code & 1) ? -v : v;
+  }
+  const int r = C.rows[k];
+  if (i == r) {
+    C.Psave[k * L + j] = s;
+    s = -1.0;
+  }
+  C.P[(size_t)k * LL + ij] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -620,7 +634,8 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   if (ev) hipEventRecord(ev[1], s);
   if (bw.nrate > 0) k_depthwork<<<bw.nrate, 64, 0, s>>>(bw.cols, bw.rate_work, bw.nrate);
   if (ev) hipEventRecord(ev[2], s);
-  k_assemble<<<bw.ncol, 64, 0, s>>>(bw.cols);
+  k_assemble<<<bw.ncol, kAsmThreads, 0, s>>>(bw.cols);
+  if (bw.any_newton && bw.npb > 0) k_pblock<<<bw.npb, 256, 0, s>>>(bw.cols, bw.pb_work, bw.npb);
   if (ev) hipEventRecord(ev[3], s);
   return hipGetLastError();
 }
@@ -628,11 +643,11 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
 // Work lists of a batch (host side): formal-solution tiles, rate items and
 // preconditioner items for every column.
 void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
-                      std::vector<int4>& rate, std::vector<int4>& prec, int& maxL) {
-  // rate items (kind 0) and preconditioner items (kind 1) share one list;
-  // prec stays empty
+                      std::vector<int4>& rate, std::vector<int2>& pblock, int& maxL) {
+  // rate items (kind 0) and preconditioner pair items (kind 1) share one list
   maxL = 0;
-  (void)prec;
+  for (int c = 0; c < ncol; ++c)
+    for (int b = 0; b < hc[c].nz * hc[c].L * hc[c].L; b += 256) pblock.push_back(make_int2(c, b));
   for (int c = 0; c < ncol; ++c) {
     const ColDev& C = hc[c];
     maxL = std::max(maxL, C.L);

@@ -609,7 +609,7 @@ struct Batch {
   ColDev* cols = nullptr;       // device array of column descriptors
   Tile* tiles = nullptr;
   int4* rate = nullptr;
-  int4* prec = nullptr;
+  int2* prec = nullptr;
   double** n0 = nullptr;
   double** nout = nullptr;
   int* done = nullptr;
@@ -646,7 +646,8 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   b.ncol = ncol;
   std::vector<ColDev> hc(ncol);
   std::vector<Tile> tiles;
-  std::vector<int4> rate_w, prec_w;
+  std::vector<int4> rate_w;
+  std::vector<int2> prec_w;
   for (int c = 0; c < ncol; ++c) {
     if (!cols[c]) return set_err(NLTE_E_INVALID, "column %d is NULL", c);
     if (column_ctx(cols[c]) != ctx) return set_err(NLTE_E_INVALID, "column %d from another context", c);
@@ -661,18 +662,18 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   HIP_TRY(hipMalloc(&b.cols, ncol * sizeof(ColDev)));
   HIP_TRY(hipMalloc(&b.tiles, tiles.size() * sizeof(Tile)));
   HIP_TRY(hipMalloc(&b.rate, std::max<size_t>(1, rate_w.size()) * sizeof(int4)));
-  HIP_TRY(hipMalloc(&b.prec, std::max<size_t>(1, prec_w.size()) * sizeof(int4)));
+  HIP_TRY(hipMalloc(&b.prec, std::max<size_t>(1, prec_w.size()) * sizeof(int2)));
   HIP_TRY(hipMemcpyAsync(b.rate, rate_w.data(), rate_w.size() * sizeof(int4), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(b.prec, prec_w.data(), prec_w.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b.prec, prec_w.data(), prec_w.size() * sizeof(int2), hipMemcpyHostToDevice, s));
   BatchWork bw;
   bw.cols = b.cols;
   bw.tiles = b.tiles;
   bw.rate_work = b.rate;
-  bw.prec_work = b.prec;
+  bw.pb_work = b.prec;
   bw.ncol = ncol;
   bw.ntiles = b.ntiles;
   bw.nrate = (int)rate_w.size();
-  bw.nprec = (int)prec_w.size();
+  bw.npb = (int)prec_w.size();
   bw.any64 = b.any64;
   bw.any32 = b.any32;
   bw.any_newton = 1;
