@@ -82,6 +82,19 @@ def cpu_baseline(workload, ncol, ftol, rtol, budget_s=20.0):
     }
 
 
+def copy_calibration(nbytes=256 << 20, reps=3):
+    """A plain elementwise copy (y = 1.0 * x, fp32) of known size: it reads and
+    writes nbytes each, so HBM byte counters read for it give their scale."""
+    import torch
+    x = torch.rand(nbytes // 4, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,7 +104,12 @@ def main():
     ap.add_argument("--ncol", type=int, default=None)
     ap.add_argument("--rtol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy kernel (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); columns are "
               f"independent, so several GPUs would each run their own share of the batch.",
