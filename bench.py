@@ -34,6 +34,26 @@ PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
 # reciprocal (shared by the two rays of an angle), transcendental at 1/4 rate
 OPS_PER_DP = 10.0 + 0.5 * 4 + 0.5 * 4
 
+# HBM bytes per k_formal launch from FETCH_SIZE / WRITE_SIZE counter runs of
+# this workload, each scaled by the same counter on a plain copy kernel; valid
+# only for the kernel source they were taken on (hash of its files).
+TRAFFIC = {
+    "batch6": {"source": "62ede18f0d1082d0", "bytes_per_launch": 2.268e9 + 2.703e9,
+               "read": 2.268e9, "written": 2.703e9},
+}
+KERNEL_SOURCES = ["paper_2406_17234_amd/csrc/nlte_residual.hip",
+                  "paper_2406_17234_amd/csrc/nlte_internal.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 WORKLOADS = {
     # name: (description, maker(i), ncol default, precision, ftol)
     "batch6": ("4096 chromosphere columns, 6-level atom (5 lines + 5 edges), "
@@ -166,6 +186,9 @@ def main():
     # the formal-solution launch covers every residual call of the step
     achieved = total_dp * OPS_PER_DP / (prof["formal_ms"] * 1e-3) / 1e12 if prof["formal_ms"] > 0 else None
     peak = PEAK_VALU_OPS / 1e12
+    tr = TRAFFIC.get(args.workload)
+    traffic = tr["bytes_per_launch"] if (tr and tr["source"] == kernel_source_hash()
+                                         and args.ncol is None) else None
     out = {
         "metric": "formal-solution depth-points/s",
         "value": value,
@@ -197,7 +220,8 @@ def main():
             "unit": "TOP/s",
             "frac": (achieved / peak) if achieved else None,
             "ops_per_depth_point": OPS_PER_DP,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (mean)",
         },
         "cpu_baseline": cpu,
     }
