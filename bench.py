@@ -123,6 +123,9 @@ def main():
     ap.add_argument("--workload", default="batch6", choices=list(WORKLOADS))
     ap.add_argument("--ncol", type=int, default=None)
     ap.add_argument("--rtol", type=float, default=1e-3)
+    ap.add_argument("--max-krylov-total", type=int, default=200,
+                    help="Krylov budget per column solve (0: none); bounds the cost of columns "
+                         "that do not converge, which otherwise set the length of the batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy kernel (calibrates HBM byte counters)")
@@ -157,7 +160,8 @@ def main():
     setup_s = time.perf_counter() - t0
     print(f"[bench] created {ncol} columns in {setup_s:.1f} s", file=sys.stderr, flush=True)
     dp_col = np.array([p.depth_points() for p in problems], dtype=np.float64)
-    opts = nlte.default_opts(ftol=ftol, rtol=args.rtol, maxiter=50)
+    opts = nlte.default_opts(ftol=ftol, rtol=args.rtol, maxiter=50,
+                             max_krylov_total=args.max_krylov_total)
 
     for w in range(args.warmup):
         _, st, rc = nlte.solve_batch(ctx, cols, opts)
@@ -203,7 +207,8 @@ def main():
         "dtype": "f32+f64" if prec == 1 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "columns": ncol,
-                   "ftol": ftol, "rtol": args.rtol,
+                   "ftol": ftol, "rtol": args.rtol, "maxiter": 50,
+                   "max_krylov_total": args.max_krylov_total,
                    "mean_nz": float(np.mean([p.atmos.nz for p in problems])),
                    "mean_nnu": float(np.mean([p.grid.nnu for p in problems]))},
         "columns_converged_per_s": float(conv.sum()) / elapsed,

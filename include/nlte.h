@@ -114,6 +114,10 @@ typedef struct {
   int32_t max_halvings;/* line-search halvings (default 8)                      */
   int32_t init;        /* 0: n0 given, 1: LTE, 2: zero radiation                */
   double eps_scale;    /* multiplies the difference step (default 1)            */
+  int32_t max_krylov_total; /* Krylov iterations over the whole solve; once spent,
+                          * each Newton iteration takes one Krylov step (a
+                          * preconditioned residual step).  0: no limit (default) */
+  int32_t reserved;    /* 0                                                      */
 } nlte_solve_opts;
 
 typedef struct {

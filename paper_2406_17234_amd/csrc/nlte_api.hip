@@ -96,6 +96,8 @@ extern "C" void nlte_solve_opts_default(nlte_solve_opts* o) {
   o->rtol = 1e-3;
   o->maxiter = 50;
   o->max_krylov = 200;
+  o->max_krylov_total = 0;
+  o->reserved = 0;
   o->restart = 30;
   o->max_halvings = 8;
   o->init = 1;
@@ -390,7 +392,7 @@ struct WorkPtrs {
 };
 
 static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, int nline_tab,
-                          int nbf_tot, int nentries, int m_cap, TrDev** tr_out, int** wbase,
+                          int nbf_tot, int nentries, int nentries_e, int m_cap, TrDev** tr_out, int** wbase,
                           int** lbase, WorkPtrs* wp, const int* wsz, int** stage, int** bf_ptr,
                           double** raw) {
   const int nz = C.nz, L = C.L, ntr = C.ntr, nnu = C.nnu, N = C.N;
@@ -420,6 +422,9 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.nstar = Lo.take<double>((size_t)nz * L);
   C.ch_lptr = Lo.take<int>(C.nchunk + 1);
   C.ch_line = Lo.take<int>(nentries);
+  C.ch_eptr = Lo.take<int>(C.nchunk + 1);
+  C.ch_edge = Lo.take<int>(nentries_e);
+  C.coef = Lo.take<double>((size_t)nz * ncoef(ntr));
   C.pairs = Lo.take<int4>(std::max(C.npair, 1));
   C.pg_ptr = Lo.take<int>(L * L + 1);
   C.pg_code = Lo.take<int>(4 * ntr + 4 * std::max(C.npair, 1));
@@ -493,6 +498,8 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   for (int m = 0; m < kMaxMu; ++m) {
     C.wm2[m] = m < nmu ? 0.5 * G->w_mu[m] : 0.0;
     C.inv2mu[m] = m < nmu ? 0.5 / G->mu[m] : 0.0;
+    C.wm2f[m] = (float)C.wm2[m];
+    C.inv2muf[m] = (float)C.inv2mu[m];
   }
   // transitions, windows, chunk lists
   std::vector<TrDev> tr(ntr);
@@ -545,6 +552,16 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
       return set_err(NLTE_E_INVALID, "more than %d line windows overlap frequencies %d..%d",
                      kMaxChunkLines, f0, f1 - 1);
   }
+  std::vector<int> ch_eptr(C.nchunk + 1, 0), ch_ed;
+  for (int c = 0; c < C.nchunk; ++c) {
+    const int f0 = c * kWave, f1 = std::min(nnu, f0 + kWave);
+    for (int t = nline; t < ntr; ++t)
+      if (tr[t].wlo < f1 && tr[t].whi > f0) ch_ed.push_back(t);
+    ch_eptr[c + 1] = (int)ch_ed.size();
+    if (ch_eptr[c + 1] - ch_eptr[c] > kMaxChunkEdges)
+      return set_err(NLTE_E_INVALID, "more than %d edge windows overlap frequencies %d..%d",
+                     kMaxChunkEdges, f0, f1 - 1);
+  }
   std::vector<int4> pairs;
   for (int t = 0; t < ntr; ++t)
     for (int u = 0; u < ntr; ++u) {
@@ -578,6 +595,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     pg_ptr[e + 1] = (int)pg_code.size();
   }
   const int nentries = std::max<int>(1, (int)ch_tr.size());
+  const int nentries_e = std::max<int>(1, (int)ch_ed.size());
   int nbf_tot = nbf ? M->bf_ptr[nbf] : 0;
   const int m_cap = 32;
 
@@ -586,7 +604,8 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   std::vector<int4> rate_w;
   std::vector<int2> prec_w;
   int maxL_w = 0;
-  build_work_lists(&C, 1, tiles, rate_w, prec_w, maxL_w);
+  std::vector<TileGroup> groups;
+  build_work_lists(&C, 1, tiles, groups, rate_w, prec_w, maxL_w);
   const int wsz[3] = {(int)tiles.size(), (int)rate_w.size(), (int)prec_w.size()};
 
   // layout
@@ -598,7 +617,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   Layout sizer(nullptr);
   {
     ColDev tmp = C;
-    layout_column(sizer, tmp, in, wbase[ntr], nline_tab, nbf_tot, nentries, m_cap, &tr_d,
+    layout_column(sizer, tmp, in, wbase[ntr], nline_tab, nbf_tot, nentries, nentries_e, m_cap, &tr_d,
                   &wbase_d, &lbase_d, &wp, wsz, &stage_d, &bfptr_d, &raw_d);
   }
   nlte_column* col = new nlte_column();
@@ -610,7 +629,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     return set_err(NLTE_E_NOMEM, "hipMalloc(%zu) failed: %s", sizer.off, hipGetErrorString(he));
   }
   Layout lay(col->arena);
-  layout_column(lay, C, in, wbase[ntr], nline_tab, nbf_tot, nentries, m_cap, &tr_d, &wbase_d,
+  layout_column(lay, C, in, wbase[ntr], nline_tab, nbf_tot, nentries, nentries_e, m_cap, &tr_d, &wbase_d,
                 &lbase_d, &wp, wsz, &stage_d, &bfptr_d, &raw_d);
   col->restart_cap = m_cap;
   col->Blu = Blu;
@@ -640,6 +659,8 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   UP(tr_d, tr.data(), ntr * sizeof(TrDev));
   UP(C.ch_lptr, ch_ptr.data(), ch_ptr.size() * 4);
   UP(C.ch_line, ch_tr.data(), ch_tr.size() * 4);
+  UP(C.ch_eptr, ch_eptr.data(), ch_eptr.size() * 4);
+  UP(C.ch_edge, ch_ed.data(), ch_ed.size() * 4);
   UP(C.pairs, pairs.data(), pairs.size() * sizeof(int4));
   UP(wp.rate, rate_w.data(), rate_w.size() * sizeof(int4));
   UP(wp.pb, prec_w.data(), prec_w.size() * sizeof(int2));
@@ -709,6 +730,9 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   col->bw.any64 = prec == NLTE_FP64;
   col->bw.any32 = prec == NLTE_FP32_FORM;
   col->bw.any_newton = 1;
+  col->bw.ngroup = (int)groups.size();
+  for (int g = 0; g < col->bw.ngroup; ++g) col->bw.groups[g] = groups[g];
+  col->bw.maxnz = nz;
 
   *out = col;
   return NLTE_OK;

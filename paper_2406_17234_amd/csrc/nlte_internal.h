@@ -24,7 +24,8 @@ constexpr int kWave = 64;       // lanes per wavefront (CDNA)
 constexpr int kMaxMu = 8;       // angles per hemisphere held in registers
 constexpr int kMaxLev = 16;     // levels per atom
 constexpr int kMaxRestart = 64; // GMRES restart length
-constexpr int kMaxChunkLines = 4;  // line windows overlapping one 64-frequency chunk
+constexpr int kMaxChunkLines = 6;  // line windows overlapping one 64-frequency chunk
+constexpr int kMaxChunkEdges = 8;  // edge windows overlapping one 64-frequency chunk
 constexpr int kMaxEdges = kMaxLev - 1;
 
 // Loads and stores through the global address space (the pointers live in
@@ -91,7 +92,9 @@ struct ColState {
   double phi0;      // ||D^-1 P^-1 F|| at the iterate (line-search reference)
   double ftol, rtol, eps_mach, eps_scale;
   int maxiter, max_krylov, restart, max_halvings;
-  int init_kind, done_flag, pad1, pad2;
+  int init_kind, done_flag;
+  int krylov_step;  // Krylov iterations of the current Newton step
+  int max_krylov_total;  // 0: no limit
 };
 
 struct ColDev {
@@ -100,6 +103,7 @@ struct ColDev {
   // angles (inline: at most kMaxMu)
   double wm2[kMaxMu];     // w_m / 2
   double inv2mu[kMaxMu];  // 1 / (2 mu_m)
+  float wm2f[kMaxMu], inv2muf[kMaxMu];  // the same, FP32 form
   // atmosphere
   const double *z, *dz, *T, *ne, *ntot, *chi_c, *chi_sca;
   // frequency grid and per-(k, f) tables [nz][nnu]
@@ -115,19 +119,23 @@ struct ColDev {
   const double *Rsp;               // [nz][ntr] n-independent part of R_ul
   const double *C_lu, *C_ul;       // [nz][ntr]
   const double *nstar;             // [nz][L]
-  // chunk -> overlapping line windows; overlapping transition pairs
+  // chunk -> overlapping line windows and edge windows; overlapping transition pairs
   const int *ch_lptr, *ch_line;
+  const int *ch_eptr, *ch_edge;
   const int4 *pairs;               // (t, t', first, last + 1) of each window intersection
   const int *pg_ptr, *pg_code;     // per block entry (i, j): contributions, see k_pblock
   // evaluation buffers
   ColState *st;
   double *eval_n;                  // [nz][L] populations to evaluate F at
+  double *coef;                    // [ntr + 2][nz][2] level coefficients of eval_n
   double *F, *G;                   // [nz][L] residual and gross rates
   double *Jdag;                    // [nz][nnu] lagged mean intensity
   double *JT;                      // [nnu][nz] J of the last evaluation (depth-contiguous)
-  double *Jm;                      // [nz][nnu] scratch: ingoing-ray part of J
-  double *XS;                      // [nz][nnu][2] scratch: chi and S of the first sweep
-  double *Dchi, *Deta;             // [nz][nnu] scratch: ingoing-ray intensity derivatives
+  // scratch of the formal solution, in the column's formal-solution precision
+  // (buffers sized for doubles):
+  double *Jm;                      // [nz][nnu] ingoing-ray part of J
+  double *XS;                      // [nz][nnu][2] chi and S of the first sweep
+  double *Dchi, *Deta;             // [nz][nnu] ingoing-ray intensity derivatives
   double *DchiT, *DetaT;           // [nnu][nz] angle-averaged local intensity derivatives
   double *RJ;                      // [nz][ntr][2] rate integrals over J
   double *M;                       // [nz][npair][2] pair sums of the radiative blocks
@@ -161,10 +169,22 @@ struct Tile {
 
 inline __host__ __device__ int chunk_of(int f) { return f / kWave; }
 
+// Level coefficients of an evaluation (k_coef), [ntr + 2][nz][2]: per
+// transition and depth two values, then two background rows.
+inline __host__ __device__ int ncoef(int ntr) { return 2 * ntr + 4; }
+
+// Tiles of one (precision, angle count) group, contiguous in the tile list.
+struct TileGroup {
+  int prec, nmu, first, count;
+};
+
 // Device work lists of a batch of columns.
 struct BatchWork {
   const ColDev* cols = nullptr;   // device array [ncol]
-  const Tile* tiles = nullptr;    // formal-solution chunks
+  const Tile* tiles = nullptr;    // formal-solution chunks, grouped by (precision, nmu)
+  TileGroup groups[2 * kMaxMu];
+  int ngroup = 0;
+  int maxnz = 0;                  // deepest column of the batch
   const int4* rate_work = nullptr;  // (col, transition, first depth, -)
   const int2* pb_work = nullptr;  // (col, first depth-entry index)
   int ncol = 0, ntiles = 0, nrate = 0, npb = 0;
@@ -178,7 +198,8 @@ struct BatchWork {
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev = nullptr);
 
 void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
-                      std::vector<int4>& rate, std::vector<int2>& pblock, int& maxL);
+                      std::vector<TileGroup>& groups, std::vector<int4>& rate,
+                      std::vector<int2>& pblock, int& maxL);
 
 }  // namespace nlte
 

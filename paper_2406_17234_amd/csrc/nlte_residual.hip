@@ -30,338 +30,413 @@ namespace nlte {
 // ---------------------------------------------------------------------------
 // piecewise-linear coefficients (Appendix A.1)
 // ---------------------------------------------------------------------------
+// e = exp(-x), a = 1 - (1 - e)/x, b = (1 - e)/x - e.  The closed forms cancel
+// at small x; below a switch point a and b come from their Taylor series
+//   a/x = sum_{m>=1} (-1)^{m+1} x^{m-1} / (m+1)!,
+//   b/x = sum_{m>=1} (-1)^{m+1} m x^{m-1} / (m+1)!,
+// and e = 1 - a - b (only the derivatives need it).
+//   FP64: 13 terms below x = 0.1 (truncation below 1e-17 relative).
+//   FP32: 6 terms below x = 0.3; the worst relative error of a and b over all
+//   x is then 1.4e-6, set by the closed forms' cancellation just above 0.3
+//   (the 10-term series below 0.25 gives 1.9e-6).
+constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+constexpr double ser_a(int m) { return ((m & 1) ? 1.0 : -1.0) / fact(m + 1); }
+constexpr double ser_b(int m) { return ((m & 1) ? 1.0 : -1.0) * m / fact(m + 1); }
 
-// e = exp(-x), a = 1 - (1 - e)/x, b = (1 - e)/x - e.  Below x = 0.1 (FP64)
-// or 0.25 (FP32) a and b come from their Taylor series, which avoids the
-// cancellation of the closed forms at small optical depth steps.
-__device__ __forceinline__ void pl_coef(double x, double& e, double& a, double& b) {
-  e = exp(-x);
-  if (x < 0.1) {
-    // a/x = sum_{m>=1} (-1)^{m+1} x^{m-1}/(m+1)!, b/x = sum_{m>=1} (-1)^{m+1} m x^{m-1}/(m+1)!
-    double sa = -1.0 / 87178291200.0, sb = -13.0 / 87178291200.0;  // m = 13 (1/14!)
-    sa = sa * x + 1.0 / 6227020800.0;  sb = sb * x + 12.0 / 6227020800.0;   // m = 12
-    sa = sa * x - 1.0 / 479001600.0;   sb = sb * x - 11.0 / 479001600.0;    // m = 11
-    sa = sa * x + 1.0 / 39916800.0;    sb = sb * x + 10.0 / 39916800.0;     // m = 10
-    sa = sa * x - 1.0 / 3628800.0;     sb = sb * x - 9.0 / 3628800.0;       // m = 9
-    sa = sa * x + 1.0 / 362880.0;      sb = sb * x + 8.0 / 362880.0;        // m = 8
-    sa = sa * x - 1.0 / 40320.0;       sb = sb * x - 7.0 / 40320.0;         // m = 7
-    sa = sa * x + 1.0 / 5040.0;        sb = sb * x + 6.0 / 5040.0;          // m = 6
-    sa = sa * x - 1.0 / 720.0;         sb = sb * x - 5.0 / 720.0;           // m = 5
-    sa = sa * x + 1.0 / 120.0;         sb = sb * x + 4.0 / 120.0;           // m = 4
-    sa = sa * x - 1.0 / 24.0;          sb = sb * x - 3.0 / 24.0;            // m = 3
-    sa = sa * x + 1.0 / 6.0;           sb = sb * x + 2.0 / 6.0;             // m = 2
-    sa = sa * x - 0.5;                 sb = sb * x - 0.5;                   // m = 1 (sign)
-    a = -sa * x;
-    b = -sb * x;
+// Explicit fused multiply-adds on the path to J: the F-only and the Newton
+// instantiations of the formal solution must produce bit-identical J (a
+// finite-difference product subtracts one from the other), so no step may be
+// left to the compiler's contraction choices.
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename R, int m, int M>
+__device__ __forceinline__ void horner_ab(R x, R& pa, R& pb) {
+  constexpr R ca = (R)ser_a(m), cb = (R)ser_b(m);
+  if constexpr (m == M) {
+    pa = ca;
+    pb = cb;
   } else {
-    const double t1 = (1.0 - e) / x;
-    a = 1.0 - t1;
-    b = t1 - e;
+    horner_ab<R, m + 1, M>(x, pa, pb);
+    pa = fmar(pa, x, ca);
+    pb = fmar(pb, x, cb);
   }
 }
 
-__device__ __forceinline__ void pl_coef(float x, float& e, float& a, float& b) {
-  e = __expf(-x);
-  if (x < 0.25f) {
-    float sa = 1.0f / 39916800.0f, sb = 10.0f / 39916800.0f;  // m = 10
-    sa = sa * x - 1.0f / 3628800.0f;   sb = sb * x - 9.0f / 3628800.0f;
-    sa = sa * x + 1.0f / 362880.0f;    sb = sb * x + 8.0f / 362880.0f;
-    sa = sa * x - 1.0f / 40320.0f;     sb = sb * x - 7.0f / 40320.0f;
-    sa = sa * x + 1.0f / 5040.0f;      sb = sb * x + 6.0f / 5040.0f;
-    sa = sa * x - 1.0f / 720.0f;       sb = sb * x - 5.0f / 720.0f;
-    sa = sa * x + 1.0f / 120.0f;       sb = sb * x + 4.0f / 120.0f;
-    sa = sa * x - 1.0f / 24.0f;        sb = sb * x - 3.0f / 24.0f;
-    sa = sa * x + 1.0f / 6.0f;         sb = sb * x + 2.0f / 6.0f;
-    sa = sa * x - 0.5f;                sb = sb * x - 0.5f;
-    a = -sa * x;
-    b = -sb * x;
+template <typename R> struct PL;
+template <> struct PL<double> {
+  static constexpr double kSwitch = 0.1;
+  static constexpr int kTerms = 13;
+  static __device__ __forceinline__ double ex(double x) { return exp(-x); }
+  static __device__ __forceinline__ double div(double p, double q) { return p / q; }
+};
+template <> struct PL<float> {
+  static constexpr float kSwitch = 0.3f;
+  static constexpr int kTerms = 6;
+  static __device__ __forceinline__ float ex(float x) { return __expf(-x); }
+  static __device__ __forceinline__ float div(float p, float q) {
+    return p * __builtin_amdgcn_rcpf(q);
+  }
+};
+
+// One step of a ray across a segment of optical thickness x:
+//   I <- I + a (S - I) + b (S_up - I).
+// With PM it also returns a, e and b/x for the local intensity derivatives.
+template <typename R, bool PM>
+__device__ __forceinline__ void ray_step(R x, R S, R Sup, R& I, R& a_o, R& e_o, R& bx_o) {
+  R a, b, e, bx;
+  if (x < PL<R>::kSwitch) {
+    R pa, pb;
+    horner_ab<R, 1, PL<R>::kTerms>(x, pa, pb);
+    a = pa * x;
+    b = pb * x;
+    if (PM) {
+      e = (R)1 - a - b;
+      bx = pb;
+    }
   } else {
-    const float t1 = (1.0f - e) * __builtin_amdgcn_rcpf(x);
-    a = 1.0f - t1;
+    e = PL<R>::ex(x);
+    const R t1 = PL<R>::div((R)1 - e, x);
+    a = (R)1 - t1;
     b = t1 - e;
+    if (PM) bx = PL<R>::div(b, x);
+  }
+  const R Iup = I;
+  I = fmar(b, Sup - Iup, fmar(a, S - Iup, Iup));
+  if (PM) {
+    a_o = a;
+    e_o = e;
+    bx_o = bx;
   }
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
 // ---------------------------------------------------------------------------
-// opacity and emissivity, Eqs. chi and eta (FP64)
+// opacity and emissivity, Eqs. chi and eta
 // ---------------------------------------------------------------------------
-// Per wave: the line windows overlapping its chunk (uniform, scalar
-// registers) and, per lane, the edges' cross-sections at its frequency
-// (depth independent, registers).  Per depth and lane: the table values that
-// change with depth, loaded one depth ahead of their use.
-struct LineMeta {
-  int lo, up, voff, wl;
-  double g;
-};
-
-struct DepthVals {
-  double B, E, Jd;
-  double v[kMaxChunkLines];
-};
-
-struct WaveOpac {
-  LineMeta lm[kMaxChunkLines];
-  int loff[kMaxChunkLines];   // f - window start (per lane)
-  unsigned amask;             // lane inside line window j
-  int nl;
-  int elo[kMaxEdges];         // edge lower levels (uniform)
-  double alpha[kMaxEdges];    // edge cross-sections at f (0 outside the window)
-  double gam;
-};
-
-__device__ __forceinline__ void wave_opac_init(WaveOpac& w, const ColDev& C, int chunk, int f) {
-  const int l0 = uni(C.ch_lptr[chunk]);
-  w.nl = uni(C.ch_lptr[chunk + 1]) - l0;
-  w.amask = 0;
-#pragma unroll
-  for (int j = 0; j < kMaxChunkLines; ++j) {
-    w.lm[j] = LineMeta{0, 0, 0, 0, 0.0};
-    w.loff[j] = 0;
-    if (j < w.nl) {
-      const int t = uni(C.ch_line[l0 + j]);
+// Per evaluation, k_coef turns the populations into two FP64 numbers per
+// transition and depth, stored transition-major ([ntr + 2][nz][2]):
+//   lines: c0 = n_l - g n_u, c1 = g n_u;   edges: c0 = n_l, c1 = (n*_l/n*_c) n_c;
+//   row ntr: chi_c + chi_sca, chi_c;       row ntr + 1: chi_sca, dz,
+// so that for every (k, nu), with E = exp(-h nu / kT),
+//   chi = chi_c + chi_sca + sum_lines V c0 + sum_edges alpha (c0 - E c1)
+//   eta = chi_c B + chi_sca J' + (2 h nu^3/c^2) (sum_lines V c1 + E sum_edges alpha c1).
+__global__ __launch_bounds__(256) void k_coef(const ColDev* __restrict__ cols) {
+  const ColDev& C = cols[blockIdx.x];
+  if (uni(C.st->mode) == kModeIdle) return;
+  const int nz = C.nz, ntr = C.ntr, nline = C.nline, L = C.L;
+  const int per = ntr + 2;
+  for (int id = threadIdx.x; id < nz * per; id += blockDim.x) {
+    const int t = id / nz, k = id - t * nz;
+    const double* nk = C.eval_n + k * L;
+    double c0, c1;
+    if (t < nline) {
       const TrDev& T = C.tr[t];
-      const int wlo = uni(T.wlo), whi = uni(T.whi);
-      w.lm[j] = LineMeta{uni(T.lo), uni(T.up), uni(T.voff), whi - wlo, uni(T.g)};
-      w.loff[j] = f - wlo;
-      if (f >= wlo && f < whi) w.amask |= 1u << j;
+      c1 = T.g * nk[T.up];
+      c0 = nk[T.lo] - c1;
+    } else if (t < ntr) {
+      c0 = nk[C.tr[t].lo];
+      c1 = C.rho_bf[k * C.nbf + (t - nline)] * nk[L - 1];
+    } else if (t == ntr) {
+      c0 = C.chi_c[k] + C.chi_sca[k];
+      c1 = C.chi_c[k];
+    } else {
+      c0 = C.chi_sca[k];
+      c1 = k + 1 < nz ? C.dz[k] : 0.0;
     }
-  }
-#pragma unroll
-  for (int e = 0; e < kMaxEdges; ++e) {
-    w.elo[e] = 0;
-    w.alpha[e] = 0.0;
-    if (e < C.nbf) {
-      const TrDev& T = C.tr[C.nline + e];
-      const int wlo = uni(T.wlo), whi = uni(T.whi);
-      w.elo[e] = uni(T.lo);
-      if (f >= wlo && f < whi) w.alpha[e] = ldg(C.V + uni(T.voff) + (f - wlo));
-    }
-  }
-  w.gam = ldg(C.gam + f);
-}
-
-__device__ __forceinline__ void load_depth(DepthVals& d, const WaveOpac& w, const ColDev& C,
-                                           int k, int f) {
-  const size_t kf = (size_t)k * C.nnu + f;
-  d.B = ldg(C.Bnu + kf);
-  d.E = C.nbf ? ldg(C.Ebf + kf) : 0.0;
-  d.Jd = C.has_sca ? ldg(C.Jdag + kf) : 0.0;
-#pragma unroll
-  for (int j = 0; j < kMaxChunkLines; ++j) {
-    d.v[j] = 0.0;
-    if (j < w.nl && ((w.amask >> j) & 1u))
-      d.v[j] = ldg(C.V + w.lm[j].voff + (size_t)k * w.lm[j].wl + w.loff[j]);
+    const size_t o = 2 * (size_t)id;
+    ((double*)C.coef)[o] = c0;
+    ((double*)C.coef)[o + 1] = c1;
   }
 }
 
-struct Opac {
-  double chi, eta;
+// Angle constants in the precision of the depth recursion.
+template <typename R> struct FTab;
+template <> struct FTab<double> {
+  static __device__ __forceinline__ double wm2(const ColDev& C, int m) { return C.wm2[m]; }
+  static __device__ __forceinline__ double i2mu(const ColDev& C, int m) { return C.inv2mu[m]; }
+};
+template <> struct FTab<float> {
+  static __device__ __forceinline__ float wm2(const ColDev& C, int m) { return C.wm2f[m]; }
+  static __device__ __forceinline__ float i2mu(const ColDev& C, int m) { return C.inv2muf[m]; }
 };
 
-__device__ __forceinline__ Opac opacity(const WaveOpac& w, const DepthVals& d, const ColDev& C,
-                                        const double* __restrict__ n, int k) {
-  const int L = C.L;
-  const double* nk = n + k * L;
-  const double cc = ldc(C.chi_c + k), cs = ldc(C.chi_sca + k);
-  Opac o;
-  o.chi = cc + cs;
-  o.eta = cc * d.B + cs * d.Jd;
-  if (C.nbf) {
-    // edges: V = alpha, g = (n*_l/n*_c) exp(-h nu/kT); sum_e alpha (n_l - g n_c)
-    const double* rho = C.rho_bf + k * C.nbf;
-    double A1 = 0.0, A2 = 0.0;
+// chi and S for one 64-frequency chunk and kOpacDepths consecutive depths:
+// one wave, one lane per frequency, the depths unrolled in registers; the
+// windows overlapping the chunk are visited one after the other, so each
+// transition's coefficients for all the wave's depths come in one scalar load.
+// Everything here is FP64 in both forms and only chi and S leave rounded to
+// R: near population inversion a line can cancel most of the background
+// opacity, and the FP32 form's preconditioner is nearly singular in
+// scattering-dominated lines, so rounding before the cancellation shows up as
+// noise in the finite-difference product (on MI355X an FP64 FMA issues at the
+// rate of a non-packed FP32 one, so this costs no extra issue slots).
+constexpr int kOpacDepths = 8;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols,
+                                                 const Tile* __restrict__ tiles, int ntiles) {
+  constexpr int KG = kOpacDepths;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int tid = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (tid >= ntiles) return;
+  const int col = uni(tiles[tid].col);
+  const int chunk = uni(tiles[tid].chunk);
+  const ColDev& C = cols[col];
+  if (uni(C.st->mode) == kModeIdle) return;
+  const int nz = uni(C.nz), nnu = uni(C.nnu);
+  const int k0 = blockIdx.y * KG;
+  if (k0 >= nz) return;
+  const int f = chunk * kWave + lane;
+  const bool fin = f < nnu;
+  const int fc = fin ? f : nnu - 1;
+  const double* __restrict__ Vt = C.V;
+  const double* __restrict__ coef = (const double*)C.coef;
+  const int ntr = uni(C.ntr);
+
+  double chi[KG], et[KG];
 #pragma unroll
-    for (int e = 0; e < kMaxEdges; ++e) {
-      if (e < C.nbf) {
-        A1 += w.alpha[e] * ldc(nk + w.elo[e]);
-        A2 += w.alpha[e] * ldc(rho + e);
-      }
-    }
-    const double nc = ldc(nk + L - 1);
-    o.chi += A1 - d.E * nc * A2;
-    o.eta += w.gam * d.E * nc * A2;
+  for (int i = 0; i < KG; ++i) {
+    chi[i] = 0.0;
+    et[i] = 0.0;
   }
+  // lines: chi += V c0, et += V c1
+  const int l0 = uni(C.ch_lptr[chunk]), l1 = uni(C.ch_lptr[chunk + 1]);
+  for (int j = l0; j < l1; ++j) {
+    const int t = uni(C.ch_line[j]);
+    const TrDev& T = C.tr[t];
+    const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
+    const int q = fc - wlo;
+    const bool in = q >= 0 && q < wl;
+    const double* vrow = Vt + uni(T.voff) + (in ? q : 0);
+    const double* ct = coef + ((size_t)t * nz + k0) * 2;
+    double v[KG];
 #pragma unroll
-  for (int j = 0; j < kMaxChunkLines; ++j) {
-    if (j < w.nl) {
-      const double nl_ = ldc(nk + w.lm[j].lo), nu_ = ldc(nk + w.lm[j].up);
-      o.chi += d.v[j] * (nl_ - w.lm[j].g * nu_);
-      o.eta += w.gam * w.lm[j].g * d.v[j] * nu_;
+    for (int i = 0; i < KG; ++i) {
+      const int k = min(k0 + i, nz - 1);
+      v[i] = ldg(vrow + (size_t)k * wl);
+    }
+#pragma unroll
+    for (int i = 0; i < KG; ++i) {
+      const int k = min(k0 + i, nz - 1) - k0;
+      const double vi = in ? v[i] : 0.0;
+      chi[i] += vi * ldc(ct + 2 * k);
+      et[i] += vi * ldc(ct + 2 * k + 1);
     }
   }
-  return o;
+  // edges: A1 = sum alpha c0, A2 = sum alpha c1
+  double A1[KG], A2[KG];
+#pragma unroll
+  for (int i = 0; i < KG; ++i) {
+    A1[i] = 0.0;
+    A2[i] = 0.0;
+  }
+  const int e0 = uni(C.ch_eptr[chunk]), e1 = uni(C.ch_eptr[chunk + 1]);
+  for (int j = e0; j < e1; ++j) {
+    const int t = uni(C.ch_edge[j]);
+    const TrDev& T = C.tr[t];
+    const int wlo = uni(T.wlo), whi = uni(T.whi);
+    const double al = (fc >= wlo && fc < whi) ? ldg(Vt + uni(T.voff) + (fc - wlo)) : 0.0;
+    const double* ct = coef + ((size_t)t * nz + k0) * 2;
+#pragma unroll
+    for (int i = 0; i < KG; ++i) {
+      const int k = min(k0 + i, nz - 1) - k0;
+      A1[i] += al * ldc(ct + 2 * k);
+      A2[i] += al * ldc(ct + 2 * k + 1);
+    }
+  }
+  // background, source function
+  const double gam = ldg(C.gam + fc);
+  const double* cb = coef + ((size_t)ntr * nz + k0) * 2;
+  const double* cs = coef + ((size_t)(ntr + 1) * nz + k0) * 2;
+  const bool sca = C.has_sca, bf = C.nbf > 0;
+  R* __restrict__ xs = reinterpret_cast<R*>(C.XS);
+#pragma unroll
+  for (int i = 0; i < KG; ++i) {
+    const int k = min(k0 + i, nz - 1);
+    const size_t kf = (size_t)k * nnu + fc;
+    const double B = ldg(C.Bnu + kf);
+    const double E = bf ? ldg(C.Ebf + kf) : 0.0;
+    const double EA2 = E * A2[i];
+    const double X = ldc(cb + 2 * (k - k0)) + chi[i] + (A1[i] - EA2);
+    double eta = ldc(cb + 2 * (k - k0) + 1) * B + gam * (et[i] + EA2);
+    if (sca) eta += ldc(cs + 2 * (k - k0)) * ldg(C.Jdag + kf);
+    if (fin && k0 + i < nz) {
+      stg(xs + 2 * kf, (R)X);
+      stg(xs + 2 * kf + 1, (R)(eta / X));
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
 // formal solution kernel
 // ---------------------------------------------------------------------------
-// R: arithmetic of the depth recursion (double, or float for the FP32 form).
-// PM: Newton mode (also the local intensity derivatives of App. A.2).
-// The first sweep assembles chi and S at every depth and keeps them in a
-// [k][nu] scratch row for the second sweep, which only reloads them.
-template <typename R, bool PM>
+// R: arithmetic of the depth recursion (double, or float for the FP32 form;
+// J and the derivatives leave in double).  PM: Newton mode (also the local
+// intensity derivatives of App. A.2).  NMU: angles per hemisphere.
+// One wave per 64-frequency chunk, one lane per frequency, all 2 NMU rays in
+// registers.  The first sweep (ingoing rays, top -> bottom) parks its share
+// of J in a scratch row; the second (outgoing rays, bottom -> top) writes J.
+template <typename R, bool PM, int NMU>
 __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane) {
-  const int nz = C.nz, nnu = C.nnu, nmu = C.nmu;
+  const int nz = C.nz, nnu = C.nnu;
   const int f = chunk * kWave + lane;
   const bool fin = f < nnu;
   const int fc = fin ? f : nnu - 1;
-  const double* __restrict__ n = C.eval_n;
-  R* __restrict__ xs = reinterpret_cast<R*>(C.XS);  // [nz][nnu][2]: chi, S
+  const double* __restrict__ dzt = (const double*)C.coef + ((size_t)(C.ntr + 1) * nz) * 2 + 1;  // stride 2
+  const R* __restrict__ xs = reinterpret_cast<const R*>(C.XS);  // [nz][nnu][2]: chi, S
+  double* __restrict__ jm = C.Jm;                                // [nz][nnu]
+  R* __restrict__ dxs = reinterpret_cast<R*>(C.Dchi);           // [nz][nnu]
+  R* __restrict__ des = reinterpret_cast<R*>(C.Deta);           // [nz][nnu]
 
-  WaveOpac w;
-  wave_opac_init(w, C, chunk, fc);
-
-  R wm2[kMaxMu], i2mu[kMaxMu];
+  R wm2[NMU], i2mu[NMU];
+  double wm2d[NMU];
 #pragma unroll
-  for (int m = 0; m < kMaxMu; ++m) {
-    wm2[m] = (R)C.wm2[m];
-    i2mu[m] = (R)C.inv2mu[m];
+  for (int m = 0; m < NMU; ++m) {
+    wm2[m] = FTab<R>::wm2(C, m);
+    i2mu[m] = FTab<R>::i2mu(C, m);
+    wm2d[m] = C.wm2[m];
   }
 
   // ---- sweep 1: ingoing rays, top -> bottom (I- = 0 at the top) ----
-  R I[kMaxMu];
+  R I[NMU];
 #pragma unroll
-  for (int m = 0; m < kMaxMu; ++m) I[m] = (R)0;
-  R chi_p = 0, S_p = 0;
-  DepthVals cur, nxt;
-  load_depth(cur, w, C, 0, fc);
-  for (int k = 0; k < nz; ++k) {
-    if (k + 1 < nz) load_depth(nxt, w, C, k + 1, fc);
-    const Opac o = opacity(w, cur, C, n, k);
-    const R chi = (R)o.chi, S = (R)(o.eta / o.chi);
-    double Jm = 0.0, dX = 0.0, dE = 0.0;
-    if (k > 0) {
-      const R dz = (R)ldc(C.dz + k - 1);
-      const R base = dz * (chi_p + chi);
+  for (int m = 0; m < NMU; ++m) I[m] = (R)0;
+  R chi_p = ldg(xs + 2 * (size_t)fc), S_p = ldg(xs + 2 * (size_t)fc + 1);
+  if (fin) {
+    stg(jm + f, 0.0);
+    if (PM) {
+      stg(dxs + f, (R)0);
+      stg(des + f, (R)0);
+    }
+  }
+  R chi_x = 0, S_x = 0;
+  if (nz > 1) {
+    chi_x = ldg(xs + 2 * ((size_t)nnu + fc));
+    S_x = ldg(xs + 2 * ((size_t)nnu + fc) + 1);
+  }
+  for (int k = 1; k < nz; ++k) {
+    const R chi = chi_x, S = S_x;
+    if (k + 1 < nz) {
+      const size_t kf = (size_t)(k + 1) * nnu + fc;
+      chi_x = ldg(xs + 2 * kf);
+      S_x = ldg(xs + 2 * kf + 1);
+    }
+    const R dz = (R)ldc(dzt + 2 * (k - 1));
+    const R base = dz * (chi_p + chi);
+    double jac = 0.0;
+    R sa = (R)0, sc = (R)0;
 #pragma unroll
-      for (int m = 0; m < kMaxMu; ++m) {
-        if (m < nmu) {
-          const R dt = base * i2mu[m];
-          R e, a, b;
-          pl_coef(dt, e, a, b);
-          const R Iup = I[m];
-          I[m] = Iup + a * (S - Iup) + b * (S_p - Iup);
-          Jm += (double)wm2[m] * (double)I[m];
-          if (PM) {
-            // c_chi, c_eta of App. A.2 (ingoing ray, segment k-1 -> k)
-            const R cchi = -(S / chi) * a +
-                           dz * i2mu[m] * (e * (S_p - Iup) - (S_p - S) * b / dt);
-            dX += (double)wm2[m] * (double)cchi;
-            dE += (double)wm2[m] * (double)(a / chi);
-          }
-        }
+    for (int m = 0; m < NMU; ++m) {
+      const R Iup = I[m];
+      R a, e, bx;
+      ray_step<R, PM>(base * i2mu[m], S, S_p, I[m], a, e, bx);
+      jac = fmar(wm2d[m], (double)I[m], jac);
+      if (PM) {
+        // c_chi, c_eta of App. A.2 (ingoing ray, segment k-1 -> k)
+        sa += wm2[m] * a;
+        sc += (wm2[m] * i2mu[m]) * (e * (S_p - Iup) - (S_p - S) * bx);
       }
     }
     if (fin) {
       const size_t kf = (size_t)k * nnu + f;
-      stg(C.Jm + kf, Jm);
-      stg(xs + 2 * kf, chi);
-      stg(xs + 2 * kf + 1, S);
+      stg(jm + kf, jac);
       if (PM) {
-        stg(C.Dchi + kf, dX);
-        stg(C.Deta + kf, dE);
+        const R rc = PL<R>::div((R)1, chi);
+        stg(dxs + kf, -(S * rc) * sa + dz * sc);
+        stg(des + kf, sa * rc);
       }
     }
     chi_p = chi;
     S_p = S;
-    cur = nxt;
   }
 
   // ---- sweep 2: outgoing rays, bottom -> top (I+ = B at the bottom) ----
   R chi_n = chi_p, S_n = S_p;
   {
     const size_t kf = (size_t)(nz - 1) * nnu + fc;
-    const R Bb = (R)ldg(C.Bnu + kf);
-    double Jp = 0.0;
+    const double Bd = ldg(C.Bnu + kf);
+    const R Bb = (R)Bd;
+    double jp = 0.0;
 #pragma unroll
-    for (int m = 0; m < kMaxMu; ++m) {
+    for (int m = 0; m < NMU; ++m) {
       I[m] = Bb;
-      if (m < nmu) Jp += (double)wm2[m] * (double)Bb;
+      jp = fmar(wm2d[m], (double)Bb, jp);
     }
     if (fin) {
       const size_t fk = (size_t)f * nz + (nz - 1);
-      stg(C.JT + fk, ldg(C.Jm + kf) + Jp);
+      stg(C.JT + fk, ldg(jm + kf) + jp);
       if (PM) {  // bottom: ingoing-ray derivatives only
-        stg(C.DchiT + fk, ldg(C.Dchi + kf));
-        stg(C.DetaT + fk, ldg(C.Deta + kf));
+        stg(C.DchiT + fk, (double)ldg(dxs + kf));
+        stg(C.DetaT + fk, (double)ldg(des + kf));
       }
     }
   }
   // prefetched: chi, S, Jm (and the ingoing derivatives) of the next depth up
-  R chi_c = 0, S_c = 0;
-  double Jm_c = 0.0, dX_c = 0.0, dE_c = 0.0;
+  R chi_c = 0, S_c = 0, dX_c = 0, dE_c = 0;
+  double jm_c = 0.0;
   if (nz >= 2) {
     const size_t kf = (size_t)(nz - 2) * nnu + fc;
     chi_c = ldg(xs + 2 * kf);
     S_c = ldg(xs + 2 * kf + 1);
-    Jm_c = ldg(C.Jm + kf);
+    jm_c = ldg(jm + kf);
     if (PM) {
-      dX_c = ldg(C.Dchi + kf);
-      dE_c = ldg(C.Deta + kf);
+      dX_c = ldg(dxs + kf);
+      dE_c = ldg(des + kf);
     }
   }
   for (int k = nz - 2; k >= 0; --k) {
-    R chi_x = 0, S_x = 0;
-    double Jm_x = 0.0, dX_x = 0.0, dE_x = 0.0;
+    R chi_y = 0, S_y = 0, dX_y = 0, dE_y = 0;
+    double jm_y = 0.0;
     if (k > 0) {
       const size_t kf = (size_t)(k - 1) * nnu + fc;
-      chi_x = ldg(xs + 2 * kf);
-      S_x = ldg(xs + 2 * kf + 1);
-      Jm_x = ldg(C.Jm + kf);
+      chi_y = ldg(xs + 2 * kf);
+      S_y = ldg(xs + 2 * kf + 1);
+      jm_y = ldg(jm + kf);
       if (PM) {
-        dX_x = ldg(C.Dchi + kf);
-        dE_x = ldg(C.Deta + kf);
+        dX_y = ldg(dxs + kf);
+        dE_y = ldg(des + kf);
       }
     }
     const R chi = chi_c, S = S_c;
-    const R dz = (R)ldc(C.dz + k);
+    const R dz = (R)ldc(dzt + 2 * k);
     const R base = dz * (chi + chi_n);
-    double Jp = 0.0, dX = 0.0, dE = 0.0;
+    double jp = 0.0;
+    R sa = (R)0, sc = (R)0;
 #pragma unroll
-    for (int m = 0; m < kMaxMu; ++m) {
-      if (m < nmu) {
-        const R dt = base * i2mu[m];
-        R e, a, b;
-        pl_coef(dt, e, a, b);
-        const R Iup = I[m];
-        I[m] = Iup + a * (S - Iup) + b * (S_n - Iup);
-        Jp += (double)wm2[m] * (double)I[m];
-        if (PM) {
-          // a_chi, a_eta of App. A.2 (outgoing ray, segment k+1 -> k)
-          const R achi = -(S / chi) * a +
-                         dz * i2mu[m] * (e * (S_n - Iup) - (S_n - S) * b / dt);
-          dX += (double)wm2[m] * (double)achi;
-          dE += (double)wm2[m] * (double)(a / chi);
-        }
+    for (int m = 0; m < NMU; ++m) {
+      const R Iup = I[m];
+      R a, e, bx;
+      ray_step<R, PM>(base * i2mu[m], S, S_n, I[m], a, e, bx);
+      jp = fmar(wm2d[m], (double)I[m], jp);
+      if (PM) {
+        // a_chi, a_eta of App. A.2 (outgoing ray, segment k+1 -> k)
+        sa += wm2[m] * a;
+        sc += (wm2[m] * i2mu[m]) * (e * (S_n - Iup) - (S_n - S) * bx);
       }
     }
     if (fin) {
       const size_t fk = (size_t)f * nz + k;
-      stg(C.JT + fk, Jm_c + Jp);
+      stg(C.JT + fk, jm_c + jp);
       if (PM) {
-        stg(C.DchiT + fk, dX_c + dX);
-        stg(C.DetaT + fk, dE_c + dE);
+        const R rc = PL<R>::div((R)1, chi);
+        stg(C.DchiT + fk, (double)dX_c + (double)(-(S * rc) * sa + dz * sc));
+        stg(C.DetaT + fk, (double)dE_c + (double)(sa * rc));
       }
     }
     chi_n = chi;
     S_n = S;
-    chi_c = chi_x;
-    S_c = S_x;
-    Jm_c = Jm_x;
-    dX_c = dX_x;
-    dE_c = dE_x;
+    chi_c = chi_y;
+    S_c = S_y;
+    jm_c = jm_y;
+    dX_c = dX_y;
+    dE_c = dE_y;
   }
 }
 
-// One launch covers every tile of a step; each wave takes the mode of its
-// column (residual only, or residual + preconditioner derivatives).
-template <typename R>
+// One launch per (precision, angle count, mode) present in a step, over that
+// group's tiles; a wave whose column is idle or in the other mode returns.
+template <typename R, bool PM, int NMU>
 __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
                                                 const Tile* __restrict__ tiles, int ntiles) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -372,12 +447,21 @@ __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
   const int chunk = uni(tiles[tid].chunk);
   const ColDev& C = cols[col];
   const int mode = uni(C.st->mode);
-  if (mode == kModeIdle) return;
-  if ((C.prec == NLTE_FP32_FORM) != (sizeof(R) == sizeof(float))) return;
-  if (mode == kModeNewton)
-    formal_tile<R, true>(C, chunk, lane);
-  else
-    formal_tile<R, false>(C, chunk, lane);
+  if (mode != (PM ? kModeNewton : kModeF)) return;
+  formal_tile<R, PM, NMU>(C, chunk, lane);
+}
+
+template <typename R, bool PM>
+static void launch_formal_mu(int nmu, int blocks, hipStream_t s, const ColDev* cols,
+                             const Tile* tiles, int ntiles) {
+  switch (nmu) {
+#define NLTE_FORMAL_CASE(M) \
+  case M: k_formal<R, PM, M><<<blocks, 256, 0, s>>>(cols, tiles, ntiles); break;
+    NLTE_FORMAL_CASE(1) NLTE_FORMAL_CASE(2) NLTE_FORMAL_CASE(3) NLTE_FORMAL_CASE(4)
+    NLTE_FORMAL_CASE(5) NLTE_FORMAL_CASE(6) NLTE_FORMAL_CASE(7) NLTE_FORMAL_CASE(8)
+#undef NLTE_FORMAL_CASE
+    default: break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -625,11 +709,28 @@ __global__ __launch_bounds__(256) void k_pblock(const ColDev* __restrict__ cols,
 // launch helpers
 // ---------------------------------------------------------------------------
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
-  const int blocks = (bw.ntiles + 3) / 4;
   if (ev) hipEventRecord(ev[0], s);
-  if (bw.ntiles > 0) {
-    if (bw.any64) k_formal<double><<<blocks, 256, 0, s>>>(bw.cols, bw.tiles, bw.ntiles);
-    if (bw.any32) k_formal<float><<<blocks, 256, 0, s>>>(bw.cols, bw.tiles, bw.ntiles);
+  k_coef<<<bw.ncol, 256, 0, s>>>(bw.cols);
+  for (int g = 0; g < bw.ngroup; ++g) {
+    const TileGroup& G = bw.groups[g];
+    const dim3 grid((G.count + 3) / 4, (bw.maxnz + kOpacDepths - 1) / kOpacDepths);
+    const Tile* tl = bw.tiles + G.first;
+    if (G.prec == NLTE_FP32_FORM)
+      k_opacity<float><<<grid, 256, 0, s>>>(bw.cols, tl, G.count);
+    else
+      k_opacity<double><<<grid, 256, 0, s>>>(bw.cols, tl, G.count);
+  }
+  for (int g = 0; g < bw.ngroup; ++g) {
+    const TileGroup& G = bw.groups[g];
+    const int nb = (G.count + 3) / 4;
+    const Tile* tl = bw.tiles + G.first;
+    if (G.prec == NLTE_FP32_FORM) {
+      launch_formal_mu<float, false>(G.nmu, nb, s, bw.cols, tl, G.count);
+      if (bw.any_newton) launch_formal_mu<float, true>(G.nmu, nb, s, bw.cols, tl, G.count);
+    } else {
+      launch_formal_mu<double, false>(G.nmu, nb, s, bw.cols, tl, G.count);
+      if (bw.any_newton) launch_formal_mu<double, true>(G.nmu, nb, s, bw.cols, tl, G.count);
+    }
   }
   if (ev) hipEventRecord(ev[1], s);
   if (bw.nrate > 0) k_depthwork<<<bw.nrate, 64, 0, s>>>(bw.cols, bw.rate_work, bw.nrate);
@@ -643,7 +744,18 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
 // Work lists of a batch (host side): formal-solution tiles, rate items and
 // preconditioner items for every column.
 void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
-                      std::vector<int4>& rate, std::vector<int2>& pblock, int& maxL) {
+                      std::vector<TileGroup>& groups, std::vector<int4>& rate,
+                      std::vector<int2>& pblock, int& maxL) {
+  // formal-solution tiles grouped by (precision, angle count)
+  for (int prec = 0; prec < 2; ++prec)
+    for (int nmu = 1; nmu <= kMaxMu; ++nmu) {
+      TileGroup G{prec, nmu, (int)tiles.size(), 0};
+      for (int c = 0; c < ncol; ++c)
+        if (hc[c].prec == prec && hc[c].nmu == nmu)
+          for (int ch = 0; ch < hc[c].nchunk; ++ch) tiles.push_back(Tile{c, ch});
+      G.count = (int)tiles.size() - G.first;
+      if (G.count) groups.push_back(G);
+    }
   // rate items (kind 0) and preconditioner pair items (kind 1) share one list
   maxL = 0;
   for (int c = 0; c < ncol; ++c)
@@ -651,7 +763,6 @@ void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
   for (int c = 0; c < ncol; ++c) {
     const ColDev& C = hc[c];
     maxL = std::max(maxL, C.L);
-    for (int ch = 0; ch < C.nchunk; ++ch) tiles.push_back(Tile{c, ch});
     for (int t = 0; t < C.ntr; ++t)
       for (int k0 = 0; k0 < C.nz; k0 += kWave) rate.push_back(make_int4(c, t, k0, 0));
     for (int p = 0; p < C.npair; ++p)

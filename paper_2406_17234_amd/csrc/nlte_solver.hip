@@ -315,7 +315,10 @@ __device__ void accept_point(const ColDev& C, double* red, int* done_count) {
     C.Vk[i] = -C.Vk[i];
     C.xk[i] = 0.0;
   }
-  if (threadIdx.x == 0) st->restarts = 0;
+  if (threadIdx.x == 0) {
+    st->restarts = 0;
+    st->krylov_step = 0;
+  }
   __syncthreads();
   start_cycle(C, true, red, done_count);
 }
@@ -375,11 +378,13 @@ __device__ void arnoldi(const ColDev& C, double* red, int* done_count) {
     s_resid = fabs(C.gv[j + 1]);
     st->krylov_j = j + 1;
     st->krylov_total += 1;
+    st->krylov_step += 1;
   }
   __syncthreads();
   const int jj = j + 1;
   const bool conv = s_resid <= st->rtol * st->beta0;
-  const bool cap = st->krylov_total >= st->max_krylov;
+  const bool cap = st->krylov_step >= st->max_krylov ||  // per Newton step
+                   (st->max_krylov_total > 0 && st->krylov_total >= st->max_krylov_total);
   if (!(conv || cap || brk || jj == m)) {
     prepare_jv(C, C.Vk + (size_t)jj * N, 1.0);
     return;
@@ -497,7 +502,7 @@ __global__ __launch_bounds__(kThreads) void k_solver_step(const ColDev* __restri
 // Solve setup: options, initial populations, J-dagger = B, first evaluation.
 struct InitArgs {
   double ftol, rtol, eps_mach, eps_scale;
-  int maxiter, max_krylov, restart, max_halvings, init;
+  int maxiter, max_krylov, restart, max_halvings, init, max_krylov_total;
 };
 
 __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* const* n0, InitArgs a) {
@@ -513,6 +518,7 @@ __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* con
     st->newton_it = 0;
     st->krylov_j = 0;
     st->krylov_total = 0;
+    st->krylov_step = 0;
     st->f_calls = 0;
     st->precond_calls = 0;
     st->stalls = 0;
@@ -527,6 +533,7 @@ __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* con
     st->eps_scale = a.eps_scale;
     st->maxiter = a.maxiter;
     st->max_krylov = a.max_krylov;
+    st->max_krylov_total = a.max_krylov_total;
     st->restart = a.restart;
     st->max_halvings = a.max_halvings;
     st->mode = kModeNewton;
@@ -637,7 +644,8 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   nlte_solve_opts_default(&o);
   if (opts) o = *opts;
   if (o.restart < 1 || o.restart > kMaxM) return set_err(NLTE_E_INVALID, "restart must be 1..%d", kMaxM);
-  if (o.maxiter < 0 || o.max_krylov < 1 || o.max_halvings < 0 || !(o.ftol >= 0) || !(o.rtol > 0) ||
+  if (o.maxiter < 0 || o.max_krylov < 1 || o.max_krylov_total < 0 || o.max_halvings < 0 ||
+      !(o.ftol >= 0) || !(o.rtol > 0) ||
       !(o.eps_scale > 0))
     return set_err(NLTE_E_INVALID, "invalid solve options");
   if (o.init == 0 && !n0_dev) return set_err(NLTE_E_INVALID, "init = 0 needs n0");
@@ -657,7 +665,8 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
     for (int d = 0; d < c; ++d)
       if (cols[d] == cols[c]) return set_err(NLTE_E_INVALID, "column %d appears twice", c);
   }
-  build_work_lists(hc.data(), ncol, tiles, rate_w, prec_w, b.maxL);
+  std::vector<TileGroup> groups;
+  build_work_lists(hc.data(), ncol, tiles, groups, rate_w, prec_w, b.maxL);
   b.ntiles = (int)tiles.size();
   HIP_TRY(hipMalloc(&b.cols, ncol * sizeof(ColDev)));
   HIP_TRY(hipMalloc(&b.tiles, tiles.size() * sizeof(Tile)));
@@ -677,6 +686,9 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   bw.any64 = b.any64;
   bw.any32 = b.any32;
   bw.any_newton = 1;
+  bw.ngroup = (int)groups.size();
+  for (int g = 0; g < bw.ngroup; ++g) bw.groups[g] = groups[g];
+  for (int c = 0; c < ncol; ++c) bw.maxnz = std::max(bw.maxnz, hc[c].nz);
 
   HIP_TRY(hipMalloc(&b.nout, ncol * sizeof(double*)));
   HIP_TRY(hipMalloc(&b.done, sizeof(int)));
@@ -690,7 +702,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   }
   HIP_TRY(hipMemsetAsync(b.done, 0, sizeof(int), s));
   InitArgs ia{o.ftol, o.rtol, 2.220446049250313e-16, o.eps_scale, o.maxiter, o.max_krylov,
-              o.restart, o.max_halvings, o.init};
+              o.restart, o.max_halvings, o.init, o.max_krylov_total};
   k_solver_init<<<ncol, 256, 0, s>>>(b.cols, o.init == 0 ? b.n0 : nullptr, ia);
   if (o.init == 2) {
     for (int c = 0; c < ncol; ++c)
@@ -729,7 +741,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
         float t[4];
         for (int q = 0; q < 4; ++q) HIP_TRY(hipEventElapsedTime(&t[q], ev[5 * r + q], ev[5 * r + q + 1]));
         ctx->prof.steps += 1;
-        ctx->prof.formal_launches += (b.any64 + b.any32);
+        ctx->prof.formal_launches += 2 * bw.ngroup;
         ctx->prof.formal_ms += t[0];
         ctx->prof.depth_ms += t[1];
         ctx->prof.assemble_ms += t[2];

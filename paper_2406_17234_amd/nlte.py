@@ -53,7 +53,8 @@ class GridDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("ftol", C.c_double), ("rtol", C.c_double), ("maxiter", C.c_int32),
                 ("max_krylov", C.c_int32), ("restart", C.c_int32),
-                ("max_halvings", C.c_int32), ("init", C.c_int32), ("eps_scale", C.c_double)]
+                ("max_halvings", C.c_int32), ("init", C.c_int32), ("eps_scale", C.c_double),
+                ("max_krylov_total", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -80,6 +81,10 @@ def lib():
     """Load libnlte.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch brings its own HIP runtime with the same soname as the system
+        # one; loading torch first makes the library bind to that runtime, so
+        # one runtime serves both (device pointers, streams).
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} missing: run `python -m paper_2406_17234_amd.build`")
         L = C.CDLL(LIB_PATH)

@@ -111,3 +111,19 @@ def test_batched_tiles_independent_of_neighbours(ctx):
     c2.residual(c2.lte())
     b = to_np(c1.residual(n1)["F"])
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,prec", [("chromo6", 0), ("chromo6_small", 1)])
+def test_f_only_and_newton_mode_agree_bitwise(ctx, name, prec):
+    """The residual-only evaluation and the Newton-mode evaluation (which also
+    builds the preconditioner) must give bit-identical F and J: the
+    finite-difference product subtracts one from the other, so any rounding
+    difference between the two would be amplified by 1/eps."""
+    prob = PROBLEMS[name]()
+    tb = O.setup(prob)
+    n = perturbed(tb.nstar, seed=5, scale=0.2)
+    col = _column(ctx, prob, prec)
+    a = col.residual(to_dev(n), want_J=True)
+    b = col.residual(to_dev(n), want_J=True, want_P=True)
+    assert np.array_equal(to_np(a["F"]), to_np(b["F"]))
+    assert np.array_equal(to_np(a["J"]), to_np(b["J"]))

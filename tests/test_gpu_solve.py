@@ -118,3 +118,26 @@ def test_maxiter_reports_noconv(ctx):
     assert rc == nlte.NLTE_E_NOCONV and st["status"] == nlte.NLTE_E_NOCONV
     assert st["newton_iters"] == 1
     assert np.all(np.isfinite(to_np(n)))
+
+
+def test_krylov_cap_is_per_newton_step(ctx):
+    """max_krylov bounds the Krylov iterations of each Newton step, not of the
+    whole solve: a solve whose total exceeds the cap still converges."""
+    from paper_2406_17234_amd import nlte
+    prob, tb, ref = oracle_root("chromo6_small", CASES["chromo6_small"])
+    col = nlte.Column(ctx, prob)
+    n, _, st, rc = col.solve(ftol=1e-12, rtol=1e-6, maxiter=60, max_krylov=40)
+    assert st["krylov_iters"] > 40
+    assert rc == 0 and st["rho_inf"] <= 1e-12
+    assert maxrel(to_np(n), ref.n) < 1e-10
+
+
+def test_krylov_budget_per_solve(ctx):
+    """Once max_krylov_total is spent every Newton iteration takes a single
+    Krylov step."""
+    from paper_2406_17234_amd import nlte
+    prob = CASES["chromo6_small"]()
+    col = nlte.Column(ctx, prob)
+    n, _, st, rc = col.solve(ftol=1e-12, rtol=1e-6, maxiter=8, max_krylov_total=10)
+    assert st["krylov_iters"] <= 10 + st["newton_iters"]
+    assert st["newton_iters"] >= 1
