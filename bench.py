@@ -102,6 +102,60 @@ def cpu_baseline(workload, ncol, ftol, rtol, budget_s=20.0):
     }
 
 
+def serve_stream(ctx, nlte, duration_s, rate, budget_gb, max_active, ftol, rtol, max_krylov_total):
+    """Served stream: Poisson arrivals of mixed 3/6/11-level requests (FP32
+    form), submitted at their arrival times to a continuous-batching server.
+    Column setup happens before the timed window (its cost is reported
+    separately); latency = finish - submit as seen by the server."""
+    import torch
+    arrivals = S.stream_arrivals(duration_s, rate)
+    nreq = len(arrivals)
+    t0 = time.perf_counter()
+    probs = [S.stream_request(j) for j in range(nreq)]
+    gen_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cols = [nlte.Column(ctx, p, precision=nlte.FP32_FORM) for p in probs]
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] stream: {nreq} requests generated in {gen_s:.1f} s, set up in {setup_s:.1f} s",
+          file=sys.stderr, flush=True)
+    opts = nlte.default_opts(ftol=ftol, rtol=rtol, maxiter=50, max_krylov_total=max_krylov_total)
+    srv = nlte.Server(ctx, hbm_budget=int(budget_gb * (1 << 30)), max_active=max_active, opts=opts)
+    tickets = []
+    t_start = time.perf_counter()
+    for i, ta in enumerate(arrivals):
+        dt = t_start + ta - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(cols[i]))
+    srv.drain(600.0)
+    wall = time.perf_counter() - t_start
+    res = [srv.poll(t)[1] for t in tickets]
+    info = srv.info()
+    srv.close()
+    lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in res])
+    conv = np.array([r["status"] == 0 for r in res])
+    span_s = (max(r["t_done_ms"] for r in res) - min(r["t_submit_ms"] for r in res)) * 1e-3
+    dp = float(sum(r["f_calls"] * p.depth_points() for r, p in zip(res, probs)))
+    out = {
+        "requests": nreq, "arrival_rate_per_s": rate, "arrival_window_s": duration_s,
+        "columns_converged_per_s": float(conv.sum()) / span_s,
+        "columns_per_s": nreq / span_s,
+        "converged_fraction": float(conv.mean()),
+        "latency_ms_p50": float(np.percentile(lat, 50)),
+        "latency_ms_p99": float(np.percentile(lat, 99)),
+        "latency_ms_max": float(lat.max()),
+        "depth_points_per_s": dp / span_s,
+        "setup_ms_per_column": setup_s / nreq * 1e3,
+        "hbm_budget_gb": budget_gb, "max_active": max_active,
+        "server_steps": info["steps"], "wall_s": wall,
+    }
+    for c in cols:
+        c.close()
+    return out
+
+
 def copy_calibration(nbytes=256 << 20, reps=3):
     """A plain elementwise copy (y = 1.0 * x, fp32) of known size: it reads and
     writes nbytes each, so HBM byte counters read for it give their scale."""
@@ -127,6 +181,11 @@ def main():
                     help="Krylov budget per column solve (0: none); bounds the cost of columns "
                          "that do not converge, which otherwise set the length of the batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
+                    help="arrival window of the served-stream phase (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=96.0)
+    ap.add_argument("--serve-max-active", type=int, default=2048)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy kernel (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -230,6 +289,13 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if args.serve_seconds > 0:
+        for c in cols:
+            c.close()
+        cols = None
+        out["served"] = serve_stream(ctx, nlte, args.serve_seconds, args.serve_rate,
+                                     args.serve_budget_gb, args.serve_max_active, 1e-6,
+                                     args.rtol, args.max_krylov_total)
     print(json.dumps(out))
 
 

@@ -48,7 +48,7 @@ typedef enum {
   NLTE_E_DEVICE = -3,     /* HIP runtime error                                 */
   NLTE_E_NOCONV = -4,     /* solve stopped at maxiter; best iterate returned   */
   NLTE_E_NONFINITE = -5,  /* NaN/Inf met in inputs or in the iteration         */
-  NLTE_E_BUSY = -6        /* request does not fit the server's memory budget   */
+  NLTE_E_BUSY = -6        /* not finished yet (server poll, drain time-out)    */
 } nlte_status;
 
 /* Precision of the formal solution and of the angle/frequency quadratures.
@@ -165,6 +165,8 @@ void nlte_column_destroy(nlte_column *col);
 
 /* dims = {nz, nlev, ntr, nline, nbf, nnu, nmu, precision} */
 nlte_status nlte_column_dims(const nlte_column *col, int32_t dims[8]);
+/* Bytes of device memory the column owns (its arena). */
+nlte_status nlte_column_bytes(const nlte_column *col, size_t *bytes);
 
 /* LTE (Saha-Boltzmann) populations n* [nz][nlev] (Sect. 2.2.1 initial guess). */
 nlte_status nlte_lte_populations(nlte_column *col, double *n_dev, hipStream_t stream);
@@ -215,6 +217,62 @@ nlte_status nlte_solve_batch(nlte_ctx *ctx, nlte_column *const *cols, int32_t nc
                              const double *const *n0_dev, const nlte_solve_opts *opts,
                              double *const *n_out_dev, nlte_solve_stats *stats,
                              hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of column solves.
+ *
+ * A server owns one host thread and one non-blocking HIP stream on the
+ * context's device.  Submitted solves wait in a FIFO queue and are admitted
+ * while the device arenas of the columns in flight stay within hbm_budget
+ * bytes and their number within max_active (a column larger than the budget
+ * is admitted alone).  Admitted columns advance together, one residual
+ * evaluation per column per step, exactly as in nlte_solve_batch, so a
+ * served result is bit-identical to the same column solved alone with the
+ * same options; their Newton/Krylov state stays in the columns' device memory.
+ * After every few steps the thread retires finished columns and admits
+ * waiting ones (requests that arrive while others run join the next step).
+ *
+ * Ownership: the caller keeps ownership of every column; a submitted column
+ * must not be used, resubmitted or destroyed until its ticket is polled (or
+ * the server destroyed).  n0_dev (NULL: LTE start) must stay valid until the
+ * request is admitted.  Thread safety: submit, poll, info and drain may be
+ * called from any host thread.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  nlte_solve_stats stats;
+  double t_submit_ms;    /* host steady clock, ms since the server was created */
+  double t_admit_ms;
+  double t_done_ms;      /* when the server saw the solve finish               */
+} nlte_server_result;
+
+typedef struct {
+  int64_t steps;         /* device steps run                                   */
+  int64_t submitted, completed;
+  int32_t active, queued;
+  int64_t active_bytes;  /* device arena bytes of the columns in flight        */
+  double busy_ms;        /* host time spent with columns in flight             */
+} nlte_server_info;
+
+/* opts as for nlte_solve (opts->init must be 1: LTE unless a request brings
+ * n0); max_active >= 1; hbm_budget > 0 bytes. */
+nlte_status nlte_server_create(nlte_ctx *ctx, size_t hbm_budget, int32_t max_active,
+                               const nlte_solve_opts *opts, nlte_server **out);
+/* Queues a solve of col; *ticket identifies it for nlte_server_poll. */
+nlte_status nlte_server_submit(nlte_server *srv, nlte_column *col, const double *n0_dev,
+                               uint64_t *ticket);
+/* NLTE_OK: the solve has finished; its populations are copied to n_out_dev
+ * ([nz][nlev] device memory, or NULL) and its result to *res (or NULL), and
+ * the ticket is released.  NLTE_E_BUSY: not finished yet (nothing copied).
+ * NLTE_E_INVALID: unknown ticket.  A solve that stops at maxiter is finished
+ * with res->stats.status = NLTE_E_NOCONV. */
+nlte_status nlte_server_poll(nlte_server *srv, uint64_t ticket, double *n_out_dev,
+                             nlte_server_result *res);
+/* Blocks until no request is queued or in flight, or timeout_s elapses
+ * (NLTE_E_BUSY). */
+nlte_status nlte_server_drain(nlte_server *srv, double timeout_s);
+nlte_status nlte_server_info_get(const nlte_server *srv, nlte_server_info *out);
+/* Stops the thread (requests still queued or in flight are dropped). */
+void nlte_server_destroy(nlte_server *srv);
 
 /* Turns kernel timing of subsequent solves on this context on (nonzero) or
  * off, and clears the accumulated profile.  Adds two HIP events per launch. */

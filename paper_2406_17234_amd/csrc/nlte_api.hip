@@ -58,6 +58,7 @@ const ColDev& column_dev(const nlte_column* c) { return c->h; }
 ColDev* column_dev_ptr(const nlte_column* c) { return c->d; }
 int column_restart_cap(const nlte_column* c) { return c->restart_cap; }
 nlte_ctx* column_ctx(const nlte_column* c) { return c->ctx; }
+size_t column_bytes(const nlte_column* c) { return c->arena_bytes; }
 }  // namespace nlte
 
 extern "C" nlte_status nlte_ctx_create(int hip_device, nlte_ctx** out) {
@@ -548,9 +549,6 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     for (int t = 0; t < nline; ++t)
       if (tr[t].wlo < f1 && tr[t].whi > f0) ch_tr.push_back(t);
     ch_ptr[c + 1] = (int)ch_tr.size();
-    if (ch_ptr[c + 1] - ch_ptr[c] > kMaxChunkLines)
-      return set_err(NLTE_E_INVALID, "more than %d line windows overlap frequencies %d..%d",
-                     kMaxChunkLines, f0, f1 - 1);
   }
   std::vector<int> ch_eptr(C.nchunk + 1, 0), ch_ed;
   for (int c = 0; c < C.nchunk; ++c) {
@@ -558,9 +556,6 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     for (int t = nline; t < ntr; ++t)
       if (tr[t].wlo < f1 && tr[t].whi > f0) ch_ed.push_back(t);
     ch_eptr[c + 1] = (int)ch_ed.size();
-    if (ch_eptr[c + 1] - ch_eptr[c] > kMaxChunkEdges)
-      return set_err(NLTE_E_INVALID, "more than %d edge windows overlap frequencies %d..%d",
-                     kMaxChunkEdges, f0, f1 - 1);
   }
   std::vector<int4> pairs;
   for (int t = 0; t < ntr; ++t)
@@ -744,6 +739,12 @@ extern "C" void nlte_column_destroy(nlte_column* col) {
   if (col->d) hipFree(col->d);
   if (col->arena) hipFree(col->arena);
   delete col;
+}
+
+extern "C" nlte_status nlte_column_bytes(const nlte_column* col, size_t* bytes) {
+  if (!col || !bytes) return set_err(NLTE_E_INVALID, "NULL argument");
+  *bytes = col->arena_bytes;
+  return NLTE_OK;
 }
 
 extern "C" nlte_status nlte_column_dims(const nlte_column* col, int32_t dims[8]) {

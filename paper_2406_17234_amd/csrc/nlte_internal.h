@@ -24,8 +24,6 @@ constexpr int kWave = 64;       // lanes per wavefront (CDNA)
 constexpr int kMaxMu = 8;       // angles per hemisphere held in registers
 constexpr int kMaxLev = 16;     // levels per atom
 constexpr int kMaxRestart = 64; // GMRES restart length
-constexpr int kMaxChunkLines = 6;  // line windows overlapping one 64-frequency chunk
-constexpr int kMaxChunkEdges = 8;  // edge windows overlapping one 64-frequency chunk
 constexpr int kMaxEdges = kMaxLev - 1;
 
 // Loads and stores through the global address space (the pointers live in
@@ -196,6 +194,17 @@ struct BatchWork {
 // four events: before the formal-solution launch, after it, after the
 // lane-per-depth work and after assembly.
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev = nullptr);
+
+// Solver driver pieces (nlte_solver.hip) shared by the batch solve and the
+// server: option checks, per-column initialisation (n0[c] NULL: LTE), one
+// Newton/Krylov step of every column, and a copy of the columns' states.
+nlte_status check_solve_opts(const nlte_solve_opts& o);
+hipError_t solver_init(const ColDev* cols, int ncol, const double* const* n0,
+                       const nlte_solve_opts& o, hipStream_t s);
+hipError_t solver_step(const ColDev* cols, int ncol, int* done, hipStream_t s);
+hipError_t solver_gather(const ColDev* cols, int ncol, ColState* out, hipStream_t s);
+bool state_done(const ColState& st);
+void state_stats(const ColState& st, nlte_solve_stats* out);
 
 void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
                       std::vector<TileGroup>& groups, std::vector<int4>& rate,

@@ -1,0 +1,385 @@
+// Serving loop: continuous batching of JFNK column solves on one device.
+//
+// One host thread per server drives a non-blocking HIP stream.  Each pass of
+// its loop admits queued requests (FIFO, within the HBM budget and the slot
+// count), initialises their solver state on the device, replays kSteps solver
+// steps over every column in flight (the same launches as the batch solve:
+// one residual evaluation per column per step, then one Newton/Krylov step),
+// reads back the columns' states and retires the finished ones.  Work lists
+// are rebuilt whenever the set of columns in flight changes.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "nlte_internal.h"
+
+nlte_status set_err(nlte_status st, const char* fmt, ...);
+
+namespace nlte {
+const ColDev& column_dev(const nlte_column* c);
+nlte_ctx* column_ctx(const nlte_column* c);
+size_t column_bytes(const nlte_column* c);
+}  // namespace nlte
+
+using namespace nlte;
+
+namespace {
+
+constexpr int kSteps = 4;  // device steps between state read-backs
+
+enum ReqState { kQueued = 0, kActive = 1, kDone = 2 };
+
+struct Request {
+  uint64_t ticket = 0;
+  nlte_column* col = nullptr;
+  const double* n0 = nullptr;
+  size_t bytes = 0;
+  int state = kQueued;
+  nlte_server_result res{};
+};
+
+// Device buffer that only grows.
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t cap = 0;
+  hipError_t fit(size_t n) {
+    if (n <= cap) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      if (e != hipSuccess) return e;
+      p = nullptr;
+    }
+    size_t c = cap ? cap : 64;
+    while (c < n) c *= 2;
+    hipError_t e = hipMalloc(&p, c * sizeof(T));
+    if (e == hipSuccess) cap = c;
+    return e;
+  }
+  ~DevBuf() {
+    if (p) hipFree(p);
+  }
+};
+
+double now_ms(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct nlte_server {
+  nlte_ctx* ctx = nullptr;
+  size_t budget = 0;
+  int max_active = 0;
+  nlte_solve_opts opts{};
+  hipStream_t stream = nullptr;
+  hipStream_t copy_stream = nullptr;
+  std::chrono::steady_clock::time_point t0;
+
+  std::mutex mu;
+  std::condition_variable cv;       // work arrived / stop
+  std::condition_variable cv_idle;  // a request finished
+  std::deque<Request*> queue;
+  std::unordered_map<uint64_t, Request*> reqs;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  nlte_status fail = NLTE_OK;
+  nlte_server_info info{};
+
+  // server-thread state
+  std::vector<Request*> active;
+  DevBuf<ColDev> d_cols;
+  DevBuf<Tile> d_tiles;
+  DevBuf<int4> d_rate;
+  DevBuf<int2> d_pb;
+  DevBuf<ColState> d_states;
+  DevBuf<const double*> d_n0;
+  DevBuf<int> d_done;
+  ColState* h_states = nullptr;  // pinned
+  size_t h_states_cap = 0;
+  BatchWork bw;
+  std::thread th;
+
+  hipError_t rebuild();
+  hipError_t admit(std::vector<Request*>& adm);
+  void run();
+};
+
+hipError_t nlte_server::rebuild() {
+  const int n = (int)active.size();
+  bw = BatchWork{};
+  if (n == 0) return hipSuccess;
+  std::vector<ColDev> hc(n);
+  for (int c = 0; c < n; ++c) hc[c] = column_dev(active[c]->col);
+  std::vector<Tile> tiles;
+  std::vector<TileGroup> groups;
+  std::vector<int4> rate;
+  std::vector<int2> pb;
+  int maxL = 0;
+  build_work_lists(hc.data(), n, tiles, groups, rate, pb, maxL);
+  hipError_t e;
+  if ((e = d_cols.fit(n)) != hipSuccess) return e;
+  if ((e = d_tiles.fit(std::max<size_t>(1, tiles.size()))) != hipSuccess) return e;
+  if ((e = d_rate.fit(std::max<size_t>(1, rate.size()))) != hipSuccess) return e;
+  if ((e = d_pb.fit(std::max<size_t>(1, pb.size()))) != hipSuccess) return e;
+  if ((e = d_states.fit(n)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(d_cols.p, hc.data(), n * sizeof(ColDev), hipMemcpyHostToDevice, stream)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(d_tiles.p, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, stream)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(d_rate.p, rate.data(), rate.size() * sizeof(int4), hipMemcpyHostToDevice, stream)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(d_pb.p, pb.data(), pb.size() * sizeof(int2), hipMemcpyHostToDevice, stream)) != hipSuccess) return e;
+  if ((size_t)n > h_states_cap) {
+    if (h_states) hipHostFree(h_states);
+    h_states = nullptr;
+    h_states_cap = 0;
+    size_t c = 64;
+    while (c < (size_t)n) c *= 2;
+    if ((e = hipHostMalloc((void**)&h_states, c * sizeof(ColState), hipHostMallocDefault)) != hipSuccess) return e;
+    h_states_cap = c;
+  }
+  bw.cols = d_cols.p;
+  bw.tiles = d_tiles.p;
+  bw.rate_work = d_rate.p;
+  bw.pb_work = d_pb.p;
+  bw.ncol = n;
+  bw.ntiles = (int)tiles.size();
+  bw.nrate = (int)rate.size();
+  bw.npb = (int)pb.size();
+  bw.any_newton = 1;
+  bw.ngroup = (int)groups.size();
+  for (int g = 0; g < bw.ngroup; ++g) bw.groups[g] = groups[g];
+  for (int c = 0; c < n; ++c) {
+    bw.maxnz = std::max(bw.maxnz, hc[c].nz);
+    if (hc[c].prec == NLTE_FP64) bw.any64 = 1; else bw.any32 = 1;
+  }
+  return hipSuccess;
+}
+
+// Newly admitted requests sit at the end of `active`; the work lists are
+// already rebuilt.  Initialise their solver state (n0 or LTE).
+hipError_t nlte_server::admit(std::vector<Request*>& adm) {
+  const int na = (int)adm.size();
+  if (!na) return hipSuccess;
+  std::vector<const double*> n0(na);
+  for (int i = 0; i < na; ++i) n0[i] = adm[i]->n0;
+  hipError_t e;
+  if ((e = d_n0.fit(na)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(d_n0.p, n0.data(), na * sizeof(const double*), hipMemcpyHostToDevice, stream)) != hipSuccess) return e;
+  const int first = (int)active.size() - na;
+  return solver_init(d_cols.p + first, na, d_n0.p, opts, stream);
+}
+
+void nlte_server::run() {
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = d_done.fit(1);
+  if (e == hipSuccess) e = hipMemsetAsync(d_done.p, 0, sizeof(int), stream);
+  bool dirty = false;
+  while (e == hipSuccess) {
+    std::vector<Request*> adm;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      if (active.empty() && queue.empty()) {
+        cv_idle.notify_all();
+        cv.wait(lk, [&] { return stop || !queue.empty(); });
+      }
+      if (stop) break;
+      size_t bytes = (size_t)info.active_bytes;
+      while (!queue.empty() && (int)(active.size() + adm.size()) < max_active) {
+        Request* r = queue.front();
+        const bool empty = active.empty() && adm.empty();
+        if (!empty && bytes + r->bytes > budget) break;
+        queue.pop_front();
+        r->state = kActive;
+        r->res.t_admit_ms = now_ms(t0);
+        bytes += r->bytes;
+        adm.push_back(r);
+      }
+      info.active_bytes = (int64_t)bytes;
+      info.queued = (int32_t)queue.size();
+    }
+    if (!adm.empty()) {
+      active.insert(active.end(), adm.begin(), adm.end());
+      dirty = true;
+    }
+    if (dirty) {
+      if ((e = rebuild()) != hipSuccess) break;
+      if ((e = admit(adm)) != hipSuccess) break;
+      dirty = false;
+    }
+    const int n = (int)active.size();
+    const double tb = now_ms(t0);
+    for (int r = 0; r < kSteps && e == hipSuccess; ++r) {
+      e = launch_residual(bw, stream);
+      if (e == hipSuccess) e = solver_step(bw.cols, n, d_done.p, stream);
+    }
+    if (e == hipSuccess) e = solver_gather(bw.cols, n, d_states.p, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h_states, d_states.p, n * sizeof(ColState), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) break;
+    const double t = now_ms(t0);
+    std::vector<Request*> still;
+    still.reserve(n);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      info.steps += kSteps;
+      info.busy_ms += t - tb;
+      for (int c = 0; c < n; ++c) {
+        Request* r = active[c];
+        if (state_done(h_states[c])) {
+          state_stats(h_states[c], &r->res.stats);
+          r->res.t_done_ms = t;
+          r->state = kDone;
+          info.active_bytes -= (int64_t)r->bytes;
+          info.completed += 1;
+          dirty = true;
+        } else {
+          still.push_back(r);
+        }
+      }
+      info.active = (int32_t)still.size();
+    }
+    if (dirty) cv_idle.notify_all();
+    active.swap(still);
+  }
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> lk(mu);
+    fail = NLTE_E_DEVICE;
+    for (auto& kv : reqs) {
+      Request* r = kv.second;
+      if (r->state != kDone) {
+        r->state = kDone;
+        r->res.stats.status = NLTE_E_DEVICE;
+        r->res.t_done_ms = now_ms(t0);
+      }
+    }
+    queue.clear();
+    active.clear();
+    cv_idle.notify_all();
+  }
+}
+
+extern "C" nlte_status nlte_server_create(nlte_ctx* ctx, size_t hbm_budget, int32_t max_active,
+                                          const nlte_solve_opts* opts, nlte_server** out) {
+  if (!ctx || !out || hbm_budget == 0 || max_active < 1)
+    return set_err(NLTE_E_INVALID, "bad server arguments");
+  nlte_solve_opts o;
+  nlte_solve_opts_default(&o);
+  if (opts) o = *opts;
+  const nlte_status vs = check_solve_opts(o);
+  if (vs != NLTE_OK) return vs;
+  if (o.init != 1) return set_err(NLTE_E_INVALID, "server requests start from n0 or LTE (opts.init = 1)");
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(NLTE_E_DEVICE, "hipSetDevice failed");
+  nlte_server* S = new nlte_server();
+  S->ctx = ctx;
+  S->budget = hbm_budget;
+  S->max_active = max_active;
+  S->opts = o;
+  S->t0 = std::chrono::steady_clock::now();
+  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+    if (S->stream) hipStreamDestroy(S->stream);
+    delete S;
+    return set_err(NLTE_E_DEVICE, "stream creation failed");
+  }
+  S->th = std::thread([S] { S->run(); });
+  *out = S;
+  return NLTE_OK;
+}
+
+extern "C" nlte_status nlte_server_submit(nlte_server* S, nlte_column* col, const double* n0_dev,
+                                          uint64_t* ticket) {
+  if (!S || !col || !ticket) return set_err(NLTE_E_INVALID, "NULL argument");
+  if (column_ctx(col) != S->ctx) return set_err(NLTE_E_INVALID, "column from another context");
+  Request* r = new Request();
+  r->col = col;
+  r->n0 = n0_dev;
+  r->bytes = column_bytes(col);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->fail != NLTE_OK) {
+      delete r;
+      return set_err(S->fail, "server stopped after a device error");
+    }
+    for (auto& kv : S->reqs)
+      if (kv.second->col == col) {
+        delete r;
+        return set_err(NLTE_E_INVALID, "column already submitted (ticket %llu)",
+                       (unsigned long long)kv.first);
+      }
+    r->ticket = S->next_ticket++;
+    r->res.t_submit_ms = now_ms(S->t0);
+    S->reqs[r->ticket] = r;
+    S->queue.push_back(r);
+    S->info.submitted += 1;
+    S->info.queued = (int32_t)S->queue.size();
+  }
+  S->cv.notify_one();
+  *ticket = r->ticket;
+  return NLTE_OK;
+}
+
+extern "C" nlte_status nlte_server_poll(nlte_server* S, uint64_t ticket, double* n_out_dev,
+                                        nlte_server_result* res) {
+  if (!S) return set_err(NLTE_E_INVALID, "NULL server");
+  Request* r = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return set_err(NLTE_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    if (it->second->state != kDone) return set_err(NLTE_E_BUSY, "ticket %llu not finished", (unsigned long long)ticket);
+    r = it->second;
+    S->reqs.erase(it);
+  }
+  nlte_status st = NLTE_OK;
+  if (n_out_dev && r->res.stats.status != NLTE_E_DEVICE) {
+    const ColDev& C = column_dev(r->col);
+    if (hipMemcpyAsync(n_out_dev, C.n, (size_t)C.N * sizeof(double), hipMemcpyDeviceToDevice,
+                       S->copy_stream) != hipSuccess ||
+        hipStreamSynchronize(S->copy_stream) != hipSuccess)
+      st = set_err(NLTE_E_DEVICE, "copy of the result failed");
+  }
+  if (res) *res = r->res;
+  delete r;
+  return st;
+}
+
+extern "C" nlte_status nlte_server_drain(nlte_server* S, double timeout_s) {
+  if (!S) return set_err(NLTE_E_INVALID, "NULL server");
+  std::unique_lock<std::mutex> lk(S->mu);
+  const auto until = std::chrono::steady_clock::now() +
+                     std::chrono::microseconds((long long)(timeout_s * 1e6));
+  const bool ok = S->cv_idle.wait_until(lk, until, [&] {
+    return S->fail != NLTE_OK || (S->queue.empty() && S->info.completed == S->info.submitted);
+  });
+  if (S->fail != NLTE_OK) return set_err(S->fail, "server stopped after a device error");
+  return ok ? NLTE_OK : set_err(NLTE_E_BUSY, "drain timed out");
+}
+
+extern "C" nlte_status nlte_server_info_get(const nlte_server* S, nlte_server_info* out) {
+  if (!S || !out) return set_err(NLTE_E_INVALID, "NULL argument");
+  nlte_server* m = const_cast<nlte_server*>(S);
+  std::lock_guard<std::mutex> lk(m->mu);
+  *out = m->info;
+  return NLTE_OK;
+}
+
+extern "C" void nlte_server_destroy(nlte_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_all();
+  if (S->th.joinable()) S->th.join();
+  hipSetDevice(S->ctx->device);
+  hipStreamSynchronize(S->stream);
+  for (auto& kv : S->reqs) delete kv.second;
+  if (S->h_states) hipHostFree(S->h_states);
+  hipStreamDestroy(S->stream);
+  hipStreamDestroy(S->copy_stream);
+  delete S;
+}

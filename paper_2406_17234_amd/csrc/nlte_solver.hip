@@ -611,6 +611,57 @@ extern "C" nlte_status nlte_zero_radiation_populations(nlte_column* col, double*
   return NLTE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// driver pieces shared by the batch solve and the server
+// ---------------------------------------------------------------------------
+__global__ void k_gather_state(const ColDev* __restrict__ cols, ColState* __restrict__ out, int ncol) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncol) out[c] = *cols[c].st;
+}
+
+namespace nlte {
+
+nlte_status check_solve_opts(const nlte_solve_opts& o) {
+  if (o.restart < 1 || o.restart > kMaxM) return set_err(NLTE_E_INVALID, "restart must be 1..%d", kMaxM);
+  if (o.maxiter < 0 || o.max_krylov < 1 || o.max_krylov_total < 0 || o.max_halvings < 0 ||
+      !(o.ftol >= 0) || !(o.rtol > 0) || !(o.eps_scale > 0) || o.init < 0 || o.init > 2)
+    return set_err(NLTE_E_INVALID, "invalid solve options");
+  return NLTE_OK;
+}
+
+hipError_t solver_init(const ColDev* cols, int ncol, const double* const* n0, const nlte_solve_opts& o,
+                       hipStream_t s) {
+  InitArgs ia{o.ftol, o.rtol, 2.220446049250313e-16, o.eps_scale, o.maxiter, o.max_krylov,
+              o.restart, o.max_halvings, 0, o.max_krylov_total};
+  k_solver_init<<<ncol, kThreads, 0, s>>>(cols, n0, ia);
+  return hipGetLastError();
+}
+
+hipError_t solver_step(const ColDev* cols, int ncol, int* done, hipStream_t s) {
+  k_solver_step<<<ncol, kThreads, 0, s>>>(cols, done);
+  return hipGetLastError();
+}
+
+hipError_t solver_gather(const ColDev* cols, int ncol, ColState* out, hipStream_t s) {
+  k_gather_state<<<(ncol + 127) / 128, 128, 0, s>>>(cols, out, ncol);
+  return hipGetLastError();
+}
+
+bool state_done(const ColState& st) { return st.phase == PH_DONE; }
+
+void state_stats(const ColState& st, nlte_solve_stats* out) {
+  out->status = st.phase == PH_DONE ? st.status : NLTE_E_NOCONV;
+  out->newton_iters = st.newton_it;
+  out->krylov_iters = st.krylov_total;
+  out->f_calls = st.f_calls;
+  out->stalls = st.stalls;
+  out->precond_calls = st.precond_calls;
+  out->rho_inf = st.rho_cur;
+  out->dn_inf = st.dn_inf;
+}
+
+}  // namespace nlte
+
 namespace {
 struct Batch {
   ColDev* cols = nullptr;       // device array of column descriptors
@@ -643,11 +694,10 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   nlte_solve_opts o;
   nlte_solve_opts_default(&o);
   if (opts) o = *opts;
-  if (o.restart < 1 || o.restart > kMaxM) return set_err(NLTE_E_INVALID, "restart must be 1..%d", kMaxM);
-  if (o.maxiter < 0 || o.max_krylov < 1 || o.max_krylov_total < 0 || o.max_halvings < 0 ||
-      !(o.ftol >= 0) || !(o.rtol > 0) ||
-      !(o.eps_scale > 0))
-    return set_err(NLTE_E_INVALID, "invalid solve options");
+  {
+    const nlte_status vs = check_solve_opts(o);
+    if (vs != NLTE_OK) return vs;
+  }
   if (o.init == 0 && !n0_dev) return set_err(NLTE_E_INVALID, "init = 0 needs n0");
   HIP_TRY(hipSetDevice(ctx->device));
   Batch b;
@@ -760,19 +810,10 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   HIP_TRY(hipStreamSynchronize(s));
   bool all_ok = true;
   for (int c = 0; c < ncol; ++c) {
-    const ColState& st = sts[c];
-    const int status = st.phase == PH_DONE ? st.status : NLTE_E_NOCONV;
-    if (status != NLTE_OK) all_ok = false;
-    if (stats) {
-      stats[c].status = status;
-      stats[c].newton_iters = st.newton_it;
-      stats[c].krylov_iters = st.krylov_total;
-      stats[c].f_calls = st.f_calls;
-      stats[c].stalls = st.stalls;
-      stats[c].precond_calls = st.precond_calls;
-      stats[c].rho_inf = st.rho_cur;
-      stats[c].dn_inf = st.dn_inf;
-    }
+    nlte_solve_stats one;
+    state_stats(sts[c], &one);
+    if (one.status != NLTE_OK) all_ok = false;
+    if (stats) stats[c] = one;
   }
   // leave columns idle for later residual calls
   for (int c = 0; c < ncol; ++c) HIP_TRY(hipMemsetAsync(hc[c].st, 0, 3 * sizeof(int), s));

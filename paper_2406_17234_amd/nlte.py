@@ -74,6 +74,25 @@ class Profile(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerResult(C.Structure):
+    _fields_ = [("stats", SolveStats), ("t_submit_ms", C.c_double), ("t_admit_ms", C.c_double),
+                ("t_done_ms", C.c_double)]
+
+    def as_dict(self):
+        d = self.stats.as_dict()
+        d.update(t_submit_ms=self.t_submit_ms, t_admit_ms=self.t_admit_ms, t_done_ms=self.t_done_ms)
+        return d
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("submitted", C.c_int64), ("completed", C.c_int64),
+                ("active", C.c_int32), ("queued", C.c_int32), ("active_bytes", C.c_int64),
+                ("busy_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -98,6 +117,7 @@ def lib():
         L.nlte_column_destroy.argtypes = [vp]
         L.nlte_column_destroy.restype = None
         L.nlte_column_dims.argtypes = [vp, _ip]
+        L.nlte_column_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.nlte_lte_populations.argtypes = [vp, vp, vp]
         L.nlte_zero_radiation_populations.argtypes = [vp, vp, vp]
         L.nlte_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
@@ -109,6 +129,14 @@ def lib():
         L.nlte_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
         L.nlte_solve_opts_default.restype = None
         L.nlte_voigt_host.argtypes = [C.c_double, _dp, C.c_int32, _dp]
+        L.nlte_server_create.argtypes = [vp, C.c_size_t, C.c_int32, C.POINTER(SolveOpts),
+                                         C.POINTER(vp)]
+        L.nlte_server_submit.argtypes = [vp, vp, vp, C.POINTER(C.c_uint64)]
+        L.nlte_server_poll.argtypes = [vp, C.c_uint64, vp, C.POINTER(ServerResult)]
+        L.nlte_server_drain.argtypes = [vp, C.c_double]
+        L.nlte_server_info_get.argtypes = [vp, C.POINTER(ServerInfo)]
+        L.nlte_server_destroy.argtypes = [vp]
+        L.nlte_server_destroy.restype = None
         L.nlte_profile_enable.argtypes = [vp, C.c_int]
         L.nlte_profile_read.argtypes = [vp, C.POINTER(Profile)]
         _lib = L
@@ -227,6 +255,9 @@ class Column:
         _check(lib().nlte_column_dims(h, dims))
         self.nz, self.nlev, self.ntr, self.nline, self.nbf, self.nnu, self.nmu, self.precision = list(dims)
         self.device = torch.device("cuda", ctx.device)
+        nb = C.c_size_t()
+        _check(lib().nlte_column_bytes(h, C.byref(nb)))
+        self.bytes = nb.value
 
     def close(self):
         if getattr(self, "h", None):
@@ -306,3 +337,56 @@ def solve_batch(ctx: Context, columns, opts: SolveOpts | None = None, n0=None, s
     if rc not in (NLTE_OK, NLTE_E_NOCONV):
         _check(rc)
     return outs, [s.as_dict() for s in stats], rc
+
+
+class Server:
+    """Continuous-batching solve server (nlte_server_*): submit columns, poll
+    tickets.  Columns stay owned by the caller and must not be touched until
+    their ticket has been polled."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_active: int = 4096,
+                 opts: SolveOpts | None = None, **kw):
+        if opts is None:
+            opts = default_opts(**kw)
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(lib().nlte_server_create(ctx.h, int(hbm_budget), int(max_active), C.byref(opts),
+                                        C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, column: Column, n0=None) -> int:
+        t = C.c_uint64()
+        _check(lib().nlte_server_submit(self.h, column.h, _ptr(n0), C.byref(t)))
+        self._keep[t.value] = (column, n0)
+        return t.value
+
+    def poll(self, ticket: int, out=None):
+        """(populations or None, result dict) once finished, else None."""
+        res = ServerResult()
+        st = lib().nlte_server_poll(self.h, C.c_uint64(ticket), _ptr(out), C.byref(res))
+        if st == NLTE_E_BUSY:
+            return None
+        _check(st)
+        self._keep.pop(ticket, None)
+        return out, res.as_dict()
+
+    def drain(self, timeout_s: float = 600.0):
+        _check(lib().nlte_server_drain(self.h, float(timeout_s)))
+
+    def info(self) -> dict:
+        i = ServerInfo()
+        _check(lib().nlte_server_info_get(self.h, C.byref(i)))
+        return i.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nlte_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -451,14 +451,15 @@ def batch6_column(i: int, nmu: int = 5) -> Problem:
     return Problem(f"batch6[{i}]", atom, atm, grid, make_collisions(atom, atm), seed)
 
 
-def stream_request(j: int) -> Problem:
+def stream_request(j: int, nz_max: int = 256, nnu_max: int = 2000) -> Problem:
     """Request j of the served stream: atom uniform over 3/6/11 levels,
-    Nz ~ U{48..256}, Nnu ~ U{200..2000}, Nmu ~ U{3..8}."""
+    Nz ~ U{48..nz_max}, Nnu ~ U{200..nnu_max}, Nmu ~ U{3..8} (defaults: the
+    served-stream workload; smaller bounds give quick test cases)."""
     seed = 4_000_000 + j
     rng = np.random.default_rng(seed)
     nlev = int(rng.choice([3, 6, 11]))
-    nz = int(rng.integers(48, 257))
-    nnu = int(rng.integers(200, 2001))
+    nz = int(rng.integers(48, nz_max + 1))
+    nnu = int(rng.integers(200, nnu_max + 1))
     nmu = int(rng.integers(3, 9))
     atom = _cached_atom(nlev)
     atm = chromosphere(nz=nz, abund=ABUND[nlev], perturb_seed=seed)

@@ -50,3 +50,14 @@ def test_invalid_device_is_reported():
 def test_default_options():
     o = nlte.default_opts()
     assert o.ftol == 1e-8 and o.rtol == 1e-3 and o.restart == 30 and o.maxiter == 50
+
+
+def test_server_rejects_bad_arguments_without_a_device():
+    """Argument checks of the server entry points run before any device use."""
+    L = nlte.lib()
+    h = ctypes.c_void_p()
+    assert L.nlte_server_create(None, 1 << 30, 16, None, ctypes.byref(h)) == nlte.NLTE_E_INVALID
+    t = ctypes.c_uint64()
+    assert L.nlte_server_submit(None, None, None, ctypes.byref(t)) == nlte.NLTE_E_INVALID
+    assert L.nlte_server_poll(None, ctypes.c_uint64(1), None, None) == nlte.NLTE_E_INVALID
+    assert L.nlte_server_drain(None, ctypes.c_double(0.0)) == nlte.NLTE_E_INVALID
