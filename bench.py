@@ -102,7 +102,8 @@ def cpu_baseline(workload, ncol, ftol, rtol, budget_s=20.0):
     }
 
 
-def serve_stream(ctx, nlte, duration_s, rate, budget_gb, max_active, ftol, rtol, max_krylov_total):
+def serve_stream(ctx, nlte, duration_s, rate, budget_gb, max_active, ftol, rtol, max_krylov_total,
+                 fp64_fallback):
     """Served stream: Poisson arrivals of mixed 3/6/11-level requests (FP32
     form), submitted at their arrival times to a continuous-batching server.
     Column setup happens before the timed window (its cost is reported
@@ -120,7 +121,8 @@ def serve_stream(ctx, nlte, duration_s, rate, budget_gb, max_active, ftol, rtol,
     setup_s = time.perf_counter() - t0
     print(f"[bench] stream: {nreq} requests generated in {gen_s:.1f} s, set up in {setup_s:.1f} s",
           file=sys.stderr, flush=True)
-    opts = nlte.default_opts(ftol=ftol, rtol=rtol, maxiter=50, max_krylov_total=max_krylov_total)
+    opts = nlte.default_opts(ftol=ftol, rtol=rtol, maxiter=50, max_krylov_total=max_krylov_total,
+                             fp64_fallback=fp64_fallback)
     srv = nlte.Server(ctx, hbm_budget=int(budget_gb * (1 << 30)), max_active=max_active, opts=opts)
     tickets = []
     t_start = time.perf_counter()
@@ -143,6 +145,7 @@ def serve_stream(ctx, nlte, duration_s, rate, budget_gb, max_active, ftol, rtol,
         "columns_converged_per_s": float(conv.sum()) / span_s,
         "columns_per_s": nreq / span_s,
         "converged_fraction": float(conv.mean()),
+        "fp64_fallback_fraction": float(np.mean([r["precision"] == 0 for r in res])),
         "latency_ms_p50": float(np.percentile(lat, 50)),
         "latency_ms_p99": float(np.percentile(lat, 99)),
         "latency_ms_max": float(lat.max()),
@@ -154,6 +157,26 @@ def serve_stream(ctx, nlte, duration_s, rate, budget_gb, max_active, ftol, rtol,
     for c in cols:
         c.close()
     return out
+
+
+def single_fp64(ctx, nlte, problems, rtol):
+    """The plain single-column FP64 GPU JFNK on the same columns, one solve at
+    a time, to the scaled residual 1e-8 (populations to ~1e-8, tighter than the
+    1e-4 the FP32 form is held to)."""
+    import torch
+    cols = [nlte.Column(ctx, p, precision=nlte.FP64) for p in problems]
+    opts = nlte.default_opts(ftol=1e-8, rtol=rtol, maxiter=50)
+    cols[0].solve(opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = [c.solve(opts=opts)[2] for c in cols]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for c in cols:
+        c.close()
+    return {"columns": len(cols), "columns_per_s": len(cols) / dt,
+            "converged_fraction": float(np.mean([s["status"] == 0 for s in st])),
+            "ms_per_column": dt / len(cols) * 1e3, "ftol": 1e-8}
 
 
 def copy_calibration(nbytes=256 << 20, reps=3):
@@ -181,6 +204,11 @@ def main():
                     help="Krylov budget per column solve (0: none); bounds the cost of columns "
                          "that do not converge, which otherwise set the length of the batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-fallback", type=int, default=12,
+                    help="FP32-form columns not converged after this many Newton iterations "
+                         "continue in FP64 (0: never)")
+    ap.add_argument("--single-fp64", type=int, default=16,
+                    help="columns of the workload also solved one at a time in FP64 (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="arrival window of the served-stream phase (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -220,7 +248,8 @@ def main():
     print(f"[bench] created {ncol} columns in {setup_s:.1f} s", file=sys.stderr, flush=True)
     dp_col = np.array([p.depth_points() for p in problems], dtype=np.float64)
     opts = nlte.default_opts(ftol=ftol, rtol=args.rtol, maxiter=50,
-                             max_krylov_total=args.max_krylov_total)
+                             max_krylov_total=args.max_krylov_total,
+                             fp64_fallback=args.fp64_fallback)
 
     for w in range(args.warmup):
         _, st, rc = nlte.solve_batch(ctx, cols, opts)
@@ -267,13 +296,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "columns": ncol,
                    "ftol": ftol, "rtol": args.rtol, "maxiter": 50,
-                   "max_krylov_total": args.max_krylov_total,
+                   "max_krylov_total": args.max_krylov_total, "fp64_fallback": args.fp64_fallback,
                    "mean_nz": float(np.mean([p.atmos.nz for p in problems])),
                    "mean_nnu": float(np.mean([p.grid.nnu for p in problems]))},
         "columns_converged_per_s": float(conv.sum()) / elapsed,
         "converged_fraction": float(conv.mean()),
         "residual_calls_per_column": float(f_calls.mean()),
         "newton_iters_mean": float(np.mean([[s["newton_iters"] for s in st] for st in stats_all])),
+        "fp64_fallback_fraction": float(np.mean([[s["precision"] == 0 and prec == 1 for s in st]
+                                                 for st in stats_all])),
         "kernel_ms_per_step": {k: prof[k] / args.steps for k in
                                ("formal_ms", "depth_ms", "assemble_ms", "solver_ms")},
         "roofline": {
@@ -289,13 +320,15 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if args.single_fp64 > 0:
+        out["single_column_fp64"] = single_fp64(ctx, nlte, problems[:args.single_fp64], args.rtol)
     if args.serve_seconds > 0:
         for c in cols:
             c.close()
         cols = None
         out["served"] = serve_stream(ctx, nlte, args.serve_seconds, args.serve_rate,
                                      args.serve_budget_gb, args.serve_max_active, 1e-6,
-                                     args.rtol, args.max_krylov_total)
+                                     args.rtol, args.max_krylov_total, args.fp64_fallback)
     print(json.dumps(out))
 
 

@@ -117,7 +117,10 @@ typedef struct {
   int32_t max_krylov_total; /* Krylov iterations over the whole solve; once spent,
                           * each Newton iteration takes one Krylov step (a
                           * preconditioned residual step).  0: no limit (default) */
-  int32_t reserved;    /* 0                                                      */
+  int32_t fp64_fallback; /* FP32-form columns that have not converged after this
+                          * many Newton iterations continue with FP64 formal
+                          * solutions from their current iterate (0: never,
+                          * default 0)                                        */
 } nlte_solve_opts;
 
 typedef struct {
@@ -129,6 +132,9 @@ typedef struct {
   int32_t precond_calls; /* evaluations that also built the preconditioner      */
   double rho_inf;        /* final max |F|/gross rate                            */
   double dn_inf;         /* last 0.5 max|(n - n_prev)/(n + n_prev)|             */
+  int32_t precision;     /* precision of the last evaluation (nlte_precision)   */
+  int32_t fp64_evals;    /* residual evaluations run in FP64 by an FP32-form
+                          * column after a fallback (0 otherwise)               */
 } nlte_solve_stats;
 
 /* Kernel timings accumulated by solves on a context while profiling is on

@@ -98,7 +98,7 @@ extern "C" void nlte_solve_opts_default(nlte_solve_opts* o) {
   o->maxiter = 50;
   o->max_krylov = 200;
   o->max_krylov_total = 0;
-  o->reserved = 0;
+  o->fp64_fallback = 0;
   o->restart = 30;
   o->max_halvings = 8;
   o->init = 1;
@@ -463,6 +463,7 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.xk = Lo.take<double>(N);
   C.w = Lo.take<double>(N);
   C.lam = Lo.take<double>(nz);
+  C.n_init = Lo.take<double>(N);
   C.dots = Lo.take<double>(2 * (m_cap + 1));
   *wbase = Lo.take<int>(ntr + 1);
   *lbase = Lo.take<int>(std::max(C.nline, 1) + 1);
@@ -786,15 +787,16 @@ __global__ void k_check_finite_pos(const double* __restrict__ n, int N, int* __r
   }
 }
 
-__global__ void k_set_eval(ColState* st, int mode, int want_J, int rows_own) {
+__global__ void k_set_eval(ColState* st, int mode, int want_J, int rows_own, int prec) {
   st->mode = mode;
   st->want_J = want_J;
   st->rows_own = rows_own;
+  st->cur_prec = prec;
 }
 
 namespace nlte {
 hipError_t set_state_eval(nlte_column* col, int mode, int want_J, int rows_own, hipStream_t s) {
-  k_set_eval<<<1, 1, 0, s>>>(col->h.st, mode, want_J, rows_own);
+  k_set_eval<<<1, 1, 0, s>>>(col->h.st, mode, want_J, rows_own, col->h.prec);
   return hipGetLastError();
 }
 }  // namespace nlte

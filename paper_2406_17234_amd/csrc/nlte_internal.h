@@ -93,6 +93,10 @@ struct ColState {
   int init_kind, done_flag;
   int krylov_step;  // Krylov iterations of the current Newton step
   int max_krylov_total;  // 0: no limit
+  int cur_prec;     // precision the next evaluation runs in (FP32-form columns may switch to FP64)
+  int fp64_fallback;  // FP32-form columns not converged after this many Newton iterations switch (0: never)
+  int fp64_evals;   // FP64 evaluations after a switch
+  int pad3;
 };
 
 struct ColDev {
@@ -149,6 +153,7 @@ struct ColDev {
   int *piv;                        // [nz][L] pivots of the LU factors
   // solver buffers
   double *n;                       // [N] Newton iterate
+  double *n_init;                  // [N] initial populations of the solve
   double *Fn;                      // [N] residual at n
   double *Vk;                      // [(m+1) N] Krylov basis
   double *H;                       // [(m+1) m] Hessenberg matrix
@@ -183,6 +188,7 @@ struct BatchWork {
   TileGroup groups[2 * kMaxMu];
   int ngroup = 0;
   int maxnz = 0;                  // deepest column of the batch
+  int fallback = 0;               // FP32-form columns may run FP64 evaluations
   const int4* rate_work = nullptr;  // (col, transition, first depth, -)
   const int2* pb_work = nullptr;  // (col, first depth-entry index)
   int ncol = 0, ntiles = 0, nrate = 0, npb = 0;

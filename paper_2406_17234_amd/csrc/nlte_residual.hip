@@ -184,6 +184,7 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
   const int chunk = uni(tiles[tid].chunk);
   const ColDev& C = cols[col];
   if (uni(C.st->mode) == kModeIdle) return;
+  if (uni(C.st->cur_prec) != (sizeof(R) == sizeof(float) ? NLTE_FP32_FORM : NLTE_FP64)) return;
   const int nz = uni(C.nz), nnu = uni(C.nnu);
   const int k0 = blockIdx.y * KG;
   if (k0 >= nz) return;
@@ -448,6 +449,7 @@ __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
   const ColDev& C = cols[col];
   const int mode = uni(C.st->mode);
   if (mode != (PM ? kModeNewton : kModeF)) return;
+  if (uni(C.st->cur_prec) != (sizeof(R) == sizeof(float) ? NLTE_FP32_FORM : NLTE_FP64)) return;
   formal_tile<R, PM, NMU>(C, chunk, lane);
 }
 
@@ -715,10 +717,8 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     const TileGroup& G = bw.groups[g];
     const dim3 grid((G.count + 3) / 4, (bw.maxnz + kOpacDepths - 1) / kOpacDepths);
     const Tile* tl = bw.tiles + G.first;
-    if (G.prec == NLTE_FP32_FORM)
-      k_opacity<float><<<grid, 256, 0, s>>>(bw.cols, tl, G.count);
-    else
-      k_opacity<double><<<grid, 256, 0, s>>>(bw.cols, tl, G.count);
+    if (G.prec == NLTE_FP32_FORM) k_opacity<float><<<grid, 256, 0, s>>>(bw.cols, tl, G.count);
+    if (G.prec == NLTE_FP64 || bw.fallback) k_opacity<double><<<grid, 256, 0, s>>>(bw.cols, tl, G.count);
   }
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
@@ -727,7 +727,8 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     if (G.prec == NLTE_FP32_FORM) {
       launch_formal_mu<float, false>(G.nmu, nb, s, bw.cols, tl, G.count);
       if (bw.any_newton) launch_formal_mu<float, true>(G.nmu, nb, s, bw.cols, tl, G.count);
-    } else {
+    }
+    if (G.prec == NLTE_FP64 || bw.fallback) {
       launch_formal_mu<double, false>(G.nmu, nb, s, bw.cols, tl, G.count);
       if (bw.any_newton) launch_formal_mu<double, true>(G.nmu, nb, s, bw.cols, tl, G.count);
     }

@@ -155,6 +155,7 @@ hipError_t nlte_server::rebuild() {
     bw.maxnz = std::max(bw.maxnz, hc[c].nz);
     if (hc[c].prec == NLTE_FP64) bw.any64 = 1; else bw.any32 = 1;
   }
+  bw.fallback = opts.fp64_fallback > 0 && bw.any32;
   return hipSuccess;
 }
 

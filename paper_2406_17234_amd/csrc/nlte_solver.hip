@@ -42,6 +42,7 @@ constexpr int kMaxM = 32;  // restart capacity allocated per column
 // epsilon drown Jv in it.  Noise levels 1e-4..1e-2 all give converging
 // Newton sequences on the 6-level chromosphere; 1e-3 sits in the middle.
 constexpr double kFp32Noise = 1e-3;
+constexpr double kEpsMach64 = 2.220446049250313e-16;
 
 enum Phase : int { PH_IDLE = 0, PH_INIT = 1, PH_ARNOLDI = 2, PH_RESTART = 3, PH_LS = 4, PH_DONE = 5 };
 
@@ -292,6 +293,27 @@ __device__ void accept_point(const ColDev& C, double* red, int* done_count) {
     finish(C, NLTE_OK, done_count);
     return;
   }
+  const bool fallback = st->cur_prec == NLTE_FP32_FORM && st->fp64_fallback > 0 &&
+                        st->newton_it >= st->fp64_fallback && st->newton_it < st->maxiter;
+  __syncthreads();  // every thread has read the state before thread 0 changes it
+  if (fallback) {
+    // FP32 form not converging: start again from the initial populations
+    // with FP64 formal solutions (own rows, new P); an iterate the FP32
+    // Newton sequence wandered to is often a poor start
+    for (int i = threadIdx.x; i < C.N; i += kThreads) C.eval_n[i] = C.n_init[i];
+    if (C.has_sca)
+      for (int i = threadIdx.x; i < C.nz * C.nnu; i += kThreads) C.Jdag[i] = C.Bnu[i];
+    if (threadIdx.x == 0) {
+      st->cur_prec = NLTE_FP64;
+      st->eps_mach = kEpsMach64;
+      st->krylov_total = 0;
+      st->phase = PH_INIT;
+      st->mode = kModeNewton;
+      st->rows_own = 1;
+      st->want_J = 1;
+    }
+    return;
+  }
   if (st->newton_it >= st->maxiter) {
     finish(C, NLTE_E_NOCONV, done_count);
     return;
@@ -485,7 +507,10 @@ __global__ __launch_bounds__(kThreads) void k_solver_step(const ColDev* __restri
   const ColDev& C = cols[blockIdx.x];
   if (threadIdx.x == 0) {
     s_phase = C.st->phase;
-    if (s_phase != PH_DONE && s_phase != PH_IDLE) C.st->f_calls += 1;
+    if (s_phase != PH_DONE && s_phase != PH_IDLE) {
+      C.st->f_calls += 1;
+      if (C.prec == NLTE_FP32_FORM && C.st->cur_prec == NLTE_FP64) C.st->fp64_evals += 1;
+    }
     if (s_phase == PH_INIT || s_phase == PH_LS) C.st->precond_calls += 1;
   }
   __syncthreads();
@@ -502,15 +527,18 @@ __global__ __launch_bounds__(kThreads) void k_solver_step(const ColDev* __restri
 // Solve setup: options, initial populations, J-dagger = B, first evaluation.
 struct InitArgs {
   double ftol, rtol, eps_mach, eps_scale;
-  int maxiter, max_krylov, restart, max_halvings, init, max_krylov_total;
+  int maxiter, max_krylov, restart, max_halvings, init, max_krylov_total, fp64_fallback;
 };
 
 __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* const* n0, InitArgs a) {
   const ColDev& C = cols[blockIdx.x];
   ColState* st = C.st;
   const double* src = n0 ? n0[blockIdx.x] : nullptr;
-  for (int i = threadIdx.x; i < C.N; i += blockDim.x)
-    C.eval_n[i] = (a.init == 0 && src) ? src[i] : C.nstar[i];
+  for (int i = threadIdx.x; i < C.N; i += blockDim.x) {
+    const double v = (a.init == 0 && src) ? src[i] : C.nstar[i];
+    C.eval_n[i] = v;
+    C.n_init[i] = v;
+  }
   for (int i = threadIdx.x; i < C.nz * C.nnu; i += blockDim.x) C.Jdag[i] = C.Bnu[i];
   if (threadIdx.x == 0) {
     st->phase = PH_INIT;
@@ -534,6 +562,9 @@ __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* con
     st->maxiter = a.maxiter;
     st->max_krylov = a.max_krylov;
     st->max_krylov_total = a.max_krylov_total;
+    st->cur_prec = C.prec;
+    st->fp64_fallback = a.fp64_fallback;
+    st->fp64_evals = 0;
     st->restart = a.restart;
     st->max_halvings = a.max_halvings;
     st->mode = kModeNewton;
@@ -632,7 +663,7 @@ nlte_status check_solve_opts(const nlte_solve_opts& o) {
 hipError_t solver_init(const ColDev* cols, int ncol, const double* const* n0, const nlte_solve_opts& o,
                        hipStream_t s) {
   InitArgs ia{o.ftol, o.rtol, 2.220446049250313e-16, o.eps_scale, o.maxiter, o.max_krylov,
-              o.restart, o.max_halvings, 0, o.max_krylov_total};
+              o.restart, o.max_halvings, 0, o.max_krylov_total, o.fp64_fallback};
   k_solver_init<<<ncol, kThreads, 0, s>>>(cols, n0, ia);
   return hipGetLastError();
 }
@@ -658,6 +689,8 @@ void state_stats(const ColState& st, nlte_solve_stats* out) {
   out->precond_calls = st.precond_calls;
   out->rho_inf = st.rho_cur;
   out->dn_inf = st.dn_inf;
+  out->precision = st.cur_prec;
+  out->fp64_evals = st.fp64_evals;
 }
 
 }  // namespace nlte
@@ -739,6 +772,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   bw.ngroup = (int)groups.size();
   for (int g = 0; g < bw.ngroup; ++g) bw.groups[g] = groups[g];
   for (int c = 0; c < ncol; ++c) bw.maxnz = std::max(bw.maxnz, hc[c].nz);
+  bw.fallback = o.fp64_fallback > 0 && b.any32;
 
   HIP_TRY(hipMalloc(&b.nout, ncol * sizeof(double*)));
   HIP_TRY(hipMalloc(&b.done, sizeof(int)));
@@ -752,7 +786,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   }
   HIP_TRY(hipMemsetAsync(b.done, 0, sizeof(int), s));
   InitArgs ia{o.ftol, o.rtol, 2.220446049250313e-16, o.eps_scale, o.maxiter, o.max_krylov,
-              o.restart, o.max_halvings, o.init, o.max_krylov_total};
+              o.restart, o.max_halvings, o.init, o.max_krylov_total, o.fp64_fallback};
   k_solver_init<<<ncol, 256, 0, s>>>(b.cols, o.init == 0 ? b.n0 : nullptr, ia);
   if (o.init == 2) {
     for (int c = 0; c < ncol; ++c)

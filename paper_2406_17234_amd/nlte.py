@@ -54,13 +54,14 @@ class SolveOpts(C.Structure):
     _fields_ = [("ftol", C.c_double), ("rtol", C.c_double), ("maxiter", C.c_int32),
                 ("max_krylov", C.c_int32), ("restart", C.c_int32),
                 ("max_halvings", C.c_int32), ("init", C.c_int32), ("eps_scale", C.c_double),
-                ("max_krylov_total", C.c_int32), ("reserved", C.c_int32)]
+                ("max_krylov_total", C.c_int32), ("fp64_fallback", C.c_int32)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("newton_iters", C.c_int32),
                 ("krylov_iters", C.c_int32), ("f_calls", C.c_int32), ("stalls", C.c_int32),
-                ("precond_calls", C.c_int32), ("rho_inf", C.c_double), ("dn_inf", C.c_double)]
+                ("precond_calls", C.c_int32), ("rho_inf", C.c_double), ("dn_inf", C.c_double),
+                ("precision", C.c_int32), ("fp64_evals", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

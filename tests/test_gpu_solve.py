@@ -141,3 +141,22 @@ def test_krylov_budget_per_solve(ctx):
     n, _, st, rc = col.solve(ftol=1e-12, rtol=1e-6, maxiter=8, max_krylov_total=10)
     assert st["krylov_iters"] <= 10 + st["newton_iters"]
     assert st["newton_iters"] >= 1
+
+
+def test_fp32_form_falls_back_to_fp64(ctx):
+    """An 11-level FP32-form column that the FP32 formal solution cannot
+    drive to convergence finishes in FP64 after the fallback, at the FP64
+    root (to the FP32-form tolerance)."""
+    from paper_2406_17234_amd import nlte
+    prob = S.stream_request(0, nz_max=96, nnu_max=500)
+    c64 = nlte.Column(ctx, prob, precision=nlte.FP64)
+    n64, _, s64, rc64 = c64.solve(ftol=1e-6, rtol=1e-3, maxiter=40)
+    assert rc64 == 0
+    c32 = nlte.Column(ctx, prob, precision=nlte.FP32_FORM)
+    n32, _, s32, rc32 = c32.solve(ftol=1e-6, rtol=1e-3, maxiter=40, fp64_fallback=10)
+    print(s32, flush=True)
+    assert rc32 == 0 and s32["precision"] == nlte.FP64 and s32["fp64_evals"] > 0
+    assert maxrel(to_np(n32), to_np(n64)) < 1e-4
+    # without the fallback the column stays in FP32 (and its stats say so)
+    _, _, s0, _ = c32.solve(ftol=1e-6, rtol=1e-3, maxiter=3)
+    assert s0["precision"] == nlte.FP32_FORM and s0["fp64_evals"] == 0
