@@ -278,8 +278,46 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
 // One wave per 64-frequency chunk, one lane per frequency, all 2 NMU rays in
 // registers.  The first sweep (ingoing rays, top -> bottom) parks its share
 // of J in a scratch row; the second (outgoing rays, bottom -> top) writes J.
+// Depth-contiguous outputs ([nu][k]) of one wave leave through a per-wave LDS
+// tile of KF depths: each depth step parks its 64 values in a row of the
+// tile, and every KF depths the tile is written out as 64/KF-frequency x
+// KF-depth blocks, so a store instruction touches KF-value runs of a few rows
+// instead of 64 scattered values.  The tile is private to the wave; the
+// wavefront-scope fences order its LDS writes and reads across lanes.
+template <int KF>
+__device__ __forceinline__ void stage_put(double* tile, int k, int lane, double v) {
+  tile[(k % KF) * kWave + lane] = v;
+}
+
+template <int KF>
+__device__ __forceinline__ void stage_flush(const double* tile, double* __restrict__ out, int k0,
+                                            int nz, int f0, int nnu, int lane) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  constexpr int FS = kWave / KF;  // frequencies per store instruction
+  const int kk = lane % KF, fs = lane / KF;
+  const int k = k0 + kk;
+#pragma unroll
+  for (int i = 0; i < KF; ++i) {
+    const int fl = i * FS + fs;
+    const double v = tile[kk * kWave + fl];
+    if (k < nz && f0 + fl < nnu) stg(out + (size_t)(f0 + fl) * nz + k, v);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool PM> struct StageDepths { static constexpr int value = PM ? 4 : 8; };
+
 template <typename R, bool PM, int NMU>
-__device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane) {
+__device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane, double* tile) {
+  constexpr int KF = StageDepths<PM>::value;
+  double* tJ = tile;
+  double* tX = tile + KF * kWave;
+  double* tE = tile + 2 * KF * kWave;
+  const int f0 = chunk * kWave;
   const int nz = C.nz, nnu = C.nnu;
   const int f = chunk * kWave + lane;
   const bool fin = f < nnu;
@@ -364,12 +402,16 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
       I[m] = Bb;
       jp = fmar(wm2d[m], (double)Bb, jp);
     }
-    if (fin) {
-      const size_t fk = (size_t)f * nz + (nz - 1);
-      stg(C.JT + fk, ldg(jm + kf) + jp);
-      if (PM) {  // bottom: ingoing-ray derivatives only
-        stg(C.DchiT + fk, (double)ldg(dxs + kf));
-        stg(C.DetaT + fk, (double)ldg(des + kf));
+    stage_put<KF>(tJ, nz - 1, lane, ldg(jm + kf) + jp);
+    if (PM) {  // bottom: ingoing-ray derivatives only
+      stage_put<KF>(tX, nz - 1, lane, (double)ldg(dxs + kf));
+      stage_put<KF>(tE, nz - 1, lane, (double)ldg(des + kf));
+    }
+    if ((nz - 1) % KF == 0) {
+      stage_flush<KF>(tJ, C.JT, nz - 1, nz, f0, nnu, lane);
+      if (PM) {
+        stage_flush<KF>(tX, C.DchiT, nz - 1, nz, f0, nnu, lane);
+        stage_flush<KF>(tE, C.DetaT, nz - 1, nz, f0, nnu, lane);
       }
     }
   }
@@ -416,13 +458,17 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
         sc += (wm2[m] * i2mu[m]) * (e * (S_n - Iup) - (S_n - S) * bx);
       }
     }
-    if (fin) {
-      const size_t fk = (size_t)f * nz + k;
-      stg(C.JT + fk, jm_c + jp);
+    stage_put<KF>(tJ, k, lane, jm_c + jp);
+    if (PM) {
+      const R rc = PL<R>::div((R)1, chi);
+      stage_put<KF>(tX, k, lane, (double)dX_c + (double)(-(S * rc) * sa + dz * sc));
+      stage_put<KF>(tE, k, lane, (double)dE_c + (double)(sa * rc));
+    }
+    if (k % KF == 0) {
+      stage_flush<KF>(tJ, C.JT, k, nz, f0, nnu, lane);
       if (PM) {
-        const R rc = PL<R>::div((R)1, chi);
-        stg(C.DchiT + fk, (double)dX_c + (double)(-(S * rc) * sa + dz * sc));
-        stg(C.DetaT + fk, (double)dE_c + (double)(sa * rc));
+        stage_flush<KF>(tX, C.DchiT, k, nz, f0, nnu, lane);
+        stage_flush<KF>(tE, C.DetaT, k, nz, f0, nnu, lane);
       }
     }
     chi_n = chi;
@@ -450,7 +496,10 @@ __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
   const int mode = uni(C.st->mode);
   if (mode != (PM ? kModeNewton : kModeF)) return;
   if (uni(C.st->cur_prec) != (sizeof(R) == sizeof(float) ? NLTE_FP32_FORM : NLTE_FP64)) return;
-  formal_tile<R, PM, NMU>(C, chunk, lane);
+  constexpr int KF = StageDepths<PM>::value;
+  constexpr int NT = PM ? 3 : 1;  // staged outputs: J (and the two derivatives)
+  __shared__ double stage[4][NT * KF * kWave];
+  formal_tile<R, PM, NMU>(C, chunk, lane, stage[wave]);
 }
 
 template <typename R, bool PM>
