@@ -291,6 +291,17 @@ __global__ void k_setup_transpose(ColDev C, int nline_tab_total) {
   }
 }
 
+// FP32 copies of the tables the FP32-form opacity kernel reads.
+__global__ void k_setup_f32(ColDev C, size_t nv) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t kf = (size_t)C.nz * C.nnu;
+  if (i < nv) ((float*)C.Vf)[i] = (float)C.V[i];
+  if (i < kf) {
+    ((float*)C.Bnuf)[i] = (float)C.Bnu[i];
+    if (C.nbf) ((float*)C.Ebff)[i] = (float)C.Ebf[i];
+  }
+}
+
 // J [nnu][nz] -> [nz][nnu]
 __global__ void k_transpose_J(const double* __restrict__ JT, double* __restrict__ out, int nz, int nnu) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -425,6 +436,13 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.ch_line = Lo.take<int>(nentries);
   C.ch_eptr = Lo.take<int>(C.nchunk + 1);
   C.ch_edge = Lo.take<int>(nentries_e);
+  if (C.prec == NLTE_FP32_FORM) {
+    C.Vf = Lo.take<float>((size_t)nline_tab * nz + (nwin_total - nline_tab));
+    C.Bnuf = Lo.take<float>(kf);
+    C.Ebff = C.nbf ? Lo.take<float>(kf) : nullptr;
+  } else {
+    C.Vf = C.Bnuf = C.Ebff = nullptr;
+  }
   C.coef = Lo.take<double>((size_t)nz * ncoef(ntr));
   C.pairs = Lo.take<int4>(std::max(C.npair, 1));
   C.pg_ptr = Lo.take<int>(L * L + 1);
@@ -703,6 +721,11 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   {
     const size_t n = std::max((size_t)nz * nnu, (size_t)nline_tab * nz);
     k_setup_transpose<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C, nline_tab * nz);
+  }
+  if (prec == NLTE_FP32_FORM) {
+    const size_t nv = (size_t)nline_tab * nz + (wbase[ntr] - nline_tab);
+    const size_t n = std::max(nv, (size_t)nz * nnu);
+    k_setup_f32<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C, nv);
   }
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMalloc(&col->d, sizeof(ColDev));

@@ -121,6 +121,9 @@ struct ColDev {
   const double *Rsp;               // [nz][ntr] n-independent part of R_ul
   const double *C_lu, *C_ul;       // [nz][ntr]
   const double *nstar;             // [nz][L]
+  // FP32 copies of V, Bnu and Ebf read by the FP32-form opacity kernel (NULL
+  // for FP64 columns); n-independent, so their rounding adds no noise to F
+  const float *Vf, *Bnuf, *Ebff;
   // chunk -> overlapping line windows and edge windows; overlapping transition pairs
   const int *ch_lptr, *ch_line;
   const int *ch_eptr, *ch_edge;
@@ -189,6 +192,8 @@ struct BatchWork {
   int ngroup = 0;
   int maxnz = 0;                  // deepest column of the batch
   int fallback = 0;               // FP32-form columns may run FP64 evaluations
+  const int* act = nullptr;       // columns the lists cover (NULL: all ncol), device
+  int nact = 0;
   const int4* rate_work = nullptr;  // (col, transition, first depth, -)
   const int2* pb_work = nullptr;  // (col, first depth-entry index)
   int ncol = 0, ntiles = 0, nrate = 0, npb = 0;
@@ -207,14 +212,15 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev = 
 nlte_status check_solve_opts(const nlte_solve_opts& o);
 hipError_t solver_init(const ColDev* cols, int ncol, const double* const* n0,
                        const nlte_solve_opts& o, hipStream_t s);
-hipError_t solver_step(const ColDev* cols, int ncol, int* done, hipStream_t s);
+hipError_t solver_step(const ColDev* cols, const int* act, int n, int* done, hipStream_t s);
 hipError_t solver_gather(const ColDev* cols, int ncol, ColState* out, hipStream_t s);
 bool state_done(const ColState& st);
 void state_stats(const ColState& st, nlte_solve_stats* out);
 
 void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
                       std::vector<TileGroup>& groups, std::vector<int4>& rate,
-                      std::vector<int2>& pblock, int& maxL);
+                      std::vector<int2>& pblock, int& maxL, const int* sel = nullptr,
+                      int nsel = 0);
 
 }  // namespace nlte
 

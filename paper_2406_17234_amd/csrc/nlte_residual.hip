@@ -120,8 +120,9 @@ __device__ __forceinline__ void ray_step(R x, R S, R Sup, R& I, R& a_o, R& e_o, 
 // so that for every (k, nu), with E = exp(-h nu / kT),
 //   chi = chi_c + chi_sca + sum_lines V c0 + sum_edges alpha (c0 - E c1)
 //   eta = chi_c B + chi_sca J' + (2 h nu^3/c^2) (sum_lines V c1 + E sum_edges alpha c1).
-__global__ __launch_bounds__(256) void k_coef(const ColDev* __restrict__ cols) {
-  const ColDev& C = cols[blockIdx.x];
+__global__ __launch_bounds__(256) void k_coef(const ColDev* __restrict__ cols,
+                                              const int* __restrict__ act) {
+  const ColDev& C = cols[act ? act[blockIdx.x] : blockIdx.x];
   if (uni(C.st->mode) == kModeIdle) return;
   const int nz = C.nz, ntr = C.ntr, nline = C.nline, L = C.L;
   const int per = ntr + 2;
@@ -149,13 +150,19 @@ __global__ __launch_bounds__(256) void k_coef(const ColDev* __restrict__ cols) {
   }
 }
 
-// Angle constants in the precision of the depth recursion.
+// Tables and angle constants in the precision of the depth recursion.
 template <typename R> struct FTab;
 template <> struct FTab<double> {
+  static __device__ __forceinline__ const double* V(const ColDev& C) { return C.V; }
+  static __device__ __forceinline__ const double* B(const ColDev& C) { return C.Bnu; }
+  static __device__ __forceinline__ const double* E(const ColDev& C) { return C.Ebf; }
   static __device__ __forceinline__ double wm2(const ColDev& C, int m) { return C.wm2[m]; }
   static __device__ __forceinline__ double i2mu(const ColDev& C, int m) { return C.inv2mu[m]; }
 };
 template <> struct FTab<float> {
+  static __device__ __forceinline__ const float* V(const ColDev& C) { return C.Vf; }
+  static __device__ __forceinline__ const float* B(const ColDev& C) { return C.Bnuf; }
+  static __device__ __forceinline__ const float* E(const ColDev& C) { return C.Ebff; }
   static __device__ __forceinline__ float wm2(const ColDev& C, int m) { return C.wm2f[m]; }
   static __device__ __forceinline__ float i2mu(const ColDev& C, int m) { return C.inv2muf[m]; }
 };
@@ -164,8 +171,9 @@ template <> struct FTab<float> {
 // one wave, one lane per frequency, the depths unrolled in registers; the
 // windows overlapping the chunk are visited one after the other, so each
 // transition's coefficients for all the wave's depths come in one scalar load.
-// Everything here is FP64 in both forms and only chi and S leave rounded to
-// R: near population inversion a line can cancel most of the background
+// The sums are FP64 in both forms (the FP32 form reads FP32 copies of the
+// n-independent tables) and only chi and S leave rounded to R: near
+// population inversion a line can cancel most of the background
 // opacity, and the FP32 form's preconditioner is nearly singular in
 // scattering-dominated lines, so rounding before the cancellation shows up as
 // noise in the finite-difference product (on MI355X an FP64 FMA issues at the
@@ -191,7 +199,7 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
   const int f = chunk * kWave + lane;
   const bool fin = f < nnu;
   const int fc = fin ? f : nnu - 1;
-  const double* __restrict__ Vt = C.V;
+  const R* __restrict__ Vt = FTab<R>::V(C);
   const double* __restrict__ coef = (const double*)C.coef;
   const int ntr = uni(C.ntr);
 
@@ -209,9 +217,9 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
     const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
     const int q = fc - wlo;
     const bool in = q >= 0 && q < wl;
-    const double* vrow = Vt + uni(T.voff) + (in ? q : 0);
+    const R* vrow = Vt + uni(T.voff) + (in ? q : 0);
     const double* ct = coef + ((size_t)t * nz + k0) * 2;
-    double v[KG];
+    R v[KG];
 #pragma unroll
     for (int i = 0; i < KG; ++i) {
       const int k = min(k0 + i, nz - 1);
@@ -220,7 +228,7 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
 #pragma unroll
     for (int i = 0; i < KG; ++i) {
       const int k = min(k0 + i, nz - 1) - k0;
-      const double vi = in ? v[i] : 0.0;
+      const double vi = in ? (double)v[i] : 0.0;
       chi[i] += vi * ldc(ct + 2 * k);
       et[i] += vi * ldc(ct + 2 * k + 1);
     }
@@ -237,7 +245,7 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
     const int t = uni(C.ch_edge[j]);
     const TrDev& T = C.tr[t];
     const int wlo = uni(T.wlo), whi = uni(T.whi);
-    const double al = (fc >= wlo && fc < whi) ? ldg(Vt + uni(T.voff) + (fc - wlo)) : 0.0;
+    const double al = (fc >= wlo && fc < whi) ? (double)ldg(Vt + uni(T.voff) + (fc - wlo)) : 0.0;
     const double* ct = coef + ((size_t)t * nz + k0) * 2;
 #pragma unroll
     for (int i = 0; i < KG; ++i) {
@@ -256,8 +264,8 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
   for (int i = 0; i < KG; ++i) {
     const int k = min(k0 + i, nz - 1);
     const size_t kf = (size_t)k * nnu + fc;
-    const double B = ldg(C.Bnu + kf);
-    const double E = bf ? ldg(C.Ebf + kf) : 0.0;
+    const double B = (double)ldg(FTab<R>::B(C) + kf);
+    const double E = bf ? (double)ldg(FTab<R>::E(C) + kf) : 0.0;
     const double EA2 = E * A2[i];
     const double X = ldc(cb + 2 * (k - k0)) + chi[i] + (A1[i] - EA2);
     double eta = ldc(cb + 2 * (k - k0) + 1) * B + gam * (et[i] + EA2);
@@ -636,10 +644,11 @@ __global__ __launch_bounds__(64) void k_depthwork(const ColDev* __restrict__ col
 // ---------------------------------------------------------------------------
 constexpr int kAsmThreads = 128;
 
-__global__ __launch_bounds__(kAsmThreads) void k_assemble(const ColDev* __restrict__ cols) {
+__global__ __launch_bounds__(kAsmThreads) void k_assemble(const ColDev* __restrict__ cols,
+                                                          const int* __restrict__ act) {
   __shared__ double sF[kAsmThreads][kMaxLev + 1];
   __shared__ double sG[kAsmThreads][kMaxLev + 1];
-  const ColDev& C = cols[blockIdx.x];
+  const ColDev& C = cols[act ? act[blockIdx.x] : blockIdx.x];
   const int mode = uni(C.st->mode);
   if (mode == kModeIdle) return;
   const int nz = C.nz, L = C.L, ntr = C.ntr, nline = C.nline;
@@ -761,7 +770,8 @@ __global__ __launch_bounds__(256) void k_pblock(const ColDev* __restrict__ cols,
 // ---------------------------------------------------------------------------
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   if (ev) hipEventRecord(ev[0], s);
-  k_coef<<<bw.ncol, 256, 0, s>>>(bw.cols);
+  const int nblk = bw.act ? bw.nact : bw.ncol;
+  k_coef<<<nblk, 256, 0, s>>>(bw.cols, bw.act);
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
     const dim3 grid((G.count + 3) / 4, (bw.maxnz + kOpacDepths - 1) / kOpacDepths);
@@ -785,7 +795,7 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   if (ev) hipEventRecord(ev[1], s);
   if (bw.nrate > 0) k_depthwork<<<bw.nrate, 64, 0, s>>>(bw.cols, bw.rate_work, bw.nrate);
   if (ev) hipEventRecord(ev[2], s);
-  k_assemble<<<bw.ncol, kAsmThreads, 0, s>>>(bw.cols);
+  k_assemble<<<nblk, kAsmThreads, 0, s>>>(bw.cols, bw.act);
   if (bw.any_newton && bw.npb > 0) k_pblock<<<bw.npb, 256, 0, s>>>(bw.cols, bw.pb_work, bw.npb);
   if (ev) hipEventRecord(ev[3], s);
   return hipGetLastError();
@@ -795,22 +805,35 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
 // preconditioner items for every column.
 void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
                       std::vector<TileGroup>& groups, std::vector<int4>& rate,
-                      std::vector<int2>& pblock, int& maxL) {
+                      std::vector<int2>& pblock, int& maxL, const int* sel, int nsel) {
+  // sel: the columns to list (indices into hc), or NULL for all of them
+  std::vector<int> all;
+  if (!sel) {
+    all.resize(ncol);
+    for (int c = 0; c < ncol; ++c) all[c] = c;
+    sel = all.data();
+    nsel = ncol;
+  }
   // formal-solution tiles grouped by (precision, angle count)
   for (int prec = 0; prec < 2; ++prec)
     for (int nmu = 1; nmu <= kMaxMu; ++nmu) {
       TileGroup G{prec, nmu, (int)tiles.size(), 0};
-      for (int c = 0; c < ncol; ++c)
+      for (int q = 0; q < nsel; ++q) {
+        const int c = sel[q];
         if (hc[c].prec == prec && hc[c].nmu == nmu)
           for (int ch = 0; ch < hc[c].nchunk; ++ch) tiles.push_back(Tile{c, ch});
+      }
       G.count = (int)tiles.size() - G.first;
       if (G.count) groups.push_back(G);
     }
   // rate items (kind 0) and preconditioner pair items (kind 1) share one list
   maxL = 0;
-  for (int c = 0; c < ncol; ++c)
+  for (int q = 0; q < nsel; ++q) {
+    const int c = sel[q];
     for (int b = 0; b < hc[c].nz * hc[c].L * hc[c].L; b += 256) pblock.push_back(make_int2(c, b));
-  for (int c = 0; c < ncol; ++c) {
+  }
+  for (int q = 0; q < nsel; ++q) {
+    const int c = sel[q];
     const ColDev& C = hc[c];
     maxL = std::max(maxL, C.L);
     for (int t = 0; t < C.ntr; ++t)

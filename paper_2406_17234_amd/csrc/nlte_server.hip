@@ -214,7 +214,7 @@ void nlte_server::run() {
     const double tb = now_ms(t0);
     for (int r = 0; r < kSteps && e == hipSuccess; ++r) {
       e = launch_residual(bw, stream);
-      if (e == hipSuccess) e = solver_step(bw.cols, n, d_done.p, stream);
+      if (e == hipSuccess) e = solver_step(bw.cols, nullptr, n, d_done.p, stream);
     }
     if (e == hipSuccess) e = solver_gather(bw.cols, n, d_states.p, stream);
     if (e == hipSuccess)

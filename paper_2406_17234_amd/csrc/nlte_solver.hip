@@ -501,10 +501,11 @@ __device__ void linesearch(const ColDev& C, double* red, int* done_count) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_solver_step(const ColDev* __restrict__ cols,
+                                                          const int* __restrict__ act,
                                                           int* done_count) {
   __shared__ double red[(kThreads / 64) * (kMaxM + 1)];
   __shared__ int s_phase;
-  const ColDev& C = cols[blockIdx.x];
+  const ColDev& C = cols[act ? act[blockIdx.x] : blockIdx.x];
   if (threadIdx.x == 0) {
     s_phase = C.st->phase;
     if (s_phase != PH_DONE && s_phase != PH_IDLE) {
@@ -668,8 +669,8 @@ hipError_t solver_init(const ColDev* cols, int ncol, const double* const* n0, co
   return hipGetLastError();
 }
 
-hipError_t solver_step(const ColDev* cols, int ncol, int* done, hipStream_t s) {
-  k_solver_step<<<ncol, kThreads, 0, s>>>(cols, done);
+hipError_t solver_step(const ColDev* cols, const int* act, int n, int* done, hipStream_t s) {
+  k_solver_step<<<n, kThreads, 0, s>>>(cols, act, done);
   return hipGetLastError();
 }
 
@@ -703,6 +704,8 @@ struct Batch {
   int2* prec = nullptr;
   double** n0 = nullptr;
   double** nout = nullptr;
+  int* act = nullptr;
+  ColState* states = nullptr;
   int* done = nullptr;
   int* done_host = nullptr;     // pinned
   int ncol = 0, ntiles = 0, maxL = 0, any64 = 0, any32 = 0;
@@ -713,6 +716,8 @@ struct Batch {
     if (prec) hipFree(prec);
     if (n0) hipFree(n0);
     if (nout) hipFree(nout);
+    if (act) hipFree(act);
+    if (states) hipFree(states);
     if (done) hipFree(done);
     if (done_host) hipHostFree(done_host);
   }
@@ -804,12 +809,16 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   }
   long step = 0;
   *b.done_host = 0;
+  int nlisted = ncol;
+  std::vector<ColState> hst(ncol);
+  HIP_TRY(hipMalloc(&b.act, ncol * sizeof(int)));
+  HIP_TRY(hipMalloc(&b.states, ncol * sizeof(ColState)));
   nlte_status loop_st = NLTE_OK;
   while (step < max_steps) {
     for (int r = 0; r < check_every; ++r, ++step) {
       hipEvent_t* e = prof ? &ev[5 * r] : nullptr;
       hipError_t he = launch_residual(bw, s, e);
-      k_solver_step<<<ncol, kThreads, 0, s>>>(b.cols, b.done);
+      k_solver_step<<<bw.act ? bw.nact : ncol, kThreads, 0, s>>>(b.cols, bw.act, b.done);
       if (prof) hipEventRecord(e[4], s);
       if (he == hipSuccess) he = hipGetLastError();
       if (he != hipSuccess) {
@@ -833,6 +842,41 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
       }
     }
     if (*b.done_host >= ncol) break;
+    // Once a quarter of the listed columns has finished, list only the
+    // columns still running, so that the launches of the tail of a batch
+    // cover live work only (finished columns would just return).
+    const int remaining = ncol - *b.done_host;
+    if (remaining * 4 <= nlisted * 3) {
+      HIP_TRY(solver_gather(b.cols, ncol, b.states, s));
+      HIP_TRY(hipMemcpyAsync(hst.data(), b.states, ncol * sizeof(ColState), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      std::vector<int> live;
+      for (int c = 0; c < ncol; ++c)
+        if (!state_done(hst[c])) live.push_back(c);
+      if (live.empty()) break;
+      tiles.clear();
+      groups.clear();
+      rate_w.clear();
+      prec_w.clear();
+      int maxL_l = 0;
+      build_work_lists(hc.data(), ncol, tiles, groups, rate_w, prec_w, maxL_l, live.data(),
+                       (int)live.size());
+      HIP_TRY(hipMemcpyAsync(b.tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(b.rate, rate_w.data(), rate_w.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(b.prec, prec_w.data(), prec_w.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(b.act, live.data(), live.size() * sizeof(int), hipMemcpyHostToDevice, s));
+      bw.ntiles = (int)tiles.size();
+      bw.nrate = (int)rate_w.size();
+      bw.npb = (int)prec_w.size();
+      bw.ngroup = (int)groups.size();
+      for (int g = 0; g < bw.ngroup; ++g) bw.groups[g] = groups[g];
+      bw.maxnz = 0;
+      for (int c : live) bw.maxnz = std::max(bw.maxnz, hc[c].nz);
+      bw.act = b.act;
+      bw.nact = (int)live.size();
+      nlisted = (int)live.size();
+      HIP_TRY(hipStreamSynchronize(s));  // host vectors are reused by the next rebuild
+    }
   }
   for (auto& e : ev) hipEventDestroy(e);
   if (loop_st != NLTE_OK) return loop_st;
