@@ -179,6 +179,37 @@ def single_fp64(ctx, nlte, problems, rtol):
             "ms_per_column": dt / len(cols) * 1e3, "ftol": 1e-8}
 
 
+def f_only(ctx, nlte, problems, prec, runs=100, tune=True):
+    """F-only loop: a residual plan over the columns (graph-captured, launch
+    shape tuned), evaluated at LTE populations `runs` times after warm-up.
+    Returns formal-solution depth-points per second over whole F evaluations
+    (opacity, formal solution, rates and rate equations included)."""
+    import torch
+    cols = [nlte.Column(ctx, p, precision=prec) for p in problems]
+    ns = [c.lte() for c in cols]
+    Fs = [torch.empty_like(n) for n in ns]
+    plan = nlte.Plan(ctx, cols, ns, Fs, graph=True, tune=tune)
+    info = plan.info()
+    for _ in range(3):
+        plan.run()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(runs):
+        plan.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / runs
+    dp = info["depth_points"]
+    plan.close()
+    for c in cols:
+        c.close()
+    rate = dp / (ms * 1e-3)
+    return {"columns": len(problems), "runs": runs, "ms_per_F": ms, "depth_points_per_F": dp,
+            "depth_points_per_s": rate, "alu_frac": rate * OPS_PER_DP / PEAK_VALU_OPS,
+            "opac_depths": info["opac_depths"], "formal_wpb": info["formal_wpb"]}
+
+
 def copy_calibration(nbytes=256 << 20, reps=3):
     """A plain elementwise copy (y = 1.0 * x, fp32) of known size: it reads and
     writes nbytes each, so HBM byte counters read for it give their scale."""
@@ -209,6 +240,9 @@ def main():
                          "continue in FP64 (0: never)")
     ap.add_argument("--single-fp64", type=int, default=16,
                     help="columns of the workload also solved one at a time in FP64 (0: skip)")
+    ap.add_argument("--f-only", type=int, default=1,
+                    help="also time F-only loops (graph-replayed residual plans) of the workload "
+                         "in FP32 form and FP64 and of the 11-level stress column")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="arrival window of the served-stream phase (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -320,10 +354,22 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if args.f_only:
+        for c in cols:
+            c.close()
+        cols = []
+        fo = {}
+        for name, probs, prec in [("batch6_fp32", problems, nlte.FP32_FORM),
+                                  ("batch6_fp64", problems, nlte.FP64),
+                                  ("chromo11_fp32", [S.chromo11()], nlte.FP32_FORM),
+                                  ("chromo11_fp64", [S.chromo11()], nlte.FP64)]:
+            fo[name] = f_only(ctx, nlte, probs, prec)
+            print(f"[bench] F-only {name}: {fo[name]['depth_points_per_s']:.3e} dp/s", file=sys.stderr, flush=True)
+        out["f_only"] = fo
     if args.single_fp64 > 0:
         out["single_column_fp64"] = single_fp64(ctx, nlte, problems[:args.single_fp64], args.rtol)
     if args.serve_seconds > 0:
-        for c in cols:
+        for c in cols or []:
             c.close()
         cols = None
         out["served"] = serve_stream(ctx, nlte, args.serve_seconds, args.serve_rate,

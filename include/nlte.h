@@ -225,6 +225,43 @@ nlte_status nlte_solve_batch(nlte_ctx *ctx, nlte_column *const *cols, int32_t nc
                              hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Residual plans: F(n) of a fixed set of columns in shared launches.
+ *
+ * A plan binds columns to caller-owned device buffers n_dev[c] ([nz][nlev]
+ * populations, read) and F_dev[c] ([nz][nlev], written).  Each run copies
+ * every n_dev[c] into its column, evaluates Algorithm 1 for all of them
+ * (conservation rows from each n, J-dagger of the column, no
+ * preconditioner) in one set of launches, and writes the residuals out.
+ * The buffers and columns must stay valid and must not be used by other
+ * calls while runs are pending.
+ *   NLTE_PLAN_GRAPH: the launch sequence is captured once into a HIP graph
+ *                    and every run replays it (one host call per run).
+ *   NLTE_PLAN_TUNE:  creation times each candidate launch shape (depths per
+ *                    opacity wave 4/8/16, waves per formal-solution block
+ *                    1/2/4) over a few runs of this batch and keeps the
+ *                    fastest; otherwise 8 and 4.
+ * ------------------------------------------------------------------------ */
+typedef struct nlte_plan nlte_plan;
+enum { NLTE_PLAN_GRAPH = 1, NLTE_PLAN_TUNE = 2 };
+
+typedef struct {
+  int32_t ncol;
+  int32_t opac_depths;   /* chosen launch shape                               */
+  int32_t formal_wpb;
+  int32_t graph;         /* 1 if runs replay a captured graph                 */
+  int64_t depth_points;  /* formal-solution depth-points per run              */
+  double tune_ms[9];     /* mean run time of each candidate (opacity depths 4,
+                          * 8, 16 x waves 1, 2, 4), 0 if not tuned            */
+} nlte_plan_info;
+
+nlte_status nlte_plan_create(nlte_ctx *ctx, nlte_column *const *cols, int32_t ncol,
+                             const double *const *n_dev, double *const *F_dev, int32_t flags,
+                             hipStream_t stream, nlte_plan **out);
+nlte_status nlte_plan_run(nlte_plan *plan, hipStream_t stream);
+nlte_status nlte_plan_info_get(const nlte_plan *plan, nlte_plan_info *out);
+void nlte_plan_destroy(nlte_plan *plan);
+
+/* ------------------------------------------------------------------------
  * Serving: continuous batching of column solves.
  *
  * A server owns one host thread and one non-blocking HIP stream on the

@@ -167,7 +167,7 @@ template <> struct FTab<float> {
   static __device__ __forceinline__ float i2mu(const ColDev& C, int m) { return C.inv2muf[m]; }
 };
 
-// chi and S for one 64-frequency chunk and kOpacDepths consecutive depths:
+// chi and S for one 64-frequency chunk and KG consecutive depths:
 // one wave, one lane per frequency, the depths unrolled in registers; the
 // windows overlapping the chunk are visited one after the other, so each
 // transition's coefficients for all the wave's depths come in one scalar load.
@@ -178,12 +178,10 @@ template <> struct FTab<float> {
 // scattering-dominated lines, so rounding before the cancellation shows up as
 // noise in the finite-difference product (on MI355X an FP64 FMA issues at the
 // rate of a non-packed FP32 one, so this costs no extra issue slots).
-constexpr int kOpacDepths = 8;
-
-template <typename R>
+// KG (depths per wave) is a launch shape the plan tuner chooses among 4, 8, 16.
+template <typename R, int KG>
 __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols,
                                                  const Tile* __restrict__ tiles, int ntiles) {
-  constexpr int KG = kOpacDepths;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int tid = blockIdx.x * (blockDim.x >> 6) + wave;
@@ -506,16 +504,18 @@ __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
   if (uni(C.st->cur_prec) != (sizeof(R) == sizeof(float) ? NLTE_FP32_FORM : NLTE_FP64)) return;
   constexpr int KF = StageDepths<PM>::value;
   constexpr int NT = PM ? 3 : 1;  // staged outputs: J (and the two derivatives)
-  __shared__ double stage[4][NT * KF * kWave];
-  formal_tile<R, PM, NMU>(C, chunk, lane, stage[wave]);
+  extern __shared__ double stage[];  // [waves per block][NT * KF * 64]
+  formal_tile<R, PM, NMU>(C, chunk, lane, stage + wave * (NT * KF * kWave));
 }
 
 template <typename R, bool PM>
-static void launch_formal_mu(int nmu, int blocks, hipStream_t s, const ColDev* cols,
+static void launch_formal_mu(int nmu, int wpb, hipStream_t s, const ColDev* cols,
                              const Tile* tiles, int ntiles) {
+  const int blocks = (ntiles + wpb - 1) / wpb;
+  const size_t lds = (size_t)wpb * (PM ? 3 : 1) * StageDepths<PM>::value * kWave * sizeof(double);
   switch (nmu) {
 #define NLTE_FORMAL_CASE(M) \
-  case M: k_formal<R, PM, M><<<blocks, 256, 0, s>>>(cols, tiles, ntiles); break;
+  case M: k_formal<R, PM, M><<<blocks, 64 * wpb, lds, s>>>(cols, tiles, ntiles); break;
     NLTE_FORMAL_CASE(1) NLTE_FORMAL_CASE(2) NLTE_FORMAL_CASE(3) NLTE_FORMAL_CASE(4)
     NLTE_FORMAL_CASE(5) NLTE_FORMAL_CASE(6) NLTE_FORMAL_CASE(7) NLTE_FORMAL_CASE(8)
 #undef NLTE_FORMAL_CASE
@@ -768,20 +768,31 @@ __global__ __launch_bounds__(256) void k_pblock(const ColDev* __restrict__ cols,
 // ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
+template <typename R>
+static void launch_opacity(int kg, int ntiles, int maxnz, hipStream_t s, const ColDev* cols,
+                           const Tile* tiles) {
+  const int bx = (ntiles + 3) / 4;
+  switch (kg) {
+    case 4: k_opacity<R, 4><<<dim3(bx, (maxnz + 3) / 4), 256, 0, s>>>(cols, tiles, ntiles); break;
+    case 16: k_opacity<R, 16><<<dim3(bx, (maxnz + 15) / 16), 256, 0, s>>>(cols, tiles, ntiles); break;
+    default: k_opacity<R, 8><<<dim3(bx, (maxnz + 7) / 8), 256, 0, s>>>(cols, tiles, ntiles); break;
+  }
+}
+
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   if (ev) hipEventRecord(ev[0], s);
   const int nblk = bw.act ? bw.nact : bw.ncol;
   k_coef<<<nblk, 256, 0, s>>>(bw.cols, bw.act);
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
-    const dim3 grid((G.count + 3) / 4, (bw.maxnz + kOpacDepths - 1) / kOpacDepths);
     const Tile* tl = bw.tiles + G.first;
-    if (G.prec == NLTE_FP32_FORM) k_opacity<float><<<grid, 256, 0, s>>>(bw.cols, tl, G.count);
-    if (G.prec == NLTE_FP64 || bw.fallback) k_opacity<double><<<grid, 256, 0, s>>>(bw.cols, tl, G.count);
+    if (G.prec == NLTE_FP32_FORM) launch_opacity<float>(bw.opac_depths, G.count, bw.maxnz, s, bw.cols, tl);
+    if (G.prec == NLTE_FP64 || bw.fallback)
+      launch_opacity<double>(bw.opac_depths, G.count, bw.maxnz, s, bw.cols, tl);
   }
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
-    const int nb = (G.count + 3) / 4;
+    const int nb = bw.formal_wpb;
     const Tile* tl = bw.tiles + G.first;
     if (G.prec == NLTE_FP32_FORM) {
       launch_formal_mu<float, false>(G.nmu, nb, s, bw.cols, tl, G.count);

@@ -75,6 +75,19 @@ class Profile(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class PlanInfo(C.Structure):
+    _fields_ = [("ncol", C.c_int32), ("opac_depths", C.c_int32), ("formal_wpb", C.c_int32),
+                ("graph", C.c_int32), ("depth_points", C.c_int64), ("tune_ms", C.c_double * 9)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "tune_ms"}
+        d["tune_ms"] = list(self.tune_ms)
+        return d
+
+
+NLTE_PLAN_GRAPH, NLTE_PLAN_TUNE = 1, 2
+
+
 class ServerResult(C.Structure):
     _fields_ = [("stats", SolveStats), ("t_submit_ms", C.c_double), ("t_admit_ms", C.c_double),
                 ("t_done_ms", C.c_double)]
@@ -130,6 +143,12 @@ def lib():
         L.nlte_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
         L.nlte_solve_opts_default.restype = None
         L.nlte_voigt_host.argtypes = [C.c_double, _dp, C.c_int32, _dp]
+        L.nlte_plan_create.argtypes = [vp, C.POINTER(vp), C.c_int32, C.POINTER(vp), C.POINTER(vp),
+                                       C.c_int32, vp, C.POINTER(vp)]
+        L.nlte_plan_run.argtypes = [vp, vp]
+        L.nlte_plan_info_get.argtypes = [vp, C.POINTER(PlanInfo)]
+        L.nlte_plan_destroy.argtypes = [vp]
+        L.nlte_plan_destroy.restype = None
         L.nlte_server_create.argtypes = [vp, C.c_size_t, C.c_int32, C.POINTER(SolveOpts),
                                          C.POINTER(vp)]
         L.nlte_server_submit.argtypes = [vp, vp, vp, C.POINTER(C.c_uint64)]
@@ -385,6 +404,43 @@ class Server:
             lib().nlte_server_destroy(self.h)
             self.h = None
             self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Residual plan (nlte_plan_*): F(n) of a fixed set of columns in shared
+    launches; each run reads n_list[c] and writes F_list[c] (device tensors
+    [nz][nlev] that must stay alive with the plan)."""
+
+    def __init__(self, ctx: Context, columns, n_list, F_list, graph: bool = True,
+                 tune: bool = False, stream=None):
+        nc = len(columns)
+        cols = (C.c_void_p * nc)(*[c.h for c in columns])
+        ns = (C.c_void_p * nc)(*[x.data_ptr() for x in n_list])
+        Fs = (C.c_void_p * nc)(*[x.data_ptr() for x in F_list])
+        flags = (NLTE_PLAN_GRAPH if graph else 0) | (NLTE_PLAN_TUNE if tune else 0)
+        h = C.c_void_p()
+        _check(lib().nlte_plan_create(ctx.h, cols, nc, ns, Fs, flags, _stream(stream), C.byref(h)))
+        self.h = h
+        self._keep = (list(columns), list(n_list), list(F_list))
+
+    def run(self, stream=None):
+        _check(lib().nlte_plan_run(self.h, _stream(stream)))
+
+    def info(self) -> dict:
+        i = PlanInfo()
+        _check(lib().nlte_plan_info_get(self.h, C.byref(i)))
+        return i.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nlte_plan_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:
