@@ -38,8 +38,8 @@ OPS_PER_DP = 10.0 + 0.5 * 4 + 0.5 * 4
 # this workload, each scaled by the same counter on a plain copy kernel; valid
 # only for the kernel source they were taken on (hash of its files).
 TRAFFIC = {
-    "batch6": {"source": "62ede18f0d1082d0", "bytes_per_launch": 2.268e9 + 2.703e9,
-               "read": 2.268e9, "written": 2.703e9},
+    "batch6": {"source": "12c8a5738fef51c8", "bytes_per_launch": 9.01e8,
+               "read": 8.257e11 / 1632, "written": 6.444e11 / 1632},
 }
 KERNEL_SOURCES = ["paper_2406_17234_amd/csrc/nlte_residual.hip",
                   "paper_2406_17234_amd/csrc/nlte_internal.h"]
@@ -340,9 +340,12 @@ def main():
         "fp64_fallback_fraction": float(np.mean([[s["precision"] == 0 and prec == 1 for s in st]
                                                  for st in stats_all])),
         "kernel_ms_per_step": {k: prof[k] / args.steps for k in
-                               ("formal_ms", "depth_ms", "assemble_ms", "solver_ms")},
+                               ("opacity_ms", "formal_ms", "depth_ms", "assemble_ms", "solver_ms")},
         "roofline": {
-            "kernel": "k_formal<float>" if prec == 1 else "k_formal<double>",
+            "kernel": ("k_formal<float, *, 5>" if prec == 1 else "k_formal<double, *, 5>") +
+                      " (depth recursion, F-only and Newton instantiations)",
+            "launches": prof["formal_launches"],
+            "launch_avg_ms": prof["formal_ms"] / max(1, prof["formal_launches"]),
             "bound": "alu",
             "achieved": achieved,
             "peak": peak,

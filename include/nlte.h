@@ -141,11 +141,12 @@ typedef struct {
  * (HIP events on the solve's stream around each launch). */
 typedef struct {
   int64_t steps;             /* solver steps (one residual per active column)   */
-  int64_t formal_launches;   /* formal-solution launches                        */
+  int64_t formal_launches;   /* depth-recursion (formal-solution) launches      */
   double formal_ms;          /* their summed duration                           */
   double depth_ms;           /* rate integrals + preconditioner pair sums       */
   double assemble_ms;        /* residual/preconditioner assembly                */
   double solver_ms;          /* Krylov/Newton step launches                     */
+  double opacity_ms;         /* level coefficients + opacity/source function    */
 } nlte_profile;
 
 /* Fills opts with the defaults listed above. */

@@ -202,10 +202,11 @@ struct BatchWork {
   int any64 = 0, any32 = 0, any_newton = 1;
 };
 
-// Residual launches for a batch (formal solution of every tile, rate
-// integrals and preconditioner pair sums, assembly).  ev, if not NULL, holds
-// four events: before the formal-solution launch, after it, after the
-// lane-per-depth work and after assembly.
+// Residual launches for a batch (level coefficients and opacity, formal
+// solution of every tile, rate integrals and preconditioner pair sums,
+// assembly).  ev, if not NULL, holds five events: before the coefficients,
+// before the formal-solution launches, after them, after the lane-per-depth
+// work and after assembly.
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev = nullptr);
 
 // Solver driver pieces (nlte_solver.hip) shared by the batch solve and the

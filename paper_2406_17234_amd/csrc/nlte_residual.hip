@@ -790,6 +790,7 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     if (G.prec == NLTE_FP64 || bw.fallback)
       launch_opacity<double>(bw.opac_depths, G.count, bw.maxnz, s, bw.cols, tl);
   }
+  if (ev) hipEventRecord(ev[1], s);
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
     const int nb = bw.formal_wpb;
@@ -803,12 +804,12 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
       if (bw.any_newton) launch_formal_mu<double, true>(G.nmu, nb, s, bw.cols, tl, G.count);
     }
   }
-  if (ev) hipEventRecord(ev[1], s);
-  if (bw.nrate > 0) k_depthwork<<<bw.nrate, 64, 0, s>>>(bw.cols, bw.rate_work, bw.nrate);
   if (ev) hipEventRecord(ev[2], s);
+  if (bw.nrate > 0) k_depthwork<<<bw.nrate, 64, 0, s>>>(bw.cols, bw.rate_work, bw.nrate);
+  if (ev) hipEventRecord(ev[3], s);
   k_assemble<<<nblk, kAsmThreads, 0, s>>>(bw.cols, bw.act);
   if (bw.any_newton && bw.npb > 0) k_pblock<<<bw.npb, 256, 0, s>>>(bw.cols, bw.pb_work, bw.npb);
-  if (ev) hipEventRecord(ev[3], s);
+  if (ev) hipEventRecord(ev[4], s);
   return hipGetLastError();
 }
 

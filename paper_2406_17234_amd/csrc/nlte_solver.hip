@@ -804,7 +804,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   const bool prof = ctx->prof_on != 0;
   std::vector<hipEvent_t> ev;
   if (prof) {
-    ev.resize(5 * check_every);
+    ev.resize(6 * check_every);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
   }
   long step = 0;
@@ -816,10 +816,10 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   nlte_status loop_st = NLTE_OK;
   while (step < max_steps) {
     for (int r = 0; r < check_every; ++r, ++step) {
-      hipEvent_t* e = prof ? &ev[5 * r] : nullptr;
+      hipEvent_t* e = prof ? &ev[6 * r] : nullptr;
       hipError_t he = launch_residual(bw, s, e);
       k_solver_step<<<bw.act ? bw.nact : ncol, kThreads, 0, s>>>(b.cols, bw.act, b.done);
-      if (prof) hipEventRecord(e[4], s);
+      if (prof) hipEventRecord(e[5], s);
       if (he == hipSuccess) he = hipGetLastError();
       if (he != hipSuccess) {
         loop_st = set_err(NLTE_E_DEVICE, "solver launch failed: %s", hipGetErrorString(he));
@@ -831,14 +831,15 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
     HIP_TRY(hipStreamSynchronize(s));
     if (prof) {
       for (int r = 0; r < check_every; ++r) {
-        float t[4];
-        for (int q = 0; q < 4; ++q) HIP_TRY(hipEventElapsedTime(&t[q], ev[5 * r + q], ev[5 * r + q + 1]));
+        float t[5];
+        for (int q = 0; q < 5; ++q) HIP_TRY(hipEventElapsedTime(&t[q], ev[6 * r + q], ev[6 * r + q + 1]));
         ctx->prof.steps += 1;
-        ctx->prof.formal_launches += 2 * bw.ngroup;
-        ctx->prof.formal_ms += t[0];
-        ctx->prof.depth_ms += t[1];
-        ctx->prof.assemble_ms += t[2];
-        ctx->prof.solver_ms += t[3];
+        ctx->prof.formal_launches += 2 * bw.ngroup * (bw.fallback ? 2 : 1);
+        ctx->prof.opacity_ms += t[0];
+        ctx->prof.formal_ms += t[1];
+        ctx->prof.depth_ms += t[2];
+        ctx->prof.assemble_ms += t[3];
+        ctx->prof.solver_ms += t[4];
       }
     }
     if (*b.done_host >= ncol) break;
