@@ -1,0 +1,84 @@
+"""Parity at the full sizes the benchmark runs, in its launch configuration.
+
+- the 11-level stress column (256 depths, ~4000 frequencies, 8 angles):
+  residual, J and rates against the oracle, FP64 and FP32 form;
+- the 4096-column batch through a graph-replayed, tuned residual plan (the
+  F-only loop of the benchmark): sampled columns against the oracle;
+- the batched FP32-form solve of all 4096 columns (the benchmark step):
+  sampled columns' populations against the oracle's FP64 root to 1e-4."""
+import numpy as np
+import pytest
+
+from oracle import nlte_oracle as O
+from paper_2406_17234_amd import synth as S
+from tests.helpers import maxrel, perturbed, require_gpu, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+NCOL = 4096
+SAMPLE = [0, 1234, 4095]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    require_gpu()
+    from paper_2406_17234_amd import nlte
+    return nlte.Context(0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stress_column_residual(ctx, prec):
+    from paper_2406_17234_amd import nlte
+    prob = S.chromo11()
+    print(f"[case] chromo11 residual prec={prec} dims={prob.dims}", flush=True)
+    tb = O.setup(prob)
+    n = perturbed(tb.nstar, seed=21, scale=0.2)
+    ref = O.residual(tb, n)
+    col = nlte.Column(ctx, prob, precision=prec)
+    out = col.residual(to_dev(n), want_J=True, want_R=True)
+    J, R, F = to_np(out["J"]), to_np(out["R"]), to_np(out["F"])
+    if prec == 0:
+        assert maxrel(J, ref.J, floor=1e-300) < 1e-12
+        assert maxrel(R[..., 0], ref.R_lu, floor=1e-300) < 1e-12
+        assert np.max(np.abs(F - ref.F) / ref.G) < 1e-12
+    else:
+        scale = np.abs(ref.J).max(axis=0, keepdims=True)  # per frequency
+        assert np.max(np.abs(J - ref.J) / np.maximum(np.abs(ref.J), 1e-6 * scale)) < 1e-4
+        assert maxrel(R[..., 1], ref.R_ul) < 1e-4
+        assert np.max(np.abs(F - ref.F) / ref.G) < 1e-4
+
+
+def test_batch_plan_sampled_columns(ctx):
+    import torch
+    from paper_2406_17234_amd import nlte
+    probs = [S.batch6_column(i) for i in range(NCOL)]
+    cols = [nlte.Column(ctx, p, precision=nlte.FP32_FORM) for p in probs]
+    ns = [c.lte() for c in cols]
+    for i in SAMPLE:  # the sampled columns are evaluated away from LTE
+        ns[i] = to_dev(perturbed(O.setup(probs[i]).nstar, seed=31 + i, scale=0.2))
+    Fs = [torch.empty_like(n) for n in ns]
+    plan = nlte.Plan(ctx, cols, ns, Fs, graph=True, tune=True)
+    for _ in range(3):
+        plan.run()
+    torch.cuda.synchronize()
+    for i in SAMPLE:
+        tb = O.setup(probs[i])
+        ref = O.residual(tb, to_np(ns[i]))
+        assert np.max(np.abs(to_np(Fs[i]) - ref.F) / ref.G) < 1e-4, i
+    plan.close()
+
+
+def test_batch_solve_sampled_columns(ctx):
+    from paper_2406_17234_amd import nlte
+    probs = [S.batch6_column(i) for i in range(NCOL)]
+    cols = [nlte.Column(ctx, p, precision=nlte.FP32_FORM) for p in probs]
+    opts = nlte.default_opts(ftol=1e-6, rtol=1e-3, maxiter=50, max_krylov_total=200,
+                             fp64_fallback=12)
+    outs, stats, rc = nlte.solve_batch(ctx, cols, opts)
+    assert np.mean([s["status"] == 0 for s in stats]) > 0.99
+    for i in SAMPLE:
+        assert stats[i]["status"] == 0, (i, stats[i])
+        tb = O.setup(probs[i])
+        ref = O.solve(tb, ftol=1e-10, rtol=1e-6, maxiter=50)
+        assert ref.converged
+        assert maxrel(to_np(outs[i]), ref.n) < 1e-4, i
