@@ -55,6 +55,16 @@ __device__ __forceinline__ double uni(double v) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Work item of block b of an nb-block launch when consecutive items should
+// share an XCD's L2: the blocks of a launch are dealt round-robin over the 8
+// XCDs (block b runs on XCD b % 8), so the items are numbered XCD by XCD.
+__device__ __forceinline__ int xcd_item(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int q = nb / kXcd, r = nb % kXcd;
+  const int x = b % kXcd, l = b / kXcd;
+  return x * q + (x < r ? x : r) + l;
+}
+
 // Evaluation modes of one residual call.
 enum EvalMode : int {
   kModeIdle = 0,    // column takes no part in this step

@@ -626,7 +626,9 @@ __device__ __forceinline__ void precond_item(const ColDev& C, int p, int k0) {
 // column and, for columns in Newton mode, preconditioner pair sums (kind 1).
 __global__ __launch_bounds__(64) void k_depthwork(const ColDev* __restrict__ cols,
                                                   const int4* __restrict__ work, int nwork) {
-  const int w = blockIdx.x;
+  // the items of a column are consecutive in the list: keeping them on one
+  // XCD lets its transitions share the column's J in that XCD's L2
+  const int w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= nwork) return;
   const int4 it = work[w];
   const int col = uni(it.x), idx = uni(it.y), k0 = uni(it.z), kind = uni(it.w);
