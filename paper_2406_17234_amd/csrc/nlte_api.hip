@@ -292,13 +292,17 @@ __global__ void k_setup_transpose(ColDev C, int nline_tab_total) {
 }
 
 // FP32 copies of the tables the FP32-form opacity kernel reads.
-__global__ void k_setup_f32(ColDev C, size_t nv) {
+__global__ void k_setup_f32(ColDev C, size_t nv, size_t nvt) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t kf = (size_t)C.nz * C.nnu;
   if (i < nv) ((float*)C.Vf)[i] = (float)C.V[i];
+  if (i < nvt) ((float*)C.VTf)[i] = (float)C.VT[i];
   if (i < kf) {
     ((float*)C.Bnuf)[i] = (float)C.Bnu[i];
-    if (C.nbf) ((float*)C.Ebff)[i] = (float)C.Ebf[i];
+    if (C.nbf) {
+      ((float*)C.Ebff)[i] = (float)C.Ebf[i];
+      ((float*)C.EbfTf)[i] = (float)C.EbfT[i];
+    }
   }
 }
 
@@ -440,8 +444,10 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
     C.Vf = Lo.take<float>((size_t)nline_tab * nz + (nwin_total - nline_tab));
     C.Bnuf = Lo.take<float>(kf);
     C.Ebff = C.nbf ? Lo.take<float>(kf) : nullptr;
+    C.VTf = Lo.take<float>((size_t)nline_tab * nz + 1);
+    C.EbfTf = C.nbf ? Lo.take<float>(kf) : nullptr;
   } else {
-    C.Vf = C.Bnuf = C.Ebff = nullptr;
+    C.Vf = C.Bnuf = C.Ebff = C.VTf = C.EbfTf = nullptr;
   }
   C.coef = Lo.take<double>((size_t)nz * ncoef(ntr));
   C.pairs = Lo.take<int4>(std::max(C.npair, 1));
@@ -724,8 +730,9 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   }
   if (prec == NLTE_FP32_FORM) {
     const size_t nv = (size_t)nline_tab * nz + (wbase[ntr] - nline_tab);
+    const size_t nvt = (size_t)nline_tab * nz;
     const size_t n = std::max(nv, (size_t)nz * nnu);
-    k_setup_f32<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C, nv);
+    k_setup_f32<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C, nv, nvt);
   }
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMalloc(&col->d, sizeof(ColDev));

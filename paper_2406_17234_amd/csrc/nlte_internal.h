@@ -134,6 +134,7 @@ struct ColDev {
   // FP32 copies of V, Bnu and Ebf read by the FP32-form opacity kernel (NULL
   // for FP64 columns); n-independent, so their rounding adds no noise to F
   const float *Vf, *Bnuf, *Ebff;
+  const float *VTf, *EbfTf;        // FP32 copies of VT and EbfT (rate integrals)
   // chunk -> overlapping line windows and edge windows; overlapping transition pairs
   const int *ch_lptr, *ch_line;
   const int *ch_eptr, *ch_edge;

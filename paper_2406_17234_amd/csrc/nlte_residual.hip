@@ -537,7 +537,20 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
   s = u;
 }
 
+template <typename TB>  // table precision: double, or float for FP32-form columns
+__device__ __forceinline__ void rates_sum(const ColDev& C, int t, int k0, const TB* __restrict__ VTt,
+                                          const TB* __restrict__ EbfTt);
+
 __device__ __forceinline__ void rates_item(const ColDev& C, int t, int k0) {
+  if (uni(C.prec) == NLTE_FP32_FORM)
+    rates_sum<float>(C, t, k0, C.VTf, C.EbfTf);
+  else
+    rates_sum<double>(C, t, k0, C.VT, C.EbfT);
+}
+
+template <typename TB>
+__device__ __forceinline__ void rates_sum(const ColDev& C, int t, int k0, const TB* __restrict__ VTt,
+                                          const TB* __restrict__ EbfTt) {
   if (uni(C.st->mode) == kModeIdle) return;
   const int nz = C.nz;
   const int k = k0 + threadIdx.x;
@@ -548,22 +561,22 @@ __device__ __forceinline__ void rates_item(const ColDev& C, int t, int k0) {
   const double* __restrict__ cw = C.cw + uni(T.cwoff);
   double* dst = C.RJ + ((size_t)k * C.ntr + t) * 2;
   if (t < C.nline) {
-    const double* __restrict__ V = C.VT + uni(T.voff) + k;
+    const TB* __restrict__ V = VTt + uni(T.voff) + k;
     double s = 0.0, c = 0.0;
 #pragma unroll 4
     for (int q = 0; q < wl; ++q)
-      neumaier(s, c, cw[q] * ldg(V + (size_t)q * nz) * ldg(J + (size_t)q * nz));
+      neumaier(s, c, cw[q] * (double)ldg(V + (size_t)q * nz) * ldg(J + (size_t)q * nz));
     stg(dst, s + c);
     stg(dst + 1, 0.0);
   } else {
     const double* __restrict__ A = C.V + uni(T.voff);
-    const double* __restrict__ E = C.EbfT + (size_t)wlo * nz + k;
+    const TB* __restrict__ E = EbfTt + (size_t)wlo * nz + k;
     double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
 #pragma unroll 4
     for (int q = 0; q < wl; ++q) {
       const double x = cw[q] * A[q] * ldg(J + (size_t)q * nz);
       neumaier(s1, c1, x);
-      neumaier(s2, c2, x * ldg(E + (size_t)q * nz));
+      neumaier(s2, c2, x * (double)ldg(E + (size_t)q * nz));
     }
     stg(dst, s1 + c1);
     stg(dst + 1, s2 + c2);
