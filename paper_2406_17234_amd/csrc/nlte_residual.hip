@@ -171,6 +171,7 @@ template <> struct FTab<float> {
 // one wave, one lane per frequency, the depths unrolled in registers; the
 // windows overlapping the chunk are visited one after the other, so each
 // transition's coefficients for all the wave's depths come in one scalar load.
+// Explicit FMAs keep the arithmetic identical for every depth-group size.
 // The sums are FP64 in both forms (the FP32 form reads FP32 copies of the
 // n-independent tables) and only chi and S leave rounded to R: near
 // population inversion a line can cancel most of the background
@@ -179,6 +180,11 @@ template <> struct FTab<float> {
 // noise in the finite-difference product (on MI355X an FP64 FMA issues at the
 // rate of a non-packed FP32 one, so this costs no extra issue slots).
 // KG (depths per wave) is a launch shape the plan tuner chooses among 4, 8, 16.
+template <typename R, int KG>
+__device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0, int nz, int nnu,
+                                              bool fin, int fc, const R* __restrict__ Vt,
+                                              const double* __restrict__ coef, int ntr);
+
 template <typename R, int KG>
 __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols,
                                                  const Tile* __restrict__ tiles, int ntiles) {
@@ -192,15 +198,20 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
   if (uni(C.st->mode) == kModeIdle) return;
   if (uni(C.st->cur_prec) != (sizeof(R) == sizeof(float) ? NLTE_FP32_FORM : NLTE_FP64)) return;
   const int nz = uni(C.nz), nnu = uni(C.nnu);
-  const int k0 = blockIdx.y * KG;
-  if (k0 >= nz) return;
   const int f = chunk * kWave + lane;
   const bool fin = f < nnu;
   const int fc = fin ? f : nnu - 1;
   const R* __restrict__ Vt = FTab<R>::V(C);
   const double* __restrict__ coef = (const double*)C.coef;
   const int ntr = uni(C.ntr);
+  for (int k0 = 0; k0 < nz; k0 += KG)
+    opacity_group<R, KG>(C, chunk, k0, nz, nnu, fin, fc, Vt, coef, ntr);
+}
 
+template <typename R, int KG>
+__device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0, int nz, int nnu,
+                                              bool fin, int fc, const R* __restrict__ Vt,
+                                              const double* __restrict__ coef, int ntr) {
   double chi[KG], et[KG];
 #pragma unroll
   for (int i = 0; i < KG; ++i) {
@@ -227,8 +238,8 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
     for (int i = 0; i < KG; ++i) {
       const int k = min(k0 + i, nz - 1) - k0;
       const double vi = in ? (double)v[i] : 0.0;
-      chi[i] += vi * ldc(ct + 2 * k);
-      et[i] += vi * ldc(ct + 2 * k + 1);
+      chi[i] = fmar(vi, ldc(ct + 2 * k), chi[i]);
+      et[i] = fmar(vi, ldc(ct + 2 * k + 1), et[i]);
     }
   }
   // edges: A1 = sum alpha c0, A2 = sum alpha c1
@@ -248,8 +259,8 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
 #pragma unroll
     for (int i = 0; i < KG; ++i) {
       const int k = min(k0 + i, nz - 1) - k0;
-      A1[i] += al * ldc(ct + 2 * k);
-      A2[i] += al * ldc(ct + 2 * k + 1);
+      A1[i] = fmar(al, ldc(ct + 2 * k), A1[i]);
+      A2[i] = fmar(al, ldc(ct + 2 * k + 1), A2[i]);
     }
   }
   // background, source function
@@ -265,9 +276,9 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
     const double B = (double)ldg(FTab<R>::B(C) + kf);
     const double E = bf ? (double)ldg(FTab<R>::E(C) + kf) : 0.0;
     const double EA2 = E * A2[i];
-    const double X = ldc(cb + 2 * (k - k0)) + chi[i] + (A1[i] - EA2);
-    double eta = ldc(cb + 2 * (k - k0) + 1) * B + gam * (et[i] + EA2);
-    if (sca) eta += ldc(cs + 2 * (k - k0)) * ldg(C.Jdag + kf);
+    const double X = (ldc(cb + 2 * (k - k0)) + chi[i]) + (A1[i] - EA2);
+    double eta = fmar(ldc(cb + 2 * (k - k0) + 1), B, gam * (et[i] + EA2));
+    if (sca) eta = fmar(ldc(cs + 2 * (k - k0)), ldg(C.Jdag + kf), eta);
     if (fin && k0 + i < nz) {
       stg(xs + 2 * kf, (R)X);
       stg(xs + 2 * kf + 1, (R)(eta / X));
@@ -787,10 +798,11 @@ template <typename R>
 static void launch_opacity(int kg, int ntiles, int maxnz, hipStream_t s, const ColDev* cols,
                            const Tile* tiles) {
   const int bx = (ntiles + 3) / 4;
+  (void)maxnz;
   switch (kg) {
-    case 4: k_opacity<R, 4><<<dim3(bx, (maxnz + 3) / 4), 256, 0, s>>>(cols, tiles, ntiles); break;
-    case 16: k_opacity<R, 16><<<dim3(bx, (maxnz + 15) / 16), 256, 0, s>>>(cols, tiles, ntiles); break;
-    default: k_opacity<R, 8><<<dim3(bx, (maxnz + 7) / 8), 256, 0, s>>>(cols, tiles, ntiles); break;
+    case 4: k_opacity<R, 4><<<bx, 256, 0, s>>>(cols, tiles, ntiles); break;
+    case 16: k_opacity<R, 16><<<bx, 256, 0, s>>>(cols, tiles, ntiles); break;
+    default: k_opacity<R, 8><<<bx, 256, 0, s>>>(cols, tiles, ntiles); break;
   }
 }
 
