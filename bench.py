@@ -365,7 +365,9 @@ def main():
         for name, probs, prec in [("batch6_fp32", problems, nlte.FP32_FORM),
                                   ("batch6_fp64", problems, nlte.FP64),
                                   ("chromo11_fp32", [S.chromo11()], nlte.FP32_FORM),
-                                  ("chromo11_fp64", [S.chromo11()], nlte.FP64)]:
+                                  ("chromo11_fp64", [S.chromo11()], nlte.FP64),
+                                  ("chromo11_fp32_scan", [S.chromo11()], nlte.FP32_FORM | nlte.DEPTH_SCAN),
+                                  ("chromo11_fp64_scan", [S.chromo11()], nlte.FP64 | nlte.DEPTH_SCAN)]:
             fo[name] = f_only(ctx, nlte, probs, prec)
             print(f"[bench] F-only {name}: {fo[name]['depth_points_per_s']:.3e} dp/s", file=sys.stderr, flush=True)
         out["f_only"] = fo

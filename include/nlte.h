@@ -56,6 +56,14 @@ typedef enum {
  * finite-difference product are FP64 in both forms. */
 typedef enum { NLTE_FP64 = 0, NLTE_FP32_FORM = 1 } nlte_precision;
 
+/* OR-ed into the precision argument of nlte_column_create: solve the
+ * transfer equation of this column by parallel scans over depth (one
+ * workgroup per frequency, one thread per depth; nz <= 256) instead of one
+ * sequential recursion per frequency.  Meant for large columns solved alone
+ * or in small batches, where one thread per frequency leaves the device
+ * idle.  Same equations; rounding differs from the sequential form. */
+#define NLTE_DEPTH_SCAN 0x100
+
 typedef struct nlte_ctx nlte_ctx;
 typedef struct nlte_column nlte_column;
 typedef struct nlte_server nlte_server;
@@ -163,14 +171,15 @@ void nlte_ctx_destroy(nlte_ctx *ctx);
  * balance, quadrature weights) on the device.  C_up is [nz][ntr] upward
  * collision rates (lower -> upper), s^-1.  The column owns its device
  * tables and solver state until nlte_column_destroy.  The lagged mean
- * intensity J-dagger of Sect. 2.1.1 starts as B_nu(T). */
+ * intensity J-dagger of Sect. 2.1.1 starts as B_nu(T).  precision is an
+ * nlte_precision, optionally OR-ed with NLTE_DEPTH_SCAN. */
 nlte_status nlte_column_create(nlte_ctx *ctx, const nlte_atmos_desc *atmos,
                                const nlte_atom_desc *atom, const nlte_grid_desc *grid,
-                               const double *C_up, nlte_precision precision,
+                               const double *C_up, int32_t precision,
                                hipStream_t stream, nlte_column **out);
 void nlte_column_destroy(nlte_column *col);
 
-/* dims = {nz, nlev, ntr, nline, nbf, nnu, nmu, precision} */
+/* dims = {nz, nlev, ntr, nline, nbf, nnu, nmu, precision (| NLTE_DEPTH_SCAN)} */
 nlte_status nlte_column_dims(const nlte_column *col, int32_t dims[8]);
 /* Bytes of device memory the column owns (its arena). */
 nlte_status nlte_column_bytes(const nlte_column *col, size_t *bytes);

@@ -503,10 +503,15 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
 
 extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* A,
                                           const nlte_atom_desc* M, const nlte_grid_desc* G,
-                                          const double* C_up, nlte_precision prec,
+                                          const double* C_up, int32_t prec_arg,
                                           hipStream_t stream, nlte_column** out) {
   if (!ctx || !out) return set_err(NLTE_E_INVALID, "NULL ctx/out");
+  const int prec = prec_arg & ~NLTE_DEPTH_SCAN;
+  const int scan = (prec_arg & NLTE_DEPTH_SCAN) != 0;
   if (prec != NLTE_FP64 && prec != NLTE_FP32_FORM) return set_err(NLTE_E_INVALID, "bad precision");
+  if (scan && A && A->nz > kScanThreads)
+    return set_err(NLTE_E_INVALID, "the depth-parallel formal solution takes at most %d depths",
+                   kScanThreads);
   nlte_status vs = validate(A, M, G, C_up);
   if (vs != NLTE_OK) return vs;
   HIP_TRY(hipSetDevice(ctx->device));
@@ -516,6 +521,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   ColDev C{};
   C.nz = nz; C.L = L; C.ntr = ntr; C.nline = nline; C.nbf = nbf; C.nnu = nnu; C.nmu = nmu;
   C.prec = prec; C.N = nz * L;
+  C.scan = scan;
   C.nchunk = (nnu + kWave - 1) / kWave;
   C.has_sca = 0;
   if (A->chi_sca)
@@ -782,7 +788,7 @@ extern "C" nlte_status nlte_column_dims(const nlte_column* col, int32_t dims[8])
   if (!col || !dims) return set_err(NLTE_E_INVALID, "NULL argument");
   const ColDev& C = col->h;
   dims[0] = C.nz; dims[1] = C.L; dims[2] = C.ntr; dims[3] = C.nline;
-  dims[4] = C.nbf; dims[5] = C.nnu; dims[6] = C.nmu; dims[7] = C.prec;
+  dims[4] = C.nbf; dims[5] = C.nnu; dims[6] = C.nmu; dims[7] = C.prec | (C.scan ? NLTE_DEPTH_SCAN : 0);
   return NLTE_OK;
 }
 

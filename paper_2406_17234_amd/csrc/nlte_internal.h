@@ -25,6 +25,7 @@ constexpr int kMaxMu = 8;       // angles per hemisphere held in registers
 constexpr int kMaxLev = 16;     // levels per atom
 constexpr int kMaxRestart = 64; // GMRES restart length
 constexpr int kMaxEdges = kMaxLev - 1;
+constexpr int kScanThreads = 256;  // depths of a column with the depth-parallel formal solution
 
 // Loads and stores through the global address space (the pointers live in
 // column descriptors, so the compiler cannot infer it and would emit flat
@@ -112,6 +113,7 @@ struct ColState {
 struct ColDev {
   int nz, L, ntr, nline, nbf, nnu, nmu, prec;
   int nchunk, npair, has_sca, N;   // N = nz * L; npair = overlapping transition pairs
+  int scan, pad_scan;              // 1: depth-parallel formal solution (nz <= 256)
   // angles (inline: at most kMaxMu)
   double wm2[kMaxMu];     // w_m / 2
   double inv2mu[kMaxMu];  // 1 / (2 mu_m)
@@ -193,6 +195,7 @@ inline __host__ __device__ int ncoef(int ntr) { return 2 * ntr + 4; }
 // Tiles of one (precision, angle count) group, contiguous in the tile list.
 struct TileGroup {
   int prec, nmu, first, count;
+  int scan;  // columns solved by the depth-parallel formal solution
 };
 
 // Device work lists of a batch of columns.

@@ -498,6 +498,208 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
   }
 }
 
+// ---------------------------------------------------------------------------
+// depth-parallel formal solution (columns created with NLTE_DEPTH_SCAN)
+// ---------------------------------------------------------------------------
+// One workgroup per frequency, one thread per depth.  Along a ray the
+// piecewise-linear scheme is an affine recursion over depth,
+//   downwards  I_k = e I_{k-1} + (a S_k + b S_{k-1}),
+//   upwards    I_k = e I_{k+1} + (a S_k + b S_{k+1}),
+// with the same e, a, b for a segment in both directions (they depend on
+// its optical thickness only), so each segment's coefficients are computed
+// once.  Composing affine maps is associative: each direction is a parallel
+// prefix over depth (shuffles within a wave, one combination across the
+// workgroup's waves).  All maps have e >= 0 and, for S >= 0, s >= 0, so the
+// scan adds no cancellation.
+
+// a, b, e = 1 - a - b and b/x of a segment (Appendix A.1, as in ray_step).
+template <typename R>
+__device__ __forceinline__ void pl_coefs(R x, R& a, R& b, R& e, R& bx) {
+  if (x < PL<R>::kSwitch) {
+    R pa, pb;
+    horner_ab<R, 1, PL<R>::kTerms>(x, pa, pb);
+    a = pa * x;
+    b = pb * x;
+    e = (R)1 - a - b;
+    bx = pb;
+  } else {
+    e = PL<R>::ex(x);
+    const R t1 = PL<R>::div((R)1 - e, x);
+    a = (R)1 - t1;
+    b = t1 - e;
+    bx = PL<R>::div(b, x);
+  }
+}
+
+// Inclusive scans of affine maps (e, s): I -> e I + s.  Downward: thread t
+// ends with M_t o ... o M_0; upward: with M_t o ... o M_last.
+template <typename R>
+__device__ __forceinline__ void scan_down(R& e, R& s, R* le, R* ls) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const R pe = __shfl_up(e, d), ps = __shfl_up(s, d);
+    if (lane >= d) {
+      s = fmar(e, ps, s);
+      e = e * pe;
+    }
+  }
+  if (lane == kWave - 1) {
+    le[wave] = e;
+    ls[wave] = s;
+  }
+  __syncthreads();
+  R ce = (R)1, cs = (R)0;
+  for (int w = 0; w < wave; ++w) {
+    cs = fmar(le[w], cs, ls[w]);
+    ce = le[w] * ce;
+  }
+  s = fmar(e, cs, s);
+  e = e * ce;
+  __syncthreads();
+}
+
+template <typename R>
+__device__ __forceinline__ void scan_up(R& e, R& s, R* le, R* ls) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const R pe = __shfl_down(e, d), ps = __shfl_down(s, d);
+    if (lane + d < kWave) {
+      s = fmar(e, ps, s);
+      e = e * pe;
+    }
+  }
+  if (lane == 0) {
+    le[wave] = e;
+    ls[wave] = s;
+  }
+  __syncthreads();
+  R ce = (R)1, cs = (R)0;
+  for (int w = nw - 1; w > wave; --w) {
+    cs = fmar(le[w], cs, ls[w]);
+    ce = le[w] * ce;
+  }
+  s = fmar(e, cs, s);
+  e = e * ce;
+  __syncthreads();
+}
+
+// 64 workgroups per chunk tile (one per frequency of the chunk).
+template <typename R, bool PM, int NMU>
+__global__ __launch_bounds__(kScanThreads) void k_formal_scan(const ColDev* __restrict__ cols,
+                                                              const Tile* __restrict__ tiles,
+                                                              int ntiles) {
+  const int tile = blockIdx.x >> 6, fl = blockIdx.x & 63;
+  if (tile >= ntiles) return;
+  const int col = uni(tiles[tile].col), chunk = uni(tiles[tile].chunk);
+  const ColDev& C = cols[col];
+  const int mode = uni(C.st->mode);
+  if (mode != (PM ? kModeNewton : kModeF)) return;
+  if (uni(C.st->cur_prec) != (sizeof(R) == sizeof(float) ? NLTE_FP32_FORM : NLTE_FP64)) return;
+  const int nz = uni(C.nz), nnu = uni(C.nnu);
+  const int f = chunk * kWave + fl;
+  if (f >= nnu) return;
+  const int t = threadIdx.x;
+  const bool in = t < nz;
+  const int k = in ? t : nz - 1;
+
+  __shared__ R sx[kScanThreads], ss[kScanThreads];
+  __shared__ R se[kScanThreads], sa[kScanThreads], sb[kScanThreads], sbx[kScanThreads];
+  __shared__ R sin_[kScanThreads], sout[kScanThreads];
+  __shared__ R le[kScanThreads / kWave], ls[kScanThreads / kWave];
+
+  const R* __restrict__ xs = reinterpret_cast<const R*>(C.XS);
+  const double* __restrict__ dzt = C.coef + ((size_t)(C.ntr + 1) * nz) * 2 + 1;  // stride 2
+  const size_t kf = (size_t)k * nnu + f;
+  const R chi = ldg(xs + 2 * kf), S = ldg(xs + 2 * kf + 1);
+  sx[t] = chi;
+  ss[t] = S;
+  __syncthreads();
+  const bool up_seg = in && t > 0;       // segment (t-1, t) exists
+  const bool dn_seg = in && t + 1 < nz;  // segment (t, t+1) exists
+  const R chi_p = up_seg ? sx[t - 1] : chi, S_p = up_seg ? ss[t - 1] : S;
+  const R S_n = dn_seg ? ss[t + 1] : S;
+  const R dz_p = up_seg ? (R)ldg(dzt + 2 * (t - 1)) : (R)0;
+  const R dz_n = dn_seg ? (R)ldg(dzt + 2 * t) : (R)0;
+  const R base = dz_p * (chi_p + chi);  // optical thickness of (t-1, t) times 2 mu
+  const R Bb = (R)ldg(C.Bnu + (size_t)(nz - 1) * nnu + f);
+  const R rc = PM ? PL<R>::div((R)1, chi) : (R)0;
+
+  double jac = 0.0, dX = 0.0, dE = 0.0;
+#pragma unroll
+  for (int m = 0; m < NMU; ++m) {
+    const R i2m = FTab<R>::i2mu(C, m);
+    R a, b, e, bx;
+    pl_coefs<R>(base * i2m, a, b, e, bx);
+    se[t] = e;
+    sa[t] = a;
+    sb[t] = b;
+    if (PM) sbx[t] = bx;
+    __syncthreads();
+    // segment (t, t+1) as computed by thread t + 1
+    const R e2 = dn_seg ? se[t + 1] : (R)0, a2 = dn_seg ? sa[t + 1] : (R)0;
+    const R b2 = dn_seg ? sb[t + 1] : (R)0, bx2 = (PM && dn_seg) ? sbx[t + 1] : (R)0;
+    // downward map at t: I_0 = 0 at the top
+    R fe = (R)1, fs = (R)0;
+    if (in) {
+      fe = up_seg ? e : (R)0;
+      fs = up_seg ? fmar(a, S, b * S_p) : (R)0;
+    }
+    // upward map at t: I = B at the bottom
+    R ge = (R)1, gs = (R)0;
+    if (in) {
+      ge = dn_seg ? e2 : (R)0;
+      gs = dn_seg ? fmar(a2, S, b2 * S_n) : Bb;
+    }
+    scan_down<R>(fe, fs, le, ls);
+    scan_up<R>(ge, gs, le, ls);
+    const double w = FTab<double>::wm2(C, m);
+    jac = fmar(w, (double)fs + (double)gs, jac);
+    if (PM) {
+      sin_[t] = fs;
+      sout[t] = gs;
+      __syncthreads();
+      const R i2 = i2m;
+      if (up_seg) {  // c_chi, c_eta of App. A.2 (ingoing ray, segment t-1 -> t)
+        const R Iup = sin_[t - 1];
+        const R cchi = -(S * rc) * a + dz_p * i2 * (e * (S_p - Iup) - (S_p - S) * bx);
+        dX = fmar(w, (double)cchi, dX);
+        dE = fmar(w, (double)(a * rc), dE);
+      }
+      if (dn_seg) {  // a_chi, a_eta (outgoing ray, segment t+1 -> t)
+        const R Iup = sout[t + 1];
+        const R achi = -(S * rc) * a2 + dz_n * i2 * (e2 * (S_n - Iup) - (S_n - S) * bx2);
+        dX = fmar(w, (double)achi, dX);
+        dE = fmar(w, (double)(a2 * rc), dE);
+      }
+    }
+    __syncthreads();  // the coefficient and intensity rows are rewritten for the next angle
+  }
+  if (in) {
+    const size_t fk = (size_t)f * nz + t;
+    stg(C.JT + fk, jac);
+    if (PM) {
+      stg(C.DchiT + fk, dX);
+      stg(C.DetaT + fk, dE);
+    }
+  }
+}
+
+template <typename R, bool PM>
+static void launch_formal_scan_mu(int nmu, hipStream_t s, const ColDev* cols, const Tile* tiles,
+                                  int ntiles) {
+  const int blocks = ntiles * kWave;
+  switch (nmu) {
+#define NLTE_SCAN_CASE(M) \
+  case M: k_formal_scan<R, PM, M><<<blocks, kScanThreads, 0, s>>>(cols, tiles, ntiles); break;
+    NLTE_SCAN_CASE(1) NLTE_SCAN_CASE(2) NLTE_SCAN_CASE(3) NLTE_SCAN_CASE(4)
+    NLTE_SCAN_CASE(5) NLTE_SCAN_CASE(6) NLTE_SCAN_CASE(7) NLTE_SCAN_CASE(8)
+#undef NLTE_SCAN_CASE
+    default: break;
+  }
+}
+
 // One launch per (precision, angle count, mode) present in a step, over that
 // group's tiles; a wave whose column is idle or in the other mode returns.
 template <typename R, bool PM, int NMU>
@@ -822,6 +1024,17 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     const TileGroup& G = bw.groups[g];
     const int nb = bw.formal_wpb;
     const Tile* tl = bw.tiles + G.first;
+    if (G.scan) {
+      if (G.prec == NLTE_FP32_FORM) {
+        launch_formal_scan_mu<float, false>(G.nmu, s, bw.cols, tl, G.count);
+        if (bw.any_newton) launch_formal_scan_mu<float, true>(G.nmu, s, bw.cols, tl, G.count);
+      }
+      if (G.prec == NLTE_FP64 || bw.fallback) {
+        launch_formal_scan_mu<double, false>(G.nmu, s, bw.cols, tl, G.count);
+        if (bw.any_newton) launch_formal_scan_mu<double, true>(G.nmu, s, bw.cols, tl, G.count);
+      }
+      continue;
+    }
     if (G.prec == NLTE_FP32_FORM) {
       launch_formal_mu<float, false>(G.nmu, nb, s, bw.cols, tl, G.count);
       if (bw.any_newton) launch_formal_mu<float, true>(G.nmu, nb, s, bw.cols, tl, G.count);
@@ -853,18 +1066,19 @@ void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
     sel = all.data();
     nsel = ncol;
   }
-  // formal-solution tiles grouped by (precision, angle count)
-  for (int prec = 0; prec < 2; ++prec)
-    for (int nmu = 1; nmu <= kMaxMu; ++nmu) {
-      TileGroup G{prec, nmu, (int)tiles.size(), 0};
-      for (int q = 0; q < nsel; ++q) {
-        const int c = sel[q];
-        if (hc[c].prec == prec && hc[c].nmu == nmu)
-          for (int ch = 0; ch < hc[c].nchunk; ++ch) tiles.push_back(Tile{c, ch});
+  // formal-solution tiles grouped by (variant, precision, angle count)
+  for (int scan = 0; scan < 2; ++scan)
+    for (int prec = 0; prec < 2; ++prec)
+      for (int nmu = 1; nmu <= kMaxMu; ++nmu) {
+        TileGroup G{prec, nmu, (int)tiles.size(), 0, scan};
+        for (int q = 0; q < nsel; ++q) {
+          const int c = sel[q];
+          if (hc[c].prec == prec && hc[c].nmu == nmu && hc[c].scan == scan)
+            for (int ch = 0; ch < hc[c].nchunk; ++ch) tiles.push_back(Tile{c, ch});
+        }
+        G.count = (int)tiles.size() - G.first;
+        if (G.count) groups.push_back(G);
       }
-      G.count = (int)tiles.size() - G.first;
-      if (G.count) groups.push_back(G);
-    }
   // rate items (kind 0) and preconditioner pair items (kind 1) share one list
   maxL = 0;
   for (int q = 0; q < nsel; ++q) {

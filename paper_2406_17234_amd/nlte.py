@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libnlte.so")
 
 NLTE_OK, NLTE_E_INVALID, NLTE_E_NOMEM, NLTE_E_DEVICE = 0, -1, -2, -3
 NLTE_E_NOCONV, NLTE_E_NONFINITE, NLTE_E_BUSY = -4, -5, -6
+DEPTH_SCAN = 0x100  # OR into a column's precision: depth-parallel formal solution
 FP64, FP32_FORM = 0, 1
 STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "DEVICE", -4: "NOCONV",
                 -5: "NONFINITE", -6: "BUSY"}
@@ -274,7 +275,9 @@ class Column:
         self.h = h
         dims = (C.c_int32 * 8)()
         _check(lib().nlte_column_dims(h, dims))
-        self.nz, self.nlev, self.ntr, self.nline, self.nbf, self.nnu, self.nmu, self.precision = list(dims)
+        self.nz, self.nlev, self.ntr, self.nline, self.nbf, self.nnu, self.nmu, pf = list(dims)
+        self.precision = pf & ~DEPTH_SCAN
+        self.depth_scan = bool(pf & DEPTH_SCAN)
         self.device = torch.device("cuda", ctx.device)
         nb = C.c_size_t()
         _check(lib().nlte_column_bytes(h, C.byref(nb)))
