@@ -450,6 +450,7 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
     C.Vf = C.Bnuf = C.Ebff = C.VTf = C.EbfTf = nullptr;
   }
   C.coef = Lo.take<double>((size_t)nz * ncoef(ntr));
+  C.rseg = Lo.take<int4>(std::max(C.nrseg, 1));
   C.pairs = Lo.take<int4>(std::max(C.npair, 1));
   C.pg_ptr = Lo.take<int>(L * L + 1);
   C.pg_code = Lo.take<int>(4 * ntr + 4 * std::max(C.npair, 1));
@@ -464,7 +465,7 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.Deta = Lo.take<double>(kf);
   C.DchiT = Lo.take<double>(kf);
   C.DetaT = Lo.take<double>(kf);
-  C.RJ = Lo.take<double>((size_t)nz * ntr * 2);
+  C.RJ = Lo.take<double>((size_t)nz * std::max(C.nrseg, 1) * 2);
   C.M = Lo.take<double>((size_t)nz * std::max(C.npair, 1) * 2);
   C.P = Lo.take<double>((size_t)nz * L * L);
   C.LU = Lo.take<double>((size_t)nz * L * L);
@@ -588,11 +589,21 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
       if (tr[t].wlo < f1 && tr[t].whi > f0) ch_ed.push_back(t);
     ch_eptr[c + 1] = (int)ch_ed.size();
   }
+  // frequency segments of the rate integrals and of the window intersections
+  const int seg_len = scan ? kSegLenScan : kSegLen;
+  std::vector<int4> rseg;
+  for (int t = 0; t < ntr; ++t) {
+    tr[t].sfirst = (int)rseg.size();
+    for (int a = tr[t].wlo; a < tr[t].whi; a += seg_len)
+      rseg.push_back(make_int4(t, a, std::min(a + seg_len, tr[t].whi), 0));
+    tr[t].nseg = (int)rseg.size() - tr[t].sfirst;
+  }
+  C.nrseg = (int)rseg.size();
   std::vector<int4> pairs;
   for (int t = 0; t < ntr; ++t)
     for (int u = 0; u < ntr; ++u) {
       const int a = std::max(tr[t].wlo, tr[u].wlo), b = std::min(tr[t].whi, tr[u].whi);
-      if (b > a) pairs.push_back(make_int4(t, u, a, b));
+      for (int q = a; q < b; q += seg_len) pairs.push_back(make_int4(t, u, q, std::min(q + seg_len, b)));
     }
   C.npair = (int)pairs.size();
   // gather lists of the preconditioner blocks: entry (i, j) sums
@@ -687,6 +698,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   UP(C.ch_line, ch_tr.data(), ch_tr.size() * 4);
   UP(C.ch_eptr, ch_eptr.data(), ch_eptr.size() * 4);
   UP(C.ch_edge, ch_ed.data(), ch_ed.size() * 4);
+  UP(C.rseg, rseg.data(), rseg.size() * sizeof(int4));
   UP(C.pairs, pairs.data(), pairs.size() * sizeof(int4));
   UP(wp.rate, rate_w.data(), rate_w.size() * sizeof(int4));
   UP(wp.pb, prec_w.data(), prec_w.size() * sizeof(int2));

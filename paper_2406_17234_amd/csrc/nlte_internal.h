@@ -79,6 +79,7 @@ struct TrDev {
   int wlo, whi;     // window on the union grid [wlo, whi)
   int voff;         // offset of its V table (lines: [nz][wlen]; edges: [wlen])
   int cwoff;        // offset of its rate weights 4 pi w / (h nu) [wlen]
+  int sfirst, nseg; // its frequency segments in ColDev::rseg
   double g;         // lines: g_l / g_u
   double Blu;       // lines: Einstein B_lu (for the profile-averaged intensity)
 };
@@ -92,7 +93,6 @@ struct ColState {
   int phase;        // solver phase (see nlte_solver.hip)
   int status;       // nlte_status of the solve
   int newton_it, krylov_j, krylov_total, f_calls, stalls, ls_try, restarts, precond_calls;
-  double rho_eval;  // max scaled residual of the last evaluation
   double rho_cur;   // max scaled residual at the Newton iterate
   double beta0;     // preconditioned residual norm at the start of the Newton step
   double eps_fd;    // difference step of the pending product
@@ -113,7 +113,8 @@ struct ColState {
 struct ColDev {
   int nz, L, ntr, nline, nbf, nnu, nmu, prec;
   int nchunk, npair, has_sca, N;   // N = nz * L; npair = overlapping transition pairs
-  int scan, pad_scan;              // 1: depth-parallel formal solution (nz <= 256)
+  int scan;                        // 1: depth-parallel formal solution (nz <= 256)
+  int nrseg;                       // frequency segments of the rate integrals
   // angles (inline: at most kMaxMu)
   double wm2[kMaxMu];     // w_m / 2
   double inv2mu[kMaxMu];  // 1 / (2 mu_m)
@@ -140,7 +141,8 @@ struct ColDev {
   // chunk -> overlapping line windows and edge windows; overlapping transition pairs
   const int *ch_lptr, *ch_line;
   const int *ch_eptr, *ch_edge;
-  const int4 *pairs;               // (t, t', first, last + 1) of each window intersection
+  const int4 *rseg;                // (t, first, last + 1, -) of each rate-integral segment
+  const int4 *pairs;               // (t, t', first, last + 1) of each window-intersection segment
   const int *pg_ptr, *pg_code;     // per block entry (i, j): contributions, see k_pblock
   // evaluation buffers
   ColState *st;
@@ -155,7 +157,7 @@ struct ColDev {
   double *XS;                      // [nz][nnu][2] chi and S of the first sweep
   double *Dchi, *Deta;             // [nz][nnu] ingoing-ray intensity derivatives
   double *DchiT, *DetaT;           // [nnu][nz] angle-averaged local intensity derivatives
-  double *RJ;                      // [nz][ntr][2] rate integrals over J
+  double *RJ;                      // [nz][nrseg][2] rate integrals over J, per segment
   double *M;                       // [nz][npair][2] pair sums of the radiative blocks
   double *P;                       // [nz][L][L] preconditioner blocks of the last Newton-mode evaluation
   double *LU;                      // [nz][L][L] LU factors of the iterate's blocks
@@ -187,6 +189,15 @@ struct Tile {
 };
 
 inline __host__ __device__ int chunk_of(int f) { return f / kWave; }
+
+// Frequency sums over a transition's window (rate integrals, preconditioner
+// pair sums) run in segments of at most this many frequencies, each summed by
+// its own wave, so that the longest serial chain of a wide window stays short.
+// A property of the column (not of the batch it is evaluated in): columns with
+// the depth-parallel formal solution, evaluated alone or few at a time, use
+// the short segments.
+constexpr int kSegLen = 512;
+constexpr int kSegLenScan = 128;
 
 // Level coefficients of an evaluation (k_coef), [ntr + 2][nz][2]: per
 // transition and depth two values, then two background rows.

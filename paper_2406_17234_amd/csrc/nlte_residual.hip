@@ -185,12 +185,17 @@ __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0
                                               bool fin, int fc, const R* __restrict__ Vt,
                                               const double* __restrict__ coef, int ntr);
 
+// nsplit waves share a tile's depth groups (round-robin), so that a launch
+// over few tiles (one large column) still fills the chip; every depth group is
+// computed the same way whichever wave takes it.
 template <typename R, int KG>
 __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols,
-                                                 const Tile* __restrict__ tiles, int ntiles) {
+                                                 const Tile* __restrict__ tiles, int ntiles,
+                                                 int nsplit) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int tid = blockIdx.x * (blockDim.x >> 6) + wave;
+  const int wid = blockIdx.x * (blockDim.x >> 6) + wave;
+  const int tid = wid / nsplit, part = wid - tid * nsplit;
   if (tid >= ntiles) return;
   const int col = uni(tiles[tid].col);
   const int chunk = uni(tiles[tid].chunk);
@@ -204,7 +209,7 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
   const R* __restrict__ Vt = FTab<R>::V(C);
   const double* __restrict__ coef = (const double*)C.coef;
   const int ntr = uni(C.ntr);
-  for (int k0 = 0; k0 < nz; k0 += KG)
+  for (int k0 = part * KG; k0 < nz; k0 += nsplit * KG)
     opacity_group<R, KG>(C, chunk, k0, nz, nnu, fin, fc, Vt, coef, ntr);
 }
 
@@ -754,27 +759,31 @@ template <typename TB>  // table precision: double, or float for FP32-form colum
 __device__ __forceinline__ void rates_sum(const ColDev& C, int t, int k0, const TB* __restrict__ VTt,
                                           const TB* __restrict__ EbfTt);
 
-__device__ __forceinline__ void rates_item(const ColDev& C, int t, int k0) {
+__device__ __forceinline__ void rates_item(const ColDev& C, int sg, int k0) {
   if (uni(C.prec) == NLTE_FP32_FORM)
-    rates_sum<float>(C, t, k0, C.VTf, C.EbfTf);
+    rates_sum<float>(C, sg, k0, C.VTf, C.EbfTf);
   else
-    rates_sum<double>(C, t, k0, C.VT, C.EbfT);
+    rates_sum<double>(C, sg, k0, C.VT, C.EbfT);
 }
 
+// One frequency segment [q0, q1) of transition t's window; the assembly adds
+// the segments of a transition in order.
 template <typename TB>
-__device__ __forceinline__ void rates_sum(const ColDev& C, int t, int k0, const TB* __restrict__ VTt,
+__device__ __forceinline__ void rates_sum(const ColDev& C, int sg, int k0, const TB* __restrict__ VTt,
                                           const TB* __restrict__ EbfTt) {
   if (uni(C.st->mode) == kModeIdle) return;
   const int nz = C.nz;
   const int k = k0 + threadIdx.x;
   if (k >= nz) return;
+  const int4 seg = C.rseg[sg];
+  const int t = uni(seg.x), q0 = uni(seg.y);
   const TrDev& T = C.tr[t];
-  const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
-  const double* __restrict__ J = C.JT + (size_t)wlo * nz + k;
-  const double* __restrict__ cw = C.cw + uni(T.cwoff);
-  double* dst = C.RJ + ((size_t)k * C.ntr + t) * 2;
+  const int wl = uni(seg.z) - q0, wo = q0 - uni(T.wlo);  // length, offset in the window
+  const double* __restrict__ J = C.JT + (size_t)q0 * nz + k;
+  const double* __restrict__ cw = C.cw + uni(T.cwoff) + wo;
+  double* dst = C.RJ + ((size_t)k * C.nrseg + sg) * 2;
   if (t < C.nline) {
-    const TB* __restrict__ V = VTt + uni(T.voff) + k;
+    const TB* __restrict__ V = VTt + uni(T.voff) + (size_t)wo * nz + k;
     double s = 0.0, c = 0.0;
 #pragma unroll 4
     for (int q = 0; q < wl; ++q)
@@ -782,8 +791,8 @@ __device__ __forceinline__ void rates_sum(const ColDev& C, int t, int k0, const 
     stg(dst, s + c);
     stg(dst + 1, 0.0);
   } else {
-    const double* __restrict__ A = C.V + uni(T.voff);
-    const TB* __restrict__ E = EbfTt + (size_t)wlo * nz + k;
+    const double* __restrict__ A = C.V + uni(T.voff) + wo;
+    const TB* __restrict__ E = EbfTt + (size_t)q0 * nz + k;
     double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
 #pragma unroll 4
     for (int q = 0; q < wl; ++q) {
@@ -870,94 +879,120 @@ __global__ __launch_bounds__(64) void k_depthwork(const ColDev* __restrict__ col
 // ---------------------------------------------------------------------------
 // assembly: rates, F rows, conservation rows, rho, preconditioner blocks
 // ---------------------------------------------------------------------------
-constexpr int kAsmThreads = 128;
+// One workgroup per kAsmDepths depths of a column.  Phase 1 spreads the
+// (depth, transition) pairs over all threads: the segment sums are added up,
+// the rates and total rates written out and each transition's net and gross
+// flows parked in LDS.  Phase 2 gives each depth one thread, which adds the
+// flows to the levels in transition order (the order fixes the rounding of F),
+// and phase 3 sets the conservation row and writes F, G and the per-depth
+// scaled residual.  Transitions go through LDS kAsmTr at a time.
+constexpr int kAsmThreads = 256;
+constexpr int kAsmDepths = 32;
+constexpr int kAsmTr = 64;
 
 __global__ __launch_bounds__(kAsmThreads) void k_assemble(const ColDev* __restrict__ cols,
-                                                          const int* __restrict__ act) {
-  __shared__ double sF[kAsmThreads][kMaxLev + 1];
-  __shared__ double sG[kAsmThreads][kMaxLev + 1];
-  const ColDev& C = cols[act ? act[blockIdx.x] : blockIdx.x];
+                                                          const int* __restrict__ act, int nsub) {
+  __shared__ double sK[kAsmDepths][kAsmTr + 1], sX[kAsmDepths][kAsmTr + 1];
+  __shared__ double sF[kAsmDepths][kMaxLev + 1], sG[kAsmDepths][kMaxLev + 1];
+  const int ci = blockIdx.x / nsub, sub = blockIdx.x - ci * nsub;
+  const ColDev& C = cols[act ? act[ci] : ci];
   const int mode = uni(C.st->mode);
   if (mode == kModeIdle) return;
-  const int nz = C.nz, L = C.L, ntr = C.ntr, nline = C.nline;
+  const int nz = C.nz, L = C.L, ntr = C.ntr, nline = C.nline, nrseg = C.nrseg;
+  const int k0 = sub * kAsmDepths;
+  if (k0 >= nz) return;
+  const int nd = min(kAsmDepths, nz - k0);
   const int tx = threadIdx.x;
-  double rmax = 0.0;
-  for (int k = tx; k < nz; k += blockDim.x) {
-    const double* nk = C.eval_n + k * L;
-    double* Fk = sF[tx];
-    double* Gk = sG[tx];
+  const double* __restrict__ en = C.eval_n;
+  if (tx < nd)
     for (int i = 0; i < L; ++i) {
-      Fk[i] = 0.0;
-      Gk[i] = 0.0;
+      sF[tx][i] = 0.0;
+      sG[tx][i] = 0.0;
     }
-    for (int t = 0; t < ntr; ++t) {
+  for (int t0 = 0; t0 < ntr; t0 += kAsmTr) {
+    const int nt = min(kAsmTr, ntr - t0);
+    for (int id = tx; id < nd * nt; id += kAsmThreads) {
+      const int kk = id / nt, tt = id - kk * nt;
+      const int k = k0 + kk, t = t0 + tt;
       const TrDev& T = C.tr[t];
-      const int lo = uni(T.lo), up = uni(T.up);
-      const double* rj = C.RJ + ((size_t)k * ntr + t) * 2;
-      const double Rlu = rj[0];
-      const double Rsp = C.Rsp[k * ntr + t];
-      const double Rul = (t < nline) ? uni(T.g) * (Rsp + Rlu)
-                                     : C.rho_bf[k * C.nbf + (t - nline)] * (Rsp + rj[1]);
-      double* R = C.R + ((size_t)k * ntr + t) * 2;
-      R[0] = Rlu;
-      R[1] = Rul;
-      const double up_rate = C.C_lu[k * ntr + t] + Rlu;
-      const double dn_rate = C.C_ul[k * ntr + t] + Rul;
-      double* Rt = C.Rtot + ((size_t)k * ntr + t) * 2;
-      Rt[0] = up_rate;
-      Rt[1] = dn_rate;
-      const double out_l = nk[lo] * up_rate;
-      const double out_u = nk[up] * dn_rate;
-      const double kap = out_l - out_u;
-      Fk[lo] += kap;
-      Fk[up] -= kap;
-      const double gross = fabs(out_l) + fabs(out_u);
-      Gk[lo] += gross;
-      Gk[up] += gross;
-    }
-    int r;
-    if (C.st->rows_own) {
-      r = 0;
-      double best = nk[0];
-      for (int i = 1; i < L; ++i)
-        if (nk[i] > best) {
-          best = nk[i];
-          r = i;
+      const double* __restrict__ rj = C.RJ + (size_t)k * nrseg * 2;
+      // the transition's segments, added in order (compensated)
+      const int s0 = T.sfirst, ns = T.nseg;
+      double Rlu = ldg(rj + 2 * s0), Rx = ldg(rj + 2 * s0 + 1);
+      if (ns > 1) {
+        double c0 = 0.0, c1 = 0.0;
+        for (int q = 1; q < ns; ++q) {
+          neumaier(Rlu, c0, ldg(rj + 2 * (s0 + q)));
+          neumaier(Rx, c1, ldg(rj + 2 * (s0 + q) + 1));
         }
-    } else {
-      r = C.rows_frozen[k];
+        Rlu += c0;
+        Rx += c1;
+      }
+      const size_t kt = (size_t)k * ntr + t;
+      const double Rsp = ldg(C.Rsp + kt);
+      const double Rul = (t < nline) ? T.g * (Rsp + Rlu)
+                                     : ldg(C.rho_bf + (size_t)k * C.nbf + (t - nline)) * (Rsp + Rx);
+      stg(C.R + 2 * kt, Rlu);
+      stg(C.R + 2 * kt + 1, Rul);
+      const double up_rate = ldg(C.C_lu + kt) + Rlu;
+      const double dn_rate = ldg(C.C_ul + kt) + Rul;
+      stg(C.Rtot + 2 * kt, up_rate);
+      stg(C.Rtot + 2 * kt + 1, dn_rate);
+      const double out_l = ldg(en + (size_t)k * L + T.lo) * up_rate;
+      const double out_u = ldg(en + (size_t)k * L + T.up) * dn_rate;
+      sK[kk][tt] = out_l - out_u;
+      sX[kk][tt] = fabs(out_l) + fabs(out_u);
     }
-    C.rows[k] = r;
-    double sum = 0.0;
-    for (int i = 0; i < L; ++i) sum += nk[i];
-    // keep the rate row that the conservation row replaces, so a caller can
-    // move the conservation row without another formal solution
-    C.Fsave[k] = Fk[r];
-    C.Gsave[k] = Gk[r];
-    Fk[r] = C.ntot[k] - sum;
-    Gk[r] = C.ntot[k];
-    double rk = 0.0;
-    for (int i = 0; i < L; ++i) {
-      C.F[k * L + i] = Fk[i];
-      C.G[k * L + i] = Gk[i];
-      const double q = fabs(Fk[i]) / Gk[i];
-      rk = (q > rk || q != q) ? q : rk;
-    }
-    C.rho_k[k] = rk;
-    rmax = (rk > rmax || rk != rk) ? rk : rmax;
-  }
-  // block max (NaN-propagating)
-  __shared__ double sm[kAsmThreads];
-  sm[tx] = rmax;
-  __syncthreads();
-  for (int o = kAsmThreads / 2; o > 0; o >>= 1) {
-    if (tx < o) {
-      const double a = sm[tx], b = sm[tx + o];
-      sm[tx] = (b > a || b != b) ? b : a;
+    __syncthreads();
+    if (tx < nd) {
+      double* Fk = sF[tx];
+      double* Gk = sG[tx];
+      for (int tt = 0; tt < nt; ++tt) {
+        const TrDev& T = C.tr[t0 + tt];
+        const int lo = uni(T.lo), up = uni(T.up);
+        const double kap = sK[tx][tt], gross = sX[tx][tt];
+        Fk[lo] += kap;
+        Fk[up] -= kap;
+        Gk[lo] += gross;
+        Gk[up] += gross;
+      }
     }
     __syncthreads();
   }
-  if (tx == 0) C.st->rho_eval = sm[0];
+  if (tx >= nd) return;
+  const int k = k0 + tx;
+  const double* nk = en + (size_t)k * L;
+  double* Fk = sF[tx];
+  double* Gk = sG[tx];
+  int r;
+  if (C.st->rows_own) {
+    r = 0;
+    double best = nk[0];
+    for (int i = 1; i < L; ++i)
+      if (nk[i] > best) {
+        best = nk[i];
+        r = i;
+      }
+  } else {
+    r = C.rows_frozen[k];
+  }
+  C.rows[k] = r;
+  double sum = 0.0;
+  for (int i = 0; i < L; ++i) sum += nk[i];
+  // keep the rate row that the conservation row replaces, so a caller can
+  // move the conservation row without another formal solution
+  C.Fsave[k] = Fk[r];
+  C.Gsave[k] = Gk[r];
+  Fk[r] = C.ntot[k] - sum;
+  Gk[r] = C.ntot[k];
+  double rk = 0.0;
+  for (int i = 0; i < L; ++i) {
+    C.F[k * L + i] = Fk[i];
+    C.G[k * L + i] = Gk[i];
+    const double q = fabs(Fk[i]) / Gk[i];
+    rk = (q > rk || q != q) ? q : rk;
+  }
+  C.rho_k[k] = rk;
 }
 
 // Preconditioner blocks of Newton-mode columns: one thread per (depth, entry)
@@ -999,12 +1034,14 @@ __global__ __launch_bounds__(256) void k_pblock(const ColDev* __restrict__ cols,
 template <typename R>
 static void launch_opacity(int kg, int ntiles, int maxnz, hipStream_t s, const ColDev* cols,
                            const Tile* tiles) {
-  const int bx = (ntiles + 3) / 4;
-  (void)maxnz;
+  // about 4096 waves in all, at most one per depth group
+  const int ngrp = (maxnz + kg - 1) / kg;
+  const int nsplit = std::max(1, std::min(ngrp, 4096 / std::max(ntiles, 1)));
+  const int bx = (ntiles * nsplit + 3) / 4;
   switch (kg) {
-    case 4: k_opacity<R, 4><<<bx, 256, 0, s>>>(cols, tiles, ntiles); break;
-    case 16: k_opacity<R, 16><<<bx, 256, 0, s>>>(cols, tiles, ntiles); break;
-    default: k_opacity<R, 8><<<bx, 256, 0, s>>>(cols, tiles, ntiles); break;
+    case 4: k_opacity<R, 4><<<bx, 256, 0, s>>>(cols, tiles, ntiles, nsplit); break;
+    case 16: k_opacity<R, 16><<<bx, 256, 0, s>>>(cols, tiles, ntiles, nsplit); break;
+    default: k_opacity<R, 8><<<bx, 256, 0, s>>>(cols, tiles, ntiles, nsplit); break;
   }
 }
 
@@ -1047,7 +1084,10 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   if (ev) hipEventRecord(ev[2], s);
   if (bw.nrate > 0) k_depthwork<<<bw.nrate, 64, 0, s>>>(bw.cols, bw.rate_work, bw.nrate);
   if (ev) hipEventRecord(ev[3], s);
-  k_assemble<<<nblk, kAsmThreads, 0, s>>>(bw.cols, bw.act);
+  {
+    const int nsub = (bw.maxnz + kAsmDepths - 1) / kAsmDepths;
+    k_assemble<<<nblk * nsub, kAsmThreads, 0, s>>>(bw.cols, bw.act, nsub);
+  }
   if (bw.any_newton && bw.npb > 0) k_pblock<<<bw.npb, 256, 0, s>>>(bw.cols, bw.pb_work, bw.npb);
   if (ev) hipEventRecord(ev[4], s);
   return hipGetLastError();
@@ -1089,8 +1129,8 @@ void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
     const int c = sel[q];
     const ColDev& C = hc[c];
     maxL = std::max(maxL, C.L);
-    for (int t = 0; t < C.ntr; ++t)
-      for (int k0 = 0; k0 < C.nz; k0 += kWave) rate.push_back(make_int4(c, t, k0, 0));
+    for (int sg = 0; sg < C.nrseg; ++sg)
+      for (int k0 = 0; k0 < C.nz; k0 += kWave) rate.push_back(make_int4(c, sg, k0, 0));
     for (int p = 0; p < C.npair; ++p)
       for (int k0 = 0; k0 < C.nz; k0 += kWave) rate.push_back(make_int4(c, p, k0, 1));
   }

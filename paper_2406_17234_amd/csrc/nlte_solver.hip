@@ -553,7 +553,6 @@ __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* con
     st->stalls = 0;
     st->ls_try = 0;
     st->restarts = 0;
-    st->rho_eval = 0;
     st->rho_cur = 0;
     st->dn_inf = 0;
     st->ftol = a.ftol;
