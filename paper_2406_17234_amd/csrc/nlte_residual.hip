@@ -33,12 +33,11 @@ namespace nlte {
 // e = exp(-x), a = 1 - (1 - e)/x, b = (1 - e)/x - e.  The closed forms cancel
 // at small x; below a switch point a and b come from their Taylor series
 //   a/x = sum_{m>=1} (-1)^{m+1} x^{m-1} / (m+1)!,
-//   b/x = sum_{m>=1} (-1)^{m+1} m x^{m-1} / (m+1)!,
-// and e = 1 - a - b (only the derivatives need it).
-//   FP64: 13 terms below x = 0.1 (truncation below 1e-17 relative).
-//   FP32: 6 terms below x = 0.3; the worst relative error of a and b over all
-//   x is then 1.4e-6, set by the closed forms' cancellation just above 0.3
-//   (the 10-term series below 0.25 gives 1.9e-6).
+//   b/x = sum_{m>=1} (-1)^{m+1} m x^{m-1} / (m+1)!.
+//   FP64: switch at x = 0.1 (series truncation below 1e-20 relative).
+//   FP32: switch at x = 0.3 with 6 terms; the worst relative error of a over
+//   all x is then 8e-7 (of q = 1 - e 1.1e-7), set by the closed form's
+//   cancellation just above the switch.
 constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
 constexpr double ser_a(int m) { return ((m & 1) ? 1.0 : -1.0) / fact(m + 1); }
 constexpr double ser_b(int m) { return ((m & 1) ? 1.0 : -1.0) * m / fact(m + 1); }
@@ -63,50 +62,78 @@ __device__ __forceinline__ void horner_ab(R x, R& pa, R& pb) {
   }
 }
 
+template <typename R, int m, int M>
+__device__ __forceinline__ R horner_a(R x) {
+  constexpr R c = (R)ser_a(m);
+  if constexpr (m == M)
+    return c;
+  else
+    return fmar(horner_a<R, m + 1, M>(x), x, c);
+}
+
+// Below kSwitch the depth recursion takes a/x from its first kTerms series
+// terms (kTermsAB for the pair a, b of the depth-parallel variant).
 template <typename R> struct PL;
 template <> struct PL<double> {
   static constexpr double kSwitch = 0.1;
-  static constexpr int kTerms = 13;
+  static constexpr int kTerms = 11;
+  static constexpr int kTermsAB = 13;
   static __device__ __forceinline__ double ex(double x) { return exp(-x); }
   static __device__ __forceinline__ double div(double p, double q) { return p / q; }
 };
 template <> struct PL<float> {
   static constexpr float kSwitch = 0.3f;
   static constexpr int kTerms = 6;
+  static constexpr int kTermsAB = 6;
   static __device__ __forceinline__ float ex(float x) { return __expf(-x); }
   static __device__ __forceinline__ float div(float p, float q) {
     return p * __builtin_amdgcn_rcpf(q);
   }
 };
 
-// One step of a ray across a segment of optical thickness x:
-//   I <- I + a (S - I) + b (S_up - I).
-// With PM it also returns a, e and b/x for the local intensity derivatives.
+// Depth recursion of the piecewise-linear scheme (Appendix A.1), written as
+//   I <- e I + q S_up + a (S - S_up),   q = 1 - e = a + b,
+// of whose three terms e I and q S_up are never negative and the last is at
+// most half their sum in size, so no step cancels (S - S_up is shared by the
+// angles).  Below kSwitch a = x (a/x) from the series of a/x, q = x (1 - a)
+// and e = 1 - q, all to relative accuracy; above, e is the exponential,
+// q = 1 - e and a = 1 - q/x with 1/x = rb mu2 (rb = 1/base shared by the
+// angles, mu2 = 2 mu).  With PM also b/x for the intensity derivatives.
+// The side is chosen per wave: a wave whose lanes all fall on one side runs
+// that side only, a mixed wave runs both and selects per lane (the same bits
+// either way).
 template <typename R, bool PM>
-__device__ __forceinline__ void ray_step(R x, R S, R Sup, R& I, R& a_o, R& e_o, R& bx_o) {
-  R a, b, e, bx;
-  if (x < PL<R>::kSwitch) {
-    R pa, pb;
-    horner_ab<R, 1, PL<R>::kTerms>(x, pa, pb);
-    a = pa * x;
-    b = pb * x;
-    if (PM) {
-      e = (R)1 - a - b;
-      bx = pb;
-    }
+__device__ __forceinline__ void seg_series(R x, R& e, R& q, R& a, R& bx) {
+  const R pa = horner_a<R, 1, PL<R>::kTerms>(x);
+  a = pa * x;
+  q = fmar(-x, a, x);
+  e = (R)1 - q;
+  if (PM) bx = ((R)1 - a) - pa;
+}
+template <typename R, bool PM>
+__device__ __forceinline__ void seg_exp(R x, R rb, R mu2, R& e, R& q, R& a, R& bx) {
+  e = PL<R>::ex(x);
+  q = (R)1 - e;
+  const R rx = rb * mu2;
+  a = fmar(-q, rx, (R)1);
+  if (PM) bx = (q * rx - e) * rx;
+}
+template <typename R, bool PM>
+__device__ __forceinline__ void seg_coef(R x, R rb, R mu2, R& e, R& q, R& a, R& bx) {
+  const bool small = x < PL<R>::kSwitch;
+  const unsigned long long vote = __builtin_amdgcn_ballot_w64(small);
+  if (vote == __builtin_amdgcn_read_exec()) {
+    seg_series<R, PM>(x, e, q, a, bx);
   } else {
-    e = PL<R>::ex(x);
-    const R t1 = PL<R>::div((R)1 - e, x);
-    a = (R)1 - t1;
-    b = t1 - e;
-    if (PM) bx = PL<R>::div(b, x);
-  }
-  const R Iup = I;
-  I = fmar(b, Sup - Iup, fmar(a, S - Iup, Iup));
-  if (PM) {
-    a_o = a;
-    e_o = e;
-    bx_o = bx;
+    seg_exp<R, PM>(x, rb, mu2, e, q, a, bx);
+    if (vote != 0) {
+      R es, qs, as, bs;
+      seg_series<R, PM>(x, es, qs, as, bs);
+      e = small ? es : e;
+      q = small ? qs : q;
+      a = small ? as : a;
+      if (PM) bx = small ? bs : bx;
+    }
   }
 }
 
@@ -350,12 +377,13 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
   R* __restrict__ dxs = reinterpret_cast<R*>(C.Dchi);           // [nz][nnu]
   R* __restrict__ des = reinterpret_cast<R*>(C.Deta);           // [nz][nnu]
 
-  R wm2[NMU], i2mu[NMU];
+  R wm2[NMU], i2mu[NMU], mu2[NMU];
   double wm2d[NMU];
 #pragma unroll
   for (int m = 0; m < NMU; ++m) {
     wm2[m] = FTab<R>::wm2(C, m);
     i2mu[m] = FTab<R>::i2mu(C, m);
+    mu2[m] = (R)(1.0 / C.inv2mu[m]);
     wm2d[m] = C.wm2[m];
   }
 
@@ -385,13 +413,17 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
     }
     const R dz = (R)ldc(dzt + 2 * (k - 1));
     const R base = dz * (chi_p + chi);
+    const R rb = PL<R>::div((R)1, base);
+    const R dS = S - S_p;
     double jac = 0.0;
     R sa = (R)0, sc = (R)0;
 #pragma unroll
     for (int m = 0; m < NMU; ++m) {
       const R Iup = I[m];
-      R a, e, bx;
-      ray_step<R, PM>(base * i2mu[m], S, S_p, I[m], a, e, bx);
+      const R x = base * i2mu[m];
+      R e, q, a, bx;
+      seg_coef<R, PM>(x, rb, mu2[m], e, q, a, bx);
+      I[m] = fmar(e, Iup, fmar(q, S_p, a * dS));
       jac = fmar(wm2d[m], (double)I[m], jac);
       if (PM) {
         // c_chi, c_eta of App. A.2 (ingoing ray, segment k-1 -> k)
@@ -466,13 +498,17 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
     const R chi = chi_c, S = S_c;
     const R dz = (R)ldc(dzt + 2 * k);
     const R base = dz * (chi + chi_n);
+    const R rb = PL<R>::div((R)1, base);
+    const R dS = S - S_n;
     double jp = 0.0;
     R sa = (R)0, sc = (R)0;
 #pragma unroll
     for (int m = 0; m < NMU; ++m) {
       const R Iup = I[m];
-      R a, e, bx;
-      ray_step<R, PM>(base * i2mu[m], S, S_n, I[m], a, e, bx);
+      const R x = base * i2mu[m];
+      R e, q, a, bx;
+      seg_coef<R, PM>(x, rb, mu2[m], e, q, a, bx);
+      I[m] = fmar(e, Iup, fmar(q, S_n, a * dS));
       jp = fmar(wm2d[m], (double)I[m], jp);
       if (PM) {
         // a_chi, a_eta of App. A.2 (outgoing ray, segment k+1 -> k)
@@ -517,12 +553,12 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
 // workgroup's waves).  All maps have e >= 0 and, for S >= 0, s >= 0, so the
 // scan adds no cancellation.
 
-// a, b, e = 1 - a - b and b/x of a segment (Appendix A.1, as in ray_step).
+// a, b, e = 1 - a - b and b/x of a segment (Appendix A.1).
 template <typename R>
 __device__ __forceinline__ void pl_coefs(R x, R& a, R& b, R& e, R& bx) {
   if (x < PL<R>::kSwitch) {
     R pa, pb;
-    horner_ab<R, 1, PL<R>::kTerms>(x, pa, pb);
+    horner_ab<R, 1, PL<R>::kTermsAB>(x, pa, pb);
     a = pa * x;
     b = pb * x;
     e = (R)1 - a - b;
@@ -746,8 +782,11 @@ static void launch_formal_mu(int nmu, int wpb, hipStream_t s, const ColDev* cols
 // each transition window (depth-contiguous operands, so every load of a
 // wave is one contiguous run).  Lines: sum cw V J.  Edges: sum cw alpha J and
 // sum cw alpha exp(-h nu/kT) J (the J part of R_ul without its depth factor).
-// Compensated (Neumaier) sums: windows run to thousands of points and the
-// residual cancels gross rates, so plain sequential sums would set its floor.
+// Every term is positive and a segment holds at most kSegLen frequencies, so
+// four interleaved FP64 partial sums, added in a fixed order, stay within
+// about kSegLen/4 roundings (below 2e-14 relative); the four chains also let
+// a wave keep four iterations' loads in flight.  Segments of a transition
+// are added with compensation in the assembly.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
   const double u = s + x;
@@ -784,24 +823,43 @@ __device__ __forceinline__ void rates_sum(const ColDev& C, int sg, int k0, const
   double* dst = C.RJ + ((size_t)k * C.nrseg + sg) * 2;
   if (t < C.nline) {
     const TB* __restrict__ V = VTt + uni(T.voff) + (size_t)wo * nz + k;
-    double s = 0.0, c = 0.0;
-#pragma unroll 4
-    for (int q = 0; q < wl; ++q)
-      neumaier(s, c, cw[q] * (double)ldg(V + (size_t)q * nz) * ldg(J + (size_t)q * nz));
-    stg(dst, s + c);
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int q = 0;
+    for (; q + 4 <= wl; q += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const size_t o = (size_t)(q + u) * nz;
+        s[u] = fma(cw[q + u] * (double)ldg(V + o), ldg(J + o), s[u]);
+      }
+    }
+    for (; q < wl; ++q) {
+      const size_t o = (size_t)q * nz;
+      s[0] = fma(cw[q] * (double)ldg(V + o), ldg(J + o), s[0]);
+    }
+    stg(dst, (s[0] + s[1]) + (s[2] + s[3]));
     stg(dst + 1, 0.0);
   } else {
     const double* __restrict__ A = C.V + uni(T.voff) + wo;
     const TB* __restrict__ E = EbfTt + (size_t)q0 * nz + k;
-    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
-#pragma unroll 4
-    for (int q = 0; q < wl; ++q) {
-      const double x = cw[q] * A[q] * ldg(J + (size_t)q * nz);
-      neumaier(s1, c1, x);
-      neumaier(s2, c2, x * (double)ldg(E + (size_t)q * nz));
+    double s1[4] = {0.0, 0.0, 0.0, 0.0}, s2[4] = {0.0, 0.0, 0.0, 0.0};
+    int q = 0;
+    for (; q + 4 <= wl; q += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const size_t o = (size_t)(q + u) * nz;
+        const double x = (cw[q + u] * A[q + u]) * ldg(J + o);
+        s1[u] += x;
+        s2[u] = fma(x, (double)ldg(E + o), s2[u]);
+      }
     }
-    stg(dst, s1 + c1);
-    stg(dst + 1, s2 + c2);
+    for (; q < wl; ++q) {
+      const size_t o = (size_t)q * nz;
+      const double x = (cw[q] * A[q]) * ldg(J + o);
+      s1[0] += x;
+      s2[0] = fma(x, (double)ldg(E + o), s2[0]);
+    }
+    stg(dst, (s1[0] + s1[1]) + (s1[2] + s1[3]));
+    stg(dst + 1, (s2[0] + s2[1]) + (s2[2] + s2[3]));
   }
 }
 
