@@ -153,7 +153,7 @@ struct ColDev {
   double *JT;                      // [nnu][nz] J of the last evaluation (depth-contiguous)
   // scratch of the formal solution, in the column's formal-solution precision
   // (buffers sized for doubles):
-  double *Jm;                      // [nz][nnu] ingoing-ray part of J
+  double *Jm;                      // [nz][nnu] ingoing-ray part of J (recursion precision)
   double *XS;                      // [nz][nnu][2] chi and S of the first sweep
   double *Dchi, *Deta;             // [nz][nnu] ingoing-ray intensity derivatives
   double *DchiT, *DetaT;           // [nnu][nz] angle-averaged local intensity derivatives

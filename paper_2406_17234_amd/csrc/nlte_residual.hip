@@ -210,7 +210,8 @@ template <> struct FTab<float> {
 template <typename R, int KG>
 __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0, int nz, int nnu,
                                               bool fin, int fc, const R* __restrict__ Vt,
-                                              const double* __restrict__ coef, int ntr);
+                                              const double* __restrict__ coef, int ntr,
+                                              R (&cx)[KG], R (&sx)[KG]);
 
 // nsplit waves share a tile's depth groups (round-robin), so that a launch
 // over few tiles (one large column) still fills the chip; every depth group is
@@ -236,14 +237,17 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
   const R* __restrict__ Vt = FTab<R>::V(C);
   const double* __restrict__ coef = (const double*)C.coef;
   const int ntr = uni(C.ntr);
-  for (int k0 = part * KG; k0 < nz; k0 += nsplit * KG)
-    opacity_group<R, KG>(C, chunk, k0, nz, nnu, fin, fc, Vt, coef, ntr);
+  for (int k0 = part * KG; k0 < nz; k0 += nsplit * KG) {
+    R cx[KG], sx[KG];
+    opacity_group<R, KG>(C, chunk, k0, nz, nnu, fin, fc, Vt, coef, ntr, cx, sx);
+  }
 }
 
 template <typename R, int KG>
 __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0, int nz, int nnu,
                                               bool fin, int fc, const R* __restrict__ Vt,
-                                              const double* __restrict__ coef, int ntr) {
+                                              const double* __restrict__ coef, int ntr,
+                                              R (&cx)[KG], R (&sx)[KG]) {
   double chi[KG], et[KG];
 #pragma unroll
   for (int i = 0; i < KG; ++i) {
@@ -311,9 +315,11 @@ __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0
     const double X = (ldc(cb + 2 * (k - k0)) + chi[i]) + (A1[i] - EA2);
     double eta = fmar(ldc(cb + 2 * (k - k0) + 1), B, gam * (et[i] + EA2));
     if (sca) eta = fmar(ldc(cs + 2 * (k - k0)), ldg(C.Jdag + kf), eta);
+    cx[i] = (R)X;
+    sx[i] = (R)(eta / X);
     if (fin && k0 + i < nz) {
-      stg(xs + 2 * kf, (R)X);
-      stg(xs + 2 * kf + 1, (R)(eta / X));
+      stg(xs + 2 * kf, cx[i]);
+      stg(xs + 2 * kf + 1, sx[i]);
     }
   }
 }
@@ -338,8 +344,8 @@ __device__ __forceinline__ void stage_put(double* tile, int k, int lane, double 
   tile[(k % KF) * kWave + lane] = v;
 }
 
-template <int KF>
-__device__ __forceinline__ void stage_flush(const double* tile, double* __restrict__ out, int k0,
+template <int KF, typename TO>
+__device__ __forceinline__ void stage_flush(const double* tile, TO* __restrict__ out, int k0,
                                             int nz, int f0, int nnu, int lane) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -351,18 +357,32 @@ __device__ __forceinline__ void stage_flush(const double* tile, double* __restri
   for (int i = 0; i < KF; ++i) {
     const int fl = i * FS + fs;
     const double v = tile[kk * kWave + fl];
-    if (k < nz && f0 + fl < nnu) stg(out + (size_t)(f0 + fl) * nz + k, v);
+    if (k < nz && f0 + fl < nnu) stg(out + (size_t)(f0 + fl) * nz + k, (TO)v);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool PM> struct StageDepths { static constexpr int value = PM ? 4 : 8; };
+// Depth-group size of the opacity made inside the first sweep.
+constexpr int kFusedDepths = 4;
+// FP32 tile groups at least this large (enough chunk waves to fill the chip)
+// make their opacity inside the formal-solution kernel; smaller ones, and the
+// FP64 recursion (whose registers leave less room), keep the depth-parallel
+// opacity kernel.  The opacity arithmetic does not depend on the depth-group
+// size, so both give the same bits.
+constexpr int kFuseMinTiles = 4096;
+// Depths per LDS staging tile: a flush writes, for each frequency of the
+// chunk, that many consecutive FP64 depths.
+template <typename R, bool PM> struct StageDepths {
+  static constexpr int value = PM ? 4 : 8;
+};
+constexpr int kDepthBlock = 4;
 
 template <typename R, bool PM, int NMU>
-__device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane, double* tile) {
-  constexpr int KF = StageDepths<PM>::value;
+__device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane, double* tile,
+                                            bool fused) {
+  constexpr int KF = StageDepths<R, PM>::value;
   double* tJ = tile;
   double* tX = tile + KF * kWave;
   double* tE = tile + 2 * KF * kWave;
@@ -372,8 +392,11 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
   const bool fin = f < nnu;
   const int fc = fin ? f : nnu - 1;
   const double* __restrict__ dzt = (const double*)C.coef + ((size_t)(C.ntr + 1) * nz) * 2 + 1;  // stride 2
-  const R* __restrict__ xs = reinterpret_cast<const R*>(C.XS);  // [nz][nnu][2]: chi, S
-  double* __restrict__ jm = C.Jm;                                // [nz][nnu]
+  // [nz][nnu][2]: chi, S (in the fused variant written by the first sweep)
+  const R* xs = reinterpret_cast<const R*>(C.XS);
+  // [nz][nnu] ingoing half of J, stored in the recursion's precision (the
+  // angle sums themselves are FP64)
+  R* __restrict__ jm = reinterpret_cast<R*>(C.Jm);
   R* __restrict__ dxs = reinterpret_cast<R*>(C.Dchi);           // [nz][nnu]
   R* __restrict__ des = reinterpret_cast<R*>(C.Deta);           // [nz][nnu]
 
@@ -387,31 +410,25 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
     wm2d[m] = C.wm2[m];
   }
 
+  // Both sweeps take their per-depth operands kDepthBlock depths at a time,
+  // loaded one block ahead (depth indices clamped into the column, so every
+  // load is unconditional): a wave has that many steps of arithmetic in hand
+  // while a block's loads are in flight.
+  constexpr int U = kDepthBlock;
+
   // ---- sweep 1: ingoing rays, top -> bottom (I- = 0 at the top) ----
   R I[NMU];
 #pragma unroll
   for (int m = 0; m < NMU; ++m) I[m] = (R)0;
-  R chi_p = ldg(xs + 2 * (size_t)fc), S_p = ldg(xs + 2 * (size_t)fc + 1);
+  R chi_p = (R)0, S_p = (R)0;
   if (fin) {
-    stg(jm + f, 0.0);
+    stg(jm + f, (R)0);
     if (PM) {
       stg(dxs + f, (R)0);
       stg(des + f, (R)0);
     }
   }
-  R chi_x = 0, S_x = 0;
-  if (nz > 1) {
-    chi_x = ldg(xs + 2 * ((size_t)nnu + fc));
-    S_x = ldg(xs + 2 * ((size_t)nnu + fc) + 1);
-  }
-  for (int k = 1; k < nz; ++k) {
-    const R chi = chi_x, S = S_x;
-    if (k + 1 < nz) {
-      const size_t kf = (size_t)(k + 1) * nnu + fc;
-      chi_x = ldg(xs + 2 * kf);
-      S_x = ldg(xs + 2 * kf + 1);
-    }
-    const R dz = (R)ldc(dzt + 2 * (k - 1));
+  auto down_step = [&](int k, R chi, R S, R dz) {
     const R base = dz * (chi_p + chi);
     const R rb = PL<R>::div((R)1, base);
     const R dS = S - S_p;
@@ -433,7 +450,7 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
     }
     if (fin) {
       const size_t kf = (size_t)k * nnu + f;
-      stg(jm + kf, jac);
+      stg(jm + kf, (R)jac);
       if (PM) {
         const R rc = PL<R>::div((R)1, chi);
         stg(dxs + kf, -(S * rc) * sa + dz * sc);
@@ -442,6 +459,63 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
     }
     chi_p = chi;
     S_p = S;
+  };
+  if (fused) {
+    // chi and S of kFusedDepths depths at a time from the opacity, made here
+    // (and kept for the second sweep): the table reads of one wave overlap
+    // the recursion arithmetic of the others
+    const R* __restrict__ Vt = FTab<R>::V(C);
+    const double* __restrict__ coef = (const double*)C.coef;
+    const int ntr = C.ntr;
+    for (int k0 = 0; k0 < nz; k0 += kFusedDepths) {
+      R gc[kFusedDepths], gs[kFusedDepths], gd[kFusedDepths];
+#pragma unroll
+      for (int u = 0; u < kFusedDepths; ++u)
+        gd[u] = (R)ldc(dzt + 2 * max(min(k0 + u, nz - 1) - 1, 0));
+      opacity_group<R, kFusedDepths>(C, chunk, k0, nz, nnu, fin, fc, Vt, coef, ntr, gc, gs);
+#pragma unroll
+      for (int u = 0; u < kFusedDepths; ++u) {
+        const int k = k0 + u;
+        if (k == 0) {
+          chi_p = gc[0];
+          S_p = gs[0];
+        } else if (k < nz) {
+          down_step(k, gc[u], gs[u], gd[u]);
+        }
+      }
+    }
+  } else {
+    chi_p = ldg(xs + 2 * (size_t)fc);
+    S_p = ldg(xs + 2 * (size_t)fc + 1);
+    // segment k-1 -> k has thickness dz[k-1]
+    R cc[U], cs[U], nc[U], ns[U], cd[U], nd[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = min(1 + u, nz - 1);
+      const size_t kf = (size_t)k * nnu + fc;
+      cc[u] = ldg(xs + 2 * kf);
+      cs[u] = ldg(xs + 2 * kf + 1);
+      cd[u] = (R)ldc(dzt + 2 * max(k - 1, 0));
+    }
+    for (int k0 = 1; k0 < nz; k0 += U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = min(k0 + U + u, nz - 1);
+        const size_t kf = (size_t)k * nnu + fc;
+        nc[u] = ldg(xs + 2 * kf);
+        ns[u] = ldg(xs + 2 * kf + 1);
+        nd[u] = (R)ldc(dzt + 2 * max(k - 1, 0));
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (k0 + u < nz) down_step(k0 + u, cc[u], cs[u], cd[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        cc[u] = nc[u];
+        cs[u] = ns[u];
+        cd[u] = nd[u];
+      }
+    }
   }
 
   // ---- sweep 2: outgoing rays, bottom -> top (I+ = B at the bottom) ----
@@ -456,7 +530,7 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
       I[m] = Bb;
       jp = fmar(wm2d[m], (double)Bb, jp);
     }
-    stage_put<KF>(tJ, nz - 1, lane, ldg(jm + kf) + jp);
+    stage_put<KF>(tJ, nz - 1, lane, (double)ldg(jm + kf) + jp);
     if (PM) {  // bottom: ingoing-ray derivatives only
       stage_put<KF>(tX, nz - 1, lane, (double)ldg(dxs + kf));
       stage_put<KF>(tE, nz - 1, lane, (double)ldg(des + kf));
@@ -469,34 +543,7 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
       }
     }
   }
-  // prefetched: chi, S, Jm (and the ingoing derivatives) of the next depth up
-  R chi_c = 0, S_c = 0, dX_c = 0, dE_c = 0;
-  double jm_c = 0.0;
-  if (nz >= 2) {
-    const size_t kf = (size_t)(nz - 2) * nnu + fc;
-    chi_c = ldg(xs + 2 * kf);
-    S_c = ldg(xs + 2 * kf + 1);
-    jm_c = ldg(jm + kf);
-    if (PM) {
-      dX_c = ldg(dxs + kf);
-      dE_c = ldg(des + kf);
-    }
-  }
-  for (int k = nz - 2; k >= 0; --k) {
-    R chi_y = 0, S_y = 0, dX_y = 0, dE_y = 0;
-    double jm_y = 0.0;
-    if (k > 0) {
-      const size_t kf = (size_t)(k - 1) * nnu + fc;
-      chi_y = ldg(xs + 2 * kf);
-      S_y = ldg(xs + 2 * kf + 1);
-      jm_y = ldg(jm + kf);
-      if (PM) {
-        dX_y = ldg(dxs + kf);
-        dE_y = ldg(des + kf);
-      }
-    }
-    const R chi = chi_c, S = S_c;
-    const R dz = (R)ldc(dzt + 2 * k);
+  auto up_step = [&](int k, R chi, R S, double jm_k, R dX_k, R dE_k, R dz) {
     const R base = dz * (chi + chi_n);
     const R rb = PL<R>::div((R)1, base);
     const R dS = S - S_n;
@@ -516,11 +563,11 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
         sc += (wm2[m] * i2mu[m]) * (e * (S_n - Iup) - (S_n - S) * bx);
       }
     }
-    stage_put<KF>(tJ, k, lane, jm_c + jp);
+    stage_put<KF>(tJ, k, lane, jm_k + jp);
     if (PM) {
       const R rc = PL<R>::div((R)1, chi);
-      stage_put<KF>(tX, k, lane, (double)dX_c + (double)(-(S * rc) * sa + dz * sc));
-      stage_put<KF>(tE, k, lane, (double)dE_c + (double)(sa * rc));
+      stage_put<KF>(tX, k, lane, (double)dX_k + (double)(-(S * rc) * sa + dz * sc));
+      stage_put<KF>(tE, k, lane, (double)dE_k + (double)(sa * rc));
     }
     if (k % KF == 0) {
       stage_flush<KF>(tJ, C.JT, k, nz, f0, nnu, lane);
@@ -531,11 +578,46 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
     }
     chi_n = chi;
     S_n = S;
-    chi_c = chi_y;
-    S_c = S_y;
-    jm_c = jm_y;
-    dX_c = dX_y;
-    dE_c = dE_y;
+  };
+  {
+    // block b covers depths k0, k0 - 1, ..., k0 - U + 1 (clamped at 0)
+    // segment k -> k+1 has thickness dz[k]
+    R cc[U], cs[U], nc[U], ns[U], cx[U], ce[U], nx[U], ne[U], cd[U], nd[U];
+    double cj[U], nj[U];
+    auto load = [&](int k0, R* c_, R* s_, double* j_, R* x_, R* e_, R* d_) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = max(k0 - u, 0);
+        const size_t kf = (size_t)k * nnu + fc;
+        d_[u] = (R)ldc(dzt + 2 * k);
+        c_[u] = ldg(xs + 2 * kf);
+        s_[u] = ldg(xs + 2 * kf + 1);
+        j_[u] = (double)ldg(jm + kf);
+        if (PM) {
+          x_[u] = ldg(dxs + kf);
+          e_[u] = ldg(des + kf);
+        } else {
+          x_[u] = (R)0;
+          e_[u] = (R)0;
+        }
+      }
+    };
+    load(nz - 2, cc, cs, cj, cx, ce, cd);
+    for (int k0 = nz - 2; k0 >= 0; k0 -= U) {
+      load(k0 - U, nc, ns, nj, nx, ne, nd);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (k0 - u >= 0) up_step(k0 - u, cc[u], cs[u], cj[u], cx[u], ce[u], cd[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        cd[u] = nd[u];
+        cc[u] = nc[u];
+        cs[u] = ns[u];
+        cj[u] = nj[u];
+        cx[u] = nx[u];
+        ce[u] = ne[u];
+      }
+    }
   }
 }
 
@@ -745,7 +827,8 @@ static void launch_formal_scan_mu(int nmu, hipStream_t s, const ColDev* cols, co
 // group's tiles; a wave whose column is idle or in the other mode returns.
 template <typename R, bool PM, int NMU>
 __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
-                                                const Tile* __restrict__ tiles, int ntiles) {
+                                                const Tile* __restrict__ tiles, int ntiles,
+                                                int fused) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int tid = blockIdx.x * (blockDim.x >> 6) + wave;
@@ -756,20 +839,20 @@ __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
   const int mode = uni(C.st->mode);
   if (mode != (PM ? kModeNewton : kModeF)) return;
   if (uni(C.st->cur_prec) != (sizeof(R) == sizeof(float) ? NLTE_FP32_FORM : NLTE_FP64)) return;
-  constexpr int KF = StageDepths<PM>::value;
+  constexpr int KF = StageDepths<R, PM>::value;
   constexpr int NT = PM ? 3 : 1;  // staged outputs: J (and the two derivatives)
   extern __shared__ double stage[];  // [waves per block][NT * KF * 64]
-  formal_tile<R, PM, NMU>(C, chunk, lane, stage + wave * (NT * KF * kWave));
+  formal_tile<R, PM, NMU>(C, chunk, lane, stage + wave * (NT * KF * kWave), fused != 0);
 }
 
 template <typename R, bool PM>
 static void launch_formal_mu(int nmu, int wpb, hipStream_t s, const ColDev* cols,
-                             const Tile* tiles, int ntiles) {
+                             const Tile* tiles, int ntiles, int fused) {
   const int blocks = (ntiles + wpb - 1) / wpb;
-  const size_t lds = (size_t)wpb * (PM ? 3 : 1) * StageDepths<PM>::value * kWave * sizeof(double);
+  const size_t lds = (size_t)wpb * (PM ? 3 : 1) * StageDepths<R, PM>::value * kWave * sizeof(double);
   switch (nmu) {
 #define NLTE_FORMAL_CASE(M) \
-  case M: k_formal<R, PM, M><<<blocks, 64 * wpb, lds, s>>>(cols, tiles, ntiles); break;
+  case M: k_formal<R, PM, M><<<blocks, 64 * wpb, lds, s>>>(cols, tiles, ntiles, fused); break;
     NLTE_FORMAL_CASE(1) NLTE_FORMAL_CASE(2) NLTE_FORMAL_CASE(3) NLTE_FORMAL_CASE(4)
     NLTE_FORMAL_CASE(5) NLTE_FORMAL_CASE(6) NLTE_FORMAL_CASE(7) NLTE_FORMAL_CASE(8)
 #undef NLTE_FORMAL_CASE
@@ -794,7 +877,10 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
   s = u;
 }
 
-template <typename TB>  // table precision: double, or float for FP32-form columns
+// TB: table precision (float for FP32-form columns).  J stays FP64 here: in
+// the FP32 form a J rounded to FP32 before these sums sets a noise floor on
+// F that doubled the share of columns needing the FP64 fallback.
+template <typename TB>
 __device__ __forceinline__ void rates_sum(const ColDev& C, int t, int k0, const TB* __restrict__ VTt,
                                           const TB* __restrict__ EbfTt);
 
@@ -829,12 +915,12 @@ __device__ __forceinline__ void rates_sum(const ColDev& C, int sg, int k0, const
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const size_t o = (size_t)(q + u) * nz;
-        s[u] = fma(cw[q + u] * (double)ldg(V + o), ldg(J + o), s[u]);
+        s[u] = fma(cw[q + u] * (double)ldg(V + o), (double)ldg(J + o), s[u]);
       }
     }
     for (; q < wl; ++q) {
       const size_t o = (size_t)q * nz;
-      s[0] = fma(cw[q] * (double)ldg(V + o), ldg(J + o), s[0]);
+      s[0] = fma(cw[q] * (double)ldg(V + o), (double)ldg(J + o), s[0]);
     }
     stg(dst, (s[0] + s[1]) + (s[2] + s[3]));
     stg(dst + 1, 0.0);
@@ -847,14 +933,14 @@ __device__ __forceinline__ void rates_sum(const ColDev& C, int sg, int k0, const
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const size_t o = (size_t)(q + u) * nz;
-        const double x = (cw[q + u] * A[q + u]) * ldg(J + o);
+        const double x = (cw[q + u] * A[q + u]) * (double)ldg(J + o);
         s1[u] += x;
         s2[u] = fma(x, (double)ldg(E + o), s2[u]);
       }
     }
     for (; q < wl; ++q) {
       const size_t o = (size_t)q * nz;
-      const double x = (cw[q] * A[q]) * ldg(J + o);
+      const double x = (cw[q] * A[q]) * (double)ldg(J + o);
       s1[0] += x;
       s2[0] = fma(x, (double)ldg(E + o), s2[0]);
     }
@@ -1110,7 +1196,9 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
     const Tile* tl = bw.tiles + G.first;
-    if (G.prec == NLTE_FP32_FORM) launch_opacity<float>(bw.opac_depths, G.count, bw.maxnz, s, bw.cols, tl);
+    const bool fused32 = !G.scan && G.count >= kFuseMinTiles;  // made inside the formal solution
+    if (G.prec == NLTE_FP32_FORM && !fused32)
+      launch_opacity<float>(bw.opac_depths, G.count, bw.maxnz, s, bw.cols, tl);
     if (G.prec == NLTE_FP64 || bw.fallback)
       launch_opacity<double>(bw.opac_depths, G.count, bw.maxnz, s, bw.cols, tl);
   }
@@ -1119,6 +1207,7 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     const TileGroup& G = bw.groups[g];
     const int nb = bw.formal_wpb;
     const Tile* tl = bw.tiles + G.first;
+    const int fused = G.count >= kFuseMinTiles;  // FP32 recursion only
     if (G.scan) {
       if (G.prec == NLTE_FP32_FORM) {
         launch_formal_scan_mu<float, false>(G.nmu, s, bw.cols, tl, G.count);
@@ -1131,12 +1220,12 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
       continue;
     }
     if (G.prec == NLTE_FP32_FORM) {
-      launch_formal_mu<float, false>(G.nmu, nb, s, bw.cols, tl, G.count);
-      if (bw.any_newton) launch_formal_mu<float, true>(G.nmu, nb, s, bw.cols, tl, G.count);
+      launch_formal_mu<float, false>(G.nmu, nb, s, bw.cols, tl, G.count, fused);
+      if (bw.any_newton) launch_formal_mu<float, true>(G.nmu, nb, s, bw.cols, tl, G.count, fused);
     }
     if (G.prec == NLTE_FP64 || bw.fallback) {
-      launch_formal_mu<double, false>(G.nmu, nb, s, bw.cols, tl, G.count);
-      if (bw.any_newton) launch_formal_mu<double, true>(G.nmu, nb, s, bw.cols, tl, G.count);
+      launch_formal_mu<double, false>(G.nmu, nb, s, bw.cols, tl, G.count, 0);
+      if (bw.any_newton) launch_formal_mu<double, true>(G.nmu, nb, s, bw.cols, tl, G.count, 0);
     }
   }
   if (ev) hipEventRecord(ev[2], s);

@@ -3,7 +3,8 @@
 - the 11-level stress column (256 depths, ~4000 frequencies, 8 angles):
   residual, J and rates against the oracle, FP64 and FP32 form;
 - the 4096-column batch through a graph-replayed, tuned residual plan (the
-  F-only loop of the benchmark): sampled columns against the oracle;
+  F-only loop of the benchmark): sampled columns against the oracle, and
+  bit-identical to the same columns evaluated alone;
 - the batched FP32-form solve of all 4096 columns (the benchmark step):
   sampled columns' populations against the oracle's FP64 root to 1e-4."""
 import numpy as np
@@ -65,6 +66,11 @@ def test_batch_plan_sampled_columns(ctx):
         tb = O.setup(probs[i])
         ref = O.residual(tb, to_np(ns[i]))
         assert np.max(np.abs(to_np(Fs[i]) - ref.F) / ref.G) < 1e-4, i
+        # alone, the column's opacity comes from the separate opacity kernel;
+        # in the full batch it is made inside the formal-solution kernel:
+        # the same bits either way
+        alone = cols[i].residual(ns[i])["F"]
+        assert np.array_equal(to_np(alone), to_np(Fs[i])), i
     plan.close()
 
 
