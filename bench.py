@@ -38,7 +38,7 @@ OPS_PER_DP = 10.0 + 0.5 * 4 + 0.5 * 4
 # this workload, each scaled by the same counter on a plain copy kernel; valid
 # only for the kernel source they were taken on (hash of its files).
 TRAFFIC = {
-    "batch6": {"source": "27a2a3cd0cc1a8eb", "bytes_per_launch": 1.217e9,
+    "batch6": {"source": "baa293c864650ce9", "bytes_per_launch": 1.217e9,
                "read": 1.136e12 / 1632, "written": 8.496e11 / 1632},
 }
 KERNEL_SOURCES = ["paper_2406_17234_amd/csrc/nlte_residual.hip",

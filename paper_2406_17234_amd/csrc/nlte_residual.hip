@@ -6,23 +6,32 @@
 // (Eqs. residuals_1, residuals_2) and, in Newton mode, the block-Jacobi
 // preconditioner (Sect. 2.5.2 first solution, App. A.2).
 //
-// Work decomposition.
-//   k_formal : one wavefront per chunk of 64 consecutive frequencies of one
-//              column, one lane per frequency carrying all 2 x nmu rays
-//              through the depth recursion in registers.  The first sweep
-//              runs top -> bottom (ingoing rays) and parks their share of J
-//              in a [k][nu] scratch row; the second runs bottom -> top
-//              (outgoing rays) and writes J.  In Newton mode it also writes
-//              the angle-averaged local intensity derivatives.
-//   k_rates  : one lane per depth, one wavefront per (column, transition,
-//              64 depths): each lane sums its transition window in frequency
-//              order, so rate integrals need no cross-lane reductions and do
-//              not depend on how columns are batched.
-//   k_precond: Newton mode only; one lane per depth accumulates the
-//              radiative part of the diagonal Jacobian blocks over a segment
-//              of frequencies.
+// Work decomposition (one launch of each per residual call of a batch):
+//   k_coef    : one block per column; the level coefficients of the
+//               evaluation, transition-major, so that one scalar load brings
+//               a transition's values for several depths.
+//   k_opacity : chi and S of a 64-frequency chunk, a few depths per wave;
+//               launches over few chunks spread a chunk's depth groups over
+//               waves.  Large FP32 launches skip it: the first sweep of
+//               k_formal makes the same opacity itself.
+//   k_formal  : one wavefront per chunk of 64 consecutive frequencies of one
+//               column, one lane per frequency carrying all 2 x nmu rays
+//               through the depth recursion in registers.  The first sweep
+//               runs top -> bottom (ingoing rays) and parks their share of J
+//               in a [k][nu] scratch row; the second runs bottom -> top
+//               (outgoing rays) and writes J.  In Newton mode it also writes
+//               the angle-averaged local intensity derivatives.
+//   k_formal_scan: the same for columns created with NLTE_DEPTH_SCAN, as
+//               parallel scans of affine maps over depth (one workgroup per
+//               frequency, one thread per depth).
+//   k_depthwork: one lane per depth, one wavefront per (column, frequency
+//               segment, 64 depths): rate integrals summed in frequency order
+//               (no cross-lane reductions, independent of batching), and in
+//               Newton mode the preconditioner pair sums.
 //   k_assemble: rates, rate-equation residual, conservation rows, scaled
-//              residual, preconditioner blocks; one block per column.
+//               residual per depth; one block per (column, 32 depths).
+//   k_pblock  : Newton mode; the preconditioner blocks from the total rates
+//               and the pair sums.
 #include "nlte_internal.h"
 
 namespace nlte {

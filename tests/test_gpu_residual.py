@@ -76,12 +76,17 @@ def test_residual_fp32_form_close_to_oracle(ctx, name):
     n = perturbed(tb.nstar, seed=2, scale=0.2)
     ref = O.residual(tb, n)
     col = _column(ctx, prob, prec=1)
-    out = col.residual(to_dev(n), want_J=True, want_R=True)
+    out = col.residual(to_dev(n), want_J=True, want_R=True, want_P=True)
     J = to_np(out["J"])
     big = ref.J > 1e-30 * ref.J.max()
     assert maxrel(J[big], ref.J[big]) < 5e-5
     R = to_np(out["R"])
     assert maxrel(R[..., 1], ref.R_ul) < 5e-5
+    # preconditioner blocks from the FP32 recursion's derivatives
+    refP = O.residual(tb, n, want_P=True).P
+    P = to_np(out["P"])
+    for k in range(tb.nz):
+        assert np.max(np.abs(P[k] - refP[k])) <= 1e-4 * np.max(np.abs(refP[k])), k
 
 
 def test_jvp_matches_oracle(ctx):
