@@ -146,15 +146,21 @@ typedef struct {
 } nlte_solve_stats;
 
 /* Kernel timings accumulated by solves on a context while profiling is on
- * (HIP events on the solve's stream around each launch). */
+ * (HIP events on the solve's stream around each phase).  The formal-solution
+ * launches of one residual call run on up to four streams at once (F mode,
+ * Newton mode, and the FP64 ones of fallback columns); formal_ms is the
+ * phase's duration, formal_f_ms that of the F-mode launches in the columns'
+ * own precision, which run on the solve's stream. */
 typedef struct {
   int64_t steps;             /* solver steps (one residual per active column)   */
   int64_t formal_launches;   /* depth-recursion (formal-solution) launches      */
-  double formal_ms;          /* their summed duration                           */
+  double formal_ms;          /* duration of the formal-solution phase           */
   double depth_ms;           /* rate integrals + preconditioner pair sums       */
   double assemble_ms;        /* residual/preconditioner assembly                */
   double solver_ms;          /* Krylov/Newton step launches                     */
   double opacity_ms;         /* level coefficients + opacity/source function    */
+  int64_t formal_f_launches; /* F-mode formal-solution launches on the stream   */
+  double formal_f_ms;        /* their summed duration                           */
 } nlte_profile;
 
 /* Fills opts with the defaults listed above. */

@@ -229,10 +229,15 @@ struct BatchWork {
 
 // Residual launches for a batch (level coefficients and opacity, formal
 // solution of every tile, rate integrals and preconditioner pair sums,
-// assembly).  ev, if not NULL, holds five events: before the coefficients,
-// before the formal-solution launches, after them, after the lane-per-depth
-// work and after assembly.
+// assembly).  ev, if not NULL, holds seven events, all recorded on s:
+// [0] before the coefficients, [1] before the formal-solution launches,
+// [2] after them (all streams joined), [3] after the lane-per-depth work,
+// [4] after assembly, [5] left to the caller, [6] after the F-mode
+// formal-solution launches that run on s itself.
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev = nullptr);
+// Creates the calling thread's side streams for the current device (done
+// lazily by launch_residual; call it before capturing launches into a graph).
+hipError_t residual_streams_init();
 
 // Solver driver pieces (nlte_solver.hip) shared by the batch solve and the
 // server: option checks, per-column initialisation (n0[c] NULL: LTE), one

@@ -191,6 +191,7 @@ extern "C" nlte_status nlte_plan_create(nlte_ctx* ctx, nlte_column* const* cols,
   if (flags & NLTE_PLAN_GRAPH) {
     // capture on a stream of the plan's own, ordered after the setup above
     PLAN_TRY(hipStreamSynchronize(s));
+    PLAN_TRY(residual_streams_init());
     PLAN_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
     PLAN_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
     const hipError_t le = P->launch(P->cap_stream);

@@ -1198,6 +1198,41 @@ static void launch_opacity(int kg, int ntiles, int maxnz, hipStream_t s, const C
   }
 }
 
+// Side streams of the formal-solution phase, one set per host thread and
+// device (a thread's launches are ordered by its own events, so threads
+// never share an event between a record and the matching wait).  Created at
+// the default priority, outside any graph capture (residual_streams_init).
+namespace {
+struct SideStreams {
+  int ready = 0;
+  hipStream_t st[3];
+  hipEvent_t fork, join[3];
+};
+thread_local SideStreams tls_side[64];
+}  // namespace
+
+static hipError_t side_streams(SideStreams** out) {
+  int d = 0;
+  hipError_t e = hipGetDevice(&d);
+  if (e != hipSuccess) return e;
+  SideStreams& S = tls_side[d & 63];
+  if (!S.ready) {
+    for (int i = 0; i < 3; ++i) {
+      if ((e = hipStreamCreateWithFlags(&S.st[i], hipStreamNonBlocking)) != hipSuccess) return e;
+      if ((e = hipEventCreateWithFlags(&S.join[i], hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    if ((e = hipEventCreateWithFlags(&S.fork, hipEventDisableTiming)) != hipSuccess) return e;
+    S.ready = 1;
+  }
+  *out = &S;
+  return hipSuccess;
+}
+
+hipError_t residual_streams_init() {
+  SideStreams* S = nullptr;
+  return side_streams(&S);
+}
+
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   if (ev) hipEventRecord(ev[0], s);
   const int nblk = bw.act ? bw.nact : bw.ncol;
@@ -1211,31 +1246,54 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     if (G.prec == NLTE_FP64 || bw.fallback)
       launch_opacity<double>(bw.opac_depths, G.count, bw.maxnz, s, bw.cols, tl);
   }
+  // Formal solutions: the F-mode launch of each group in its own precision
+  // on s, the Newton-mode launches and the FP64 launches of FP32-form groups
+  // (fallback columns) on side streams.  The launches of a residual call
+  // touch disjoint columns (each checks its columns' mode and precision), so
+  // they may overlap: late in a batch most of them cover a few columns each
+  // and would otherwise queue up their depth-recursion latencies.
+  SideStreams* SS = nullptr;
+  {
+    const hipError_t e = side_streams(&SS);
+    if (e != hipSuccess) return e;
+  }
   if (ev) hipEventRecord(ev[1], s);
+  hipEventRecord(SS->fork, s);
+  for (int i = 0; i < 3; ++i) hipStreamWaitEvent(SS->st[i], SS->fork, 0);
+  const hipStream_t sNewton = SS->st[0], sF64 = SS->st[1], sN64 = SS->st[2];
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
     const int nb = bw.formal_wpb;
     const Tile* tl = bw.tiles + G.first;
     const int fused = G.count >= kFuseMinTiles;  // FP32 recursion only
+    const bool f32 = G.prec == NLTE_FP32_FORM;
+    // FP64 launches: on s / sNewton for FP64 groups, on sF64 / sN64 for the
+    // fallback columns of FP32-form groups
+    const hipStream_t dF = f32 ? sF64 : s, dN = f32 ? sN64 : sNewton;
     if (G.scan) {
-      if (G.prec == NLTE_FP32_FORM) {
+      if (f32) {
         launch_formal_scan_mu<float, false>(G.nmu, s, bw.cols, tl, G.count);
-        if (bw.any_newton) launch_formal_scan_mu<float, true>(G.nmu, s, bw.cols, tl, G.count);
+        if (bw.any_newton) launch_formal_scan_mu<float, true>(G.nmu, sNewton, bw.cols, tl, G.count);
       }
-      if (G.prec == NLTE_FP64 || bw.fallback) {
-        launch_formal_scan_mu<double, false>(G.nmu, s, bw.cols, tl, G.count);
-        if (bw.any_newton) launch_formal_scan_mu<double, true>(G.nmu, s, bw.cols, tl, G.count);
+      if (!f32 || bw.fallback) {
+        launch_formal_scan_mu<double, false>(G.nmu, dF, bw.cols, tl, G.count);
+        if (bw.any_newton) launch_formal_scan_mu<double, true>(G.nmu, dN, bw.cols, tl, G.count);
       }
       continue;
     }
-    if (G.prec == NLTE_FP32_FORM) {
+    if (f32) {
       launch_formal_mu<float, false>(G.nmu, nb, s, bw.cols, tl, G.count, fused);
-      if (bw.any_newton) launch_formal_mu<float, true>(G.nmu, nb, s, bw.cols, tl, G.count, fused);
+      if (bw.any_newton) launch_formal_mu<float, true>(G.nmu, nb, sNewton, bw.cols, tl, G.count, fused);
     }
-    if (G.prec == NLTE_FP64 || bw.fallback) {
-      launch_formal_mu<double, false>(G.nmu, nb, s, bw.cols, tl, G.count, 0);
-      if (bw.any_newton) launch_formal_mu<double, true>(G.nmu, nb, s, bw.cols, tl, G.count, 0);
+    if (!f32 || bw.fallback) {
+      launch_formal_mu<double, false>(G.nmu, nb, dF, bw.cols, tl, G.count, 0);
+      if (bw.any_newton) launch_formal_mu<double, true>(G.nmu, nb, dN, bw.cols, tl, G.count, 0);
     }
+  }
+  if (ev) hipEventRecord(ev[6], s);  // end of the F-mode launches on s
+  for (int i = 0; i < 3; ++i) {
+    hipEventRecord(SS->join[i], SS->st[i]);
+    hipStreamWaitEvent(s, SS->join[i], 0);
   }
   if (ev) hipEventRecord(ev[2], s);
   if (bw.nrate > 0) k_depthwork<<<bw.nrate, 64, 0, s>>>(bw.cols, bw.rate_work, bw.nrate);

@@ -803,7 +803,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   const bool prof = ctx->prof_on != 0;
   std::vector<hipEvent_t> ev;
   if (prof) {
-    ev.resize(6 * check_every);
+    ev.resize(7 * check_every);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
   }
   long step = 0;
@@ -815,7 +815,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   nlte_status loop_st = NLTE_OK;
   while (step < max_steps) {
     for (int r = 0; r < check_every; ++r, ++step) {
-      hipEvent_t* e = prof ? &ev[6 * r] : nullptr;
+      hipEvent_t* e = prof ? &ev[7 * r] : nullptr;
       hipError_t he = launch_residual(bw, s, e);
       k_solver_step<<<bw.act ? bw.nact : ncol, kThreads, 0, s>>>(b.cols, bw.act, b.done);
       if (prof) hipEventRecord(e[5], s);
@@ -830,10 +830,13 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
     HIP_TRY(hipStreamSynchronize(s));
     if (prof) {
       for (int r = 0; r < check_every; ++r) {
-        float t[5];
-        for (int q = 0; q < 5; ++q) HIP_TRY(hipEventElapsedTime(&t[q], ev[6 * r + q], ev[6 * r + q + 1]));
+        float t[5], tf;
+        for (int q = 0; q < 5; ++q) HIP_TRY(hipEventElapsedTime(&t[q], ev[7 * r + q], ev[7 * r + q + 1]));
+        HIP_TRY(hipEventElapsedTime(&tf, ev[7 * r + 1], ev[7 * r + 6]));
         ctx->prof.steps += 1;
         ctx->prof.formal_launches += 2 * bw.ngroup * (bw.fallback ? 2 : 1);
+        ctx->prof.formal_f_launches += bw.ngroup;
+        ctx->prof.formal_f_ms += tf;
         ctx->prof.opacity_ms += t[0];
         ctx->prof.formal_ms += t[1];
         ctx->prof.depth_ms += t[2];

@@ -71,7 +71,8 @@ class SolveStats(C.Structure):
 class Profile(C.Structure):
     _fields_ = [("steps", C.c_int64), ("formal_launches", C.c_int64), ("formal_ms", C.c_double),
                 ("depth_ms", C.c_double), ("assemble_ms", C.c_double), ("solver_ms", C.c_double),
-                ("opacity_ms", C.c_double)]
+                ("opacity_ms", C.c_double), ("formal_f_launches", C.c_int64),
+                ("formal_f_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
