@@ -34,12 +34,13 @@ PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
 # reciprocal (shared by the two rays of an angle), transcendental at 1/4 rate
 OPS_PER_DP = 10.0 + 0.5 * 4 + 0.5 * 4
 
-# HBM bytes per k_formal launch from FETCH_SIZE / WRITE_SIZE counter runs of
-# this workload, each scaled by the same counter on a plain copy kernel; valid
-# only for the kernel source they were taken on (hash of its files).
+# HBM bytes per F-mode k_formal launch (the roofline kernel) from FETCH_SIZE /
+# WRITE_SIZE counter runs of this workload, each scaled by the same counter on
+# a plain copy kernel; valid only for the kernel source they were taken on
+# (hash of its files).
 TRAFFIC = {
-    "batch6": {"source": "baa293c864650ce9", "bytes_per_launch": 1.217e9,
-               "read": 1.136e12 / 1632, "written": 8.496e11 / 1632},
+    "batch6": {"source": "f359b41c7c9dbdb2", "bytes_per_launch": 4.1385e9,
+               "read": 1.00938e12 / 408, "written": 6.7914e11 / 408},
 }
 KERNEL_SOURCES = ["paper_2406_17234_amd/csrc/nlte_residual.hip",
                   "paper_2406_17234_amd/csrc/nlte_internal.h"]
