@@ -127,8 +127,9 @@ typedef struct {
                           * preconditioned residual step).  0: no limit (default) */
   int32_t fp64_fallback; /* FP32-form columns that have not converged after this
                           * many Newton iterations continue with FP64 formal
-                          * solutions from their current iterate (0: never,
-                          * default 0)                                        */
+                          * solutions: from their current iterate when its
+                          * max |F|/gross-rate is at most 1e-2, else from their
+                          * initial populations (0: never, default 0)         */
 } nlte_solve_opts;
 
 typedef struct {

@@ -723,7 +723,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
 #undef UP
   if (e == hipSuccess) e = hipMemsetAsync(C.st, 0, sizeof(ColState), stream);
   if (e != hipSuccess) {
-    hipFree(col->arena);
+    (void)hipFree(col->arena);
     delete col;
     return set_err(NLTE_E_DEVICE, "upload failed: %s", hipGetErrorString(e));
   }
@@ -757,8 +757,8 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   if (e == hipSuccess) e = hipMemcpyAsync(col->d, &C, sizeof(ColDev), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
-    if (col->d) hipFree(col->d);
-    hipFree(col->arena);
+    if (col->d) (void)hipFree(col->d);
+    (void)hipFree(col->arena);
     delete col;
     return set_err(NLTE_E_DEVICE, "column setup failed: %s", hipGetErrorString(e));
   }
@@ -784,9 +784,9 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
 
 extern "C" void nlte_column_destroy(nlte_column* col) {
   if (!col) return;
-  hipSetDevice(col->ctx->device);
-  if (col->d) hipFree(col->d);
-  if (col->arena) hipFree(col->arena);
+  (void)hipSetDevice(col->ctx->device);
+  if (col->d) (void)hipFree(col->d);
+  if (col->arena) (void)hipFree(col->arena);
   delete col;
 }
 
@@ -866,7 +866,7 @@ static nlte_status check_populations(nlte_column* col, const double* n_dev, hipS
     e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFreeAsync(flag, s);
+  (void)hipFreeAsync(flag, s);
   if (e != hipSuccess) return set_err(NLTE_E_DEVICE, "population check failed: %s", hipGetErrorString(e));
   if (h) return set_err(NLTE_E_NONFINITE, "populations must be finite and positive");
   return NLTE_OK;

@@ -893,8 +893,10 @@ template <typename TB>
 __device__ __forceinline__ void rates_sum(const ColDev& C, int t, int k0, const TB* __restrict__ VTt,
                                           const TB* __restrict__ EbfTt);
 
+// The tables follow the evaluation's precision, so that an FP32-form column
+// after its FP64 fallback evaluates the same F as an FP64 column.
 __device__ __forceinline__ void rates_item(const ColDev& C, int sg, int k0) {
-  if (uni(C.prec) == NLTE_FP32_FORM)
+  if (uni(C.st->cur_prec) == NLTE_FP32_FORM)
     rates_sum<float>(C, sg, k0, C.VTf, C.EbfTf);
   else
     rates_sum<double>(C, sg, k0, C.VT, C.EbfT);

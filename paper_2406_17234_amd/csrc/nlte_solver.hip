@@ -43,6 +43,12 @@ constexpr int kMaxM = 32;  // restart capacity allocated per column
 // Newton sequences on the 6-level chromosphere; 1e-3 sits in the middle.
 constexpr double kFp32Noise = 1e-3;
 constexpr double kEpsMach64 = 2.220446049250313e-16;
+// An FP32-form column that falls back to FP64 keeps its iterate when its
+// max |F|/gross-rate is at most this (on the 6-level batch these are mostly
+// columns stalled at the FP32 noise floor just above the tolerance, which
+// FP64 finishes in one or two Newton iterations); one further from the root
+// starts again from its initial populations.
+constexpr double kFallbackKeepRho = 1e-2;
 
 enum Phase : int { PH_IDLE = 0, PH_INIT = 1, PH_ARNOLDI = 2, PH_RESTART = 3, PH_LS = 4, PH_DONE = 5 };
 
@@ -152,14 +158,71 @@ __device__ void lu_solve(const double* A, const int* piv, double* x, int L) {
   }
 }
 
-// out = D^-1 P^-1 in (per depth), in/out may alias; D = diag(n).
-__device__ void apply_scaled_pinv(const ColDev& C, const double* in, double* out) {
+// The LU solve with the level count fixed at compile time, so that the
+// right-hand side stays in registers (atoms of up to 8 levels; larger blocks
+// take the general loop below, whose vector lives in private memory; fixing
+// those too raised the solver kernel's register count for every column).
+template <int L>
+__device__ __forceinline__ void pinv_depths(const ColDev& C, const double* in, double* out) {
+  for (int k = threadIdx.x; k < C.nz; k += kThreads) {
+    const double* A = C.LU + (size_t)k * L * L;
+    const int* piv = C.piv + k * L;
+    double x[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) x[i] = in[k * L + i];
+#pragma unroll
+    for (int c = 0; c < L; ++c) {
+      const int p = piv[c];
+      // swap x[c] and x[p] (p >= c) without a runtime register index
+      double xp = x[c];
+#pragma unroll
+      for (int r = c + 1; r < L; ++r)
+        if (r == p) xp = x[r];
+#pragma unroll
+      for (int r = c + 1; r < L; ++r)
+        if (r == p) x[r] = x[c];
+      x[c] = xp;
+    }
+#pragma unroll
+    for (int r = 1; r < L; ++r) {
+      double t = x[r];
+#pragma unroll
+      for (int c = 0; c < r; ++c) t -= A[r * L + c] * x[c];
+      x[r] = t;
+    }
+#pragma unroll
+    for (int r = L - 1; r >= 0; --r) {
+      double t = x[r];
+#pragma unroll
+      for (int c = r + 1; c < L; ++c) t -= A[r * L + c] * x[c];
+      x[r] = t / A[r * L + r];
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) out[k * L + i] = x[i] / C.n[k * L + i];
+  }
+}
+
+__device__ void pinv_depths_any(const ColDev& C, const double* in, double* out) {
   const int L = C.L;
   for (int k = threadIdx.x; k < C.nz; k += kThreads) {
     double x[kMaxLev];
     for (int i = 0; i < L; ++i) x[i] = in[k * L + i];
     lu_solve(C.LU + (size_t)k * L * L, C.piv + k * L, x, L);
     for (int i = 0; i < L; ++i) out[k * L + i] = x[i] / C.n[k * L + i];
+  }
+}
+
+// out = D^-1 P^-1 in (per depth), in/out may alias; D = diag(n).
+__device__ void apply_scaled_pinv(const ColDev& C, const double* in, double* out) {
+  switch (C.L) {
+    case 2: pinv_depths<2>(C, in, out); break;
+    case 3: pinv_depths<3>(C, in, out); break;
+    case 4: pinv_depths<4>(C, in, out); break;
+    case 5: pinv_depths<5>(C, in, out); break;
+    case 6: pinv_depths<6>(C, in, out); break;
+    case 7: pinv_depths<7>(C, in, out); break;
+    case 8: pinv_depths<8>(C, in, out); break;
+    default: pinv_depths_any(C, in, out); break;
   }
   __syncthreads();
 }
@@ -297,12 +360,16 @@ __device__ void accept_point(const ColDev& C, double* red, int* done_count) {
                         st->newton_it >= st->fp64_fallback && st->newton_it < st->maxiter;
   __syncthreads();  // every thread has read the state before thread 0 changes it
   if (fallback) {
-    // FP32 form not converging: start again from the initial populations
-    // with FP64 formal solutions (own rows, new P); an iterate the FP32
-    // Newton sequence wandered to is often a poor start
-    for (int i = threadIdx.x; i < C.N; i += kThreads) C.eval_n[i] = C.n_init[i];
-    if (C.has_sca)
-      for (int i = threadIdx.x; i < C.nz * C.nnu; i += kThreads) C.Jdag[i] = C.Bnu[i];
+    // FP32 form not converging: continue with FP64 formal solutions (own
+    // rows, new P), from the current iterate when it is close to the root,
+    // else from the initial populations (an iterate the FP32 Newton sequence
+    // wandered to is often a poor start).  eval_n and Jdag hold the current
+    // iterate and its J.
+    if (!(rho <= kFallbackKeepRho)) {
+      for (int i = threadIdx.x; i < C.N; i += kThreads) C.eval_n[i] = C.n_init[i];
+      if (C.has_sca)
+        for (int i = threadIdx.x; i < C.nz * C.nnu; i += kThreads) C.Jdag[i] = C.Bnu[i];
+    }
     if (threadIdx.x == 0) {
       st->cur_prec = NLTE_FP64;
       st->eps_mach = kEpsMach64;
@@ -354,16 +421,28 @@ __device__ void arnoldi(const ColDev& C, double* red, int* done_count) {
   for (int i = threadIdx.x; i < N; i += kThreads) w[i] = (C.F[i] - C.Fn[i]) * ieps;
   __syncthreads();
   apply_scaled_pinv(C, w, w);
-  // classical Gram-Schmidt, twice
+  // classical Gram-Schmidt, twice; the j + 1 dot products go to the waves
+  // four basis vectors at a time (lane-strided sums, then a wave reduction)
   __shared__ double h[kMaxM + 1];
-  double part[kMaxM + 1];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int i = 0; i <= j; ++i) part[i] = 0.0;
-    for (int q = threadIdx.x; q < N; q += kThreads) {
-      const double wq = w[q];
-      for (int i = 0; i <= j; ++i) part[i] += C.Vk[(size_t)i * N + q] * wq;
+    for (int i0 = 4 * wave; i0 <= j; i0 += 4 * (kThreads / 64)) {
+      const int ni = min(4, j + 1 - i0);
+      const double* v0 = C.Vk + (size_t)i0 * N;
+      double d[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int q = lane; q < N; q += 64) {
+        const double wq = w[q];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (u < ni) d[u] = fma(v0[(size_t)u * N + q], wq, d[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double t = warp_sum(d[u]);
+        if (lane == 0 && u < ni) h[i0 + u] = t;
+      }
     }
-    block_sums(part, j + 1, red, h);
+    __syncthreads();
     for (int q = threadIdx.x; q < N; q += kThreads) {
       double s = w[q];
       for (int i = 0; i <= j; ++i) s -= h[i] * C.Vk[(size_t)i * N + q];

@@ -160,3 +160,35 @@ def test_fp32_form_falls_back_to_fp64(ctx):
     # without the fallback the column stays in FP32 (and its stats say so)
     _, _, s0, _ = c32.solve(ftol=1e-6, rtol=1e-3, maxiter=3)
     assert s0["precision"] == nlte.FP32_FORM and s0["fp64_evals"] == 0
+
+
+def test_fp64_fallback_keeps_a_close_iterate(ctx):
+    """At the fallback an FP32-form iterate within max |F|/G <= 1e-2 of the
+    root is kept (FP64 then needs only a few Newton iterations), while one
+    further away starts again from LTE (as many FP64 iterations as a plain
+    FP64 solve).  ftol = 1e-12 is out of the FP32 form's reach, so the
+    fallback always triggers; both runs end at the FP64 root."""
+    from paper_2406_17234_amd import nlte
+    prob, tb, ref = oracle_root("chromo6_small", CASES["chromo6_small"])
+    c64 = nlte.Column(ctx, prob, precision=nlte.FP64)
+    _, _, s64, rc64 = c64.solve(ftol=1e-12, rtol=1e-6, maxiter=40)
+    assert rc64 == 0
+    c32 = nlte.Column(ctx, prob, precision=nlte.FP32_FORM)
+    rho = {}
+    for k in range(1, 13):
+        _, _, sk, _ = c32.solve(ftol=1e-12, rtol=1e-6, maxiter=k)
+        rho[k] = sk["rho_inf"]
+    print(rho, s64, flush=True)
+    far = [k for k in rho if rho[k] > 0.1]
+    close = [k for k in rho if rho[k] <= 1e-3]
+    assert far and close
+    for k, kept in ((max(far), False), (min(close), True)):
+        n, _, st, rc = c32.solve(ftol=1e-12, rtol=1e-6, maxiter=40, fp64_fallback=k)
+        print(k, kept, st, flush=True)
+        assert rc == 0 and st["precision"] == nlte.FP64
+        assert maxrel(to_np(n), ref.n) < 1e-10
+        fp64_its = st["newton_iters"] - k
+        if kept:
+            assert fp64_its < s64["newton_iters"]
+        else:
+            assert abs(fp64_its - s64["newton_iters"]) <= 1
