@@ -450,10 +450,10 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
     C.Vf = C.Bnuf = C.Ebff = C.VTf = C.EbfTf = nullptr;
   }
   C.coef = Lo.take<double>((size_t)nz * ncoef(ntr));
-  C.rseg = Lo.take<int4>(std::max(C.nrseg, 1));
-  C.pairs = Lo.take<int4>(std::max(C.npair, 1));
+  C.rseg = Lo.take<RSeg>(std::max(C.nrseg, 1));
+  C.pitem = Lo.take<PItem>(std::max(C.npitem, 1));
   C.pg_ptr = Lo.take<int>(L * L + 1);
-  C.pg_code = Lo.take<int>(4 * ntr + 4 * std::max(C.npair, 1));
+  C.pg_code = Lo.take<int>(4 * ntr + 4 * std::max(C.nment, 1));
   C.eval_n = Lo.take<double>(N);
   C.F = Lo.take<double>(N);
   C.G = Lo.take<double>(N);
@@ -466,7 +466,7 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.DchiT = Lo.take<double>(kf);
   C.DetaT = Lo.take<double>(kf);
   C.RJ = Lo.take<double>((size_t)nz * std::max(C.nrseg, 1) * 2);
-  C.M = Lo.take<double>((size_t)nz * std::max(C.npair, 1) * 2);
+  C.M = Lo.take<double>((size_t)nz * std::max(C.nment, 1) * 2);
   C.P = Lo.take<double>((size_t)nz * L * L);
   C.LU = Lo.take<double>((size_t)nz * L * L);
   C.Fsave = Lo.take<double>(nz);
@@ -591,24 +591,58 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   }
   // frequency segments of the rate integrals and of the window intersections
   const int seg_len = scan ? kSegLenScan : kSegLen;
-  std::vector<int4> rseg;
+  std::vector<RSeg> rseg;
   for (int t = 0; t < ntr; ++t) {
     tr[t].sfirst = (int)rseg.size();
     for (int a = tr[t].wlo; a < tr[t].whi; a += seg_len)
-      rseg.push_back(make_int4(t, a, std::min(a + seg_len, tr[t].whi), 0));
+      rseg.push_back(RSeg{t, a, std::min(a + seg_len, tr[t].whi), a - tr[t].wlo, tr[t].voff,
+                          tr[t].cwoff, 0, 0});
     tr[t].nseg = (int)rseg.size() - tr[t].sfirst;
   }
   C.nrseg = (int)rseg.size();
-  std::vector<int4> pairs;
-  for (int t = 0; t < ntr; ++t)
-    for (int u = 0; u < ntr; ++u) {
-      const int a = std::max(tr[t].wlo, tr[u].wlo), b = std::min(tr[t].whi, tr[u].whi);
-      for (int q = a; q < b; q += seg_len) pairs.push_back(make_int4(t, u, q, std::min(q + seg_len, b)));
+  // pair-sum pieces: cut at every window edge, so that each piece lies
+  // inside or outside every window; s transitions cover a piece, which gets
+  // s^2 entries (t, t') and runs as blocks of at most kPairBlk^2 of them
+  std::vector<int> cuts;
+  for (int t = 0; t < ntr; ++t) {
+    cuts.push_back(tr[t].wlo);
+    cuts.push_back(tr[t].whi);
+  }
+  std::sort(cuts.begin(), cuts.end());
+  cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
+  std::vector<PItem> pitem;
+  std::vector<int2> ment;  // (t, t') of each entry
+  for (size_t c = 0; c + 1 < cuts.size(); ++c) {
+    std::vector<int> A;
+    for (int t = 0; t < ntr; ++t)
+      if (tr[t].wlo <= cuts[c] && tr[t].whi >= cuts[c + 1]) A.push_back(t);
+    const int s = (int)A.size();
+    for (int a = cuts[c]; s > 0 && a < cuts[c + 1]; a += seg_len) {
+      const int b = std::min(a + seg_len, cuts[c + 1]);
+      const int e0 = (int)ment.size();
+      for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) ment.push_back(make_int2(A[i], A[j]));
+      for (int ti = 0; ti < s; ti += kPairBlk)
+        for (int ui = 0; ui < s; ui += kPairBlk) {
+          PItem P{};
+          P.f0 = a;
+          P.f1 = b;
+          P.nt = std::min(kPairBlk, s - ti);
+          P.nu = std::min(kPairBlk, s - ui);
+          P.e0 = e0 + ti * s + ui;
+          P.es = s;
+          P.same = ti == ui;
+          for (int i = 0; i < P.nt; ++i) P.t[i] = A[ti + i];
+          for (int j = 0; j < P.nu; ++j) P.u[j] = A[ui + j];
+          pitem.push_back(P);
+        }
     }
-  C.npair = (int)pairs.size();
+  }
+  C.npitem = (int)pitem.size();
+  C.nment = (int)ment.size();
   // gather lists of the preconditioner blocks: entry (i, j) sums
   //   Gamma: (lo,lo) += C_lu+R_lu, (up,up) += C_ul+R_ul, (lo,up) -= C_ul+R_ul, (up,lo) -= C_lu+R_lu
-  //   pairs: (lo_t,lo_u) += M1, (up_t,lo_u) -= M1, (lo_t,up_u) += M2, (up_t,up_u) -= M2
+  //   entries: (lo_t,lo_u) += M1, (up_t,lo_u) -= M1, (lo_t,up_u) += M2, (up_t,up_u) -= M2
   // code = (index << 3) | (kind << 1) | negate; kind 0/1: total up/down rate, 2/3: M1/M2
   std::vector<std::vector<int>> gl(L * L);
   for (int t = 0; t < ntr; ++t) {
@@ -618,9 +652,9 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     gl[lo * L + up].push_back((t << 3) | (1 << 1) | 1);
     gl[up * L + lo].push_back((t << 3) | (0 << 1) | 1);
   }
-  for (int q = 0; q < C.npair; ++q) {
-    const TrDev& Tt = tr[pairs[q].x];
-    const TrDev& Tu = tr[pairs[q].y];
+  for (int q = 0; q < C.nment; ++q) {
+    const TrDev& Tt = tr[ment[q].x];
+    const TrDev& Tu = tr[ment[q].y];
     gl[Tt.lo * L + Tu.lo].push_back((q << 3) | (2 << 1) | 0);
     gl[Tt.up * L + Tu.lo].push_back((q << 3) | (2 << 1) | 1);
     gl[Tt.lo * L + Tu.up].push_back((q << 3) | (3 << 1) | 0);
@@ -642,7 +676,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   std::vector<int2> prec_w;
   int maxL_w = 0;
   std::vector<TileGroup> groups;
-  build_work_lists(&C, 1, tiles, groups, rate_w, prec_w, maxL_w);
+  const int nrate0_w = build_work_lists(&C, 1, tiles, groups, rate_w, prec_w, maxL_w);
   const int wsz[3] = {(int)tiles.size(), (int)rate_w.size(), (int)prec_w.size()};
 
   // layout
@@ -698,8 +732,8 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   UP(C.ch_line, ch_tr.data(), ch_tr.size() * 4);
   UP(C.ch_eptr, ch_eptr.data(), ch_eptr.size() * 4);
   UP(C.ch_edge, ch_ed.data(), ch_ed.size() * 4);
-  UP(C.rseg, rseg.data(), rseg.size() * sizeof(int4));
-  UP(C.pairs, pairs.data(), pairs.size() * sizeof(int4));
+  UP(C.rseg, rseg.data(), rseg.size() * sizeof(RSeg));
+  UP(C.pitem, pitem.data(), pitem.size() * sizeof(PItem));
   UP(wp.rate, rate_w.data(), rate_w.size() * sizeof(int4));
   UP(wp.pb, prec_w.data(), prec_w.size() * sizeof(int2));
   UP(C.pg_ptr, pg_ptr.data(), pg_ptr.size() * 4);
@@ -770,6 +804,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   col->bw.ncol = 1;
   col->bw.ntiles = wsz[0];
   col->bw.nrate = wsz[1];
+  col->bw.nrate0 = nrate0_w;
   col->bw.npb = wsz[2];
   col->bw.any64 = prec == NLTE_FP64;
   col->bw.any32 = prec == NLTE_FP32_FORM;

@@ -24,7 +24,6 @@ constexpr int kWave = 64;       // lanes per wavefront (CDNA)
 constexpr int kMaxMu = 8;       // angles per hemisphere held in registers
 constexpr int kMaxLev = 16;     // levels per atom
 constexpr int kMaxRestart = 64; // GMRES restart length
-constexpr int kMaxEdges = kMaxLev - 1;
 constexpr int kScanThreads = 256;  // depths of a column with the depth-parallel formal solution
 
 // Loads and stores through the global address space (the pointers live in
@@ -45,6 +44,19 @@ __device__ __forceinline__ void stg(T* p, T v) {
 template <typename T>
 __device__ __forceinline__ T ldc(const T* p) {
   return *(const __attribute__((address_space(4))) T*)p;
+}
+
+// The same for a small record of ints (copied int by int; the compiler
+// merges the loads into a few wide scalar loads).
+template <typename T>
+__device__ __forceinline__ T ldc_rec(const T* p) {
+  static_assert(sizeof(T) % sizeof(int) == 0, "record of ints");
+  T v;
+  int* d = reinterpret_cast<int*>(&v);
+  const int* s = reinterpret_cast<const int*>(p);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / sizeof(int)); ++i) d[i] = ldc(s + i);
+  return v;
 }
 
 // Values the compiler cannot prove wave-uniform, moved to scalar registers.
@@ -110,9 +122,30 @@ struct ColState {
   int pad3;
 };
 
+// Preconditioner pair sums.  The frequency axis of a column is cut at every
+// window edge (and into pieces of at most the segment length), so that on a
+// piece [f0, f1) the set of transitions whose windows cover it is constant.
+// A piece with s transitions has s^2 entries (t, t') in M and is summed in
+// blocks of at most kPairBlk x kPairBlk of them: block entry (i, j) pairs
+// transitions t[i] and u[j] and is entry e0 + i * es + j.
+constexpr int kPairBlk = 4;
+
+// One rate-integral segment: frequencies [q0, q1) of transition t's window,
+// wo = q0 - (window start); voff, cwoff: the transition's table offsets.
+struct RSeg {
+  int t, q0, q1, wo;
+  int voff, cwoff, pad0, pad1;
+};
+struct PItem {
+  int f0, f1, nt, nu;
+  int e0, es, same, pad;  // same: u[] lists the same transitions as t[]
+  int t[kPairBlk], u[kPairBlk];
+};
+
 struct ColDev {
   int nz, L, ntr, nline, nbf, nnu, nmu, prec;
-  int nchunk, npair, has_sca, N;   // N = nz * L; npair = overlapping transition pairs
+  int nchunk, has_sca, N;          // N = nz * L
+  int npitem, nment;               // pair-sum blocks, entries of M
   int scan;                        // 1: depth-parallel formal solution (nz <= 256)
   int nrseg;                       // frequency segments of the rate integrals
   // angles (inline: at most kMaxMu)
@@ -141,8 +174,8 @@ struct ColDev {
   // chunk -> overlapping line windows and edge windows; overlapping transition pairs
   const int *ch_lptr, *ch_line;
   const int *ch_eptr, *ch_edge;
-  const int4 *rseg;                // (t, first, last + 1, -) of each rate-integral segment
-  const int4 *pairs;               // (t, t', first, last + 1) of each window-intersection segment
+  const RSeg *rseg;                // rate-integral segments
+  const PItem *pitem;              // blocks of the preconditioner pair sums
   const int *pg_ptr, *pg_code;     // per block entry (i, j): contributions, see k_pblock
   // evaluation buffers
   ColState *st;
@@ -158,7 +191,7 @@ struct ColDev {
   double *Dchi, *Deta;             // [nz][nnu] ingoing-ray intensity derivatives
   double *DchiT, *DetaT;           // [nnu][nz] angle-averaged local intensity derivatives
   double *RJ;                      // [nz][nrseg][2] rate integrals over J, per segment
-  double *M;                       // [nz][npair][2] pair sums of the radiative blocks
+  double *M;                       // [nment][nz][2] pair sums of the radiative blocks
   double *P;                       // [nz][L][L] preconditioner blocks of the last Newton-mode evaluation
   double *LU;                      // [nz][L][L] LU factors of the iterate's blocks
   double *Fsave, *Gsave;           // [nz] rate-row F and gross rate under each conservation row
@@ -188,7 +221,6 @@ struct Tile {
   int chunk;
 };
 
-inline __host__ __device__ int chunk_of(int f) { return f / kWave; }
 
 // Frequency sums over a transition's window (rate integrals, preconditioner
 // pair sums) run in segments of at most this many frequencies, each summed by
@@ -221,9 +253,10 @@ struct BatchWork {
   int nact = 0;
   int opac_depths = 8;            // launch shapes (tuned by residual plans): depths per
   int formal_wpb = 4;             // opacity wave (4, 8, 16); waves per formal block (1, 2, 4)
-  const int4* rate_work = nullptr;  // (col, transition, first depth, -)
+  const int4* rate_work = nullptr;  // (col, segment or block, first depth, kind)
   const int2* pb_work = nullptr;  // (col, first depth-entry index)
   int ncol = 0, ntiles = 0, nrate = 0, npb = 0;
+  int nrate0 = 0;                 // rate items at the front of rate_work; pair-sum blocks follow
   int any64 = 0, any32 = 0, any_newton = 1;
 };
 
@@ -250,10 +283,10 @@ hipError_t solver_gather(const ColDev* cols, int ncol, ColState* out, hipStream_
 bool state_done(const ColState& st);
 void state_stats(const ColState& st, nlte_solve_stats* out);
 
-void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
-                      std::vector<TileGroup>& groups, std::vector<int4>& rate,
-                      std::vector<int2>& pblock, int& maxL, const int* sel = nullptr,
-                      int nsel = 0);
+int build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
+                     std::vector<TileGroup>& groups, std::vector<int4>& rate,
+                     std::vector<int2>& pblock, int& maxL, const int* sel = nullptr,
+                     int nsel = 0);
 
 }  // namespace nlte
 

@@ -139,7 +139,7 @@ extern "C" nlte_status nlte_plan_create(nlte_ctx* ctx, nlte_column* const* cols,
   std::vector<int4> rate;
   std::vector<int2> pb;
   int maxL = 0;
-  build_work_lists(hc.data(), ncol, tiles, groups, rate, pb, maxL);
+  const int nrate0 = build_work_lists(hc.data(), ncol, tiles, groups, rate, pb, maxL);
   auto fail = [&](nlte_status st) {
     delete P;
     return st;
@@ -170,6 +170,7 @@ extern "C" nlte_status nlte_plan_create(nlte_ctx* ctx, nlte_column* const* cols,
   bw.ncol = ncol;
   bw.ntiles = (int)tiles.size();
   bw.nrate = (int)rate.size();
+  bw.nrate0 = nrate0;
   bw.npb = (int)pb.size();
   bw.any_newton = 0;  // F only: no preconditioner work
   bw.ngroup = (int)groups.size();

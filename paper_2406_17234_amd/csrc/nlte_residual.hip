@@ -27,7 +27,8 @@
 //   k_depthwork: one lane per depth, one wavefront per (column, frequency
 //               segment, 64 depths): rate integrals summed in frequency order
 //               (no cross-lane reductions, independent of batching), and in
-//               Newton mode the preconditioner pair sums.
+//               Newton mode the preconditioner pair sums, per (column, piece
+//               of constant transition set, block of pairs, 64 depths).
 //   k_assemble: rates, rate-equation residual, conservation rows, scaled
 //               residual per depth; one block per (column, 32 depths).
 //   k_pblock  : Newton mode; the preconditioner blocks from the total rates
@@ -890,36 +891,39 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
 // the FP32 form a J rounded to FP32 before these sums sets a noise floor on
 // F that doubled the share of columns needing the FP64 fallback.
 template <typename TB>
-__device__ __forceinline__ void rates_sum(const ColDev& C, int t, int k0, const TB* __restrict__ VTt,
-                                          const TB* __restrict__ EbfTt);
+__device__ __forceinline__ void rates_sum(const ColDev& C, const RSeg& seg, int sg, int k0,
+                                          const TB* __restrict__ VTt, const TB* __restrict__ EbfTt);
 
-// The tables follow the evaluation's precision, so that an FP32-form column
-// after its FP64 fallback evaluates the same F as an FP64 column.
+// The column state and the segment descriptor are read with independent
+// scalar loads, so that a wave waits for one memory round trip, not three,
+// before its first table loads.  The tables follow the evaluation's
+// precision, so that an FP32-form column after its FP64 fallback evaluates
+// the same F as an FP64 column.
 __device__ __forceinline__ void rates_item(const ColDev& C, int sg, int k0) {
-  if (uni(C.st->cur_prec) == NLTE_FP32_FORM)
-    rates_sum<float>(C, sg, k0, C.VTf, C.EbfTf);
+  const int mode = ldc(&C.st->mode), prec = ldc(&C.st->cur_prec);
+  const RSeg seg = ldc_rec(C.rseg + sg);
+  if (mode == kModeIdle) return;
+  if (prec == NLTE_FP32_FORM)
+    rates_sum<float>(C, seg, sg, k0, C.VTf, C.EbfTf);
   else
-    rates_sum<double>(C, sg, k0, C.VT, C.EbfT);
+    rates_sum<double>(C, seg, sg, k0, C.VT, C.EbfT);
 }
 
 // One frequency segment [q0, q1) of transition t's window; the assembly adds
 // the segments of a transition in order.
 template <typename TB>
-__device__ __forceinline__ void rates_sum(const ColDev& C, int sg, int k0, const TB* __restrict__ VTt,
-                                          const TB* __restrict__ EbfTt) {
-  if (uni(C.st->mode) == kModeIdle) return;
+__device__ __forceinline__ void rates_sum(const ColDev& C, const RSeg& seg, int sg, int k0,
+                                          const TB* __restrict__ VTt, const TB* __restrict__ EbfTt) {
   const int nz = C.nz;
   const int k = k0 + threadIdx.x;
   if (k >= nz) return;
-  const int4 seg = C.rseg[sg];
-  const int t = uni(seg.x), q0 = uni(seg.y);
-  const TrDev& T = C.tr[t];
-  const int wl = uni(seg.z) - q0, wo = q0 - uni(T.wlo);  // length, offset in the window
+  const int t = seg.t, q0 = seg.q0;
+  const int wl = seg.q1 - q0, wo = seg.wo;  // length, offset in the window
   const double* __restrict__ J = C.JT + (size_t)q0 * nz + k;
-  const double* __restrict__ cw = C.cw + uni(T.cwoff) + wo;
+  const double* __restrict__ cw = C.cw + seg.cwoff + wo;
   double* dst = C.RJ + ((size_t)k * C.nrseg + sg) * 2;
   if (t < C.nline) {
-    const TB* __restrict__ V = VTt + uni(T.voff) + (size_t)wo * nz + k;
+    const TB* __restrict__ V = VTt + seg.voff + (size_t)wo * nz + k;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     int q = 0;
     for (; q + 4 <= wl; q += 4) {
@@ -936,7 +940,7 @@ __device__ __forceinline__ void rates_sum(const ColDev& C, int sg, int k0, const
     stg(dst, (s[0] + s[1]) + (s[2] + s[3]));
     stg(dst + 1, 0.0);
   } else {
-    const double* __restrict__ A = C.V + uni(T.voff) + wo;
+    const double* __restrict__ A = C.V + seg.voff + wo;
     const TB* __restrict__ E = EbfTt + (size_t)q0 * nz + k;
     double s1[4] = {0.0, 0.0, 0.0, 0.0}, s2[4] = {0.0, 0.0, 0.0, 0.0};
     int q = 0;
@@ -968,52 +972,128 @@ __device__ __forceinline__ void rates_sum(const ColDev& C, int sg, int k0, const
 //   M1 = sum_nu cw_t A_t V_t' D_chi,
 //   M2 = sum_nu cw_t A_t g_t' V_t' (2 h nu^3/c^2 D_eta - D_chi),
 // over the intersection of their windows, A_t = V_t (n_l - g_t n_u); the
-// assembly scatters M1, M2 to the levels.  One lane per depth.
+// assembly scatters M1, M2 to the levels.
+//
+// The sums run per piece of the frequency axis on which the covering set of
+// transitions is constant, in blocks of NT x NU pairs: per frequency a lane
+// (one depth) loads D_chi, D_eta, e^{-h nu/kT} and the V of the block's
+// transitions once and updates all NT x NU pairs, instead of reloading them
+// for every pair.  SAME: the two transition lists are the same (NT == NU).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void tr_vg(const ColDev& C, int t, int voff, int wlo, double gline,
-                                      int kk, int q, double E, double& V, double& g) {
+struct PairSide {
+  const double* V;  // V at the piece's first frequency, this lane's depth
+  int vs;           // step per frequency (nz for line tables, 1 for edges)
+  double g0, gE;    // g = g0 + gE e^{-h nu/kT} (lines: g0 = g_l/g_u; edges: gE = n*_l/n*_c)
+};
+
+__device__ __forceinline__ PairSide pair_side(const ColDev& C, int t, int f0, int k) {
+  const TrDev& T = C.tr[t];
+  const int wlo = uni(T.wlo), voff = uni(T.voff);
+  PairSide S;
   if (t < C.nline) {
-    V = ldg(C.VT + voff + (size_t)(q - wlo) * C.nz + kk);
-    g = gline;
+    S.V = C.VT + voff + (size_t)(f0 - wlo) * C.nz + k;
+    S.vs = C.nz;
+    S.g0 = uni(T.g);
+    S.gE = 0.0;
   } else {
-    V = C.V[voff + (q - wlo)];
-    g = C.rho_bf[kk * C.nbf + (t - C.nline)] * E;
+    S.V = C.V + voff + (f0 - wlo);
+    S.vs = 1;
+    S.g0 = 0.0;
+    S.gE = C.rho_bf[k * C.nbf + (t - C.nline)];
   }
+  return S;
 }
 
-__device__ __forceinline__ void precond_item(const ColDev& C, int p, int k0) {
-  const int nz = C.nz, L = C.L;
+template <int NT, int NU, bool SAME>
+__device__ __forceinline__ void pair_block(const ColDev& C, const PItem& it, int k) {
+  const int nz = C.nz, L = C.L, f0 = it.f0, nf = it.f1 - it.f0;
+  PairSide ts[NT], us[NU];
+  const double* cw[NT];
+  double pa[NT], pb[NT];  // n_l - g n_u = pa - pb e^{-h nu/kT}
+  bool edge = false;
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const int t = it.t[i];
+    const TrDev& T = C.tr[t];
+    ts[i] = pair_side(C, t, f0, k);
+    cw[i] = C.cw + uni(T.cwoff) + (f0 - uni(T.wlo));
+    const double nl = C.eval_n[k * L + uni(T.lo)], nu = C.eval_n[k * L + uni(T.up)];
+    pa[i] = nl - ts[i].g0 * nu;
+    pb[i] = ts[i].gE * nu;
+    edge |= t >= C.nline;
+  }
+#pragma unroll
+  for (int j = 0; j < NU; ++j) {
+    const int u = it.u[j];
+    us[j] = SAME ? ts[j] : pair_side(C, u, f0, k);
+    edge |= u >= C.nline;
+  }
+  const double* DX = C.DchiT + (size_t)f0 * nz + k;
+  const double* DE = C.DetaT + (size_t)f0 * nz + k;
+  const double* EB = edge ? C.EbfT + (size_t)f0 * nz + k : DX;  // DX: any valid address
+  const double* gam = C.gam + f0;
+  double m1[NT][NU], m2[NT][NU];
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = 0; j < NU; ++j) m1[i][j] = m2[i][j] = 0.0;
+  for (int q = 0; q < nf; ++q) {
+    const size_t o = (size_t)q * nz;
+    const double dx = ldg(DX + o), de = ldg(DE + o);
+    const double E = edge ? ldg(EB + o) : 0.0;
+    const double dd = gam[q] * de - dx;
+    double vt[NT], a[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      vt[i] = ldg(ts[i].V + (size_t)q * ts[i].vs);
+      a[i] = cw[i][q] * vt[i] * (pa[i] - pb[i] * E);
+    }
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      const double v = SAME ? vt[j] : ldg(us[j].V + (size_t)q * us[j].vs);
+      const double b = v * dx, c = (us[j].g0 + us[j].gE * E) * v * dd;
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        m1[i][j] = fma(a[i], b, m1[i][j]);
+        m2[i][j] = fma(a[i], c, m2[i][j]);
+      }
+    }
+  }
+  // M is [entry][nz][2]: lanes (depths) store contiguously
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      double* dst = C.M + ((size_t)(it.e0 + i * it.es + j) * nz + k) * 2;
+      stg(dst, m1[i][j]);
+      stg(dst + 1, m2[i][j]);
+    }
+}
+
+__device__ __forceinline__ void pair_item(const ColDev& C, int p, int k0) {
+  // state and block descriptor: independent scalar loads
+  const int mode = ldc(&C.st->mode);
+  const PItem it = ldc_rec(C.pitem + p);
+  if (mode != kModeNewton) return;
   const int k = k0 + threadIdx.x;
-  if (k >= nz) return;
-  const int4 pr = C.pairs[p];
-  const int t = uni(pr.x), u = uni(pr.y), f0 = uni(pr.z), f1 = uni(pr.w);
-  const TrDev& Tt = C.tr[t];
-  const TrDev& Tu = C.tr[u];
-  const int tw = uni(Tt.wlo), uw = uni(Tu.wlo), tv = uni(Tt.voff), uv = uni(Tu.voff);
-  const double tg = uni(Tt.g), ug = uni(Tu.g);
-  const double* cwt = C.cw + uni(Tt.cwoff) - tw;
-  const double nl = C.eval_n[k * L + uni(Tt.lo)], nu_ = C.eval_n[k * L + uni(Tt.up)];
-  const bool edge = t >= C.nline || u >= C.nline;
-  double m1 = 0.0, m2 = 0.0;
-#pragma unroll 4
-  for (int q = f0; q < f1; ++q) {
-    const size_t fk = (size_t)q * nz + k;
-    const double E = edge ? ldg(C.EbfT + fk) : 0.0;
-    double Vt, gt, Vu, gu;
-    tr_vg(C, t, tv, tw, tg, k, q, E, Vt, gt);
-    tr_vg(C, u, uv, uw, ug, k, q, E, Vu, gu);
-    const double DX = ldg(C.DchiT + fk), DE = ldg(C.DetaT + fk);
-    const double cA = cwt[q] * Vt * (nl - gt * nu_);
-    m1 += cA * Vu * DX;
-    m2 += cA * gu * Vu * (C.gam[q] * DE - DX);
+  if (k >= C.nz) return;
+  const int shape = (it.same ? 16 : 0) + (it.nt - 1) * 4 + (it.nu - 1);
+  switch (shape) {
+#define PB(NT, NU) \
+    case (NT - 1) * 4 + (NU - 1): pair_block<NT, NU, false>(C, it, k); break;
+    PB(1, 1) PB(1, 2) PB(1, 3) PB(1, 4) PB(2, 1) PB(2, 2) PB(2, 3) PB(2, 4)
+    PB(3, 1) PB(3, 2) PB(3, 3) PB(3, 4) PB(4, 1) PB(4, 2) PB(4, 3) PB(4, 4)
+#undef PB
+    case 16 + 0: pair_block<1, 1, true>(C, it, k); break;
+    case 16 + 5: pair_block<2, 2, true>(C, it, k); break;
+    case 16 + 10: pair_block<3, 3, true>(C, it, k); break;
+    case 16 + 15: pair_block<4, 4, true>(C, it, k); break;
+    default: break;
   }
-  double* dst = C.M + ((size_t)k * C.npair + p) * 2;
-  stg(dst, m1);
-  stg(dst + 1, m2);
 }
 
-// Lane-per-depth work of a step: rate integrals (kind 0) of every active
-// column and, for columns in Newton mode, preconditioner pair sums (kind 1).
+// Rate integrals of a step: one item per (column, frequency segment, 64
+// depths), lane per depth.
 __global__ __launch_bounds__(64) void k_depthwork(const ColDev* __restrict__ cols,
                                                   const int4* __restrict__ work, int nwork) {
   // the items of a column are consecutive in the list: keeping them on one
@@ -1021,14 +1101,21 @@ __global__ __launch_bounds__(64) void k_depthwork(const ColDev* __restrict__ col
   const int w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= nwork) return;
   const int4 it = work[w];
-  const int col = uni(it.x), idx = uni(it.y), k0 = uni(it.z), kind = uni(it.w);
-  const ColDev& C = cols[col];
-  const int mode = uni(C.st->mode);
-  if (kind == 0) {
-    if (mode != kModeIdle) rates_item(C, idx, k0);
-  } else {
-    if (mode == kModeNewton) precond_item(C, idx, k0);
-  }
+  const int col = uni(it.x), idx = uni(it.y), k0 = uni(it.z);
+  rates_item(cols[col], idx, k0);
+}
+
+// Preconditioner pair sums of the columns in Newton mode: one item per
+// (column, pair-sum block, 64 depths), lane per depth.  A kernel of its own:
+// the block's accumulators need about three times the registers of the rate
+// integrals, which would otherwise run at the lower occupancy too.
+__global__ __launch_bounds__(64) void k_pairsum(const ColDev* __restrict__ cols,
+                                                const int4* __restrict__ work, int nwork) {
+  const int w = xcd_item(blockIdx.x, gridDim.x);
+  if (w >= nwork) return;
+  const int4 it = work[w];
+  const int col = uni(it.x), idx = uni(it.y), k0 = uni(it.z);
+  pair_item(cols[col], idx, k0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1150,10 +1237,12 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble(const ColDev* __restri
   C.rho_k[k] = rk;
 }
 
-// Preconditioner blocks of Newton-mode columns: one thread per (depth, entry)
-// gathers its contributions (Gamma from the total rates, the radiative part
-// from the pair sums) from a per-column list, then the conservation row of
-// the depth becomes -1 (the original row is kept in Psave).
+// Preconditioner blocks of Newton-mode columns: one thread per (entry,
+// depth) gathers its contributions (Gamma from the total rates, the
+// radiative part from the pair sums) from a per-column list, then the
+// conservation row of the depth becomes -1 (the original row is kept in
+// Psave).  Threads are numbered depth-fastest, so a wave walks one entry's
+// list in step and reads the pair sums of consecutive depths together.
 __global__ __launch_bounds__(256) void k_pblock(const ColDev* __restrict__ cols,
                                                 const int2* __restrict__ work, int nwork) {
   const int w = blockIdx.x;
@@ -1161,18 +1250,19 @@ __global__ __launch_bounds__(256) void k_pblock(const ColDev* __restrict__ cols,
   const int col = uni(work[w].x), base = uni(work[w].y);
   const ColDev& C = cols[col];
   if (uni(C.st->mode) != kModeNewton) return;
-  const int L = C.L, LL = L * L;
+  const int L = C.L, LL = L * L, nz = C.nz;
   const int id = base + threadIdx.x;
-  if (id >= C.nz * LL) return;
-  const int k = id / LL, ij = id - k * LL;
+  if (id >= nz * LL) return;
+  const int ij = id / nz, k = id - ij * nz;
   const int i = ij / L, j = ij - i * L;
   const double* Rt = C.Rtot + (size_t)k * C.ntr * 2;
-  const double* Mk = C.M + (size_t)k * C.npair * 2;
+  const double* Mk = C.M + (size_t)k * 2;
+  const size_t ms = (size_t)C.nz * 2;
   double s = 0.0;
   for (int e = C.pg_ptr[ij]; e < C.pg_ptr[ij + 1]; ++e) {
     const int code = C.pg_code[e];
     const int kind = (code >> 1) & 3, idx = code >> 3;
-    const double v = kind < 2 ? Rt[idx * 2 + kind] : Mk[idx * 2 + (kind - 2)];
+    const double v = kind < 2 ? Rt[idx * 2 + kind] : Mk[idx * ms + (kind - 2)];
     s += (code & 1) ? -v : v;
   }
   const int r = C.rows[k];
@@ -1236,7 +1326,12 @@ hipError_t residual_streams_init() {
 }
 
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
-  if (ev) hipEventRecord(ev[0], s);
+  // the first failing event or stream call, else the launch status at the end
+  hipError_t er = hipSuccess;
+  auto chk = [&er](hipError_t x) {
+    if (er == hipSuccess) er = x;
+  };
+  if (ev) chk(hipEventRecord(ev[0], s));
   const int nblk = bw.act ? bw.nact : bw.ncol;
   k_coef<<<nblk, 256, 0, s>>>(bw.cols, bw.act);
   for (int g = 0; g < bw.ngroup; ++g) {
@@ -1259,9 +1354,9 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     const hipError_t e = side_streams(&SS);
     if (e != hipSuccess) return e;
   }
-  if (ev) hipEventRecord(ev[1], s);
-  hipEventRecord(SS->fork, s);
-  for (int i = 0; i < 3; ++i) hipStreamWaitEvent(SS->st[i], SS->fork, 0);
+  if (ev) chk(hipEventRecord(ev[1], s));
+  chk(hipEventRecord(SS->fork, s));
+  for (int i = 0; i < 3; ++i) chk(hipStreamWaitEvent(SS->st[i], SS->fork, 0));
   const hipStream_t sNewton = SS->st[0], sF64 = SS->st[1], sN64 = SS->st[2];
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
@@ -1292,26 +1387,37 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
       if (bw.any_newton) launch_formal_mu<double, true>(G.nmu, nb, dN, bw.cols, tl, G.count, 0);
     }
   }
-  if (ev) hipEventRecord(ev[6], s);  // end of the F-mode launches on s
+  if (ev) chk(hipEventRecord(ev[6], s));  // end of the F-mode launches on s
   for (int i = 0; i < 3; ++i) {
-    hipEventRecord(SS->join[i], SS->st[i]);
-    hipStreamWaitEvent(s, SS->join[i], 0);
+    chk(hipEventRecord(SS->join[i], SS->st[i]));
+    chk(hipStreamWaitEvent(s, SS->join[i], 0));
   }
-  if (ev) hipEventRecord(ev[2], s);
-  if (bw.nrate > 0) k_depthwork<<<bw.nrate, 64, 0, s>>>(bw.cols, bw.rate_work, bw.nrate);
-  if (ev) hipEventRecord(ev[3], s);
+  if (ev) chk(hipEventRecord(ev[2], s));
+  // The rate integrals stream V and J of many (column, segment) pairs at
+  // once; at full occupancy (32 waves per CU) they ran 20 % slower than with
+  // at most 13.  The kernel uses no LDS: the allocation only caps waves per CU
+  // (160 KB / 12 KB).
+  constexpr size_t kDepthworkLds = 12 * 1024;
+  if (bw.nrate0 > 0)
+    k_depthwork<<<bw.nrate0, 64, kDepthworkLds, s>>>(bw.cols, bw.rate_work, bw.nrate0);
+  if (bw.any_newton && bw.nrate > bw.nrate0)
+    k_pairsum<<<bw.nrate - bw.nrate0, 64, 0, s>>>(bw.cols, bw.rate_work + bw.nrate0,
+                                                   bw.nrate - bw.nrate0);
+  if (ev) chk(hipEventRecord(ev[3], s));
   {
     const int nsub = (bw.maxnz + kAsmDepths - 1) / kAsmDepths;
     k_assemble<<<nblk * nsub, kAsmThreads, 0, s>>>(bw.cols, bw.act, nsub);
   }
   if (bw.any_newton && bw.npb > 0) k_pblock<<<bw.npb, 256, 0, s>>>(bw.cols, bw.pb_work, bw.npb);
-  if (ev) hipEventRecord(ev[4], s);
+  if (ev) chk(hipEventRecord(ev[4], s));
+  if (er != hipSuccess) return er;
   return hipGetLastError();
 }
 
 // Work lists of a batch (host side): formal-solution tiles, rate items and
-// preconditioner items for every column.
-void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
+// preconditioner items for every column.  Returns the number of rate items,
+// which come first in `rate`; the pair-sum blocks follow.
+int build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
                       std::vector<TileGroup>& groups, std::vector<int4>& rate,
                       std::vector<int2>& pblock, int& maxL, const int* sel, int nsel) {
   // sel: the columns to list (indices into hc), or NULL for all of them
@@ -1335,7 +1441,8 @@ void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
         G.count = (int)tiles.size() - G.first;
         if (G.count) groups.push_back(G);
       }
-  // rate items (kind 0) and preconditioner pair items (kind 1) share one list
+  // rate items (kind 0), then preconditioner pair-sum blocks (kind 1), each
+  // kind column by column
   maxL = 0;
   for (int q = 0; q < nsel; ++q) {
     const int c = sel[q];
@@ -1347,9 +1454,14 @@ void build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
     maxL = std::max(maxL, C.L);
     for (int sg = 0; sg < C.nrseg; ++sg)
       for (int k0 = 0; k0 < C.nz; k0 += kWave) rate.push_back(make_int4(c, sg, k0, 0));
-    for (int p = 0; p < C.npair; ++p)
-      for (int k0 = 0; k0 < C.nz; k0 += kWave) rate.push_back(make_int4(c, p, k0, 1));
   }
+  const int nrate0 = (int)rate.size();
+  for (int q = 0; q < nsel; ++q) {
+    const ColDev& C = hc[sel[q]];
+    for (int p = 0; p < C.npitem; ++p)
+      for (int k0 = 0; k0 < C.nz; k0 += kWave) rate.push_back(make_int4(sel[q], p, k0, 1));
+  }
+  return nrate0;
 }
 
 }  // namespace nlte

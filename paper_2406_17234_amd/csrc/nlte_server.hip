@@ -120,7 +120,7 @@ hipError_t nlte_server::rebuild() {
   std::vector<int4> rate;
   std::vector<int2> pb;
   int maxL = 0;
-  build_work_lists(hc.data(), n, tiles, groups, rate, pb, maxL);
+  const int nrate0 = build_work_lists(hc.data(), n, tiles, groups, rate, pb, maxL);
   hipError_t e;
   if ((e = d_cols.fit(n)) != hipSuccess) return e;
   if ((e = d_tiles.fit(std::max<size_t>(1, tiles.size()))) != hipSuccess) return e;
@@ -147,6 +147,7 @@ hipError_t nlte_server::rebuild() {
   bw.ncol = n;
   bw.ntiles = (int)tiles.size();
   bw.nrate = (int)rate.size();
+  bw.nrate0 = nrate0;
   bw.npb = (int)pb.size();
   bw.any_newton = 1;
   bw.ngroup = (int)groups.size();

@@ -832,7 +832,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
       if (cols[d] == cols[c]) return set_err(NLTE_E_INVALID, "column %d appears twice", c);
   }
   std::vector<TileGroup> groups;
-  build_work_lists(hc.data(), ncol, tiles, groups, rate_w, prec_w, b.maxL);
+  const int nrate0 = build_work_lists(hc.data(), ncol, tiles, groups, rate_w, prec_w, b.maxL);
   b.ntiles = (int)tiles.size();
   HIP_TRY(hipMalloc(&b.cols, ncol * sizeof(ColDev)));
   HIP_TRY(hipMalloc(&b.tiles, tiles.size() * sizeof(Tile)));
@@ -848,6 +848,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   bw.ncol = ncol;
   bw.ntiles = b.ntiles;
   bw.nrate = (int)rate_w.size();
+  bw.nrate0 = nrate0;
   bw.npb = (int)prec_w.size();
   bw.any64 = b.any64;
   bw.any32 = b.any32;
@@ -941,14 +942,15 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
       rate_w.clear();
       prec_w.clear();
       int maxL_l = 0;
-      build_work_lists(hc.data(), ncol, tiles, groups, rate_w, prec_w, maxL_l, live.data(),
-                       (int)live.size());
+      const int nrate0_l = build_work_lists(hc.data(), ncol, tiles, groups, rate_w, prec_w, maxL_l,
+                                            live.data(), (int)live.size());
       HIP_TRY(hipMemcpyAsync(b.tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
       HIP_TRY(hipMemcpyAsync(b.rate, rate_w.data(), rate_w.size() * sizeof(int4), hipMemcpyHostToDevice, s));
       HIP_TRY(hipMemcpyAsync(b.prec, prec_w.data(), prec_w.size() * sizeof(int2), hipMemcpyHostToDevice, s));
       HIP_TRY(hipMemcpyAsync(b.act, live.data(), live.size() * sizeof(int), hipMemcpyHostToDevice, s));
       bw.ntiles = (int)tiles.size();
       bw.nrate = (int)rate_w.size();
+      bw.nrate0 = nrate0_l;
       bw.npb = (int)prec_w.size();
       bw.ngroup = (int)groups.size();
       for (int g = 0; g < bw.ngroup; ++g) bw.groups[g] = groups[g];
