@@ -729,6 +729,17 @@ __global__ void k_gather_state(const ColDev* __restrict__ cols, ColState* __rest
   if (c < ncol) out[c] = *cols[c].st;
 }
 
+// After a batch solve: every column idle for later residual calls.
+__global__ void k_idle_state(const ColDev* __restrict__ cols, int ncol) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncol) {
+    ColState* st = cols[c].st;
+    st->mode = kModeIdle;
+    st->want_J = 0;
+    st->rows_own = 0;
+  }
+}
+
 namespace nlte {
 
 nlte_status check_solve_opts(const nlte_solve_opts& o) {
@@ -966,9 +977,12 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   if (loop_st != NLTE_OK) return loop_st;
   k_copy_out<<<ncol, 256, 0, s>>>(b.cols, b.nout);
   HIP_TRY(hipGetLastError());
+  // final states in one copy, then every column idle for later residual calls
   std::vector<ColState> sts(ncol);
-  for (int c = 0; c < ncol; ++c)
-    HIP_TRY(hipMemcpyAsync(&sts[c], hc[c].st, sizeof(ColState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(solver_gather(b.cols, ncol, b.states, s));
+  HIP_TRY(hipMemcpyAsync(sts.data(), b.states, ncol * sizeof(ColState), hipMemcpyDeviceToHost, s));
+  k_idle_state<<<(ncol + 127) / 128, 128, 0, s>>>(b.cols, ncol);
+  HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   bool all_ok = true;
   for (int c = 0; c < ncol; ++c) {
@@ -977,9 +991,6 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
     if (one.status != NLTE_OK) all_ok = false;
     if (stats) stats[c] = one;
   }
-  // leave columns idle for later residual calls
-  for (int c = 0; c < ncol; ++c) HIP_TRY(hipMemsetAsync(hc[c].st, 0, 3 * sizeof(int), s));
-  HIP_TRY(hipStreamSynchronize(s));
   if (!all_ok) {
     set_err(NLTE_E_NOCONV, "not every column converged (see stats)");
     return NLTE_E_NOCONV;
