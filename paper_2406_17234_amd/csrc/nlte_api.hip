@@ -298,9 +298,10 @@ __global__ void k_setup_f32(ColDev C, size_t nv, size_t nvt) {
   if (i < nv) ((float*)C.Vf)[i] = (float)C.V[i];
   if (i < nvt) ((float*)C.VTf)[i] = (float)C.VT[i];
   if (i < kf) {
-    ((float*)C.Bnuf)[i] = (float)C.Bnu[i];
+    const size_t k = i / C.nnu, ip = k * C.fp + (i - k * C.nnu);  // padded rows
+    ((float*)C.Bnuf)[ip] = (float)C.Bnu[i];
     if (C.nbf) {
-      ((float*)C.Ebff)[i] = (float)C.Ebf[i];
+      ((float*)C.Ebff)[ip] = (float)C.Ebf[i];
       ((float*)C.EbfTf)[i] = (float)C.EbfT[i];
     }
   }
@@ -412,7 +413,7 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
                           int** lbase, WorkPtrs* wp, const int* wsz, int** stage, int** bf_ptr,
                           double** raw) {
   const int nz = C.nz, L = C.L, ntr = C.ntr, nnu = C.nnu, N = C.N;
-  const size_t kf = (size_t)nz * nnu;
+  const size_t kf = (size_t)nz * nnu, kfp = (size_t)nz * C.fp;
   C.st = Lo.take<ColState>(1);
   C.z = Lo.take<double>(nz);
   C.dz = Lo.take<double>(nz);
@@ -442,8 +443,8 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.ch_edge = Lo.take<int>(nentries_e);
   if (C.prec == NLTE_FP32_FORM) {
     C.Vf = Lo.take<float>((size_t)nline_tab * nz + (nwin_total - nline_tab));
-    C.Bnuf = Lo.take<float>(kf);
-    C.Ebff = C.nbf ? Lo.take<float>(kf) : nullptr;
+    C.Bnuf = Lo.take<float>(kfp);
+    C.Ebff = C.nbf ? Lo.take<float>(kfp) : nullptr;
     C.VTf = Lo.take<float>((size_t)nline_tab * nz + 1);
     C.EbfTf = C.nbf ? Lo.take<float>(kf) : nullptr;
   } else {
@@ -459,10 +460,10 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.G = Lo.take<double>(N);
   C.Jdag = Lo.take<double>(kf);
   C.JT = Lo.take<double>(kf);
-  C.Jm = Lo.take<double>(kf);
-  C.XS = Lo.take<double>(2 * kf);
-  C.Dchi = Lo.take<double>(kf);
-  C.Deta = Lo.take<double>(kf);
+  C.Jm = Lo.take<double>(kfp);
+  C.XS = Lo.take<double>(2 * kfp);
+  C.Dchi = Lo.take<double>(kfp);
+  C.Deta = Lo.take<double>(kfp);
   C.DchiT = Lo.take<double>(kf);
   C.DetaT = Lo.take<double>(kf);
   C.RJ = Lo.take<double>((size_t)nz * std::max(C.nrseg, 1) * 2);
@@ -524,6 +525,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   C.prec = prec; C.N = nz * L;
   C.scan = scan;
   C.nchunk = (nnu + kWave - 1) / kWave;
+  C.fp = C.nchunk * kWave;
   C.has_sca = 0;
   if (A->chi_sca)
     for (int k = 0; k < nz; ++k)
@@ -929,8 +931,6 @@ extern "C" nlte_status nlte_residual(nlte_column* col, const double* n_dev, doub
   st = run_single(col, s);
   if (st != NLTE_OK) return st;
   HIP_TRY(hipMemcpyAsync(F_dev, C.F, C.N * 8, hipMemcpyDeviceToDevice, s));
-  const size_t kf = (size_t)C.nz * C.nnu * 8;
-  (void)kf;
   if (J_dev) transpose_J(C, J_dev, s);
   if (update_J) transpose_J(C, C.Jdag, s);
   if (R_dev) HIP_TRY(hipMemcpyAsync(R_dev, C.R, (size_t)C.nz * C.ntr * 16, hipMemcpyDeviceToDevice, s));

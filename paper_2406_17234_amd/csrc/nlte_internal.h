@@ -144,6 +144,9 @@ struct PItem {
 
 struct ColDev {
   int nz, L, ntr, nline, nbf, nnu, nmu, prec;
+  int fp;                          // row pitch of the [nz][nnu] formal-solution scratch and
+                                   // FP32 tables: nnu rounded up to a multiple of 64, so that
+                                   // a chunk's 64 frequencies start on a cache-line boundary
   int nchunk, has_sca, N;          // N = nz * L
   int npitem, nment;               // pair-sum blocks, entries of M
   int scan;                        // 1: depth-parallel formal solution (nz <= 256)

@@ -315,12 +315,15 @@ __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0
   const double* cs = coef + ((size_t)(ntr + 1) * nz + k0) * 2;
   const bool sca = C.has_sca, bf = C.nbf > 0;
   R* __restrict__ xs = reinterpret_cast<R*>(C.XS);
+  // the FP32 tables share the scratch's padded row pitch; the FP64 ones
+  // (and the lagged J) keep rows of nnu
+  const int fp = uni(C.fp), tp = sizeof(R) == sizeof(float) ? fp : nnu;
 #pragma unroll
   for (int i = 0; i < KG; ++i) {
     const int k = min(k0 + i, nz - 1);
-    const size_t kf = (size_t)k * nnu + fc;
-    const double B = (double)ldg(FTab<R>::B(C) + kf);
-    const double E = bf ? (double)ldg(FTab<R>::E(C) + kf) : 0.0;
+    const size_t kf = (size_t)k * nnu + fc, kt = (size_t)k * tp + fc, kx = (size_t)k * fp + fc;
+    const double B = (double)ldg(FTab<R>::B(C) + kt);
+    const double E = bf ? (double)ldg(FTab<R>::E(C) + kt) : 0.0;
     const double EA2 = E * A2[i];
     const double X = (ldc(cb + 2 * (k - k0)) + chi[i]) + (A1[i] - EA2);
     double eta = fmar(ldc(cb + 2 * (k - k0) + 1), B, gam * (et[i] + EA2));
@@ -328,8 +331,8 @@ __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0
     cx[i] = (R)X;
     sx[i] = (R)(eta / X);
     if (fin && k0 + i < nz) {
-      stg(xs + 2 * kf, cx[i]);
-      stg(xs + 2 * kf + 1, sx[i]);
+      stg(xs + 2 * kx, cx[i]);
+      stg(xs + 2 * kx + 1, sx[i]);
     }
   }
 }
@@ -397,7 +400,7 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
   double* tX = tile + KF * kWave;
   double* tE = tile + 2 * KF * kWave;
   const int f0 = chunk * kWave;
-  const int nz = C.nz, nnu = C.nnu;
+  const int nz = C.nz, nnu = C.nnu, fp = C.fp;
   const int f = chunk * kWave + lane;
   const bool fin = f < nnu;
   const int fc = fin ? f : nnu - 1;
@@ -459,7 +462,7 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
       }
     }
     if (fin) {
-      const size_t kf = (size_t)k * nnu + f;
+      const size_t kf = (size_t)k * fp + f;
       stg(jm + kf, (R)jac);
       if (PM) {
         const R rc = PL<R>::div((R)1, chi);
@@ -502,7 +505,7 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = min(1 + u, nz - 1);
-      const size_t kf = (size_t)k * nnu + fc;
+      const size_t kf = (size_t)k * fp + fc;
       cc[u] = ldg(xs + 2 * kf);
       cs[u] = ldg(xs + 2 * kf + 1);
       cd[u] = (R)ldc(dzt + 2 * max(k - 1, 0));
@@ -511,7 +514,7 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = min(k0 + U + u, nz - 1);
-        const size_t kf = (size_t)k * nnu + fc;
+        const size_t kf = (size_t)k * fp + fc;
         nc[u] = ldg(xs + 2 * kf);
         ns[u] = ldg(xs + 2 * kf + 1);
         nd[u] = (R)ldc(dzt + 2 * max(k - 1, 0));
@@ -531,8 +534,8 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
   // ---- sweep 2: outgoing rays, bottom -> top (I+ = B at the bottom) ----
   R chi_n = chi_p, S_n = S_p;
   {
-    const size_t kf = (size_t)(nz - 1) * nnu + fc;
-    const double Bd = ldg(C.Bnu + kf);
+    const size_t kf = (size_t)(nz - 1) * fp + fc;
+    const double Bd = ldg(C.Bnu + (size_t)(nz - 1) * nnu + fc);
     const R Bb = (R)Bd;
     double jp = 0.0;
 #pragma unroll
@@ -598,7 +601,7 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = max(k0 - u, 0);
-        const size_t kf = (size_t)k * nnu + fc;
+        const size_t kf = (size_t)k * fp + fc;
         d_[u] = (R)ldc(dzt + 2 * k);
         c_[u] = ldg(xs + 2 * kf);
         s_[u] = ldg(xs + 2 * kf + 1);
@@ -744,7 +747,7 @@ __global__ __launch_bounds__(kScanThreads) void k_formal_scan(const ColDev* __re
 
   const R* __restrict__ xs = reinterpret_cast<const R*>(C.XS);
   const double* __restrict__ dzt = C.coef + ((size_t)(C.ntr + 1) * nz) * 2 + 1;  // stride 2
-  const size_t kf = (size_t)k * nnu + f;
+  const size_t kf = (size_t)k * uni(C.fp) + f;
   const R chi = ldg(xs + 2 * kf), S = ldg(xs + 2 * kf + 1);
   sx[t] = chi;
   ss[t] = S;
