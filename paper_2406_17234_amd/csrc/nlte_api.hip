@@ -277,7 +277,7 @@ __global__ void k_setup_transpose(ColDev C, int nline_tab_total) {
   const size_t kf = (size_t)C.nz * C.nnu;
   if (C.nbf && i < kf) {
     const int k = (int)(i / C.nnu), f = (int)(i % C.nnu);
-    ((double*)C.EbfT)[(size_t)f * C.nz + k] = C.Ebf[i];
+    ((double*)C.EbfT)[(size_t)f * C.zp + k] = C.Ebf[i];
   }
   if (i < (size_t)nline_tab_total) {
     // find the line owning element i of the packed [nz][wl] tables
@@ -302,23 +302,25 @@ __global__ void k_setup_f32(ColDev C, size_t nv, size_t nvt) {
     ((float*)C.Bnuf)[ip] = (float)C.Bnu[i];
     if (C.nbf) {
       ((float*)C.Ebff)[ip] = (float)C.Ebf[i];
-      ((float*)C.EbfTf)[i] = (float)C.EbfT[i];
+      const size_t f = i / C.nz, iz = f * C.zp + (i - f * C.nz);  // padded [nnu][zp]
+      ((float*)C.EbfTf)[iz] = (float)C.EbfT[iz];
     }
   }
 }
 
 // J [nnu][nz] -> [nz][nnu]
-__global__ void k_transpose_J(const double* __restrict__ JT, double* __restrict__ out, int nz, int nnu) {
+__global__ void k_transpose_J(const double* __restrict__ JT, double* __restrict__ out, int nz, int nnu,
+                              int zp) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (size_t)nz * nnu) return;
   const int k = (int)(i / nnu), f = (int)(i % nnu);
-  out[i] = JT[(size_t)f * nz + k];
+  out[i] = JT[(size_t)f * zp + k];
 }
 
 namespace nlte {
 void transpose_J(const ColDev& C, double* out, hipStream_t s) {
   const size_t n = (size_t)C.nz * C.nnu;
-  k_transpose_J<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(C.JT, out, C.nz, C.nnu);
+  k_transpose_J<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(C.JT, out, C.nz, C.nnu, C.zp);
 }
 }  // namespace nlte
 
@@ -413,7 +415,7 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
                           int** lbase, WorkPtrs* wp, const int* wsz, int** stage, int** bf_ptr,
                           double** raw) {
   const int nz = C.nz, L = C.L, ntr = C.ntr, nnu = C.nnu, N = C.N;
-  const size_t kf = (size_t)nz * nnu, kfp = (size_t)nz * C.fp;
+  const size_t kf = (size_t)nz * nnu, kfp = (size_t)nz * C.fp, kfz = (size_t)nnu * C.zp;
   C.st = Lo.take<ColState>(1);
   C.z = Lo.take<double>(nz);
   C.dz = Lo.take<double>(nz);
@@ -426,7 +428,7 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.gam = Lo.take<double>(nnu);
   C.Bnu = Lo.take<double>(kf);
   C.Ebf = C.nbf ? Lo.take<double>(kf) : nullptr;
-  C.EbfT = C.nbf ? Lo.take<double>(kf) : nullptr;
+  C.EbfT = C.nbf ? Lo.take<double>(kfz) : nullptr;
   *tr_out = Lo.take<TrDev>(ntr);
   C.tr = *tr_out;
   C.V = Lo.take<double>((size_t)nline_tab * nz + (nwin_total - nline_tab));
@@ -446,7 +448,7 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
     C.Bnuf = Lo.take<float>(kfp);
     C.Ebff = C.nbf ? Lo.take<float>(kfp) : nullptr;
     C.VTf = Lo.take<float>((size_t)nline_tab * nz + 1);
-    C.EbfTf = C.nbf ? Lo.take<float>(kf) : nullptr;
+    C.EbfTf = C.nbf ? Lo.take<float>(kfz) : nullptr;
   } else {
     C.Vf = C.Bnuf = C.Ebff = C.VTf = C.EbfTf = nullptr;
   }
@@ -459,13 +461,13 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.F = Lo.take<double>(N);
   C.G = Lo.take<double>(N);
   C.Jdag = Lo.take<double>(kf);
-  C.JT = Lo.take<double>(kf);
+  C.JT = Lo.take<double>(kfz);
   C.Jm = Lo.take<double>(kfp);
   C.XS = Lo.take<double>(2 * kfp);
   C.Dchi = Lo.take<double>(kfp);
   C.Deta = Lo.take<double>(kfp);
-  C.DchiT = Lo.take<double>(kf);
-  C.DetaT = Lo.take<double>(kf);
+  C.DchiT = Lo.take<double>(kfz);
+  C.DetaT = Lo.take<double>(kfz);
   C.RJ = Lo.take<double>((size_t)nz * std::max(C.nrseg, 1) * 2);
   C.M = Lo.take<double>((size_t)nz * std::max(C.nment, 1) * 2);
   C.P = Lo.take<double>((size_t)nz * L * L);
@@ -526,6 +528,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   C.scan = scan;
   C.nchunk = (nnu + kWave - 1) / kWave;
   C.fp = C.nchunk * kWave;
+  C.zp = (nz + 15) & ~15;
   C.has_sca = 0;
   if (A->chi_sca)
     for (int k = 0; k < nz; ++k)

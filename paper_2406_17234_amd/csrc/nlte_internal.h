@@ -147,6 +147,9 @@ struct ColDev {
   int fp;                          // row pitch of the [nz][nnu] formal-solution scratch and
                                    // FP32 tables: nnu rounded up to a multiple of 64, so that
                                    // a chunk's 64 frequencies start on a cache-line boundary
+  int zp;                          // row pitch of the depth-contiguous [nnu][nz] arrays (J, the
+                                   // derivatives, e^{-h nu/kT}): nz rounded up to a multiple
+                                   // of 16, so that a wave's 64 depths start on a line boundary
   int nchunk, has_sca, N;          // N = nz * L
   int npitem, nment;               // pair-sum blocks, entries of M
   int scan;                        // 1: depth-parallel formal solution (nz <= 256)
@@ -160,7 +163,7 @@ struct ColDev {
   // frequency grid and per-(k, f) tables [nz][nnu]
   const double *nu, *gam;          // gam = 2 h nu^3 / c^2
   const double *Bnu, *Ebf;         // Planck function, exp(-h nu / kT)
-  const double *EbfT;              // [nnu][nz] exp(-h nu / kT), depth-contiguous
+  const double *EbfT;              // [nnu][zp] exp(-h nu / kT), depth-contiguous
   // transitions
   const TrDev *tr;
   const double *V;                 // per-transition V tables
@@ -173,7 +176,7 @@ struct ColDev {
   // FP32 copies of V, Bnu and Ebf read by the FP32-form opacity kernel (NULL
   // for FP64 columns); n-independent, so their rounding adds no noise to F
   const float *Vf, *Bnuf, *Ebff;
-  const float *VTf, *EbfTf;        // FP32 copies of VT and EbfT (rate integrals)
+  const float *VTf, *EbfTf;        // FP32 copies of VT and EbfT (rate integrals; EbfTf [nnu][zp])
   // chunk -> overlapping line windows and edge windows; overlapping transition pairs
   const int *ch_lptr, *ch_line;
   const int *ch_eptr, *ch_edge;
@@ -186,13 +189,13 @@ struct ColDev {
   double *coef;                    // [ntr + 2][nz][2] level coefficients of eval_n
   double *F, *G;                   // [nz][L] residual and gross rates
   double *Jdag;                    // [nz][nnu] lagged mean intensity
-  double *JT;                      // [nnu][nz] J of the last evaluation (depth-contiguous)
+  double *JT;                      // [nnu][zp] J of the last evaluation (depth-contiguous)
   // scratch of the formal solution, in the column's formal-solution precision
   // (buffers sized for doubles):
   double *Jm;                      // [nz][nnu] ingoing-ray part of J (recursion precision)
   double *XS;                      // [nz][nnu][2] chi and S of the first sweep
   double *Dchi, *Deta;             // [nz][nnu] ingoing-ray intensity derivatives
-  double *DchiT, *DetaT;           // [nnu][nz] angle-averaged local intensity derivatives
+  double *DchiT, *DetaT;           // [nnu][zp] angle-averaged local intensity derivatives
   double *RJ;                      // [nz][nrseg][2] rate integrals over J, per segment
   double *M;                       // [nment][nz][2] pair sums of the radiative blocks
   double *P;                       // [nz][L][L] preconditioner blocks of the last Newton-mode evaluation

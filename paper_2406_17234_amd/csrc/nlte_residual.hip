@@ -359,7 +359,7 @@ __device__ __forceinline__ void stage_put(double* tile, int k, int lane, double 
 
 template <int KF, typename TO>
 __device__ __forceinline__ void stage_flush(const double* tile, TO* __restrict__ out, int k0,
-                                            int nz, int f0, int nnu, int lane) {
+                                            int nz, int zp, int f0, int nnu, int lane) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -370,7 +370,7 @@ __device__ __forceinline__ void stage_flush(const double* tile, TO* __restrict__
   for (int i = 0; i < KF; ++i) {
     const int fl = i * FS + fs;
     const double v = tile[kk * kWave + fl];
-    if (k < nz && f0 + fl < nnu) stg(out + (size_t)(f0 + fl) * nz + k, (TO)v);
+    if (k < nz && f0 + fl < nnu) stg(out + (size_t)(f0 + fl) * zp + k, (TO)v);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -400,7 +400,7 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
   double* tX = tile + KF * kWave;
   double* tE = tile + 2 * KF * kWave;
   const int f0 = chunk * kWave;
-  const int nz = C.nz, nnu = C.nnu, fp = C.fp;
+  const int nz = C.nz, nnu = C.nnu, fp = C.fp, zp = C.zp;
   const int f = chunk * kWave + lane;
   const bool fin = f < nnu;
   const int fc = fin ? f : nnu - 1;
@@ -549,10 +549,10 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
       stage_put<KF>(tE, nz - 1, lane, (double)ldg(des + kf));
     }
     if ((nz - 1) % KF == 0) {
-      stage_flush<KF>(tJ, C.JT, nz - 1, nz, f0, nnu, lane);
+      stage_flush<KF>(tJ, C.JT, nz - 1, nz, zp, f0, nnu, lane);
       if (PM) {
-        stage_flush<KF>(tX, C.DchiT, nz - 1, nz, f0, nnu, lane);
-        stage_flush<KF>(tE, C.DetaT, nz - 1, nz, f0, nnu, lane);
+        stage_flush<KF>(tX, C.DchiT, nz - 1, nz, zp, f0, nnu, lane);
+        stage_flush<KF>(tE, C.DetaT, nz - 1, nz, zp, f0, nnu, lane);
       }
     }
   }
@@ -583,10 +583,10 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
       stage_put<KF>(tE, k, lane, (double)dE_k + (double)(sa * rc));
     }
     if (k % KF == 0) {
-      stage_flush<KF>(tJ, C.JT, k, nz, f0, nnu, lane);
+      stage_flush<KF>(tJ, C.JT, k, nz, zp, f0, nnu, lane);
       if (PM) {
-        stage_flush<KF>(tX, C.DchiT, k, nz, f0, nnu, lane);
-        stage_flush<KF>(tE, C.DetaT, k, nz, f0, nnu, lane);
+        stage_flush<KF>(tX, C.DchiT, k, nz, zp, f0, nnu, lane);
+        stage_flush<KF>(tE, C.DetaT, k, nz, zp, f0, nnu, lane);
       }
     }
     chi_n = chi;
@@ -813,7 +813,7 @@ __global__ __launch_bounds__(kScanThreads) void k_formal_scan(const ColDev* __re
     __syncthreads();  // the coefficient and intensity rows are rewritten for the next angle
   }
   if (in) {
-    const size_t fk = (size_t)f * nz + t;
+    const size_t fk = (size_t)f * uni(C.zp) + t;
     stg(C.JT + fk, jac);
     if (PM) {
       stg(C.DchiT + fk, dX);
@@ -917,12 +917,13 @@ __device__ __forceinline__ void rates_item(const ColDev& C, int sg, int k0) {
 template <typename TB>
 __device__ __forceinline__ void rates_sum(const ColDev& C, const RSeg& seg, int sg, int k0,
                                           const TB* __restrict__ VTt, const TB* __restrict__ EbfTt) {
-  const int nz = C.nz;
+  // line tables have rows of nz depths, J and e^{-h nu/kT} rows of zp
+  const int nz = C.nz, zp = C.zp;
   const int k = k0 + threadIdx.x;
   if (k >= nz) return;
   const int t = seg.t, q0 = seg.q0;
   const int wl = seg.q1 - q0, wo = seg.wo;  // length, offset in the window
-  const double* __restrict__ J = C.JT + (size_t)q0 * nz + k;
+  const double* __restrict__ J = C.JT + (size_t)q0 * zp + k;
   const double* __restrict__ cw = C.cw + seg.cwoff + wo;
   double* dst = C.RJ + ((size_t)k * C.nrseg + sg) * 2;
   if (t < C.nline) {
@@ -932,32 +933,32 @@ __device__ __forceinline__ void rates_sum(const ColDev& C, const RSeg& seg, int 
     for (; q + 4 <= wl; q += 4) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const size_t o = (size_t)(q + u) * nz;
-        s[u] = fma(cw[q + u] * (double)ldg(V + o), (double)ldg(J + o), s[u]);
+        const size_t ov = (size_t)(q + u) * nz, oj = (size_t)(q + u) * zp;
+        s[u] = fma(cw[q + u] * (double)ldg(V + ov), (double)ldg(J + oj), s[u]);
       }
     }
     for (; q < wl; ++q) {
-      const size_t o = (size_t)q * nz;
-      s[0] = fma(cw[q] * (double)ldg(V + o), (double)ldg(J + o), s[0]);
+      const size_t ov = (size_t)q * nz, oj = (size_t)q * zp;
+      s[0] = fma(cw[q] * (double)ldg(V + ov), (double)ldg(J + oj), s[0]);
     }
     stg(dst, (s[0] + s[1]) + (s[2] + s[3]));
     stg(dst + 1, 0.0);
   } else {
     const double* __restrict__ A = C.V + seg.voff + wo;
-    const TB* __restrict__ E = EbfTt + (size_t)q0 * nz + k;
+    const TB* __restrict__ E = EbfTt + (size_t)q0 * zp + k;
     double s1[4] = {0.0, 0.0, 0.0, 0.0}, s2[4] = {0.0, 0.0, 0.0, 0.0};
     int q = 0;
     for (; q + 4 <= wl; q += 4) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const size_t o = (size_t)(q + u) * nz;
+        const size_t o = (size_t)(q + u) * zp;
         const double x = (cw[q + u] * A[q + u]) * (double)ldg(J + o);
         s1[u] += x;
         s2[u] = fma(x, (double)ldg(E + o), s2[u]);
       }
     }
     for (; q < wl; ++q) {
-      const size_t o = (size_t)q * nz;
+      const size_t o = (size_t)q * zp;
       const double x = (cw[q] * A[q]) * (double)ldg(J + o);
       s1[0] += x;
       s2[0] = fma(x, (double)ldg(E + o), s2[0]);
@@ -1031,9 +1032,10 @@ __device__ __forceinline__ void pair_block(const ColDev& C, const PItem& it, int
     us[j] = SAME ? ts[j] : pair_side(C, u, f0, k);
     edge |= u >= C.nline;
   }
-  const double* DX = C.DchiT + (size_t)f0 * nz + k;
-  const double* DE = C.DetaT + (size_t)f0 * nz + k;
-  const double* EB = edge ? C.EbfT + (size_t)f0 * nz + k : DX;  // DX: any valid address
+  const int zp = C.zp;  // rows of the derivatives and of e^{-h nu/kT}
+  const double* DX = C.DchiT + (size_t)f0 * zp + k;
+  const double* DE = C.DetaT + (size_t)f0 * zp + k;
+  const double* EB = edge ? C.EbfT + (size_t)f0 * zp + k : DX;  // DX: any valid address
   const double* gam = C.gam + f0;
   double m1[NT][NU], m2[NT][NU];
 #pragma unroll
@@ -1041,7 +1043,7 @@ __device__ __forceinline__ void pair_block(const ColDev& C, const PItem& it, int
 #pragma unroll
     for (int j = 0; j < NU; ++j) m1[i][j] = m2[i][j] = 0.0;
   for (int q = 0; q < nf; ++q) {
-    const size_t o = (size_t)q * nz;
+    const size_t o = (size_t)q * zp;
     const double dx = ldg(DX + o), de = ldg(DE + o);
     const double E = edge ? ldg(EB + o) : 0.0;
     const double dd = gam[q] * de - dx;

@@ -344,7 +344,7 @@ __device__ void accept_point(const ColDev& C, double* red, int* done_count) {
   if (C.has_sca)
     for (int i = threadIdx.x; i < C.nz * C.nnu; i += kThreads) {
       const int k = i / C.nnu, f = i - k * C.nnu;
-      C.Jdag[i] = C.JT[(size_t)f * C.nz + k];
+      C.Jdag[i] = C.JT[(size_t)f * C.zp + k];
     }
   __syncthreads();
   if (threadIdx.x == 0) st->rho_cur = rho;
