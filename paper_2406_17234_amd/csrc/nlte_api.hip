@@ -453,7 +453,7 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
     C.Vf = C.Bnuf = C.Ebff = C.VTf = C.EbfTf = nullptr;
   }
   C.coef = Lo.take<double>((size_t)nz * ncoef(ntr));
-  C.rseg = Lo.take<RSeg>(std::max(C.nrseg, 1));
+  C.ritem = Lo.take<RItem>(std::max(C.nritem, 1));
   C.pitem = Lo.take<PItem>(std::max(C.npitem, 1));
   C.pg_ptr = Lo.take<int>(L * L + 1);
   C.pg_code = Lo.take<int>(4 * ntr + 4 * std::max(C.nment, 1));
@@ -594,20 +594,12 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
       if (tr[t].wlo < f1 && tr[t].whi > f0) ch_ed.push_back(t);
     ch_eptr[c + 1] = (int)ch_ed.size();
   }
-  // frequency segments of the rate integrals and of the window intersections
+  // pieces of the frequency axis: cut at every window edge (and into at most
+  // seg_len frequencies), so that each piece lies inside or outside every
+  // window.  The rate integrals of the s transitions covering a piece run as
+  // blocks of up to kRateBlk lines and kRateBlk edges; the pair sums give the
+  // piece s^2 entries (t, t') and run as blocks of at most kPairBlk^2 of them
   const int seg_len = scan ? kSegLenScan : kSegLen;
-  std::vector<RSeg> rseg;
-  for (int t = 0; t < ntr; ++t) {
-    tr[t].sfirst = (int)rseg.size();
-    for (int a = tr[t].wlo; a < tr[t].whi; a += seg_len)
-      rseg.push_back(RSeg{t, a, std::min(a + seg_len, tr[t].whi), a - tr[t].wlo, tr[t].voff,
-                          tr[t].cwoff, 0, 0});
-    tr[t].nseg = (int)rseg.size() - tr[t].sfirst;
-  }
-  C.nrseg = (int)rseg.size();
-  // pair-sum pieces: cut at every window edge, so that each piece lies
-  // inside or outside every window; s transitions cover a piece, which gets
-  // s^2 entries (t, t') and runs as blocks of at most kPairBlk^2 of them
   std::vector<int> cuts;
   for (int t = 0; t < ntr; ++t) {
     cuts.push_back(tr[t].wlo);
@@ -616,7 +608,9 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   std::sort(cuts.begin(), cuts.end());
   cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
   std::vector<PItem> pitem;
+  std::vector<RItem> ritem;
   std::vector<int2> ment;  // (t, t') of each entry
+  std::vector<int> rcount(ntr, 0);  // rate entries per transition so far
   for (size_t c = 0; c + 1 < cuts.size(); ++c) {
     std::vector<int> A;
     for (int t = 0; t < ntr; ++t)
@@ -624,6 +618,22 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     const int s = (int)A.size();
     for (int a = cuts[c]; s > 0 && a < cuts[c + 1]; a += seg_len) {
       const int b = std::min(a + seg_len, cuts[c + 1]);
+      // rate blocks: lines and edges of A (A is sorted, lines first)
+      std::vector<int> Ln, Ed;
+      for (int t : A) (t < nline ? Ln : Ed).push_back(t);
+      for (size_t li = 0, ei = 0; li < Ln.size() || ei < Ed.size();) {
+        RItem R{};
+        R.f0 = a;
+        R.f1 = b;
+        R.nl = (int)std::min<size_t>(kRateBlk, Ln.size() - li);
+        R.ne = (int)std::min<size_t>(kRateBlk, Ed.size() - ei);
+        for (int i = 0; i < R.nl; ++i) R.t[i] = Ln[li + i];
+        for (int i = 0; i < R.ne; ++i) R.t[R.nl + i] = Ed[ei + i];
+        for (int i = 0; i < R.nl + R.ne; ++i) R.e[i] = rcount[R.t[i]]++;  // ordinal, offset below
+        li += R.nl;
+        ei += R.ne;
+        ritem.push_back(R);
+      }
       const int e0 = (int)ment.size();
       for (int i = 0; i < s; ++i)
         for (int j = 0; j < s; ++j) ment.push_back(make_int2(A[i], A[j]));
@@ -645,6 +655,19 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   }
   C.npitem = (int)pitem.size();
   C.nment = (int)ment.size();
+  // rate entries: transition by transition, each in frequency order
+  {
+    int first = 0;
+    for (int t = 0; t < ntr; ++t) {
+      tr[t].sfirst = first;
+      tr[t].nseg = rcount[t];
+      first += rcount[t];
+    }
+    for (RItem& R : ritem)
+      for (int i = 0; i < R.nl + R.ne; ++i) R.e[i] += tr[R.t[i]].sfirst;
+    C.nrseg = first;
+    C.nritem = (int)ritem.size();
+  }
   // gather lists of the preconditioner blocks: entry (i, j) sums
   //   Gamma: (lo,lo) += C_lu+R_lu, (up,up) += C_ul+R_ul, (lo,up) -= C_ul+R_ul, (up,lo) -= C_lu+R_lu
   //   entries: (lo_t,lo_u) += M1, (up_t,lo_u) -= M1, (lo_t,up_u) += M2, (up_t,up_u) -= M2
@@ -737,7 +760,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   UP(C.ch_line, ch_tr.data(), ch_tr.size() * 4);
   UP(C.ch_eptr, ch_eptr.data(), ch_eptr.size() * 4);
   UP(C.ch_edge, ch_ed.data(), ch_ed.size() * 4);
-  UP(C.rseg, rseg.data(), rseg.size() * sizeof(RSeg));
+  UP(C.ritem, ritem.data(), ritem.size() * sizeof(RItem));
   UP(C.pitem, pitem.data(), pitem.size() * sizeof(PItem));
   UP(wp.rate, rate_w.data(), rate_w.size() * sizeof(int4));
   UP(wp.pb, prec_w.data(), prec_w.size() * sizeof(int2));

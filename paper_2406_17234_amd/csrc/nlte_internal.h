@@ -91,7 +91,7 @@ struct TrDev {
   int wlo, whi;     // window on the union grid [wlo, whi)
   int voff;         // offset of its V table (lines: [nz][wlen]; edges: [wlen])
   int cwoff;        // offset of its rate weights 4 pi w / (h nu) [wlen]
-  int sfirst, nseg; // its frequency segments in ColDev::rseg
+  int sfirst, nseg; // its rate entries (one per piece of its window)
   double g;         // lines: g_l / g_u
   double Blu;       // lines: Einstein B_lu (for the profile-averaged intensity)
 };
@@ -130,11 +130,16 @@ struct ColState {
 // transitions t[i] and u[j] and is entry e0 + i * es + j.
 constexpr int kPairBlk = 4;
 
-// One rate-integral segment: frequencies [q0, q1) of transition t's window,
-// wo = q0 - (window start); voff, cwoff: the transition's table offsets.
-struct RSeg {
-  int t, q0, q1, wo;
-  int voff, cwoff, pad0, pad1;
+// Rate integrals run over the same pieces as the pair sums.  One block of a
+// piece: frequencies [f0, f1), nl lines t[0..nl) and ne edges t[nl..nl+ne)
+// among the transitions covering it (at most kRateBlk of each); the partial
+// sums of t[i] go to rate entry e[i].  A transition's entries are numbered
+// in frequency order (TrDev::sfirst, nseg), and the assembly adds them in
+// that order.
+constexpr int kRateBlk = 4;
+struct RItem {
+  int f0, f1, nl, ne;
+  int t[2 * kRateBlk], e[2 * kRateBlk];
 };
 struct PItem {
   int f0, f1, nt, nu;
@@ -153,7 +158,7 @@ struct ColDev {
   int nchunk, has_sca, N;          // N = nz * L
   int npitem, nment;               // pair-sum blocks, entries of M
   int scan;                        // 1: depth-parallel formal solution (nz <= 256)
-  int nrseg;                       // frequency segments of the rate integrals
+  int nrseg, nritem;               // rate-integral entries (partial sums) and blocks
   // angles (inline: at most kMaxMu)
   double wm2[kMaxMu];     // w_m / 2
   double inv2mu[kMaxMu];  // 1 / (2 mu_m)
@@ -180,7 +185,7 @@ struct ColDev {
   // chunk -> overlapping line windows and edge windows; overlapping transition pairs
   const int *ch_lptr, *ch_line;
   const int *ch_eptr, *ch_edge;
-  const RSeg *rseg;                // rate-integral segments
+  const RItem *ritem;              // rate-integral blocks
   const PItem *pitem;              // blocks of the preconditioner pair sums
   const int *pg_ptr, *pg_code;     // per block entry (i, j): contributions, see k_pblock
   // evaluation buffers

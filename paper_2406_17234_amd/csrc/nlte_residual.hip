@@ -24,8 +24,8 @@
 //   k_formal_scan: the same for columns created with NLTE_DEPTH_SCAN, as
 //               parallel scans of affine maps over depth (one workgroup per
 //               frequency, one thread per depth).
-//   k_depthwork: one lane per depth, one wavefront per (column, frequency
-//               segment, 64 depths): rate integrals summed in frequency order
+//   k_depthwork: one lane per depth, one wavefront per (column, block of a
+//               piece, 64 depths): rate integrals summed in frequency order
 //               (no cross-lane reductions, independent of batching), and in
 //               Newton mode the preconditioner pair sums, per (column, piece
 //               of constant transition set, block of pairs, 64 depths).
@@ -875,97 +875,107 @@ static void launch_formal_mu(int nmu, int wpb, hipStream_t s, const ColDev* cols
 
 // ---------------------------------------------------------------------------
 // rate integrals (Eqs. Rij, Rji): one lane per depth, sequential sums over
-// each transition window (depth-contiguous operands, so every load of a
-// wave is one contiguous run).  Lines: sum cw V J.  Edges: sum cw alpha J and
-// sum cw alpha exp(-h nu/kT) J (the J part of R_ul without its depth factor).
-// Every term is positive and a segment holds at most kSegLen frequencies, so
-// four interleaved FP64 partial sums, added in a fixed order, stay within
-// about kSegLen/4 roundings (below 2e-14 relative); the four chains also let
-// a wave keep four iterations' loads in flight.  Segments of a transition
-// are added with compensation in the assembly.
+// the frequencies of a piece for every transition covering it (depth-
+// contiguous operands, so every load of a wave is one contiguous run).
+// Lines: sum cw V J.  Edges: sum cw alpha J and sum cw alpha exp(-h nu/kT) J
+// (the J part of R_ul without its depth factor).  A block loads J (and
+// e^{-h nu/kT}) once per frequency for all its transitions.  Every term is
+// positive and a piece holds at most kSegLen frequencies, so each partial
+// sum stays within kSegLen roundings (below 6e-14 relative); the assembly
+// adds the pieces of a transition in frequency order.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void neumaier(double& s, double& c, double x) {
-  const double u = s + x;
-  c += (fabs(s) >= fabs(x)) ? (s - u) + x : (x - u) + s;
-  s = u;
+// TB: line-table precision (float for FP32-form evaluations).  J stays FP64
+// here: in the FP32 form a J rounded to FP32 before these sums sets a noise
+// floor on F that doubled the share of columns needing the FP64 fallback.
+template <typename TB, int NL, int NE>
+__device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, int k,
+                                            const TB* __restrict__ VTt, const TB* __restrict__ EbfTt) {
+  const int nz = C.nz, zp = C.zp, f0 = it.f0, nf = it.f1 - it.f0;
+  const TB* vl[NL > 0 ? NL : 1];      // line V at f0, this lane's depth (rows of nz)
+  const double* cl[NL > 0 ? NL : 1];  // line rate weights at f0
+  const double* ae[NE > 0 ? NE : 1];  // edge cross-sections at f0
+  const double* ce[NE > 0 ? NE : 1];  // edge rate weights at f0
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const TrDev& T = C.tr[it.t[i]];
+    const int wo = f0 - uni(T.wlo);
+    vl[i] = VTt + uni(T.voff) + (size_t)wo * nz + k;
+    cl[i] = C.cw + uni(T.cwoff) + wo;
+  }
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const TrDev& T = C.tr[it.t[NL + i]];
+    const int wo = f0 - uni(T.wlo);
+    ae[i] = C.V + uni(T.voff) + wo;
+    ce[i] = C.cw + uni(T.cwoff) + wo;
+  }
+  const double* __restrict__ J = C.JT + (size_t)f0 * zp + k;
+  const TB* __restrict__ E = NE > 0 ? EbfTt + (size_t)f0 * zp + k : nullptr;
+  double sl[NL > 0 ? NL : 1], s1[NE > 0 ? NE : 1], s2[NE > 0 ? NE : 1];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) sl[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < NE; ++i) s1[i] = s2[i] = 0.0;
+#pragma unroll 4
+  for (int q = 0; q < nf; ++q) {
+    const size_t o = (size_t)q * zp;
+    const double j = ldg(J + o);
+#pragma unroll
+    for (int i = 0; i < NL; ++i) sl[i] = fma(cl[i][q] * (double)ldg(vl[i] + (size_t)q * nz), j, sl[i]);
+    if (NE > 0) {
+      const double e = (double)ldg(E + o);
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const double x = (ce[i][q] * ae[i][q]) * j;
+        s1[i] += x;
+        s2[i] = fma(x, e, s2[i]);
+      }
+    }
+  }
+  double* row = C.RJ + (size_t)k * C.nrseg * 2;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    stg(row + 2 * it.e[i], sl[i]);
+    stg(row + 2 * it.e[i] + 1, 0.0);
+  }
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    stg(row + 2 * it.e[NL + i], s1[i]);
+    stg(row + 2 * it.e[NL + i] + 1, s2[i]);
+  }
 }
 
-// TB: table precision (float for FP32-form columns).  J stays FP64 here: in
-// the FP32 form a J rounded to FP32 before these sums sets a noise floor on
-// F that doubled the share of columns needing the FP64 fallback.
 template <typename TB>
-__device__ __forceinline__ void rates_sum(const ColDev& C, const RSeg& seg, int sg, int k0,
-                                          const TB* __restrict__ VTt, const TB* __restrict__ EbfTt);
+__device__ __forceinline__ void rates_shape(const ColDev& C, const RItem& it, int k,
+                                            const TB* __restrict__ VTt, const TB* __restrict__ EbfTt) {
+  switch (it.nl * 8 + it.ne) {
+#define RB(L, E) \
+  case L * 8 + E: rates_block<TB, L, E>(C, it, k, VTt, EbfTt); break;
+    RB(0, 1) RB(0, 2) RB(0, 3) RB(0, 4)
+    RB(1, 0) RB(1, 1) RB(1, 2) RB(1, 3) RB(1, 4)
+    RB(2, 0) RB(2, 1) RB(2, 2) RB(2, 3) RB(2, 4)
+    RB(3, 0) RB(3, 1) RB(3, 2) RB(3, 3) RB(3, 4)
+    RB(4, 0) RB(4, 1) RB(4, 2) RB(4, 3) RB(4, 4)
+#undef RB
+    default: break;
+  }
+}
 
-// The column state and the segment descriptor are read with independent
+// The column state and the block descriptor are read with independent
 // scalar loads, so that a wave waits for one memory round trip, not three,
 // before its first table loads.  The tables follow the evaluation's
 // precision, so that an FP32-form column after its FP64 fallback evaluates
 // the same F as an FP64 column.
-__device__ __forceinline__ void rates_item(const ColDev& C, int sg, int k0) {
+__device__ __forceinline__ void rates_item(const ColDev& C, int b, int k0) {
   const int mode = ldc(&C.st->mode), prec = ldc(&C.st->cur_prec);
-  const RSeg seg = ldc_rec(C.rseg + sg);
+  const RItem it = ldc_rec(C.ritem + b);
   if (mode == kModeIdle) return;
-  if (prec == NLTE_FP32_FORM)
-    rates_sum<float>(C, seg, sg, k0, C.VTf, C.EbfTf);
-  else
-    rates_sum<double>(C, seg, sg, k0, C.VT, C.EbfT);
-}
-
-// One frequency segment [q0, q1) of transition t's window; the assembly adds
-// the segments of a transition in order.
-template <typename TB>
-__device__ __forceinline__ void rates_sum(const ColDev& C, const RSeg& seg, int sg, int k0,
-                                          const TB* __restrict__ VTt, const TB* __restrict__ EbfTt) {
-  // line tables have rows of nz depths, J and e^{-h nu/kT} rows of zp
-  const int nz = C.nz, zp = C.zp;
   const int k = k0 + threadIdx.x;
-  if (k >= nz) return;
-  const int t = seg.t, q0 = seg.q0;
-  const int wl = seg.q1 - q0, wo = seg.wo;  // length, offset in the window
-  const double* __restrict__ J = C.JT + (size_t)q0 * zp + k;
-  const double* __restrict__ cw = C.cw + seg.cwoff + wo;
-  double* dst = C.RJ + ((size_t)k * C.nrseg + sg) * 2;
-  if (t < C.nline) {
-    const TB* __restrict__ V = VTt + seg.voff + (size_t)wo * nz + k;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    int q = 0;
-    for (; q + 4 <= wl; q += 4) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const size_t ov = (size_t)(q + u) * nz, oj = (size_t)(q + u) * zp;
-        s[u] = fma(cw[q + u] * (double)ldg(V + ov), (double)ldg(J + oj), s[u]);
-      }
-    }
-    for (; q < wl; ++q) {
-      const size_t ov = (size_t)q * nz, oj = (size_t)q * zp;
-      s[0] = fma(cw[q] * (double)ldg(V + ov), (double)ldg(J + oj), s[0]);
-    }
-    stg(dst, (s[0] + s[1]) + (s[2] + s[3]));
-    stg(dst + 1, 0.0);
-  } else {
-    const double* __restrict__ A = C.V + seg.voff + wo;
-    const TB* __restrict__ E = EbfTt + (size_t)q0 * zp + k;
-    double s1[4] = {0.0, 0.0, 0.0, 0.0}, s2[4] = {0.0, 0.0, 0.0, 0.0};
-    int q = 0;
-    for (; q + 4 <= wl; q += 4) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const size_t o = (size_t)(q + u) * zp;
-        const double x = (cw[q + u] * A[q + u]) * (double)ldg(J + o);
-        s1[u] += x;
-        s2[u] = fma(x, (double)ldg(E + o), s2[u]);
-      }
-    }
-    for (; q < wl; ++q) {
-      const size_t o = (size_t)q * zp;
-      const double x = (cw[q] * A[q]) * (double)ldg(J + o);
-      s1[0] += x;
-      s2[0] = fma(x, (double)ldg(E + o), s2[0]);
-    }
-    stg(dst, (s1[0] + s1[1]) + (s1[2] + s1[3]));
-    stg(dst + 1, (s2[0] + s2[1]) + (s2[2] + s2[3]));
-  }
+  if (k >= C.nz) return;
+  if (prec == NLTE_FP32_FORM)
+    rates_shape<float>(C, it, k, C.VTf, C.EbfTf);
+  else
+    rates_shape<double>(C, it, k, C.VT, C.EbfT);
 }
 
 // ---------------------------------------------------------------------------
@@ -1097,7 +1107,7 @@ __device__ __forceinline__ void pair_item(const ColDev& C, int p, int k0) {
   }
 }
 
-// Rate integrals of a step: one item per (column, frequency segment, 64
+// Rate integrals of a step: one item per (column, rate block of a piece, 64
 // depths), lane per depth.
 __global__ __launch_bounds__(64) void k_depthwork(const ColDev* __restrict__ cols,
                                                   const int4* __restrict__ work, int nwork) {
@@ -1162,18 +1172,14 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble(const ColDev* __restri
       const int kk = id / nt, tt = id - kk * nt;
       const int k = k0 + kk, t = t0 + tt;
       const TrDev& T = C.tr[t];
-      const double* __restrict__ rj = C.RJ + (size_t)k * nrseg * 2;
-      // the transition's segments, added in order (compensated)
-      const int s0 = T.sfirst, ns = T.nseg;
-      double Rlu = ldg(rj + 2 * s0), Rx = ldg(rj + 2 * s0 + 1);
-      if (ns > 1) {
-        double c0 = 0.0, c1 = 0.0;
-        for (int q = 1; q < ns; ++q) {
-          neumaier(Rlu, c0, ldg(rj + 2 * (s0 + q)));
-          neumaier(Rx, c1, ldg(rj + 2 * (s0 + q) + 1));
-        }
-        Rlu += c0;
-        Rx += c1;
+      const double* __restrict__ rj = C.RJ + ((size_t)k * nrseg + T.sfirst) * 2;
+      // the transition's pieces, added in frequency order (positive terms,
+      // a few dozen at most: plain sums stay within 1e-14 relative)
+      const int ns = T.nseg;
+      double Rlu = ldg(rj), Rx = ldg(rj + 1);
+      for (int q = 1; q < ns; ++q) {
+        Rlu += ldg(rj + 2 * q);
+        Rx += ldg(rj + 2 * q + 1);
       }
       const size_t kt = (size_t)k * ntr + t;
       const double Rsp = ldg(C.Rsp + kt);
@@ -1457,8 +1463,8 @@ int build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
     const int c = sel[q];
     const ColDev& C = hc[c];
     maxL = std::max(maxL, C.L);
-    for (int sg = 0; sg < C.nrseg; ++sg)
-      for (int k0 = 0; k0 < C.nz; k0 += kWave) rate.push_back(make_int4(c, sg, k0, 0));
+    for (int b = 0; b < C.nritem; ++b)
+      for (int k0 = 0; k0 < C.nz; k0 += kWave) rate.push_back(make_int4(c, b, k0, 0));
   }
   const int nrate0 = (int)rate.size();
   for (int q = 0; q < nsel; ++q) {
