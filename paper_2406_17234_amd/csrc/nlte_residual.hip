@@ -30,7 +30,7 @@
 //               Newton mode the preconditioner pair sums, per (column, piece
 //               of constant transition set, block of pairs, 64 depths).
 //   k_assemble: rates, rate-equation residual, conservation rows, scaled
-//               residual per depth; one block per (column, 32 depths).
+//               residual per depth; one block per (column, 16 depths).
 //   k_pblock  : Newton mode; the preconditioner blocks from the total rates
 //               and the pair sums.
 #include "nlte_internal.h"
@@ -1144,7 +1144,7 @@ __global__ __launch_bounds__(64) void k_pairsum(const ColDev* __restrict__ cols,
 // and phase 3 sets the conservation row and writes F, G and the per-depth
 // scaled residual.  Transitions go through LDS kAsmTr at a time.
 constexpr int kAsmThreads = 256;
-constexpr int kAsmDepths = 32;
+constexpr int kAsmDepths = 16;
 constexpr int kAsmTr = 64;
 
 __global__ __launch_bounds__(kAsmThreads) void k_assemble(const ColDev* __restrict__ cols,
