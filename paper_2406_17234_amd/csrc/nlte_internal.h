@@ -263,7 +263,7 @@ struct BatchWork {
   const int* act = nullptr;       // columns the lists cover (NULL: all ncol), device
   int nact = 0;
   int opac_depths = 8;            // launch shapes (tuned by residual plans): depths per
-  int formal_wpb = 4;             // opacity wave (4, 8, 16); waves per formal block (1, 2, 4)
+  int formal_wpb = 1;             // opacity wave (4, 8, 16); waves per formal block (1, 2, 4)
   const int4* rate_work = nullptr;  // (col, segment or block, first depth, kind)
   const int2* pb_work = nullptr;  // (col, first depth-entry index)
   int ncol = 0, ntiles = 0, nrate = 0, npb = 0;
