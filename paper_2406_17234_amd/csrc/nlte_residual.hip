@@ -232,7 +232,8 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
                                                  int nsplit) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int wid = blockIdx.x * (blockDim.x >> 6) + wave;
+  // a column's chunks and depth groups on one XCD (shared coefficients)
+  const int wid = xcd_item(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
   const int tid = wid / nsplit, part = wid - tid * nsplit;
   if (tid >= ntiles) return;
   const int col = uni(tiles[tid].col);
@@ -726,7 +727,8 @@ template <typename R, bool PM, int NMU>
 __global__ __launch_bounds__(kScanThreads) void k_formal_scan(const ColDev* __restrict__ cols,
                                                               const Tile* __restrict__ tiles,
                                                               int ntiles) {
-  const int tile = blockIdx.x >> 6, fl = blockIdx.x & 63;
+  const int b = xcd_item(blockIdx.x, gridDim.x);  // a column's frequencies on one XCD
+  const int tile = b >> 6, fl = b & 63;
   if (tile >= ntiles) return;
   const int col = uni(tiles[tile].col), chunk = uni(tiles[tile].chunk);
   const ColDev& C = cols[col];
@@ -844,7 +846,10 @@ __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
                                                 int fused) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int tid = blockIdx.x * (blockDim.x >> 6) + wave;
+  // the chunks of a column are consecutive tiles: keeping them on one XCD
+  // lets them share the column's level coefficients and the table lines
+  // their rows have in common in that XCD's L2
+  const int tid = xcd_item(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
   if (tid >= ntiles) return;
   const int col = uni(tiles[tid].col);
   const int chunk = uni(tiles[tid].chunk);
