@@ -496,6 +496,56 @@ def matvec_restart(matvec, x):
 
 
 # ----------------------------------------------------------------------------
+# Krylov solver (Sect. 2.3): BiCGSTAB, the paper's second inner solver
+# ----------------------------------------------------------------------------
+
+def bicgstab(matvec, b, rtol=1e-3, maxit=200):
+    """BiCGSTAB (van der Vorst 1992, as cited in Sect. 2.3): Lanczos-type
+    bi-orthogonal directions with a one-parameter minimal-residual smoothing
+    step, two products with A per iteration.  x0 = 0, shadow residual r^ =
+    r0 = b; stops when ||r|| <= rtol ||b|| (checked on the half-step residual
+    s and on r), on a breakdown (rho or (r^, v) or omega zero), or after
+    maxit products.  Returns (x, products, final relative residual)."""
+    N = b.size
+    x = np.zeros(N)
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return x, 0, 0.0
+    r = b.copy()
+    rh = b.copy()
+    p = r.copy()
+    rho = rh @ r
+    products = 0
+    rel = 1.0
+    while products < maxit:
+        v = matvec(p)
+        products += 1
+        den = rh @ v
+        if den == 0.0 or rho == 0.0:
+            break
+        alpha = rho / den
+        s_ = r - alpha * v
+        rel = np.linalg.norm(s_) / bnorm
+        if rel <= rtol or products >= maxit:
+            x = x + alpha * p
+            break
+        t = matvec(s_)
+        products += 1
+        tt = t @ t
+        omega = (t @ s_) / tt if tt > 0.0 else 0.0
+        x = x + alpha * p + omega * s_
+        r = s_ - omega * t
+        rel = np.linalg.norm(r) / bnorm
+        if rel <= rtol or omega == 0.0:
+            break
+        rho_new = rh @ r
+        beta = (rho_new / rho) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        rho = rho_new
+    return x, products, rel
+
+
+# ----------------------------------------------------------------------------
 # Newton driver (Sect. 2.2, Algorithm 2)
 # ----------------------------------------------------------------------------
 
@@ -546,14 +596,15 @@ def positivity_limit(n, dn, frac=0.9):
 
 def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
           max_krylov=200, max_halvings=8, Jdag0=None, eps_mach=2.0 ** -52,
-          verbose=False):
+          verbose=False, krylov="gmres"):
     """JFNK solve of F(n) = 0 (Algorithm 2) with left block-Jacobi
     preconditioning, populations scaled by the Newton iterate for the
     finite-difference product, per-depth positivity limiting and damped
     backtracking (Sect. 2.2.2).  The backtracking compares the norm the Krylov
     step reduces, ||D^-1 P^-1 F||_2 with the iterate's P, D and conservation
     rows held fixed, and asks for an Armijo decrease (1 - 1e-4 alpha).
-    Convergence: ||rho||_inf <= ftol.
+    Convergence: ||rho||_inf <= ftol.  krylov: "gmres" (GMRES(m)) or
+    "bicgstab" (max_krylov then counts products with the Jacobian).
 
     Returns a namespace with n, J, history and call counts (one call per
     formal solution; re-assigning conservation rows at an accepted point
@@ -588,7 +639,10 @@ def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
 
         b = -(lu_solve_blocks(lus, F0) / D).ravel()
         phi0 = np.linalg.norm(b)
-        u, kit, krel = gmres(matvec, b, rtol=rtol, m=m, maxit=max_krylov)
+        if krylov == "bicgstab":
+            u, kit, krel = bicgstab(matvec, b, rtol=rtol, maxit=max_krylov)
+        else:
+            u, kit, krel = gmres(matvec, b, rtol=rtol, m=m, maxit=max_krylov)
         dn = D * u.reshape(n.shape)
         lam = positivity_limit(n, dn)[:, None]
         alpha = 1.0

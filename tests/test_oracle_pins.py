@@ -247,6 +247,29 @@ def test_gmres_solves_small_system():
     assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-9, atol=1e-11)
 
 
+def test_bicgstab_solves_small_system():
+    """The oracle's BiCGSTAB against a direct solve of a nonsymmetric
+    system (a library routine, not the method under test)."""
+    rng = np.random.default_rng(3)
+    A = np.eye(40) + 0.3 * rng.standard_normal((40, 40)) / np.sqrt(40)
+    b = rng.standard_normal(40)
+    x, k, rel = O.bicgstab(lambda v: A @ v, b, rtol=1e-12, maxit=400)
+    assert rel <= 1e-12
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-9, atol=1e-11)
+
+
+def test_bicgstab_two_eigenvalues_one_iteration():
+    """A diagonal operator with two distinct eigenvalues: the first
+    iteration's step (BiCG direction plus the minimal-residual omega) already
+    spans its minimal polynomial, so the residual vanishes after two
+    products, to rounding."""
+    d = np.where(np.arange(30) % 2 == 0, 2.0, 5.0)
+    b = np.linspace(1.0, 2.0, 30)
+    x, k, rel = O.bicgstab(lambda v: d * v, b, rtol=1e-13, maxit=50)
+    assert k <= 4 and rel <= 1e-13
+    assert np.allclose(x, b / d, rtol=1e-12)
+
+
 def test_zero_radiation_guess_satisfies_rate_equations():
     """The radiation-free guess solves F = 0 with J forced to zero."""
     tb = O.setup(S.chromo6(nz=20, nnu=120))
@@ -268,6 +291,16 @@ def test_jfnk_root_equals_dense_newton_root(tiny_tb):
     assert np.max(np.abs(s.n / nd - 1)) < 1e-11
     # particle conservation at convergence
     assert np.max(np.abs(s.n.sum(axis=1) / tb.ntot - 1)) < 1e-13
+
+
+def test_jfnk_bicgstab_root_equals_gmres_root(tiny_tb):
+    """Both inner solvers of the paper (Sect. 3.2: they converge to the same
+    solution) reach the dense-Newton root."""
+    tb = tiny_tb
+    s = O.solve(tb, ftol=1e-13, rtol=1e-8, maxiter=40, krylov="bicgstab")
+    assert s.converged
+    nd, _ = O.dense_newton(tb, tb.nstar, ftol=1e-13)
+    assert np.max(np.abs(s.n / nd - 1)) < 1e-11
 
 
 def test_collisional_limit_gives_lte():
