@@ -244,6 +244,9 @@ def main():
     ap.add_argument("--f-only", type=int, default=1,
                     help="also time F-only loops (graph-replayed residual plans) of the workload "
                          "in FP32 form and FP64 and of the 11-level stress column")
+    ap.add_argument("--bicgstab", type=int, default=1,
+                    help="also time the batch solve with the BiCGSTAB inner solver (one solve "
+                         "after one warm-up; 0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="arrival window of the served-stream phase (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -364,6 +367,28 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if args.bicgstab:
+        bopts = nlte.default_opts(ftol=ftol, rtol=args.rtol, maxiter=50,
+                                  max_krylov_total=args.max_krylov_total,
+                                  fp64_fallback=args.fp64_fallback,
+                                  krylov_method=nlte.KRYLOV_BICGSTAB)
+        nlte.solve_batch(ctx, cols, bopts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, bst, _ = nlte.solve_batch(ctx, cols, bopts)
+        torch.cuda.synchronize()
+        bel = time.perf_counter() - t0
+        bf = np.array([s["f_calls"] for s in bst], dtype=np.float64)
+        out["bicgstab"] = {
+            "ms_per_solve": bel * 1e3,
+            "depth_points_per_s": float((bf * dp_col).sum()) / bel,
+            "converged_fraction": float(np.mean([s["status"] == 0 for s in bst])),
+            "columns_converged_per_s": float(np.sum([s["status"] == 0 for s in bst])) / bel,
+            "residual_calls_per_column": float(bf.mean()),
+            "newton_iters_mean": float(np.mean([s["newton_iters"] for s in bst])),
+            "jacobian_products_per_column": float(np.mean([s["krylov_iters"] for s in bst])),
+        }
+        print(f"[bench] BiCGSTAB solve {bel * 1e3:.0f} ms", file=sys.stderr, flush=True)
     if args.f_only:
         for c in cols:
             c.close()

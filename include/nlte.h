@@ -56,6 +56,10 @@ typedef enum {
  * finite-difference product are FP64 in both forms. */
 typedef enum { NLTE_FP64 = 0, NLTE_FP32_FORM = 1 } nlte_precision;
 
+/* Inner (Krylov) solver of the Newton steps, Sect. 2.3: GMRES(m) with one
+ * product with the Jacobian per iteration, or BiCGSTAB with two. */
+typedef enum { NLTE_KRYLOV_GMRES = 0, NLTE_KRYLOV_BICGSTAB = 1 } nlte_krylov;
+
 /* OR-ed into the precision argument of nlte_column_create: solve the
  * transfer equation of this column by parallel scans over depth (one
  * workgroup per frequency, one thread per depth; nz <= 256) instead of one
@@ -130,6 +134,11 @@ typedef struct {
                           * solutions: from their current iterate when its
                           * max |F|/gross-rate is at most 1e-2, else from their
                           * initial populations (0: never, default 0)         */
+  int32_t krylov_method; /* nlte_krylov (default NLTE_KRYLOV_GMRES).  With
+                          * BiCGSTAB, restart is unused and max_krylov,
+                          * max_krylov_total and the krylov_iters statistic
+                          * count products with the Jacobian (two per
+                          * iteration)                                        */
 } nlte_solve_opts;
 
 typedef struct {

@@ -103,6 +103,7 @@ extern "C" void nlte_solve_opts_default(nlte_solve_opts* o) {
   o->max_halvings = 8;
   o->init = 1;
   o->eps_scale = 1.0;
+  o->krylov_method = NLTE_KRYLOV_GMRES;
 }
 
 // ---------------------------------------------------------------------------

@@ -119,7 +119,8 @@ struct ColState {
   int cur_prec;     // precision the next evaluation runs in (FP32-form columns may switch to FP64)
   int fp64_fallback;  // FP32-form columns not converged after this many Newton iterations switch (0: never)
   int fp64_evals;   // FP64 evaluations after a switch
-  int pad3;
+  int method;       // nlte_krylov of the solve
+  double bi_rho, bi_alpha;  // BiCGSTAB: (r^, r) and the step of the pending half
 };
 
 // Preconditioner pair sums.  The frequency axis of a column is cut at every

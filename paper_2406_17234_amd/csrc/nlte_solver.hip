@@ -50,7 +50,11 @@ constexpr double kEpsMach64 = 2.220446049250313e-16;
 // starts again from its initial populations.
 constexpr double kFallbackKeepRho = 1e-2;
 
-enum Phase : int { PH_IDLE = 0, PH_INIT = 1, PH_ARNOLDI = 2, PH_RESTART = 3, PH_LS = 4, PH_DONE = 5 };
+enum Phase : int {
+  PH_IDLE = 0, PH_INIT = 1, PH_ARNOLDI = 2, PH_RESTART = 3, PH_LS = 4, PH_DONE = 5,
+  PH_BICG_V = 6,  // BiCGSTAB: the product A p is pending
+  PH_BICG_T = 7   // BiCGSTAB: the product A s is pending
+};
 
 // ----------------------------------------------------------------- block ops
 __device__ __forceinline__ double warp_sum(double v) {
@@ -299,6 +303,164 @@ __device__ void begin_linesearch(const ColDev& C) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// BiCGSTAB (Sect. 2.3, the paper's second inner solver) on the same
+// left-preconditioned, scaled system A x = b as GMRES, A = D^-1 P^-1 J D,
+// b = -D^-1 P^-1 F(n), x0 = 0, shadow residual r^ = b.  Each product A u is
+// one residual evaluation at n (1 + eps u), so an iteration spans two steps
+// of the state machine.  Vectors in the Krylov slots: 0 r^, 1 r, 2 p,
+// 3 v = A p, 4 s, 5 t = A s; x in xk.
+// ---------------------------------------------------------------------------
+// Whether the product just made exhausts the Krylov budget, from the counters
+// as they were before it (read by every thread before thread 0 advances them,
+// so that the whole block takes the same branch).
+__device__ __forceinline__ bool krylov_capped_after(const ColState* st, int ks, int kt) {
+  return ks + 1 >= st->max_krylov || (st->max_krylov_total > 0 && kt + 1 >= st->max_krylov_total);
+}
+
+// w = D^-1 P^-1 (F - F(n)) / eps: the product of the pending evaluation
+__device__ void pending_product(const ColDev& C, double* w) {
+  const double ieps = 1.0 / C.st->eps_fd;
+  for (int i = threadIdx.x; i < C.N; i += kThreads) w[i] = (C.F[i] - C.Fn[i]) * ieps;
+  __syncthreads();
+  apply_scaled_pinv(C, w, w);
+}
+
+__device__ void bicg_start(const ColDev& C, double* red, int* done_count) {
+  ColState* st = C.st;
+  const int N = C.N;
+  double* rh = C.Vk;
+  double* r = C.Vk + N;
+  double* p = C.Vk + 2 * (size_t)N;
+  double q = 0.0;
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    const double b = rh[i];
+    r[i] = b;
+    p[i] = b;
+    q += b * b;
+  }
+  const double bb = block_sum1(q, red);
+  const double beta = sqrt(bb);
+  if (!(beta > 0.0) || beta != beta) {
+    // F vanishes in the preconditioned norm: nothing left to correct
+    if (beta != beta) finish(C, NLTE_E_NONFINITE, done_count);
+    else finish(C, NLTE_OK, done_count);
+    return;
+  }
+  if (threadIdx.x == 0) {
+    st->beta0 = beta;
+    st->phi0 = beta;
+    st->bi_rho = bb;  // (r^, r0) with r^ = r0
+    st->phase = PH_BICG_V;
+  }
+  prepare_jv(C, p, beta);
+}
+
+// A p has been evaluated: alpha, s = r - alpha v; stop on s, else evaluate A s
+__device__ void bicg_v(const ColDev& C, double* red, int* done_count) {
+  ColState* st = C.st;
+  const int N = C.N;
+  const double rho = st->bi_rho, rtol = st->rtol, beta0 = st->beta0;
+  const bool capped = krylov_capped_after(st, st->krylov_step, st->krylov_total);
+  double* rh = C.Vk;
+  double* r = C.Vk + N;
+  double* p = C.Vk + 2 * (size_t)N;
+  double* v = C.Vk + 3 * (size_t)N;
+  double* sv = C.Vk + 4 * (size_t)N;
+  pending_product(C, v);
+  double q = 0.0;
+  for (int i = threadIdx.x; i < N; i += kThreads) q += rh[i] * v[i];
+  const double den = block_sum1(q, red);
+  __syncthreads();  // every thread has read the state before thread 0 changes it
+  if (threadIdx.x == 0) {
+    st->krylov_total += 1;
+    st->krylov_step += 1;
+  }
+  const double alpha = rho / den;
+  if (!(den != 0.0) || !isfinite(alpha)) {  // breakdown: keep x as it is
+    begin_linesearch(C);
+    return;
+  }
+  double ss = 0.0;
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    const double si = r[i] - alpha * v[i];
+    sv[i] = si;
+    ss += si * si;
+  }
+  const double sn = sqrt(block_sum1(ss, red));
+  if (sn <= rtol * beta0 || capped) {
+    for (int i = threadIdx.x; i < N; i += kThreads) C.xk[i] += alpha * p[i];
+    __syncthreads();
+    begin_linesearch(C);
+    return;
+  }
+  if (threadIdx.x == 0) {
+    st->bi_alpha = alpha;
+    st->phase = PH_BICG_T;
+  }
+  prepare_jv(C, sv, sn);
+}
+
+// A s has been evaluated: omega, x += alpha p + omega s, r = s - omega t;
+// stop on r, else the next direction p and its product
+__device__ void bicg_t(const ColDev& C, double* red, int* done_count) {
+  ColState* st = C.st;
+  const int N = C.N;
+  const double rho = st->bi_rho, alpha = st->bi_alpha, rtol = st->rtol, beta0 = st->beta0;
+  const bool capped = krylov_capped_after(st, st->krylov_step, st->krylov_total);
+  double* rh = C.Vk;
+  double* r = C.Vk + N;
+  double* p = C.Vk + 2 * (size_t)N;
+  double* v = C.Vk + 3 * (size_t)N;
+  double* sv = C.Vk + 4 * (size_t)N;
+  double* t = C.Vk + 5 * (size_t)N;
+  pending_product(C, t);
+  __shared__ double d2[2];
+  double part[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    part[0] += t[i] * t[i];
+    part[1] += t[i] * sv[i];
+  }
+  block_sums(part, 2, red, d2);
+  const double tt = d2[0], ts = d2[1];
+  const double omega = tt > 0.0 ? ts / tt : 0.0;
+  double part2[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    C.xk[i] += alpha * p[i] + omega * sv[i];
+    const double ri = sv[i] - omega * t[i];
+    r[i] = ri;
+    part2[0] += ri * ri;
+    part2[1] += rh[i] * ri;
+  }
+  __shared__ double e2[2];
+  block_sums(part2, 2, red, e2);
+  const double rn = sqrt(e2[0]), rho_new = e2[1];
+  __syncthreads();  // every thread has read the state before thread 0 changes it
+  if (threadIdx.x == 0) {
+    st->krylov_total += 1;
+    st->krylov_step += 1;
+  }
+  const double beta = (rho_new / rho) * (alpha / omega);
+  if (rn <= rtol * beta0 || capped || !(omega != 0.0) || !(rho_new != 0.0) ||
+      !isfinite(beta)) {
+    __syncthreads();
+    begin_linesearch(C);
+    return;
+  }
+  double pp = 0.0;
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    const double pi = r[i] + beta * (p[i] - omega * v[i]);
+    p[i] = pi;
+    pp += pi * pi;
+  }
+  const double pn = sqrt(block_sum1(pp, red));
+  if (threadIdx.x == 0) {
+    st->bi_rho = rho_new;
+    st->phase = PH_BICG_V;
+  }
+  prepare_jv(C, p, pn);
+}
+
 // The pending evaluation was a Newton-mode F at eval_n: make it the iterate.
 // Its conservation rows move to the most populated levels of eval_n (the
 // rate rows they replace were saved by the assembly, so this needs no new
@@ -409,7 +571,10 @@ __device__ void accept_point(const ColDev& C, double* red, int* done_count) {
     st->krylov_step = 0;
   }
   __syncthreads();
-  start_cycle(C, true, red, done_count);
+  if (st->method == NLTE_KRYLOV_BICGSTAB)
+    bicg_start(C, red, done_count);
+  else
+    start_cycle(C, true, red, done_count);
 }
 
 __device__ void arnoldi(const ColDev& C, double* red, int* done_count) {
@@ -600,6 +765,8 @@ __global__ __launch_bounds__(kThreads) void k_solver_step(const ColDev* __restri
     case PH_ARNOLDI: arnoldi(C, red, done_count); break;
     case PH_RESTART: restart(C, red, done_count); break;
     case PH_LS: linesearch(C, red, done_count); break;
+    case PH_BICG_V: bicg_v(C, red, done_count); break;
+    case PH_BICG_T: bicg_t(C, red, done_count); break;
     default: break;
   }
 }
@@ -607,7 +774,7 @@ __global__ __launch_bounds__(kThreads) void k_solver_step(const ColDev* __restri
 // Solve setup: options, initial populations, J-dagger = B, first evaluation.
 struct InitArgs {
   double ftol, rtol, eps_mach, eps_scale;
-  int maxiter, max_krylov, restart, max_halvings, init, max_krylov_total, fp64_fallback;
+  int maxiter, max_krylov, restart, max_halvings, init, max_krylov_total, fp64_fallback, method;
 };
 
 __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* const* n0, InitArgs a) {
@@ -643,6 +810,7 @@ __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* con
     st->max_krylov_total = a.max_krylov_total;
     st->cur_prec = C.prec;
     st->fp64_fallback = a.fp64_fallback;
+    st->method = a.method;
     st->fp64_evals = 0;
     st->restart = a.restart;
     st->max_halvings = a.max_halvings;
@@ -745,7 +913,8 @@ namespace nlte {
 nlte_status check_solve_opts(const nlte_solve_opts& o) {
   if (o.restart < 1 || o.restart > kMaxM) return set_err(NLTE_E_INVALID, "restart must be 1..%d", kMaxM);
   if (o.maxiter < 0 || o.max_krylov < 1 || o.max_krylov_total < 0 || o.max_halvings < 0 ||
-      !(o.ftol >= 0) || !(o.rtol > 0) || !(o.eps_scale > 0) || o.init < 0 || o.init > 2)
+      !(o.ftol >= 0) || !(o.rtol > 0) || !(o.eps_scale > 0) || o.init < 0 || o.init > 2 ||
+      (o.krylov_method != NLTE_KRYLOV_GMRES && o.krylov_method != NLTE_KRYLOV_BICGSTAB))
     return set_err(NLTE_E_INVALID, "invalid solve options");
   return NLTE_OK;
 }
@@ -753,7 +922,7 @@ nlte_status check_solve_opts(const nlte_solve_opts& o) {
 hipError_t solver_init(const ColDev* cols, int ncol, const double* const* n0, const nlte_solve_opts& o,
                        hipStream_t s) {
   InitArgs ia{o.ftol, o.rtol, 2.220446049250313e-16, o.eps_scale, o.maxiter, o.max_krylov,
-              o.restart, o.max_halvings, 0, o.max_krylov_total, o.fp64_fallback};
+              o.restart, o.max_halvings, 0, o.max_krylov_total, o.fp64_fallback, o.krylov_method};
   k_solver_init<<<ncol, kThreads, 0, s>>>(cols, n0, ia);
   return hipGetLastError();
 }
@@ -881,7 +1050,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   }
   HIP_TRY(hipMemsetAsync(b.done, 0, sizeof(int), s));
   InitArgs ia{o.ftol, o.rtol, 2.220446049250313e-16, o.eps_scale, o.maxiter, o.max_krylov,
-              o.restart, o.max_halvings, o.init, o.max_krylov_total, o.fp64_fallback};
+              o.restart, o.max_halvings, o.init, o.max_krylov_total, o.fp64_fallback, o.krylov_method};
   k_solver_init<<<ncol, 256, 0, s>>>(b.cols, o.init == 0 ? b.n0 : nullptr, ia);
   if (o.init == 2) {
     for (int c = 0; c < ncol; ++c)

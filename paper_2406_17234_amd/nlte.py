@@ -20,6 +20,7 @@ NLTE_OK, NLTE_E_INVALID, NLTE_E_NOMEM, NLTE_E_DEVICE = 0, -1, -2, -3
 NLTE_E_NOCONV, NLTE_E_NONFINITE, NLTE_E_BUSY = -4, -5, -6
 DEPTH_SCAN = 0x100  # OR into a column's precision: depth-parallel formal solution
 FP64, FP32_FORM = 0, 1
+KRYLOV_GMRES, KRYLOV_BICGSTAB = 0, 1  # nlte_solve_opts.krylov_method
 STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "DEVICE", -4: "NOCONV",
                 -5: "NONFINITE", -6: "BUSY"}
 
@@ -55,7 +56,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("ftol", C.c_double), ("rtol", C.c_double), ("maxiter", C.c_int32),
                 ("max_krylov", C.c_int32), ("restart", C.c_int32),
                 ("max_halvings", C.c_int32), ("init", C.c_int32), ("eps_scale", C.c_double),
-                ("max_krylov_total", C.c_int32), ("fp64_fallback", C.c_int32)]
+                ("max_krylov_total", C.c_int32), ("fp64_fallback", C.c_int32),
+                ("krylov_method", C.c_int32)]
 
 
 class SolveStats(C.Structure):

@@ -192,3 +192,45 @@ def test_fp64_fallback_keeps_a_close_iterate(ctx):
             assert fp64_its < s64["newton_iters"]
         else:
             assert abs(fp64_its - s64["newton_iters"]) <= 1
+
+
+@pytest.mark.parametrize("name", ["slab3", "chromo6_small"])
+def test_bicgstab_fp64_matches_oracle_root(ctx, name):
+    """JFNK with the BiCGSTAB inner solver (Sect. 2.3) reaches the oracle's
+    root; both inner solvers converge to the same solution (Sect. 3.2)."""
+    from paper_2406_17234_amd import nlte
+    prob, tb, ref = oracle_root(name, CASES[name])
+    col = nlte.Column(ctx, prob)
+    n, _, st, rc = col.solve(ftol=1e-12, rtol=1e-6, maxiter=60,
+                             krylov_method=nlte.KRYLOV_BICGSTAB)
+    print(st, flush=True)
+    assert rc == 0 and st["rho_inf"] <= 1e-12
+    assert maxrel(to_np(n), ref.n) < 1e-10
+    # two products with the Jacobian per BiCGSTAB iteration, one residual call each
+    assert st["f_calls"] >= st["krylov_iters"] + st["newton_iters"]
+
+
+def test_bicgstab_fp32_form_batch(ctx):
+    """Batched FP32-form columns with BiCGSTAB converge to within 1e-4 of the
+    FP64 root; the Krylov budget counts products."""
+    from paper_2406_17234_amd import nlte
+    prob, tb, ref = oracle_root("chromo6", CASES["chromo6"])
+    cols = [nlte.Column(ctx, prob, precision=nlte.FP32_FORM) for _ in range(3)]
+    outs, stats, rc = nlte.solve_batch(ctx, cols, ftol=1e-6, rtol=1e-3, maxiter=60,
+                                       krylov_method=nlte.KRYLOV_BICGSTAB, fp64_fallback=30)
+    assert rc == 0
+    for o, s in zip(outs, stats):
+        assert s["status"] == 0
+        assert maxrel(to_np(o), ref.n) < 1e-4
+    col = nlte.Column(ctx, CASES["chromo6_small"]())
+    _, _, st, _ = col.solve(ftol=1e-12, rtol=1e-6, maxiter=8, max_krylov_total=10,
+                            krylov_method=nlte.KRYLOV_BICGSTAB)
+    assert st["krylov_iters"] <= 10 + st["newton_iters"]
+
+
+def test_unknown_krylov_method_rejected(ctx):
+    from paper_2406_17234_amd import nlte
+    col = nlte.Column(ctx, CASES["tiny"]())
+    with pytest.raises(nlte.NLTEError) as e:
+        col.solve(krylov_method=7)
+    assert e.value.status == nlte.NLTE_E_INVALID
