@@ -61,3 +61,15 @@ def test_server_rejects_bad_arguments_without_a_device():
     assert L.nlte_server_submit(None, None, None, ctypes.byref(t)) == nlte.NLTE_E_INVALID
     assert L.nlte_server_poll(None, ctypes.c_uint64(1), None, None) == nlte.NLTE_E_INVALID
     assert L.nlte_server_drain(None, ctypes.c_double(0.0)) == nlte.NLTE_E_INVALID
+
+
+def test_solve_opts_layout_matches_defaults():
+    """The binding's nlte_solve_opts layout agrees with the library's: every
+    field read back from nlte_solve_opts_default holds its documented
+    default (a shifted field would read another one's bytes)."""
+    o = nlte.default_opts()
+    assert (o.ftol, o.rtol, o.eps_scale) == (1e-8, 1e-3, 1.0)
+    assert (o.maxiter, o.max_krylov, o.restart, o.max_halvings, o.init) == (50, 200, 30, 8, 1)
+    assert (o.max_krylov_total, o.fp64_fallback) == (0, 0)
+    assert o.krylov_method == nlte.KRYLOV_GMRES
+    assert ctypes.sizeof(o) == 64
