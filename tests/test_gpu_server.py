@@ -43,14 +43,16 @@ def _wait(srv, ticket, col, timeout=120.0):
         time.sleep(0.002)
 
 
-def test_served_equals_alone(ctx):
+@pytest.mark.parametrize("krylov", [0, 1], ids=["gmres", "bicgstab"])
+def test_served_equals_alone(ctx, krylov):
     from paper_2406_17234_amd import nlte
+    opts = dict(OPTS, krylov_method=krylov)
     cols = _mixed_columns(ctx)
     alone = []
     for c in cols:
-        n, _, st, rc = c.solve(**OPTS)
+        n, _, st, rc = c.solve(**opts)
         alone.append((to_np(n), st))
-    srv = nlte.Server(ctx, hbm_budget=1 << 36, max_active=64, **OPTS)
+    srv = nlte.Server(ctx, hbm_budget=1 << 36, max_active=64, **opts)
     try:
         first = [srv.submit(c) for c in cols[:3]]
         n0, r0 = _wait(srv, first[0], cols[0])        # later requests arrive mid-flight
