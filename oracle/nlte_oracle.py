@@ -416,6 +416,18 @@ def jvp_fd(tb, n, v, F0, eps, Jdag=None, rows=None):
     return (Fp - F0) / eps
 
 
+def jvp_complex_step(tb, n, v, Jdag=None, rows=None, h=1e-200):
+    """Complex-step product Im F(n + i h v) / h (Eq. complex, Sect. 2.4.2),
+    with the conservation rows and lagged J held at those of n.  No
+    subtraction of nearby values takes place, so the step can be as small as
+    the paper's 1e-200: the result is the directional derivative of F to
+    rounding, linear in v."""
+    if rows is None:
+        rows = conservation_rows(n)
+    Fc = residual(tb, np.asarray(n, float) + 1j * h * np.asarray(v, float), Jdag=Jdag, rows=rows).F
+    return Fc.imag / h
+
+
 def jacobian_complex_step(tb, n, Jdag=None, rows=None, h=1e-20):
     """Dense Jacobian by the complex-step scheme (Eq. complex), one column per
     population: Im F(n + i h e_j) / h.  For tiny grids only."""
@@ -596,7 +608,7 @@ def positivity_limit(n, dn, frac=0.9):
 
 def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
           max_krylov=200, max_halvings=8, Jdag0=None, eps_mach=2.0 ** -52,
-          verbose=False, krylov="gmres"):
+          verbose=False, krylov="gmres", jv="fd"):
     """JFNK solve of F(n) = 0 (Algorithm 2) with left block-Jacobi
     preconditioning, populations scaled by the Newton iterate for the
     finite-difference product, per-depth positivity limiting and damped
@@ -605,6 +617,8 @@ def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
     rows held fixed, and asks for an Armijo decrease (1 - 1e-4 alpha).
     Convergence: ||rho||_inf <= ftol.  krylov: "gmres" (GMRES(m)) or
     "bicgstab" (max_krylov then counts products with the Jacobian).
+    jv: "fd" (forward difference, Eq. fordif) or "complex" (complex step,
+    Eq. complex) for the Jacobian-vector products.
 
     Returns a namespace with n, J, history and call counts (one call per
     formal solution; re-assigning conservation rows at an accepted point
@@ -632,8 +646,11 @@ def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
             un = np.linalg.norm(u)
             if un == 0.0:
                 return np.zeros_like(u)
-            eps = fd_step(N, un, eps_mach)
-            Jv = jvp_fd(tb, n, D * u.reshape(n.shape), F0, eps, Jdag=Jdag, rows=rows)
+            if jv == "complex":
+                Jv = jvp_complex_step(tb, n, D * u.reshape(n.shape), Jdag=Jdag, rows=rows)
+            else:
+                eps = fd_step(N, un, eps_mach)
+                Jv = jvp_fd(tb, n, D * u.reshape(n.shape), F0, eps, Jdag=Jdag, rows=rows)
             calls += 1
             return (lu_solve_blocks(lus, Jv) / D).ravel()
 

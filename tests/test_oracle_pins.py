@@ -238,6 +238,79 @@ def test_conservation_rows_in_jacobian(tiny_tb):
         assert np.array_equal(row, expect)
 
 
+def _richardson_product(tb, n, v, rows, h):
+    """Central differences of the real residual at steps h and h/2, combined
+    so that the O(h^2) error cancels (error O(h^4))."""
+    def central(s):
+        Fp = O.residual(tb, n + s * v, rows=rows).F
+        Fm = O.residual(tb, n - s * v, rows=rows).F
+        return (Fp - Fm) / (2 * s)
+    return (4 * central(h / 2) - central(h)) / 3
+
+
+@pytest.mark.parametrize("maker", ["tiny", "slab3"])
+def test_complex_step_product_matches_extrapolated_differences(maker, tiny_tb):
+    """Complex-step product of Eq. complex (step 1e-200, Sect. 2.4.2) against
+    Richardson-extrapolated central differences of the real residual, which
+    share none of its complex arithmetic: a dropped or mis-signed term in
+    the derivative of any step of Algorithm 1 (opacity, formal solution,
+    rates, assembly) shows up far above the 1e-10 the differences reach."""
+    tb = tiny_tb if maker == "tiny" else O.setup(S.slab3())
+    n = _mid_populations(tb)
+    rows = O.conservation_rows(n)
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(n.shape) * n
+    cs = O.jvp_complex_step(tb, n, v, rows=rows)
+    ref = _richardson_product(tb, n, v, rows, 2e-3)
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(cs - ref)) < 1e-10 * scale
+    # the coupling through the radiation field is in it: with J held fixed
+    # the product differs by far more than that tolerance
+    r = O.residual(tb, n)
+    Ff = O.residual(tb, n + 1j * 1e-200 * v, rows=rows, I_override=r.J).F.imag / 1e-200
+    assert np.max(np.abs(Ff - cs)) > 1e-4 * scale
+
+
+def test_complex_step_with_frozen_radiation_is_rate_matrix(tiny_tb):
+    """With J held fixed, F is linear in n (Eqs. residuals_1/2): the complex
+    step returns the rate matrix times v, and -sum v on the conservation rows
+    (Sect. 2.5.1)."""
+    tb = tiny_tb
+    n = _mid_populations(tb)
+    r = O.residual(tb, n)
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal(n.shape) * n
+    Ff = O.residual(tb, n + 1j * 1e-200 * v, rows=r.rows, I_override=r.J).F.imag / 1e-200
+    L = tb.nlev
+    for k in range(tb.nz):
+        A = np.zeros((L, L))  # A[i, j]: rate from level j into level i, minus outflow on the diagonal
+        for t in range(tb.ntr):
+            lo, up = tb.lo[t], tb.up[t]
+            ul = tb.C_lu[k, t] + r.R_lu[k, t]
+            dl = tb.C_ul[k, t] + r.R_ul[k, t]
+            A[lo, lo] += ul
+            A[up, lo] -= ul
+            A[lo, up] -= dl
+            A[up, up] += dl
+        expect = A @ v[k]
+        expect[r.rows[k]] = -v[k].sum()
+        assert np.allclose(Ff[k], expect, rtol=1e-12, atol=1e-12 * np.abs(expect).max()), k
+
+
+def test_complex_step_product_is_linear(tiny_tb):
+    """The complex-step product is exact to rounding, so it is linear in v
+    (a forward difference is not: its error depends on the step and on v)."""
+    tb = tiny_tb
+    n = _mid_populations(tb)
+    rows = O.conservation_rows(n)
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal(n.shape) * n
+    b = rng.standard_normal(n.shape) * n
+    lhs = O.jvp_complex_step(tb, n, 2.0 * a - 3.0 * b, rows=rows)
+    rhs = 2.0 * O.jvp_complex_step(tb, n, a, rows=rows) - 3.0 * O.jvp_complex_step(tb, n, b, rows=rows)
+    assert np.max(np.abs(lhs - rhs)) < 1e-12 * np.abs(rhs).max()
+
+
 def test_gmres_solves_small_system():
     rng = np.random.default_rng(2)
     A = np.eye(40) + 0.3 * rng.standard_normal((40, 40)) / np.sqrt(40)
@@ -301,6 +374,17 @@ def test_jfnk_bicgstab_root_equals_gmres_root(tiny_tb):
     assert s.converged
     nd, _ = O.dense_newton(tb, tb.nstar, ftol=1e-13)
     assert np.max(np.abs(s.n / nd - 1)) < 1e-11
+
+
+def test_jfnk_complex_step_root_equals_dense_newton_root(tiny_tb):
+    """JFNK with complex-step products (Eq. complex, the products the paper's
+    runs use) reaches the dense-Newton root, with both inner solvers."""
+    tb = tiny_tb
+    nd, _ = O.dense_newton(tb, tb.nstar, ftol=1e-13)
+    for kr in ("gmres", "bicgstab"):
+        s = O.solve(tb, ftol=1e-13, rtol=1e-8, maxiter=40, krylov=kr, jv="complex")
+        assert s.converged, kr
+        assert np.max(np.abs(s.n / nd - 1)) < 1e-11, kr
 
 
 def test_collisional_limit_gives_lte():
