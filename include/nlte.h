@@ -60,6 +60,12 @@ typedef enum { NLTE_FP64 = 0, NLTE_FP32_FORM = 1 } nlte_precision;
  * product with the Jacobian per iteration, or BiCGSTAB with two. */
 typedef enum { NLTE_KRYLOV_GMRES = 0, NLTE_KRYLOV_BICGSTAB = 1 } nlte_krylov;
 
+/* Jacobian-vector products of the Krylov solver, Sect. 2.4: the forward
+ * difference of Eq. fordif, or the exact directional derivative that the
+ * complex step of Eq. complex reaches for vanishing steps, computed by
+ * tangent-linear (dual-number) kernels in FP64. */
+typedef enum { NLTE_JV_FD = 0, NLTE_JV_TANGENT = 1 } nlte_jv;
+
 /* OR-ed into the precision argument of nlte_column_create: solve the
  * transfer equation of this column by parallel scans over depth (one
  * workgroup per frequency, one thread per depth; nz <= 256) instead of one
@@ -139,6 +145,9 @@ typedef struct {
                           * max_krylov_total and the krylov_iters statistic
                           * count products with the Jacobian (two per
                           * iteration)                                        */
+  int32_t jv_method;     /* nlte_jv (default NLTE_JV_FD).  With
+                          * NLTE_JV_TANGENT a product costs one tangent
+                          * evaluation (no difference step; eps_scale unused) */
 } nlte_solve_opts;
 
 typedef struct {
@@ -227,6 +236,19 @@ nlte_status nlte_residual(nlte_column *col, const double *n_dev, double *F_dev,
  * of n.  Costs two residual evaluations (F(n) is recomputed). */
 nlte_status nlte_jvp(nlte_column *col, const double *n_dev, const double *v_dev,
                      double eps, double *Jv_dev, hipStream_t stream);
+
+/* Exact Jacobian-vector product (Sect. 2.4.2, Eq. complex in the limit of a
+ * vanishing step): Jv = dF/dn(n) . v with the conservation rows and J-dagger
+ * of n, by tangent-linear kernels that carry a derivative beside every
+ * quantity of Algorithm 1 (opacity, formal solution, rates, assembly), all in
+ * FP64 whatever the column's precision.
+ *   n_dev  [nz][nlev] populations (positive, finite);
+ *   v_dev  [nz][nlev] direction (any finite values);
+ *   Jv_dev [nz][nlev] output.
+ * Costs one residual evaluation at n (for the rates and rows of n) and one
+ * tangent evaluation.  The column's solver iterate is overwritten with n. */
+nlte_status nlte_jvp_tangent(nlte_column *col, const double *n_dev, const double *v_dev,
+                             double *Jv_dev, hipStream_t stream);
 
 /* JFNK solve (Algorithm 2) of one column, entirely on the device.
  *   n0_dev   [nz][nlev] initial populations when opts->init == 0 (else unused);

@@ -104,6 +104,7 @@ extern "C" void nlte_solve_opts_default(nlte_solve_opts* o) {
   o->init = 1;
   o->eps_scale = 1.0;
   o->krylov_method = NLTE_KRYLOV_GMRES;
+  o->jv_method = NLTE_JV_FD;
 }
 
 // ---------------------------------------------------------------------------
@@ -990,6 +991,34 @@ extern "C" nlte_status nlte_jvp(nlte_column* col, const double* n_dev, const dou
   if (st != NLTE_OK) return st;
   k_diff_scaled<<<(C.N + 255) / 256, 256, 0, s>>>(Jv_dev, C.F, C.Fn, 1.0 / eps, C.N);
   HIP_TRY(set_state_eval(col, kModeIdle, 0, 0, s));
+  HIP_TRY(hipGetLastError());
+  return NLTE_OK;
+}
+
+__global__ void k_set_tangent(ColState* st, int on) {
+  st->mode = kModeIdle;
+  st->tan_pending = on;
+}
+
+extern "C" nlte_status nlte_jvp_tangent(nlte_column* col, const double* n_dev, const double* v_dev,
+                                        double* Jv_dev, hipStream_t s) {
+  if (!col || !n_dev || !v_dev || !Jv_dev) return set_err(NLTE_E_INVALID, "NULL argument");
+  HIP_TRY(hipSetDevice(col->ctx->device));
+  nlte_status st = check_populations(col, n_dev, s);
+  if (st != NLTE_OK) return st;
+  const ColDev& C = col->h;
+  // rates, total rates and rows of n (its own rows)
+  HIP_TRY(hipMemcpyAsync(C.eval_n, n_dev, C.N * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(set_state_eval(col, kModeF, 0, 1, s));
+  st = run_single(col, s);
+  if (st != NLTE_OK) return st;
+  HIP_TRY(hipMemcpyAsync(C.rows_frozen, C.rows, C.nz * 4, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(C.n, n_dev, C.N * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(C.eval_n, v_dev, C.N * 8, hipMemcpyDeviceToDevice, s));
+  k_set_tangent<<<1, 1, 0, s>>>(C.st, 1);
+  HIP_TRY(launch_tangent(col->bw, s));
+  HIP_TRY(hipMemcpyAsync(Jv_dev, C.F, C.N * 8, hipMemcpyDeviceToDevice, s));
+  k_set_tangent<<<1, 1, 0, s>>>(C.st, 0);
   HIP_TRY(hipGetLastError());
   return NLTE_OK;
 }

@@ -120,6 +120,9 @@ struct ColState {
   int fp64_fallback;  // FP32-form columns not converged after this many Newton iterations switch (0: never)
   int fp64_evals;   // FP64 evaluations after a switch
   int method;       // nlte_krylov of the solve
+  int jv;           // nlte_jv of the solve
+  int tan_pending;  // a tangent product (n in n, direction in eval_n) is pending
+  int pad_jv;
   double bi_rho, bi_alpha;  // BiCGSTAB: (r^, r) and the step of the pending half
 };
 
@@ -270,6 +273,7 @@ struct BatchWork {
   int ncol = 0, ntiles = 0, nrate = 0, npb = 0;
   int nrate0 = 0;                 // rate items at the front of rate_work; pair-sum blocks follow
   int any64 = 0, any32 = 0, any_newton = 1;
+  int any_tangent = 0;            // columns may request tangent products
 };
 
 // Residual launches for a batch (level coefficients and opacity, formal
@@ -280,6 +284,9 @@ struct BatchWork {
 // [4] after assembly, [5] left to the caller, [6] after the F-mode
 // formal-solution launches that run on s itself.
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev = nullptr);
+// Tangent-linear products (nlte_tangent.hip) of the columns whose state has
+// tan_pending set: J v into F.  launch_residual runs it when bw.any_tangent.
+hipError_t launch_tangent(const BatchWork& bw, hipStream_t s);
 // Creates the calling thread's side streams for the current device (done
 // lazily by launch_residual; call it before capturing launches into a graph).
 hipError_t residual_streams_init();

@@ -1425,6 +1425,7 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     k_assemble<<<nblk * nsub, kAsmThreads, 0, s>>>(bw.cols, bw.act, nsub);
   }
   if (bw.any_newton && bw.npb > 0) k_pblock<<<bw.npb, 256, 0, s>>>(bw.cols, bw.pb_work, bw.npb);
+  if (bw.any_tangent) chk(launch_tangent(bw, s));
   if (ev) chk(hipEventRecord(ev[4], s));
   if (er != hipSuccess) return er;
   return hipGetLastError();

@@ -150,6 +150,7 @@ hipError_t nlte_server::rebuild() {
   bw.nrate0 = nrate0;
   bw.npb = (int)pb.size();
   bw.any_newton = 1;
+  bw.any_tangent = opts.jv_method == NLTE_JV_TANGENT;
   bw.ngroup = (int)groups.size();
   for (int g = 0; g < bw.ngroup; ++g) bw.groups[g] = groups[g];
   for (int c = 0; c < n; ++c) {

@@ -240,9 +240,21 @@ __device__ void finish(const ColDev& C, int status, int* done_count) {
   }
 }
 
-// eval_n = n (1 + eps v), the perturbed state of a forward-difference product
+// The product J D v of the next step.  Forward difference (Eq. fordif):
+// eval_n = n (1 + eps v), the perturbed state.  Tangent (Eq. complex in the
+// limit of a vanishing step): eval_n = D v = n v, the direction, with the
+// column's residual kernels idle and its tangent kernels on.
 __device__ void prepare_jv(const ColDev& C, const double* v, double vnorm) {
   ColState* st = C.st;
+  if (st->jv == NLTE_JV_TANGENT) {
+    for (int i = threadIdx.x; i < C.N; i += kThreads) C.eval_n[i] = C.n[i] * v[i];
+    if (threadIdx.x == 0) {
+      st->mode = kModeIdle;
+      st->tan_pending = 1;
+      st->want_J = 0;
+    }
+    return;
+  }
   const double eps = st->eps_scale * sqrt(st->eps_mach) * sqrt(1.0 + sqrt((double)C.N)) / vnorm;
   for (int i = threadIdx.x; i < C.N; i += kThreads) C.eval_n[i] = C.n[i] * (1.0 + eps * v[i]);
   if (threadIdx.x == 0) {
@@ -318,11 +330,21 @@ __device__ __forceinline__ bool krylov_capped_after(const ColState* st, int ks, 
   return ks + 1 >= st->max_krylov || (st->max_krylov_total > 0 && kt + 1 >= st->max_krylov_total);
 }
 
-// w = D^-1 P^-1 (F - F(n)) / eps: the product of the pending evaluation
-__device__ void pending_product(const ColDev& C, double* w) {
-  const double ieps = 1.0 / C.st->eps_fd;
-  for (int i = threadIdx.x; i < C.N; i += kThreads) w[i] = (C.F[i] - C.Fn[i]) * ieps;
+// J D v of the evaluation just made: (F - F(n)) / eps for a forward
+// difference, F itself for a tangent product
+__device__ void product_into(const ColDev& C, double* w) {
+  if (C.st->jv == NLTE_JV_TANGENT) {
+    for (int i = threadIdx.x; i < C.N; i += kThreads) w[i] = C.F[i];
+  } else {
+    const double ieps = 1.0 / C.st->eps_fd;
+    for (int i = threadIdx.x; i < C.N; i += kThreads) w[i] = (C.F[i] - C.Fn[i]) * ieps;
+  }
   __syncthreads();
+}
+
+// w = D^-1 P^-1 J D v: the product of the pending evaluation
+__device__ void pending_product(const ColDev& C, double* w) {
+  product_into(C, w);
   apply_scaled_pinv(C, w, w);
 }
 
@@ -581,10 +603,8 @@ __device__ void arnoldi(const ColDev& C, double* red, int* done_count) {
   ColState* st = C.st;
   const int N = C.N, m = st->restart;
   const int j = st->krylov_j;
-  const double ieps = 1.0 / st->eps_fd;
   double* w = C.w;
-  for (int i = threadIdx.x; i < N; i += kThreads) w[i] = (C.F[i] - C.Fn[i]) * ieps;
-  __syncthreads();
+  product_into(C, w);
   apply_scaled_pinv(C, w, w);
   // classical Gram-Schmidt, twice; the j + 1 dot products go to the waves
   // four basis vectors at a time (lane-strided sums, then a wave reduction)
@@ -693,10 +713,8 @@ __device__ void arnoldi(const ColDev& C, double* red, int* done_count) {
 
 __device__ void restart(const ColDev& C, double* red, int* done_count) {
   const int N = C.N;
-  const double ieps = 1.0 / C.st->eps_fd;
   double* w = C.w;
-  for (int i = threadIdx.x; i < N; i += kThreads) w[i] = (C.F[i] - C.Fn[i]) * ieps;
-  __syncthreads();
+  product_into(C, w);
   apply_scaled_pinv(C, w, w);           // A x
   apply_scaled_pinv(C, C.Fn, C.Vk);     // -b
   for (int i = threadIdx.x; i < N; i += kThreads) C.Vk[i] = -C.Vk[i] - w[i];
@@ -752,6 +770,7 @@ __global__ __launch_bounds__(kThreads) void k_solver_step(const ColDev* __restri
   const ColDev& C = cols[act ? act[blockIdx.x] : blockIdx.x];
   if (threadIdx.x == 0) {
     s_phase = C.st->phase;
+    C.st->tan_pending = 0;  // the tangent product (if any) has been made
     if (s_phase != PH_DONE && s_phase != PH_IDLE) {
       C.st->f_calls += 1;
       if (C.prec == NLTE_FP32_FORM && C.st->cur_prec == NLTE_FP64) C.st->fp64_evals += 1;
@@ -774,7 +793,7 @@ __global__ __launch_bounds__(kThreads) void k_solver_step(const ColDev* __restri
 // Solve setup: options, initial populations, J-dagger = B, first evaluation.
 struct InitArgs {
   double ftol, rtol, eps_mach, eps_scale;
-  int maxiter, max_krylov, restart, max_halvings, init, max_krylov_total, fp64_fallback, method;
+  int maxiter, max_krylov, restart, max_halvings, init, max_krylov_total, fp64_fallback, method, jv;
 };
 
 __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* const* n0, InitArgs a) {
@@ -811,6 +830,8 @@ __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* con
     st->cur_prec = C.prec;
     st->fp64_fallback = a.fp64_fallback;
     st->method = a.method;
+    st->jv = a.jv;
+    st->tan_pending = 0;
     st->fp64_evals = 0;
     st->restart = a.restart;
     st->max_halvings = a.max_halvings;
@@ -914,7 +935,8 @@ nlte_status check_solve_opts(const nlte_solve_opts& o) {
   if (o.restart < 1 || o.restart > kMaxM) return set_err(NLTE_E_INVALID, "restart must be 1..%d", kMaxM);
   if (o.maxiter < 0 || o.max_krylov < 1 || o.max_krylov_total < 0 || o.max_halvings < 0 ||
       !(o.ftol >= 0) || !(o.rtol > 0) || !(o.eps_scale > 0) || o.init < 0 || o.init > 2 ||
-      (o.krylov_method != NLTE_KRYLOV_GMRES && o.krylov_method != NLTE_KRYLOV_BICGSTAB))
+      (o.krylov_method != NLTE_KRYLOV_GMRES && o.krylov_method != NLTE_KRYLOV_BICGSTAB) ||
+      (o.jv_method != NLTE_JV_FD && o.jv_method != NLTE_JV_TANGENT))
     return set_err(NLTE_E_INVALID, "invalid solve options");
   return NLTE_OK;
 }
@@ -922,7 +944,8 @@ nlte_status check_solve_opts(const nlte_solve_opts& o) {
 hipError_t solver_init(const ColDev* cols, int ncol, const double* const* n0, const nlte_solve_opts& o,
                        hipStream_t s) {
   InitArgs ia{o.ftol, o.rtol, 2.220446049250313e-16, o.eps_scale, o.maxiter, o.max_krylov,
-              o.restart, o.max_halvings, 0, o.max_krylov_total, o.fp64_fallback, o.krylov_method};
+              o.restart, o.max_halvings, 0, o.max_krylov_total, o.fp64_fallback, o.krylov_method,
+              o.jv_method};
   k_solver_init<<<ncol, kThreads, 0, s>>>(cols, n0, ia);
   return hipGetLastError();
 }
@@ -1033,6 +1056,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   bw.any64 = b.any64;
   bw.any32 = b.any32;
   bw.any_newton = 1;
+  bw.any_tangent = o.jv_method == NLTE_JV_TANGENT;
   bw.ngroup = (int)groups.size();
   for (int g = 0; g < bw.ngroup; ++g) bw.groups[g] = groups[g];
   for (int c = 0; c < ncol; ++c) bw.maxnz = std::max(bw.maxnz, hc[c].nz);
@@ -1050,7 +1074,8 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   }
   HIP_TRY(hipMemsetAsync(b.done, 0, sizeof(int), s));
   InitArgs ia{o.ftol, o.rtol, 2.220446049250313e-16, o.eps_scale, o.maxiter, o.max_krylov,
-              o.restart, o.max_halvings, o.init, o.max_krylov_total, o.fp64_fallback, o.krylov_method};
+              o.restart, o.max_halvings, o.init, o.max_krylov_total, o.fp64_fallback, o.krylov_method,
+              o.jv_method};
   k_solver_init<<<ncol, 256, 0, s>>>(b.cols, o.init == 0 ? b.n0 : nullptr, ia);
   if (o.init == 2) {
     for (int c = 0; c < ncol; ++c)

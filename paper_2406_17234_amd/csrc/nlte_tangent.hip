@@ -1,0 +1,300 @@
+// Tangent-linear Jacobian-vector products (Sect. 2.4.2, Eq. complex).
+//
+// The complex-step product Im F(n + i h v) / h of the paper is, for h far
+// below the rounding level of the real part, the directional derivative
+// dF/dn . v evaluated exactly: every O(h^2) term vanishes.  These kernels
+// compute that derivative directly, carrying a derivative beside each
+// quantity of Algorithm 1 (dual numbers) instead of complex arithmetic, so the
+// work per depth point is one extra recurrence rather than a complex one:
+//   opacity:  chi' and eta' are linear in v (the background and the lagged
+//             scattering emissivity do not depend on n);  S' = (eta' - S chi')/chi
+//   formal solution (Eqs. Iplus/Iminus, App. A.1): for each segment with
+//             optical depth x, x' = dz (chi'_k + chi'_k+1) / (2 mu), and
+//             e' = -e x',  a' = (b/x) x',  b' = (e - b/x) x', so that
+//             I'_k = I'_prev e + I_prev e' + a' S_k + a S'_k + b' S_prev + b S'_prev
+//             with I' = 0 at both boundaries;  J' = sum_m w_m/2 (I+' + I-')
+//   rates:    R_lu' and the J part of R_ul' over J' (Eqs. Rij, Rji)
+//   assembly: F'_i = sum_t +-(v_l Rtot_lu + n_l R_lu' - v_u Rtot_ul - n_u R_ul'),
+//             and -sum_l v_l on the conservation rows (Eqs. residuals_1/2).
+// Everything runs in FP64 whatever the column's formal-solution precision.
+//
+// Inputs per column: the populations n in ColDev::n, the direction v in
+// ColDev::eval_n, the total rates of n in ColDev::Rtot and the conservation
+// rows in ColDev::rows_frozen (both from an evaluation at n), the lagged J.
+// Output: J v in ColDev::F.  Scratch: XS (chi, S), Dchi (chi'), Deta (S'),
+// Jm (J'), RJ (R').  A column takes part when its state has tan_pending set
+// (its mode is then idle, so the residual kernels skip it).
+#include "nlte_internal.h"
+
+namespace nlte {
+
+namespace {
+
+constexpr int kTanSplit = 4;       // waves sharing one chunk's depths (opacity)
+constexpr int kTanRateSplit = 8;   // blocks per column (rate derivatives)
+constexpr int kTanRateThreads = 256;
+
+__device__ __forceinline__ bool tan_on(const ColDev& C) {
+  return __builtin_amdgcn_readfirstlane(C.st->tan_pending) != 0;
+}
+
+// e = exp(-x) and the piecewise-linear coefficients a = 1 - (1 - e)/x,
+// b = (1 - e)/x - e of App. A.1, with bx = b / x (the derivative of a).
+// Below x = 0.1 the three come from their Taylor series about 0,
+//   a  = sum_{m>=1} (-1)^(m+1) x^m / (m+1)!,
+//   b  = sum_{m>=1} (-1)^(m+1) m x^m / (m+1)!,
+//   bx = sum_{m>=1} (-1)^(m+1) m x^(m-1) / (m+1)!,
+// twelve terms (truncation below 1e-20 relative there).
+__device__ __forceinline__ void seg_ab(double x, double& e, double& a, double& b, double& bx) {
+  e = exp(-x);
+  if (x < 0.1) {
+    constexpr int kTerms = 12;
+    double fa = 0.0, fb = 0.0;
+    double fact = 1.0;  // (m+1)! for m = kTerms
+    for (int j = 2; j <= kTerms + 1; ++j) fact *= j;
+#pragma unroll
+    for (int m = kTerms; m >= 1; --m) {
+      const double c = ((m & 1) ? 1.0 : -1.0) / fact;  // (-1)^(m+1) / (m+1)!
+      fa = fma(fa, x, c);
+      fb = fma(fb, x, c * m);
+      fact /= (m + 1);
+    }
+    // fa = sum c_m x^(m-1), fb = sum c_m m x^(m-1)
+    a = fa * x;
+    bx = fb;
+    b = fb * x;
+  } else {
+    const double t1 = -expm1(-x) / x;
+    a = 1.0 - t1;
+    b = t1 - e;
+    bx = b / x;
+  }
+}
+
+// chi, S and their derivatives for one chunk of 64 frequencies, the depths
+// k = part, part + kTanSplit, ... of one column.
+__global__ __launch_bounds__(64) void k_tan_opacity(const ColDev* __restrict__ cols,
+                                                    const Tile* __restrict__ tiles, int ntiles) {
+  const int tid = blockIdx.x / kTanSplit, part = blockIdx.x - tid * kTanSplit;
+  if (tid >= ntiles) return;
+  const ColDev& C = cols[uni(tiles[tid].col)];
+  if (!tan_on(C)) return;
+  const int chunk = uni(tiles[tid].chunk);
+  const int nz = C.nz, nnu = C.nnu, L = C.L, fp = C.fp, nline = C.nline, nbf = C.nbf;
+  const int f = chunk * kWave + (int)threadIdx.x;
+  if (f >= nnu) return;
+  const int l0 = C.ch_lptr[chunk], l1 = C.ch_lptr[chunk + 1];
+  const int e0 = C.ch_eptr[chunk], e1 = C.ch_eptr[chunk + 1];
+  const double gam = C.gam[f];
+  for (int k = part; k < nz; k += kTanSplit) {
+    const double* nk = C.n + (size_t)k * L;
+    const double* vk = C.eval_n + (size_t)k * L;
+    double chi = 0.0, et = 0.0, chid = 0.0, etd = 0.0;
+    for (int j = l0; j < l1; ++j) {
+      const TrDev& T = C.tr[C.ch_line[j]];
+      const int wl = T.whi - T.wlo, q = f - T.wlo;
+      if (q < 0 || q >= wl) continue;
+      const double V = C.V[T.voff + (size_t)k * wl + q];
+      const double c1 = T.g * nk[T.up], c1d = T.g * vk[T.up];
+      chi += V * (nk[T.lo] - c1);
+      et += V * c1;
+      chid += V * (vk[T.lo] - c1d);
+      etd += V * c1d;
+    }
+    double A1 = 0.0, A2 = 0.0, A1d = 0.0, A2d = 0.0;
+    for (int j = e0; j < e1; ++j) {
+      const int t = C.ch_edge[j];
+      const TrDev& T = C.tr[t];
+      const int q = f - T.wlo;
+      if (q < 0 || q >= T.whi - T.wlo) continue;
+      const double al = C.V[T.voff + q];
+      const double rb = C.rho_bf[(size_t)k * nbf + (t - nline)];
+      A1 += al * nk[T.lo];
+      A2 += al * rb * nk[L - 1];
+      A1d += al * vk[T.lo];
+      A2d += al * rb * vk[L - 1];
+    }
+    const size_t kf = (size_t)k * nnu + f;
+    const double E = nbf ? C.Ebf[kf] : 0.0;
+    const double X = (C.chi_c[k] + C.chi_sca[k]) + chi + (A1 - E * A2);
+    double eta = C.chi_c[k] * C.Bnu[kf] + gam * (et + E * A2);
+    if (C.has_sca) eta += C.chi_sca[k] * C.Jdag[kf];
+    const double Xd = chid + (A1d - E * A2d);
+    const double etad = gam * (etd + E * A2d);
+    const double S = eta / X;
+    const double Sd = (etad - S * Xd) / X;
+    const size_t kx = (size_t)k * fp + f;
+    C.XS[2 * kx] = X;
+    C.XS[2 * kx + 1] = S;
+    C.Dchi[kx] = Xd;
+    C.Deta[kx] = Sd;
+  }
+}
+
+// Intensities and their derivatives along every ray of one frequency (one
+// lane per frequency of a chunk), all angles at once; J' of each depth goes
+// to Jm (the ingoing part on the way down, the outgoing part added on the way
+// up by the same lane).
+__global__ __launch_bounds__(64) void k_tan_formal(const ColDev* __restrict__ cols,
+                                                   const Tile* __restrict__ tiles, int ntiles) {
+  if ((int)blockIdx.x >= ntiles) return;
+  const ColDev& C = cols[uni(tiles[blockIdx.x].col)];
+  if (!tan_on(C)) return;
+  const int chunk = uni(tiles[blockIdx.x].chunk);
+  const int nz = C.nz, nnu = C.nnu, fp = C.fp, nmu = C.nmu;
+  const int f = chunk * kWave + (int)threadIdx.x;
+  if (f >= nnu) return;
+  const double* __restrict__ XS = C.XS;
+  double* __restrict__ Jd = C.Jm;
+  double I[kMaxMu], Id[kMaxMu];
+  // ingoing rays, top -> bottom (I- = 0 at the top)
+#pragma unroll
+  for (int m = 0; m < kMaxMu; ++m) I[m] = Id[m] = 0.0;
+  size_t kx = (size_t)f;
+  double X0 = XS[2 * kx], S0 = XS[2 * kx + 1], Xd0 = C.Dchi[kx], Sd0 = C.Deta[kx];
+  Jd[kx] = 0.0;
+  for (int k = 1; k < nz; ++k) {
+    kx = (size_t)k * fp + f;
+    const double X1 = XS[2 * kx], S1 = XS[2 * kx + 1], Xd1 = C.Dchi[kx], Sd1 = C.Deta[kx];
+    const double dz = C.dz[k - 1];
+    const double sx = dz * (X0 + X1), sxd = dz * (Xd0 + Xd1);
+    double jd = 0.0;
+#pragma unroll
+    for (int m = 0; m < kMaxMu; ++m) {
+      if (m < nmu) {
+        const double x = sx * C.inv2mu[m], xd = sxd * C.inv2mu[m];
+        double e, a, b, bx;
+        seg_ab(x, e, a, b, bx);
+        const double ed = -e * xd, ad = bx * xd, bd = (e - bx) * xd;
+        const double In = I[m] * e + a * S1 + b * S0;
+        const double Idn = Id[m] * e + I[m] * ed + ad * S1 + a * Sd1 + bd * S0 + b * Sd0;
+        I[m] = In;
+        Id[m] = Idn;
+        jd += C.wm2[m] * Idn;
+      }
+    }
+    Jd[kx] = jd;
+    X0 = X1; S0 = S1; Xd0 = Xd1; Sd0 = Sd1;
+  }
+  // outgoing rays, bottom -> top (I+ = B at the bottom, I+' = 0)
+  const double Bb = C.Bnu[(size_t)(nz - 1) * nnu + f];
+#pragma unroll
+  for (int m = 0; m < kMaxMu; ++m) {
+    I[m] = Bb;
+    Id[m] = 0.0;
+  }
+  for (int k = nz - 2; k >= 0; --k) {
+    kx = (size_t)k * fp + f;
+    const double X1 = XS[2 * kx], S1 = XS[2 * kx + 1], Xd1 = C.Dchi[kx], Sd1 = C.Deta[kx];
+    const double dz = C.dz[k];
+    const double sx = dz * (X0 + X1), sxd = dz * (Xd0 + Xd1);
+    double jd = 0.0;
+#pragma unroll
+    for (int m = 0; m < kMaxMu; ++m) {
+      if (m < nmu) {
+        const double x = sx * C.inv2mu[m], xd = sxd * C.inv2mu[m];
+        double e, a, b, bx;
+        seg_ab(x, e, a, b, bx);
+        const double ed = -e * xd, ad = bx * xd, bd = (e - bx) * xd;
+        const double In = I[m] * e + a * S1 + b * S0;
+        const double Idn = Id[m] * e + I[m] * ed + ad * S1 + a * Sd1 + bd * S0 + b * Sd0;
+        I[m] = In;
+        Id[m] = Idn;
+        jd += C.wm2[m] * Idn;
+      }
+    }
+    Jd[kx] += jd;
+    X0 = X1; S0 = S1; Xd0 = Xd1; Sd0 = Sd1;
+  }
+}
+
+// R_lu' and R_ul' of every (depth, transition): one wave per pair, lanes
+// strided over the transition's window, then a wave reduction.  Stored in RJ
+// as [nz][ntr][2] (rows of nrseg >= ntr entries).
+__global__ __launch_bounds__(kTanRateThreads) void k_tan_rates(const ColDev* __restrict__ cols,
+                                                               const int* __restrict__ act) {
+  const int ci = blockIdx.x / kTanRateSplit, part = blockIdx.x - ci * kTanRateSplit;
+  const ColDev& C = cols[act ? act[ci] : ci];
+  if (!tan_on(C)) return;
+  const int nz = C.nz, ntr = C.ntr, nline = C.nline, nnu = C.nnu, fp = C.fp;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int kWaves = kTanRateThreads / 64;
+  for (int it = part * kWaves + wave; it < nz * ntr; it += kTanRateSplit * kWaves) {
+    const int k = it / ntr, t = it - k * ntr;
+    const TrDev& T = C.tr[t];
+    const int wlo = T.wlo, wl = T.whi - T.wlo;
+    const double* cw = C.cw + T.cwoff;
+    const double* Jk = C.Jm + (size_t)k * fp + wlo;
+    double s1 = 0.0, s2 = 0.0;
+    if (t < nline) {
+      const double* V = C.V + T.voff + (size_t)k * wl;
+      for (int q = lane; q < wl; q += kWave) s1 += cw[q] * V[q] * Jk[q];
+    } else {
+      const double* al = C.V + T.voff;
+      const double* E = C.Ebf + (size_t)k * nnu + wlo;
+      for (int q = lane; q < wl; q += kWave) {
+        const double x = cw[q] * al[q] * Jk[q];
+        s1 += x;
+        s2 += x * E[q];
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      s1 += __shfl_xor(s1, o);
+      s2 += __shfl_xor(s2, o);
+    }
+    if (lane == 0) {
+      const double Rul = t < nline ? T.g * s1 : C.rho_bf[(size_t)k * C.nbf + (t - nline)] * s2;
+      double* out = C.RJ + ((size_t)k * C.nrseg + t) * 2;
+      out[0] = s1;
+      out[1] = Rul;
+    }
+  }
+}
+
+// F' of one depth per thread (the rows of a thread live in its own LDS row).
+constexpr int kTanAsmDepths = 64;
+__global__ __launch_bounds__(kTanAsmDepths) void k_tan_assemble(const ColDev* __restrict__ cols,
+                                                                const int* __restrict__ act,
+                                                                int nsub) {
+  __shared__ double sF[kTanAsmDepths][kMaxLev + 1];
+  const int ci = blockIdx.x / nsub, sub = blockIdx.x - ci * nsub;
+  const ColDev& C = cols[act ? act[ci] : ci];
+  if (!tan_on(C)) return;
+  const int nz = C.nz, L = C.L, ntr = C.ntr;
+  const int k = sub * kTanAsmDepths + (int)threadIdx.x;
+  if (k >= nz) return;
+  double* Fk = sF[threadIdx.x];
+  const double* nk = C.n + (size_t)k * L;
+  const double* vk = C.eval_n + (size_t)k * L;
+  for (int i = 0; i < L; ++i) Fk[i] = 0.0;
+  const double* Rd = C.RJ + (size_t)k * C.nrseg * 2;
+  const double* Rt = C.Rtot + (size_t)k * ntr * 2;
+  for (int t = 0; t < ntr; ++t) {
+    const TrDev& T = C.tr[t];
+    const int lo = T.lo, up = T.up;
+    const double kap = (vk[lo] * Rt[2 * t] + nk[lo] * Rd[2 * t]) -
+                       (vk[up] * Rt[2 * t + 1] + nk[up] * Rd[2 * t + 1]);
+    Fk[lo] += kap;
+    Fk[up] -= kap;
+  }
+  double sum = 0.0;
+  for (int i = 0; i < L; ++i) sum += vk[i];
+  Fk[C.rows_frozen[k]] = -sum;
+  for (int i = 0; i < L; ++i) C.F[(size_t)k * L + i] = Fk[i];
+}
+
+}  // namespace
+
+hipError_t launch_tangent(const BatchWork& bw, hipStream_t s) {
+  if (bw.ntiles <= 0) return hipSuccess;
+  const int nblk = bw.act ? bw.nact : bw.ncol;
+  k_tan_opacity<<<bw.ntiles * kTanSplit, 64, 0, s>>>(bw.cols, bw.tiles, bw.ntiles);
+  k_tan_formal<<<bw.ntiles, 64, 0, s>>>(bw.cols, bw.tiles, bw.ntiles);
+  k_tan_rates<<<nblk * kTanRateSplit, kTanRateThreads, 0, s>>>(bw.cols, bw.act);
+  const int nsub = (bw.maxnz + kTanAsmDepths - 1) / kTanAsmDepths;
+  k_tan_assemble<<<nblk * nsub, kTanAsmDepths, 0, s>>>(bw.cols, bw.act, nsub);
+  return hipGetLastError();
+}
+
+}  // namespace nlte

@@ -21,6 +21,7 @@ NLTE_E_NOCONV, NLTE_E_NONFINITE, NLTE_E_BUSY = -4, -5, -6
 DEPTH_SCAN = 0x100  # OR into a column's precision: depth-parallel formal solution
 FP64, FP32_FORM = 0, 1
 KRYLOV_GMRES, KRYLOV_BICGSTAB = 0, 1  # nlte_solve_opts.krylov_method
+JV_FD, JV_TANGENT = 0, 1               # nlte_solve_opts.jv_method
 STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "DEVICE", -4: "NOCONV",
                 -5: "NONFINITE", -6: "BUSY"}
 
@@ -57,7 +58,8 @@ class SolveOpts(C.Structure):
                 ("max_krylov", C.c_int32), ("restart", C.c_int32),
                 ("max_halvings", C.c_int32), ("init", C.c_int32), ("eps_scale", C.c_double),
                 ("max_krylov_total", C.c_int32), ("fp64_fallback", C.c_int32),
-                ("krylov_method", C.c_int32)]
+                ("krylov_method", C.c_int32),
+                ("jv_method", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -141,6 +143,7 @@ def lib():
         L.nlte_zero_radiation_populations.argtypes = [vp, vp, vp]
         L.nlte_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
         L.nlte_jvp.argtypes = [vp, vp, vp, C.c_double, vp, vp]
+        L.nlte_jvp_tangent.argtypes = [vp, vp, vp, vp, vp]
         L.nlte_solve.argtypes = [vp, vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveStats), vp]
         L.nlte_solve_batch.argtypes = [vp, C.POINTER(vp), C.c_int32, C.POINTER(vp),
                                        C.POINTER(SolveOpts), C.POINTER(vp),
@@ -332,6 +335,12 @@ class Column:
         out = self._empty(self.nz, self.nlev)
         _check(lib().nlte_jvp(self.h, _ptr(n.contiguous()), _ptr(v.contiguous()), float(eps),
                               _ptr(out), _stream(stream)))
+        return out
+
+    def jvp_tangent(self, n, v, stream=None):
+        out = self._empty(self.nz, self.nlev)
+        _check(lib().nlte_jvp_tangent(self.h, _ptr(n.contiguous()), _ptr(v.contiguous()),
+                                      _ptr(out), _stream(stream)))
         return out
 
     def solve(self, n0=None, opts: SolveOpts | None = None, want_J=False, stream=None, **kw):

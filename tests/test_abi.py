@@ -72,4 +72,5 @@ def test_solve_opts_layout_matches_defaults():
     assert (o.maxiter, o.max_krylov, o.restart, o.max_halvings, o.init) == (50, 200, 30, 8, 1)
     assert (o.max_krylov_total, o.fp64_fallback) == (0, 0)
     assert o.krylov_method == nlte.KRYLOV_GMRES
+    assert o.jv_method == nlte.JV_FD
     assert ctypes.sizeof(o) == 64
