@@ -247,6 +247,9 @@ def main():
     ap.add_argument("--bicgstab", type=int, default=1,
                     help="also time the batch solve with the BiCGSTAB inner solver (one solve "
                          "after one warm-up; 0: skip)")
+    ap.add_argument("--tangent", type=int, default=1,
+                    help="also time the batch solve with tangent-linear Jacobian-vector products "
+                         "(one solve after one warm-up; 0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="arrival window of the served-stream phase (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -367,19 +370,21 @@ def main():
         },
         "cpu_baseline": cpu,
     }
-    if args.bicgstab:
-        bopts = nlte.default_opts(ftol=ftol, rtol=args.rtol, maxiter=50,
-                                  max_krylov_total=args.max_krylov_total,
-                                  fp64_fallback=args.fp64_fallback,
-                                  krylov_method=nlte.KRYLOV_BICGSTAB)
-        nlte.solve_batch(ctx, cols, bopts)
+    def other_solve(label, **kw):
+        # the same batch solved with another inner solver or product: one
+        # warm-up solve, one timed solve
+        o2 = nlte.default_opts(ftol=ftol, rtol=args.rtol, maxiter=50,
+                               max_krylov_total=args.max_krylov_total,
+                               fp64_fallback=args.fp64_fallback, **kw)
+        nlte.solve_batch(ctx, cols, o2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, bst, _ = nlte.solve_batch(ctx, cols, bopts)
+        _, bst, _ = nlte.solve_batch(ctx, cols, o2)
         torch.cuda.synchronize()
         bel = time.perf_counter() - t0
         bf = np.array([s["f_calls"] for s in bst], dtype=np.float64)
-        out["bicgstab"] = {
+        print(f"[bench] {label} solve {bel * 1e3:.0f} ms", file=sys.stderr, flush=True)
+        return {
             "ms_per_solve": bel * 1e3,
             "depth_points_per_s": float((bf * dp_col).sum()) / bel,
             "converged_fraction": float(np.mean([s["status"] == 0 for s in bst])),
@@ -387,8 +392,16 @@ def main():
             "residual_calls_per_column": float(bf.mean()),
             "newton_iters_mean": float(np.mean([s["newton_iters"] for s in bst])),
             "jacobian_products_per_column": float(np.mean([s["krylov_iters"] for s in bst])),
+            "fp64_fallback_fraction": float(np.mean([s["precision"] == 0 and prec == 1
+                                                     for s in bst])),
         }
-        print(f"[bench] BiCGSTAB solve {bel * 1e3:.0f} ms", file=sys.stderr, flush=True)
+
+    if args.bicgstab:
+        out["bicgstab"] = other_solve("BiCGSTAB", krylov_method=nlte.KRYLOV_BICGSTAB)
+    if args.tangent:
+        # residual calls count each tangent product as one (a formal solution
+        # carrying its derivative)
+        out["tangent_jv"] = other_solve("tangent-product", jv_method=nlte.JV_TANGENT)
     if args.f_only:
         for c in cols:
             c.close()

@@ -22,15 +22,16 @@
 // ColDev::eval_n, the total rates of n in ColDev::Rtot and the conservation
 // rows in ColDev::rows_frozen (both from an evaluation at n), the lagged J.
 // Output: J v in ColDev::F.  Scratch: XS (chi, S), Dchi (chi'), Deta (S'),
-// Jm (J'), RJ (R').  A column takes part when its state has tan_pending set
-// (its mode is then idle, so the residual kernels skip it).
+// Jm (J'), RJ (R').  Three launches: the formal solution (which makes the
+// opacity on its way down), the rate derivatives, the assembly.  A column
+// takes part when its state has tan_pending set (its mode is then idle, so
+// the residual kernels skip it).
 #include "nlte_internal.h"
 
 namespace nlte {
 
 namespace {
 
-constexpr int kTanSplit = 4;       // waves sharing one chunk's depths (opacity)
 constexpr int kTanRateSplit = 8;   // blocks per column (rate derivatives)
 constexpr int kTanRateThreads = 256;
 
@@ -44,7 +45,9 @@ __device__ __forceinline__ bool tan_on(const ColDev& C) {
 //   a  = sum_{m>=1} (-1)^(m+1) x^m / (m+1)!,
 //   b  = sum_{m>=1} (-1)^(m+1) m x^m / (m+1)!,
 //   bx = sum_{m>=1} (-1)^(m+1) m x^(m-1) / (m+1)!,
-// twelve terms (truncation below 1e-20 relative there).
+// twelve terms (truncation below 1e-20 relative there); above, 1 - e has no
+// cancellation (it is at least 0.095) and one reciprocal of x serves both
+// quotients.
 __device__ __forceinline__ void seg_ab(double x, double& e, double& a, double& b, double& bx) {
   e = exp(-x);
   if (x < 0.1) {
@@ -64,116 +67,133 @@ __device__ __forceinline__ void seg_ab(double x, double& e, double& a, double& b
     bx = fb;
     b = fb * x;
   } else {
-    const double t1 = -expm1(-x) / x;
+    const double rx = 1.0 / x;
+    const double t1 = (1.0 - e) * rx;
     a = 1.0 - t1;
     b = t1 - e;
-    bx = b / x;
+    bx = b * rx;
   }
 }
 
-// chi, S and their derivatives for one chunk of 64 frequencies, the depths
-// k = part, part + kTanSplit, ... of one column.
-__global__ __launch_bounds__(64) void k_tan_opacity(const ColDev* __restrict__ cols,
-                                                    const Tile* __restrict__ tiles, int ntiles) {
-  const int tid = blockIdx.x / kTanSplit, part = blockIdx.x - tid * kTanSplit;
-  if (tid >= ntiles) return;
-  const ColDev& C = cols[uni(tiles[tid].col)];
-  if (!tan_on(C)) return;
-  const int chunk = uni(tiles[tid].chunk);
-  const int nz = C.nz, nnu = C.nnu, L = C.L, fp = C.fp, nline = C.nline, nbf = C.nbf;
-  const int f = chunk * kWave + (int)threadIdx.x;
-  if (f >= nnu) return;
+// chi, S, chi' = d chi . v and S' at depth k and frequency f (f < nnu) of
+// a chunk; the transition lists of the chunk are the same for every lane.
+__device__ __forceinline__ void tan_opacity(const ColDev& C, int chunk, int k, int f, int L,
+                                            int nnu, int nbf, int nline, double gam,
+                                            double& X, double& S, double& Xd, double& Sd) {
+  const double* nk = C.n + (size_t)k * L;
+  const double* vk = C.eval_n + (size_t)k * L;
+  double chi = 0.0, et = 0.0, chid = 0.0, etd = 0.0;
   const int l0 = C.ch_lptr[chunk], l1 = C.ch_lptr[chunk + 1];
-  const int e0 = C.ch_eptr[chunk], e1 = C.ch_eptr[chunk + 1];
-  const double gam = C.gam[f];
-  for (int k = part; k < nz; k += kTanSplit) {
-    const double* nk = C.n + (size_t)k * L;
-    const double* vk = C.eval_n + (size_t)k * L;
-    double chi = 0.0, et = 0.0, chid = 0.0, etd = 0.0;
-    for (int j = l0; j < l1; ++j) {
-      const TrDev& T = C.tr[C.ch_line[j]];
-      const int wl = T.whi - T.wlo, q = f - T.wlo;
-      if (q < 0 || q >= wl) continue;
-      const double V = C.V[T.voff + (size_t)k * wl + q];
-      const double c1 = T.g * nk[T.up], c1d = T.g * vk[T.up];
-      chi += V * (nk[T.lo] - c1);
-      et += V * c1;
-      chid += V * (vk[T.lo] - c1d);
-      etd += V * c1d;
-    }
-    double A1 = 0.0, A2 = 0.0, A1d = 0.0, A2d = 0.0;
-    for (int j = e0; j < e1; ++j) {
-      const int t = C.ch_edge[j];
-      const TrDev& T = C.tr[t];
-      const int q = f - T.wlo;
-      if (q < 0 || q >= T.whi - T.wlo) continue;
-      const double al = C.V[T.voff + q];
-      const double rb = C.rho_bf[(size_t)k * nbf + (t - nline)];
-      A1 += al * nk[T.lo];
-      A2 += al * rb * nk[L - 1];
-      A1d += al * vk[T.lo];
-      A2d += al * rb * vk[L - 1];
-    }
-    const size_t kf = (size_t)k * nnu + f;
-    const double E = nbf ? C.Ebf[kf] : 0.0;
-    const double X = (C.chi_c[k] + C.chi_sca[k]) + chi + (A1 - E * A2);
-    double eta = C.chi_c[k] * C.Bnu[kf] + gam * (et + E * A2);
-    if (C.has_sca) eta += C.chi_sca[k] * C.Jdag[kf];
-    const double Xd = chid + (A1d - E * A2d);
-    const double etad = gam * (etd + E * A2d);
-    const double S = eta / X;
-    const double Sd = (etad - S * Xd) / X;
-    const size_t kx = (size_t)k * fp + f;
-    C.XS[2 * kx] = X;
-    C.XS[2 * kx + 1] = S;
-    C.Dchi[kx] = Xd;
-    C.Deta[kx] = Sd;
+  for (int j = l0; j < l1; ++j) {
+    const TrDev& T = C.tr[C.ch_line[j]];
+    const int wl = T.whi - T.wlo, q = f - T.wlo;
+    if (q < 0 || q >= wl) continue;
+    const double V = C.V[T.voff + (size_t)k * wl + q];
+    const double c1 = T.g * nk[T.up], c1d = T.g * vk[T.up];
+    chi += V * (nk[T.lo] - c1);
+    et += V * c1;
+    chid += V * (vk[T.lo] - c1d);
+    etd += V * c1d;
   }
+  double A1 = 0.0, A2 = 0.0, A1d = 0.0, A2d = 0.0;
+  const int e0 = C.ch_eptr[chunk], e1 = C.ch_eptr[chunk + 1];
+  for (int j = e0; j < e1; ++j) {
+    const int t = C.ch_edge[j];
+    const TrDev& T = C.tr[t];
+    const int q = f - T.wlo;
+    if (q < 0 || q >= T.whi - T.wlo) continue;
+    const double al = C.V[T.voff + q];
+    const double rb = C.rho_bf[(size_t)k * nbf + (t - nline)];
+    A1 += al * nk[T.lo];
+    A2 += al * rb * nk[L - 1];
+    A1d += al * vk[T.lo];
+    A2d += al * rb * vk[L - 1];
+  }
+  const size_t kf = (size_t)k * nnu + f;
+  const double E = nbf ? C.Ebf[kf] : 0.0;
+  X = (C.chi_c[k] + C.chi_sca[k]) + chi + (A1 - E * A2);
+  double eta = C.chi_c[k] * C.Bnu[kf] + gam * (et + E * A2);
+  if (C.has_sca) eta += C.chi_sca[k] * C.Jdag[kf];
+  Xd = chid + (A1d - E * A2d);
+  const double etad = gam * (etd + E * A2d);
+  S = eta / X;
+  Sd = (etad - S * Xd) / X;
+}
+
+// One segment of every ray of a lane (NMU angles in registers): I and I'
+// advance from the segment's start (S0, S0') to its end (S1, S1');
+// returns sum_m w_m/2 I'_m at the end.
+template <int NMU>
+__device__ __forceinline__ double tan_segment(double sx, double sxd, double S0, double Sd0,
+                                              double S1, double Sd1, const double (&i2mu)[kMaxMu],
+                                              const double (&wm2)[kMaxMu], double (&I)[kMaxMu],
+                                              double (&Id)[kMaxMu]) {
+  double jd = 0.0;
+#pragma unroll
+  for (int m = 0; m < NMU; ++m) {
+    const double x = sx * i2mu[m], xd = sxd * i2mu[m];
+    double e, a, b, bx;
+    seg_ab(x, e, a, b, bx);
+    const double ed = -e * xd, ad = bx * xd, bd = (e - bx) * xd;
+    const double In = I[m] * e + a * S1 + b * S0;
+    const double Idn = Id[m] * e + I[m] * ed + ad * S1 + a * Sd1 + bd * S0 + b * Sd0;
+    I[m] = In;
+    Id[m] = Idn;
+    jd += wm2[m] * Idn;
+  }
+  return jd;
 }
 
 // Intensities and their derivatives along every ray of one frequency (one
-// lane per frequency of a chunk), all angles at once; J' of each depth goes
-// to Jm (the ingoing part on the way down, the outgoing part added on the way
-// up by the same lane).
+// lane per frequency of a chunk), all angles at once.  The downward sweep
+// makes chi, S and their derivatives depth by depth and parks them for the
+// upward one; J' of each depth goes to Jm (the ingoing part on the way down,
+// the outgoing part added on the way up by the same lane).
+template <int NMU>
 __global__ __launch_bounds__(64) void k_tan_formal(const ColDev* __restrict__ cols,
                                                    const Tile* __restrict__ tiles, int ntiles) {
   if ((int)blockIdx.x >= ntiles) return;
   const ColDev& C = cols[uni(tiles[blockIdx.x].col)];
   if (!tan_on(C)) return;
+  if (uni(C.nmu) != NMU) return;
   const int chunk = uni(tiles[blockIdx.x].chunk);
-  const int nz = C.nz, nnu = C.nnu, fp = C.fp, nmu = C.nmu;
+  const int nz = C.nz, nnu = C.nnu, fp = C.fp, L = C.L, nbf = C.nbf, nline = C.nline;
   const int f = chunk * kWave + (int)threadIdx.x;
   if (f >= nnu) return;
-  const double* __restrict__ XS = C.XS;
+  double* __restrict__ XS = C.XS;
+  double* __restrict__ Dx = C.Dchi;
+  double* __restrict__ Ds = C.Deta;
   double* __restrict__ Jd = C.Jm;
+  const double* __restrict__ dzs = C.dz;
+  const double gam = C.gam[f];
+  double i2mu[kMaxMu], wm2[kMaxMu];
+#pragma unroll
+  for (int m = 0; m < kMaxMu; ++m) {
+    i2mu[m] = C.inv2mu[m];
+    wm2[m] = C.wm2[m];
+  }
   double I[kMaxMu], Id[kMaxMu];
   // ingoing rays, top -> bottom (I- = 0 at the top)
 #pragma unroll
   for (int m = 0; m < kMaxMu; ++m) I[m] = Id[m] = 0.0;
+  double X0, S0, Xd0, Sd0;
+  tan_opacity(C, chunk, 0, f, L, nnu, nbf, nline, gam, X0, S0, Xd0, Sd0);
   size_t kx = (size_t)f;
-  double X0 = XS[2 * kx], S0 = XS[2 * kx + 1], Xd0 = C.Dchi[kx], Sd0 = C.Deta[kx];
+  XS[2 * kx] = X0;
+  XS[2 * kx + 1] = S0;
+  Dx[kx] = Xd0;
+  Ds[kx] = Sd0;
   Jd[kx] = 0.0;
   for (int k = 1; k < nz; ++k) {
+    double X1, S1, Xd1, Sd1;
+    tan_opacity(C, chunk, k, f, L, nnu, nbf, nline, gam, X1, S1, Xd1, Sd1);
     kx = (size_t)k * fp + f;
-    const double X1 = XS[2 * kx], S1 = XS[2 * kx + 1], Xd1 = C.Dchi[kx], Sd1 = C.Deta[kx];
-    const double dz = C.dz[k - 1];
-    const double sx = dz * (X0 + X1), sxd = dz * (Xd0 + Xd1);
-    double jd = 0.0;
-#pragma unroll
-    for (int m = 0; m < kMaxMu; ++m) {
-      if (m < nmu) {
-        const double x = sx * C.inv2mu[m], xd = sxd * C.inv2mu[m];
-        double e, a, b, bx;
-        seg_ab(x, e, a, b, bx);
-        const double ed = -e * xd, ad = bx * xd, bd = (e - bx) * xd;
-        const double In = I[m] * e + a * S1 + b * S0;
-        const double Idn = Id[m] * e + I[m] * ed + ad * S1 + a * Sd1 + bd * S0 + b * Sd0;
-        I[m] = In;
-        Id[m] = Idn;
-        jd += C.wm2[m] * Idn;
-      }
-    }
-    Jd[kx] = jd;
+    XS[2 * kx] = X1;
+    XS[2 * kx + 1] = S1;
+    Dx[kx] = Xd1;
+    Ds[kx] = Sd1;
+    const double dz = dzs[k - 1];
+    Jd[kx] = tan_segment<NMU>(dz * (X0 + X1), dz * (Xd0 + Xd1), S0, Sd0, S1, Sd1, i2mu, wm2, I, Id);
     X0 = X1; S0 = S1; Xd0 = Xd1; Sd0 = Sd1;
   }
   // outgoing rays, bottom -> top (I+ = B at the bottom, I+' = 0)
@@ -185,25 +205,9 @@ __global__ __launch_bounds__(64) void k_tan_formal(const ColDev* __restrict__ co
   }
   for (int k = nz - 2; k >= 0; --k) {
     kx = (size_t)k * fp + f;
-    const double X1 = XS[2 * kx], S1 = XS[2 * kx + 1], Xd1 = C.Dchi[kx], Sd1 = C.Deta[kx];
-    const double dz = C.dz[k];
-    const double sx = dz * (X0 + X1), sxd = dz * (Xd0 + Xd1);
-    double jd = 0.0;
-#pragma unroll
-    for (int m = 0; m < kMaxMu; ++m) {
-      if (m < nmu) {
-        const double x = sx * C.inv2mu[m], xd = sxd * C.inv2mu[m];
-        double e, a, b, bx;
-        seg_ab(x, e, a, b, bx);
-        const double ed = -e * xd, ad = bx * xd, bd = (e - bx) * xd;
-        const double In = I[m] * e + a * S1 + b * S0;
-        const double Idn = Id[m] * e + I[m] * ed + ad * S1 + a * Sd1 + bd * S0 + b * Sd0;
-        I[m] = In;
-        Id[m] = Idn;
-        jd += C.wm2[m] * Idn;
-      }
-    }
-    Jd[kx] += jd;
+    const double X1 = XS[2 * kx], S1 = XS[2 * kx + 1], Xd1 = Dx[kx], Sd1 = Ds[kx];
+    const double dz = dzs[k];
+    Jd[kx] += tan_segment<NMU>(dz * (X0 + X1), dz * (Xd0 + Xd1), S0, Sd0, S1, Sd1, i2mu, wm2, I, Id);
     X0 = X1; S0 = S1; Xd0 = Xd1; Sd0 = Sd1;
   }
 }
@@ -289,8 +293,19 @@ __global__ __launch_bounds__(kTanAsmDepths) void k_tan_assemble(const ColDev* __
 hipError_t launch_tangent(const BatchWork& bw, hipStream_t s) {
   if (bw.ntiles <= 0) return hipSuccess;
   const int nblk = bw.act ? bw.nact : bw.ncol;
-  k_tan_opacity<<<bw.ntiles * kTanSplit, 64, 0, s>>>(bw.cols, bw.tiles, bw.ntiles);
-  k_tan_formal<<<bw.ntiles, 64, 0, s>>>(bw.cols, bw.tiles, bw.ntiles);
+  // one instantiation per angle count present (tile groups are per angle
+  // count; each launch covers the tiles of its groups)
+  for (int g = 0; g < bw.ngroup; ++g) {
+    const TileGroup& G = bw.groups[g];
+    const Tile* tl = bw.tiles + G.first;
+    switch (G.nmu) {
+#define TF(M) \
+  case M: k_tan_formal<M><<<G.count, 64, 0, s>>>(bw.cols, tl, G.count); break;
+      TF(1) TF(2) TF(3) TF(4) TF(5) TF(6) TF(7) TF(8)
+#undef TF
+      default: return hipErrorInvalidValue;
+    }
+  }
   k_tan_rates<<<nblk * kTanRateSplit, kTanRateThreads, 0, s>>>(bw.cols, bw.act);
   const int nsub = (bw.maxnz + kTanAsmDepths - 1) / kTanAsmDepths;
   k_tan_assemble<<<nblk * nsub, kTanAsmDepths, 0, s>>>(bw.cols, bw.act, nsub);
