@@ -43,10 +43,11 @@ def _wait(srv, ticket, col, timeout=120.0):
         time.sleep(0.002)
 
 
-@pytest.mark.parametrize("krylov", [0, 1], ids=["gmres", "bicgstab"])
-def test_served_equals_alone(ctx, krylov):
+@pytest.mark.parametrize("krylov,jv", [(0, 0), (1, 0), (0, 1)],
+                         ids=["gmres", "bicgstab", "gmres-tangent"])
+def test_served_equals_alone(ctx, krylov, jv):
     from paper_2406_17234_amd import nlte
-    opts = dict(OPTS, krylov_method=krylov)
+    opts = dict(OPTS, krylov_method=krylov, jv_method=jv)
     cols = _mixed_columns(ctx)
     alone = []
     for c in cols:
