@@ -59,6 +59,34 @@ def test_tangent_product_matches_oracle_complex_step(ctx, name, flags, tol):
     col.close()
 
 
+def _sixteen():
+    from tests.test_gpu_edges import _sixteen_levels
+    return _sixteen_levels()
+
+
+@pytest.mark.parametrize("name,maker", [
+    ("smallest column, one angle", lambda: S.tiny(nz=3, nmu=1, nline_pts=3, nbf_pts=2)),
+    ("eight angles", lambda: S.tiny(nmu=8)),
+    ("16 levels, 24 lines, 15 edges", _sixteen),
+])
+def test_tangent_product_at_the_size_limits(ctx, name, maker):
+    """The angle counts at both ends of the range (each its own kernel
+    instantiation), the smallest column and the largest atom."""
+    from paper_2406_17234_amd import nlte
+    prob = maker()
+    tb = O.setup(prob)
+    n = perturbed(tb.nstar, seed=73, scale=0.2)
+    v = np.random.default_rng(173).standard_normal(n.shape) * n
+    print(f"[case] tangent product {name} dims={prob.dims}", flush=True)
+    ref = O.jvp_complex_step(tb, n, v)
+    col = nlte.Column(ctx, prob, precision=nlte.FP64)
+    Jv = to_np(col.jvp_tangent(to_dev(n), to_dev(v)))
+    err = np.max(np.abs(Jv - ref)) / np.max(np.abs(ref))
+    print(f"  max err / max |Jv| = {err:.3e}", flush=True)
+    assert err < 1e-13
+    col.close()
+
+
 def test_tangent_product_is_linear_and_close_to_forward_difference(ctx):
     """Exact to rounding, so linear in v; the forward difference of Eq. fordif
     approaches it to its truncation error."""
