@@ -45,13 +45,14 @@ __device__ __forceinline__ bool tan_on(const ColDev& C) {
 //   a  = sum_{m>=1} (-1)^(m+1) x^m / (m+1)!,
 //   b  = sum_{m>=1} (-1)^(m+1) m x^m / (m+1)!,
 //   bx = sum_{m>=1} (-1)^(m+1) m x^(m-1) / (m+1)!,
-// twelve terms (truncation below 1e-20 relative there); above, 1 - e has no
-// cancellation (it is at least 0.095) and one reciprocal of x serves both
-// quotients.
-__device__ __forceinline__ void seg_ab(double x, double& e, double& a, double& b, double& bx) {
+// ten terms (truncation below 1e-17 relative there); above, 1 - e has no
+// cancellation (it is at least 0.095) and rx = 1/x (shared by the angles of
+// a segment, passed in) serves both quotients.
+__device__ __forceinline__ void seg_ab(double x, double rx, double& e, double& a, double& b,
+                                       double& bx) {
   e = exp(-x);
   if (x < 0.1) {
-    constexpr int kTerms = 12;
+    constexpr int kTerms = 10;
     double fa = 0.0, fb = 0.0;
     double fact = 1.0;  // (m+1)! for m = kTerms
     for (int j = 2; j <= kTerms + 1; ++j) fact *= j;
@@ -67,7 +68,6 @@ __device__ __forceinline__ void seg_ab(double x, double& e, double& a, double& b
     bx = fb;
     b = fb * x;
   } else {
-    const double rx = 1.0 / x;
     const double t1 = (1.0 - e) * rx;
     a = 1.0 - t1;
     b = t1 - e;
@@ -116,24 +116,28 @@ __device__ __forceinline__ void tan_opacity(const ColDev& C, int chunk, int k, i
   if (C.has_sca) eta += C.chi_sca[k] * C.Jdag[kf];
   Xd = chid + (A1d - E * A2d);
   const double etad = gam * (etd + E * A2d);
-  S = eta / X;
-  Sd = (etad - S * Xd) / X;
+  const double rX = 1.0 / X;
+  S = eta * rX;
+  Sd = (etad - S * Xd) * rX;
 }
 
 // One segment of every ray of a lane (NMU angles in registers): I and I'
 // advance from the segment's start (S0, S0') to its end (S1, S1');
-// returns sum_m w_m/2 I'_m at the end.
+// returns sum_m w_m/2 I'_m at the end.  x_m = sx / (2 mu_m), so one
+// reciprocal of sx gives every 1/x_m = (2 mu_m) / sx.
 template <int NMU>
 __device__ __forceinline__ double tan_segment(double sx, double sxd, double S0, double Sd0,
                                               double S1, double Sd1, const double (&i2mu)[kMaxMu],
+                                              const double (&mu2)[kMaxMu],
                                               const double (&wm2)[kMaxMu], double (&I)[kMaxMu],
                                               double (&Id)[kMaxMu]) {
   double jd = 0.0;
+  const double rs = 1.0 / sx;
 #pragma unroll
   for (int m = 0; m < NMU; ++m) {
     const double x = sx * i2mu[m], xd = sxd * i2mu[m];
     double e, a, b, bx;
-    seg_ab(x, e, a, b, bx);
+    seg_ab(x, rs * mu2[m], e, a, b, bx);
     const double ed = -e * xd, ad = bx * xd, bd = (e - bx) * xd;
     const double In = I[m] * e + a * S1 + b * S0;
     const double Idn = Id[m] * e + I[m] * ed + ad * S1 + a * Sd1 + bd * S0 + b * Sd0;
@@ -166,10 +170,11 @@ __global__ __launch_bounds__(64) void k_tan_formal(const ColDev* __restrict__ co
   double* __restrict__ Jd = C.Jm;
   const double* __restrict__ dzs = C.dz;
   const double gam = C.gam[f];
-  double i2mu[kMaxMu], wm2[kMaxMu];
+  double i2mu[kMaxMu], mu2[kMaxMu], wm2[kMaxMu];
 #pragma unroll
   for (int m = 0; m < kMaxMu; ++m) {
     i2mu[m] = C.inv2mu[m];
+    mu2[m] = m < NMU ? 1.0 / i2mu[m] : 0.0;
     wm2[m] = C.wm2[m];
   }
   double I[kMaxMu], Id[kMaxMu];
@@ -193,7 +198,7 @@ __global__ __launch_bounds__(64) void k_tan_formal(const ColDev* __restrict__ co
     Dx[kx] = Xd1;
     Ds[kx] = Sd1;
     const double dz = dzs[k - 1];
-    Jd[kx] = tan_segment<NMU>(dz * (X0 + X1), dz * (Xd0 + Xd1), S0, Sd0, S1, Sd1, i2mu, wm2, I, Id);
+    Jd[kx] = tan_segment<NMU>(dz * (X0 + X1), dz * (Xd0 + Xd1), S0, Sd0, S1, Sd1, i2mu, mu2, wm2, I, Id);
     X0 = X1; S0 = S1; Xd0 = Xd1; Sd0 = Sd1;
   }
   // outgoing rays, bottom -> top (I+ = B at the bottom, I+' = 0)
@@ -207,7 +212,7 @@ __global__ __launch_bounds__(64) void k_tan_formal(const ColDev* __restrict__ co
     kx = (size_t)k * fp + f;
     const double X1 = XS[2 * kx], S1 = XS[2 * kx + 1], Xd1 = Dx[kx], Sd1 = Ds[kx];
     const double dz = dzs[k];
-    Jd[kx] += tan_segment<NMU>(dz * (X0 + X1), dz * (Xd0 + Xd1), S0, Sd0, S1, Sd1, i2mu, wm2, I, Id);
+    Jd[kx] += tan_segment<NMU>(dz * (X0 + X1), dz * (Xd0 + Xd1), S0, Sd0, S1, Sd1, i2mu, mu2, wm2, I, Id);
     X0 = X1; S0 = S1; Xd0 = Xd1; Sd0 = Sd1;
   }
 }
