@@ -43,6 +43,7 @@ extern "C" const char* nlte_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 struct nlte_column {
   nlte_ctx* ctx = nullptr;
+  int device = 0;             // ctx->device, kept so that destruction never reads ctx
   ColDev h{};                 // device pointers, host copy
   ColDev* d = nullptr;        // device copy (one-element batch)
   void* arena = nullptr;
@@ -512,6 +513,10 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
                                           const double* C_up, int32_t prec_arg,
                                           hipStream_t stream, nlte_column** out) {
   if (!ctx || !out) return set_err(NLTE_E_INVALID, "NULL ctx/out");
+  // the setup checks its launches with hipGetLastError: start from a clear
+  // state so that an error left by an unrelated earlier call is not reported
+  // as this column's
+  (void)hipGetLastError();
   const int prec = prec_arg & ~NLTE_DEPTH_SCAN;
   const int scan = (prec_arg & NLTE_DEPTH_SCAN) != 0;
   if (prec != NLTE_FP64 && prec != NLTE_FP32_FORM) return set_err(NLTE_E_INVALID, "bad precision");
@@ -723,6 +728,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   }
   nlte_column* col = new nlte_column();
   col->ctx = ctx;
+  col->device = ctx->device;
   col->arena_bytes = sizer.off + 256;
   hipError_t he = hipMalloc(&col->arena, col->arena_bytes);
   if (he != hipSuccess) {
@@ -849,7 +855,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
 
 extern "C" void nlte_column_destroy(nlte_column* col) {
   if (!col) return;
-  (void)hipSetDevice(col->ctx->device);
+  (void)hipSetDevice(col->device);
   if (col->d) (void)hipFree(col->d);
   if (col->arena) (void)hipFree(col->arena);
   delete col;

@@ -47,6 +47,7 @@ __global__ void k_plan_out(const ColDev* __restrict__ cols, double* const* __res
 
 struct nlte_plan {
   nlte_ctx* ctx = nullptr;
+  int device = 0;  // ctx->device, kept so that destruction never reads ctx
   int ncol = 0;
   ColDev* cols = nullptr;
   Tile* tiles = nullptr;
@@ -133,6 +134,7 @@ extern "C" nlte_status nlte_plan_create(nlte_ctx* ctx, nlte_column* const* cols,
   HIP_TRY(hipSetDevice(ctx->device));
   nlte_plan* P = new nlte_plan();
   P->ctx = ctx;
+  P->device = ctx->device;
   P->ncol = ncol;
   std::vector<Tile> tiles;
   std::vector<TileGroup> groups;
@@ -228,6 +230,6 @@ extern "C" nlte_status nlte_plan_info_get(const nlte_plan* P, nlte_plan_info* ou
 
 extern "C" void nlte_plan_destroy(nlte_plan* P) {
   if (!P) return;
-  hipSetDevice(P->ctx->device);
+  (void)hipSetDevice(P->device);
   delete P;
 }

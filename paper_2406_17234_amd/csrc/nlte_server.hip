@@ -73,6 +73,7 @@ double now_ms(std::chrono::steady_clock::time_point t0) {
 
 struct nlte_server {
   nlte_ctx* ctx = nullptr;
+  int device = 0;  // ctx->device, kept so that the worker and destruction never read ctx
   size_t budget = 0;
   int max_active = 0;
   nlte_solve_opts opts{};
@@ -176,7 +177,7 @@ hipError_t nlte_server::admit(std::vector<Request*>& adm) {
 }
 
 void nlte_server::run() {
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = d_done.fit(1);
   if (e == hipSuccess) e = hipMemsetAsync(d_done.p, 0, sizeof(int), stream);
   bool dirty = false;
@@ -278,6 +279,7 @@ extern "C" nlte_status nlte_server_create(nlte_ctx* ctx, size_t hbm_budget, int3
   if (hipSetDevice(ctx->device) != hipSuccess) return set_err(NLTE_E_DEVICE, "hipSetDevice failed");
   nlte_server* S = new nlte_server();
   S->ctx = ctx;
+  S->device = ctx->device;
   S->budget = hbm_budget;
   S->max_active = max_active;
   S->opts = o;
@@ -378,7 +380,7 @@ extern "C" void nlte_server_destroy(nlte_server* S) {
   }
   S->cv.notify_all();
   if (S->th.joinable()) S->th.join();
-  hipSetDevice(S->ctx->device);
+  (void)hipSetDevice(S->device);
   hipStreamSynchronize(S->stream);
   for (auto& kv : S->reqs) delete kv.second;
   if (S->h_states) hipHostFree(S->h_states);

@@ -122,3 +122,27 @@ def test_sizes_beyond_limits_rejected(ctx):
     stats = (nlte.SolveStats * 1)()
     rc = L.nlte_solve_batch(ctx.h, None, 0, None, ctypes.byref(opts), None, stats, None)
     assert rc == nlte.NLTE_E_INVALID
+
+
+def test_objects_outliving_their_context(ctx):
+    """A column, plan or server destroyed after its context (as a cyclic
+    garbage collection may order it) releases its memory on its own device
+    and leaves no error behind for the next call."""
+    from paper_2406_17234_amd import nlte
+    other = nlte.Context(0)
+    col = nlte.Column(other, S.tiny(), precision=nlte.FP64)
+    tb = O.setup(S.tiny())
+    nd = to_dev(tb.nstar)
+    Fd = to_dev(np.zeros_like(tb.nstar))
+    plan = nlte.Plan(other, [col], [nd], [Fd], graph=False)
+    srv = nlte.Server(other, hbm_budget=1 << 30, max_active=4)
+    other.close()
+    srv.close()
+    plan.close()
+    col.close()
+    fresh = nlte.Column(ctx, S.tiny(), precision=nlte.FP64)
+    n = perturbed(tb.nstar, seed=54, scale=0.2)
+    out = fresh.residual(to_dev(n))
+    ref = O.residual(tb, n)
+    assert np.max(np.abs(to_np(out["F"]) - ref.F) / ref.G) < 1e-11
+    fresh.close()
