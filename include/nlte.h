@@ -85,9 +85,11 @@ typedef struct {
   const double *T;         /* [nz] K                                            */
   const double *ne;        /* [nz] electron density, cm^-3                      */
   const double *ntot;      /* [nz] total density of the active atom, cm^-3      */
-  const double *chi_c;     /* [nz] gray background opacity, cm^-1; the
-                              background emissivity is chi_c B_nu(T)           */
+  const double *chi_c;     /* [nz] gray background opacity, cm^-1               */
   const double *chi_sca;   /* [nz] background scattering opacity or NULL (0)   */
+  const double *eta_c;     /* [nz][nnu] thermal background emissivity
+                              (erg s^-1 cm^-3 Hz^-1 sr^-1, finite, >= 0; nnu of
+                              the grid descriptor) or NULL: chi_c B_nu(T)     */
 } nlte_atmos_desc;
 
 /* Model atom, Sect. 2.1.1.  If nbf > 0 the last level is the continuum
@@ -121,6 +123,11 @@ typedef struct {
   int32_t nmu;             /* 1..8 angles; two rays (+-mu) each                 */
   const double *mu;        /* [nmu] Gauss-Legendre nodes on (0, 1)              */
   const double *w_mu;      /* [nmu] weights, summing to 1                        */
+  const double *w_nu;      /* [nnu] frequency quadrature weights (Hz, > 0) that
+                              every transition uses over its window, or NULL:
+                              trapezoid weights over each transition's own
+                              window.  Line profiles are normalised on their
+                              window with the same weights.                    */
 } nlte_grid_desc;
 
 typedef struct {
@@ -148,6 +155,11 @@ typedef struct {
   int32_t jv_method;     /* nlte_jv (default NLTE_JV_FD).  With
                           * NLTE_JV_TANGENT a product costs one tangent
                           * evaluation (no difference step; eps_scale unused) */
+  int32_t krylov_x0;     /* initial guess of each Krylov solve (Algorithm 2):
+                          * 0 (default) x0 = 0; 1 x0 = -P^-1 F(n), which costs
+                          * one more Jacobian product per Newton iteration
+                          * (counted in krylov_iters and the budgets)          */
+  int32_t pad_opts;      /* reserved, set to 0                                 */
 } nlte_solve_opts;
 
 typedef struct {
@@ -204,6 +216,15 @@ nlte_status nlte_column_create(nlte_ctx *ctx, const nlte_atmos_desc *atmos,
                                hipStream_t stream, nlte_column **out);
 void nlte_column_destroy(nlte_column *col);
 
+/* Host-only check and sizing of a column (no device is used): validates the
+ * descriptors exactly as nlte_column_create does and, on NLTE_OK, writes the
+ * bytes of device memory such a column would own.  Errors: NLTE_E_INVALID
+ * (sizes, orderings, level indices, windows, signs), NLTE_E_NONFINITE
+ * (NaN/Inf in any array). */
+nlte_status nlte_column_plan_bytes(const nlte_atmos_desc *atmos, const nlte_atom_desc *atom,
+                                   const nlte_grid_desc *grid, const double *C_up,
+                                   int32_t precision, size_t *bytes);
+
 /* dims = {nz, nlev, ntr, nline, nbf, nnu, nmu, precision (| NLTE_DEPTH_SCAN)} */
 nlte_status nlte_column_dims(const nlte_column *col, int32_t dims[8]);
 /* Bytes of device memory the column owns (its arena). */
@@ -250,27 +271,37 @@ nlte_status nlte_jvp(nlte_column *col, const double *n_dev, const double *v_dev,
 nlte_status nlte_jvp_tangent(nlte_column *col, const double *n_dev, const double *v_dev,
                              double *Jv_dev, hipStream_t stream);
 
-/* JFNK solve (Algorithm 2) of one column, entirely on the device.
+/* JFNK solve (Algorithm 2, whose Data are n0 and an initial estimate of J)
+ * of one column, entirely on the device.
  *   n0_dev   [nz][nlev] initial populations when opts->init == 0 (else unused);
+ *   J0_dev   [nz][nnu] initial J-dagger, the lagged mean intensity of the
+ *            background-scattering emissivity (Sect. 2.1.1), or NULL: B_nu(T);
  *   n_out_dev[nz][nlev] converged (or best) populations;
- *   J_out_dev[nz][nnu] final mean intensity or NULL;
+ *   J_out_dev[nz][nnu] or NULL: the J-dagger of the final residual, so that
+ *            F(n_out; J_out) is the residual the stopping test saw.  For a
+ *            column with background scattering it is the mean intensity of
+ *            the evaluation before the last, and (n_out, J_out) restarts the
+ *            solve where it stopped (pass them as n0 with init = 0 and as J0);
+ *            without scattering F does not depend on it and it is the mean
+ *            intensity of the final evaluation;
  *   stats    host struct or NULL.
  * Returns NLTE_E_NOCONV when maxiter is reached (n_out holds the last
  * iterate).  Blocks until the solve has finished on `stream`. */
-nlte_status nlte_solve(nlte_column *col, const double *n0_dev, const nlte_solve_opts *opts,
-                       double *n_out_dev, double *J_out_dev, nlte_solve_stats *stats,
-                       hipStream_t stream);
+nlte_status nlte_solve(nlte_column *col, const double *n0_dev, const double *J0_dev,
+                       const nlte_solve_opts *opts, double *n_out_dev, double *J_out_dev,
+                       nlte_solve_stats *stats, hipStream_t stream);
 
 /* Solves ncol independent columns (any sizes, any precision) together: every
  * step evaluates one residual per active column in the same launches, with
  * per-column Krylov/Newton state on the device.  Arrays are indexed by
- * column; n0_dev may be NULL when opts->init != 0; stats is [ncol] or NULL.
+ * column; n0_dev may be NULL when opts->init != 0; J0_dev (initial J-dagger
+ * per column, entries may be NULL) may be NULL; stats is [ncol] or NULL.
  * Returns NLTE_OK if every column converged, else NLTE_E_NOCONV (per-column
  * status in stats). */
 nlte_status nlte_solve_batch(nlte_ctx *ctx, nlte_column *const *cols, int32_t ncol,
-                             const double *const *n0_dev, const nlte_solve_opts *opts,
-                             double *const *n_out_dev, nlte_solve_stats *stats,
-                             hipStream_t stream);
+                             const double *const *n0_dev, const double *const *J0_dev,
+                             const nlte_solve_opts *opts, double *const *n_out_dev,
+                             nlte_solve_stats *stats, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Residual plans: F(n) of a fixed set of columns in shared launches.

@@ -73,7 +73,7 @@ def voigt_H(a, v):
 
 def window_weights(nu_win):
     """Trapezoid weights over one transition's window (quadrature coefficients
-    omega_nu of Sect. 2.1.2)."""
+    omega_nu of Sect. 2.1.2; used unless the grid brings its own weights)."""
     w = np.empty_like(nu_win)
     d = np.diff(nu_win)
     w[0] = 0.5 * d[0]
@@ -84,9 +84,11 @@ def window_weights(nu_win):
 
 def setup(prob):
     """Build the tables that do not depend on the populations: LTE n*,
-    Planck B, background emissivity, the unified transition coefficients
-    V_ij and g_ij (Sect. 2.1.1) on each transition window, collision rates in
-    both directions (detailed balance), quadrature weights."""
+    Planck B, background emissivity (the atmosphere's eta_c if it has one,
+    else chi_c B_nu), the unified transition coefficients V_ij and g_ij
+    (Sect. 2.1.1) on each transition window, collision rates in both
+    directions (detailed balance), quadrature weights (the grid's w_nu over
+    each window if it has them, else trapezoid weights per window)."""
     a, atm, gr = prob.atom, prob.atmos, prob.grid
     nz, nlev, ntr, nline = atm.nz, a.nlev, a.ntr, a.nline
     nu = gr.nu
@@ -96,10 +98,11 @@ def setup(prob):
     lo = a.tr_lo()
     up = a.tr_up()
     tr = []
+    w_nu = getattr(gr, "w_nu", None)
     for t in range(ntr):
         f0, f1 = int(gr.win_lo[t]), int(gr.win_hi[t])
         nuw = nu[f0:f1]
-        w = window_weights(nuw)
+        w = window_weights(nuw) if w_nu is None else np.array(w_nu[f0:f1], dtype=float)
         c = 4.0 * np.pi * w / (HP * nuw)                  # 4 pi w / (h nu)
         l, u = int(lo[t]), int(up[t])
         if t < nline:
@@ -125,7 +128,8 @@ def setup(prob):
     C_lu = prob.C_up.copy()
     C_ul = C_lu * nstar[:, lo] / nstar[:, up]
     chi_c = np.broadcast_to(atm.chi_c[:, None], (nz, gr.nnu)).copy()
-    eta_c = chi_c * B
+    eta_given = getattr(atm, "eta_c", None)
+    eta_c = chi_c * B if eta_given is None else np.array(eta_given, dtype=float)
     dz = np.abs(np.diff(atm.z))
     return SimpleNamespace(prob=prob, nz=nz, nlev=nlev, ntr=ntr, nline=nline,
                            nnu=gr.nnu, nmu=gr.nmu, nu=nu, T=T, nstar=nstar, B=B,
@@ -447,10 +451,12 @@ def jacobian_complex_step(tb, n, Jdag=None, rows=None, h=1e-20):
 # Krylov solver (Sect. 2.3): left-preconditioned restarted GMRES
 # ----------------------------------------------------------------------------
 
-def gmres(matvec, b, rtol=1e-3, m=30, maxit=200):
+def gmres(matvec, b, rtol=1e-3, m=30, maxit=200, x0=None):
     """GMRES(m) (Arnoldi with modified Gram-Schmidt and one
-    re-orthogonalisation, Givens rotations), x0 = 0; stops when
-    ||b - A x|| <= rtol ||b||.  Returns (x, iterations, final relative residual)."""
+    re-orthogonalisation, Givens rotations) from the initial guess x0 (zero
+    by default; Algorithm 2 also names -P^-1 f); stops when
+    ||b - A x|| <= rtol ||b||.  Returns (x, products with A, final relative
+    residual); a nonzero x0 costs one product for r0 = b - A x0."""
     N = b.size
     x = np.zeros(N)
     bnorm = np.linalg.norm(b)
@@ -458,6 +464,10 @@ def gmres(matvec, b, rtol=1e-3, m=30, maxit=200):
         return x, 0, 0.0
     r = b.copy()
     it = 0
+    if x0 is not None:
+        x = np.array(x0, dtype=float)
+        r = b - matvec(x)
+        it = 1
     rel = 1.0
     while it < maxit:
         beta = np.linalg.norm(r)
@@ -511,23 +521,29 @@ def matvec_restart(matvec, x):
 # Krylov solver (Sect. 2.3): BiCGSTAB, the paper's second inner solver
 # ----------------------------------------------------------------------------
 
-def bicgstab(matvec, b, rtol=1e-3, maxit=200):
+def bicgstab(matvec, b, rtol=1e-3, maxit=200, x0=None):
     """BiCGSTAB (van der Vorst 1992, as cited in Sect. 2.3): Lanczos-type
     bi-orthogonal directions with a one-parameter minimal-residual smoothing
-    step, two products with A per iteration.  x0 = 0, shadow residual r^ =
-    r0 = b; stops when ||r|| <= rtol ||b|| (checked on the half-step residual
-    s and on r), on a breakdown (rho or (r^, v) or omega zero), or after
-    maxit products.  Returns (x, products, final relative residual)."""
+    step, two products with A per iteration.  Initial guess x0 (zero by
+    default; a nonzero one costs one product for r0 = b - A x0), shadow
+    residual r^ = r0; stops when ||r|| <= rtol ||b|| (checked on the
+    half-step residual s and on r), on a breakdown (rho or (r^, v) or omega
+    zero), or after maxit products.  Returns (x, products, final relative
+    residual)."""
     N = b.size
     x = np.zeros(N)
     bnorm = np.linalg.norm(b)
     if bnorm == 0.0:
         return x, 0, 0.0
     r = b.copy()
-    rh = b.copy()
+    products = 0
+    if x0 is not None:
+        x = np.array(x0, dtype=float)
+        r = b - matvec(x)
+        products = 1
+    rh = r.copy()
     p = r.copy()
     rho = rh @ r
-    products = 0
     rel = 1.0
     while products < maxit:
         v = matvec(p)
@@ -608,7 +624,7 @@ def positivity_limit(n, dn, frac=0.9):
 
 def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
           max_krylov=200, max_halvings=8, Jdag0=None, eps_mach=2.0 ** -52,
-          verbose=False, krylov="gmres", jv="fd"):
+          verbose=False, krylov="gmres", jv="fd", krylov_x0="zero"):
     """JFNK solve of F(n) = 0 (Algorithm 2) with left block-Jacobi
     preconditioning, populations scaled by the Newton iterate for the
     finite-difference product, per-depth positivity limiting and damped
@@ -618,16 +634,30 @@ def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
     Convergence: ||rho||_inf <= ftol.  krylov: "gmres" (GMRES(m)) or
     "bicgstab" (max_krylov then counts products with the Jacobian).
     jv: "fd" (forward difference, Eq. fordif) or "complex" (complex step,
-    Eq. complex) for the Jacobian-vector products.
+    Eq. complex) for the Jacobian-vector products.  krylov_x0: "zero" or
+    "precond" (x0 = -P^-1 F, the second initial guess of Algorithm 2, which in
+    the scaled unknowns is b itself).
 
-    Returns a namespace with n, J, history and call counts (one call per
-    formal solution; re-assigning conservation rows at an accepted point
-    repeats no formal solution and is not counted).
+    Lagged scattering term (Sect. 2.1.1, Algorithm 2 "update J"): F(n0) uses
+    the initial estimate Jdag0 (default B_nu(T)).  At every accepted Newton
+    point J-dagger becomes the J of that point's evaluation; when the
+    atmosphere has background scattering, F is then evaluated again at the
+    same point with the new J-dagger, so that F(n), the Krylov products and
+    the line search of the next Newton step all see one J-dagger (the
+    difference of Eq. fordif would otherwise pick up the change of J-dagger
+    between its two terms).
+
+    Returns a namespace with n, J (the J-dagger of the final F: with it,
+    F(n; J) is the residual the stopping test saw; without scattering F does
+    not depend on it and it is the J of the final evaluation), history and
+    call counts (one call per formal solution; re-assigning conservation rows
+    at an accepted point repeats no formal solution and is not counted).
     """
     if n0 is None:
         n0 = tb.nstar.copy() if init == "lte" else zero_radiation_guess(tb)
     n = np.array(n0, dtype=float)
-    Jdag = tb.B.copy() if Jdag0 is None else Jdag0.copy()
+    Jdag = tb.B.copy() if Jdag0 is None else np.array(Jdag0, dtype=float)
+    has_sca = bool(np.any(tb.chi_sca != 0.0))
     res = residual(tb, n, Jdag=Jdag, want_P=True)
     calls = 1
     hist = [dict(rho=res.rho.max(), Finf=np.abs(res.F).max(), dn=np.nan, krylov=0)]
@@ -656,10 +686,11 @@ def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
 
         b = -(lu_solve_blocks(lus, F0) / D).ravel()
         phi0 = np.linalg.norm(b)
+        x0 = b.copy() if krylov_x0 == "precond" and phi0 > 0.0 else None
         if krylov == "bicgstab":
-            u, kit, krel = bicgstab(matvec, b, rtol=rtol, maxit=max_krylov)
+            u, kit, krel = bicgstab(matvec, b, rtol=rtol, maxit=max_krylov, x0=x0)
         else:
-            u, kit, krel = gmres(matvec, b, rtol=rtol, m=m, maxit=max_krylov)
+            u, kit, krel = gmres(matvec, b, rtol=rtol, m=m, maxit=max_krylov, x0=x0)
         dn = D * u.reshape(n.shape)
         lam = positivity_limit(n, dn)[:, None]
         alpha = 1.0
@@ -678,6 +709,9 @@ def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
         n = trial
         res = residual(tb, n, Jdag=Jdag, want_P=True)
         Jdag = res.J
+        if has_sca:
+            res = residual(tb, n, Jdag=Jdag, want_P=True)
+            calls += 1
         it += 1
         dnorm = 0.5 * np.max(np.abs((n - n_prev) / (n + n_prev)))
         hist.append(dict(rho=res.rho.max(), Finf=np.abs(res.F).max(), dn=dnorm,

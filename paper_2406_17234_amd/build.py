@@ -1,11 +1,16 @@
 """Build step: compiles the HIP sources into the in-tree shared library
-``libnlte.so`` for gfx950 (and the oracle's C helpers, if any)."""
+``libnlte.so`` for gfx950 (and the oracle's C helpers, if any).
+
+Each source is compiled to its own object in parallel, then the objects are
+linked; every call recompiles everything."""
 from __future__ import annotations
 
 import os
 import shutil
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -15,7 +20,7 @@ SOURCES = ["nlte_api.hip", "nlte_residual.hip", "nlte_solver.hip", "nlte_server.
            "nlte_plan.hip", "nlte_tangent.hip"]
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # keep FP32 arithmetic in scalar (non-packed) instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
@@ -29,18 +34,28 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = True) -> str:
-    """Compile every source into libnlte.so (always recompiles)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-o", tmp, *srcs]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed")
+        raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
+
+
+def build(verbose: bool = True) -> str:
+    """Compile every source into libnlte.so (always recompiles)."""
+    cc = hipcc()
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    with tempfile.TemporaryDirectory(prefix="nlte_build_") as tmpd:
+        objs = [os.path.join(tmpd, s.replace(".hip", ".o")) for s in SOURCES]
+        cmds = [[cc, *HIPCC_FLAGS, *inc, "-c", "-o", o, os.path.join(CSRC, s)]
+                for s, o in zip(SOURCES, objs)]
+        jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(jobs) as ex:
+            list(ex.map(lambda c: _run(c, verbose), cmds))
+        tmp = LIB + ".tmp"
+        _run([cc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
     return LIB
 

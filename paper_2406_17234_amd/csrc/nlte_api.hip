@@ -106,6 +106,8 @@ extern "C" void nlte_solve_opts_default(nlte_solve_opts* o) {
   o->eps_scale = 1.0;
   o->krylov_method = NLTE_KRYLOV_GMRES;
   o->jv_method = NLTE_JV_FD;
+  o->krylov_x0 = 0;
+  o->pad_opts = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -128,6 +130,7 @@ struct Layout {
 // raw inputs that only the setup kernels read
 struct SetupIn {
   const double *E, *g, *A_ul, *a_damp, *bf_nu, *bf_alpha, *C_up;
+  const double *w_nu;  // caller frequency weights [nnu] or NULL (trapezoid per window)
   const int *stage, *bf_ptr;
   double mass_amu, vturb;
 };
@@ -191,8 +194,8 @@ __global__ void k_setup_freq(ColDev C) {
 }
 
 // Per (t, window point): rate weight 4 pi w/(h nu) with trapezoid weights
-// over the transition's own window; edges: cross-section interpolated
-// linearly onto the union grid (their V table).
+// over the transition's own window (or the caller's weights); edges:
+// cross-section interpolated linearly onto the union grid (their V table).
 __global__ void k_setup_window(ColDev C, SetupIn in, const int* __restrict__ wbase, int wtotal) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= wtotal) return;
@@ -202,7 +205,7 @@ __global__ void k_setup_window(ColDev C, SetupIn in, const int* __restrict__ wba
   const int fl = i - wbase[t];
   const int f = T.wlo + fl;
   const int fm = max(f - 1, T.wlo), fp = min(f + 1, T.whi - 1);
-  const double w = 0.5 * (C.nu[fp] - C.nu[fm]);
+  const double w = in.w_nu ? in.w_nu[f] : 0.5 * (C.nu[fp] - C.nu[fm]);
   ((double*)C.cw)[T.cwoff + fl] = 4.0 * kPi * w / (kH * C.nu[f]);
   if (t >= C.nline) {
     const int e = t - C.nline;
@@ -257,7 +260,7 @@ __global__ void k_setup_norm(ColDev C, SetupIn in) {
     for (int fl = 0; fl < wl; ++fl) {
       const int f = T.wlo + fl;
       const int fm = max(f - 1, T.wlo), fp = min(f + 1, T.whi - 1);
-      s += 0.5 * (C.nu[fp] - C.nu[fm]) * phi[fl];
+      s += (in.w_nu ? in.w_nu[f] : 0.5 * (C.nu[fp] - C.nu[fm])) * phi[fl];
     }
     for (int fl = 0; fl < wl; ++fl) {
       const int f = T.wlo + fl;
@@ -303,6 +306,7 @@ __global__ void k_setup_f32(ColDev C, size_t nv, size_t nvt) {
   if (i < kf) {
     const size_t k = i / C.nnu, ip = k * C.fp + (i - k * C.nnu);  // padded rows
     ((float*)C.Bnuf)[ip] = (float)C.Bnu[i];
+    if (C.bg_eta) ((float*)C.ECf)[ip] = (float)C.EC[i];
     if (C.nbf) {
       ((float*)C.Ebff)[ip] = (float)C.Ebf[i];
       const size_t f = i / C.nz, iz = f * C.zp + (i - f * C.nz);  // padded [nnu][zp]
@@ -347,6 +351,16 @@ static nlte_status validate(const nlte_atmos_desc* A, const nlte_atom_desc* M,
   for (auto p : zs)
     if (!finite_all(p, nz)) return set_err(NLTE_E_NONFINITE, "non-finite atmosphere value");
   if (A->chi_sca && !finite_all(A->chi_sca, nz)) return set_err(NLTE_E_NONFINITE, "non-finite chi_sca");
+  if (A->eta_c) {
+    if (!finite_all(A->eta_c, (size_t)nz * nnu)) return set_err(NLTE_E_NONFINITE, "non-finite eta_c");
+    for (size_t i = 0; i < (size_t)nz * nnu; ++i)
+      if (A->eta_c[i] < 0) return set_err(NLTE_E_INVALID, "negative eta_c");
+  }
+  if (G->w_nu) {
+    if (!finite_all(G->w_nu, nnu)) return set_err(NLTE_E_NONFINITE, "non-finite w_nu");
+    for (int f = 0; f < nnu; ++f)
+      if (!(G->w_nu[f] > 0)) return set_err(NLTE_E_INVALID, "w_nu[%d] <= 0", f);
+  }
   for (int k = 0; k < nz; ++k) {
     if (A->ntot[k] <= 0) return set_err(NLTE_E_INVALID, "ntot[%d] <= 0", k);
     if (A->T[k] <= 0) return set_err(NLTE_E_INVALID, "T[%d] <= 0", k);
@@ -430,6 +444,7 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   C.nu = Lo.take<double>(nnu);
   C.gam = Lo.take<double>(nnu);
   C.Bnu = Lo.take<double>(kf);
+  C.EC = C.bg_eta ? Lo.take<double>(kf) : C.Bnu;
   C.Ebf = C.nbf ? Lo.take<double>(kf) : nullptr;
   C.EbfT = C.nbf ? Lo.take<double>(kfz) : nullptr;
   *tr_out = Lo.take<TrDev>(ntr);
@@ -449,11 +464,12 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   if (C.prec == NLTE_FP32_FORM) {
     C.Vf = Lo.take<float>((size_t)nline_tab * nz + (nwin_total - nline_tab));
     C.Bnuf = Lo.take<float>(kfp);
+    C.ECf = C.bg_eta ? Lo.take<float>(kfp) : C.Bnuf;
     C.Ebff = C.nbf ? Lo.take<float>(kfp) : nullptr;
     C.VTf = Lo.take<float>((size_t)nline_tab * nz + 1);
     C.EbfTf = C.nbf ? Lo.take<float>(kfz) : nullptr;
   } else {
-    C.Vf = C.Bnuf = C.Ebff = C.VTf = C.EbfTf = nullptr;
+    C.Vf = C.Bnuf = C.Ebff = C.VTf = C.EbfTf = C.ECf = nullptr;
   }
   C.coef = Lo.take<double>((size_t)nz * ncoef(ntr));
   C.ritem = Lo.take<RItem>(std::max(C.nritem, 1));
@@ -503,20 +519,39 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   wp->pb = Lo.take<int2>(std::max(wsz[2], 1));
   *stage = Lo.take<int>(L);
   *bf_ptr = Lo.take<int>(C.nbf + 1);
-  // raw setup inputs (doubles): E, g, A_ul, a_damp, bf_nu, bf_alpha, C_up
-  *raw = Lo.take<double>(2 * L + 2 * std::max(C.nline, 1) + 2 * std::max(nbf_tot, 1) + (size_t)nz * ntr);
+  // raw setup inputs (doubles): E, g, A_ul, a_damp, bf_nu, bf_alpha, C_up, w_nu
+  *raw = Lo.take<double>(2 * L + 2 * std::max(C.nline, 1) + 2 * std::max(nbf_tot, 1) + (size_t)nz * ntr +
+                         nnu);
   (void)in;
 }
 
-extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* A,
-                                          const nlte_atom_desc* M, const nlte_grid_desc* G,
-                                          const double* C_up, int32_t prec_arg,
-                                          hipStream_t stream, nlte_column** out) {
-  if (!ctx || !out) return set_err(NLTE_E_INVALID, "NULL ctx/out");
-  // the setup checks its launches with hipGetLastError: start from a clear
-  // state so that an error left by an unrelated earlier call is not reported
-  // as this column's
-  (void)hipGetLastError();
+namespace {
+// Everything column creation computes on the host before it touches the
+// device (plan_column), kept for the upload (nlte_column_create).
+struct ColumnPlan {
+  ColDev C{};
+  std::vector<TrDev> tr;
+  std::vector<int> wbase, lbase, ch_ptr, ch_tr, ch_eptr, ch_ed, pg_ptr, pg_code;
+  std::vector<double> Blu;
+  std::vector<RItem> ritem;
+  std::vector<PItem> pitem;
+  std::vector<Tile> tiles;
+  std::vector<int4> rate_w;
+  std::vector<int2> prec_w;
+  std::vector<TileGroup> groups;
+  int nline_tab = 0, nbf_tot = 0, nentries = 1, nentries_e = 1, m_cap = 32, nrate0_w = 0;
+  int wsz[3] = {0, 0, 0};
+  size_t bytes = 0;
+};
+}  // namespace
+
+// Host half of column creation: validates the descriptors and builds every
+// host-side table of the column (transitions, chunk and piece lists, gather
+// lists of the preconditioner blocks, single-column work lists) and the size
+// of its device arena, with no device call.
+static nlte_status plan_column(const nlte_atmos_desc* A, const nlte_atom_desc* M,
+                               const nlte_grid_desc* G, const double* C_up, int32_t prec_arg,
+                               ColumnPlan& P) {
   const int prec = prec_arg & ~NLTE_DEPTH_SCAN;
   const int scan = (prec_arg & NLTE_DEPTH_SCAN) != 0;
   if (prec != NLTE_FP64 && prec != NLTE_FP32_FORM) return set_err(NLTE_E_INVALID, "bad precision");
@@ -525,17 +560,18 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
                    kScanThreads);
   nlte_status vs = validate(A, M, G, C_up);
   if (vs != NLTE_OK) return vs;
-  HIP_TRY(hipSetDevice(ctx->device));
 
   const int nz = A->nz, L = M->nlev, nline = M->nline, nbf = M->nbf, ntr = nline + nbf;
   const int nnu = G->nnu, nmu = G->nmu;
-  ColDev C{};
+  P = ColumnPlan{};
+  ColDev& C = P.C;
   C.nz = nz; C.L = L; C.ntr = ntr; C.nline = nline; C.nbf = nbf; C.nnu = nnu; C.nmu = nmu;
   C.prec = prec; C.N = nz * L;
   C.scan = scan;
   C.nchunk = (nnu + kWave - 1) / kWave;
   C.fp = C.nchunk * kWave;
   C.zp = (nz + 15) & ~15;
+  C.bg_eta = A->eta_c != nullptr;
   C.has_sca = 0;
   if (A->chi_sca)
     for (int k = 0; k < nz; ++k)
@@ -547,10 +583,15 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     C.inv2muf[m] = (float)C.inv2mu[m];
   }
   // transitions, windows, chunk lists
-  std::vector<TrDev> tr(ntr);
-  std::vector<int> wbase(ntr + 1, 0), lbase(std::max(nline, 1) + 1, 0);
-  int nline_tab = 0;
-  std::vector<double> Blu(nline);
+  std::vector<TrDev>& tr = P.tr;
+  tr.assign(ntr, TrDev{});
+  std::vector<int>& wbase = P.wbase;
+  std::vector<int>& lbase = P.lbase;
+  wbase.assign(ntr + 1, 0);
+  lbase.assign(std::max(nline, 1) + 1, 0);
+  int& nline_tab = P.nline_tab;
+  std::vector<double>& Blu = P.Blu;
+  Blu.assign(nline, 0.0);
   for (int t = 0; t < ntr; ++t) {
     TrDev& T = tr[t];
     T.lo = t < nline ? M->line_lo[t] : M->bf_lo[t - nline];
@@ -587,14 +628,18 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     if (off > 0x7fffffff) return set_err(NLTE_E_INVALID, "profile tables too large");
   }
 
-  std::vector<int> ch_ptr(C.nchunk + 1, 0), ch_tr;
+  std::vector<int>& ch_ptr = P.ch_ptr;
+  std::vector<int>& ch_tr = P.ch_tr;
+  ch_ptr.assign(C.nchunk + 1, 0);
   for (int c = 0; c < C.nchunk; ++c) {
     const int f0 = c * kWave, f1 = std::min(nnu, f0 + kWave);
     for (int t = 0; t < nline; ++t)
       if (tr[t].wlo < f1 && tr[t].whi > f0) ch_tr.push_back(t);
     ch_ptr[c + 1] = (int)ch_tr.size();
   }
-  std::vector<int> ch_eptr(C.nchunk + 1, 0), ch_ed;
+  std::vector<int>& ch_eptr = P.ch_eptr;
+  std::vector<int>& ch_ed = P.ch_ed;
+  ch_eptr.assign(C.nchunk + 1, 0);
   for (int c = 0; c < C.nchunk; ++c) {
     const int f0 = c * kWave, f1 = std::min(nnu, f0 + kWave);
     for (int t = nline; t < ntr; ++t)
@@ -614,8 +659,8 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   }
   std::sort(cuts.begin(), cuts.end());
   cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
-  std::vector<PItem> pitem;
-  std::vector<RItem> ritem;
+  std::vector<PItem>& pitem = P.pitem;
+  std::vector<RItem>& ritem = P.ritem;
   std::vector<int2> ment;  // (t, t') of each entry
   std::vector<int> rcount(ntr, 0);  // rate entries per transition so far
   for (size_t c = 0; c + 1 < cuts.size(); ++c) {
@@ -695,51 +740,88 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     gl[Tt.lo * L + Tu.up].push_back((q << 3) | (3 << 1) | 0);
     gl[Tt.up * L + Tu.up].push_back((q << 3) | (3 << 1) | 1);
   }
-  std::vector<int> pg_ptr(L * L + 1, 0), pg_code;
+  std::vector<int>& pg_ptr = P.pg_ptr;
+  std::vector<int>& pg_code = P.pg_code;
+  pg_ptr.assign(L * L + 1, 0);
   for (int e = 0; e < L * L; ++e) {
     pg_code.insert(pg_code.end(), gl[e].begin(), gl[e].end());
     pg_ptr[e + 1] = (int)pg_code.size();
   }
-  const int nentries = std::max<int>(1, (int)ch_tr.size());
-  const int nentries_e = std::max<int>(1, (int)ch_ed.size());
-  int nbf_tot = nbf ? M->bf_ptr[nbf] : 0;
-  const int m_cap = 32;
+  P.nentries = std::max<int>(1, (int)ch_tr.size());
+  P.nentries_e = std::max<int>(1, (int)ch_ed.size());
+  P.nbf_tot = nbf ? M->bf_ptr[nbf] : 0;
+  P.m_cap = 32;
 
   // single-column work lists
-  std::vector<Tile> tiles;
-  std::vector<int4> rate_w;
-  std::vector<int2> prec_w;
   int maxL_w = 0;
-  std::vector<TileGroup> groups;
-  const int nrate0_w = build_work_lists(&C, 1, tiles, groups, rate_w, prec_w, maxL_w);
-  const int wsz[3] = {(int)tiles.size(), (int)rate_w.size(), (int)prec_w.size()};
+  P.nrate0_w = build_work_lists(&C, 1, P.tiles, P.groups, P.rate_w, P.prec_w, maxL_w);
+  P.wsz[0] = (int)P.tiles.size();
+  P.wsz[1] = (int)P.rate_w.size();
+  P.wsz[2] = (int)P.prec_w.size();
 
-  // layout
+  // size of the device arena
   SetupIn in{};
   TrDev* tr_d;
   int *wbase_d, *lbase_d, *stage_d, *bfptr_d;
   WorkPtrs wp{};
   double* raw_d;
   Layout sizer(nullptr);
-  {
-    ColDev tmp = C;
-    layout_column(sizer, tmp, in, wbase[ntr], nline_tab, nbf_tot, nentries, nentries_e, m_cap, &tr_d,
-                  &wbase_d, &lbase_d, &wp, wsz, &stage_d, &bfptr_d, &raw_d);
-  }
+  ColDev tmp = C;
+  layout_column(sizer, tmp, in, wbase[ntr], nline_tab, P.nbf_tot, P.nentries, P.nentries_e, P.m_cap,
+                &tr_d, &wbase_d, &lbase_d, &wp, P.wsz, &stage_d, &bfptr_d, &raw_d);
+  P.bytes = sizer.off + 256;
+  return NLTE_OK;
+}
+
+extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* A,
+                                          const nlte_atom_desc* M, const nlte_grid_desc* G,
+                                          const double* C_up, int32_t prec_arg,
+                                          hipStream_t stream, nlte_column** out) {
+  if (!ctx || !out) return set_err(NLTE_E_INVALID, "NULL ctx/out");
+  // the setup checks its launches with hipGetLastError: start from a clear
+  // state so that an error left by an unrelated earlier call is not reported
+  // as this column's
+  (void)hipGetLastError();
+  ColumnPlan P;
+  const nlte_status ps = plan_column(A, M, G, C_up, prec_arg, P);
+  if (ps != NLTE_OK) return ps;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ColDev& C = P.C;
+  const int nz = C.nz, L = C.L, nline = C.nline, nbf = C.nbf, ntr = C.ntr, nnu = C.nnu;
+  const int prec = C.prec;
+  const std::vector<TrDev>& tr = P.tr;
+  const std::vector<int>& wbase = P.wbase;
+  const std::vector<int>& lbase = P.lbase;
+  const int nline_tab = P.nline_tab, nbf_tot = P.nbf_tot;
+  const int* wsz = P.wsz;
+  const std::vector<int>&ch_ptr = P.ch_ptr, &ch_tr = P.ch_tr, &ch_eptr = P.ch_eptr, &ch_ed = P.ch_ed;
+  const std::vector<RItem>& ritem = P.ritem;
+  const std::vector<PItem>& pitem = P.pitem;
+  const std::vector<int>&pg_ptr = P.pg_ptr, &pg_code = P.pg_code;
+  const std::vector<Tile>& tiles = P.tiles;
+  const std::vector<int4>& rate_w = P.rate_w;
+  const std::vector<int2>& prec_w = P.prec_w;
+  const std::vector<TileGroup>& groups = P.groups;
+  const int nrate0_w = P.nrate0_w;
   nlte_column* col = new nlte_column();
   col->ctx = ctx;
   col->device = ctx->device;
-  col->arena_bytes = sizer.off + 256;
+  col->arena_bytes = P.bytes;
   hipError_t he = hipMalloc(&col->arena, col->arena_bytes);
   if (he != hipSuccess) {
     delete col;
-    return set_err(NLTE_E_NOMEM, "hipMalloc(%zu) failed: %s", sizer.off, hipGetErrorString(he));
+    return set_err(NLTE_E_NOMEM, "hipMalloc(%zu) failed: %s", P.bytes, hipGetErrorString(he));
   }
+  SetupIn in{};
+  TrDev* tr_d;
+  int *wbase_d, *lbase_d, *stage_d, *bfptr_d;
+  WorkPtrs wp{};
+  double* raw_d;
   Layout lay(col->arena);
-  layout_column(lay, C, in, wbase[ntr], nline_tab, nbf_tot, nentries, nentries_e, m_cap, &tr_d, &wbase_d,
-                &lbase_d, &wp, wsz, &stage_d, &bfptr_d, &raw_d);
-  col->restart_cap = m_cap;
-  col->Blu = Blu;
+  layout_column(lay, C, in, wbase[ntr], nline_tab, nbf_tot, P.nentries, P.nentries_e, P.m_cap, &tr_d,
+                &wbase_d, &lbase_d, &wp, wsz, &stage_d, &bfptr_d, &raw_d);
+  col->restart_cap = P.m_cap;
+  col->Blu = P.Blu;
 
   // upload
   auto up = [&](const void* dst, const void* src, size_t bytes) -> hipError_t {
@@ -754,6 +836,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   double* rbn = ra + std::max(nline, 1);
   double* rba = rbn + std::max(nbf_tot, 1);
   double* rC = rba + std::max(nbf_tot, 1);
+  double* rW = rC + (size_t)nz * ntr;
   hipError_t e = hipSuccess;
 #define UP(d, s, b) if (e == hipSuccess) e = up(d, s, b)
   UP(C.z, A->z, nz * 8);
@@ -790,6 +873,8 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     UP(rba, M->bf_alpha, nbf_tot * 8);
   }
   UP(rC, C_up, (size_t)nz * ntr * 8);
+  if (G->w_nu) UP(rW, G->w_nu, (size_t)nnu * 8);
+  if (A->eta_c) UP(C.EC, A->eta_c, (size_t)nz * nnu * 8);
 #undef UP
   if (e == hipSuccess) e = hipMemsetAsync(C.st, 0, sizeof(ColState), stream);
   if (e != hipSuccess) {
@@ -798,6 +883,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     return set_err(NLTE_E_DEVICE, "upload failed: %s", hipGetErrorString(e));
   }
   in.E = rE; in.g = rg; in.A_ul = rA; in.a_damp = ra; in.bf_nu = rbn; in.bf_alpha = rba; in.C_up = rC;
+  in.w_nu = G->w_nu ? rW : nullptr;
   in.stage = stage_d; in.bf_ptr = bfptr_d; in.mass_amu = M->mass_amu; in.vturb = M->vturb;
 
   // setup kernels
@@ -845,8 +931,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   col->bw.any64 = prec == NLTE_FP64;
   col->bw.any32 = prec == NLTE_FP32_FORM;
   col->bw.any_newton = 1;
-  col->bw.ngroup = (int)groups.size();
-  for (int g = 0; g < col->bw.ngroup; ++g) col->bw.groups[g] = groups[g];
+  set_groups(col->bw, groups);  // one column: at most one group
   col->bw.maxnz = nz;
 
   *out = col;
@@ -859,6 +944,18 @@ extern "C" void nlte_column_destroy(nlte_column* col) {
   if (col->d) (void)hipFree(col->d);
   if (col->arena) (void)hipFree(col->arena);
   delete col;
+}
+
+extern "C" nlte_status nlte_column_plan_bytes(const nlte_atmos_desc* atmos,
+                                              const nlte_atom_desc* atom,
+                                              const nlte_grid_desc* grid, const double* C_up,
+                                              int32_t precision, size_t* bytes) {
+  if (!bytes) return set_err(NLTE_E_INVALID, "bytes is NULL");
+  ColumnPlan P;
+  const nlte_status st = plan_column(atmos, atom, grid, C_up, precision, P);
+  if (st != NLTE_OK) return st;
+  *bytes = P.bytes;
+  return NLTE_OK;
 }
 
 extern "C" nlte_status nlte_column_bytes(const nlte_column* col, size_t* bytes) {

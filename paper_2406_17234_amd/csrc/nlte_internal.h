@@ -101,7 +101,7 @@ struct ColState {
   int mode;         // EvalMode of the pending evaluation
   int want_J;       // write J of the evaluation to Jeval
   int rows_own;     // kModeF: 1 = rows from the evaluated n, 0 = rows_frozen
-  int pad_rows;
+  int jdag_fresh;   // J-dagger already refreshed at the current Newton point
   int phase;        // solver phase (see nlte_solver.hip)
   int status;       // nlte_status of the solve
   int newton_it, krylov_j, krylov_total, f_calls, stalls, ls_try, restarts, precond_calls;
@@ -122,7 +122,7 @@ struct ColState {
   int method;       // nlte_krylov of the solve
   int jv;           // nlte_jv of the solve
   int tan_pending;  // a tangent product (n in n, direction in eval_n) is pending
-  int pad_jv;
+  int krylov_x0;    // initial guess of the Krylov solves: 0 zero, 1 -P^-1 F (scaled: b)
   double bi_rho, bi_alpha;  // BiCGSTAB: (r^, r) and the step of the pending half
 };
 
@@ -160,6 +160,7 @@ struct ColDev {
                                    // derivatives, e^{-h nu/kT}): nz rounded up to a multiple
                                    // of 16, so that a wave's 64 depths start on a line boundary
   int nchunk, has_sca, N;          // N = nz * L
+  int bg_eta;                      // 1: the caller gave the background emissivity eta_c
   int npitem, nment;               // pair-sum blocks, entries of M
   int scan;                        // 1: depth-parallel formal solution (nz <= 256)
   int nrseg, nritem;               // rate-integral entries (partial sums) and blocks
@@ -172,6 +173,8 @@ struct ColDev {
   // frequency grid and per-(k, f) tables [nz][nnu]
   const double *nu, *gam;          // gam = 2 h nu^3 / c^2
   const double *Bnu, *Ebf;         // Planck function, exp(-h nu / kT)
+  const double *EC;                // thermal background emission table: Bnu (emissivity
+                                   // chi_c B_nu, bg_eta = 0) or the caller's eta_c (bg_eta = 1)
   const double *EbfT;              // [nnu][zp] exp(-h nu / kT), depth-contiguous
   // transitions
   const TrDev *tr;
@@ -185,6 +188,7 @@ struct ColDev {
   // FP32 copies of V, Bnu and Ebf read by the FP32-form opacity kernel (NULL
   // for FP64 columns); n-independent, so their rounding adds no noise to F
   const float *Vf, *Bnuf, *Ebff;
+  const float *ECf;                // FP32 copy of EC (rows of fp)
   const float *VTf, *EbfTf;        // FP32 copies of VT and EbfT (rate integrals; EbfTf [nnu][zp])
   // chunk -> overlapping line windows and edge windows; overlapping transition pairs
   const int *ch_lptr, *ch_line;
@@ -256,11 +260,15 @@ struct TileGroup {
   int scan;  // columns solved by the depth-parallel formal solution
 };
 
+// Tile groups a batch can have: one per (formal-solution variant, precision,
+// angle count).
+constexpr int kMaxGroups = 2 * 2 * kMaxMu;
+
 // Device work lists of a batch of columns.
 struct BatchWork {
   const ColDev* cols = nullptr;   // device array [ncol]
   const Tile* tiles = nullptr;    // formal-solution chunks, grouped by (precision, nmu)
-  TileGroup groups[2 * kMaxMu];
+  TileGroup groups[kMaxGroups];
   int ngroup = 0;
   int maxnz = 0;                  // deepest column of the batch
   int fallback = 0;               // FP32-form columns may run FP64 evaluations
@@ -296,11 +304,20 @@ hipError_t residual_streams_init();
 // Newton/Krylov step of every column, and a copy of the columns' states.
 nlte_status check_solve_opts(const nlte_solve_opts& o);
 hipError_t solver_init(const ColDev* cols, int ncol, const double* const* n0,
-                       const nlte_solve_opts& o, hipStream_t s);
+                       const double* const* J0, const nlte_solve_opts& o, hipStream_t s);
 hipError_t solver_step(const ColDev* cols, const int* act, int n, int* done, hipStream_t s);
 hipError_t solver_gather(const ColDev* cols, int ncol, ColState* out, hipStream_t s);
 bool state_done(const ColState& st);
 void state_stats(const ColState& st, nlte_solve_stats* out);
+
+// Copies the tile groups of build_work_lists into bw; false (bw untouched)
+// if there are more than kMaxGroups of them.
+inline bool set_groups(BatchWork& bw, const std::vector<TileGroup>& groups) {
+  if (groups.size() > (size_t)kMaxGroups) return false;
+  bw.ngroup = (int)groups.size();
+  for (int g = 0; g < bw.ngroup; ++g) bw.groups[g] = groups[g];
+  return true;
+}
 
 int build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
                      std::vector<TileGroup>& groups, std::vector<int4>& rate,

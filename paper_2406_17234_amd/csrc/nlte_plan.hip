@@ -175,8 +175,7 @@ extern "C" nlte_status nlte_plan_create(nlte_ctx* ctx, nlte_column* const* cols,
   bw.nrate0 = nrate0;
   bw.npb = (int)pb.size();
   bw.any_newton = 0;  // F only: no preconditioner work
-  bw.ngroup = (int)groups.size();
-  for (int g = 0; g < bw.ngroup; ++g) bw.groups[g] = groups[g];
+  if (!set_groups(bw, groups)) return fail(set_err(NLTE_E_INVALID, "too many tile groups"));
   int64_t dp = 0;
   for (int c = 0; c < ncol; ++c) {
     bw.maxnz = std::max(bw.maxnz, hc[c].nz);

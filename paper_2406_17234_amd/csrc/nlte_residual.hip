@@ -153,10 +153,12 @@ __device__ __forceinline__ void seg_coef(R x, R rb, R mu2, R& e, R& q, R& a, R& 
 // Per evaluation, k_coef turns the populations into two FP64 numbers per
 // transition and depth, stored transition-major ([ntr + 2][nz][2]):
 //   lines: c0 = n_l - g n_u, c1 = g n_u;   edges: c0 = n_l, c1 = (n*_l/n*_c) n_c;
-//   row ntr: chi_c + chi_sca, chi_c;       row ntr + 1: chi_sca, dz,
-// so that for every (k, nu), with E = exp(-h nu / kT),
+//   row ntr: chi_c + chi_sca, chi_c (1 when the caller gave eta_c);
+//   row ntr + 1: chi_sca, dz,
+// so that for every (k, nu), with E = exp(-h nu / kT) and EC the background
+// emission table (B_nu, or eta_c),
 //   chi = chi_c + chi_sca + sum_lines V c0 + sum_edges alpha (c0 - E c1)
-//   eta = chi_c B + chi_sca J' + (2 h nu^3/c^2) (sum_lines V c1 + E sum_edges alpha c1).
+//   eta = c1(ntr) EC + chi_sca J' + (2 h nu^3/c^2) (sum_lines V c1 + E sum_edges alpha c1).
 __global__ __launch_bounds__(256) void k_coef(const ColDev* __restrict__ cols,
                                               const int* __restrict__ act) {
   const ColDev& C = cols[act ? act[blockIdx.x] : blockIdx.x];
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(256) void k_coef(const ColDev* __restrict__ cols,
       c1 = C.rho_bf[k * C.nbf + (t - nline)] * nk[L - 1];
     } else if (t == ntr) {
       c0 = C.chi_c[k] + C.chi_sca[k];
-      c1 = C.chi_c[k];
+      c1 = C.bg_eta ? 1.0 : C.chi_c[k];
     } else {
       c0 = C.chi_sca[k];
       c1 = k + 1 < nz ? C.dz[k] : 0.0;
@@ -191,14 +193,14 @@ __global__ __launch_bounds__(256) void k_coef(const ColDev* __restrict__ cols,
 template <typename R> struct FTab;
 template <> struct FTab<double> {
   static __device__ __forceinline__ const double* V(const ColDev& C) { return C.V; }
-  static __device__ __forceinline__ const double* B(const ColDev& C) { return C.Bnu; }
+  static __device__ __forceinline__ const double* B(const ColDev& C) { return C.EC; }
   static __device__ __forceinline__ const double* E(const ColDev& C) { return C.Ebf; }
   static __device__ __forceinline__ double wm2(const ColDev& C, int m) { return C.wm2[m]; }
   static __device__ __forceinline__ double i2mu(const ColDev& C, int m) { return C.inv2mu[m]; }
 };
 template <> struct FTab<float> {
   static __device__ __forceinline__ const float* V(const ColDev& C) { return C.Vf; }
-  static __device__ __forceinline__ const float* B(const ColDev& C) { return C.Bnuf; }
+  static __device__ __forceinline__ const float* B(const ColDev& C) { return C.ECf; }
   static __device__ __forceinline__ const float* E(const ColDev& C) { return C.Ebff; }
   static __device__ __forceinline__ float wm2(const ColDev& C, int m) { return C.wm2f[m]; }
   static __device__ __forceinline__ float i2mu(const ColDev& C, int m) { return C.inv2muf[m]; }

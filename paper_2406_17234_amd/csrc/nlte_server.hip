@@ -152,8 +152,7 @@ hipError_t nlte_server::rebuild() {
   bw.npb = (int)pb.size();
   bw.any_newton = 1;
   bw.any_tangent = opts.jv_method == NLTE_JV_TANGENT;
-  bw.ngroup = (int)groups.size();
-  for (int g = 0; g < bw.ngroup; ++g) bw.groups[g] = groups[g];
+  if (!set_groups(bw, groups)) return hipErrorInvalidValue;
   for (int c = 0; c < n; ++c) {
     bw.maxnz = std::max(bw.maxnz, hc[c].nz);
     if (hc[c].prec == NLTE_FP64) bw.any64 = 1; else bw.any32 = 1;
@@ -173,7 +172,7 @@ hipError_t nlte_server::admit(std::vector<Request*>& adm) {
   if ((e = d_n0.fit(na)) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(d_n0.p, n0.data(), na * sizeof(const double*), hipMemcpyHostToDevice, stream)) != hipSuccess) return e;
   const int first = (int)active.size() - na;
-  return solver_init(d_cols.p + first, na, d_n0.p, opts, stream);
+  return solver_init(d_cols.p + first, na, d_n0.p, nullptr, opts, stream);
 }
 
 void nlte_server::run() {

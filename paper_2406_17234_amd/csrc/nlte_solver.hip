@@ -53,7 +53,8 @@ constexpr double kFallbackKeepRho = 1e-2;
 enum Phase : int {
   PH_IDLE = 0, PH_INIT = 1, PH_ARNOLDI = 2, PH_RESTART = 3, PH_LS = 4, PH_DONE = 5,
   PH_BICG_V = 6,  // BiCGSTAB: the product A p is pending
-  PH_BICG_T = 7   // BiCGSTAB: the product A s is pending
+  PH_BICG_T = 7,  // BiCGSTAB: the product A s is pending
+  PH_X0 = 8       // the product A x0 of a nonzero initial guess is pending
 };
 
 // ----------------------------------------------------------------- block ops
@@ -348,7 +349,10 @@ __device__ void pending_product(const ColDev& C, double* w) {
   apply_scaled_pinv(C, w, w);
 }
 
-__device__ void bicg_start(const ColDev& C, double* red, int* done_count) {
+// first: the Krylov solve starts here from x0 = 0, so ||r0|| = ||b|| is the
+// reference of its tolerance and of the line search; otherwise (nonzero x0)
+// that reference was set when b was formed.
+__device__ void bicg_start(const ColDev& C, bool first, double* red, int* done_count) {
   ColState* st = C.st;
   const int N = C.N;
   double* rh = C.Vk;
@@ -370,8 +374,10 @@ __device__ void bicg_start(const ColDev& C, double* red, int* done_count) {
     return;
   }
   if (threadIdx.x == 0) {
-    st->beta0 = beta;
-    st->phi0 = beta;
+    if (first) {
+      st->beta0 = beta;
+      st->phi0 = beta;
+    }
     st->bi_rho = bb;  // (r^, r0) with r^ = r0
     st->phase = PH_BICG_V;
   }
@@ -488,9 +494,35 @@ __device__ void bicg_t(const ColDev& C, double* red, int* done_count) {
 // rate rows they replace were saved by the assembly, so this needs no new
 // formal solution), then the preconditioner blocks are factored and a GMRES
 // cycle starts on b = -D^-1 P^-1 F.
+//
+// Lagged scattering (Sect. 2.1.1, Algorithm 2 "update J"): at a newly
+// accepted point of a column with background scattering, J-dagger first
+// becomes the J of the evaluation just made, and F is evaluated again at the
+// same point with it; the Newton step then starts from that second
+// evaluation, so that F(n), its products and its line search share one
+// J-dagger (the difference of Eq. fordif would otherwise pick up the change
+// of J-dagger between its two terms).  The first evaluation of a solve (and
+// of an FP64 fallback) keeps the J-dagger it was given.
 __device__ void accept_point(const ColDev& C, double* red, int* done_count) {
   ColState* st = C.st;
   const int N = C.N, L = C.L;
+  const bool refresh = C.has_sca && !st->jdag_fresh;
+  __syncthreads();  // every thread has read the state before thread 0 changes it
+  if (refresh) {
+    for (int i = threadIdx.x; i < C.nz * C.nnu; i += kThreads) {
+      const int k = i / C.nnu, f = i - k * C.nnu;
+      C.Jdag[i] = C.JT[(size_t)f * C.zp + k];
+    }
+    if (threadIdx.x == 0) {
+      st->jdag_fresh = 1;
+      st->phase = PH_INIT;
+      st->mode = kModeNewton;
+      st->rows_own = 1;
+      st->want_J = 1;
+    }
+    return;
+  }
+  if (threadIdx.x == 0) st->jdag_fresh = 0;
   double rk = 0.0;
   for (int k = threadIdx.x; k < C.nz; k += kThreads) {
     const double* nk = C.eval_n + k * L;
@@ -525,11 +557,6 @@ __device__ void accept_point(const ColDev& C, double* red, int* done_count) {
     C.n[i] = C.eval_n[i];
     C.Fn[i] = C.F[i];
   }
-  if (C.has_sca)
-    for (int i = threadIdx.x; i < C.nz * C.nnu; i += kThreads) {
-      const int k = i / C.nnu, f = i - k * C.nnu;
-      C.Jdag[i] = C.JT[(size_t)f * C.zp + k];
-    }
   __syncthreads();
   if (threadIdx.x == 0) st->rho_cur = rho;
   if (rho != rho || isinf(rho)) {
@@ -555,6 +582,7 @@ __device__ void accept_point(const ColDev& C, double* red, int* done_count) {
         for (int i = threadIdx.x; i < C.nz * C.nnu; i += kThreads) C.Jdag[i] = C.Bnu[i];
     }
     if (threadIdx.x == 0) {
+      st->jdag_fresh = 1;  // the fallback's first evaluation keeps its J-dagger
       st->cur_prec = NLTE_FP64;
       st->eps_mach = kEpsMach64;
       st->krylov_total = 0;
@@ -584,19 +612,59 @@ __device__ void accept_point(const ColDev& C, double* red, int* done_count) {
   }
   // b = -D^-1 P^-1 F(n) -> Vk[0]
   apply_scaled_pinv(C, C.Fn, C.Vk);
+  const bool x0 = st->krylov_x0 != 0;
+  double bb = 0.0;
   for (int i = threadIdx.x; i < N; i += kThreads) {
-    C.Vk[i] = -C.Vk[i];
-    C.xk[i] = 0.0;
+    const double b = -C.Vk[i];
+    C.Vk[i] = b;
+    C.xk[i] = x0 ? b : 0.0;  // x0 = -P^-1 F in the unscaled unknowns is b here
+    bb += b * b;
   }
   if (threadIdx.x == 0) {
     st->restarts = 0;
     st->krylov_step = 0;
   }
+  if (x0) {
+    // the Krylov solve starts from r0 = b - A x0: evaluate A x0 first
+    const double bn = sqrt(block_sum1(bb, red));
+    if (!(bn > 0.0) || bn != bn) {
+      if (bn != bn) finish(C, NLTE_E_NONFINITE, done_count);
+      else finish(C, NLTE_OK, done_count);
+      return;
+    }
+    if (threadIdx.x == 0) {
+      st->beta0 = bn;
+      st->phi0 = bn;
+      st->phase = PH_X0;
+    }
+    prepare_jv(C, C.xk, bn);
+    return;
+  }
   __syncthreads();
   if (st->method == NLTE_KRYLOV_BICGSTAB)
-    bicg_start(C, red, done_count);
+    bicg_start(C, true, red, done_count);
   else
     start_cycle(C, true, red, done_count);
+}
+
+// A x0 has been evaluated: r0 = b - A x0 replaces b in Vk[0] and the Krylov
+// solve starts from x = x0 (its tolerance and the line search still refer to
+// ||b||, set when b was formed).
+__device__ void x0_product(const ColDev& C, double* red, int* done_count) {
+  ColState* st = C.st;
+  double* w = C.w;
+  pending_product(C, w);
+  for (int i = threadIdx.x; i < C.N; i += kThreads) C.Vk[i] -= w[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->krylov_total += 1;
+    st->krylov_step += 1;
+  }
+  __syncthreads();
+  if (st->method == NLTE_KRYLOV_BICGSTAB)
+    bicg_start(C, false, red, done_count);
+  else
+    start_cycle(C, false, red, done_count);
 }
 
 __device__ void arnoldi(const ColDev& C, double* red, int* done_count) {
@@ -786,6 +854,7 @@ __global__ __launch_bounds__(kThreads) void k_solver_step(const ColDev* __restri
     case PH_LS: linesearch(C, red, done_count); break;
     case PH_BICG_V: bicg_v(C, red, done_count); break;
     case PH_BICG_T: bicg_t(C, red, done_count); break;
+    case PH_X0: x0_product(C, red, done_count); break;
     default: break;
   }
 }
@@ -794,9 +863,11 @@ __global__ __launch_bounds__(kThreads) void k_solver_step(const ColDev* __restri
 struct InitArgs {
   double ftol, rtol, eps_mach, eps_scale;
   int maxiter, max_krylov, restart, max_halvings, init, max_krylov_total, fp64_fallback, method, jv;
+  int x0;
 };
 
-__global__ void k_solver_init(const ColDev* __restrict__ cols, const double* const* n0, InitArgs a) {
+__global__ void k_solver_init(const ColDev* __restrict__ cols, const double* const* n0,
+                              const double* const* J0, InitArgs a) {
   const ColDev& C = cols[blockIdx.x];
   ColState* st = C.st;
   const double* src = n0 ? n0[blockIdx.x] : nullptr;
@@ -805,7 +876,9 @@ __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* con
     C.eval_n[i] = v;
     C.n_init[i] = v;
   }
-  for (int i = threadIdx.x; i < C.nz * C.nnu; i += blockDim.x) C.Jdag[i] = C.Bnu[i];
+  const double* jsrc = J0 ? J0[blockIdx.x] : nullptr;
+  const double* jin = jsrc ? jsrc : C.Bnu;
+  for (int i = threadIdx.x; i < C.nz * C.nnu; i += blockDim.x) C.Jdag[i] = jin[i];
   if (threadIdx.x == 0) {
     st->phase = PH_INIT;
     st->status = NLTE_E_NOCONV;
@@ -831,6 +904,7 @@ __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* con
     st->fp64_fallback = a.fp64_fallback;
     st->method = a.method;
     st->jv = a.jv;
+    st->krylov_x0 = a.x0;
     st->tan_pending = 0;
     st->fp64_evals = 0;
     st->restart = a.restart;
@@ -838,6 +912,7 @@ __global__ void k_solver_init(const ColDev* __restrict__ cols, const double* con
     st->mode = kModeNewton;
     st->rows_own = 1;
     st->want_J = 1;
+    st->jdag_fresh = 1;  // F(n0) uses the J-dagger the solve starts with
   }
 }
 
@@ -935,18 +1010,19 @@ nlte_status check_solve_opts(const nlte_solve_opts& o) {
   if (o.restart < 1 || o.restart > kMaxM) return set_err(NLTE_E_INVALID, "restart must be 1..%d", kMaxM);
   if (o.maxiter < 0 || o.max_krylov < 1 || o.max_krylov_total < 0 || o.max_halvings < 0 ||
       !(o.ftol >= 0) || !(o.rtol > 0) || !(o.eps_scale > 0) || o.init < 0 || o.init > 2 ||
+      o.krylov_x0 < 0 || o.krylov_x0 > 1 ||
       (o.krylov_method != NLTE_KRYLOV_GMRES && o.krylov_method != NLTE_KRYLOV_BICGSTAB) ||
       (o.jv_method != NLTE_JV_FD && o.jv_method != NLTE_JV_TANGENT))
     return set_err(NLTE_E_INVALID, "invalid solve options");
   return NLTE_OK;
 }
 
-hipError_t solver_init(const ColDev* cols, int ncol, const double* const* n0, const nlte_solve_opts& o,
-                       hipStream_t s) {
+hipError_t solver_init(const ColDev* cols, int ncol, const double* const* n0, const double* const* J0,
+                       const nlte_solve_opts& o, hipStream_t s) {
   InitArgs ia{o.ftol, o.rtol, 2.220446049250313e-16, o.eps_scale, o.maxiter, o.max_krylov,
               o.restart, o.max_halvings, 0, o.max_krylov_total, o.fp64_fallback, o.krylov_method,
-              o.jv_method};
-  k_solver_init<<<ncol, kThreads, 0, s>>>(cols, n0, ia);
+              o.jv_method, o.krylov_x0};
+  k_solver_init<<<ncol, kThreads, 0, s>>>(cols, n0, J0, ia);
   return hipGetLastError();
 }
 
@@ -984,6 +1060,7 @@ struct Batch {
   int4* rate = nullptr;
   int2* prec = nullptr;
   double** n0 = nullptr;
+  double** J0 = nullptr;
   double** nout = nullptr;
   int* act = nullptr;
   ColState* states = nullptr;
@@ -996,6 +1073,7 @@ struct Batch {
     if (rate) hipFree(rate);
     if (prec) hipFree(prec);
     if (n0) hipFree(n0);
+    if (J0) hipFree(J0);
     if (nout) hipFree(nout);
     if (act) hipFree(act);
     if (states) hipFree(states);
@@ -1006,9 +1084,9 @@ struct Batch {
 }  // namespace
 
 extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols, int32_t ncol,
-                                        const double* const* n0_dev, const nlte_solve_opts* opts,
-                                        double* const* n_out_dev, nlte_solve_stats* stats,
-                                        hipStream_t s) {
+                                        const double* const* n0_dev, const double* const* J0_dev,
+                                        const nlte_solve_opts* opts, double* const* n_out_dev,
+                                        nlte_solve_stats* stats, hipStream_t s) {
   if (!ctx || !cols || ncol <= 0 || !n_out_dev) return set_err(NLTE_E_INVALID, "bad arguments");
   nlte_solve_opts o;
   nlte_solve_opts_default(&o);
@@ -1057,8 +1135,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   bw.any32 = b.any32;
   bw.any_newton = 1;
   bw.any_tangent = o.jv_method == NLTE_JV_TANGENT;
-  bw.ngroup = (int)groups.size();
-  for (int g = 0; g < bw.ngroup; ++g) bw.groups[g] = groups[g];
+  if (!set_groups(bw, groups)) return set_err(NLTE_E_INVALID, "too many tile groups");
   for (int c = 0; c < ncol; ++c) bw.maxnz = std::max(bw.maxnz, hc[c].nz);
   bw.fallback = o.fp64_fallback > 0 && b.any32;
 
@@ -1072,11 +1149,15 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
     HIP_TRY(hipMalloc(&b.n0, ncol * sizeof(double*)));
     HIP_TRY(hipMemcpyAsync(b.n0, n0_dev, ncol * sizeof(double*), hipMemcpyHostToDevice, s));
   }
+  if (J0_dev) {
+    HIP_TRY(hipMalloc(&b.J0, ncol * sizeof(double*)));
+    HIP_TRY(hipMemcpyAsync(b.J0, J0_dev, ncol * sizeof(double*), hipMemcpyHostToDevice, s));
+  }
   HIP_TRY(hipMemsetAsync(b.done, 0, sizeof(int), s));
   InitArgs ia{o.ftol, o.rtol, 2.220446049250313e-16, o.eps_scale, o.maxiter, o.max_krylov,
               o.restart, o.max_halvings, o.init, o.max_krylov_total, o.fp64_fallback, o.krylov_method,
-              o.jv_method};
-  k_solver_init<<<ncol, 256, 0, s>>>(b.cols, o.init == 0 ? b.n0 : nullptr, ia);
+              o.jv_method, o.krylov_x0};
+  k_solver_init<<<ncol, 256, 0, s>>>(b.cols, o.init == 0 ? b.n0 : nullptr, b.J0, ia);
   if (o.init == 2) {
     for (int c = 0; c < ncol; ++c)
       k_zero_radiation<<<(hc[c].nz + 63) / 64, 64, 0, s>>>(column_dev_ptr(cols[c]), hc[c].eval_n);
@@ -1157,8 +1238,7 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
       bw.nrate = (int)rate_w.size();
       bw.nrate0 = nrate0_l;
       bw.npb = (int)prec_w.size();
-      bw.ngroup = (int)groups.size();
-      for (int g = 0; g < bw.ngroup; ++g) bw.groups[g] = groups[g];
+      set_groups(bw, groups);  // a subset of the groups checked above
       bw.maxnz = 0;
       for (int c : live) bw.maxnz = std::max(bw.maxnz, hc[c].nz);
       bw.act = b.act;
@@ -1192,18 +1272,25 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   return NLTE_OK;
 }
 
-extern "C" nlte_status nlte_solve(nlte_column* col, const double* n0_dev, const nlte_solve_opts* opts,
-                                  double* n_out_dev, double* J_out_dev, nlte_solve_stats* stats,
-                                  hipStream_t s) {
+extern "C" nlte_status nlte_solve(nlte_column* col, const double* n0_dev, const double* J0_dev,
+                                  const nlte_solve_opts* opts, double* n_out_dev, double* J_out_dev,
+                                  nlte_solve_stats* stats, hipStream_t s) {
   if (!col || !n_out_dev) return set_err(NLTE_E_INVALID, "NULL argument");
   nlte_column* cols[1] = {col};
   const double* n0s[1] = {n0_dev};
+  const double* J0s[1] = {J0_dev};
   double* outs[1] = {n_out_dev};
-  nlte_status st = nlte_solve_batch(column_ctx(col), cols, 1, n0_dev ? n0s : nullptr, opts, outs,
-                                    stats, s);
+  nlte_status st = nlte_solve_batch(column_ctx(col), cols, 1, n0_dev ? n0s : nullptr,
+                                    J0_dev ? J0s : nullptr, opts, outs, stats, s);
   if (J_out_dev && (st == NLTE_OK || st == NLTE_E_NOCONV)) {
+    // the J-dagger of the final residual: with background scattering the
+    // column's lagged J, otherwise (F does not depend on it) the final J
     const ColDev& C = column_dev(col);
-    transpose_J(C, J_out_dev, s);
+    if (C.has_sca)
+      HIP_TRY(hipMemcpyAsync(J_out_dev, C.Jdag, (size_t)C.nz * C.nnu * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    else
+      transpose_J(C, J_out_dev, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
   }

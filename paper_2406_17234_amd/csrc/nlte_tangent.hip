@@ -112,7 +112,7 @@ __device__ __forceinline__ void tan_opacity(const ColDev& C, int chunk, int k, i
   const size_t kf = (size_t)k * nnu + f;
   const double E = nbf ? C.Ebf[kf] : 0.0;
   X = (C.chi_c[k] + C.chi_sca[k]) + chi + (A1 - E * A2);
-  double eta = C.chi_c[k] * C.Bnu[kf] + gam * (et + E * A2);
+  double eta = (C.bg_eta ? 1.0 : C.chi_c[k]) * C.EC[kf] + gam * (et + E * A2);
   if (C.has_sca) eta += C.chi_sca[k] * C.Jdag[kf];
   Xd = chid + (A1d - E * A2d);
   const double etad = gam * (etd + E * A2d);

@@ -37,7 +37,7 @@ class NLTEError(RuntimeError):
 
 class AtmosDesc(C.Structure):
     _fields_ = [("nz", C.c_int32), ("z", _dp), ("T", _dp), ("ne", _dp), ("ntot", _dp),
-                ("chi_c", _dp), ("chi_sca", _dp)]
+                ("chi_c", _dp), ("chi_sca", _dp), ("eta_c", _dp)]
 
 
 class AtomDesc(C.Structure):
@@ -50,7 +50,7 @@ class AtomDesc(C.Structure):
 
 class GridDesc(C.Structure):
     _fields_ = [("nnu", C.c_int32), ("nu", _dp), ("win_lo", _ip), ("win_hi", _ip),
-                ("nmu", C.c_int32), ("mu", _dp), ("w_mu", _dp)]
+                ("nmu", C.c_int32), ("mu", _dp), ("w_mu", _dp), ("w_nu", _dp)]
 
 
 class SolveOpts(C.Structure):
@@ -59,7 +59,7 @@ class SolveOpts(C.Structure):
                 ("max_halvings", C.c_int32), ("init", C.c_int32), ("eps_scale", C.c_double),
                 ("max_krylov_total", C.c_int32), ("fp64_fallback", C.c_int32),
                 ("krylov_method", C.c_int32),
-                ("jv_method", C.c_int32)]
+                ("jv_method", C.c_int32), ("krylov_x0", C.c_int32), ("pad_opts", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -139,13 +139,17 @@ def lib():
         L.nlte_column_destroy.restype = None
         L.nlte_column_dims.argtypes = [vp, _ip]
         L.nlte_column_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.nlte_column_plan_bytes.argtypes = [C.POINTER(AtmosDesc), C.POINTER(AtomDesc),
+                                             C.POINTER(GridDesc), _dp, C.c_int,
+                                             C.POINTER(C.c_size_t)]
         L.nlte_lte_populations.argtypes = [vp, vp, vp]
         L.nlte_zero_radiation_populations.argtypes = [vp, vp, vp]
         L.nlte_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
         L.nlte_jvp.argtypes = [vp, vp, vp, C.c_double, vp, vp]
         L.nlte_jvp_tangent.argtypes = [vp, vp, vp, vp, vp]
-        L.nlte_solve.argtypes = [vp, vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveStats), vp]
-        L.nlte_solve_batch.argtypes = [vp, C.POINTER(vp), C.c_int32, C.POINTER(vp),
+        L.nlte_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveStats),
+                                 vp]
+        L.nlte_solve_batch.argtypes = [vp, C.POINTER(vp), C.c_int32, C.POINTER(vp), C.POINTER(vp),
                                        C.POINTER(SolveOpts), C.POINTER(vp),
                                        C.POINTER(SolveStats), vp]
         L.nlte_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
@@ -241,6 +245,51 @@ class Context:
             pass
 
 
+def _descriptors(problem):
+    """Descriptor structs of a problem (any object with ``atom``, ``atmos``,
+    ``grid`` and ``C_up`` shaped like the synthetic generator's ``Problem``)
+    and the arrays they point into (keep them alive while the structs are
+    used)."""
+    a, m, g = problem.atmos, problem.atom, problem.grid
+    keep = []
+
+    def D(x):
+        arr, p = _d(x)
+        keep.append(arr)
+        return p
+
+    def I(x):
+        arr, p = _i(x)
+        keep.append(arr)
+        return p
+
+    eta_c = getattr(a, "eta_c", None)
+    atm = AtmosDesc(len(a.z), D(a.z), D(a.T), D(a.ne), D(a.ntot), D(a.chi_c),
+                    D(a.chi_sca) if a.chi_sca is not None else None,
+                    D(eta_c) if eta_c is not None else None)
+    bf_ptr = np.concatenate([[0], np.cumsum([len(x) for x in g.bf_nu])]).astype(np.int32)
+    bf_nu = np.concatenate(g.bf_nu) if len(g.bf_nu) else np.zeros(1)
+    bf_al = np.concatenate(g.bf_alpha) if len(g.bf_alpha) else np.zeros(1)
+    atom = AtomDesc(m.nlev, D(m.E), D(m.g), I(m.stage), m.nline, I(m.line_lo), I(m.line_up),
+                    D(m.A_ul), D(m.a_damp), float(m.mass_amu), float(m.vturb), m.nbf,
+                    I(m.bf_lo), I(bf_ptr), D(bf_nu), D(bf_al))
+    w_nu = getattr(g, "w_nu", None)
+    grid = GridDesc(len(g.nu), D(g.nu), I(g.win_lo), I(g.win_hi), len(g.mu), D(g.mu), D(g.w_mu),
+                    D(w_nu) if w_nu is not None else None)
+    cup = D(np.ascontiguousarray(problem.C_up))
+    return atm, atom, grid, cup, keep
+
+
+def plan_bytes(problem, precision: int = FP64) -> int:
+    """Device bytes a column of this problem would own (host-only validation
+    and sizing, nlte_column_plan_bytes); raises NLTEError on bad input."""
+    atm, atom, grid, cup, keep = _descriptors(problem)
+    nb = C.c_size_t()
+    _check(lib().nlte_column_plan_bytes(C.byref(atm), C.byref(atom), C.byref(grid), cup,
+                                        int(precision), C.byref(nb)))
+    return nb.value
+
+
 class Column:
     """One column: model atmosphere + model atom + grids (+ collision rates).
 
@@ -251,33 +300,11 @@ class Column:
     def __init__(self, ctx: Context, problem, precision: int = FP64, stream=None):
         import torch
         self.ctx = ctx
-        a, m, g = problem.atmos, problem.atom, problem.grid
-        keep = []
-
-        def D(x):
-            arr, p = _d(x)
-            keep.append(arr)
-            return p
-
-        def I(x):
-            arr, p = _i(x)
-            keep.append(arr)
-            return p
-
-        atm = AtmosDesc(len(a.z), D(a.z), D(a.T), D(a.ne), D(a.ntot), D(a.chi_c),
-                        D(a.chi_sca) if a.chi_sca is not None else None)
-        bf_ptr = np.concatenate([[0], np.cumsum([len(x) for x in g.bf_nu])]).astype(np.int32)
-        bf_nu = np.concatenate(g.bf_nu) if len(g.bf_nu) else np.zeros(1)
-        bf_al = np.concatenate(g.bf_alpha) if len(g.bf_alpha) else np.zeros(1)
-        atom = AtomDesc(m.nlev, D(m.E), D(m.g), I(m.stage), m.nline, I(m.line_lo), I(m.line_up),
-                        D(m.A_ul), D(m.a_damp), float(m.mass_amu), float(m.vturb), m.nbf,
-                        I(m.bf_lo), I(bf_ptr), D(bf_nu), D(bf_al))
-        grid = GridDesc(len(g.nu), D(g.nu), I(g.win_lo), I(g.win_hi), len(g.mu), D(g.mu), D(g.w_mu))
+        atm, atom, grid, cup, keep = _descriptors(problem)
         h = C.c_void_p()
         torch.cuda.set_device(ctx.device)
         _check(lib().nlte_column_create(ctx.h, C.byref(atm), C.byref(atom), C.byref(grid),
-                                        D(np.ascontiguousarray(problem.C_up)), int(precision),
-                                        _stream(stream), C.byref(h)))
+                                        cup, int(precision), _stream(stream), C.byref(h)))
         self.h = h
         dims = (C.c_int32 * 8)()
         _check(lib().nlte_column_dims(h, dims))
@@ -343,21 +370,24 @@ class Column:
                                       _ptr(out), _stream(stream)))
         return out
 
-    def solve(self, n0=None, opts: SolveOpts | None = None, want_J=False, stream=None, **kw):
+    def solve(self, n0=None, opts: SolveOpts | None = None, want_J=False, J0=None, stream=None,
+              **kw):
         if opts is None:
             opts = default_opts(**kw)
         n = self._empty(self.nz, self.nlev)
         J = self._empty(self.nz, self.nnu) if want_J else None
         st = SolveStats()
-        rc = lib().nlte_solve(self.h, _ptr(n0), C.byref(opts), _ptr(n), _ptr(J), C.byref(st),
-                              _stream(stream))
+        rc = lib().nlte_solve(self.h, _ptr(n0), _ptr(None if J0 is None else J0.contiguous()),
+                              C.byref(opts), _ptr(n), _ptr(J), C.byref(st), _stream(stream))
         if rc not in (NLTE_OK, NLTE_E_NOCONV):
             _check(rc)
         return n, J, st.as_dict(), rc
 
 
-def solve_batch(ctx: Context, columns, opts: SolveOpts | None = None, n0=None, stream=None, **kw):
-    """Solve many columns in shared launches; returns (list of n, stats list, status)."""
+def solve_batch(ctx: Context, columns, opts: SolveOpts | None = None, n0=None, J0=None,
+                stream=None, **kw):
+    """Solve many columns in shared launches; returns (list of n, stats list, status).
+    n0, J0: optional lists of device tensors (entries of J0 may be None)."""
     import torch
     if opts is None:
         opts = default_opts(**kw)
@@ -368,8 +398,12 @@ def solve_batch(ctx: Context, columns, opts: SolveOpts | None = None, n0=None, s
     n0p = None
     if n0 is not None:
         n0p = (C.c_void_p * nc)(*[x.data_ptr() for x in n0])
+    J0p = None
+    if J0 is not None:
+        J0p = (C.c_void_p * nc)(*[0 if x is None else x.data_ptr() for x in J0])
     stats = (SolveStats * nc)()
-    rc = lib().nlte_solve_batch(ctx.h, cols, nc, n0p, C.byref(opts), outp, stats, _stream(stream))
+    rc = lib().nlte_solve_batch(ctx.h, cols, nc, n0p, J0p, C.byref(opts), outp, stats,
+                                _stream(stream))
     if rc not in (NLTE_OK, NLTE_E_NOCONV):
         _check(rc)
     return outs, [s.as_dict() for s in stats], rc

@@ -97,6 +97,7 @@ class Atmos:
     ntot: np.ndarray     # [nz] cm^-3, total density of the active atom
     chi_c: np.ndarray    # [nz] gray background opacity, cm^-1
     chi_sca: np.ndarray  # [nz] background scattering opacity, cm^-1 (zeros = none)
+    eta_c: np.ndarray | None = None  # [nz, nnu] thermal background emissivity (None: chi_c B_nu)
 
     @property
     def nz(self):
@@ -112,6 +113,7 @@ class Grid:
     w_mu: np.ndarray     # [nmu] weights, sum = 1
     bf_nu: list = field(default_factory=list)     # per edge: its own tabulation grid
     bf_alpha: list = field(default_factory=list)  # per edge: cross-section on bf_nu
+    w_nu: np.ndarray | None = None  # [nnu] frequency weights (None: trapezoid per window)
 
     @property
     def nnu(self):

@@ -120,7 +120,7 @@ def test_sizes_beyond_limits_rejected(ctx):
     L = nlte.lib()
     opts = nlte.default_opts()
     stats = (nlte.SolveStats * 1)()
-    rc = L.nlte_solve_batch(ctx.h, None, 0, None, ctypes.byref(opts), None, stats, None)
+    rc = L.nlte_solve_batch(ctx.h, None, 0, None, None, ctypes.byref(opts), None, stats, None)
     assert rc == nlte.NLTE_E_INVALID
 
 

@@ -166,6 +166,64 @@ def test_spontaneous_rate_equals_einstein_A():
         assert np.max(np.abs(R_ul[:, t] / p.atom.A_ul[t] - 1)) < 1e-5
 
 
+def _einstein_B_lu(atom, t):
+    """Einstein relations (textbook): B_ul = A_ul c^2 / (2 h nu0^3),
+    g_l B_lu = g_u B_ul."""
+    lo, up = atom.line_lo[t], atom.line_up[t]
+    nu0 = (atom.E[up] - atom.E[lo]) / O.HP
+    return atom.g[up] / atom.g[lo] * atom.A_ul[t] * O.CL ** 2 / (2 * O.HP * nu0 ** 3), nu0
+
+
+@pytest.mark.parametrize("maker", [S.chromo6, S.chromo11])
+def test_mean_line_intensity_of_a_flat_field(maker):
+    """Profile-averaged line intensity Jbar_t = sum_f w_f phi_t J (the
+    absorption-profile average behind Eq. Rij): a field that does not vary
+    with frequency is returned unchanged at every depth, because each profile
+    is normalised on its own window with the same weights."""
+    tb = O.setup(maker())
+    c = np.geomspace(1e-3, 1e3, tb.nz)[:, None]
+    Jb = O.mean_line_intensity(tb, c * np.ones((1, tb.nnu)))
+    assert Jb.shape == (tb.nz, tb.nline)
+    assert np.max(np.abs(Jb / c - 1)) < 1e-14
+
+
+def test_upward_line_rate_is_B_lu_times_mean_line_intensity():
+    """Eq. Rij with V_ij = (h nu / 4 pi) B_lu phi (Sect. 2.1.1) and the 4 pi of
+    the solid angle: R_lu = B_lu Jbar_t for any radiation field, with B_lu
+    from the Einstein relations."""
+    p = S.chromo6()
+    tb = O.setup(p)
+    rng = np.random.default_rng(4)
+    J = tb.B * np.exp(rng.standard_normal(tb.B.shape))
+    R_lu, _ = O.rates_from_J(tb, J)
+    Jb = O.mean_line_intensity(tb, J)
+    for t in range(tb.nline):
+        Blu, _ = _einstein_B_lu(p.atom, t)
+        assert np.max(np.abs(R_lu[:, t] / (Blu * Jb[:, t]) - 1)) < 1e-13, t
+
+
+@pytest.mark.parametrize("maker", [S.slab3, S.chromo6])
+def test_mean_line_intensity_in_a_planck_field(maker):
+    """In the field J = B_nu(T) the profile average is a weighted mean (weights
+    w phi >= 0 summing to 1) of B_nu over the line window, so it lies between
+    the window's extreme values of B_nu, and close to B_nu0: the window spans
+    50 Doppler widths, so |Jbar/B_nu0 - 1| is of order
+    50 (1 + h nu0/kT) dnu_D/nu0."""
+    p = maker()
+    tb = O.setup(p)
+    Jb = O.mean_line_intensity(tb, tb.B)
+    T = p.atmos.T
+    for tr in tb.tr[:tb.nline]:
+        Bw = tb.B[:, tr.f0:tr.f1]
+        assert np.all(Jb[:, tr.t] >= Bw.min(axis=1) * (1 - 1e-14))
+        assert np.all(Jb[:, tr.t] <= Bw.max(axis=1) * (1 + 1e-14))
+        _, nu0 = _einstein_B_lu(p.atom, tr.t)
+        x = O.HP * nu0 / (O.KB * T)
+        dnuD = nu0 / O.CL * np.sqrt(2 * O.KB * T / (p.atom.mass_amu * O.AMU_G))
+        bound = 50 * (1 + x) * dnuD / nu0
+        assert np.all(np.abs(Jb[:, tr.t] / O.planck(nu0, T) - 1) < bound), tr.t
+
+
 @pytest.mark.parametrize("maker", [S.slab3, S.chromo6])
 def test_detailed_balance_at_planck_field(maker):
     """With I = B_nu(T) everywhere and n = n*, every transition is in detailed
@@ -331,6 +389,35 @@ def test_bicgstab_solves_small_system():
     assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-9, atol=1e-11)
 
 
+@pytest.mark.parametrize("method", ["gmres", "bicgstab"])
+def test_krylov_from_a_nonzero_initial_guess(method):
+    """Both inner solvers started from a nonzero x0 (Algorithm 2's second
+    initial guess) against a direct solve; the start costs one product (GMRES
+    does not count the products of its restarts), and from the exact
+    solution the first iteration already meets the tolerance."""
+    rng = np.random.default_rng(6)
+    A = np.eye(40) + 0.3 * rng.standard_normal((40, 40)) / np.sqrt(40)
+    b = rng.standard_normal(40)
+    xs = np.linalg.solve(A, b)
+    x0 = xs + 0.1 * rng.standard_normal(40)
+    calls = []
+
+    def mv(v):
+        calls.append(1)
+        return A @ v
+    if method == "gmres":
+        x, k, rel = O.gmres(mv, b, rtol=1e-12, m=10, maxit=400, x0=x0)
+    else:
+        x, k, rel = O.bicgstab(mv, b, rtol=1e-12, maxit=400, x0=x0)
+    assert k <= len(calls) and rel <= 1e-12
+    if method == "bicgstab":
+        assert k == len(calls)
+    assert np.allclose(x, xs, rtol=1e-9, atol=1e-11)
+    fn = O.gmres if method == "gmres" else O.bicgstab
+    x, k, rel = fn(lambda v: A @ v, b, rtol=1e-10, maxit=10, x0=xs)
+    assert k <= 2 and rel <= 1e-10 and np.allclose(x, xs, rtol=1e-12)
+
+
 def test_bicgstab_two_eigenvalues_one_iteration():
     """A diagonal operator with two distinct eigenvalues: the first
     iteration's step (BiCG direction plus the minimal-residual omega) already
@@ -374,6 +461,17 @@ def test_jfnk_bicgstab_root_equals_gmres_root(tiny_tb):
     assert s.converged
     nd, _ = O.dense_newton(tb, tb.nstar, ftol=1e-13)
     assert np.max(np.abs(s.n / nd - 1)) < 1e-11
+
+
+def test_jfnk_preconditioned_initial_guess_root(tiny_tb):
+    """JFNK whose Krylov solves start from x0 = -P^-1 F (Algorithm 2) reaches
+    the dense-Newton root with both inner solvers."""
+    tb = tiny_tb
+    nd, _ = O.dense_newton(tb, tb.nstar, ftol=1e-13)
+    for kr in ("gmres", "bicgstab"):
+        s = O.solve(tb, ftol=1e-13, rtol=1e-8, maxiter=40, krylov=kr, krylov_x0="precond")
+        assert s.converged, kr
+        assert np.max(np.abs(s.n / nd - 1)) < 1e-11, kr
 
 
 def test_jfnk_complex_step_root_equals_dense_newton_root(tiny_tb):
@@ -420,3 +518,22 @@ def test_sqrt_eps_law(eps, tol):
     fine = _surface_ratio(eps, 20)
     assert abs(fine - 1) < tol, (coarse, fine)
     assert abs(fine - 1) < 0.6 * abs(coarse - 1), (coarse, fine)
+
+
+@pytest.mark.slow
+def test_scattering_forward_difference_root_equals_complex_step_root():
+    """Background (Thomson) scattering makes F depend on the lagged J-dagger
+    (Sect. 2.1.1).  JFNK with forward-difference products (Eq. fordif) and
+    with complex-step products (Eq. complex) reaches the same root only if
+    F(n), the products and the line search of a Newton step share one
+    J-dagger; at the root J-dagger is self-consistent (J(n; J-dagger) =
+    J-dagger)."""
+    tb = O.setup(S.chromo6(nz=40, nnu=200, thomson=True))
+    assert np.any(tb.chi_sca > 0)
+    fd = O.solve(tb, ftol=1e-12, rtol=1e-4, maxiter=40, jv="fd")
+    cs = O.solve(tb, ftol=1e-12, rtol=1e-4, maxiter=40, jv="complex")
+    assert fd.converged and cs.converged
+    assert np.max(np.abs(fd.n / cs.n - 1)) < 1e-10
+    r = O.residual(tb, cs.n, Jdag=cs.J)
+    assert np.max(r.rho) <= 1e-12
+    assert np.max(np.abs(r.J / cs.J - 1)) < 1e-9
