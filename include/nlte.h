@@ -252,6 +252,28 @@ nlte_status nlte_residual(nlte_column *col, const double *n_dev, double *F_dev,
                           double *J_dev, double *R_dev, double *Jbar_dev,
                           double *P_dev, int update_J, hipStream_t stream);
 
+/* nlte_residual for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the same
+ * arguments, kernels and results as nlte_residual, bit for bit, but the
+ * evaluation's scratch (the column descriptor, the population-check flag,
+ * the level coefficients, the formal-solution, rate and pair-sum buffers)
+ * lives in one fixed device array of 64 MiB per device, held from the first
+ * context on that device until the process ends, and every launch runs on
+ * `stream`.  Calls no hipMalloc, hipFree or other allocating routine.
+ *   A column whose evaluation needs more than 64 MiB of scratch (about
+ *   64 bytes per (depth, frequency) plus the rate and pair-sum entries) is
+ *   rejected with NLTE_E_INVALID before any device work.
+ *   Every call on a device shares that device's array and leaves its
+ *   contents behind: calls that overlap on one device (other streams, other
+ *   host threads) race and must be serialised by the caller.  The column's
+ *   own scratch is not touched (its J of the last evaluation is not updated;
+ *   update_J still sets its J-dagger).
+ * Errors as nlte_residual (NLTE_E_NONFINITE for populations that are not
+ * finite and positive). */
+nlte_status nlte_residual_noalloc(nlte_column *col, const double *n_dev, double *F_dev,
+                                  double *J_dev, double *R_dev, double *Jbar_dev,
+                                  double *P_dev, int update_J, hipStream_t stream);
+
 /* Forward-difference Jacobian-vector product (Eq. fordif):
  * Jv = (F(n + eps v) - F(n)) / eps with the conservation rows and J-dagger
  * of n.  Costs two residual evaluations (F(n) is recomputed). */

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,46 @@ nlte_ctx* column_ctx(const nlte_column* c) { return c->ctx; }
 size_t column_bytes(const nlte_column* c) { return c->arena_bytes; }
 }  // namespace nlte
 
+// ---------------------------------------------------------------------------
+// device-resident scratch of the allocation-free residual entry point
+// ---------------------------------------------------------------------------
+// One fixed array per device, held until the process ends.  In host code its
+// name is only a host-side stand-in: kernels get the device address that
+// hipGetSymbolAddress returns for each device (scratch_base).
+namespace {
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+struct ScratchSlot {
+  std::once_flag once;
+  char* ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+ScratchSlot g_scratch[kMaxDevices];
+
+// Looks the array's address up once per device (that device current).
+void scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  ScratchSlot& S = g_scratch[dev];
+  std::call_once(S.once, [&S] {
+    void* p = nullptr;
+    S.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (S.err == hipSuccess) S.ptr = static_cast<char*>(p);
+  });
+}
+
+char* scratch_base(int dev, hipError_t* err) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  scratch_init(dev);
+  *err = g_scratch[dev].err;
+  return g_scratch[dev].ptr;
+}
+}  // namespace
+
 extern "C" nlte_status nlte_ctx_create(int hip_device, nlte_ctx** out) {
   if (!out) return set_err(NLTE_E_INVALID, "out is NULL");
   int ndev = 0;
@@ -69,6 +110,7 @@ extern "C" nlte_status nlte_ctx_create(int hip_device, nlte_ctx** out) {
   if (hip_device < 0 || hip_device >= ndev)
     return set_err(NLTE_E_INVALID, "device %d out of range (%d devices)", hip_device, ndev);
   HIP_TRY(hipSetDevice(hip_device));
+  scratch_init(hip_device);  // errors are reported by the entry point that needs it
   nlte_ctx* c = new nlte_ctx();
   c->device = hip_device;
   c->prof_on = 0;
@@ -1068,6 +1110,78 @@ extern "C" nlte_status nlte_residual(nlte_column* col, const double* n_dev, doub
   if (Jbar_dev && C.nline)
     k_jbar<<<(C.nz * C.nline + 255) / 256, 256, 0, s>>>(Jbar_dev, C.R, C.tr, C.nz, C.ntr, C.nline);
   if (P_dev) HIP_TRY(hipMemcpyAsync(P_dev, C.P, (size_t)C.nz * C.L * C.L * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(set_state_eval(col, kModeIdle, 0, 0, s));
+  HIP_TRY(hipGetLastError());
+  return NLTE_OK;
+}
+
+// Scratch layout of one allocation-free residual evaluation: the column's
+// descriptor, the population-check flag, the level coefficients and the
+// formal-solution, rate and pair-sum scratch (the buffers the column's own
+// evaluations keep in its arena).  Returns the bytes needed.
+static size_t noalloc_layout(const ColDev& H, char* base, ColDev* C, int** flag, ColDev** dcol) {
+  Layout Lo(base);
+  const size_t kfp = (size_t)H.nz * H.fp, kfz = (size_t)H.nnu * H.zp;
+  *dcol = Lo.take<ColDev>(1);
+  *flag = Lo.take<int>(1);
+  C->coef = Lo.take<double>((size_t)H.nz * ncoef(H.ntr));
+  C->Jm = Lo.take<double>(kfp);
+  C->XS = Lo.take<double>(2 * kfp);
+  C->Dchi = Lo.take<double>(kfp);
+  C->Deta = Lo.take<double>(kfp);
+  C->JT = Lo.take<double>(kfz);
+  C->DchiT = Lo.take<double>(kfz);
+  C->DetaT = Lo.take<double>(kfz);
+  C->RJ = Lo.take<double>((size_t)H.nz * std::max(H.nrseg, 1) * 2);
+  C->M = Lo.take<double>((size_t)H.nz * std::max(H.nment, 1) * 2);
+  return Lo.off;
+}
+
+__global__ void k_put_coldev(ColDev c, ColDev* dst) { *dst = c; }
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+extern "C" nlte_status nlte_residual_noalloc(nlte_column* col, const double* n_dev, double* F_dev,
+                                             double* J_dev, double* R_dev, double* Jbar_dev,
+                                             double* P_dev, int update_J, hipStream_t s) {
+  if (!col || !n_dev || !F_dev) return set_err(NLTE_E_INVALID, "NULL argument");
+  const ColDev& H = col->h;
+  ColDev C = H;
+  int* flag = nullptr;
+  ColDev* dcol = nullptr;
+  const size_t need = noalloc_layout(H, nullptr, &C, &flag, &dcol);
+  if (need > kScratchBytes)
+    return set_err(NLTE_E_INVALID,
+                   "column needs %zu bytes of evaluation scratch; the allocation-free entry point "
+                   "holds %zu",
+                   need, kScratchBytes);
+  HIP_TRY(hipSetDevice(col->device));
+  hipError_t se = hipSuccess;
+  char* base = scratch_base(col->device, &se);
+  if (!base) return set_err(NLTE_E_DEVICE, "scratch address lookup failed: %s", hipGetErrorString(se));
+  noalloc_layout(H, base, &C, &flag, &dcol);
+  k_put_coldev<<<1, 1, 0, s>>>(C, dcol);
+  // populations positive and finite (flag in the scratch, cleared first)
+  k_zero_int<<<1, 1, 0, s>>>(flag);
+  k_check_finite_pos<<<(H.N + 255) / 256, 256, 0, s>>>(n_dev, H.N, flag);
+  int h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h) return set_err(NLTE_E_NONFINITE, "populations must be finite and positive");
+  const int newton = P_dev != nullptr;
+  const int wantJ = (J_dev != nullptr) || update_J;
+  HIP_TRY(hipMemcpyAsync(H.eval_n, n_dev, H.N * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(set_state_eval(col, newton ? kModeNewton : kModeF, wantJ, 1, s));
+  BatchWork bw = col->bw;
+  bw.cols = dcol;
+  bw.single_stream = 1;
+  HIP_TRY(launch_residual(bw, s));
+  HIP_TRY(hipMemcpyAsync(F_dev, H.F, H.N * 8, hipMemcpyDeviceToDevice, s));
+  if (J_dev) transpose_J(C, J_dev, s);
+  if (update_J) transpose_J(C, H.Jdag, s);
+  if (R_dev) HIP_TRY(hipMemcpyAsync(R_dev, H.R, (size_t)H.nz * H.ntr * 16, hipMemcpyDeviceToDevice, s));
+  if (Jbar_dev && H.nline)
+    k_jbar<<<(H.nz * H.nline + 255) / 256, 256, 0, s>>>(Jbar_dev, H.R, H.tr, H.nz, H.ntr, H.nline);
+  if (P_dev) HIP_TRY(hipMemcpyAsync(P_dev, H.P, (size_t)H.nz * H.L * H.L * 8, hipMemcpyDeviceToDevice, s));
   HIP_TRY(set_state_eval(col, kModeIdle, 0, 0, s));
   HIP_TRY(hipGetLastError());
   return NLTE_OK;

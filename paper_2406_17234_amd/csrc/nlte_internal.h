@@ -282,6 +282,8 @@ struct BatchWork {
   int nrate0 = 0;                 // rate items at the front of rate_work; pair-sum blocks follow
   int any64 = 0, any32 = 0, any_newton = 1;
   int any_tangent = 0;            // columns may request tangent products
+  int single_stream = 0;          // 1: every launch on the caller's stream (no side streams
+                                  // are created or used)
 };
 
 // Residual launches for a batch (level coefficients and opacity, formal

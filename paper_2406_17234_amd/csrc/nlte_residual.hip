@@ -1368,14 +1368,16 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   // they may overlap: late in a batch most of them cover a few columns each
   // and would otherwise queue up their depth-recursion latencies.
   SideStreams* SS = nullptr;
-  {
+  if (!bw.single_stream) {
     const hipError_t e = side_streams(&SS);
     if (e != hipSuccess) return e;
   }
   if (ev) chk(hipEventRecord(ev[1], s));
-  chk(hipEventRecord(SS->fork, s));
-  for (int i = 0; i < 3; ++i) chk(hipStreamWaitEvent(SS->st[i], SS->fork, 0));
-  const hipStream_t sNewton = SS->st[0], sF64 = SS->st[1], sN64 = SS->st[2];
+  if (SS) {
+    chk(hipEventRecord(SS->fork, s));
+    for (int i = 0; i < 3; ++i) chk(hipStreamWaitEvent(SS->st[i], SS->fork, 0));
+  }
+  const hipStream_t sNewton = SS ? SS->st[0] : s, sF64 = SS ? SS->st[1] : s, sN64 = SS ? SS->st[2] : s;
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
     const int nb = bw.formal_wpb;
@@ -1406,10 +1408,11 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     }
   }
   if (ev) chk(hipEventRecord(ev[6], s));  // end of the F-mode launches on s
-  for (int i = 0; i < 3; ++i) {
-    chk(hipEventRecord(SS->join[i], SS->st[i]));
-    chk(hipStreamWaitEvent(s, SS->join[i], 0));
-  }
+  if (SS)
+    for (int i = 0; i < 3; ++i) {
+      chk(hipEventRecord(SS->join[i], SS->st[i]));
+      chk(hipStreamWaitEvent(s, SS->join[i], 0));
+    }
   if (ev) chk(hipEventRecord(ev[2], s));
   // The rate integrals stream V and J of many (column, segment) pairs at
   // once; at full occupancy (32 waves per CU) they ran 20 % slower than with

@@ -145,6 +145,7 @@ def lib():
         L.nlte_lte_populations.argtypes = [vp, vp, vp]
         L.nlte_zero_radiation_populations.argtypes = [vp, vp, vp]
         L.nlte_residual.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
+        L.nlte_residual_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int, vp]
         L.nlte_jvp.argtypes = [vp, vp, vp, C.c_double, vp, vp]
         L.nlte_jvp_tangent.argtypes = [vp, vp, vp, vp, vp]
         L.nlte_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveStats),
@@ -342,7 +343,9 @@ class Column:
         return n
 
     def residual(self, n, want_J=False, want_R=False, want_Jbar=False, want_P=False,
-                 update_J=False, stream=None):
+                 update_J=False, stream=None, noalloc=False):
+        """F(n) and optional outputs (nlte_residual; with noalloc, the
+        allocation-free nlte_residual_noalloc)."""
         n = n.contiguous()
         out = {"F": self._empty(self.nz, self.nlev)}
         if want_J:
@@ -353,9 +356,9 @@ class Column:
             out["Jbar"] = self._empty(self.nz, max(self.nline, 1))
         if want_P:
             out["P"] = self._empty(self.nz, self.nlev, self.nlev)
-        _check(lib().nlte_residual(self.h, _ptr(n), _ptr(out["F"]), _ptr(out.get("J")),
-                                   _ptr(out.get("R")), _ptr(out.get("Jbar")), _ptr(out.get("P")),
-                                   int(update_J), _stream(stream)))
+        fn = lib().nlte_residual_noalloc if noalloc else lib().nlte_residual
+        _check(fn(self.h, _ptr(n), _ptr(out["F"]), _ptr(out.get("J")), _ptr(out.get("R")),
+                  _ptr(out.get("Jbar")), _ptr(out.get("P")), int(update_J), _stream(stream)))
         return out
 
     def jvp(self, n, v, eps, stream=None):

@@ -1,0 +1,85 @@
+"""The allocation-free residual entry point (nlte_residual_noalloc) against
+nlte_residual: the same kernels on the same inputs, so every output must be
+bit-identical; two calls in a row, the second on a smaller column (the shared
+scratch keeps the first call's contents), and a column too large for the
+fixed scratch is rejected before any device work."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import nlte_oracle as O
+from paper_2406_17234_amd import synth as S
+from tests.helpers import perturbed, require_gpu, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+OUTS = ("F", "J", "R", "Jbar", "P")
+
+
+def _both(col, n, **kw):
+    a = col.residual(n, **kw)
+    b = col.residual(n, noalloc=True, **kw)
+    return a, b
+
+
+def test_noalloc_residual_equals_residual():
+    require_gpu()
+    import torch
+    from paper_2406_17234_amd import nlte
+    ctx = nlte.Context(0)
+    big = S.chromo6(nz=60, nnu=400)
+    small = S.slab3(nz=24)
+    cols = [(big, nlte.Column(ctx, big, precision=nlte.FP32_FORM)),
+            (small, nlte.Column(ctx, small, precision=nlte.FP64))]
+    kw = dict(want_J=True, want_R=True, want_Jbar=True, want_P=True)
+    for prob, col in cols:  # the second call is the smaller column
+        print(f"[case] noalloc {prob.name} dims={prob.dims}", flush=True)
+        tb = O.setup(prob)
+        n = to_dev(perturbed(tb.nstar, seed=5, scale=0.25))
+        a, b = _both(col, n, **kw)
+        torch.cuda.synchronize()
+        for k in OUTS:
+            assert np.array_equal(to_np(a[k]), to_np(b[k])), (prob.name, k)
+        # F-only mode (no preconditioner) as well
+        a, b = _both(col, n, want_J=True)
+        for k in ("F", "J"):
+            assert np.array_equal(to_np(a[k]), to_np(b[k])), (prob.name, k)
+        if prob is small:
+            ref = O.residual(tb, to_np(n))
+            assert np.max(np.abs(to_np(b["F"]) - ref.F) / ref.G) < 1e-12
+    # repeated calls allocate nothing: device free memory does not move
+    prob, col = cols[1]
+    n = to_dev(O.setup(prob).nstar)
+    col.residual(n, noalloc=True, **kw)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(3):
+        col.residual(n, noalloc=True, **kw)
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] == free0
+    # non-finite populations are reported as by nlte_residual
+    bad = to_np(n).copy()
+    bad[3, 0] = np.nan
+    with pytest.raises(nlte.NLTEError) as e:
+        col.residual(to_dev(bad), noalloc=True)
+    assert e.value.status == nlte.NLTE_E_NONFINITE
+    for _, c in cols:
+        c.close()
+
+
+def test_noalloc_rejects_a_column_beyond_the_scratch():
+    require_gpu()
+    from paper_2406_17234_amd import nlte
+    ctx = nlte.Context(0)
+    prob = S.chromo6(nz=256, nnu=6000)
+    col = nlte.Column(ctx, prob)
+    n = to_dev(np.ones((col.nz, col.nlev)))
+    with pytest.raises(nlte.NLTEError) as e:
+        col.residual(n, noalloc=True)
+    assert e.value.status == nlte.NLTE_E_INVALID
+    assert "scratch" in str(e.value)
+    # the ordinary entry point still evaluates it
+    out = col.residual(n)
+    assert np.all(np.isfinite(to_np(out["F"])))
+    col.close()
