@@ -65,6 +65,32 @@ def test_two_level_atom(ctx):
     assert maxrel(to_np(n), ref.n) < 1e-10
 
 
+@pytest.mark.parametrize("nz", [8, 9, 10, 16, 17, 25])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("newton", [False, True])
+def test_rate_blocks_at_every_depth_alignment(ctx, nz, precision, newton):
+    """The formal-solution kernel integrates the rates in blocks of 8 depths
+    per sweep and writes J through the same tile: columns whose depth count
+    ends anywhere in a block (the bottom depth opening a block, ending one,
+    or inside one) give the oracle's J, R and F in both modes."""
+    from paper_2406_17234_amd import nlte
+    prob = S.chromo6(nz=nz, nnu=150)
+    tb = O.setup(prob)
+    n = perturbed(tb.nstar, seed=nz, scale=0.2)
+    ref = O.residual(tb, n)
+    prec = nlte.FP64 if precision == "fp64" else nlte.FP32_FORM
+    col = nlte.Column(ctx, prob, precision=prec)
+    out = col.residual(to_dev(n), want_J=True, want_R=True, want_P=newton)
+    tol = 1e-11 if precision == "fp64" else 5e-5
+    big = ref.J > (1e-300 if precision == "fp64" else 1e-30 * ref.J.max())
+    assert maxrel(to_np(out["J"])[big], ref.J[big]) < tol
+    R = to_np(out["R"])
+    assert maxrel(R[..., 0], ref.R_lu, floor=1e-300) < tol
+    assert maxrel(R[..., 1], ref.R_ul, floor=1e-300) < tol
+    assert np.max(np.abs(to_np(out["F"]) - ref.F) / ref.G) < 2 * tol
+    col.close()
+
+
 def _level_ladder(nlev, name):
     """An atom of nlev - 1 evenly spaced bound levels (0 to 7.5 eV) plus a
     continuum at 9 eV, lines between neighbours and next neighbours, an edge
