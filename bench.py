@@ -255,6 +255,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-budget-gb", type=float, default=96.0)
     ap.add_argument("--serve-max-active", type=int, default=2048)
+    ap.add_argument("--launch", default="eager", choices=["eager", "graph", "graph+tune"],
+                    help="step replay of the timed batch solves (HIP graphs, launch-shape tuner); "
+                         "graph replay of the full 4096-column batch is not cleared for use "
+                         "(a host-side crash in its second solve is not understood yet)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy kernel (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -288,15 +292,16 @@ def main():
     setup_s = time.perf_counter() - t0
     print(f"[bench] created {ncol} columns in {setup_s:.1f} s", file=sys.stderr, flush=True)
     dp_col = np.array([p.depth_points() for p in problems], dtype=np.float64)
+    launch = {"eager": 0, "graph": nlte.NLTE_SOLVE_GRAPH,
+              "graph+tune": nlte.NLTE_SOLVE_GRAPH | nlte.NLTE_SOLVE_TUNE}[args.launch]
     opts = nlte.default_opts(ftol=ftol, rtol=args.rtol, maxiter=50,
                              max_krylov_total=args.max_krylov_total,
-                             fp64_fallback=args.fp64_fallback)
+                             fp64_fallback=args.fp64_fallback, launch=launch)
 
     for w in range(args.warmup):
         _, st, rc = nlte.solve_batch(ctx, cols, opts)
         print(f"[bench] warmup {w} rc={rc}", file=sys.stderr, flush=True)
 
-    ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats_all = []
@@ -306,19 +311,37 @@ def main():
         print(f"[bench] step {k} rc={rc}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    replay = ctx.read_profile()
+    # the same solve launched eagerly (no graphs, one wave per formal
+    # workgroup), and once more with per-phase HIP events (eager by necessity)
+    # for the phase breakdown and the roofline of the F-mode formal launches
+    opts_e = nlte.default_opts(ftol=ftol, rtol=args.rtol, maxiter=50,
+                               max_krylov_total=args.max_krylov_total,
+                               fp64_fallback=args.fp64_fallback, launch=0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nlte.solve_batch(ctx, cols, opts_e)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t1) * 1e3
+    ctx.profile(True)
+    _, st_prof, _ = nlte.solve_batch(ctx, cols, opts_e)
     prof = ctx.read_profile()
     ctx.profile(False)
+    print(f"[bench] eager solve {eager_ms:.0f} ms; replayed {elapsed / args.steps * 1e3:.0f} ms "
+          f"(wpb {replay['last_formal_wpb']}, tune {replay['last_tune_ms']})", file=sys.stderr, flush=True)
 
     f_calls = np.array([[s["f_calls"] for s in st] for st in stats_all], dtype=np.float64)
-    pc_calls = np.array([[s["precond_calls"] for s in st] for st in stats_all], dtype=np.float64)
     conv = np.array([[s["status"] == 0 for s in st] for st in stats_all])
     total_dp = float((f_calls * dp_col[None, :]).sum())
-    fp64_evals = np.array([[s["fp64_evals"] for s in st] for st in stats_all], dtype=np.float64)
-    # depth-points of the F-mode evaluations in the columns' own precision (the
-    # launches on the solve stream that formal_f_ms times); FP64 evaluations
-    # of fallback columns are all subtracted, a slight undercount
-    own = f_calls - pc_calls - (fp64_evals if prec == 1 else 0.0)
-    fmode_dp = float((np.maximum(own, 0.0) * dp_col[None, :]).sum())
+    # depth-points of the profiled solve's F-mode evaluations in the columns'
+    # own precision (the launches on the solve stream that formal_f_ms
+    # times); FP64 evaluations of fallback columns are all subtracted, a
+    # slight undercount
+    pf = np.array([s["f_calls"] for s in st_prof], dtype=np.float64)
+    ppc = np.array([s["precond_calls"] for s in st_prof], dtype=np.float64)
+    p64 = np.array([s["fp64_evals"] for s in st_prof], dtype=np.float64)
+    own = pf - ppc - (p64 if prec == 1 else 0.0)
+    fmode_dp = float((np.maximum(own, 0.0) * dp_col).sum())
     ms_per_step = elapsed / args.steps * 1e3
     value = total_dp / elapsed
     achieved = (fmode_dp * OPS_PER_DP / (prof["formal_f_ms"] * 1e-3) / 1e12
@@ -351,8 +374,13 @@ def main():
         "newton_iters_mean": float(np.mean([[s["newton_iters"] for s in st] for st in stats_all])),
         "fp64_fallback_fraction": float(np.mean([[s["precision"] == 0 and prec == 1 for s in st]
                                                  for st in stats_all])),
-        "kernel_ms_per_step": {k: prof[k] / args.steps for k in
-                               ("opacity_ms", "formal_ms", "depth_ms", "assemble_ms", "solver_ms")},
+        "launch": {"mode": args.launch, "formal_wpb": replay["last_formal_wpb"],
+                   "tune_ms_per_step_wpb_1_2_4": replay["last_tune_ms"],
+                   "graph_captures_per_solve": replay["last_captures"],
+                   "eager_ms_per_solve": eager_ms},
+        "kernel_ms_per_solve_eager_profiled": {k: prof[k] for k in
+                                               ("opacity_ms", "formal_ms", "depth_ms",
+                                                "assemble_ms", "solver_ms")},
         "roofline": {
             "kernel": ("k_formal<float, false, 5>" if prec == 1 else "k_formal<double, false, 5>") +
                       " (F-mode depth recursion; in launches over at least 4096 chunks it"
@@ -375,7 +403,7 @@ def main():
         # warm-up solve, one timed solve
         o2 = nlte.default_opts(ftol=ftol, rtol=args.rtol, maxiter=50,
                                max_krylov_total=args.max_krylov_total,
-                               fp64_fallback=args.fp64_fallback, **kw)
+                               fp64_fallback=args.fp64_fallback, launch=launch, **kw)
         nlte.solve_batch(ctx, cols, o2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

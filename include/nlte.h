@@ -159,8 +159,19 @@ typedef struct {
                           * 0 (default) x0 = 0; 1 x0 = -P^-1 F(n), which costs
                           * one more Jacobian product per Newton iteration
                           * (counted in krylov_iters and the budgets)          */
-  int32_t pad_opts;      /* reserved, set to 0                                 */
+  int32_t launch;        /* how the batch solve replays its steps (OR of):
+                          * NLTE_SOLVE_GRAPH: every block of steps between two
+                          * host checks is captured once into a HIP graph and
+                          * replayed (captured again when the list of running
+                          * columns is compacted); NLTE_SOLVE_TUNE: the first
+                          * blocks try 1, 2 and 4 waves per formal-solution
+                          * workgroup and the rest use the fastest.  Results
+                          * do not depend on it (default 0: eager launches,
+                          * one wave per workgroup).  Profiled solves
+                          * (nlte_profile_enable) launch eagerly.               */
 } nlte_solve_opts;
+
+enum { NLTE_SOLVE_GRAPH = 1, NLTE_SOLVE_TUNE = 2 };
 
 typedef struct {
   int32_t status;        /* nlte_status of this column                          */
@@ -192,6 +203,12 @@ typedef struct {
   double opacity_ms;         /* level coefficients + opacity/source function    */
   int64_t formal_f_launches; /* F-mode formal-solution launches on the stream   */
   double formal_f_ms;        /* their summed duration                           */
+  /* last batch solve on the context (recorded whether or not profiling is on) */
+  int32_t last_graph;        /* 1 if its steps were replayed from HIP graphs    */
+  int32_t last_formal_wpb;   /* waves per formal-solution workgroup it used     */
+  double last_tune_ms[3];    /* mean step time with 1, 2, 4 waves (0: untuned)  */
+  int32_t last_captures;     /* graphs captured (one more per compaction)       */
+  int32_t pad_profile;
 } nlte_profile;
 
 /* Fills opts with the defaults listed above. */
@@ -395,18 +412,37 @@ typedef struct {
   int32_t active, queued;
   int64_t active_bytes;  /* device arena bytes of the columns in flight        */
   double busy_ms;        /* host time spent with columns in flight             */
+  int64_t peak_active_bytes; /* largest active_bytes so far                    */
 } nlte_server_info;
 
-/* opts as for nlte_solve (opts->init must be 1: LTE unless a request brings
- * n0); max_active >= 1; hbm_budget > 0 bytes. */
+/* opts as for nlte_solve; requests that bring no n0 start from LTE
+ * (opts->init = 1) or from the radiation-free populations (opts->init = 2,
+ * Sect. 2.2.1); opts->init = 0 is rejected.  max_active >= 1; hbm_budget > 0
+ * bytes. */
 nlte_status nlte_server_create(nlte_ctx *ctx, size_t hbm_budget, int32_t max_active,
                                const nlte_solve_opts *opts, nlte_server **out);
 /* Queues a solve of col; *ticket identifies it for nlte_server_poll. */
 nlte_status nlte_server_submit(nlte_server *srv, nlte_column *col, const double *n0_dev,
                                uint64_t *ticket);
+/* Queues a solve of a problem the server holds on the host until admission:
+ * the descriptors are validated (as nlte_column_create; errors are returned
+ * here) and deep-copied, so the caller may free them at once.  The request
+ * is admitted when the device bytes of its column (nlte_column_plan_bytes)
+ * fit the budget next to the columns in flight; its column is then created
+ * (device memory allocated, setup run: part of the request's latency) and
+ * solved with the others, and when the solve finishes its populations are
+ * copied to n_out_dev ([nz][nlev] device memory owned by the caller, valid
+ * until the ticket is polled) and the column is destroyed.  If the column
+ * cannot be created, the request finishes with that status.  Sect. 2.1 (the
+ * problem), Algorithm 2 (the solve). */
+nlte_status nlte_server_submit_problem(nlte_server *srv, const nlte_atmos_desc *atmos,
+                                       const nlte_atom_desc *atom, const nlte_grid_desc *grid,
+                                       const double *C_up, int32_t precision, double *n_out_dev,
+                                       uint64_t *ticket);
 /* NLTE_OK: the solve has finished; its populations are copied to n_out_dev
- * ([nz][nlev] device memory, or NULL) and its result to *res (or NULL), and
- * the ticket is released.  NLTE_E_BUSY: not finished yet (nothing copied).
+ * ([nz][nlev] device memory, or NULL; unused for problem requests, whose
+ * populations are already in the buffer given at submission) and its result
+ * to *res (or NULL), and the ticket is released.  NLTE_E_BUSY: not finished yet (nothing copied).
  * NLTE_E_INVALID: unknown ticket.  A solve that stops at maxiter is finished
  * with res->stats.status = NLTE_E_NOCONV. */
 nlte_status nlte_server_poll(nlte_server *srv, uint64_t ticket, double *n_out_dev,

@@ -149,7 +149,7 @@ extern "C" void nlte_solve_opts_default(nlte_solve_opts* o) {
   o->krylov_method = NLTE_KRYLOV_GMRES;
   o->jv_method = NLTE_JV_FD;
   o->krylov_x0 = 0;
-  o->pad_opts = 0;
+  o->launch = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -987,6 +987,79 @@ extern "C" void nlte_column_destroy(nlte_column* col) {
   if (col->arena) (void)hipFree(col->arena);
   delete col;
 }
+
+// ---------------------------------------------------------------------------
+// problems held on the host until their column is created (served requests)
+// ---------------------------------------------------------------------------
+namespace nlte {
+struct HostProblem {
+  std::vector<double> z, T, ne, ntot, chi_c, chi_sca, eta_c;
+  std::vector<double> E, g, A_ul, a_damp, bf_nu, bf_alpha;
+  std::vector<int32_t> stage, line_lo, line_up, bf_lo, bf_ptr;
+  std::vector<double> nu, mu, w_mu, w_nu, C_up;
+  std::vector<int32_t> win_lo, win_hi;
+  nlte_atmos_desc A{};
+  nlte_atom_desc M{};
+  nlte_grid_desc G{};
+  int32_t precision = 0;
+  size_t bytes = 0;
+};
+
+template <typename T>
+static void copy_in(std::vector<T>& v, const T* p, size_t n) {
+  if (p) v.assign(p, p + n);
+}
+template <typename T>
+static const T* ptr_or_null(const std::vector<T>& v) {
+  return v.empty() ? nullptr : v.data();
+}
+
+// Validates and sizes a problem (as nlte_column_plan_bytes), then copies
+// every descriptor array, so the caller may free its own right away.
+nlte_status problem_copy(const nlte_atmos_desc* A, const nlte_atom_desc* M, const nlte_grid_desc* G,
+                         const double* C_up, int32_t precision, HostProblem** out) {
+  ColumnPlan P;
+  const nlte_status st = plan_column(A, M, G, C_up, precision, P);
+  if (st != NLTE_OK) return st;
+  HostProblem* H = new HostProblem();
+  const int nz = A->nz, L = M->nlev, nline = M->nline, nbf = M->nbf, ntr = nline + nbf;
+  const int nnu = G->nnu, nmu = G->nmu;
+  const size_t nbft = nbf ? (size_t)M->bf_ptr[nbf] : 0;
+  copy_in(H->z, A->z, nz); copy_in(H->T, A->T, nz); copy_in(H->ne, A->ne, nz);
+  copy_in(H->ntot, A->ntot, nz); copy_in(H->chi_c, A->chi_c, nz);
+  copy_in(H->chi_sca, A->chi_sca, nz); copy_in(H->eta_c, A->eta_c, (size_t)nz * nnu);
+  copy_in(H->E, M->E, L); copy_in(H->g, M->g, L); copy_in(H->stage, M->stage, L);
+  copy_in(H->line_lo, M->line_lo, nline); copy_in(H->line_up, M->line_up, nline);
+  copy_in(H->A_ul, M->A_ul, nline); copy_in(H->a_damp, M->a_damp, nline);
+  copy_in(H->bf_lo, M->bf_lo, nbf);
+  if (nbf) copy_in(H->bf_ptr, M->bf_ptr, nbf + 1);
+  copy_in(H->bf_nu, M->bf_nu, nbft); copy_in(H->bf_alpha, M->bf_alpha, nbft);
+  copy_in(H->nu, G->nu, nnu); copy_in(H->win_lo, G->win_lo, ntr); copy_in(H->win_hi, G->win_hi, ntr);
+  copy_in(H->mu, G->mu, nmu); copy_in(H->w_mu, G->w_mu, nmu); copy_in(H->w_nu, G->w_nu, nnu);
+  copy_in(H->C_up, C_up, (size_t)nz * ntr);
+  H->A = nlte_atmos_desc{nz, H->z.data(), H->T.data(), H->ne.data(), H->ntot.data(), H->chi_c.data(),
+                         ptr_or_null(H->chi_sca), ptr_or_null(H->eta_c)};
+  H->M = nlte_atom_desc{L, H->E.data(), H->g.data(), H->stage.data(), nline, ptr_or_null(H->line_lo),
+                        ptr_or_null(H->line_up), ptr_or_null(H->A_ul), ptr_or_null(H->a_damp),
+                        M->mass_amu, M->vturb, nbf, ptr_or_null(H->bf_lo), ptr_or_null(H->bf_ptr),
+                        ptr_or_null(H->bf_nu), ptr_or_null(H->bf_alpha)};
+  H->G = nlte_grid_desc{nnu, H->nu.data(), H->win_lo.data(), H->win_hi.data(), nmu, H->mu.data(),
+                        H->w_mu.data(), ptr_or_null(H->w_nu)};
+  H->precision = precision;
+  H->bytes = P.bytes;
+  *out = H;
+  return NLTE_OK;
+}
+
+size_t problem_bytes(const HostProblem* H) { return H->bytes; }
+
+nlte_status problem_create_column(nlte_ctx* ctx, const HostProblem* H, hipStream_t s,
+                                  nlte_column** out) {
+  return nlte_column_create(ctx, &H->A, &H->M, &H->G, H->C_up.data(), H->precision, s, out);
+}
+
+void problem_free(HostProblem* H) { delete H; }
+}  // namespace nlte
 
 extern "C" nlte_status nlte_column_plan_bytes(const nlte_atmos_desc* atmos,
                                               const nlte_atom_desc* atom,

@@ -310,6 +310,7 @@ hipError_t solver_init(const ColDev* cols, int ncol, const double* const* n0,
 hipError_t solver_step(const ColDev* cols, const int* act, int n, int* done, hipStream_t s);
 hipError_t solver_gather(const ColDev* cols, int ncol, ColState* out, hipStream_t s);
 bool state_done(const ColState& st);
+void zero_radiation_into(const ColDev* dcol, const ColDev& hc, hipStream_t s);
 void state_stats(const ColState& st, nlte_solve_stats* out);
 
 // Copies the tile groups of build_work_lists into bw; false (bw untouched)

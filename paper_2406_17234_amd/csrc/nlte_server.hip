@@ -7,6 +7,13 @@
 // one residual evaluation per column per step, then one Newton/Krylov step),
 // reads back the columns' states and retires the finished ones.  Work lists
 // are rebuilt whenever the set of columns in flight changes.
+//
+// A request is either a column the caller created (its device memory exists
+// before admission and is counted while it is in flight) or a problem
+// description copied at submission: its column is created (device memory
+// allocated, n-independent setup run) when the request is admitted within
+// the budget, and destroyed, after its populations are copied out, when it
+// retires, so the budget bounds the device memory the requests hold.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -23,6 +30,14 @@ namespace nlte {
 const ColDev& column_dev(const nlte_column* c);
 nlte_ctx* column_ctx(const nlte_column* c);
 size_t column_bytes(const nlte_column* c);
+ColDev* column_dev_ptr(const nlte_column* c);
+struct HostProblem;
+nlte_status problem_copy(const nlte_atmos_desc* A, const nlte_atom_desc* M, const nlte_grid_desc* G,
+                         const double* C_up, int32_t precision, HostProblem** out);
+size_t problem_bytes(const HostProblem* H);
+nlte_status problem_create_column(nlte_ctx* ctx, const HostProblem* H, hipStream_t s,
+                                  nlte_column** out);
+void problem_free(HostProblem* H);
 }  // namespace nlte
 
 using namespace nlte;
@@ -40,6 +55,11 @@ struct Request {
   size_t bytes = 0;
   int state = kQueued;
   nlte_server_result res{};
+  HostProblem* prob = nullptr;  // problem requests: the description, until destruction
+  double* n_out = nullptr;      // problem requests: where the populations go at retirement
+  ~Request() {
+    if (prob) problem_free(prob);
+  }
 };
 
 // Device buffer that only grows.
@@ -172,7 +192,15 @@ hipError_t nlte_server::admit(std::vector<Request*>& adm) {
   if ((e = d_n0.fit(na)) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(d_n0.p, n0.data(), na * sizeof(const double*), hipMemcpyHostToDevice, stream)) != hipSuccess) return e;
   const int first = (int)active.size() - na;
-  return solver_init(d_cols.p + first, na, d_n0.p, nullptr, opts, stream);
+  e = solver_init(d_cols.p + first, na, d_n0.p, nullptr, opts, stream);
+  if (e != hipSuccess || opts.init != 2) return e;
+  // radiation-free start (Sect. 2.2.1): per admitted column, over its LTE
+  // initial populations
+  for (int i = 0; i < na; ++i) {
+    if (adm[i]->n0) continue;  // a request that brings n0 starts from it
+    zero_radiation_into(column_dev_ptr(adm[i]->col), column_dev(adm[i]->col), stream);
+  }
+  return hipGetLastError();
 }
 
 void nlte_server::run() {
@@ -201,11 +229,35 @@ void nlte_server::run() {
         adm.push_back(r);
       }
       info.active_bytes = (int64_t)bytes;
+      info.peak_active_bytes = std::max(info.peak_active_bytes, info.active_bytes);
       info.queued = (int32_t)queue.size();
     }
     if (!adm.empty()) {
+      // problem requests: their columns are created now, within the budget
+      std::vector<Request*> ok;
+      ok.reserve(adm.size());
+      for (Request* r : adm) {
+        if (r->prob && !r->col) {
+          nlte_column* c = nullptr;
+          const nlte_status cs = problem_create_column(ctx, r->prob, stream, &c);
+          if (cs != NLTE_OK) {
+            std::lock_guard<std::mutex> lk(mu);
+            r->res.stats = nlte_solve_stats{};
+            r->res.stats.status = cs;
+            r->res.t_done_ms = now_ms(t0);
+            r->state = kDone;
+            info.active_bytes -= (int64_t)r->bytes;
+            info.completed += 1;
+            cv_idle.notify_all();
+            continue;
+          }
+          r->col = c;
+        }
+        ok.push_back(r);
+      }
+      adm.swap(ok);
       active.insert(active.end(), adm.begin(), adm.end());
-      dirty = true;
+      dirty = !adm.empty() || dirty;
     }
     if (dirty) {
       if ((e = rebuild()) != hipSuccess) break;
@@ -223,6 +275,27 @@ void nlte_server::run() {
       e = hipMemcpyAsync(h_states, d_states.p, n * sizeof(ColState), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) break;
+    // problem requests that finished: populations to the caller's buffer,
+    // then the column (and its device memory) goes
+    bool freed = false;
+    for (int c = 0; c < n && e == hipSuccess; ++c) {
+      Request* r = active[c];
+      if (r->prob && state_done(h_states[c])) {
+        const ColDev& C = column_dev(r->col);
+        if (r->n_out)
+          e = hipMemcpyAsync(r->n_out, C.n, (size_t)C.N * sizeof(double), hipMemcpyDeviceToDevice, stream);
+        freed = true;
+      }
+    }
+    if (freed && e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) break;
+    for (int c = 0; c < n; ++c) {
+      Request* r = active[c];
+      if (r->prob && r->col && state_done(h_states[c])) {
+        nlte_column_destroy(r->col);
+        r->col = nullptr;
+      }
+    }
     const double t = now_ms(t0);
     std::vector<Request*> still;
     still.reserve(n);
@@ -274,7 +347,9 @@ extern "C" nlte_status nlte_server_create(nlte_ctx* ctx, size_t hbm_budget, int3
   if (opts) o = *opts;
   const nlte_status vs = check_solve_opts(o);
   if (vs != NLTE_OK) return vs;
-  if (o.init != 1) return set_err(NLTE_E_INVALID, "server requests start from n0 or LTE (opts.init = 1)");
+  if (o.init == 0)
+    return set_err(NLTE_E_INVALID, "server requests start from n0 when they bring one, else from "
+                                   "LTE (opts.init = 1) or the radiation-free populations (2)");
   if (hipSetDevice(ctx->device) != hipSuccess) return set_err(NLTE_E_DEVICE, "hipSetDevice failed");
   nlte_server* S = new nlte_server();
   S->ctx = ctx;
@@ -326,6 +401,37 @@ extern "C" nlte_status nlte_server_submit(nlte_server* S, nlte_column* col, cons
   return NLTE_OK;
 }
 
+extern "C" nlte_status nlte_server_submit_problem(nlte_server* S, const nlte_atmos_desc* atmos,
+                                                  const nlte_atom_desc* atom,
+                                                  const nlte_grid_desc* grid, const double* C_up,
+                                                  int32_t precision, double* n_out_dev,
+                                                  uint64_t* ticket) {
+  if (!S || !ticket || !n_out_dev) return set_err(NLTE_E_INVALID, "NULL argument");
+  HostProblem* H = nullptr;
+  const nlte_status ps = problem_copy(atmos, atom, grid, C_up, precision, &H);
+  if (ps != NLTE_OK) return ps;
+  Request* r = new Request();
+  r->prob = H;
+  r->n_out = n_out_dev;
+  r->bytes = problem_bytes(H);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->fail != NLTE_OK) {
+      delete r;
+      return set_err(S->fail, "server stopped after a device error");
+    }
+    r->ticket = S->next_ticket++;
+    r->res.t_submit_ms = now_ms(S->t0);
+    S->reqs[r->ticket] = r;
+    S->queue.push_back(r);
+    S->info.submitted += 1;
+    S->info.queued = (int32_t)S->queue.size();
+  }
+  S->cv.notify_one();
+  *ticket = r->ticket;
+  return NLTE_OK;
+}
+
 extern "C" nlte_status nlte_server_poll(nlte_server* S, uint64_t ticket, double* n_out_dev,
                                         nlte_server_result* res) {
   if (!S) return set_err(NLTE_E_INVALID, "NULL server");
@@ -339,7 +445,7 @@ extern "C" nlte_status nlte_server_poll(nlte_server* S, uint64_t ticket, double*
     S->reqs.erase(it);
   }
   nlte_status st = NLTE_OK;
-  if (n_out_dev && r->res.stats.status != NLTE_E_DEVICE) {
+  if (n_out_dev && !r->prob && r->res.stats.status != NLTE_E_DEVICE) {
     const ColDev& C = column_dev(r->col);
     if (hipMemcpyAsync(n_out_dev, C.n, (size_t)C.N * sizeof(double), hipMemcpyDeviceToDevice,
                        S->copy_stream) != hipSuccess ||
@@ -381,7 +487,10 @@ extern "C" void nlte_server_destroy(nlte_server* S) {
   if (S->th.joinable()) S->th.join();
   (void)hipSetDevice(S->device);
   hipStreamSynchronize(S->stream);
-  for (auto& kv : S->reqs) delete kv.second;
+  for (auto& kv : S->reqs) {
+    if (kv.second->prob && kv.second->col) nlte_column_destroy(kv.second->col);
+    delete kv.second;
+  }
   if (S->h_states) hipHostFree(S->h_states);
   hipStreamDestroy(S->stream);
   hipStreamDestroy(S->copy_stream);

@@ -1010,7 +1010,7 @@ nlte_status check_solve_opts(const nlte_solve_opts& o) {
   if (o.restart < 1 || o.restart > kMaxM) return set_err(NLTE_E_INVALID, "restart must be 1..%d", kMaxM);
   if (o.maxiter < 0 || o.max_krylov < 1 || o.max_krylov_total < 0 || o.max_halvings < 0 ||
       !(o.ftol >= 0) || !(o.rtol > 0) || !(o.eps_scale > 0) || o.init < 0 || o.init > 2 ||
-      o.krylov_x0 < 0 || o.krylov_x0 > 1 ||
+      o.krylov_x0 < 0 || o.krylov_x0 > 1 || (o.launch & ~(NLTE_SOLVE_GRAPH | NLTE_SOLVE_TUNE)) ||
       (o.krylov_method != NLTE_KRYLOV_GMRES && o.krylov_method != NLTE_KRYLOV_BICGSTAB) ||
       (o.jv_method != NLTE_JV_FD && o.jv_method != NLTE_JV_TANGENT))
     return set_err(NLTE_E_INVALID, "invalid solve options");
@@ -1038,6 +1038,14 @@ hipError_t solver_gather(const ColDev* cols, int ncol, ColState* out, hipStream_
 
 bool state_done(const ColState& st) { return st.phase == PH_DONE; }
 
+// Radiation-free start of a column whose solver state was just initialised:
+// its first evaluation point and its initial populations (the restart point
+// of an FP64 fallback) become the radiation-free populations.
+void zero_radiation_into(const ColDev* dcol, const ColDev& hc, hipStream_t s) {
+  k_zero_radiation<<<(hc.nz + 63) / 64, 64, 0, s>>>(dcol, hc.eval_n);
+  (void)hipMemcpyAsync(hc.n_init, hc.eval_n, (size_t)hc.N * sizeof(double), hipMemcpyDeviceToDevice, s);
+}
+
 void state_stats(const ColState& st, nlte_solve_stats* out) {
   out->status = st.phase == PH_DONE ? st.status : NLTE_E_NOCONV;
   out->newton_iters = st.newton_it;
@@ -1054,6 +1062,29 @@ void state_stats(const ColState& st, nlte_solve_stats* out) {
 }  // namespace nlte
 
 namespace {
+// Graph replay of a batch solve's step blocks: the capture stream, the graph
+// of the current block shape and work lists, and two timing events of the
+// shape tuner.
+struct StepReplay {
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  int captures = 0;
+  void drop() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~StepReplay() {
+    drop();
+    if (cap) hipStreamDestroy(cap);
+    if (t0) hipEventDestroy(t0);
+    if (t1) hipEventDestroy(t1);
+  }
+};
+
 struct Batch {
   ColDev* cols = nullptr;       // device array of column descriptors
   Tile* tiles = nullptr;
@@ -1158,42 +1189,105 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
               o.restart, o.max_halvings, o.init, o.max_krylov_total, o.fp64_fallback, o.krylov_method,
               o.jv_method, o.krylov_x0};
   k_solver_init<<<ncol, 256, 0, s>>>(b.cols, o.init == 0 ? b.n0 : nullptr, b.J0, ia);
-  if (o.init == 2) {
-    for (int c = 0; c < ncol; ++c)
-      k_zero_radiation<<<(hc[c].nz + 63) / 64, 64, 0, s>>>(column_dev_ptr(cols[c]), hc[c].eval_n);
-  }
+  if (o.init == 2)
+    for (int c = 0; c < ncol; ++c) zero_radiation_into(column_dev_ptr(cols[c]), hc[c], s);
   HIP_TRY(hipGetLastError());
   // every step evaluates one residual per active column; bound the step count
   const long max_steps = (long)(o.maxiter + 1) * (o.max_krylov + o.max_krylov / o.restart + o.max_halvings + 4) + 16;
   const int check_every = 4;
   const bool prof = ctx->prof_on != 0;
+  // graph replay of the blocks of check_every steps (eager when profiling,
+  // whose per-phase events sit between the launches)
+  const bool use_graph = (o.launch & NLTE_SOLVE_GRAPH) && !prof;
+  const bool tune = (o.launch & NLTE_SOLVE_TUNE) != 0;
+  StepReplay G;
+  if (use_graph) {
+    HIP_TRY(residual_streams_init());
+    HIP_TRY(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+  }
+  if (tune) {
+    HIP_TRY(hipEventCreate(&G.t0));
+    HIP_TRY(hipEventCreate(&G.t1));
+  }
+  // waves per formal-solution workgroup: one (the four concurrent launches
+  // of a residual call share the device best), or tried 1, 2, 4 on blocks
+  // 1..3 (block 0 holds the first, preconditioned evaluations)
+  const int wpb_try[3] = {1, 2, 4};
+  double tune_ms[3] = {0.0, 0.0, 0.0};
+  int tune_next = tune ? 0 : 3;
+  bw.formal_wpb = 1;
   std::vector<hipEvent_t> ev;
   if (prof) {
     ev.resize(7 * check_every);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
   }
   long step = 0;
+  long block = 0;
   *b.done_host = 0;
   int nlisted = ncol;
   std::vector<ColState> hst(ncol);
   HIP_TRY(hipMalloc(&b.act, ncol * sizeof(int)));
   HIP_TRY(hipMalloc(&b.states, ncol * sizeof(ColState)));
   nlte_status loop_st = NLTE_OK;
-  while (step < max_steps) {
-    for (int r = 0; r < check_every; ++r, ++step) {
-      hipEvent_t* e = prof ? &ev[7 * r] : nullptr;
-      hipError_t he = launch_residual(bw, s, e);
-      k_solver_step<<<bw.act ? bw.nact : ncol, kThreads, 0, s>>>(b.cols, bw.act, b.done);
-      if (prof) hipEventRecord(e[5], s);
+  auto launch_block = [&](hipStream_t st, bool with_events) -> hipError_t {
+    for (int r = 0; r < check_every; ++r) {
+      hipEvent_t* e = with_events ? &ev[7 * r] : nullptr;
+      hipError_t he = launch_residual(bw, st, e);
+      k_solver_step<<<bw.act ? bw.nact : ncol, kThreads, 0, st>>>(b.cols, bw.act, b.done);
+      if (with_events) hipEventRecord(e[5], st);
       if (he == hipSuccess) he = hipGetLastError();
-      if (he != hipSuccess) {
-        loop_st = set_err(NLTE_E_DEVICE, "solver launch failed: %s", hipGetErrorString(he));
-        break;
-      }
+      if (he != hipSuccess) return he;
     }
-    if (loop_st != NLTE_OK) break;
+    return hipSuccess;
+  };
+  while (step < max_steps) {
+    const bool timing = block >= 1 && tune_next < 3;
+    if (timing && bw.formal_wpb != wpb_try[tune_next]) {
+      bw.formal_wpb = wpb_try[tune_next];
+      G.drop();  // captured with another shape
+    }
+    if (timing) HIP_TRY(hipEventRecord(G.t0, s));
+    hipError_t he = hipSuccess;
+    if (use_graph) {
+      if (!G.exec) {
+        he = hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal);
+        if (he == hipSuccess) {
+          const hipError_t le = launch_block(G.cap, false);
+          hipGraph_t g = nullptr;
+          he = hipStreamEndCapture(G.cap, &g);
+          G.graph = g;
+          if (he == hipSuccess) he = le;
+        }
+        if (he == hipSuccess) he = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0);
+        G.captures += 1;
+      }
+      if (he == hipSuccess) he = hipGraphLaunch(G.exec, s);
+    } else {
+      he = launch_block(s, prof);
+    }
+    if (he != hipSuccess) {
+      loop_st = set_err(NLTE_E_DEVICE, "solver launch failed: %s", hipGetErrorString(he));
+      break;
+    }
+    if (timing) HIP_TRY(hipEventRecord(G.t1, s));
+    step += check_every;
+    block += 1;
     HIP_TRY(hipMemcpyAsync(b.done_host, b.done, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (timing) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, G.t0, G.t1));
+      tune_ms[tune_next] = ms / check_every;
+      if (++tune_next == 3) {
+        int best = 0;
+        for (int i = 1; i < 3; ++i)
+          if (tune_ms[i] < tune_ms[best]) best = i;
+        if (bw.formal_wpb != wpb_try[best]) {
+          bw.formal_wpb = wpb_try[best];
+          G.drop();
+        }
+      }
+    }
     if (prof) {
       for (int r = 0; r < check_every; ++r) {
         float t[5], tf;
@@ -1244,9 +1338,14 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
       bw.act = b.act;
       bw.nact = (int)live.size();
       nlisted = (int)live.size();
+      G.drop();  // the lists changed: capture again
       HIP_TRY(hipStreamSynchronize(s));  // host vectors are reused by the next rebuild
     }
   }
+  ctx->prof.last_graph = use_graph ? 1 : 0;
+  ctx->prof.last_formal_wpb = bw.formal_wpb;
+  for (int i = 0; i < 3; ++i) ctx->prof.last_tune_ms[i] = tune_ms[i];
+  ctx->prof.last_captures = G.captures;
   for (auto& e : ev) hipEventDestroy(e);
   if (loop_st != NLTE_OK) return loop_st;
   k_copy_out<<<ncol, 256, 0, s>>>(b.cols, b.nout);

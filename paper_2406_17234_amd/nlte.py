@@ -59,7 +59,7 @@ class SolveOpts(C.Structure):
                 ("max_halvings", C.c_int32), ("init", C.c_int32), ("eps_scale", C.c_double),
                 ("max_krylov_total", C.c_int32), ("fp64_fallback", C.c_int32),
                 ("krylov_method", C.c_int32),
-                ("jv_method", C.c_int32), ("krylov_x0", C.c_int32), ("pad_opts", C.c_int32)]
+                ("jv_method", C.c_int32), ("krylov_x0", C.c_int32), ("launch", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -76,10 +76,17 @@ class Profile(C.Structure):
     _fields_ = [("steps", C.c_int64), ("formal_launches", C.c_int64), ("formal_ms", C.c_double),
                 ("depth_ms", C.c_double), ("assemble_ms", C.c_double), ("solver_ms", C.c_double),
                 ("opacity_ms", C.c_double), ("formal_f_launches", C.c_int64),
-                ("formal_f_ms", C.c_double)]
+                ("formal_f_ms", C.c_double), ("last_graph", C.c_int32),
+                ("last_formal_wpb", C.c_int32), ("last_tune_ms", C.c_double * 3),
+                ("last_captures", C.c_int32), ("pad_profile", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("last_tune_ms", "pad_profile")}
+        d["last_tune_ms"] = list(self.last_tune_ms)
+        return d
+
+
+NLTE_SOLVE_GRAPH, NLTE_SOLVE_TUNE = 1, 2
 
 
 class PlanInfo(C.Structure):
@@ -108,7 +115,7 @@ class ServerResult(C.Structure):
 class ServerInfo(C.Structure):
     _fields_ = [("steps", C.c_int64), ("submitted", C.c_int64), ("completed", C.c_int64),
                 ("active", C.c_int32), ("queued", C.c_int32), ("active_bytes", C.c_int64),
-                ("busy_ms", C.c_double)]
+                ("busy_ms", C.c_double), ("peak_active_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -165,6 +172,9 @@ def lib():
         L.nlte_server_create.argtypes = [vp, C.c_size_t, C.c_int32, C.POINTER(SolveOpts),
                                          C.POINTER(vp)]
         L.nlte_server_submit.argtypes = [vp, vp, vp, C.POINTER(C.c_uint64)]
+        L.nlte_server_submit_problem.argtypes = [vp, C.POINTER(AtmosDesc), C.POINTER(AtomDesc),
+                                                 C.POINTER(GridDesc), _dp, C.c_int, vp,
+                                                 C.POINTER(C.c_uint64)]
         L.nlte_server_poll.argtypes = [vp, C.c_uint64, vp, C.POINTER(ServerResult)]
         L.nlte_server_drain.argtypes = [vp, C.c_double]
         L.nlte_server_info_get.argtypes = [vp, C.POINTER(ServerInfo)]
@@ -432,6 +442,17 @@ class Server:
         t = C.c_uint64()
         _check(lib().nlte_server_submit(self.h, column.h, _ptr(n0), C.byref(t)))
         self._keep[t.value] = (column, n0)
+        return t.value
+
+    def submit_problem(self, problem, n_out, precision: int = FP64) -> int:
+        """Queue a problem whose column the server creates at admission and
+        destroys at retirement; the populations land in ``n_out`` (a device
+        tensor [nz][nlev] kept alive until the ticket is polled)."""
+        atm, atom, grid, cup, keep = _descriptors(problem)
+        t = C.c_uint64()
+        _check(lib().nlte_server_submit_problem(self.h, C.byref(atm), C.byref(atom), C.byref(grid),
+                                                cup, int(precision), _ptr(n_out), C.byref(t)))
+        self._keep[t.value] = (n_out,)
         return t.value
 
     def poll(self, ticket: int, out=None):

@@ -73,5 +73,5 @@ def test_solve_opts_layout_matches_defaults():
     assert (o.max_krylov_total, o.fp64_fallback) == (0, 0)
     assert o.krylov_method == nlte.KRYLOV_GMRES
     assert o.jv_method == nlte.JV_FD
-    assert (o.krylov_x0, o.pad_opts) == (0, 0)
+    assert (o.krylov_x0, o.launch) == (0, 0)
     assert ctypes.sizeof(o) == 72
