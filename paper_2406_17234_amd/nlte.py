@@ -291,6 +291,15 @@ def _descriptors(problem):
     return atm, atom, grid, cup, keep
 
 
+class Prepared:
+    """The descriptor structs of a problem and the arrays behind them, built
+    once (e.g. before a timed window) and passed to calls that take
+    descriptors."""
+
+    def __init__(self, problem):
+        self.atm, self.atom, self.grid, self.cup, self._keep = _descriptors(problem)
+
+
 def plan_bytes(problem, precision: int = FP64) -> int:
     """Device bytes a column of this problem would own (host-only validation
     and sizing, nlte_column_plan_bytes); raises NLTEError on bad input."""
@@ -447,11 +456,13 @@ class Server:
     def submit_problem(self, problem, n_out, precision: int = FP64) -> int:
         """Queue a problem whose column the server creates at admission and
         destroys at retirement; the populations land in ``n_out`` (a device
-        tensor [nz][nlev] kept alive until the ticket is polled)."""
-        atm, atom, grid, cup, keep = _descriptors(problem)
+        tensor [nz][nlev] kept alive until the ticket is polled).  ``problem``
+        may be a Prepared (descriptors built beforehand)."""
+        prep = problem if isinstance(problem, Prepared) else Prepared(problem)
         t = C.c_uint64()
-        _check(lib().nlte_server_submit_problem(self.h, C.byref(atm), C.byref(atom), C.byref(grid),
-                                                cup, int(precision), _ptr(n_out), C.byref(t)))
+        _check(lib().nlte_server_submit_problem(self.h, C.byref(prep.atm), C.byref(prep.atom),
+                                                C.byref(prep.grid), prep.cup, int(precision),
+                                                _ptr(n_out), C.byref(t)))
         self._keep[t.value] = (n_out,)
         return t.value
 
