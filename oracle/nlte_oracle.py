@@ -99,6 +99,8 @@ def setup(prob):
     up = a.tr_up()
     tr = []
     w_nu = getattr(gr, "w_nu", None)
+    vel = getattr(atm, "vlos", None)
+    vel = None if vel is None else np.asarray(vel, dtype=float)
     for t in range(ntr):
         f0, f1 = int(gr.win_lo[t]), int(gr.win_hi[t])
         nuw = nu[f0:f1]
@@ -116,6 +118,19 @@ def setup(prob):
             V = HP * nuw[None, :] / (4.0 * np.pi) * B_lu * phi
             gt = np.full((nz, f1 - f0), a.g[l] / a.g[u])
             extra = dict(phi=phi, B_lu=B_lu, nu0=nu0)
+            if vel is not None:
+                # the profile each ray sees, Doppler-shifted by the velocity
+                # component along it (Sect. 3.5): centre nu0 (1 + s v / c)
+                # with s = +mu for the outgoing and -mu for the ingoing ray of
+                # an angle; normalised per (ray, depth) on the window
+                phir = np.empty((2 * gr.nmu, nz, f1 - f0))
+                for r in range(2 * gr.nmu):
+                    sgn = 1.0 if r < gr.nmu else -1.0
+                    proj = sgn * gr.mu[r % gr.nmu] * vel
+                    vr = (nuw[None, :] - nu0 * (1.0 + proj[:, None] / CL)) / dnuD[:, None]
+                    pr = voigt_H(a.a_damp[t], vr) / (SQRT_PI * dnuD[:, None])
+                    phir[r] = pr / (pr * w[None, :]).sum(axis=1, keepdims=True)
+                extra.update(phir=phir, Vr=HP * nuw[None, None, :] / (4.0 * np.pi) * B_lu * phir)
         else:
             e = t - nline
             alpha = np.interp(nuw, gr.bf_nu[e], gr.bf_alpha[e])
@@ -137,7 +152,8 @@ def setup(prob):
                            chi_c=chi_c, eta_c=eta_c, chi_sca=atm.chi_sca.copy(),
                            ntot=atm.ntot.copy(), z=atm.z.copy(), dz=dz,
                            mu=gr.mu.copy(), w_mu=gr.w_mu.copy(),
-                           two_h_nu3_c2=2.0 * HP * nu ** 3 / CL ** 2)
+                           two_h_nu3_c2=2.0 * HP * nu ** 3 / CL ** 2,
+                           vel=vel is not None, nray=2 * gr.nmu)
 
 
 # ----------------------------------------------------------------------------
@@ -288,8 +304,10 @@ def residual(tb, n, Jdag=None, rows=None, want_P=False, I_override=None):
     Jdag: lagged mean intensity [nz, nnu] for the scattering emissivity
     (default B_nu(T)); rows: conservation rows (default: most populated level
     of n); want_P: also build the block-Jacobi preconditioner; I_override:
-    replace the formal solution by a given intensity field (used to test the
-    rate equations on their own).
+    replace the formal solution by a given isotropic intensity field [nz, nnu]
+    (used to test the rate equations on their own).  With a velocity field
+    (Sect. 3.5) the opacity, the formal solution and the line rates are taken
+    ray by ray (residual_rays).
     Returns a namespace with F, rho (scaled residual), J, R_lu, R_ul, Jbar,
     rows and optionally P [nz, nlev, nlev].
     """
@@ -297,6 +315,8 @@ def residual(tb, n, Jdag=None, rows=None, want_P=False, I_override=None):
         Jdag = tb.B
     if rows is None:
         rows = conservation_rows(n)
+    if tb.vel:
+        return residual_rays(tb, n, Jdag, rows, want_P, I_override)
     chi, eta = opacity(tb, n, Jdag)
     S = eta / chi
     if I_override is None:
@@ -313,6 +333,127 @@ def residual(tb, n, Jdag=None, rows=None, want_P=False, I_override=None):
     if want_P:
         out.P = preconditioner(tb, n, R_lu, R_ul, rows, chi, S, Ip, Im, co)
     return out
+
+
+# ----------------------------------------------------------------------------
+# atmospheres with a velocity field (Sect. 3.5): opacity per ray
+# ----------------------------------------------------------------------------
+
+def ray_weights(tb):
+    """Angle weight w_m / 2 of each ray: rays 0..nmu-1 outgoing (+mu_m),
+    nmu..2 nmu-1 ingoing (-mu_m)."""
+    return np.concatenate([0.5 * tb.w_mu, 0.5 * tb.w_mu])
+
+
+def opacity_rays(tb, n, Jdag):
+    """Eqs. chi and eta for every ray: the lines use the profile the ray sees
+    (Doppler-shifted by the velocity along it); the background and the
+    bound-free terms do not depend on the ray.  [nray, nz, nnu] each."""
+    dt = np.result_type(n, float)
+    chi0 = (tb.chi_c + tb.chi_sca[:, None]).astype(dt)
+    eta0 = (tb.eta_c + tb.chi_sca[:, None] * Jdag).astype(dt)
+    for tr in tb.tr[tb.nline:]:
+        nl = n[:, tr.lo][:, None]
+        nu_ = n[:, tr.up][:, None]
+        chi0[:, tr.f0:tr.f1] += tr.V * (nl - tr.g * nu_)
+        eta0[:, tr.f0:tr.f1] += tb.two_h_nu3_c2[None, tr.f0:tr.f1] * tr.g * tr.V * nu_
+    chi = np.repeat(chi0[None], tb.nray, axis=0)
+    eta = np.repeat(eta0[None], tb.nray, axis=0)
+    for tr in tb.tr[:tb.nline]:
+        nl = n[:, tr.lo][None, :, None]
+        nu_ = n[:, tr.up][None, :, None]
+        chi[:, :, tr.f0:tr.f1] += tr.Vr * (nl - tr.g[None] * nu_)
+        eta[:, :, tr.f0:tr.f1] += tb.two_h_nu3_c2[None, None, tr.f0:tr.f1] * tr.g[None] * tr.Vr * nu_
+    return chi, eta
+
+
+def formal_rays(tb, chi, S):
+    """The formal solution of Eqs. Iplus/Iminus along every ray with that
+    ray's own opacity and source function.  Returns I [nray, nz, nnu] and the
+    segment coefficients of each ray."""
+    I = np.empty(chi.shape, dtype=np.result_type(chi, S, float))
+    co = []
+    for r in range(tb.nray):
+        m = r % tb.nmu
+        Ip, Im, c = formal_solution(chi[r], S[r], tb.z, tb.mu[m:m + 1], tb.B[-1], want_coeffs=True)
+        I[r] = (Ip if r < tb.nmu else Im)[:, :, 0]
+        co.append((Ip, Im, c))
+    return I, co
+
+
+def residual_rays(tb, n, Jdag, rows, want_P, I_override=None):
+    """F(n) of Algorithm 1 with a velocity field: the rates (Eqs. Rij, Rji)
+    keep their angle integral, sum over rays of (w_m/2) V_ray I_ray, since V
+    depends on the ray; J (background scattering, outputs) and the
+    profile-averaged intensity Jbar are the same angle sums.  I_override
+    [nz, nnu]: the intensity of every ray (no formal solution, no P)."""
+    chi, eta = opacity_rays(tb, n, Jdag)
+    S = eta / chi
+    if I_override is None:
+        I, co = formal_rays(tb, chi, S)
+    else:
+        if want_P:
+            raise ValueError("want_P needs the formal solution")
+        I = np.repeat(np.asarray(I_override)[None], tb.nray, axis=0)
+        co = None
+    wr = ray_weights(tb)
+    J = (wr[:, None, None] * I).sum(axis=0)
+    dt = np.result_type(J, float)
+    R_lu = np.zeros((tb.nz, tb.ntr), dtype=dt)
+    R_ul = np.zeros((tb.nz, tb.ntr), dtype=dt)
+    Jbar = np.zeros((tb.nz, tb.nline), dtype=dt)
+    for tr in tb.tr:
+        Iw = I[:, :, tr.f0:tr.f1]
+        if tr.is_line:
+            VI = (wr[:, None, None] * tr.Vr * Iw).sum(axis=0)
+            Vbar = (wr[:, None, None] * tr.Vr).sum(axis=0)
+            R_lu[:, tr.t] = (tr.c[None, :] * VI).sum(axis=1)
+            R_ul[:, tr.t] = (tr.c[None, :] * tr.g *
+                             (tb.two_h_nu3_c2[None, tr.f0:tr.f1] * Vbar + VI)).sum(axis=1)
+            Jbar[:, tr.t] = (tr.w[None, :] * (wr[:, None, None] * tr.phir * Iw).sum(axis=0)).sum(axis=1)
+        else:
+            Jw = J[:, tr.f0:tr.f1]
+            cV = tr.c[None, :] * tr.V
+            R_lu[:, tr.t] = (cV * Jw).sum(axis=1)
+            R_ul[:, tr.t] = (cV * tr.g * (tb.two_h_nu3_c2[None, tr.f0:tr.f1] + Jw)).sum(axis=1)
+    F, G = assemble_F(tb, n, R_lu, R_ul, rows)
+    out = SimpleNamespace(F=F, G=G, rho=np.abs(F) / G, J=J, R_lu=R_lu, R_ul=R_ul, Jbar=Jbar,
+                          rows=rows, chi=chi, S=S, I=I)
+    if want_P:
+        out.P = preconditioner_rays(tb, n, R_lu, R_ul, rows, chi, S, co)
+    return out
+
+
+def preconditioner_rays(tb, n, R_lu, R_ul, rows, chi, S, co):
+    """The diagonal blocks of Sect. 2.5.1/2.5.2 (first solution) with a
+    velocity field: the local derivative of each ray's intensity (App. A.2,
+    with that ray's chi and S) times the ray's own alpha, beta, gamma."""
+    nz, L = tb.nz, tb.nlev
+    P = np.zeros((nz, L, L), dtype=np.result_type(n, float))
+    for t in range(tb.ntr):
+        l, u = tb.lo[t], tb.up[t]
+        r_lu = tb.C_lu[:, t] + R_lu[:, t]
+        r_ul = tb.C_ul[:, t] + R_ul[:, t]
+        P[:, l, l] += r_lu
+        P[:, u, u] += r_ul
+        P[:, l, u] -= r_ul
+        P[:, u, l] -= r_lu
+    wr = ray_weights(tb)
+    for r in range(tb.nray):
+        m = r % tb.nmu
+        Ip, Im, c = co[r]
+        a_chi, a_eta, c_chi, c_eta = intensity_derivatives(chi[r], S[r], Ip, Im, c, tb.dz,
+                                                           tb.mu[m:m + 1])
+        if r < tb.nmu:
+            Dchi, Deta = a_chi[:, :, 0], a_eta[:, :, 0]
+        else:
+            Dchi, Deta = c_chi[:, :, 0], c_eta[:, :, 0]
+        alpha, beta, gamma = level_coefficients(tb, n, ray=r)
+        X = beta * Dchi[:, :, None] + gamma * Deta[:, :, None]
+        P += wr[r] * np.einsum("kfi,kfj->kij", alpha, X)
+    k = np.arange(nz)
+    P[k, rows, :] = -1.0
+    return P
 
 
 # ----------------------------------------------------------------------------
@@ -345,9 +486,10 @@ def intensity_derivatives(chi, S, Ip, Im, co, dz, mu):
     return a_chi, a_eta, c_chi, c_eta
 
 
-def level_coefficients(tb, n):
+def level_coefficients(tb, n, ray=None):
     """alpha_i (times the rate quadrature weight), beta_j = d chi / d n_j and
-    gamma_j = d eta / d n_j of Sect. 2.5.1, each [nz, nnu, nlev]."""
+    gamma_j = d eta / d n_j of Sect. 2.5.1, each [nz, nnu, nlev]; with a
+    velocity field, those of one ray (its line profiles)."""
     dt = np.result_type(n, float)
     shape = (tb.nz, tb.nnu, tb.nlev)
     alpha = np.zeros(shape, dtype=dt)
@@ -355,13 +497,14 @@ def level_coefficients(tb, n):
     gamma = np.zeros(shape)
     for tr in tb.tr:
         sl = slice(tr.f0, tr.f1)
-        A = tr.V * (n[:, tr.lo][:, None] - tr.g * n[:, tr.up][:, None])
+        V = tr.Vr[ray] if (ray is not None and tr.is_line) else tr.V
+        A = V * (n[:, tr.lo][:, None] - tr.g * n[:, tr.up][:, None])
         cA = tr.c[None, :] * A
         alpha[:, sl, tr.lo] += cA
         alpha[:, sl, tr.up] -= cA
-        beta[:, sl, tr.lo] += tr.V
-        beta[:, sl, tr.up] -= tr.g * tr.V
-        gamma[:, sl, tr.up] += tb.two_h_nu3_c2[None, sl] * tr.g * tr.V
+        beta[:, sl, tr.lo] += V
+        beta[:, sl, tr.up] -= tr.g * V
+        gamma[:, sl, tr.up] += tb.two_h_nu3_c2[None, sl] * tr.g * V
     return alpha, beta, gamma
 
 
@@ -614,12 +757,19 @@ def fd_step(N, vnorm, eps_mach=2.0 ** -52):
     return math.sqrt(eps_mach) * math.sqrt(1.0 + math.sqrt(N)) / vnorm
 
 
-def positivity_limit(n, dn, frac=0.9):
-    """Per-depth limiter keeping n + dn positive (Sect. 2.2.2): lambda_k =
-    min(1, frac * min_{dn_i<0} n_i / |dn_i|)."""
+def positivity_limit(n, dn, factor=3.0):
+    """Per-depth limit of the Newton correction (Sect. 2.2.2, which limits the
+    correction at each depth independently and leaves the form open): the
+    factor lambda_k <= 1 of depth k keeps every level of n + lambda_k dn
+    within [n / factor, factor n], i.e. lambda_k = min(1,
+    (1 - 1/factor) min_{dn_i<0} n_i/|dn_i|, (factor - 1) min_{dn_i>0} n_i/dn_i).
+    Positive populations stay positive, and no level moves by more than the
+    factor in one step."""
     with np.errstate(divide="ignore", invalid="ignore"):
-        r = np.where(dn < 0.0, n / -dn, np.inf)
-    return np.minimum(1.0, frac * r.min(axis=1))
+        r_neg = np.where(dn < 0.0, n / -dn, np.inf)
+        r_pos = np.where(dn > 0.0, n / dn, np.inf)
+    lam = np.minimum(1.0, (1.0 - 1.0 / factor) * r_neg.min(axis=1))
+    return np.minimum(lam, (factor - 1.0) * r_pos.min(axis=1))
 
 
 def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,

@@ -298,10 +298,18 @@ __device__ void start_cycle(const ColDev& C, bool first, double* red, int* done_
 __device__ void begin_linesearch(const ColDev& C) {
   ColState* st = C.st;
   const int L = C.L;
+  // per-depth limit (Sect. 2.2.2): with u = dn / n, every level of
+  // n (1 + lambda u) stays within [n / 3, 3 n]
   for (int k = threadIdx.x; k < C.nz; k += kThreads) {
-    double worst = 0.0;
-    for (int i = 0; i < L; ++i) worst = fmax(worst, -C.xk[k * L + i]);
-    C.lam[k] = worst > 0.0 ? fmin(1.0, 0.9 / worst) : 1.0;
+    double dec = 0.0, inc = 0.0;
+    for (int i = 0; i < L; ++i) {
+      dec = fmax(dec, -C.xk[k * L + i]);
+      inc = fmax(inc, C.xk[k * L + i]);
+    }
+    double lam = 1.0;
+    if (dec > 0.0) lam = fmin(lam, (2.0 / 3.0) / dec);
+    if (inc > 0.0) lam = fmin(lam, 2.0 / inc);
+    C.lam[k] = lam;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < C.N; i += kThreads)

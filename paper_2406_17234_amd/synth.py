@@ -98,6 +98,7 @@ class Atmos:
     chi_c: np.ndarray    # [nz] gray background opacity, cm^-1
     chi_sca: np.ndarray  # [nz] background scattering opacity, cm^-1 (zeros = none)
     eta_c: np.ndarray | None = None  # [nz, nnu] thermal background emissivity (None: chi_c B_nu)
+    vlos: np.ndarray | None = None   # [nz] vertical velocity, cm/s, positive upwards (None: static)
 
     @property
     def nz(self):
@@ -268,12 +269,14 @@ def chromosphere_T(h_km):
 def chromosphere(nz: int = 82, nH0: float = 1e17, abund: float = 1e-6,
                  h_top_km: float = 2000.0, h_bot_km: float = -100.0,
                  perturb_seed: int | None = None, perturb_amp: float = 0.1,
-                 thomson: bool = False) -> Atmos:
+                 thomson: bool = False, h_km: np.ndarray | None = None) -> Atmos:
     """Chromosphere-like column: temperature minimum of 4400 K near 500 km,
     1e4 K at 2000 km, hydrostatic hydrogen density, LTE hydrogen electrons.
 
     With ``perturb_seed`` the temperature is multiplied by (1 + amp*xi(h)), xi
     a clipped sum of three random sinusoids, and the density re-derived.
+    Depths: ``nz`` heights evenly spaced from the top down, or the decreasing
+    heights ``h_km`` (then ``nz`` is ignored).
     """
     hf = np.linspace(h_bot_km, h_top_km, 8401)
     Tf = chromosphere_T(hf)
@@ -297,7 +300,8 @@ def chromosphere(nz: int = 82, nH0: float = 1e17, abund: float = 1e-6,
     above = hf >= 0.0
     col = np.trapezoid(nHf[above], hf[above]) * 1e5
     sigma_c = 1.0 / col
-    h = np.linspace(h_top_km, h_bot_km, nz)
+    h = np.linspace(h_top_km, h_bot_km, nz) if h_km is None else np.asarray(h_km, dtype=float)
+    nz = len(h)
     T = np.interp(h, hf, Tf)
     nH = np.exp(np.interp(h, hf, np.log(nHf)))
     ne = nH * (1e-4 + _hydrogen_ion_fraction(T, nH))
@@ -316,11 +320,14 @@ def gauss_legendre_01(nmu: int):
 
 
 def make_grid(atom: Atom, atmos: Atmos, n_line_pts, n_bf_pts, nmu: int,
-              q_max: float = 50.0) -> Grid:
+              q_max: float = 50.0, v_max: float = 0.0) -> Grid:
     """Union frequency grid of all transitions' own sub-grids.
 
     Line sub-grid: odd count, v = q_max * sign(t) t^2 with t uniform on [-1, 1],
-    in Doppler widths at the column's minimum temperature.  Edge sub-grid:
+    in Doppler widths at the column's minimum temperature; with a velocity
+    field of largest speed ``v_max`` (cm/s) also points every quarter Doppler
+    width out to v_max / v_D + 3 Doppler widths on both sides of the centre,
+    so that the Doppler-shifted cores are resolved.  Edge sub-grid:
     geometric from nu0 (1 + 1e-9) to 3 nu0; the edge's cross-section is
     tabulated there as alpha0 (nu0/nu)^3.  Points closer than 1e-12 relative
     are merged.  A transition's window is the run of union points inside the
@@ -339,6 +346,10 @@ def make_grid(atom: Atom, atmos: Atmos, n_line_pts, n_bf_pts, nmu: int,
         s = np.linspace(-1.0, 1.0, npt)
         v = q_max * np.sign(s) * s * s
         dnu = nu0[t] * _doppler_rel(Tmin, atom.mass_amu, atom.vturb)
+        if v_max > 0.0:
+            reach = v_max / (C_LIGHT * _doppler_rel(Tmin, atom.mass_amu, atom.vturb)) + 3.0
+            core = np.arange(-np.floor(4.0 * reach), np.floor(4.0 * reach) + 1.0) / 4.0
+            v = np.unique(np.concatenate([v, core[np.abs(core) < q_max]]))
         sub = nu0[t] + v * dnu
         subs.append(sub)
         spans.append((sub[0], sub[-1]))
@@ -418,6 +429,48 @@ def chromo6(nz: int = 82, nmu: int = 5, seed: int = 2, nnu: int = 600,
     nl, nb = _split_points(nnu, 5, 5)
     grid = make_grid(atom, atm, nl, nb, nmu)
     return Problem("chromo6", atom, atm, grid, make_collisions(atom, atm), seed)
+
+
+def velocity_step(h_km, v_jump_kms: float = 5.0, h0_km: float = 1000.0,
+                  width_km: float = 50.0):
+    """Vertical velocity (cm/s, positive upwards) that rises smoothly by
+    v_jump around height h0: a sharp positive gradient at the base of the
+    chromosphere (Sect. 3.5)."""
+    h = np.asarray(h_km, dtype=float)
+    return 1e5 * v_jump_kms * 0.5 * (1.0 + np.tanh((h - h0_km) / width_km))
+
+
+def optimised_heights(atm_fine: Atmos, h_fine_km, vel_fine, nz: int, v_dopp: float):
+    """Depth optimisation extended to velocity gradients (Sect. 3.5): nz
+    heights placed at equal steps of the combined change of log continuum
+    optical depth, log temperature, log density and velocity along a fine
+    model (steps of 0.1 dex, 0.01 dex, 0.1 dex and v_dopp / 5 weigh the
+    same; the optical depth counted from chi_c x 1000 km at the top).
+    Returns decreasing heights, top and bottom kept."""
+    z = atm_fine.z
+    tau = np.concatenate([[0.0], np.cumsum(0.5 * (atm_fine.chi_c[1:] + atm_fine.chi_c[:-1]) * np.diff(z))])
+    tau += atm_fine.chi_c[0] * 1e8
+    d = np.sqrt((np.diff(np.log10(tau)) / 0.1) ** 2 + (np.diff(np.log10(atm_fine.T)) / 0.01) ** 2
+                + (np.diff(np.log10(atm_fine.nH)) / 0.1) ** 2 + (np.diff(vel_fine) / (0.2 * v_dopp)) ** 2)
+    s = np.concatenate([[0.0], np.cumsum(d)])
+    return np.interp(np.linspace(0.0, s[-1], nz), s, h_fine_km)
+
+
+def chromo6_vel(nz: int = 82, nmu: int = 5, seed: int = 2, nnu: int = 600,
+                v_jump_kms: float = 5.0) -> Problem:
+    """chromo6's atom in the chromosphere with a velocity step of v_jump
+    (upwards above 1000 km), on depths optimised for the gradients and a
+    frequency grid that resolves the shifted cores (Sect. 3.5)."""
+    atom = make_atom(6, 5, seed, name="atom6")
+    h_fine = np.linspace(2000.0, -100.0, 4201)
+    fine = chromosphere(abund=ABUND[6], h_km=h_fine)
+    v_dopp = C_LIGHT * _doppler_rel(float(np.min(fine.T)), atom.mass_amu, atom.vturb)
+    h = optimised_heights(fine, h_fine, velocity_step(h_fine, v_jump_kms), nz, v_dopp)
+    atm = chromosphere(abund=ABUND[6], h_km=h)
+    atm.vlos = velocity_step(h, v_jump_kms)
+    nl, nb = _split_points(nnu, 5, 5)
+    grid = make_grid(atom, atm, nl, nb, nmu, v_max=float(np.max(np.abs(atm.vlos))))
+    return Problem("chromo6_vel", atom, atm, grid, make_collisions(atom, atm), seed)
 
 
 def chromo11(nz: int = 256, nmu: int = 8, seed: int = 5) -> Problem:
