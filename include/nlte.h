@@ -90,6 +90,18 @@ typedef struct {
   const double *eta_c;     /* [nz][nnu] thermal background emissivity
                               (erg s^-1 cm^-3 Hz^-1 sr^-1, finite, >= 0; nnu of
                               the grid descriptor) or NULL: chi_c B_nu(T)     */
+  const double *vlos;      /* [nz] vertical gas velocity, cm/s, positive
+                              outwards (towards depth 0, the observer), finite,
+                              |v| < c/10; or NULL: static.  Sect. 3.5: each ray
+                              sees the line profiles Doppler-shifted to
+                              nu0 (1 + s mu v / c), s = +1 outgoing, -1 ingoing,
+                              normalised per ray and depth on the window, so
+                              opacity, formal solution and line rates are
+                              taken ray by ray.  Columns with a velocity
+                              field are FP64 (no NLTE_FP32_FORM), sequential
+                              (no NLTE_DEPTH_SCAN) and take forward-difference
+                              products only (no NLTE_JV_TANGENT); otherwise
+                              NLTE_E_INVALID.                                 */
 } nlte_atmos_desc;
 
 /* Model atom, Sect. 2.1.1.  If nbf > 0 the last level is the continuum
@@ -461,6 +473,13 @@ nlte_status nlte_profile_read(const nlte_ctx *ctx, nlte_profile *out);
 
 /* Message describing the last non-OK status returned on this thread. */
 const char *nlte_last_error(void);
+
+/* Size in bytes of the public structure named `name` ("nlte_atmos_desc",
+ * "nlte_atom_desc", "nlte_grid_desc", "nlte_solve_opts", "nlte_solve_stats",
+ * "nlte_profile", "nlte_plan_info", "nlte_server_result", "nlte_server_info")
+ * as this library was compiled, or -1 for another name.  Host only; lets a
+ * binding check its own layouts against the library's. */
+int32_t nlte_struct_size(const char *name);
 
 /* Voigt function H(a, v) evaluated on the host with the same routine the
  * device setup uses (Taylor expansion about the real axis with Rybicki's

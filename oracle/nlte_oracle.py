@@ -797,6 +797,9 @@ def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
     difference of Eq. fordif would otherwise pick up the change of J-dagger
     between its two terms).
 
+    A line search that ends on a non-finite merit (every trial failed, the
+    last one overflowed) stops the solve with status "nonfinite".
+
     Returns a namespace with n, J (the J-dagger of the final F: with it,
     F(n; J) is the residual the stopping test saw; without scattering F does
     not depend on it and it is the J of the final evaluation), history and
@@ -814,6 +817,7 @@ def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
     converged = res.rho.max() <= ftol
     it = 0
     stalls = 0
+    status = None
     N = n.size
     while not converged and it < maxiter:
         rows = res.rows
@@ -855,6 +859,11 @@ def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
                 stalls += 1
                 break
             alpha *= 0.5
+        if not np.isfinite(phi):
+            # every trial failed and the last one is not even finite (an
+            # inverted line turned the opacity negative): stop, n unchanged
+            status = "nonfinite"
+            break
         n_prev = n
         n = trial
         res = residual(tb, n, Jdag=Jdag, want_P=True)
@@ -870,8 +879,10 @@ def solve(tb, n0=None, init="lte", ftol=1e-8, rtol=1e-3, maxiter=50, m=30,
             print(f"newton {it}: rho={res.rho.max():.3e} dn={dnorm:.3e} "
                   f"krylov={kit} alpha={alpha}")
         converged = res.rho.max() <= ftol
+    if status is None:
+        status = "converged" if converged else "maxiter"
     return SimpleNamespace(n=n, J=Jdag, res=res, iters=it, calls=calls,
-                           converged=converged, history=hist, stalls=stalls)
+                           converged=converged, history=hist, stalls=stalls, status=status)
 
 
 def dense_newton(tb, n0, ftol=1e-12, maxiter=30, verbose=False):

@@ -175,6 +175,7 @@ struct SetupIn {
   const double *w_nu;  // caller frequency weights [nnu] or NULL (trapezoid per window)
   const int *stage, *bf_ptr;
   double mass_amu, vturb;
+  double mu[kMaxMu];   // angle cosines (Doppler shifts of the rays)
 };
 
 bool finite_all(const double* p, size_t n) {
@@ -319,6 +320,66 @@ __global__ void k_setup_norm(ColDev C, SetupIn in) {
   ((double*)C.Rsp)[k * C.ntr + t] = rsp;
 }
 
+// Velocity fields (Sect. 3.5).  Per (ray, k, line window point): raw Voigt
+// value of the profile the ray sees, centred on nu0 (1 + s mu v_k / c),
+// s = +1 for the outgoing rays 0..nmu-1 and -1 for the ingoing ones.
+__global__ void k_setup_voigt_vel(ColDev C, SetupIn in, const int* __restrict__ lbase, int ltotal) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)ltotal * C.nz * C.nray) return;
+  const int j = (int)(i % ltotal);
+  const size_t rest = i / ltotal;
+  const int k = (int)(rest % C.nz), r = (int)(rest / C.nz);
+  int t = 0;
+  while (t + 1 < C.nline && lbase[t + 1] <= j) ++t;
+  const TrDev T = C.tr[t];
+  const int fl = j - lbase[t];
+  const int wl = T.whi - T.wlo;
+  const double nu0 = (in.E[T.up] - in.E[T.lo]) / kH;
+  const double dnuD = nu0 / kC * sqrt(2.0 * kK * C.T[k] / (in.mass_amu * kAmu) + in.vturb * in.vturb);
+  const double s = r < C.nmu ? 1.0 : -1.0;
+  const double proj = s * in.mu[r < C.nmu ? r : r - C.nmu] * C.vlos[k];
+  const double v = (C.nu[T.wlo + fl] - nu0 * (1.0 + proj / kC)) / dnuD;
+  ((double*)C.VR)[(size_t)C.nray * T.voff + ((size_t)r * C.nz + k) * wl + fl] = voigt_H(in.a_damp[t], v);
+}
+
+// Per (line, ray, k): normalisation of the ray's profile on the window and
+// V = (h nu / 4 pi) B_lu phi_ray.
+__global__ void k_setup_norm_vel(ColDev C, SetupIn in) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= C.nline * C.nray * C.nz) return;
+  const int t = i / (C.nray * C.nz), rk = i % (C.nray * C.nz);
+  const TrDev T = C.tr[t];
+  const int wl = T.whi - T.wlo;
+  double* phi = (double*)C.VR + (size_t)C.nray * T.voff + (size_t)rk * wl;
+  double s = 0.0;
+  for (int fl = 0; fl < wl; ++fl) {
+    const int f = T.wlo + fl;
+    const int fm = max(f - 1, T.wlo), fp = min(f + 1, T.whi - 1);
+    s += (in.w_nu ? in.w_nu[f] : 0.5 * (C.nu[fp] - C.nu[fm])) * phi[fl];
+  }
+  for (int fl = 0; fl < wl; ++fl)
+    phi[fl] = kH * C.nu[T.wlo + fl] / (4.0 * kPi) * T.Blu * (phi[fl] / s);
+}
+
+// Per (line, k): the n-independent part of R_ul with the angle integral
+// inside, sum_f cw (2 h nu^3/c^2) sum_rays (w_m/2) V_ray (replaces the
+// static value written by k_setup_norm).
+__global__ void k_setup_rsp_vel(ColDev C) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= C.nline * C.nz) return;
+  const int t = i / C.nz, k = i % C.nz;
+  const TrDev T = C.tr[t];
+  const int wl = T.whi - T.wlo;
+  const double* V = C.VR + (size_t)C.nray * T.voff + (size_t)k * wl;
+  double rsp = 0.0;
+  for (int fl = 0; fl < wl; ++fl) {
+    double vb = 0.0;
+    for (int r = 0; r < C.nray; ++r) vb += C.wm2[r < C.nmu ? r : r - C.nmu] * V[(size_t)r * C.nz * wl + fl];
+    rsp += C.cw[T.cwoff + fl] * vb * C.gam[T.wlo + fl];
+  }
+  ((double*)C.Rsp)[k * C.ntr + t] = rsp;
+}
+
 // Depth-contiguous copies for the kernels that run one lane per depth.
 __global__ void k_setup_transpose(ColDev C, int nline_tab_total) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -393,6 +454,11 @@ static nlte_status validate(const nlte_atmos_desc* A, const nlte_atom_desc* M,
   for (auto p : zs)
     if (!finite_all(p, nz)) return set_err(NLTE_E_NONFINITE, "non-finite atmosphere value");
   if (A->chi_sca && !finite_all(A->chi_sca, nz)) return set_err(NLTE_E_NONFINITE, "non-finite chi_sca");
+  if (A->vlos) {
+    if (!finite_all(A->vlos, nz)) return set_err(NLTE_E_NONFINITE, "non-finite vlos");
+    for (int k = 0; k < nz; ++k)
+      if (!(fabs(A->vlos[k]) < 0.1 * kC)) return set_err(NLTE_E_INVALID, "|vlos[%d]| >= c/10", k);
+  }
   if (A->eta_c) {
     if (!finite_all(A->eta_c, (size_t)nz * nnu)) return set_err(NLTE_E_NONFINITE, "non-finite eta_c");
     for (size_t i = 0; i < (size_t)nz * nnu; ++i)
@@ -513,6 +579,16 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   } else {
     C.Vf = C.Bnuf = C.Ebff = C.VTf = C.EbfTf = C.ECf = nullptr;
   }
+  if (C.vel) {
+    C.vlos = Lo.take<double>(nz);
+    C.VR = Lo.take<double>((size_t)C.nray * nline_tab * nz + 1);
+    C.IR = Lo.take<double>((size_t)C.nray * kfp);
+    C.DXR = Lo.take<double>((size_t)C.nray * kfp);
+    C.DER = Lo.take<double>((size_t)C.nray * kfp);
+  } else {
+    C.vlos = C.VR = nullptr;
+    C.IR = C.DXR = C.DER = nullptr;
+  }
   C.coef = Lo.take<double>((size_t)nz * ncoef(ntr));
   C.ritem = Lo.take<RItem>(std::max(C.nritem, 1));
   C.pitem = Lo.take<PItem>(std::max(C.npitem, 1));
@@ -600,6 +676,8 @@ static nlte_status plan_column(const nlte_atmos_desc* A, const nlte_atom_desc* M
   if (scan && A && A->nz > kScanThreads)
     return set_err(NLTE_E_INVALID, "the depth-parallel formal solution takes at most %d depths",
                    kScanThreads);
+  if (A && A->vlos && (prec != NLTE_FP64 || scan))
+    return set_err(NLTE_E_INVALID, "columns with a velocity field are FP64 and sequential");
   nlte_status vs = validate(A, M, G, C_up);
   if (vs != NLTE_OK) return vs;
 
@@ -614,6 +692,8 @@ static nlte_status plan_column(const nlte_atmos_desc* A, const nlte_atom_desc* M
   C.fp = C.nchunk * kWave;
   C.zp = (nz + 15) & ~15;
   C.bg_eta = A->eta_c != nullptr;
+  C.vel = A->vlos != nullptr;
+  C.nray = 2 * nmu;
   C.has_sca = 0;
   if (A->chi_sca)
     for (int k = 0; k < nz; ++k)
@@ -917,6 +997,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   UP(rC, C_up, (size_t)nz * ntr * 8);
   if (G->w_nu) UP(rW, G->w_nu, (size_t)nnu * 8);
   if (A->eta_c) UP(C.EC, A->eta_c, (size_t)nz * nnu * 8);
+  if (A->vlos) UP(C.vlos, A->vlos, (size_t)nz * 8);
 #undef UP
   if (e == hipSuccess) e = hipMemsetAsync(C.st, 0, sizeof(ColState), stream);
   if (e != hipSuccess) {
@@ -927,6 +1008,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   in.E = rE; in.g = rg; in.A_ul = rA; in.a_damp = ra; in.bf_nu = rbn; in.bf_alpha = rba; in.C_up = rC;
   in.w_nu = G->w_nu ? rW : nullptr;
   in.stage = stage_d; in.bf_ptr = bfptr_d; in.mass_amu = M->mass_amu; in.vturb = M->vturb;
+  for (int m = 0; m < kMaxMu; ++m) in.mu[m] = m < G->nmu ? G->mu[m] : 0.0;
 
   // setup kernels
   k_setup_depth<<<(nz + 63) / 64, 64, 0, stream>>>(C, in);
@@ -940,6 +1022,12 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     k_setup_voigt<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C, in, lbase_d, lbase[nline]);
   }
   k_setup_norm<<<(ntr * nz + 63) / 64, 64, 0, stream>>>(C, in);
+  if (C.vel && nline) {
+    const size_t n = (size_t)lbase[nline] * nz * C.nray;
+    k_setup_voigt_vel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C, in, lbase_d, lbase[nline]);
+    k_setup_norm_vel<<<(nline * C.nray * nz + 63) / 64, 64, 0, stream>>>(C, in);
+    k_setup_rsp_vel<<<(nline * nz + 63) / 64, 64, 0, stream>>>(C);
+  }
   {
     const size_t n = std::max((size_t)nz * nnu, (size_t)nline_tab * nz);
     k_setup_transpose<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C, nline_tab * nz);
@@ -993,7 +1081,7 @@ extern "C" void nlte_column_destroy(nlte_column* col) {
 // ---------------------------------------------------------------------------
 namespace nlte {
 struct HostProblem {
-  std::vector<double> z, T, ne, ntot, chi_c, chi_sca, eta_c;
+  std::vector<double> z, T, ne, ntot, chi_c, chi_sca, eta_c, vlos;
   std::vector<double> E, g, A_ul, a_damp, bf_nu, bf_alpha;
   std::vector<int32_t> stage, line_lo, line_up, bf_lo, bf_ptr;
   std::vector<double> nu, mu, w_mu, w_nu, C_up;
@@ -1028,6 +1116,7 @@ nlte_status problem_copy(const nlte_atmos_desc* A, const nlte_atom_desc* M, cons
   copy_in(H->z, A->z, nz); copy_in(H->T, A->T, nz); copy_in(H->ne, A->ne, nz);
   copy_in(H->ntot, A->ntot, nz); copy_in(H->chi_c, A->chi_c, nz);
   copy_in(H->chi_sca, A->chi_sca, nz); copy_in(H->eta_c, A->eta_c, (size_t)nz * nnu);
+  copy_in(H->vlos, A->vlos, nz);
   copy_in(H->E, M->E, L); copy_in(H->g, M->g, L); copy_in(H->stage, M->stage, L);
   copy_in(H->line_lo, M->line_lo, nline); copy_in(H->line_up, M->line_up, nline);
   copy_in(H->A_ul, M->A_ul, nline); copy_in(H->a_damp, M->a_damp, nline);
@@ -1038,7 +1127,7 @@ nlte_status problem_copy(const nlte_atmos_desc* A, const nlte_atom_desc* M, cons
   copy_in(H->mu, G->mu, nmu); copy_in(H->w_mu, G->w_mu, nmu); copy_in(H->w_nu, G->w_nu, nnu);
   copy_in(H->C_up, C_up, (size_t)nz * ntr);
   H->A = nlte_atmos_desc{nz, H->z.data(), H->T.data(), H->ne.data(), H->ntot.data(), H->chi_c.data(),
-                         ptr_or_null(H->chi_sca), ptr_or_null(H->eta_c)};
+                         ptr_or_null(H->chi_sca), ptr_or_null(H->eta_c), ptr_or_null(H->vlos)};
   H->M = nlte_atom_desc{L, H->E.data(), H->g.data(), H->stage.data(), nline, ptr_or_null(H->line_lo),
                         ptr_or_null(H->line_up), ptr_or_null(H->A_ul), ptr_or_null(H->a_damp),
                         M->mass_amu, M->vturb, nbf, ptr_or_null(H->bf_lo), ptr_or_null(H->bf_ptr),
@@ -1293,6 +1382,7 @@ __global__ void k_set_tangent(ColState* st, int on) {
 extern "C" nlte_status nlte_jvp_tangent(nlte_column* col, const double* n_dev, const double* v_dev,
                                         double* Jv_dev, hipStream_t s) {
   if (!col || !n_dev || !v_dev || !Jv_dev) return set_err(NLTE_E_INVALID, "NULL argument");
+  if (col->h.vel) return set_err(NLTE_E_INVALID, "no tangent product for a column with a velocity field");
   HIP_TRY(hipSetDevice(col->ctx->device));
   nlte_status st = check_populations(col, n_dev, s);
   if (st != NLTE_OK) return st;
@@ -1311,6 +1401,24 @@ extern "C" nlte_status nlte_jvp_tangent(nlte_column* col, const double* n_dev, c
   k_set_tangent<<<1, 1, 0, s>>>(C.st, 0);
   HIP_TRY(hipGetLastError());
   return NLTE_OK;
+}
+
+extern "C" int32_t nlte_struct_size(const char* name) {
+  if (!name) return -1;
+  struct Entry {
+    const char* n;
+    size_t sz;
+  };
+  static const Entry tab[] = {
+      {"nlte_atmos_desc", sizeof(nlte_atmos_desc)},   {"nlte_atom_desc", sizeof(nlte_atom_desc)},
+      {"nlte_grid_desc", sizeof(nlte_grid_desc)},     {"nlte_solve_opts", sizeof(nlte_solve_opts)},
+      {"nlte_solve_stats", sizeof(nlte_solve_stats)}, {"nlte_profile", sizeof(nlte_profile)},
+      {"nlte_plan_info", sizeof(nlte_plan_info)},     {"nlte_server_result", sizeof(nlte_server_result)},
+      {"nlte_server_info", sizeof(nlte_server_info)},
+  };
+  for (const Entry& e : tab)
+    if (strcmp(e.n, name) == 0) return (int32_t)e.sz;
+  return -1;
 }
 
 extern "C" nlte_status nlte_voigt_host(double a, const double* v, int32_t n, double* out) {

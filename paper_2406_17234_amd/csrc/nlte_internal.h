@@ -164,6 +164,8 @@ struct ColDev {
   int npitem, nment;               // pair-sum blocks, entries of M
   int scan;                        // 1: depth-parallel formal solution (nz <= 256)
   int nrseg, nritem;               // rate-integral entries (partial sums) and blocks
+  int vel;                         // 1: velocity field, line opacity per ray (FP64, sequential)
+  int nray;                        // 2 nmu: rays 0..nmu-1 outgoing, nmu..2nmu-1 ingoing
   // angles (inline: at most kMaxMu)
   double wm2[kMaxMu];     // w_m / 2
   double inv2mu[kMaxMu];  // 1 / (2 mu_m)
@@ -185,6 +187,10 @@ struct ColDev {
   const double *Rsp;               // [nz][ntr] n-independent part of R_ul
   const double *C_lu, *C_ul;       // [nz][ntr]
   const double *nstar;             // [nz][L]
+  // velocity fields: line V tables of every ray, [nray][nz][wlen] per line at
+  // offset nray * voff (the line tables come first, so the offsets are those
+  // of V scaled by nray); vlos [nz]
+  const double *VR, *vlos;
   // FP32 copies of V, Bnu and Ebf read by the FP32-form opacity kernel (NULL
   // for FP64 columns); n-independent, so their rounding adds no noise to F
   const float *Vf, *Bnuf, *Ebff;
@@ -211,6 +217,8 @@ struct ColDev {
   double *DchiT, *DetaT;           // [nnu][zp] angle-averaged local intensity derivatives
   double *RJ;                      // [nz][nrseg][2] rate integrals over J, per segment
   double *M;                       // [nment][nz][2] pair sums of the radiative blocks
+  double *IR;                      // velocity fields: [nray][nz][fp] intensity of every ray
+  double *DXR, *DER;               // velocity fields: [nray][nz][fp] local intensity derivatives
   double *P;                       // [nz][L][L] preconditioner blocks of the last Newton-mode evaluation
   double *LU;                      // [nz][L][L] LU factors of the iterate's blocks
   double *Fsave, *Gsave;           // [nz] rate-row F and gross rate under each conservation row
@@ -258,11 +266,12 @@ inline __host__ __device__ int ncoef(int ntr) { return 2 * ntr + 4; }
 struct TileGroup {
   int prec, nmu, first, count;
   int scan;  // columns solved by the depth-parallel formal solution
+  int vel;   // columns with a velocity field (FP64, sequential)
 };
 
 // Tile groups a batch can have: one per (formal-solution variant, precision,
-// angle count).
-constexpr int kMaxGroups = 2 * 2 * kMaxMu;
+// angle count), plus the velocity-field columns per angle count.
+constexpr int kMaxGroups = 2 * 2 * kMaxMu + kMaxMu;
 
 // Device work lists of a batch of columns.
 struct BatchWork {

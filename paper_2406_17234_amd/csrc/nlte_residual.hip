@@ -881,6 +881,230 @@ static void launch_formal_mu(int nmu, int wpb, hipStream_t s, const ColDev* cols
 }
 
 // ---------------------------------------------------------------------------
+// formal solution with a velocity field (Sect. 3.5)
+// ---------------------------------------------------------------------------
+// Each ray sees the line profiles Doppler-shifted by the velocity along it,
+// so chi and S differ from ray to ray and every ray carries its own through
+// the recursion.  FP64; one wave per 64-frequency chunk, one lane per
+// frequency, as k_formal.  The ray-independent part of the opacity
+// (background, edges, scattering) is made once per depth in the first sweep
+// and kept in XS for the second; each ray adds its line part from its own V
+// table.  Outputs: J (depth-contiguous, staged through LDS as in k_formal),
+// the intensity of every ray ([ray][k][nu], for the line rates) and in
+// Newton mode the local derivatives of every ray's intensity (App. A.2, one
+// per ray: the preconditioner weighs them with the ray's own profiles).
+// Every lane of the last chunk computes (its frequency clamped into the grid)
+// and stores into the padded rows, so no store needs a guard.
+
+// Ray-independent chi and eta at (k, fc): background, edges, scattering.
+__device__ __forceinline__ void vel_base(const ColDev& C, int chunk, int k, int fc, double& chi0,
+                                         double& eta0) {
+  const int nz = C.nz, ntr = C.ntr;
+  const double* __restrict__ coef = (const double*)C.coef;
+  double A1 = 0.0, A2 = 0.0;
+  const int e0 = uni(C.ch_eptr[chunk]), e1 = uni(C.ch_eptr[chunk + 1]);
+  for (int j = e0; j < e1; ++j) {
+    const int t = uni(C.ch_edge[j]);
+    const TrDev& T = C.tr[t];
+    const int wlo = uni(T.wlo), whi = uni(T.whi);
+    const double al = (fc >= wlo && fc < whi) ? ldg(C.V + uni(T.voff) + (fc - wlo)) : 0.0;
+    const double* ct = coef + ((size_t)t * nz + k) * 2;
+    A1 = fmar(al, ldc(ct), A1);
+    A2 = fmar(al, ldc(ct + 1), A2);
+  }
+  const size_t kf = (size_t)k * C.nnu + fc;
+  const double E = C.nbf ? ldg(C.Ebf + kf) : 0.0;
+  const double EA2 = E * A2;
+  const double* cb = coef + ((size_t)ntr * nz + k) * 2;
+  chi0 = ldc(cb) + (A1 - EA2);
+  eta0 = fmar(ldc(cb + 1), ldg(C.EC + kf), ldg(C.gam + fc) * EA2);
+  if (C.has_sca) eta0 = fmar(ldc(coef + ((size_t)(ntr + 1) * nz + k) * 2), ldg(C.Jdag + kf), eta0);
+}
+
+// chi and S at (k, fc) of the NMU rays r0 .. r0 + NMU - 1: the lines'
+// V c0 and V c1 with each ray's V added to the ray-independent part.
+template <int NMU>
+__device__ __forceinline__ void vel_rays(const ColDev& C, int chunk, int k, int fc, double chi0,
+                                         double eta0, int r0, double (&chi)[NMU], double (&S)[NMU]) {
+  const int nz = C.nz, nray = C.nray;
+  const double* __restrict__ coef = (const double*)C.coef;
+  double cl[NMU], el[NMU];
+#pragma unroll
+  for (int m = 0; m < NMU; ++m) cl[m] = el[m] = 0.0;
+  const int l0 = uni(C.ch_lptr[chunk]), l1 = uni(C.ch_lptr[chunk + 1]);
+  for (int j = l0; j < l1; ++j) {
+    const int t = uni(C.ch_line[j]);
+    const TrDev& T = C.tr[t];
+    const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
+    const int q = fc - wlo;
+    const bool in = q >= 0 && q < wl;
+    const double* ct = coef + ((size_t)t * nz + k) * 2;
+    const double c0 = ldc(ct), c1 = ldc(ct + 1);
+    const size_t rstep = (size_t)nz * wl;
+    const double* vr = C.VR + (size_t)nray * uni(T.voff) + (size_t)r0 * rstep + (size_t)k * wl + (in ? q : 0);
+    double v[NMU];
+#pragma unroll
+    for (int m = 0; m < NMU; ++m) v[m] = ldg(vr + m * rstep);
+#pragma unroll
+    for (int m = 0; m < NMU; ++m) {
+      const double vi = in ? v[m] : 0.0;
+      cl[m] = fmar(vi, c0, cl[m]);
+      el[m] = fmar(vi, c1, el[m]);
+    }
+  }
+  const double gam = ldg(C.gam + fc);
+#pragma unroll
+  for (int m = 0; m < NMU; ++m) {
+    chi[m] = chi0 + cl[m];
+    S[m] = fmar(gam, el[m], eta0) / chi[m];
+  }
+}
+
+template <bool PM, int NMU>
+__device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int lane, double* tJ) {
+  constexpr int KF = 8;
+  const int nz = C.nz, nnu = C.nnu, fp = C.fp, zp = C.zp;
+  const int f0 = chunk * kWave, f = f0 + lane;
+  const int fc = f < nnu ? f : nnu - 1;
+  const double* __restrict__ dzt = (const double*)C.coef + ((size_t)(C.ntr + 1) * nz) * 2 + 1;  // stride 2
+  double* __restrict__ xb = C.XS;  // [nz][fp][2] ray-independent chi, eta
+  double* __restrict__ jm = C.Jm;  // [nz][fp] ingoing half of J
+  const size_t rs = (size_t)nz * fp;  // ray stride of IR, DXR, DER
+  double i2mu[NMU], mu2[NMU], wm2[NMU];
+#pragma unroll
+  for (int m = 0; m < NMU; ++m) {
+    i2mu[m] = C.inv2mu[m];
+    mu2[m] = 1.0 / C.inv2mu[m];
+    wm2[m] = C.wm2[m];
+  }
+  double I[NMU], chp[NMU], Sp[NMU], ch[NMU], Sx[NMU];
+
+  // ---- sweep 1: ingoing rays (NMU + m), top -> bottom, I- = 0 at the top ----
+  double chi0, eta0;
+  vel_base(C, chunk, 0, fc, chi0, eta0);
+  stg(xb + 2 * (size_t)f, chi0);
+  stg(xb + 2 * (size_t)f + 1, eta0);
+  vel_rays<NMU>(C, chunk, 0, fc, chi0, eta0, NMU, chp, Sp);
+  stg(jm + f, 0.0);
+#pragma unroll
+  for (int m = 0; m < NMU; ++m) {
+    I[m] = 0.0;
+    const size_t o = (size_t)(NMU + m) * rs + f;
+    stg(C.IR + o, 0.0);
+    if (PM) {
+      stg(C.DXR + o, 0.0);
+      stg(C.DER + o, 0.0);
+    }
+  }
+  for (int k = 1; k < nz; ++k) {
+    vel_base(C, chunk, k, fc, chi0, eta0);
+    const size_t kx = (size_t)k * fp + f;
+    stg(xb + 2 * kx, chi0);
+    stg(xb + 2 * kx + 1, eta0);
+    vel_rays<NMU>(C, chunk, k, fc, chi0, eta0, NMU, ch, Sx);
+    const double dz = ldc(dzt + 2 * (k - 1));  // segment k-1 -> k
+    double jac = 0.0;
+#pragma unroll
+    for (int m = 0; m < NMU; ++m) {
+      const double base = dz * (chp[m] + ch[m]);
+      double e, q, a, bx;
+      seg_coef<double, PM>(base * i2mu[m], 1.0 / base, mu2[m], e, q, a, bx);
+      const double Iup = I[m];
+      I[m] = fmar(e, Iup, fmar(q, Sp[m], a * (Sx[m] - Sp[m])));
+      jac = fmar(wm2[m], I[m], jac);
+      const size_t o = (size_t)(NMU + m) * rs + kx;
+      stg(C.IR + o, I[m]);
+      if (PM) {  // c_chi, c_eta of App. A.2 for this ray
+        const double rc = 1.0 / ch[m];
+        stg(C.DXR + o, -(Sx[m] * rc) * a + dz * (i2mu[m] * (e * (Sp[m] - Iup) - (Sp[m] - Sx[m]) * bx)));
+        stg(C.DER + o, a * rc);
+      }
+      chp[m] = ch[m];
+      Sp[m] = Sx[m];
+    }
+    stg(jm + kx, jac);
+  }
+
+  // ---- sweep 2: outgoing rays (m), bottom -> top, I+ = B at the bottom ----
+  {
+    const int k = nz - 1;
+    const size_t kx = (size_t)k * fp + f;
+    vel_rays<NMU>(C, chunk, k, fc, ldg(xb + 2 * kx), ldg(xb + 2 * kx + 1), 0, chp, Sp);
+    const double Bb = ldg(C.Bnu + (size_t)k * nnu + fc);
+    double jp = 0.0;
+#pragma unroll
+    for (int m = 0; m < NMU; ++m) {
+      I[m] = Bb;
+      jp = fmar(wm2[m], Bb, jp);
+      const size_t o = (size_t)m * rs + kx;
+      stg(C.IR + o, Bb);
+      if (PM) {
+        stg(C.DXR + o, 0.0);
+        stg(C.DER + o, 0.0);
+      }
+    }
+    stage_put<KF>(tJ, k, lane, ldg(jm + kx) + jp);
+    if (k % KF == 0) stage_flush<KF>(tJ, C.JT, k, nz, zp, f0, nnu, lane);
+  }
+  for (int k = nz - 2; k >= 0; --k) {
+    const size_t kx = (size_t)k * fp + f;
+    vel_rays<NMU>(C, chunk, k, fc, ldg(xb + 2 * kx), ldg(xb + 2 * kx + 1), 0, ch, Sx);
+    const double dz = ldc(dzt + 2 * k);  // segment k -> k+1
+    double jp = 0.0;
+#pragma unroll
+    for (int m = 0; m < NMU; ++m) {
+      const double base = dz * (ch[m] + chp[m]);
+      double e, q, a, bx;
+      seg_coef<double, PM>(base * i2mu[m], 1.0 / base, mu2[m], e, q, a, bx);
+      const double Iup = I[m];
+      I[m] = fmar(e, Iup, fmar(q, Sp[m], a * (Sx[m] - Sp[m])));
+      jp = fmar(wm2[m], I[m], jp);
+      const size_t o = (size_t)m * rs + kx;
+      stg(C.IR + o, I[m]);
+      if (PM) {  // a_chi, a_eta of App. A.2 for this ray
+        const double rc = 1.0 / ch[m];
+        stg(C.DXR + o, -(Sx[m] * rc) * a + dz * (i2mu[m] * (e * (Sp[m] - Iup) - (Sp[m] - Sx[m]) * bx)));
+        stg(C.DER + o, a * rc);
+      }
+      chp[m] = ch[m];
+      Sp[m] = Sx[m];
+    }
+    stage_put<KF>(tJ, k, lane, ldg(jm + kx) + jp);
+    if (k % KF == 0) stage_flush<KF>(tJ, C.JT, k, nz, zp, f0, nnu, lane);
+  }
+}
+
+template <bool PM, int NMU>
+__global__ __launch_bounds__(256) void k_formal_vel(const ColDev* __restrict__ cols,
+                                                    const Tile* __restrict__ tiles, int ntiles) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int tid = xcd_item(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
+  if (tid >= ntiles) return;
+  const int col = uni(tiles[tid].col);
+  const int chunk = uni(tiles[tid].chunk);
+  const ColDev& C = cols[col];
+  if (uni(C.st->mode) != (PM ? kModeNewton : kModeF)) return;
+  extern __shared__ double stage[];  // [waves per block][8 * 64]
+  formal_tile_vel<PM, NMU>(C, chunk, lane, stage + wave * (8 * kWave));
+}
+
+template <bool PM>
+static void launch_formal_vel(int nmu, int wpb, hipStream_t s, const ColDev* cols, const Tile* tiles,
+                              int ntiles) {
+  const int blocks = (ntiles + wpb - 1) / wpb;
+  const size_t lds = (size_t)wpb * 8 * kWave * sizeof(double);
+  switch (nmu) {
+#define NLTE_VEL_CASE(M) \
+  case M: k_formal_vel<PM, M><<<blocks, 64 * wpb, lds, s>>>(cols, tiles, ntiles); break;
+    NLTE_VEL_CASE(1) NLTE_VEL_CASE(2) NLTE_VEL_CASE(3) NLTE_VEL_CASE(4)
+    NLTE_VEL_CASE(5) NLTE_VEL_CASE(6) NLTE_VEL_CASE(7) NLTE_VEL_CASE(8)
+#undef NLTE_VEL_CASE
+    default: break;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // rate integrals (Eqs. Rij, Rji): one lane per depth, sequential sums over
 // the frequencies of a piece for every transition covering it (depth-
 // contiguous operands, so every load of a wave is one contiguous run).
@@ -894,7 +1118,7 @@ static void launch_formal_mu(int nmu, int wpb, hipStream_t s, const ColDev* cols
 // TB: line-table precision (float for FP32-form evaluations).  J stays FP64
 // here: in the FP32 form a J rounded to FP32 before these sums sets a noise
 // floor on F that doubled the share of columns needing the FP64 fallback.
-template <typename TB, int NL, int NE>
+template <typename TB, int NL, int NE, bool LINES = true>
 __device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, int k,
                                             const TB* __restrict__ VTt, const TB* __restrict__ EbfTt) {
   const int nz = C.nz, zp = C.zp, f0 = it.f0, nf = it.f1 - it.f0;
@@ -927,8 +1151,10 @@ __device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, in
   for (int q = 0; q < nf; ++q) {
     const size_t o = (size_t)q * zp;
     const double j = ldg(J + o);
+    if (LINES) {
 #pragma unroll
-    for (int i = 0; i < NL; ++i) sl[i] = fma(cl[i][q] * (double)ldg(vl[i] + (size_t)q * nz), j, sl[i]);
+      for (int i = 0; i < NL; ++i) sl[i] = fma(cl[i][q] * (double)ldg(vl[i] + (size_t)q * nz), j, sl[i]);
+    }
     if (NE > 0) {
       const double e = (double)ldg(E + o);
 #pragma unroll
@@ -940,10 +1166,12 @@ __device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, in
     }
   }
   double* row = C.RJ + (size_t)k * C.nrseg * 2;
+  if (LINES) {
 #pragma unroll
-  for (int i = 0; i < NL; ++i) {
-    stg(row + 2 * it.e[i], sl[i]);
-    stg(row + 2 * it.e[i] + 1, 0.0);
+    for (int i = 0; i < NL; ++i) {
+      stg(row + 2 * it.e[i], sl[i]);
+      stg(row + 2 * it.e[i] + 1, 0.0);
+    }
   }
 #pragma unroll
   for (int i = 0; i < NE; ++i) {
@@ -952,12 +1180,12 @@ __device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, in
   }
 }
 
-template <typename TB>
+template <typename TB, bool LINES = true>
 __device__ __forceinline__ void rates_shape(const ColDev& C, const RItem& it, int k,
                                             const TB* __restrict__ VTt, const TB* __restrict__ EbfTt) {
   switch (it.nl * 8 + it.ne) {
 #define RB(L, E) \
-  case L * 8 + E: rates_block<TB, L, E>(C, it, k, VTt, EbfTt); break;
+  case L * 8 + E: rates_block<TB, L, E, LINES>(C, it, k, VTt, EbfTt); break;
     RB(0, 1) RB(0, 2) RB(0, 3) RB(0, 4)
     RB(1, 0) RB(1, 1) RB(1, 2) RB(1, 3) RB(1, 4)
     RB(2, 0) RB(2, 1) RB(2, 2) RB(2, 3) RB(2, 4)
@@ -968,6 +1196,35 @@ __device__ __forceinline__ void rates_shape(const ColDev& C, const RItem& it, in
   }
 }
 
+// Velocity fields: the line rates keep the angle integral inside the
+// frequency sum, sum_nu cw sum_rays (w_m/2) V_ray I_ray, since V depends on
+// the ray (Eqs. Rij, Rji); the edges' cross-sections do not, and their sums
+// over J are those of the static case.  Same pieces and entries as above,
+// and the same fixed order (frequency, then ray).
+__device__ __forceinline__ void rates_vel(const ColDev& C, const RItem& it, int k) {
+  const int nz = C.nz, fp = C.fp, nray = C.nray, nmu = C.nmu, f0 = it.f0, nf = it.f1 - it.f0;
+  const size_t rs = (size_t)nz * fp;
+  double* row = C.RJ + (size_t)k * C.nrseg * 2;
+  const double* __restrict__ Ik = C.IR + (size_t)k * fp + f0;
+  for (int i = 0; i < it.nl; ++i) {
+    const TrDev& T = C.tr[it.t[i]];
+    const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo, wo = f0 - wlo;
+    const size_t vs = (size_t)nz * wl;
+    const double* __restrict__ vr = C.VR + (size_t)nray * uni(T.voff) + (size_t)k * wl + wo;
+    const double* __restrict__ cw = C.cw + uni(T.cwoff) + wo;
+    double sum = 0.0;
+    for (int q = 0; q < nf; ++q) {
+      double u = 0.0;
+      for (int r = 0; r < nray; ++r)
+        u = fma(C.wm2[r < nmu ? r : r - nmu] * ldg(vr + r * vs + q), ldg(Ik + r * rs + q), u);
+      sum = fma(cw[q], u, sum);
+    }
+    stg(row + 2 * it.e[i], sum);
+    stg(row + 2 * it.e[i] + 1, 0.0);
+  }
+  rates_shape<double, false>(C, it, k, C.VT, C.EbfT);  // the edges of the block
+}
+
 // The column state and the block descriptor are read with independent
 // scalar loads, so that a wave waits for one memory round trip, not three,
 // before its first table loads.  The tables follow the evaluation's
@@ -976,7 +1233,7 @@ __device__ __forceinline__ void rates_shape(const ColDev& C, const RItem& it, in
 __device__ __forceinline__ void rates_item(const ColDev& C, int b, int k0) {
   const int mode = ldc(&C.st->mode), prec = ldc(&C.st->cur_prec);
   const RItem it = ldc_rec(C.ritem + b);
-  if (mode == kModeIdle) return;
+  if (mode == kModeIdle || C.vel) return;  // velocity-field columns: k_depthwork_vel
   const int k = k0 + threadIdx.x;
   if (k >= C.nz) return;
   if (prec == NLTE_FP32_FORM)
@@ -1092,11 +1349,100 @@ __device__ __forceinline__ void pair_block(const ColDev& C, const PItem& it, int
     }
 }
 
+// Velocity fields: the same pair sums with the angle integral inside,
+//   M1 = sum_nu cw_t sum_rays (w_m/2) A_t,ray V_t',ray D_chi,ray,
+//   M2 = sum_nu cw_t sum_rays (w_m/2) A_t,ray g_t' V_t',ray (2 h nu^3/c^2 D_eta,ray - D_chi,ray),
+// each ray with its own line profiles and local intensity derivatives (the
+// edges' cross-sections are the same for every ray).
+__device__ __forceinline__ void pair_side_vel(const ColDev& C, int t, int f0, int k, const double*& V,
+                                              size_t& rstep, double& g0, double& gE) {
+  const TrDev& T = C.tr[t];
+  const int wlo = uni(T.wlo), voff = uni(T.voff);
+  if (t < C.nline) {
+    const int wl = uni(T.whi) - wlo;
+    V = C.VR + (size_t)C.nray * voff + (size_t)k * wl + (f0 - wlo);
+    rstep = (size_t)C.nz * wl;
+    g0 = uni(T.g);
+    gE = 0.0;
+  } else {
+    V = C.V + voff + (f0 - wlo);
+    rstep = 0;
+    g0 = 0.0;
+    gE = C.rho_bf[k * C.nbf + (t - C.nline)];
+  }
+}
+
+__device__ void pair_vel(const ColDev& C, const PItem& it, int k) {
+  const int nz = C.nz, L = C.L, fp = C.fp, zp = C.zp, nray = C.nray, nmu = C.nmu;
+  const int f0 = it.f0, nf = it.f1 - it.f0, nt = it.nt, nu = it.nu;
+  const size_t rs = (size_t)nz * fp;
+  const double *Vt[kPairBlk], *Vu[kPairBlk], *cw[kPairBlk];
+  size_t st[kPairBlk], su[kPairBlk];
+  double pa[kPairBlk], pb[kPairBlk], g0u[kPairBlk], gEu[kPairBlk];
+  bool edge = false;
+#pragma unroll
+  for (int i = 0; i < kPairBlk; ++i) {
+    const int t = it.t[i < nt ? i : 0];
+    const TrDev& T = C.tr[t];
+    double g0, gE;
+    pair_side_vel(C, t, f0, k, Vt[i], st[i], g0, gE);
+    cw[i] = C.cw + uni(T.cwoff) + (f0 - uni(T.wlo));
+    const double nl = C.eval_n[k * L + uni(T.lo)], nup = C.eval_n[k * L + uni(T.up)];
+    pa[i] = nl - g0 * nup;
+    pb[i] = gE * nup;
+    edge |= i < nt && t >= C.nline;
+    const int u = it.u[i < nu ? i : 0];
+    pair_side_vel(C, u, f0, k, Vu[i], su[i], g0u[i], gEu[i]);
+    edge |= i < nu && u >= C.nline;
+  }
+  const double* EB = C.EbfT ? C.EbfT + (size_t)f0 * zp + k : nullptr;
+  const double* DX = C.DXR + (size_t)k * fp + f0;
+  const double* DE = C.DER + (size_t)k * fp + f0;
+  double m1[kPairBlk][kPairBlk], m2[kPairBlk][kPairBlk];
+#pragma unroll
+  for (int i = 0; i < kPairBlk; ++i)
+#pragma unroll
+    for (int j = 0; j < kPairBlk; ++j) m1[i][j] = m2[i][j] = 0.0;
+  for (int q = 0; q < nf; ++q) {
+    const double E = edge ? ldg(EB + (size_t)q * zp) : 0.0;
+    const double gam = ldg(C.gam + f0 + q);
+    for (int r = 0; r < nray; ++r) {
+      const double w = C.wm2[r < nmu ? r : r - nmu];
+      const double dx = ldg(DX + r * rs + q), de = ldg(DE + r * rs + q);
+      const double dd = gam * de - dx;
+      double a[kPairBlk];
+#pragma unroll
+      for (int i = 0; i < kPairBlk; ++i)
+        a[i] = i < nt ? w * cw[i][q] * ldg(Vt[i] + r * st[i] + q) * (pa[i] - pb[i] * E) : 0.0;
+#pragma unroll
+      for (int j = 0; j < kPairBlk; ++j) {
+        if (j >= nu) break;
+        const double v = ldg(Vu[j] + r * su[j] + q);
+        const double b = v * dx, c = (g0u[j] + gEu[j] * E) * v * dd;
+#pragma unroll
+        for (int i = 0; i < kPairBlk; ++i) {
+          m1[i][j] = fma(a[i], b, m1[i][j]);
+          m2[i][j] = fma(a[i], c, m2[i][j]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kPairBlk; ++i)
+#pragma unroll
+    for (int j = 0; j < kPairBlk; ++j)
+      if (i < nt && j < nu) {
+        double* dst = C.M + ((size_t)(it.e0 + i * it.es + j) * nz + k) * 2;
+        stg(dst, m1[i][j]);
+        stg(dst + 1, m2[i][j]);
+      }
+}
+
 __device__ __forceinline__ void pair_item(const ColDev& C, int p, int k0) {
   // state and block descriptor: independent scalar loads
   const int mode = ldc(&C.st->mode);
   const PItem it = ldc_rec(C.pitem + p);
-  if (mode != kModeNewton) return;
+  if (mode != kModeNewton || C.vel) return;  // velocity-field columns: k_pairsum_vel
   const int k = k0 + threadIdx.x;
   if (k >= C.nz) return;
   const int shape = (it.same ? 16 : 0) + (it.nt - 1) * 4 + (it.nu - 1);
@@ -1138,6 +1484,37 @@ __global__ __launch_bounds__(64) void k_pairsum(const ColDev* __restrict__ cols,
   const int4 it = work[w];
   const int col = uni(it.x), idx = uni(it.y), k0 = uni(it.z);
   pair_item(cols[col], idx, k0);
+}
+
+// The rate and pair-sum items of velocity-field columns, over the same work
+// lists (the other columns' items return at once): kernels of their own, so
+// that the ray loops do not cost the static kernels registers.
+__global__ __launch_bounds__(64) void k_depthwork_vel(const ColDev* __restrict__ cols,
+                                                      const int4* __restrict__ work, int nwork) {
+  const int w = xcd_item(blockIdx.x, gridDim.x);
+  if (w >= nwork) return;
+  const int4 wi = work[w];
+  const ColDev& C = cols[uni(wi.x)];
+  const int mode = ldc(&C.st->mode);
+  if (!C.vel || mode == kModeIdle) return;
+  const int k = uni(wi.z) + threadIdx.x;
+  if (k >= C.nz) return;
+  const RItem it = ldc_rec(C.ritem + uni(wi.y));
+  rates_vel(C, it, k);
+}
+
+__global__ __launch_bounds__(64) void k_pairsum_vel(const ColDev* __restrict__ cols,
+                                                    const int4* __restrict__ work, int nwork) {
+  const int w = xcd_item(blockIdx.x, gridDim.x);
+  if (w >= nwork) return;
+  const int4 wi = work[w];
+  const ColDev& C = cols[uni(wi.x)];
+  const int mode = ldc(&C.st->mode);
+  if (!C.vel || mode != kModeNewton) return;
+  const int k = uni(wi.z) + threadIdx.x;
+  if (k >= C.nz) return;
+  const PItem it = ldc_rec(C.pitem + uni(wi.y));
+  pair_vel(C, it, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -1354,6 +1731,7 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   k_coef<<<nblk, 256, 0, s>>>(bw.cols, bw.act);
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
+    if (G.vel) continue;  // the velocity formal solution makes its opacity itself
     const Tile* tl = bw.tiles + G.first;
     const bool fused32 = !G.scan && G.count >= kFuseMinTiles;  // made inside the formal solution
     if (G.prec == NLTE_FP32_FORM && !fused32)
@@ -1387,6 +1765,11 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     // FP64 launches: on s / sNewton for FP64 groups, on sF64 / sN64 for the
     // fallback columns of FP32-form groups
     const hipStream_t dF = f32 ? sF64 : s, dN = f32 ? sN64 : sNewton;
+    if (G.vel) {
+      launch_formal_vel<false>(G.nmu, nb, s, bw.cols, tl, G.count);
+      if (bw.any_newton) launch_formal_vel<true>(G.nmu, nb, sNewton, bw.cols, tl, G.count);
+      continue;
+    }
     if (G.scan) {
       if (f32) {
         launch_formal_scan_mu<float, false>(G.nmu, s, bw.cols, tl, G.count);
@@ -1424,6 +1807,14 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   if (bw.any_newton && bw.nrate > bw.nrate0)
     k_pairsum<<<bw.nrate - bw.nrate0, 64, 0, s>>>(bw.cols, bw.rate_work + bw.nrate0,
                                                    bw.nrate - bw.nrate0);
+  bool any_vel = false;
+  for (int g = 0; g < bw.ngroup; ++g) any_vel |= bw.groups[g].vel != 0;
+  if (any_vel) {
+    if (bw.nrate0 > 0) k_depthwork_vel<<<bw.nrate0, 64, 0, s>>>(bw.cols, bw.rate_work, bw.nrate0);
+    if (bw.any_newton && bw.nrate > bw.nrate0)
+      k_pairsum_vel<<<bw.nrate - bw.nrate0, 64, 0, s>>>(bw.cols, bw.rate_work + bw.nrate0,
+                                                         bw.nrate - bw.nrate0);
+  }
   if (ev) chk(hipEventRecord(ev[3], s));
   {
     const int nsub = (bw.maxnz + kAsmDepths - 1) / kAsmDepths;
@@ -1450,19 +1841,30 @@ int build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
     sel = all.data();
     nsel = ncol;
   }
-  // formal-solution tiles grouped by (variant, precision, angle count)
+  // formal-solution tiles grouped by (variant, precision, angle count); the
+  // velocity-field columns (FP64, sequential) by angle count
   for (int scan = 0; scan < 2; ++scan)
     for (int prec = 0; prec < 2; ++prec)
       for (int nmu = 1; nmu <= kMaxMu; ++nmu) {
-        TileGroup G{prec, nmu, (int)tiles.size(), 0, scan};
+        TileGroup G{prec, nmu, (int)tiles.size(), 0, scan, 0};
         for (int q = 0; q < nsel; ++q) {
           const int c = sel[q];
-          if (hc[c].prec == prec && hc[c].nmu == nmu && hc[c].scan == scan)
+          if (hc[c].prec == prec && hc[c].nmu == nmu && hc[c].scan == scan && !hc[c].vel)
             for (int ch = 0; ch < hc[c].nchunk; ++ch) tiles.push_back(Tile{c, ch});
         }
         G.count = (int)tiles.size() - G.first;
         if (G.count) groups.push_back(G);
       }
+  for (int nmu = 1; nmu <= kMaxMu; ++nmu) {
+    TileGroup G{NLTE_FP64, nmu, (int)tiles.size(), 0, 0, 1};
+    for (int q = 0; q < nsel; ++q) {
+      const int c = sel[q];
+      if (hc[c].vel && hc[c].nmu == nmu)
+        for (int ch = 0; ch < hc[c].nchunk; ++ch) tiles.push_back(Tile{c, ch});
+    }
+    G.count = (int)tiles.size() - G.first;
+    if (G.count) groups.push_back(G);
+  }
   // rate items (kind 0), then preconditioner pair-sum blocks (kind 1), each
   // kind column by column
   maxL = 0;

@@ -37,7 +37,7 @@ class NLTEError(RuntimeError):
 
 class AtmosDesc(C.Structure):
     _fields_ = [("nz", C.c_int32), ("z", _dp), ("T", _dp), ("ne", _dp), ("ntot", _dp),
-                ("chi_c", _dp), ("chi_sca", _dp), ("eta_c", _dp)]
+                ("chi_c", _dp), ("chi_sca", _dp), ("eta_c", _dp), ("vlos", _dp)]
 
 
 class AtomDesc(C.Structure):
@@ -163,6 +163,8 @@ def lib():
         L.nlte_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
         L.nlte_solve_opts_default.restype = None
         L.nlte_voigt_host.argtypes = [C.c_double, _dp, C.c_int32, _dp]
+        L.nlte_struct_size.argtypes = [C.c_char_p]
+        L.nlte_struct_size.restype = C.c_int32
         L.nlte_plan_create.argtypes = [vp, C.POINTER(vp), C.c_int32, C.POINTER(vp), C.POINTER(vp),
                                        C.c_int32, vp, C.POINTER(vp)]
         L.nlte_plan_run.argtypes = [vp, vp]
@@ -275,9 +277,11 @@ def _descriptors(problem):
         return p
 
     eta_c = getattr(a, "eta_c", None)
+    vlos = getattr(a, "vlos", None)
     atm = AtmosDesc(len(a.z), D(a.z), D(a.T), D(a.ne), D(a.ntot), D(a.chi_c),
                     D(a.chi_sca) if a.chi_sca is not None else None,
-                    D(eta_c) if eta_c is not None else None)
+                    D(eta_c) if eta_c is not None else None,
+                    D(vlos) if vlos is not None else None)
     bf_ptr = np.concatenate([[0], np.cumsum([len(x) for x in g.bf_nu])]).astype(np.int32)
     bf_nu = np.concatenate(g.bf_nu) if len(g.bf_nu) else np.zeros(1)
     bf_al = np.concatenate(g.bf_alpha) if len(g.bf_alpha) else np.zeros(1)

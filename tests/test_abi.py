@@ -75,3 +75,17 @@ def test_solve_opts_layout_matches_defaults():
     assert o.jv_method == nlte.JV_FD
     assert (o.krylov_x0, o.launch) == (0, 0)
     assert ctypes.sizeof(o) == 72
+
+
+def test_struct_sizes_match_the_library():
+    """Every public structure of the binding has the size the library was
+    compiled with (a missing or extra field changes it)."""
+    L = nlte.lib()
+    pairs = {"nlte_atmos_desc": nlte.AtmosDesc, "nlte_atom_desc": nlte.AtomDesc,
+             "nlte_grid_desc": nlte.GridDesc, "nlte_solve_opts": nlte.SolveOpts,
+             "nlte_solve_stats": nlte.SolveStats, "nlte_profile": nlte.Profile,
+             "nlte_plan_info": nlte.PlanInfo, "nlte_server_result": nlte.ServerResult,
+             "nlte_server_info": nlte.ServerInfo}
+    for name, cls in pairs.items():
+        assert L.nlte_struct_size(name.encode()) == ctypes.sizeof(cls), name
+    assert L.nlte_struct_size(b"nlte_nothing") == -1

@@ -6,12 +6,16 @@
   F-only loop of the benchmark): sampled columns against the oracle, and
   bit-identical to the same columns evaluated alone;
 - the batched FP32-form solve of all 4096 columns (the benchmark step):
-  sampled columns' populations against the oracle's FP64 root to 1e-4."""
+  sampled columns' populations against the oracle's FP64 root to 1e-4;
+- converged 11-level solves against stored oracle roots: a full-size
+  served-stream request (211 depths, 1800 frequencies, 6 angles) in FP64 at
+  1e-10, and the stress column in the FP32 form (FP64 fallback) at 1e-4."""
 import numpy as np
 import pytest
 
 from oracle import nlte_oracle as O
 from paper_2406_17234_amd import synth as S
+from tests.golden.make_roots import load as load_root
 from tests.helpers import maxrel, perturbed, require_gpu, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
@@ -88,3 +92,34 @@ def test_batch_solve_sampled_columns(ctx):
         ref = O.solve(tb, ftol=1e-10, rtol=1e-6, maxiter=50)
         assert ref.converged
         assert maxrel(to_np(outs[i]), ref.n) < 1e-4, i
+
+
+def test_eleven_level_request_fp64_root(ctx):
+    """Served-stream request 3 (11 levels, 211 depths, 1800 frequencies, 6
+    angles) solved alone in FP64 from LTE reaches the oracle's root."""
+    from paper_2406_17234_amd import nlte
+    p = S.stream_request(3)
+    ref = load_root("stream3_root")
+    assert ref.shape == (p.atmos.nz, p.atom.nlev) and p.atom.nlev == 11
+    print(f"[case] 11-level FP64 root dims={p.dims}", flush=True)
+    col = nlte.Column(ctx, p, precision=nlte.FP64)
+    n, _, st, rc = col.solve(ftol=1e-12, rtol=1e-3, maxiter=80, max_krylov=300)
+    print(st, flush=True)
+    assert rc == 0 and st["status"] == 0
+    assert maxrel(to_np(n), ref) < 1e-10
+
+
+def test_stress_column_fp32_form_root(ctx):
+    """The 11-level stress column (256 depths, ~4000 frequencies, 8 angles)
+    solved in the FP32 form with the FP64 fallback lands within 1e-4 of the
+    oracle's FP64 root."""
+    from paper_2406_17234_amd import nlte
+    p = S.chromo11()
+    ref = load_root("chromo11_root")
+    assert ref.shape == (p.atmos.nz, p.atom.nlev)
+    print(f"[case] chromo11 FP32-form root dims={p.dims}", flush=True)
+    col = nlte.Column(ctx, p, precision=nlte.FP32_FORM)
+    n, _, st, rc = col.solve(ftol=1e-6, rtol=1e-3, maxiter=80, max_krylov=300, fp64_fallback=12)
+    print(st, flush=True)
+    assert rc == 0 and st["status"] == 0
+    assert maxrel(to_np(n), ref) < 1e-4

@@ -73,6 +73,7 @@ NONFINITE = {
     "eta_c NaN": lambda p: setattr(p.atmos, "eta_c", np.where(
         np.arange(p.atmos.nz * p.grid.nnu).reshape(p.atmos.nz, -1) == 9, np.nan, 1.0)),
     "w_nu Inf": lambda p: setattr(p.grid, "w_nu", np.where(np.arange(p.grid.nnu) == 4, np.inf, 1.0)),
+    "vlos NaN": lambda p: setattr(p.atmos, "vlos", np.where(np.arange(p.atmos.nz) == 2, np.nan, 1e5)),
 }
 
 INVALID = {
@@ -97,6 +98,7 @@ INVALID = {
     "negative background opacity": _set("atmos.chi_c", _at(3, -1.0)),
     "negative eta_c": lambda p: setattr(p.atmos, "eta_c", -np.ones((p.atmos.nz, p.grid.nnu))),
     "zero frequency weight": lambda p: setattr(p.grid, "w_nu", np.zeros(p.grid.nnu)),
+    "vlos beyond c/10": lambda p: setattr(p.atmos, "vlos", np.full(p.atmos.nz, 4e9)),
 }
 
 
@@ -132,3 +134,14 @@ def test_null_arguments_rejected():
     assert L.nlte_column_plan_bytes(None, None, None, None, 0, ctypes.byref(nb)) == nlte.NLTE_E_INVALID
     assert L.nlte_column_plan_bytes(None, None, None, None, 0, None) == nlte.NLTE_E_INVALID
     assert len(L.nlte_last_error()) > 0
+
+
+def test_velocity_field_limits(base):
+    """A velocity field is accepted in FP64 with the sequential formal
+    solution and sized with its per-ray tables; the FP32 form and the
+    depth-parallel variant reject it."""
+    p = copy.deepcopy(base)
+    p.atmos.vlos = np.linspace(0.0, 3e5, p.atmos.nz)
+    assert nlte.plan_bytes(p) > nlte.plan_bytes(base) + 2 * p.grid.nmu * p.atmos.nz * p.grid.nnu * 8
+    assert _status(p, nlte.FP32_FORM) == nlte.NLTE_E_INVALID
+    assert _status(p, nlte.FP64 | nlte.DEPTH_SCAN) == nlte.NLTE_E_INVALID
