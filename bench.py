@@ -101,7 +101,8 @@ def _oracle_single(args):
     os.environ["OMP_NUM_THREADS"] = "1"
     from oracle import nlte_oracle as O
     name, ftol = args
-    prob = {"C1_slab3": S.slab3, "C2_chromo6": S.chromo6, "C5_chromo11": S.chromo11}[name]()
+    prob = {"C1_slab3": S.slab3, "C2_chromo6": S.chromo6, "C5_chromo11": S.chromo11,
+            "V_chromo6_vel": S.chromo6_vel}[name]()
     tb = O.setup(prob)
     if name == "C5_chromo11":
         t0 = time.perf_counter()
@@ -111,18 +112,19 @@ def _oracle_single(args):
         dt = time.perf_counter() - t0
         return {"config": name, "kind": "residual calls", "calls": calls, "s_per_call": dt / calls,
                 "depth_points_per_s": calls * prob.depth_points() / dt, "cores": 1}
+    rtol = 1e-2 if name == "V_chromo6_vel" else 1e-3
     t0 = time.perf_counter()
-    s = O.solve(tb, ftol=ftol, rtol=1e-3, maxiter=50)
+    s = O.solve(tb, ftol=ftol, rtol=rtol, maxiter=80)
     dt = time.perf_counter() - t0
-    return {"config": name, "kind": "JFNK solve", "ftol": ftol, "s_per_solve": dt,
+    return {"config": name, "kind": "JFNK solve", "ftol": ftol, "rtol": rtol, "s_per_solve": dt,
             "calls": s.calls, "s_per_call": dt / max(s.calls, 1), "converged": bool(s.converged),
             "depth_points_per_s": s.calls * prob.depth_points() / dt, "cores": 1}
 
 
 def oracle_single_columns():
-    """C1, C2 and C5 on one core each, run side by side (one process per
-    configuration)."""
-    jobs = [("C1_slab3", 1e-8), ("C2_chromo6", 1e-8), ("C5_chromo11", None)]
+    """C1, C2, C5 and the velocity-step column on one core each, run side by
+    side (one process per configuration)."""
+    jobs = [("C1_slab3", 1e-8), ("C2_chromo6", 1e-8), ("C5_chromo11", None), ("V_chromo6_vel", 1e-8)]
     with mp.get_context("fork").Pool(len(jobs)) as pool:
         return {r["config"]: r for r in pool.map(_oracle_single, jobs)}
 
@@ -323,6 +325,96 @@ def f_only(ctx, nlte, problems, prec, runs=100, tune=True):
             "opac_depths": info["opac_depths"], "formal_wpb": info["formal_wpb"]}
 
 
+def vel_bytes_per_eval(p):
+    """Algorithmic HBM bytes of one column's F-mode velocity formal solution
+    (k_formal_vel): per ray-depth-point, the ray's V of every line window
+    covering the frequency (8 B each) and the ray's intensity written for the
+    line rates (8 B); per (depth, frequency), the ray-independent opacity
+    written and read back (32 B), the ingoing half of J written and read back
+    (16 B) and J (8 B)."""
+    g = p.grid
+    cover = np.zeros(g.nnu)
+    for t in range(p.atom.nline):
+        cover[g.win_lo[t]:g.win_hi[t]] += 1.0
+    nray = 2 * len(g.mu)
+    return p.atmos.nz * (nray * (8.0 * cover.sum() + 8.0 * g.nnu) + 56.0 * g.nnu)
+
+
+def velocity_leg(ctx, nlte, ncol):
+    """Velocity fields (Sect. 3.5).  The velocity-step column of the paper's
+    test solved alone (FP64, Krylov tolerance 1e-2, stop at 1e-8; median of 3
+    after a warm-up), and a batch of ncol velocity columns: FP64 batch solve
+    (one warm-up, one timed), a profiled solve for the roofline of the F-mode
+    velocity formal-solution launches (HBM-bound: its algorithmic bytes over
+    their time), and F-only loops of the batch with and without the velocity
+    field (same depths and frequencies)."""
+    import torch
+    out = {}
+    p = S.chromo6_vel()
+    col = nlte.Column(ctx, p, precision=nlte.FP64)
+    o1 = nlte.default_opts(ftol=1e-8, rtol=1e-2, maxiter=80)
+    col.solve(opts=o1)
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, st, _ = col.solve(opts=o1)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    col.close()
+    out["chromo6_vel_alone"] = {"dims": p.dims, "ms_per_solve": float(np.median(ts)) * 1e3,
+                                "newton_iters": st["newton_iters"], "residual_calls": st["f_calls"],
+                                "status": st["status"], "ftol": 1e-8, "rtol": 1e-2}
+    probs = [S.batch6_vel_column(i) for i in range(ncol)]
+    cols = [nlte.Column(ctx, q, precision=nlte.FP64) for q in probs]
+    ob = nlte.default_opts(ftol=1e-8, rtol=1e-3, maxiter=50, max_krylov_total=200)
+    nlte.solve_batch(ctx, cols, ob)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, bst, _ = nlte.solve_batch(ctx, cols, ob)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.profile(True)
+    _, pst, _ = nlte.solve_batch(ctx, cols, ob)
+    prof = ctx.read_profile()
+    ctx.profile(False)
+    for c in cols:
+        c.close()
+    dp = np.array([q.depth_points() for q in probs], dtype=np.float64)
+    bf = np.array([s["f_calls"] for s in bst], dtype=np.float64)
+    own = np.array([s["f_calls"] - s["precond_calls"] for s in pst], dtype=np.float64)
+    nbytes = float((own * np.array([vel_bytes_per_eval(q) for q in probs])).sum())
+    achieved = nbytes / (prof["formal_f_ms"] * 1e-3) / 1e9 if prof["formal_f_ms"] > 0 else None
+    out["batch"] = {
+        "workload": f"{ncol} velocity columns (batch6 recipe with a 2-8 km/s velocity step, "
+                    "depth-optimised, core-resolving line grid), FP64",
+        "columns": ncol,
+        "mean_nz": float(np.mean([q.atmos.nz for q in probs])),
+        "mean_nnu": float(np.mean([q.grid.nnu for q in probs])),
+        "ms_per_solve": el * 1e3,
+        "depth_points_per_s": float((bf * dp).sum()) / el,
+        "converged_fraction": float(np.mean([s["status"] == 0 for s in bst])),
+        "columns_converged_per_s": float(np.sum([s["status"] == 0 for s in bst])) / el,
+        "residual_calls_per_column": float(bf.mean()),
+        "newton_iters_mean": float(np.mean([s["newton_iters"] for s in bst])),
+        "kernel_ms_per_solve_profiled": {k: prof[k] for k in ("opacity_ms", "formal_ms", "depth_ms",
+                                                              "assemble_ms", "solver_ms")},
+    }
+    out["roofline"] = {
+        "kernel": "k_formal_vel<false, 5> (F-mode velocity formal solution, opacity made per ray)",
+        "launches": prof["formal_f_launches"],
+        "launch_avg_ms": prof["formal_f_ms"] / max(1, prof["formal_f_launches"]),
+        "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+        "frac": achieved / 8000.0 if achieved else None,
+        "algorithmic_bytes_per_launch": nbytes / max(1, prof["formal_f_launches"]),
+        "traffic": None,
+    }
+    out["f_only_fp64"] = f_only(ctx, nlte, probs, nlte.FP64)
+    out["f_only_fp64_static_twin"] = f_only(ctx, nlte, [S.batch6_vel_column(i, static=True)
+                                                        for i in range(ncol)], nlte.FP64)
+    return out
+
+
 def copy_calibration(nbytes=256 << 20, reps=3):
     """A plain elementwise copy (y = 1.0 * x, fp32) of known size: it reads and
     writes nbytes each, so HBM byte counters read for it give their scale."""
@@ -390,6 +482,10 @@ def main():
                     help="only run that F-only loop (--runs evaluations) and print its figures: "
                          "a short command for profilers")
     ap.add_argument("--runs", type=int, default=100)
+    ap.add_argument("--velocity", type=int, default=512,
+                    help="columns of the velocity-field batch leg (0: skip the velocity leg)")
+    ap.add_argument("--velocity-only", action="store_true",
+                    help="only run the velocity leg and print its figures")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy kernel (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -404,6 +500,10 @@ def main():
                  if name.startswith("batch6") else [S.chromo11()])
         prec = (nlte.FP64 if "fp64" in name else nlte.FP32_FORM) | (nlte.DEPTH_SCAN if "scan" in name else 0)
         print(json.dumps({name: f_only(ctx, nlte, probs, prec, runs=args.runs)}))
+        return
+    if args.velocity_only:
+        from paper_2406_17234_amd import nlte
+        print(json.dumps({"velocity": velocity_leg(nlte.Context(0), nlte, args.velocity or 512)}))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); columns are "
@@ -620,6 +720,13 @@ def main():
     out["single_column_latency"] = gpu_single_columns(ctx, nlte)
     if oracle_single:
         out["oracle_single_column_1core"] = oracle_single
+    if args.velocity > 0:
+        for c in cols or []:
+            c.close()
+        cols = None
+        out["velocity"] = velocity_leg(ctx, nlte, args.velocity)
+        print(f"[bench] velocity: alone {out['velocity']['chromo6_vel_alone']['ms_per_solve']:.0f} ms, "
+              f"batch {out['velocity']['batch']['ms_per_solve']:.0f} ms", file=sys.stderr, flush=True)
     if args.serve_seconds > 0:
         for c in cols or []:
             c.close()

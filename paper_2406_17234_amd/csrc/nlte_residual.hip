@@ -1199,30 +1199,48 @@ __device__ __forceinline__ void rates_shape(const ColDev& C, const RItem& it, in
 // Velocity fields: the line rates keep the angle integral inside the
 // frequency sum, sum_nu cw sum_rays (w_m/2) V_ray I_ray, since V depends on
 // the ray (Eqs. Rij, Rji); the edges' cross-sections do not, and their sums
-// over J are those of the static case.  Same pieces and entries as above,
-// and the same fixed order (frequency, then ray).
-__device__ __forceinline__ void rates_vel(const ColDev& C, const RItem& it, int k) {
-  const int nz = C.nz, fp = C.fp, nray = C.nray, nmu = C.nmu, f0 = it.f0, nf = it.f1 - it.f0;
+// over J are those of the static case.  Same pieces and entries as above.
+// The per-ray intensities and V tables are frequency-contiguous, so the line
+// sums run one lane per frequency of the piece, depth by depth, each ending
+// in a wave sum of fixed order (lane 0's butterfly): deterministic and
+// independent of batching.  The edges keep one lane per depth.
+__device__ __forceinline__ double wave_sum0(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;  // lane 0's value has a fixed order
+}
+
+__device__ void rates_vel(const ColDev& C, const RItem& it, int k0) {
+  const int lane = threadIdx.x;
+  const int nz = C.nz, fp = C.fp, nray = C.nray, nmu = C.nmu;
   const size_t rs = (size_t)nz * fp;
-  double* row = C.RJ + (size_t)k * C.nrseg * 2;
-  const double* __restrict__ Ik = C.IR + (size_t)k * fp + f0;
+  if (it.ne > 0 && k0 + lane < nz) rates_shape<double, false>(C, it, k0 + lane, C.VT, C.EbfT);
+  const int kend = min(k0 + kWave, nz);
   for (int i = 0; i < it.nl; ++i) {
     const TrDev& T = C.tr[it.t[i]];
-    const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo, wo = f0 - wlo;
+    const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
     const size_t vs = (size_t)nz * wl;
-    const double* __restrict__ vr = C.VR + (size_t)nray * uni(T.voff) + (size_t)k * wl + wo;
-    const double* __restrict__ cw = C.cw + uni(T.cwoff) + wo;
-    double sum = 0.0;
-    for (int q = 0; q < nf; ++q) {
-      double u = 0.0;
-      for (int r = 0; r < nray; ++r)
-        u = fma(C.wm2[r < nmu ? r : r - nmu] * ldg(vr + r * vs + q), ldg(Ik + r * rs + q), u);
-      sum = fma(cw[q], u, sum);
+    const double* __restrict__ vb = C.VR + (size_t)nray * uni(T.voff);
+    const double* __restrict__ cw = C.cw + uni(T.cwoff);
+    const int e = it.e[i];
+    for (int k = k0; k < kend; ++k) {
+      double acc = 0.0;
+      for (int f = it.f0 + lane; f < it.f1; f += kWave) {
+        double u = 0.0;
+        const int q = f - wlo;
+        for (int r = 0; r < nray; ++r)
+          u = fma(C.wm2[r < nmu ? r : r - nmu] * ldg(vb + r * vs + (size_t)k * wl + q),
+                  ldg(C.IR + r * rs + (size_t)k * fp + f), u);
+        acc = fma(cw[q], u, acc);
+      }
+      const double tot = wave_sum0(acc);
+      if (lane == 0) {
+        double* row = C.RJ + (size_t)k * C.nrseg * 2;
+        stg(row + 2 * e, tot);
+        stg(row + 2 * e + 1, 0.0);
+      }
     }
-    stg(row + 2 * it.e[i], sum);
-    stg(row + 2 * it.e[i] + 1, 0.0);
   }
-  rates_shape<double, false>(C, it, k, C.VT, C.EbfT);  // the edges of the block
 }
 
 // The column state and the block descriptor are read with independent
@@ -1353,89 +1371,107 @@ __device__ __forceinline__ void pair_block(const ColDev& C, const PItem& it, int
 //   M1 = sum_nu cw_t sum_rays (w_m/2) A_t,ray V_t',ray D_chi,ray,
 //   M2 = sum_nu cw_t sum_rays (w_m/2) A_t,ray g_t' V_t',ray (2 h nu^3/c^2 D_eta,ray - D_chi,ray),
 // each ray with its own line profiles and local intensity derivatives (the
-// edges' cross-sections are the same for every ray).
-__device__ __forceinline__ void pair_side_vel(const ColDev& C, int t, int f0, int k, const double*& V,
-                                              size_t& rstep, double& g0, double& gE) {
-  const TrDev& T = C.tr[t];
-  const int wlo = uni(T.wlo), voff = uni(T.voff);
-  if (t < C.nline) {
-    const int wl = uni(T.whi) - wlo;
-    V = C.VR + (size_t)C.nray * voff + (size_t)k * wl + (f0 - wlo);
-    rstep = (size_t)C.nz * wl;
-    g0 = uni(T.g);
-    gE = 0.0;
-  } else {
-    V = C.V + voff + (f0 - wlo);
-    rstep = 0;
-    g0 = 0.0;
-    gE = C.rho_bf[k * C.nbf + (t - C.nline)];
-  }
-}
-
-__device__ void pair_vel(const ColDev& C, const PItem& it, int k) {
-  const int nz = C.nz, L = C.L, fp = C.fp, zp = C.zp, nray = C.nray, nmu = C.nmu;
-  const int f0 = it.f0, nf = it.f1 - it.f0, nt = it.nt, nu = it.nu;
+// edges' cross-sections are the same for every ray).  One lane per frequency
+// of the piece, depth by depth (the per-ray operands are frequency-
+// contiguous), each depth's sums ending in fixed-order wave sums.
+__device__ void pair_vel(const ColDev& C, const PItem& it, int k0) {
+  const int lane = threadIdx.x;
+  const int nz = C.nz, L = C.L, fp = C.fp, nnu = C.nnu, nray = C.nray, nmu = C.nmu, nline = C.nline;
+  const int nt = it.nt, nu = it.nu;
   const size_t rs = (size_t)nz * fp;
+  // per side: table base (indexed by (ray, k, f)), steps, and level data
   const double *Vt[kPairBlk], *Vu[kPairBlk], *cw[kPairBlk];
-  size_t st[kPairBlk], su[kPairBlk];
-  double pa[kPairBlk], pb[kPairBlk], g0u[kPairBlk], gEu[kPairBlk];
+  size_t rt[kPairBlk], ru[kPairBlk];  // ray steps (0: edge)
+  int kt[kPairBlk], ku[kPairBlk];     // depth steps (0: edge)
+  int ot[kPairBlk], ou[kPairBlk];     // first frequency of the window
   bool edge = false;
 #pragma unroll
   for (int i = 0; i < kPairBlk; ++i) {
     const int t = it.t[i < nt ? i : 0];
     const TrDev& T = C.tr[t];
-    double g0, gE;
-    pair_side_vel(C, t, f0, k, Vt[i], st[i], g0, gE);
-    cw[i] = C.cw + uni(T.cwoff) + (f0 - uni(T.wlo));
-    const double nl = C.eval_n[k * L + uni(T.lo)], nup = C.eval_n[k * L + uni(T.up)];
-    pa[i] = nl - g0 * nup;
-    pb[i] = gE * nup;
-    edge |= i < nt && t >= C.nline;
+    const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
+    const bool line = t < nline;
+    Vt[i] = line ? C.VR + (size_t)nray * uni(T.voff) : C.V + uni(T.voff);
+    rt[i] = line ? (size_t)nz * wl : 0;
+    kt[i] = line ? wl : 0;
+    ot[i] = wlo;
+    cw[i] = C.cw + uni(T.cwoff);
+    edge |= i < nt && !line;
     const int u = it.u[i < nu ? i : 0];
-    pair_side_vel(C, u, f0, k, Vu[i], su[i], g0u[i], gEu[i]);
-    edge |= i < nu && u >= C.nline;
+    const TrDev& U = C.tr[u];
+    const int ulo = uni(U.wlo), ul = uni(U.whi) - ulo;
+    const bool uline = u < nline;
+    Vu[i] = uline ? C.VR + (size_t)nray * uni(U.voff) : C.V + uni(U.voff);
+    ru[i] = uline ? (size_t)nz * ul : 0;
+    ku[i] = uline ? ul : 0;
+    ou[i] = ulo;
+    edge |= i < nu && !uline;
   }
-  const double* EB = C.EbfT ? C.EbfT + (size_t)f0 * zp + k : nullptr;
-  const double* DX = C.DXR + (size_t)k * fp + f0;
-  const double* DE = C.DER + (size_t)k * fp + f0;
-  double m1[kPairBlk][kPairBlk], m2[kPairBlk][kPairBlk];
+  const int kend = min(k0 + kWave, nz);
+  for (int k = k0; k < kend; ++k) {
+    double pa[kPairBlk], pb[kPairBlk], g0u[kPairBlk], gEu[kPairBlk];
 #pragma unroll
-  for (int i = 0; i < kPairBlk; ++i)
+    for (int i = 0; i < kPairBlk; ++i) {
+      const int t = it.t[i < nt ? i : 0];
+      const TrDev& T = C.tr[t];
+      const double nl = C.eval_n[k * L + uni(T.lo)], nup = C.eval_n[k * L + uni(T.up)];
+      if (t < nline) {
+        pa[i] = nl - uni(T.g) * nup;
+        pb[i] = 0.0;
+      } else {
+        pa[i] = nl;
+        pb[i] = C.rho_bf[k * C.nbf + (t - nline)] * nup;
+      }
+      const int u = it.u[i < nu ? i : 0];
+      const TrDev& U = C.tr[u];
+      g0u[i] = u < nline ? uni(U.g) : 0.0;
+      gEu[i] = u < nline ? 0.0 : C.rho_bf[k * C.nbf + (u - nline)];
+    }
+    double m1[kPairBlk][kPairBlk], m2[kPairBlk][kPairBlk];
 #pragma unroll
-    for (int j = 0; j < kPairBlk; ++j) m1[i][j] = m2[i][j] = 0.0;
-  for (int q = 0; q < nf; ++q) {
-    const double E = edge ? ldg(EB + (size_t)q * zp) : 0.0;
-    const double gam = ldg(C.gam + f0 + q);
-    for (int r = 0; r < nray; ++r) {
-      const double w = C.wm2[r < nmu ? r : r - nmu];
-      const double dx = ldg(DX + r * rs + q), de = ldg(DE + r * rs + q);
-      const double dd = gam * de - dx;
-      double a[kPairBlk];
+    for (int i = 0; i < kPairBlk; ++i)
 #pragma unroll
-      for (int i = 0; i < kPairBlk; ++i)
-        a[i] = i < nt ? w * cw[i][q] * ldg(Vt[i] + r * st[i] + q) * (pa[i] - pb[i] * E) : 0.0;
+      for (int j = 0; j < kPairBlk; ++j) m1[i][j] = m2[i][j] = 0.0;
+    for (int f = it.f0 + lane; f < it.f1; f += kWave) {
+      const double E = edge ? ldg(C.Ebf + (size_t)k * nnu + f) : 0.0;
+      const double gam = ldg(C.gam + f);
+      for (int r = 0; r < nray; ++r) {
+        const double w = C.wm2[r < nmu ? r : r - nmu];
+        const size_t o = r * rs + (size_t)k * fp + f;
+        const double dx = ldg(C.DXR + o), de = ldg(C.DER + o);
+        const double dd = gam * de - dx;
+        double a[kPairBlk];
 #pragma unroll
-      for (int j = 0; j < kPairBlk; ++j) {
-        if (j >= nu) break;
-        const double v = ldg(Vu[j] + r * su[j] + q);
-        const double b = v * dx, c = (g0u[j] + gEu[j] * E) * v * dd;
+        for (int i = 0; i < kPairBlk; ++i)
+          a[i] = i < nt ? w * cw[i][f - ot[i]] * ldg(Vt[i] + r * rt[i] + (size_t)k * kt[i] + (f - ot[i])) *
+                              (pa[i] - pb[i] * E)
+                        : 0.0;
 #pragma unroll
-        for (int i = 0; i < kPairBlk; ++i) {
-          m1[i][j] = fma(a[i], b, m1[i][j]);
-          m2[i][j] = fma(a[i], c, m2[i][j]);
+        for (int j = 0; j < kPairBlk; ++j) {
+          if (j >= nu) break;
+          const double v = ldg(Vu[j] + r * ru[j] + (size_t)k * ku[j] + (f - ou[j]));
+          const double b = v * dx, c = (g0u[j] + gEu[j] * E) * v * dd;
+#pragma unroll
+          for (int i = 0; i < kPairBlk; ++i) {
+            m1[i][j] = fma(a[i], b, m1[i][j]);
+            m2[i][j] = fma(a[i], c, m2[i][j]);
+          }
         }
       }
     }
+#pragma unroll
+    for (int i = 0; i < kPairBlk; ++i)
+#pragma unroll
+      for (int j = 0; j < kPairBlk; ++j)
+        if (i < nt && j < nu) {
+          const double s1 = wave_sum0(m1[i][j]), s2 = wave_sum0(m2[i][j]);
+          if (lane == 0) {
+            double* dst = C.M + ((size_t)(it.e0 + i * it.es + j) * nz + k) * 2;
+            stg(dst, s1);
+            stg(dst + 1, s2);
+          }
+        }
   }
-#pragma unroll
-  for (int i = 0; i < kPairBlk; ++i)
-#pragma unroll
-    for (int j = 0; j < kPairBlk; ++j)
-      if (i < nt && j < nu) {
-        double* dst = C.M + ((size_t)(it.e0 + i * it.es + j) * nz + k) * 2;
-        stg(dst, m1[i][j]);
-        stg(dst + 1, m2[i][j]);
-      }
 }
 
 __device__ __forceinline__ void pair_item(const ColDev& C, int p, int k0) {
@@ -1497,10 +1533,8 @@ __global__ __launch_bounds__(64) void k_depthwork_vel(const ColDev* __restrict__
   const ColDev& C = cols[uni(wi.x)];
   const int mode = ldc(&C.st->mode);
   if (!C.vel || mode == kModeIdle) return;
-  const int k = uni(wi.z) + threadIdx.x;
-  if (k >= C.nz) return;
   const RItem it = ldc_rec(C.ritem + uni(wi.y));
-  rates_vel(C, it, k);
+  rates_vel(C, it, uni(wi.z));  // every lane takes part (wave sums)
 }
 
 __global__ __launch_bounds__(64) void k_pairsum_vel(const ColDev* __restrict__ cols,
@@ -1511,10 +1545,8 @@ __global__ __launch_bounds__(64) void k_pairsum_vel(const ColDev* __restrict__ c
   const ColDev& C = cols[uni(wi.x)];
   const int mode = ldc(&C.st->mode);
   if (!C.vel || mode != kModeNewton) return;
-  const int k = uni(wi.z) + threadIdx.x;
-  if (k >= C.nz) return;
   const PItem it = ldc_rec(C.pitem + uni(wi.y));
-  pair_vel(C, it, k);
+  pair_vel(C, it, uni(wi.z));  // every lane takes part (wave sums)
 }
 
 // ---------------------------------------------------------------------------

@@ -506,6 +506,34 @@ def batch6_column(i: int, nmu: int = 5) -> Problem:
     return Problem(f"batch6[{i}]", atom, atm, grid, make_collisions(atom, atm), seed)
 
 
+def batch6_vel_column(i: int, nmu: int = 5, static: bool = False) -> Problem:
+    """Column i of a batch with velocity fields: batch6's atom and recipe
+    (temperature perturbed +-10%, Nz ~ U{64..160}, Nnu ~ U{400..800} before
+    the core points) with an upward velocity step of U[2, 8] km/s,
+    U[30, 120] km wide, at U[700, 1400] km, on depths optimised for the
+    gradients and a line grid resolving the shifted cores (Sect. 3.5).
+    static: the same column (same depths and frequencies) without the
+    velocity field."""
+    seed = 5_000_000 + i
+    rng = np.random.default_rng(seed)
+    nz = int(rng.integers(64, 161))
+    nnu = int(rng.integers(400, 801))
+    vj = float(rng.uniform(2.0, 8.0))
+    width = float(rng.uniform(30.0, 120.0))
+    h0 = float(rng.uniform(700.0, 1400.0))
+    atom = _cached_atom(6)
+    h_fine = np.linspace(2000.0, -100.0, 4201)
+    fine = chromosphere(abund=ABUND[6], perturb_seed=seed, h_km=h_fine)
+    v_dopp = C_LIGHT * _doppler_rel(float(np.min(fine.T)), atom.mass_amu, atom.vturb)
+    h = optimised_heights(fine, h_fine, velocity_step(h_fine, vj, h0, width), nz, v_dopp)
+    atm = chromosphere(abund=ABUND[6], perturb_seed=seed, h_km=h)
+    vel = velocity_step(h, vj, h0, width)
+    nl, nb = _split_points(nnu, atom.nline, atom.nbf)
+    grid = make_grid(atom, atm, nl, nb, nmu, v_max=float(np.max(np.abs(vel))))
+    atm.vlos = None if static else vel
+    return Problem(f"batch6_vel[{i}]", atom, atm, grid, make_collisions(atom, atm), seed)
+
+
 def stream_request(j: int, nz_max: int = 256, nnu_max: int = 2000) -> Problem:
     """Request j of the served stream: atom uniform over 3/6/11 levels,
     Nz ~ U{48..nz_max}, Nnu ~ U{200..nnu_max}, Nmu ~ U{3..8} (defaults: the

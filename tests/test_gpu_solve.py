@@ -1,9 +1,10 @@
 """GPU JFNK solves against the FP64 oracle's converged populations.
 
-Both sides are driven to a scaled residual of 1e-12, where the root is
-determined to ~1e-12 and the Newton paths (which need not agree) no longer
-matter; converged populations and profile-averaged intensities must agree to
-1e-10 relative (FP64) and 1e-4 (FP32 formal-solution form)."""
+FP64 solves on both sides are driven to a scaled residual of 1e-14 (one
+quadratic step past 1e-12, where a stop can leave ~1e-10 of the last
+correction in the populations), so the Newton paths (which need not agree) no
+longer matter; converged populations and profile-averaged intensities must
+agree to 1e-10 relative (FP64) and 1e-4 (FP32 formal-solution form)."""
 import numpy as np
 import pytest
 
@@ -16,7 +17,7 @@ pytestmark = pytest.mark.gpu
 _ORACLE_CACHE = {}
 
 
-def oracle_root(name, maker, ftol=1e-12):
+def oracle_root(name, maker, ftol=1e-14):
     if name not in _ORACLE_CACHE:
         prob = maker()
         tb = O.setup(prob)
@@ -47,10 +48,10 @@ def test_solve_fp64_matches_oracle_root(ctx, name):
     prob, tb, ref = oracle_root(name, CASES[name])
     print(f"[case] solve fp64 {name} dims={prob.dims}", flush=True)
     col = nlte.Column(ctx, prob)
-    n, J, st, rc = col.solve(ftol=1e-12, rtol=1e-6, maxiter=60, want_J=True)
+    n, J, st, rc = col.solve(ftol=1e-14, rtol=1e-6, maxiter=60, want_J=True)
     print(st, flush=True)
     assert rc == 0 and st["status"] == 0
-    assert st["rho_inf"] <= 1e-12
+    assert st["rho_inf"] <= 1e-14
     n = to_np(n)
     assert maxrel(n, ref.n) < 1e-10
     out = col.residual(to_dev(n), want_Jbar=True)
