@@ -327,17 +327,16 @@ def f_only(ctx, nlte, problems, prec, runs=100, tune=True):
 
 def vel_bytes_per_eval(p):
     """Algorithmic HBM bytes of one column's F-mode velocity formal solution
-    (k_formal_vel): per ray-depth-point, the ray's V of every line window
-    covering the frequency (8 B each) and the ray's intensity written for the
-    line rates (8 B); per (depth, frequency), the ray-independent opacity
-    written and read back (32 B), the ingoing half of J written and read back
-    (16 B) and J (8 B)."""
+    (k_formal_vel, which also takes the line rates): per ray-depth-point, the
+    ray's V of every line window covering the frequency (8 B each); per
+    (depth, frequency), the ray-independent opacity written and read back
+    (32 B), the ingoing half of J written and read back (16 B) and J (8 B)."""
     g = p.grid
     cover = np.zeros(g.nnu)
     for t in range(p.atom.nline):
         cover[g.win_lo[t]:g.win_hi[t]] += 1.0
     nray = 2 * len(g.mu)
-    return p.atmos.nz * (nray * (8.0 * cover.sum() + 8.0 * g.nnu) + 56.0 * g.nnu)
+    return p.atmos.nz * (nray * 8.0 * cover.sum() + 56.0 * g.nnu)
 
 
 def velocity_leg(ctx, nlte, ncol):
@@ -401,7 +400,8 @@ def velocity_leg(ctx, nlte, ncol):
                                                               "assemble_ms", "solver_ms")},
     }
     out["roofline"] = {
-        "kernel": "k_formal_vel<false, 5> (F-mode velocity formal solution, opacity made per ray)",
+        "kernel": "k_formal_vel<false, 5> (F-mode velocity formal solution: opacity made per ray, "
+                  "line rates taken in the kernel)",
         "launches": prof["formal_f_launches"],
         "launch_avg_ms": prof["formal_f_ms"] / max(1, prof["formal_f_launches"]),
         "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",

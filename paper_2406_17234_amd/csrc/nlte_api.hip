@@ -380,6 +380,21 @@ __global__ void k_setup_rsp_vel(ColDev C) {
   ((double*)C.Rsp)[k * C.ntr + t] = rsp;
 }
 
+// Depth-contiguous copies of the per-ray V tables (velocity fields):
+// element (ray, k, q) of a line's [nray][nz][wl] block goes to (ray, q, k).
+__global__ void k_setup_transpose_vel(ColDev C, size_t total) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  int t = 0;
+  while (t + 1 < C.nline && (size_t)C.nray * C.tr[t + 1].voff <= i) ++t;
+  const TrDev T = C.tr[t];
+  const size_t wl = T.whi - T.wlo, blk = (size_t)C.nz * wl;
+  const size_t loc = i - (size_t)C.nray * T.voff;
+  const size_t r = loc / blk, rem = loc % blk;
+  const size_t k = rem / wl, q = rem % wl;
+  ((double*)C.VRT)[(size_t)C.nray * T.voff + r * blk + q * C.nz + k] = C.VR[i];
+}
+
 // Depth-contiguous copies for the kernels that run one lane per depth.
 __global__ void k_setup_transpose(ColDev C, int nline_tab_total) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -582,12 +597,12 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
   if (C.vel) {
     C.vlos = Lo.take<double>(nz);
     C.VR = Lo.take<double>((size_t)C.nray * nline_tab * nz + 1);
-    C.IR = Lo.take<double>((size_t)C.nray * kfp);
-    C.DXR = Lo.take<double>((size_t)C.nray * kfp);
-    C.DER = Lo.take<double>((size_t)C.nray * kfp);
+    C.VRT = Lo.take<double>((size_t)C.nray * nline_tab * nz + 1);
+    C.DXR = Lo.take<double>((size_t)C.nray * kfz);
+    C.DER = Lo.take<double>((size_t)C.nray * kfz);
   } else {
-    C.vlos = C.VR = nullptr;
-    C.IR = C.DXR = C.DER = nullptr;
+    C.vlos = C.VR = C.VRT = nullptr;
+    C.DXR = C.DER = nullptr;
   }
   C.coef = Lo.take<double>((size_t)nz * ncoef(ntr));
   C.ritem = Lo.take<RItem>(std::max(C.nritem, 1));
@@ -792,9 +807,12 @@ static nlte_status plan_column(const nlte_atmos_desc* A, const nlte_atom_desc* M
     const int s = (int)A.size();
     for (int a = cuts[c]; s > 0 && a < cuts[c + 1]; a += seg_len) {
       const int b = std::min(a + seg_len, cuts[c + 1]);
-      // rate blocks: lines and edges of A (A is sorted, lines first)
+      // rate blocks: lines and edges of A (A is sorted, lines first); the
+      // line rates of velocity-field columns come from their formal-solution
+      // kernel (entries per chunk, below)
       std::vector<int> Ln, Ed;
       for (int t : A) (t < nline ? Ln : Ed).push_back(t);
+      if (C.vel) Ln.clear();
       for (size_t li = 0, ei = 0; li < Ln.size() || ei < Ed.size();) {
         RItem R{};
         R.f0 = a;
@@ -829,7 +847,10 @@ static nlte_status plan_column(const nlte_atmos_desc* A, const nlte_atom_desc* M
   }
   C.npitem = (int)pitem.size();
   C.nment = (int)ment.size();
-  // rate entries: transition by transition, each in frequency order
+  // rate entries: transition by transition, each in frequency order;
+  // velocity-field columns: one per 64-frequency chunk a line's window meets
+  if (C.vel)
+    for (int t = 0; t < nline; ++t) rcount[t] = (tr[t].whi - 1) / kWave - tr[t].wlo / kWave + 1;
   {
     int first = 0;
     for (int t = 0; t < ntr; ++t) {
@@ -1027,6 +1048,8 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     k_setup_voigt_vel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C, in, lbase_d, lbase[nline]);
     k_setup_norm_vel<<<(nline * C.nray * nz + 63) / 64, 64, 0, stream>>>(C, in);
     k_setup_rsp_vel<<<(nline * nz + 63) / 64, 64, 0, stream>>>(C);
+    const size_t nvr = (size_t)C.nray * nline_tab * nz;
+    k_setup_transpose_vel<<<(unsigned)((nvr + 255) / 256), 256, 0, stream>>>(C, nvr);
   }
   {
     const size_t n = std::max((size_t)nz * nnu, (size_t)nline_tab * nz);
@@ -1296,6 +1319,10 @@ static size_t noalloc_layout(const ColDev& H, char* base, ColDev* C, int** flag,
   C->DetaT = Lo.take<double>(kfz);
   C->RJ = Lo.take<double>((size_t)H.nz * std::max(H.nrseg, 1) * 2);
   C->M = Lo.take<double>((size_t)H.nz * std::max(H.nment, 1) * 2);
+  if (H.vel) {  // per-ray local intensity derivatives of velocity-field columns
+    C->DXR = Lo.take<double>((size_t)H.nray * kfz);
+    C->DER = Lo.take<double>((size_t)H.nray * kfz);
+  }
   return Lo.off;
 }
 

@@ -134,7 +134,9 @@ struct ColState {
 // transitions t[i] and u[j] and is entry e0 + i * es + j.
 constexpr int kPairBlk = 4;
 
-// Rate integrals run over the same pieces as the pair sums.  One block of a
+// Rate integrals run over the same pieces as the pair sums (the line rates
+// of velocity-field columns instead come from their formal-solution kernel,
+// one entry per (line, 64-frequency chunk) of its window).  One block of a
 // piece: frequencies [f0, f1), nl lines t[0..nl) and ne edges t[nl..nl+ne)
 // among the transitions covering it (at most kRateBlk of each); the partial
 // sums of t[i] go to rate entry e[i].  A transition's entries are numbered
@@ -189,8 +191,9 @@ struct ColDev {
   const double *nstar;             // [nz][L]
   // velocity fields: line V tables of every ray, [nray][nz][wlen] per line at
   // offset nray * voff (the line tables come first, so the offsets are those
-  // of V scaled by nray); vlos [nz]
-  const double *VR, *vlos;
+  // of V scaled by nray), their depth-contiguous copies VRT ([nray][wlen][nz]
+  // at the same offsets); vlos [nz]
+  const double *VR, *VRT, *vlos;
   // FP32 copies of V, Bnu and Ebf read by the FP32-form opacity kernel (NULL
   // for FP64 columns); n-independent, so their rounding adds no noise to F
   const float *Vf, *Bnuf, *Ebff;
@@ -217,8 +220,7 @@ struct ColDev {
   double *DchiT, *DetaT;           // [nnu][zp] angle-averaged local intensity derivatives
   double *RJ;                      // [nz][nrseg][2] rate integrals over J, per segment
   double *M;                       // [nment][nz][2] pair sums of the radiative blocks
-  double *IR;                      // velocity fields: [nray][nz][fp] intensity of every ray
-  double *DXR, *DER;               // velocity fields: [nray][nz][fp] local intensity derivatives
+  double *DXR, *DER;               // velocity fields: [nray][nnu][zp] local intensity derivatives
   double *P;                       // [nz][L][L] preconditioner blocks of the last Newton-mode evaluation
   double *LU;                      // [nz][L][L] LU factors of the iterate's blocks
   double *Fsave, *Gsave;           // [nz] rate-row F and gross rate under each conservation row

@@ -889,12 +889,65 @@ static void launch_formal_mu(int nmu, int wpb, hipStream_t s, const ColDev* cols
 // frequency, as k_formal.  The ray-independent part of the opacity
 // (background, edges, scattering) is made once per depth in the first sweep
 // and kept in XS for the second; each ray adds its line part from its own V
-// table.  Outputs: J (depth-contiguous, staged through LDS as in k_formal),
-// the intensity of every ray ([ray][k][nu], for the line rates) and in
-// Newton mode the local derivatives of every ray's intensity (App. A.2, one
-// per ray: the preconditioner weighs them with the ray's own profiles).
-// Every lane of the last chunk computes (its frequency clamped into the grid)
-// and stores into the padded rows, so no store needs a guard.
+// table.  The line rates need the angle integral inside the frequency sum
+// (sum_nu cw sum_rays (w_m/2) V_ray I_ray, Eqs. Rij, Rji), so the kernel
+// takes them itself while every ray's intensity is in registers: per depth
+// and line window covering the chunk, a fixed-order wave sum over the
+// chunk's 64 frequencies gives one rate entry per (line, chunk); the
+// ingoing sweep parks its half in the entry's second slot and the outgoing
+// sweep completes it (deterministic, independent of batching; the edges'
+// rates are the static sums over J).  Outputs: J (depth-contiguous, staged
+// through LDS as in k_formal), the line rate entries and in Newton mode the
+// local derivatives of every ray's intensity (App. A.2, one per ray: the
+// preconditioner weighs them with the ray's own profiles).  Every lane of
+// the last chunk computes (its frequency clamped into the grid) and stores
+// into the padded rows, so no store needs a guard; its lanes beyond the grid
+// add nothing to the rates.
+
+// Wave-wide sum in a fixed butterfly order: lane 0's value is the same for
+// every launch.
+__device__ __forceinline__ double wave_sum0(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Line rate entries of depth k from the NMU rays r0 .. r0 + NMU - 1 of one
+// sweep: per line window covering the chunk, sum over the chunk's
+// frequencies of cw sum_m (w_m/2) V_ray I_ray.  The ingoing sweep (first)
+// parks its sum in the entry's second slot; the outgoing sweep adds its own
+// and writes the entry (second slot back to zero, as for every line entry).
+template <int NMU>
+__device__ __forceinline__ void vel_rate_step(const ColDev& C, int chunk, int k, int f, int fc,
+                                              int r0, const double (&I)[NMU], const double (&wm2)[NMU],
+                                              bool first) {
+  const int nz = C.nz, nray = C.nray, nnu = C.nnu;
+  const int l0 = uni(C.ch_lptr[chunk]), l1 = uni(C.ch_lptr[chunk + 1]);
+  double* row = C.RJ + (size_t)k * C.nrseg * 2;
+  for (int j = l0; j < l1; ++j) {
+    const int t = uni(C.ch_line[j]);
+    const TrDev& T = C.tr[t];
+    const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
+    const int q = fc - wlo;
+    const bool in = f < nnu && q >= 0 && q < wl;
+    const size_t rstep = (size_t)nz * wl;
+    const double* vr = C.VR + (size_t)nray * uni(T.voff) + (size_t)r0 * rstep + (size_t)k * wl + (in ? q : 0);
+    double u = 0.0;
+#pragma unroll
+    for (int m = 0; m < NMU; ++m) u = fmar(wm2[m] * ldg(vr + m * rstep), I[m], u);
+    const double x = in ? ldg(C.cw + uni(T.cwoff) + q) * u : 0.0;
+    const double tot = wave_sum0(x);
+    if ((threadIdx.x & 63) == 0) {
+      double* ent = row + 2 * (uni(T.sfirst) + chunk - wlo / kWave);
+      if (first) {
+        stg(ent + 1, tot);
+      } else {
+        stg(ent, ldg(ent + 1) + tot);
+        stg(ent + 1, 0.0);
+      }
+    }
+  }
+}
 
 // Ray-independent chi and eta at (k, fc): background, edges, scattering.
 __device__ __forceinline__ void vel_base(const ColDev& C, int chunk, int k, int fc, double& chi0,
@@ -960,16 +1013,26 @@ __device__ __forceinline__ void vel_rays(const ColDev& C, int chunk, int k, int 
   }
 }
 
+// LDS per wave of the velocity formal solution: the J tile of KFV depths
+// and, in Newton mode, one tile of KDV depths per ray and derivative.
+constexpr int KFV = 8, KDV = 4;
+template <bool PM, int NMU> struct VelStage {
+  static constexpr int doubles = (KFV + (PM ? 2 * NMU * KDV : 0)) * kWave;
+};
+
 template <bool PM, int NMU>
-__device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int lane, double* tJ) {
-  constexpr int KF = 8;
+__device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int lane, double* tile) {
+  constexpr int KF = KFV, KD = KDV;
+  double* tJ = tile;
+  double* tX = tile + KF * kWave;            // [NMU][KD * 64] per-ray D_chi
+  double* tE = tX + NMU * KD * kWave;        // [NMU][KD * 64] per-ray D_eta
   const int nz = C.nz, nnu = C.nnu, fp = C.fp, zp = C.zp;
   const int f0 = chunk * kWave, f = f0 + lane;
   const int fc = f < nnu ? f : nnu - 1;
   const double* __restrict__ dzt = (const double*)C.coef + ((size_t)(C.ntr + 1) * nz) * 2 + 1;  // stride 2
   double* __restrict__ xb = C.XS;  // [nz][fp][2] ray-independent chi, eta
   double* __restrict__ jm = C.Jm;  // [nz][fp] ingoing half of J
-  const size_t rs = (size_t)nz * fp;  // ray stride of IR, DXR, DER
+  const size_t rs = (size_t)nnu * zp;  // ray stride of DXR, DER ([nray][nnu][zp])
   double i2mu[NMU], mu2[NMU], wm2[NMU];
 #pragma unroll
   for (int m = 0; m < NMU; ++m) {
@@ -989,13 +1052,23 @@ __device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int 
 #pragma unroll
   for (int m = 0; m < NMU; ++m) {
     I[m] = 0.0;
-    const size_t o = (size_t)(NMU + m) * rs + f;
-    stg(C.IR + o, 0.0);
-    if (PM) {
-      stg(C.DXR + o, 0.0);
-      stg(C.DER + o, 0.0);
+    if (PM) {  // ingoing rays at the top: I prescribed, no local dependence
+      stage_put<KD>(tX + m * KD * kWave, 0, lane, 0.0);
+      stage_put<KD>(tE + m * KD * kWave, 0, lane, 0.0);
     }
   }
+  // Newton mode: the ingoing rays' derivatives leave KD depths at a time
+  auto flush_down = [&](int k) {
+    if (PM && (k % KD == KD - 1 || k == nz - 1)) {
+#pragma unroll
+      for (int m = 0; m < NMU; ++m) {
+        stage_flush<KD>(tX + m * KD * kWave, C.DXR + (NMU + m) * rs, k - k % KD, nz, zp, f0, nnu, lane);
+        stage_flush<KD>(tE + m * KD * kWave, C.DER + (NMU + m) * rs, k - k % KD, nz, zp, f0, nnu, lane);
+      }
+    }
+  };
+  flush_down(0);
+  vel_rate_step<NMU>(C, chunk, 0, f, fc, NMU, I, wm2, true);
   for (int k = 1; k < nz; ++k) {
     vel_base(C, chunk, k, fc, chi0, eta0);
     const size_t kx = (size_t)k * fp + f;
@@ -1012,19 +1085,30 @@ __device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int 
       const double Iup = I[m];
       I[m] = fmar(e, Iup, fmar(q, Sp[m], a * (Sx[m] - Sp[m])));
       jac = fmar(wm2[m], I[m], jac);
-      const size_t o = (size_t)(NMU + m) * rs + kx;
-      stg(C.IR + o, I[m]);
       if (PM) {  // c_chi, c_eta of App. A.2 for this ray
         const double rc = 1.0 / ch[m];
-        stg(C.DXR + o, -(Sx[m] * rc) * a + dz * (i2mu[m] * (e * (Sp[m] - Iup) - (Sp[m] - Sx[m]) * bx)));
-        stg(C.DER + o, a * rc);
+        stage_put<KD>(tX + m * KD * kWave, k, lane,
+                      -(Sx[m] * rc) * a + dz * (i2mu[m] * (e * (Sp[m] - Iup) - (Sp[m] - Sx[m]) * bx)));
+        stage_put<KD>(tE + m * KD * kWave, k, lane, a * rc);
       }
       chp[m] = ch[m];
       Sp[m] = Sx[m];
     }
     stg(jm + kx, jac);
+    flush_down(k);
+    vel_rate_step<NMU>(C, chunk, k, f, fc, NMU, I, wm2, true);
   }
 
+  // Newton mode: the outgoing rays' derivatives leave KD depths at a time
+  auto flush_up = [&](int k) {
+    if (PM && k % KD == 0) {
+#pragma unroll
+      for (int m = 0; m < NMU; ++m) {
+        stage_flush<KD>(tX + m * KD * kWave, C.DXR + m * rs, k, nz, zp, f0, nnu, lane);
+        stage_flush<KD>(tE + m * KD * kWave, C.DER + m * rs, k, nz, zp, f0, nnu, lane);
+      }
+    }
+  };
   // ---- sweep 2: outgoing rays (m), bottom -> top, I+ = B at the bottom ----
   {
     const int k = nz - 1;
@@ -1036,15 +1120,15 @@ __device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int 
     for (int m = 0; m < NMU; ++m) {
       I[m] = Bb;
       jp = fmar(wm2[m], Bb, jp);
-      const size_t o = (size_t)m * rs + kx;
-      stg(C.IR + o, Bb);
-      if (PM) {
-        stg(C.DXR + o, 0.0);
-        stg(C.DER + o, 0.0);
+      if (PM) {  // outgoing rays at the bottom: I prescribed
+        stage_put<KD>(tX + m * KD * kWave, k, lane, 0.0);
+        stage_put<KD>(tE + m * KD * kWave, k, lane, 0.0);
       }
     }
+    vel_rate_step<NMU>(C, chunk, k, f, fc, 0, I, wm2, false);
     stage_put<KF>(tJ, k, lane, ldg(jm + kx) + jp);
     if (k % KF == 0) stage_flush<KF>(tJ, C.JT, k, nz, zp, f0, nnu, lane);
+    flush_up(k);
   }
   for (int k = nz - 2; k >= 0; --k) {
     const size_t kx = (size_t)k * fp + f;
@@ -1059,18 +1143,19 @@ __device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int 
       const double Iup = I[m];
       I[m] = fmar(e, Iup, fmar(q, Sp[m], a * (Sx[m] - Sp[m])));
       jp = fmar(wm2[m], I[m], jp);
-      const size_t o = (size_t)m * rs + kx;
-      stg(C.IR + o, I[m]);
       if (PM) {  // a_chi, a_eta of App. A.2 for this ray
         const double rc = 1.0 / ch[m];
-        stg(C.DXR + o, -(Sx[m] * rc) * a + dz * (i2mu[m] * (e * (Sp[m] - Iup) - (Sp[m] - Sx[m]) * bx)));
-        stg(C.DER + o, a * rc);
+        stage_put<KD>(tX + m * KD * kWave, k, lane,
+                      -(Sx[m] * rc) * a + dz * (i2mu[m] * (e * (Sp[m] - Iup) - (Sp[m] - Sx[m]) * bx)));
+        stage_put<KD>(tE + m * KD * kWave, k, lane, a * rc);
       }
       chp[m] = ch[m];
       Sp[m] = Sx[m];
     }
+    vel_rate_step<NMU>(C, chunk, k, f, fc, 0, I, wm2, false);
     stage_put<KF>(tJ, k, lane, ldg(jm + kx) + jp);
     if (k % KF == 0) stage_flush<KF>(tJ, C.JT, k, nz, zp, f0, nnu, lane);
+    flush_up(k);
   }
 }
 
@@ -1085,18 +1170,20 @@ __global__ __launch_bounds__(256) void k_formal_vel(const ColDev* __restrict__ c
   const int chunk = uni(tiles[tid].chunk);
   const ColDev& C = cols[col];
   if (uni(C.st->mode) != (PM ? kModeNewton : kModeF)) return;
-  extern __shared__ double stage[];  // [waves per block][8 * 64]
-  formal_tile_vel<PM, NMU>(C, chunk, lane, stage + wave * (8 * kWave));
+  extern __shared__ double stage[];  // [waves per block][VelStage doubles]
+  formal_tile_vel<PM, NMU>(C, chunk, lane, stage + wave * VelStage<PM, NMU>::doubles);
 }
 
 template <bool PM>
 static void launch_formal_vel(int nmu, int wpb, hipStream_t s, const ColDev* cols, const Tile* tiles,
                               int ntiles) {
   const int blocks = (ntiles + wpb - 1) / wpb;
-  const size_t lds = (size_t)wpb * 8 * kWave * sizeof(double);
   switch (nmu) {
-#define NLTE_VEL_CASE(M) \
-  case M: k_formal_vel<PM, M><<<blocks, 64 * wpb, lds, s>>>(cols, tiles, ntiles); break;
+#define NLTE_VEL_CASE(M)                                                                   \
+  case M:                                                                                  \
+    k_formal_vel<PM, M><<<blocks, 64 * wpb, (size_t)wpb * VelStage<PM, M>::doubles * 8, s>>>( \
+        cols, tiles, ntiles);                                                              \
+    break;
     NLTE_VEL_CASE(1) NLTE_VEL_CASE(2) NLTE_VEL_CASE(3) NLTE_VEL_CASE(4)
     NLTE_VEL_CASE(5) NLTE_VEL_CASE(6) NLTE_VEL_CASE(7) NLTE_VEL_CASE(8)
 #undef NLTE_VEL_CASE
@@ -1118,7 +1205,7 @@ static void launch_formal_vel(int nmu, int wpb, hipStream_t s, const ColDev* col
 // TB: line-table precision (float for FP32-form evaluations).  J stays FP64
 // here: in the FP32 form a J rounded to FP32 before these sums sets a noise
 // floor on F that doubled the share of columns needing the FP64 fallback.
-template <typename TB, int NL, int NE, bool LINES = true>
+template <typename TB, int NL, int NE>
 __device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, int k,
                                             const TB* __restrict__ VTt, const TB* __restrict__ EbfTt) {
   const int nz = C.nz, zp = C.zp, f0 = it.f0, nf = it.f1 - it.f0;
@@ -1151,10 +1238,8 @@ __device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, in
   for (int q = 0; q < nf; ++q) {
     const size_t o = (size_t)q * zp;
     const double j = ldg(J + o);
-    if (LINES) {
 #pragma unroll
-      for (int i = 0; i < NL; ++i) sl[i] = fma(cl[i][q] * (double)ldg(vl[i] + (size_t)q * nz), j, sl[i]);
-    }
+    for (int i = 0; i < NL; ++i) sl[i] = fma(cl[i][q] * (double)ldg(vl[i] + (size_t)q * nz), j, sl[i]);
     if (NE > 0) {
       const double e = (double)ldg(E + o);
 #pragma unroll
@@ -1166,12 +1251,10 @@ __device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, in
     }
   }
   double* row = C.RJ + (size_t)k * C.nrseg * 2;
-  if (LINES) {
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      stg(row + 2 * it.e[i], sl[i]);
-      stg(row + 2 * it.e[i] + 1, 0.0);
-    }
+  for (int i = 0; i < NL; ++i) {
+    stg(row + 2 * it.e[i], sl[i]);
+    stg(row + 2 * it.e[i] + 1, 0.0);
   }
 #pragma unroll
   for (int i = 0; i < NE; ++i) {
@@ -1180,12 +1263,12 @@ __device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, in
   }
 }
 
-template <typename TB, bool LINES = true>
+template <typename TB>
 __device__ __forceinline__ void rates_shape(const ColDev& C, const RItem& it, int k,
                                             const TB* __restrict__ VTt, const TB* __restrict__ EbfTt) {
   switch (it.nl * 8 + it.ne) {
 #define RB(L, E) \
-  case L * 8 + E: rates_block<TB, L, E, LINES>(C, it, k, VTt, EbfTt); break;
+  case L * 8 + E: rates_block<TB, L, E>(C, it, k, VTt, EbfTt); break;
     RB(0, 1) RB(0, 2) RB(0, 3) RB(0, 4)
     RB(1, 0) RB(1, 1) RB(1, 2) RB(1, 3) RB(1, 4)
     RB(2, 0) RB(2, 1) RB(2, 2) RB(2, 3) RB(2, 4)
@@ -1193,53 +1276,6 @@ __device__ __forceinline__ void rates_shape(const ColDev& C, const RItem& it, in
     RB(4, 0) RB(4, 1) RB(4, 2) RB(4, 3) RB(4, 4)
 #undef RB
     default: break;
-  }
-}
-
-// Velocity fields: the line rates keep the angle integral inside the
-// frequency sum, sum_nu cw sum_rays (w_m/2) V_ray I_ray, since V depends on
-// the ray (Eqs. Rij, Rji); the edges' cross-sections do not, and their sums
-// over J are those of the static case.  Same pieces and entries as above.
-// The per-ray intensities and V tables are frequency-contiguous, so the line
-// sums run one lane per frequency of the piece, depth by depth, each ending
-// in a wave sum of fixed order (lane 0's butterfly): deterministic and
-// independent of batching.  The edges keep one lane per depth.
-__device__ __forceinline__ double wave_sum0(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;  // lane 0's value has a fixed order
-}
-
-__device__ void rates_vel(const ColDev& C, const RItem& it, int k0) {
-  const int lane = threadIdx.x;
-  const int nz = C.nz, fp = C.fp, nray = C.nray, nmu = C.nmu;
-  const size_t rs = (size_t)nz * fp;
-  if (it.ne > 0 && k0 + lane < nz) rates_shape<double, false>(C, it, k0 + lane, C.VT, C.EbfT);
-  const int kend = min(k0 + kWave, nz);
-  for (int i = 0; i < it.nl; ++i) {
-    const TrDev& T = C.tr[it.t[i]];
-    const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
-    const size_t vs = (size_t)nz * wl;
-    const double* __restrict__ vb = C.VR + (size_t)nray * uni(T.voff);
-    const double* __restrict__ cw = C.cw + uni(T.cwoff);
-    const int e = it.e[i];
-    for (int k = k0; k < kend; ++k) {
-      double acc = 0.0;
-      for (int f = it.f0 + lane; f < it.f1; f += kWave) {
-        double u = 0.0;
-        const int q = f - wlo;
-        for (int r = 0; r < nray; ++r)
-          u = fma(C.wm2[r < nmu ? r : r - nmu] * ldg(vb + r * vs + (size_t)k * wl + q),
-                  ldg(C.IR + r * rs + (size_t)k * fp + f), u);
-        acc = fma(cw[q], u, acc);
-      }
-      const double tot = wave_sum0(acc);
-      if (lane == 0) {
-        double* row = C.RJ + (size_t)k * C.nrseg * 2;
-        stg(row + 2 * e, tot);
-        stg(row + 2 * e + 1, 0.0);
-      }
-    }
   }
 }
 
@@ -1251,7 +1287,8 @@ __device__ void rates_vel(const ColDev& C, const RItem& it, int k0) {
 __device__ __forceinline__ void rates_item(const ColDev& C, int b, int k0) {
   const int mode = ldc(&C.st->mode), prec = ldc(&C.st->cur_prec);
   const RItem it = ldc_rec(C.ritem + b);
-  if (mode == kModeIdle || C.vel) return;  // velocity-field columns: k_depthwork_vel
+  if (mode == kModeIdle) return;  // (velocity-field columns list edges only: their line
+                                  // rates come from the formal-solution kernel)
   const int k = k0 + threadIdx.x;
   if (k >= C.nz) return;
   if (prec == NLTE_FP32_FORM)
@@ -1370,108 +1407,100 @@ __device__ __forceinline__ void pair_block(const ColDev& C, const PItem& it, int
 // Velocity fields: the same pair sums with the angle integral inside,
 //   M1 = sum_nu cw_t sum_rays (w_m/2) A_t,ray V_t',ray D_chi,ray,
 //   M2 = sum_nu cw_t sum_rays (w_m/2) A_t,ray g_t' V_t',ray (2 h nu^3/c^2 D_eta,ray - D_chi,ray),
-// each ray with its own line profiles and local intensity derivatives (the
-// edges' cross-sections are the same for every ray).  One lane per frequency
-// of the piece, depth by depth (the per-ray operands are frequency-
-// contiguous), each depth's sums ending in fixed-order wave sums.
-__device__ void pair_vel(const ColDev& C, const PItem& it, int k0) {
-  const int lane = threadIdx.x;
-  const int nz = C.nz, L = C.L, fp = C.fp, nnu = C.nnu, nray = C.nray, nmu = C.nmu, nline = C.nline;
-  const int nt = it.nt, nu = it.nu;
-  const size_t rs = (size_t)nz * fp;
-  // per side: table base (indexed by (ray, k, f)), steps, and level data
+// each ray with its own line profiles (depth-contiguous copies of the per-ray
+// V tables) and local intensity derivatives (written depth-contiguous by the
+// Newton-mode formal solution); the edges' cross-sections are the same for
+// every ray.  One lane per depth, as pair_block.
+__device__ void pair_vel(const ColDev& C, const PItem& it, int k) {
+  const int nz = C.nz, L = C.L, zp = C.zp, nray = C.nray, nmu = C.nmu, nline = C.nline;
+  const int f0 = it.f0, nf = it.f1 - it.f0, nt = it.nt, nu = it.nu;
+  const size_t rs = (size_t)C.nnu * zp;
   const double *Vt[kPairBlk], *Vu[kPairBlk], *cw[kPairBlk];
   size_t rt[kPairBlk], ru[kPairBlk];  // ray steps (0: edge)
-  int kt[kPairBlk], ku[kPairBlk];     // depth steps (0: edge)
-  int ot[kPairBlk], ou[kPairBlk];     // first frequency of the window
+  int ft[kPairBlk], fu[kPairBlk];     // frequency steps (nz: line, 1: edge)
+  double pa[kPairBlk], pb[kPairBlk], g0u[kPairBlk], gEu[kPairBlk];
   bool edge = false;
 #pragma unroll
   for (int i = 0; i < kPairBlk; ++i) {
     const int t = it.t[i < nt ? i : 0];
     const TrDev& T = C.tr[t];
     const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
-    const bool line = t < nline;
-    Vt[i] = line ? C.VR + (size_t)nray * uni(T.voff) : C.V + uni(T.voff);
-    rt[i] = line ? (size_t)nz * wl : 0;
-    kt[i] = line ? wl : 0;
-    ot[i] = wlo;
-    cw[i] = C.cw + uni(T.cwoff);
-    edge |= i < nt && !line;
+    const double nl = C.eval_n[k * L + uni(T.lo)], nup = C.eval_n[k * L + uni(T.up)];
+    if (t < nline) {
+      Vt[i] = C.VRT + (size_t)nray * uni(T.voff) + (size_t)(f0 - wlo) * nz + k;
+      rt[i] = (size_t)nz * wl;
+      ft[i] = nz;
+      pa[i] = nl - uni(T.g) * nup;
+      pb[i] = 0.0;
+    } else {
+      Vt[i] = C.V + uni(T.voff) + (f0 - wlo);
+      rt[i] = 0;
+      ft[i] = 1;
+      pa[i] = nl;
+      pb[i] = C.rho_bf[k * C.nbf + (t - nline)] * nup;
+      edge |= i < nt;
+    }
+    cw[i] = C.cw + uni(T.cwoff) + (f0 - wlo);
     const int u = it.u[i < nu ? i : 0];
     const TrDev& U = C.tr[u];
     const int ulo = uni(U.wlo), ul = uni(U.whi) - ulo;
-    const bool uline = u < nline;
-    Vu[i] = uline ? C.VR + (size_t)nray * uni(U.voff) : C.V + uni(U.voff);
-    ru[i] = uline ? (size_t)nz * ul : 0;
-    ku[i] = uline ? ul : 0;
-    ou[i] = ulo;
-    edge |= i < nu && !uline;
-  }
-  const int kend = min(k0 + kWave, nz);
-  for (int k = k0; k < kend; ++k) {
-    double pa[kPairBlk], pb[kPairBlk], g0u[kPairBlk], gEu[kPairBlk];
-#pragma unroll
-    for (int i = 0; i < kPairBlk; ++i) {
-      const int t = it.t[i < nt ? i : 0];
-      const TrDev& T = C.tr[t];
-      const double nl = C.eval_n[k * L + uni(T.lo)], nup = C.eval_n[k * L + uni(T.up)];
-      if (t < nline) {
-        pa[i] = nl - uni(T.g) * nup;
-        pb[i] = 0.0;
-      } else {
-        pa[i] = nl;
-        pb[i] = C.rho_bf[k * C.nbf + (t - nline)] * nup;
-      }
-      const int u = it.u[i < nu ? i : 0];
-      const TrDev& U = C.tr[u];
-      g0u[i] = u < nline ? uni(U.g) : 0.0;
-      gEu[i] = u < nline ? 0.0 : C.rho_bf[k * C.nbf + (u - nline)];
+    if (u < nline) {
+      Vu[i] = C.VRT + (size_t)nray * uni(U.voff) + (size_t)(f0 - ulo) * nz + k;
+      ru[i] = (size_t)nz * ul;
+      fu[i] = nz;
+      g0u[i] = uni(U.g);
+      gEu[i] = 0.0;
+    } else {
+      Vu[i] = C.V + uni(U.voff) + (f0 - ulo);
+      ru[i] = 0;
+      fu[i] = 1;
+      g0u[i] = 0.0;
+      gEu[i] = C.rho_bf[k * C.nbf + (u - nline)];
+      edge |= i < nu;
     }
-    double m1[kPairBlk][kPairBlk], m2[kPairBlk][kPairBlk];
+  }
+  const double* DX = C.DXR + (size_t)f0 * zp + k;
+  const double* DE = C.DER + (size_t)f0 * zp + k;
+  const double* EB = edge ? C.EbfT + (size_t)f0 * zp + k : DX;  // DX: any valid address
+  double m1[kPairBlk][kPairBlk], m2[kPairBlk][kPairBlk];
 #pragma unroll
-    for (int i = 0; i < kPairBlk; ++i)
+  for (int i = 0; i < kPairBlk; ++i)
 #pragma unroll
-      for (int j = 0; j < kPairBlk; ++j) m1[i][j] = m2[i][j] = 0.0;
-    for (int f = it.f0 + lane; f < it.f1; f += kWave) {
-      const double E = edge ? ldg(C.Ebf + (size_t)k * nnu + f) : 0.0;
-      const double gam = ldg(C.gam + f);
-      for (int r = 0; r < nray; ++r) {
-        const double w = C.wm2[r < nmu ? r : r - nmu];
-        const size_t o = r * rs + (size_t)k * fp + f;
-        const double dx = ldg(C.DXR + o), de = ldg(C.DER + o);
-        const double dd = gam * de - dx;
-        double a[kPairBlk];
+    for (int j = 0; j < kPairBlk; ++j) m1[i][j] = m2[i][j] = 0.0;
+  for (int q = 0; q < nf; ++q) {
+    const size_t oq = (size_t)q * zp;
+    const double E = edge ? ldg(EB + oq) : 0.0;
+    const double gam = ldg(C.gam + f0 + q);
+    for (int r = 0; r < nray; ++r) {
+      const double w = C.wm2[r < nmu ? r : r - nmu];
+      const double dx = ldg(DX + r * rs + oq), de = ldg(DE + r * rs + oq);
+      const double dd = gam * de - dx;
+      double a[kPairBlk];
 #pragma unroll
-        for (int i = 0; i < kPairBlk; ++i)
-          a[i] = i < nt ? w * cw[i][f - ot[i]] * ldg(Vt[i] + r * rt[i] + (size_t)k * kt[i] + (f - ot[i])) *
-                              (pa[i] - pb[i] * E)
-                        : 0.0;
+      for (int i = 0; i < kPairBlk; ++i)
+        a[i] = i < nt ? w * cw[i][q] * ldg(Vt[i] + r * rt[i] + (size_t)q * ft[i]) * (pa[i] - pb[i] * E) : 0.0;
 #pragma unroll
-        for (int j = 0; j < kPairBlk; ++j) {
-          if (j >= nu) break;
-          const double v = ldg(Vu[j] + r * ru[j] + (size_t)k * ku[j] + (f - ou[j]));
-          const double b = v * dx, c = (g0u[j] + gEu[j] * E) * v * dd;
+      for (int j = 0; j < kPairBlk; ++j) {
+        if (j >= nu) break;
+        const double v = ldg(Vu[j] + r * ru[j] + (size_t)q * fu[j]);
+        const double b = v * dx, c = (g0u[j] + gEu[j] * E) * v * dd;
 #pragma unroll
-          for (int i = 0; i < kPairBlk; ++i) {
-            m1[i][j] = fma(a[i], b, m1[i][j]);
-            m2[i][j] = fma(a[i], c, m2[i][j]);
-          }
+        for (int i = 0; i < kPairBlk; ++i) {
+          m1[i][j] = fma(a[i], b, m1[i][j]);
+          m2[i][j] = fma(a[i], c, m2[i][j]);
         }
       }
     }
-#pragma unroll
-    for (int i = 0; i < kPairBlk; ++i)
-#pragma unroll
-      for (int j = 0; j < kPairBlk; ++j)
-        if (i < nt && j < nu) {
-          const double s1 = wave_sum0(m1[i][j]), s2 = wave_sum0(m2[i][j]);
-          if (lane == 0) {
-            double* dst = C.M + ((size_t)(it.e0 + i * it.es + j) * nz + k) * 2;
-            stg(dst, s1);
-            stg(dst + 1, s2);
-          }
-        }
   }
+#pragma unroll
+  for (int i = 0; i < kPairBlk; ++i)
+#pragma unroll
+    for (int j = 0; j < kPairBlk; ++j)
+      if (i < nt && j < nu) {
+        double* dst = C.M + ((size_t)(it.e0 + i * it.es + j) * nz + k) * 2;
+        stg(dst, m1[i][j]);
+        stg(dst + 1, m2[i][j]);
+      }
 }
 
 __device__ __forceinline__ void pair_item(const ColDev& C, int p, int k0) {
@@ -1522,21 +1551,9 @@ __global__ __launch_bounds__(64) void k_pairsum(const ColDev* __restrict__ cols,
   pair_item(cols[col], idx, k0);
 }
 
-// The rate and pair-sum items of velocity-field columns, over the same work
-// lists (the other columns' items return at once): kernels of their own, so
-// that the ray loops do not cost the static kernels registers.
-__global__ __launch_bounds__(64) void k_depthwork_vel(const ColDev* __restrict__ cols,
-                                                      const int4* __restrict__ work, int nwork) {
-  const int w = xcd_item(blockIdx.x, gridDim.x);
-  if (w >= nwork) return;
-  const int4 wi = work[w];
-  const ColDev& C = cols[uni(wi.x)];
-  const int mode = ldc(&C.st->mode);
-  if (!C.vel || mode == kModeIdle) return;
-  const RItem it = ldc_rec(C.ritem + uni(wi.y));
-  rates_vel(C, it, uni(wi.z));  // every lane takes part (wave sums)
-}
-
+// The pair-sum items of velocity-field columns, over the same work list (the
+// other columns' items return at once): a kernel of its own, so that the ray
+// loops do not cost the static kernel registers.
 __global__ __launch_bounds__(64) void k_pairsum_vel(const ColDev* __restrict__ cols,
                                                     const int4* __restrict__ work, int nwork) {
   const int w = xcd_item(blockIdx.x, gridDim.x);
@@ -1546,7 +1563,9 @@ __global__ __launch_bounds__(64) void k_pairsum_vel(const ColDev* __restrict__ c
   const int mode = ldc(&C.st->mode);
   if (!C.vel || mode != kModeNewton) return;
   const PItem it = ldc_rec(C.pitem + uni(wi.y));
-  pair_vel(C, it, uni(wi.z));  // every lane takes part (wave sums)
+  const int k = uni(wi.z) + threadIdx.x;
+  if (k >= C.nz) return;
+  pair_vel(C, it, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -1841,12 +1860,9 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
                                                    bw.nrate - bw.nrate0);
   bool any_vel = false;
   for (int g = 0; g < bw.ngroup; ++g) any_vel |= bw.groups[g].vel != 0;
-  if (any_vel) {
-    if (bw.nrate0 > 0) k_depthwork_vel<<<bw.nrate0, 64, 0, s>>>(bw.cols, bw.rate_work, bw.nrate0);
-    if (bw.any_newton && bw.nrate > bw.nrate0)
-      k_pairsum_vel<<<bw.nrate - bw.nrate0, 64, 0, s>>>(bw.cols, bw.rate_work + bw.nrate0,
-                                                         bw.nrate - bw.nrate0);
-  }
+  if (any_vel && bw.any_newton && bw.nrate > bw.nrate0)
+    k_pairsum_vel<<<bw.nrate - bw.nrate0, 64, 0, s>>>(bw.cols, bw.rate_work + bw.nrate0,
+                                                       bw.nrate - bw.nrate0);
   if (ev) chk(hipEventRecord(ev[3], s));
   {
     const int nsub = (bw.maxnz + kAsmDepths - 1) / kAsmDepths;

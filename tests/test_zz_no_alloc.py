@@ -83,3 +83,28 @@ def test_noalloc_rejects_a_column_beyond_the_scratch():
     out = col.residual(n)
     assert np.all(np.isfinite(to_np(out["F"])))
     col.close()
+
+
+def test_noalloc_velocity_columns_equal_residual():
+    """Velocity-field columns (their per-ray intensity derivatives also in
+    the fixed scratch): the allocation-free call equals nlte_residual bit for
+    bit, a larger column first, then a smaller one."""
+    require_gpu()
+    import copy
+
+    import torch
+    from paper_2406_17234_amd import nlte
+    ctx = nlte.Context(0)
+    big = S.chromo6_vel(nz=40, nnu=300, nmu=3)
+    small = copy.deepcopy(S.tiny())
+    small.atmos.vlos = np.linspace(3e5, -2e5, small.atmos.nz)
+    kw = dict(want_J=True, want_R=True, want_Jbar=True, want_P=True)
+    for prob in (big, small):
+        print(f"[case] noalloc velocity {prob.name} dims={prob.dims}", flush=True)
+        col = nlte.Column(ctx, prob, precision=nlte.FP64)
+        n = to_dev(perturbed(O.setup(prob).nstar, seed=9, scale=0.25))
+        a, b = _both(col, n, **kw)
+        torch.cuda.synchronize()
+        for k in OUTS:
+            assert np.array_equal(to_np(a[k]), to_np(b[k])), (prob.name, k)
+        col.close()
