@@ -39,17 +39,25 @@ OPS_PER_DP = 10.0 + 0.5 * 4 + 0.5 * 4
 # a plain copy kernel; valid only for the kernel source they were taken on
 # (hash of its files).
 TRAFFIC = {
-    "batch6": {"source": "e2ab551a0d375f40", "bytes_per_launch": 3.7857e+09,
-               "read": 8.35217e+11 / 380, "written": 6.03358e+11 / 380},
+    "batch6": {"source": "973add010432f075", "bytes_per_launch": 6.1028e+09,
+               "read": 7.0884e+11 / 200, "written": 5.1173e+11 / 200},
 }
+# the same for the F-mode velocity formal solution of the 512-column velocity
+# batch (mean over the profiled solve's 140 launches)
+TRAFFIC_VEL = {"source": "24dc45070f6817d1", "columns": 512, "bytes_per_launch": 6.366e+09,
+               "read": 5.355e+09, "written": 1.011e+09}
 KERNEL_SOURCES = ["paper_2406_17234_amd/csrc/nlte_residual.hip",
+                  "paper_2406_17234_amd/csrc/nlte_kernels.h",
                   "paper_2406_17234_amd/csrc/nlte_internal.h"]
+VEL_KERNEL_SOURCES = ["paper_2406_17234_amd/csrc/nlte_velocity.hip",
+                      "paper_2406_17234_amd/csrc/nlte_kernels.h",
+                      "paper_2406_17234_amd/csrc/nlte_internal.h"]
 
 
-def kernel_source_hash():
+def kernel_source_hash(files=KERNEL_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -407,7 +415,10 @@ def velocity_leg(ctx, nlte, ncol):
         "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
         "frac": achieved / 8000.0 if achieved else None,
         "algorithmic_bytes_per_launch": nbytes / max(1, prof["formal_f_launches"]),
-        "traffic": None,
+        "traffic": (TRAFFIC_VEL["bytes_per_launch"]
+                    if TRAFFIC_VEL["source"] == kernel_source_hash(VEL_KERNEL_SOURCES)
+                    and ncol == TRAFFIC_VEL["columns"] else None),
+        "traffic_unit": "bytes per launch (mean)",
     }
     out["f_only_fp64"] = f_only(ctx, nlte, probs, nlte.FP64)
     out["f_only_fp64_static_twin"] = f_only(ctx, nlte, [S.batch6_vel_column(i, static=True)

@@ -921,10 +921,10 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
                                           const double* C_up, int32_t prec_arg,
                                           hipStream_t stream, nlte_column** out) {
   if (!ctx || !out) return set_err(NLTE_E_INVALID, "NULL ctx/out");
-  // the setup checks its launches with hipGetLastError: start from a clear
-  // state so that an error left by an unrelated earlier call is not reported
-  // as this column's
-  (void)hipGetLastError();
+  // an error left pending by an unrelated earlier call stays pending for its
+  // owner (peeked, not cleared); the setup launches are judged by whether
+  // they leave a different one
+  const hipError_t pending = hipPeekAtLastError();
   ColumnPlan P;
   const nlte_status ps = plan_column(A, M, G, C_up, prec_arg, P);
   if (ps != NLTE_OK) return ps;
@@ -1061,7 +1061,9 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
     const size_t n = std::max(nv, (size_t)nz * nnu);
     k_setup_f32<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(C, nv, nvt);
   }
-  e = hipGetLastError();
+  e = hipPeekAtLastError();
+  if (e == pending) e = hipSuccess;  // nothing new from the setup launches
+  else (void)hipGetLastError();     // the setup's own launch error, reported below
   if (e == hipSuccess) e = hipMalloc(&col->d, sizeof(ColDev));
   if (e == hipSuccess) e = hipMemcpyAsync(col->d, &C, sizeof(ColDev), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);

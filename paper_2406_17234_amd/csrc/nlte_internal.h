@@ -305,6 +305,12 @@ struct BatchWork {
 // [4] after assembly, [5] left to the caller, [6] after the F-mode
 // formal-solution launches that run on s itself.
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev = nullptr);
+// Velocity-field columns (nlte_velocity.hip): the formal-solution launch of
+// one tile group in F (newton false) or Newton mode, and the pair sums over
+// the preconditioner items of a batch (other columns' items return at once).
+void launch_formal_vel(bool newton, int nmu, int wpb, hipStream_t s, const ColDev* cols,
+                       const Tile* tiles, int ntiles);
+void launch_pairsum_vel(const ColDev* cols, const int4* work, int nwork, hipStream_t s);
 // Tangent-linear products (nlte_tangent.hip) of the columns whose state has
 // tan_pending set: J v into F.  launch_residual runs it when bw.any_tangent.
 hipError_t launch_tangent(const BatchWork& bw, hipStream_t s);
