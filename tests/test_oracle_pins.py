@@ -537,3 +537,23 @@ def test_scattering_forward_difference_root_equals_complex_step_root():
     r = O.residual(tb, cs.n, Jdag=cs.J)
     assert np.max(r.rho) <= 1e-12
     assert np.max(np.abs(r.J / cs.J - 1)) < 1e-9
+
+
+def test_per_depth_correction_limit():
+    """Sect. 2.2.2 limits the Newton correction depth by depth: with the
+    factor-3 reading, every level of n + lambda_k dn stays within
+    [n/3, 3n] and stays positive, lambda_k is 1 when the full step already
+    does, and otherwise the bound is reached by one level of that depth."""
+    rng = np.random.default_rng(21)
+    n = 10.0 ** rng.uniform(-3, 12, (200, 6))
+    dn = n * rng.normal(0.0, 1.5, n.shape)
+    lam = O.positivity_limit(n, dn)
+    assert lam.shape == (200,) and np.all((lam > 0) & (lam <= 1))
+    new = n + lam[:, None] * dn
+    r = new / n
+    assert np.all(r >= 1 / 3 - 1e-12) and np.all(r <= 3 + 1e-12) and np.all(new > 0)
+    full = n + dn
+    ok = np.all((full / n >= 1 / 3) & (full / n <= 3), axis=1)
+    assert np.all(lam[ok] == 1.0)
+    tight = np.min(np.minimum(np.abs(r - 1 / 3), np.abs(r - 3)), axis=1)
+    assert np.all(tight[~ok] < 1e-12) and np.any(~ok)
