@@ -98,9 +98,8 @@ typedef struct {
                               normalised per ray and depth on the window, so
                               opacity, formal solution and line rates are
                               taken ray by ray.  Columns with a velocity
-                              field are FP64 (no NLTE_FP32_FORM), sequential
-                              (no NLTE_DEPTH_SCAN) and take forward-difference
-                              products only (no NLTE_JV_TANGENT); otherwise
+                              field are FP64 (no NLTE_FP32_FORM) and
+                              sequential (no NLTE_DEPTH_SCAN); otherwise
                               NLTE_E_INVALID.                                 */
 } nlte_atmos_desc;
 

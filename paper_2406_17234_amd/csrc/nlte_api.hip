@@ -598,8 +598,10 @@ static void layout_column(Layout& Lo, ColDev& C, SetupIn& in, int nwin_total, in
     C.vlos = Lo.take<double>(nz);
     C.VR = Lo.take<double>((size_t)C.nray * nline_tab * nz + 1);
     C.VRT = Lo.take<double>((size_t)C.nray * nline_tab * nz + 1);
-    C.DXR = Lo.take<double>((size_t)C.nray * kfz);
-    C.DER = Lo.take<double>((size_t)C.nray * kfz);
+    // per ray: the Newton-mode derivatives [nnu][zp], or a tangent
+    // product's I' [nz][fp]
+    C.DXR = Lo.take<double>((size_t)C.nray * std::max(kfz, kfp));
+    C.DER = Lo.take<double>((size_t)C.nray * std::max(kfz, kfp));
   } else {
     C.vlos = C.VR = C.VRT = nullptr;
     C.DXR = C.DER = nullptr;
@@ -1411,7 +1413,6 @@ __global__ void k_set_tangent(ColState* st, int on) {
 extern "C" nlte_status nlte_jvp_tangent(nlte_column* col, const double* n_dev, const double* v_dev,
                                         double* Jv_dev, hipStream_t s) {
   if (!col || !n_dev || !v_dev || !Jv_dev) return set_err(NLTE_E_INVALID, "NULL argument");
-  if (col->h.vel) return set_err(NLTE_E_INVALID, "no tangent product for a column with a velocity field");
   HIP_TRY(hipSetDevice(col->ctx->device));
   nlte_status st = check_populations(col, n_dev, s);
   if (st != NLTE_OK) return st;

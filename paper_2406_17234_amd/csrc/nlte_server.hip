@@ -373,8 +373,6 @@ extern "C" nlte_status nlte_server_submit(nlte_server* S, nlte_column* col, cons
                                           uint64_t* ticket) {
   if (!S || !col || !ticket) return set_err(NLTE_E_INVALID, "NULL argument");
   if (column_ctx(col) != S->ctx) return set_err(NLTE_E_INVALID, "column from another context");
-  if (column_dev(col).vel && S->opts.jv_method == NLTE_JV_TANGENT)
-    return set_err(NLTE_E_INVALID, "column with a velocity field: no tangent products");
   Request* r = new Request();
   r->col = col;
   r->n0 = n0_dev;
@@ -409,8 +407,6 @@ extern "C" nlte_status nlte_server_submit_problem(nlte_server* S, const nlte_atm
                                                   int32_t precision, double* n_out_dev,
                                                   uint64_t* ticket) {
   if (!S || !ticket || !n_out_dev) return set_err(NLTE_E_INVALID, "NULL argument");
-  if (atmos && atmos->vlos && S->opts.jv_method == NLTE_JV_TANGENT)
-    return set_err(NLTE_E_INVALID, "problem with a velocity field: no tangent products");
   HostProblem* H = nullptr;
   const nlte_status ps = problem_copy(atmos, atom, grid, C_up, precision, &H);
   if (ps != NLTE_OK) return ps;

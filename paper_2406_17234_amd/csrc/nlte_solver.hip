@@ -1146,8 +1146,6 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
     if (!cols[c]) return set_err(NLTE_E_INVALID, "column %d is NULL", c);
     if (column_ctx(cols[c]) != ctx) return set_err(NLTE_E_INVALID, "column %d from another context", c);
     hc[c] = column_dev(cols[c]);
-    if (hc[c].vel && o.jv_method == NLTE_JV_TANGENT)
-      return set_err(NLTE_E_INVALID, "column %d has a velocity field: no tangent products", c);
     b.maxL = std::max(b.maxL, hc[c].L);
     if (hc[c].prec == NLTE_FP64) b.any64 = 1; else b.any32 = 1;
     for (int d = 0; d < c; ++d)

@@ -25,7 +25,9 @@
 // Jm (J'), RJ (R').  Three launches: the formal solution (which makes the
 // opacity on its way down), the rate derivatives, the assembly.  A column
 // takes part when its state has tan_pending set (its mode is then idle, so
-// the residual kernels skip it).
+// the residual kernels skip it).  Columns with a velocity field run their
+// own formal-solution variant (k_tan_formal_vel) and keep the angle integral
+// inside the line rates' frequency sum.
 #include "nlte_internal.h"
 
 namespace nlte {
@@ -217,6 +219,183 @@ __global__ __launch_bounds__(64) void k_tan_formal(const ColDev* __restrict__ co
   }
 }
 
+// Velocity fields (Sect. 3.5): every ray has its own line opacity, so each
+// carries its own chi, S and derivatives through the recursion (segment
+// optical depths differ between rays); the ray-independent part (background,
+// edges) is made once per depth on the way down and parked.  Each ray's I'
+// is kept ([ray][k][fp] in the column's per-ray derivative buffer, free while
+// a tangent product runs) for the line rates, whose angle integral stays
+// inside the frequency sum.
+
+// Ray-independent chi, eta and derivatives at (k, f): background, edges and
+// the lagged scattering emissivity.
+__device__ __forceinline__ void tan_base_vel(const ColDev& C, int chunk, int k, int f, int L, int nnu,
+                                             int nbf, int nline, double gam, double& X, double& Et,
+                                             double& Xd, double& Ed) {
+  const double* nk = C.n + (size_t)k * L;
+  const double* vk = C.eval_n + (size_t)k * L;
+  double A1 = 0.0, A2 = 0.0, A1d = 0.0, A2d = 0.0;
+  const int e0 = C.ch_eptr[chunk], e1 = C.ch_eptr[chunk + 1];
+  for (int j = e0; j < e1; ++j) {
+    const int t = C.ch_edge[j];
+    const TrDev& T = C.tr[t];
+    const int q = f - T.wlo;
+    if (q < 0 || q >= T.whi - T.wlo) continue;
+    const double al = C.V[T.voff + q];
+    const double rb = C.rho_bf[(size_t)k * nbf + (t - nline)];
+    A1 += al * nk[T.lo];
+    A2 += al * rb * nk[L - 1];
+    A1d += al * vk[T.lo];
+    A2d += al * rb * vk[L - 1];
+  }
+  const size_t kf = (size_t)k * nnu + f;
+  const double E = nbf ? C.Ebf[kf] : 0.0;
+  X = (C.chi_c[k] + C.chi_sca[k]) + (A1 - E * A2);
+  Et = (C.bg_eta ? 1.0 : C.chi_c[k]) * C.EC[kf] + gam * (E * A2);
+  if (C.has_sca) Et += C.chi_sca[k] * C.Jdag[kf];
+  Xd = A1d - E * A2d;
+  Ed = gam * (E * A2d);
+}
+
+// chi, S and their derivatives at (k, f) of the rays r0 .. r0 + NMU - 1.
+template <int NMU>
+__device__ __forceinline__ void tan_rays_vel(const ColDev& C, int chunk, int k, int f, int L, int r0,
+                                             double gam, double X0, double E0, double Xd0, double Ed0,
+                                             double (&X)[NMU], double (&S)[NMU], double (&Xd)[NMU],
+                                             double (&Sd)[NMU]) {
+  const double* nk = C.n + (size_t)k * L;
+  const double* vk = C.eval_n + (size_t)k * L;
+  double et[NMU], etd[NMU];
+#pragma unroll
+  for (int m = 0; m < NMU; ++m) {
+    X[m] = X0;
+    Xd[m] = Xd0;
+    et[m] = 0.0;
+    etd[m] = 0.0;
+  }
+  const int nz = C.nz;
+  const int l0 = C.ch_lptr[chunk], l1 = C.ch_lptr[chunk + 1];
+  for (int j = l0; j < l1; ++j) {
+    const TrDev& T = C.tr[C.ch_line[j]];
+    const int wl = T.whi - T.wlo, q = f - T.wlo;
+    if (q < 0 || q >= wl) continue;
+    const double c1 = T.g * nk[T.up], c1d = T.g * vk[T.up];
+    const double c0 = nk[T.lo] - c1, c0d = vk[T.lo] - c1d;
+    const double* vr = C.VR + (size_t)C.nray * T.voff + ((size_t)r0 * nz + k) * wl + q;
+#pragma unroll
+    for (int m = 0; m < NMU; ++m) {
+      const double V = vr[(size_t)m * nz * wl];
+      X[m] += V * c0;
+      Xd[m] += V * c0d;
+      et[m] += V * c1;
+      etd[m] += V * c1d;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NMU; ++m) {
+    const double rX = 1.0 / X[m];
+    S[m] = (E0 + gam * et[m]) * rX;
+    Sd[m] = ((Ed0 + gam * etd[m]) - S[m] * Xd[m]) * rX;
+  }
+}
+
+template <int NMU>
+__global__ __launch_bounds__(64) void k_tan_formal_vel(const ColDev* __restrict__ cols,
+                                                       const Tile* __restrict__ tiles, int ntiles) {
+  if ((int)blockIdx.x >= ntiles) return;
+  const ColDev& C = cols[uni(tiles[blockIdx.x].col)];
+  if (!tan_on(C)) return;
+  if (uni(C.nmu) != NMU) return;
+  const int chunk = uni(tiles[blockIdx.x].chunk);
+  const int nz = C.nz, nnu = C.nnu, fp = C.fp, L = C.L, nbf = C.nbf, nline = C.nline;
+  const int f = chunk * kWave + (int)threadIdx.x;
+  if (f >= nnu) return;
+  double* __restrict__ XS = C.XS;    // ray-independent chi, eta
+  double* __restrict__ Dx = C.Dchi;  // and their derivatives
+  double* __restrict__ De = C.Deta;
+  double* __restrict__ Jd = C.Jm;
+  double* __restrict__ Id_out = C.DXR;  // [ray][k][fp] I' of every ray
+  const size_t rs = (size_t)nz * fp;
+  const double* __restrict__ dzs = C.dz;
+  const double gam = C.gam[f];
+  double i2mu[NMU], wm2[NMU];
+#pragma unroll
+  for (int m = 0; m < NMU; ++m) {
+    i2mu[m] = C.inv2mu[m];
+    wm2[m] = C.wm2[m];
+  }
+  double I[NMU], Id[NMU], Xp[NMU], Sp[NMU], Xdp[NMU], Sdp[NMU];
+  double X[NMU], S[NMU], Xd[NMU], Sd[NMU];
+  // one segment of every ray of the sweep, from (Xp, Sp) to (X, S)
+  auto step = [&](double dz, int k, int r0) {
+    double jd = 0.0;
+#pragma unroll
+    for (int m = 0; m < NMU; ++m) {
+      const double sx = dz * (Xp[m] + X[m]), sxd = dz * (Xdp[m] + Xd[m]);
+      const double x = sx * i2mu[m], xd = sxd * i2mu[m];
+      double e, a, b, bx;
+      seg_ab(x, 1.0 / x, e, a, b, bx);
+      const double ed = -e * xd, ad = bx * xd, bd = (e - bx) * xd;
+      const double In = I[m] * e + a * S[m] + b * Sp[m];
+      const double Idn = Id[m] * e + I[m] * ed + ad * S[m] + a * Sd[m] + bd * Sp[m] + b * Sdp[m];
+      I[m] = In;
+      Id[m] = Idn;
+      jd += wm2[m] * Idn;
+      Id_out[(size_t)(r0 + m) * rs + (size_t)k * fp + f] = Idn;
+      Xp[m] = X[m];
+      Sp[m] = S[m];
+      Xdp[m] = Xd[m];
+      Sdp[m] = Sd[m];
+    }
+    return jd;
+  };
+  // ingoing rays (NMU + m), top -> bottom (I- = 0 at the top)
+  double X0, E0, Xd0, Ed0;
+  tan_base_vel(C, chunk, 0, f, L, nnu, nbf, nline, gam, X0, E0, Xd0, Ed0);
+  size_t kx = (size_t)f;
+  XS[2 * kx] = X0;
+  XS[2 * kx + 1] = E0;
+  Dx[kx] = Xd0;
+  De[kx] = Ed0;
+  Jd[kx] = 0.0;
+  tan_rays_vel<NMU>(C, chunk, 0, f, L, NMU, gam, X0, E0, Xd0, Ed0, Xp, Sp, Xdp, Sdp);
+#pragma unroll
+  for (int m = 0; m < NMU; ++m) {
+    I[m] = Id[m] = 0.0;
+    Id_out[(size_t)(NMU + m) * rs + f] = 0.0;
+  }
+  for (int k = 1; k < nz; ++k) {
+    tan_base_vel(C, chunk, k, f, L, nnu, nbf, nline, gam, X0, E0, Xd0, Ed0);
+    kx = (size_t)k * fp + f;
+    XS[2 * kx] = X0;
+    XS[2 * kx + 1] = E0;
+    Dx[kx] = Xd0;
+    De[kx] = Ed0;
+    tan_rays_vel<NMU>(C, chunk, k, f, L, NMU, gam, X0, E0, Xd0, Ed0, X, S, Xd, Sd);
+    Jd[kx] = step(dzs[k - 1], k, NMU);
+  }
+  // outgoing rays (m), bottom -> top (I+ = B at the bottom, I+' = 0)
+  {
+    const int k = nz - 1;
+    kx = (size_t)k * fp + f;
+    tan_rays_vel<NMU>(C, chunk, k, f, L, 0, gam, XS[2 * kx], XS[2 * kx + 1], Dx[kx], De[kx], Xp, Sp,
+                      Xdp, Sdp);
+    const double Bb = C.Bnu[(size_t)k * nnu + f];
+#pragma unroll
+    for (int m = 0; m < NMU; ++m) {
+      I[m] = Bb;
+      Id[m] = 0.0;
+      Id_out[(size_t)m * rs + kx] = 0.0;
+    }
+  }
+  for (int k = nz - 2; k >= 0; --k) {
+    kx = (size_t)k * fp + f;
+    tan_rays_vel<NMU>(C, chunk, k, f, L, 0, gam, XS[2 * kx], XS[2 * kx + 1], Dx[kx], De[kx], X, S, Xd,
+                      Sd);
+    Jd[kx] += step(dzs[k], k, 0);
+  }
+}
+
 // R_lu' and R_ul' of every (depth, transition): one wave per pair, lanes
 // strided over the transition's window, then a wave reduction.  Stored in RJ
 // as [nz][ntr][2] (rows of nrseg >= ntr entries).
@@ -235,7 +414,18 @@ __global__ __launch_bounds__(kTanRateThreads) void k_tan_rates(const ColDev* __r
     const double* cw = C.cw + T.cwoff;
     const double* Jk = C.Jm + (size_t)k * fp + wlo;
     double s1 = 0.0, s2 = 0.0;
-    if (t < nline) {
+    if (t < nline && C.vel) {
+      // velocity fields: the angle integral inside, sum_rays (w_m/2) V_ray I'_ray
+      const int nray = C.nray, nmu = C.nmu;
+      const size_t vs = (size_t)nz * wl, rs = (size_t)nz * fp;
+      const double* V = C.VR + (size_t)nray * T.voff + (size_t)k * wl;
+      const double* Ik = C.DXR + (size_t)k * fp + wlo;
+      for (int q = lane; q < wl; q += kWave) {
+        double u = 0.0;
+        for (int r = 0; r < nray; ++r) u += C.wm2[r < nmu ? r : r - nmu] * V[r * vs + q] * Ik[r * rs + q];
+        s1 += cw[q] * u;
+      }
+    } else if (t < nline) {
       const double* V = C.V + T.voff + (size_t)k * wl;
       for (int q = lane; q < wl; q += kWave) s1 += cw[q] * V[q] * Jk[q];
     } else {
@@ -303,6 +493,16 @@ hipError_t launch_tangent(const BatchWork& bw, hipStream_t s) {
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
     const Tile* tl = bw.tiles + G.first;
+    if (G.vel) {
+      switch (G.nmu) {
+#define TFV(M) \
+  case M: k_tan_formal_vel<M><<<G.count, 64, 0, s>>>(bw.cols, tl, G.count); break;
+        TFV(1) TFV(2) TFV(3) TFV(4) TFV(5) TFV(6) TFV(7) TFV(8)
+#undef TFV
+        default: return hipErrorInvalidValue;
+      }
+      continue;
+    }
     switch (G.nmu) {
 #define TF(M) \
   case M: k_tan_formal<M><<<G.count, 64, 0, s>>>(bw.cols, tl, G.count); break;
