@@ -51,6 +51,9 @@ namespace nlte {
 // emission table (B_nu, or eta_c),
 //   chi = chi_c + chi_sca + sum_lines V c0 + sum_edges alpha (c0 - E c1)
 //   eta = c1(ntr) EC + chi_sca J' + (2 h nu^3/c^2) (sum_lines V c1 + E sum_edges alpha c1).
+// In the FP32 form, B_nu and E are made in FP32 from T and nu where they are
+// used (one exponential per (k, nu), shared by the rays), unless the caller
+// gave the background emissivity; the FP64 form reads its FP64 tables.
 __global__ __launch_bounds__(256) void k_coef(const ColDev* __restrict__ cols,
                                               const int* __restrict__ act) {
   const ColDev& C = cols[act ? act[blockIdx.x] : blockIdx.x];
@@ -213,12 +216,26 @@ __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0
   // the FP32 tables share the scratch's padded row pitch; the FP64 ones
   // (and the lagged J) keep rows of nnu
   const int fp = uni(C.fp), tp = sizeof(R) == sizeof(float) ? fp : nnu;
+  // FP32 form: B_nu(T) and exp(-h nu / kT) made here in FP32 (n-independent,
+  // like the FP32 tables they replace) unless the caller gave the emissivity
+  constexpr bool kOnTheFly = sizeof(R) == sizeof(float);
+  const bool fly = kOnTheFly && !C.bg_eta;
+  const float hnuk = fly ? (float)(kH / kK * ldg(C.nu + fc)) : 0.0f;
+  const float gamf = (float)gam;
 #pragma unroll
   for (int i = 0; i < KG; ++i) {
     const int k = min(k0 + i, nz - 1);
     const size_t kf = (size_t)k * nnu + fc, kt = (size_t)k * tp + fc, kx = (size_t)k * fp + fc;
-    const double B = (double)ldg(FTab<R>::B(C) + kt);
-    const double E = bf ? (double)ldg(FTab<R>::E(C) + kt) : 0.0;
+    double B, E;
+    if (fly) {
+      const float Ef = __expf(-hnuk * __builtin_amdgcn_rcpf((float)ldc(C.T + k)));
+      E = (double)Ef;
+      B = (double)(gamf * Ef * __builtin_amdgcn_rcpf(1.0f - Ef));
+    } else {
+      B = (double)ldg(FTab<R>::B(C) + kt);
+      E = bf ? (double)ldg(FTab<R>::E(C) + kt) : 0.0;
+    }
+    if (!bf) E = 0.0;
     const double EA2 = E * A2[i];
     const double X = (ldc(cb + 2 * (k - k0)) + chi[i]) + (A1[i] - EA2);
     double eta = fmar(ldc(cb + 2 * (k - k0) + 1), B, gam * (et[i] + EA2));
