@@ -352,9 +352,10 @@ def velocity_leg(ctx, nlte, ncol):
     test solved alone (FP64, Krylov tolerance 1e-2, stop at 1e-8; median of 3
     after a warm-up), and a batch of ncol velocity columns: FP64 batch solve
     (one warm-up, one timed), a profiled solve for the roofline of the F-mode
-    velocity formal-solution launches (HBM-bound: its algorithmic bytes over
-    their time), and F-only loops of the batch with and without the velocity
-    field (same depths and frequencies)."""
+    velocity formal-solution launches (its algorithmic bytes over their
+    time), the FP32-form batch solve (against the FP64 batch's populations),
+    and F-only loops of the batch (FP64, FP32 form, and FP64 without the
+    velocity field: same depths and frequencies)."""
     import torch
     out = {}
     p = S.chromo6_vel()
@@ -382,11 +383,25 @@ def velocity_leg(ctx, nlte, ncol):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ctx.profile(True)
-    _, pst, _ = nlte.solve_batch(ctx, cols, ob)
+    outs64, pst, _ = nlte.solve_batch(ctx, cols, ob)
     prof = ctx.read_profile()
     ctx.profile(False)
+    ref64 = [o.cpu().numpy() for o in outs64]
     for c in cols:
         c.close()
+    # the FP32 form of the same batch (stop at 1e-6, FP64 fallback after 12)
+    cols32 = [nlte.Column(ctx, q, precision=nlte.FP32_FORM) for q in probs]
+    o32 = nlte.default_opts(ftol=1e-6, rtol=1e-3, maxiter=50, max_krylov_total=200, fp64_fallback=12)
+    nlte.solve_batch(ctx, cols32, o32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs32, st32, _ = nlte.solve_batch(ctx, cols32, o32)
+    torch.cuda.synchronize()
+    el32 = time.perf_counter() - t0
+    for c in cols32:
+        c.close()
+    f32c = np.array([s["f_calls"] for s in st32], dtype=np.float64)
+    err32 = max(float(np.max(np.abs(o.cpu().numpy() / r - 1.0))) for o, r in zip(outs32, ref64))
     dp = np.array([q.depth_points() for q in probs], dtype=np.float64)
     bf = np.array([s["f_calls"] for s in bst], dtype=np.float64)
     own = np.array([s["f_calls"] - s["precond_calls"] for s in pst], dtype=np.float64)
@@ -407,8 +422,17 @@ def velocity_leg(ctx, nlte, ncol):
         "kernel_ms_per_solve_profiled": {k: prof[k] for k in ("opacity_ms", "formal_ms", "depth_ms",
                                                               "assemble_ms", "solver_ms")},
     }
+    out["batch_fp32_form"] = {
+        "ms_per_solve": el32 * 1e3,
+        "depth_points_per_s": float((f32c * dp).sum()) / el32,
+        "converged_fraction": float(np.mean([s["status"] == 0 for s in st32])),
+        "columns_converged_per_s": float(np.sum([s["status"] == 0 for s in st32])) / el32,
+        "residual_calls_per_column": float(f32c.mean()),
+        "fp64_fallback_fraction": float(np.mean([s["precision"] == 0 for s in st32])),
+        "max_rel_error_vs_fp64_batch": err32,
+    }
     out["roofline"] = {
-        "kernel": "k_formal_vel<false, 5> (F-mode velocity formal solution: opacity made per ray, "
+        "kernel": "k_formal_vel<double, false, 5> (F-mode velocity formal solution: opacity made per ray, "
                   "line rates taken in the kernel)",
         "launches": prof["formal_f_launches"],
         "launch_avg_ms": prof["formal_f_ms"] / max(1, prof["formal_f_launches"]),
@@ -421,6 +445,7 @@ def velocity_leg(ctx, nlte, ncol):
         "traffic_unit": "bytes per launch (mean)",
     }
     out["f_only_fp64"] = f_only(ctx, nlte, probs, nlte.FP64)
+    out["f_only_fp32_form"] = f_only(ctx, nlte, probs, nlte.FP32_FORM)
     out["f_only_fp64_static_twin"] = f_only(ctx, nlte, [S.batch6_vel_column(i, static=True)
                                                         for i in range(ncol)], nlte.FP64)
     return out

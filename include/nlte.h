@@ -98,9 +98,8 @@ typedef struct {
                               normalised per ray and depth on the window, so
                               opacity, formal solution and line rates are
                               taken ray by ray.  Columns with a velocity
-                              field are FP64 (no NLTE_FP32_FORM) and
-                              sequential (no NLTE_DEPTH_SCAN); otherwise
-                              NLTE_E_INVALID.                                 */
+                              field use the sequential formal solution (no
+                              NLTE_DEPTH_SCAN; NLTE_E_INVALID otherwise).     */
 } nlte_atmos_desc;
 
 /* Model atom, Sect. 2.1.1.  If nbf > 0 the last level is the continuum

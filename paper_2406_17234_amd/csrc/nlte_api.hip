@@ -693,8 +693,8 @@ static nlte_status plan_column(const nlte_atmos_desc* A, const nlte_atom_desc* M
   if (scan && A && A->nz > kScanThreads)
     return set_err(NLTE_E_INVALID, "the depth-parallel formal solution takes at most %d depths",
                    kScanThreads);
-  if (A && A->vlos && (prec != NLTE_FP64 || scan))
-    return set_err(NLTE_E_INVALID, "columns with a velocity field are FP64 and sequential");
+  if (A && A->vlos && scan)
+    return set_err(NLTE_E_INVALID, "columns with a velocity field use the sequential formal solution");
   nlte_status vs = validate(A, M, G, C_up);
   if (vs != NLTE_OK) return vs;
 

@@ -166,7 +166,7 @@ struct ColDev {
   int npitem, nment;               // pair-sum blocks, entries of M
   int scan;                        // 1: depth-parallel formal solution (nz <= 256)
   int nrseg, nritem;               // rate-integral entries (partial sums) and blocks
-  int vel;                         // 1: velocity field, line opacity per ray (FP64, sequential)
+  int vel;                         // 1: velocity field, line opacity per ray (sequential)
   int nray;                        // 2 nmu: rays 0..nmu-1 outgoing, nmu..2nmu-1 ingoing
   // angles (inline: at most kMaxMu)
   double wm2[kMaxMu];     // w_m / 2
@@ -268,12 +268,12 @@ inline __host__ __device__ int ncoef(int ntr) { return 2 * ntr + 4; }
 struct TileGroup {
   int prec, nmu, first, count;
   int scan;  // columns solved by the depth-parallel formal solution
-  int vel;   // columns with a velocity field (FP64, sequential)
+  int vel;   // columns with a velocity field (sequential)
 };
 
 // Tile groups a batch can have: one per (formal-solution variant, precision,
-// angle count), plus the velocity-field columns per angle count.
-constexpr int kMaxGroups = 2 * 2 * kMaxMu + kMaxMu;
+// angle count), plus the velocity-field columns per (precision, angle count).
+constexpr int kMaxGroups = 2 * 2 * kMaxMu + 2 * kMaxMu;
 
 // Device work lists of a batch of columns.
 struct BatchWork {
@@ -306,9 +306,10 @@ struct BatchWork {
 // formal-solution launches that run on s itself.
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev = nullptr);
 // Velocity-field columns (nlte_velocity.hip): the formal-solution launch of
-// one tile group in F (newton false) or Newton mode, and the pair sums over
+// one tile group in the FP32 form or FP64 and in F or Newton mode (each wave
+// skips the columns evaluated in the other), and the pair sums over
 // the preconditioner items of a batch (other columns' items return at once).
-void launch_formal_vel(bool newton, int nmu, int wpb, hipStream_t s, const ColDev* cols,
+void launch_formal_vel(bool fp32, bool newton, int nmu, int wpb, hipStream_t s, const ColDev* cols,
                        const Tile* tiles, int ntiles);
 void launch_pairsum_vel(const ColDev* cols, const int4* work, int nwork, hipStream_t s);
 // Tangent-linear products (nlte_tangent.hip) of the columns whose state has

@@ -1270,9 +1270,15 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     // FP64 launches: on s / sNewton for FP64 groups, on sF64 / sN64 for the
     // fallback columns of FP32-form groups
     const hipStream_t dF = f32 ? sF64 : s, dN = f32 ? sN64 : sNewton;
-    if (G.vel) {  // nlte_velocity.hip
-      launch_formal_vel(false, G.nmu, nb, s, bw.cols, tl, G.count);
-      if (bw.any_newton) launch_formal_vel(true, G.nmu, nb, sNewton, bw.cols, tl, G.count);
+    if (G.vel) {  // nlte_velocity.hip; streams as for the other groups
+      if (f32) {
+        launch_formal_vel(true, false, G.nmu, nb, s, bw.cols, tl, G.count);
+        if (bw.any_newton) launch_formal_vel(true, true, G.nmu, nb, sNewton, bw.cols, tl, G.count);
+      }
+      if (!f32 || bw.fallback) {
+        launch_formal_vel(false, false, G.nmu, nb, dF, bw.cols, tl, G.count);
+        if (bw.any_newton) launch_formal_vel(false, true, G.nmu, nb, dN, bw.cols, tl, G.count);
+      }
       continue;
     }
     if (G.scan) {
@@ -1343,7 +1349,7 @@ int build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
     nsel = ncol;
   }
   // formal-solution tiles grouped by (variant, precision, angle count); the
-  // velocity-field columns (FP64, sequential) by angle count
+  // velocity-field columns (sequential) by (precision, angle count)
   for (int scan = 0; scan < 2; ++scan)
     for (int prec = 0; prec < 2; ++prec)
       for (int nmu = 1; nmu <= kMaxMu; ++nmu) {
@@ -1356,16 +1362,17 @@ int build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
         G.count = (int)tiles.size() - G.first;
         if (G.count) groups.push_back(G);
       }
-  for (int nmu = 1; nmu <= kMaxMu; ++nmu) {
-    TileGroup G{NLTE_FP64, nmu, (int)tiles.size(), 0, 0, 1};
-    for (int q = 0; q < nsel; ++q) {
-      const int c = sel[q];
-      if (hc[c].vel && hc[c].nmu == nmu)
-        for (int ch = 0; ch < hc[c].nchunk; ++ch) tiles.push_back(Tile{c, ch});
+  for (int prec = 0; prec < 2; ++prec)
+    for (int nmu = 1; nmu <= kMaxMu; ++nmu) {
+      TileGroup G{prec, nmu, (int)tiles.size(), 0, 0, 1};
+      for (int q = 0; q < nsel; ++q) {
+        const int c = sel[q];
+        if (hc[c].vel && hc[c].prec == prec && hc[c].nmu == nmu)
+          for (int ch = 0; ch < hc[c].nchunk; ++ch) tiles.push_back(Tile{c, ch});
+      }
+      G.count = (int)tiles.size() - G.first;
+      if (G.count) groups.push_back(G);
     }
-    G.count = (int)tiles.size() - G.first;
-    if (G.count) groups.push_back(G);
-  }
   // rate items (kind 0), then preconditioner pair-sum blocks (kind 1), each
   // kind column by column
   maxL = 0;

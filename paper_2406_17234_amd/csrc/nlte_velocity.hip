@@ -3,7 +3,7 @@
 // function and the formal solution are per ray, the line rates keep the
 // angle integral inside the frequency sum (Eqs. Rij, Rji) and the
 // preconditioner's local blocks take each ray's own intensity derivatives
-// (App. A.2).  FP64, sequential formal solution.  The other residual
+// (App. A.2).  FP64 or the FP32 form, sequential formal solution.  The other residual
 // launches (level coefficients, edge rates, assembly, block gather) are
 // those of nlte_residual.hip.
 #include "nlte_kernels.h"
@@ -47,9 +47,9 @@ __device__ __forceinline__ double wave_sum0(double v) {
 // frequencies of cw sum_m (w_m/2) V_ray I_ray.  The ingoing sweep (first)
 // parks its sum in the entry's second slot; the outgoing sweep adds its own
 // and writes the entry (second slot back to zero, as for every line entry).
-template <int NMU>
+template <int NMU, typename R>
 __device__ __forceinline__ void vel_rate_step(const ColDev& C, int chunk, int k, int f, int fc,
-                                              int r0, const double (&I)[NMU], const double (&wm2)[NMU],
+                                              int r0, const R (&I)[NMU], const double (&wm2)[NMU],
                                               bool first) {
   const int nz = C.nz, nray = C.nray, nnu = C.nnu;
   const int l0 = uni(C.ch_lptr[chunk]), l1 = uni(C.ch_lptr[chunk + 1]);
@@ -64,7 +64,7 @@ __device__ __forceinline__ void vel_rate_step(const ColDev& C, int chunk, int k,
     const double* vr = C.VR + (size_t)nray * uni(T.voff) + (size_t)r0 * rstep + (size_t)k * wl + (in ? q : 0);
     double u = 0.0;
 #pragma unroll
-    for (int m = 0; m < NMU; ++m) u = fmar(wm2[m] * ldg(vr + m * rstep), I[m], u);
+    for (int m = 0; m < NMU; ++m) u = fmar(wm2[m] * ldg(vr + m * rstep), (double)I[m], u);
     const double x = in ? ldg(C.cw + uni(T.cwoff) + q) * u : 0.0;
     const double tot = wave_sum0(x);
     if ((threadIdx.x & 63) == 0) {
@@ -106,9 +106,9 @@ __device__ __forceinline__ void vel_base(const ColDev& C, int chunk, int k, int 
 
 // chi and S at (k, fc) of the NMU rays r0 .. r0 + NMU - 1: the lines'
 // V c0 and V c1 with each ray's V added to the ray-independent part.
-template <int NMU>
+template <int NMU, typename R>
 __device__ __forceinline__ void vel_rays(const ColDev& C, int chunk, int k, int fc, double chi0,
-                                         double eta0, int r0, double (&chi)[NMU], double (&S)[NMU]) {
+                                         double eta0, int r0, R (&chi)[NMU], R (&S)[NMU]) {
   const int nz = C.nz, nray = C.nray;
   const double* __restrict__ coef = (const double*)C.coef;
   double cl[NMU], el[NMU];
@@ -138,8 +138,11 @@ __device__ __forceinline__ void vel_rays(const ColDev& C, int chunk, int k, int 
   const double gam = ldg(C.gam + fc);
 #pragma unroll
   for (int m = 0; m < NMU; ++m) {
-    chi[m] = chi0 + cl[m];
-    S[m] = fmar(gam, el[m], eta0) / chi[m];
+    // the sums in FP64; only chi and S leave rounded to the recursion's
+    // precision (as in the static FP32 form)
+    const double X = chi0 + cl[m];
+    chi[m] = (R)X;
+    S[m] = (R)(fmar(gam, el[m], eta0) / X);
   }
 }
 
@@ -150,7 +153,10 @@ template <bool PM, int NMU> struct VelStage {
   static constexpr int doubles = (KFV + (PM ? 2 * NMU * KDV : 0)) * kWave;
 };
 
-template <bool PM, int NMU>
+// R: the recursion's precision (double, or float for the FP32 form: chi and
+// S rounded from their FP64 sums, the depth recursion in FP32, the angle
+// sums into J, the rates and the derivatives' storage in FP64).
+template <typename R, bool PM, int NMU>
 __device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int lane, double* tile) {
   constexpr int KF = KFV, KD = KDV;
   double* tJ = tile;
@@ -163,14 +169,38 @@ __device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int 
   double* __restrict__ xb = C.XS;  // [nz][fp][2] ray-independent chi, eta
   double* __restrict__ jm = C.Jm;  // [nz][fp] ingoing half of J
   const size_t rs = (size_t)nnu * zp;  // ray stride of DXR, DER ([nray][nnu][zp])
-  double i2mu[NMU], mu2[NMU], wm2[NMU];
+  R i2mu[NMU], mu2[NMU];
+  double wm2[NMU];
 #pragma unroll
   for (int m = 0; m < NMU; ++m) {
-    i2mu[m] = C.inv2mu[m];
-    mu2[m] = 1.0 / C.inv2mu[m];
+    i2mu[m] = (R)C.inv2mu[m];
+    mu2[m] = (R)(1.0 / C.inv2mu[m]);
     wm2[m] = C.wm2[m];
   }
-  double I[NMU], chp[NMU], Sp[NMU], ch[NMU], Sx[NMU];
+  R I[NMU], chp[NMU], Sp[NMU], ch[NMU], Sx[NMU];
+  // one segment of every ray of a sweep, from (chp, Sp) to (ch, Sx); returns
+  // the rays' share of J and leaves the local derivatives in the tiles
+  auto step = [&](int k, R dz) {
+    double js = 0.0;
+#pragma unroll
+    for (int m = 0; m < NMU; ++m) {
+      const R base = dz * (chp[m] + ch[m]);
+      R e, q, a, bx;
+      seg_coef<R, PM>(base * i2mu[m], PL<R>::div((R)1, base), mu2[m], e, q, a, bx);
+      const R Iup = I[m];
+      I[m] = fmar(e, Iup, fmar(q, Sp[m], a * (Sx[m] - Sp[m])));
+      js = fmar(wm2[m], (double)I[m], js);
+      if (PM) {  // App. A.2 for this ray: c_chi, c_eta (ingoing) or a_chi, a_eta (outgoing)
+        const R rc = PL<R>::div((R)1, ch[m]);
+        stage_put<KD>(tX + m * KD * kWave, k, lane,
+                      (double)(-(Sx[m] * rc) * a + dz * (i2mu[m] * (e * (Sp[m] - Iup) - (Sp[m] - Sx[m]) * bx))));
+        stage_put<KD>(tE + m * KD * kWave, k, lane, (double)(a * rc));
+      }
+      chp[m] = ch[m];
+      Sp[m] = Sx[m];
+    }
+    return js;
+  };
 
   // ---- sweep 1: ingoing rays (NMU + m), top -> bottom, I- = 0 at the top ----
   double chi0, eta0;
@@ -181,7 +211,7 @@ __device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int 
   stg(jm + f, 0.0);
 #pragma unroll
   for (int m = 0; m < NMU; ++m) {
-    I[m] = 0.0;
+    I[m] = (R)0;
     if (PM) {  // ingoing rays at the top: I prescribed, no local dependence
       stage_put<KD>(tX + m * KD * kWave, 0, lane, 0.0);
       stage_put<KD>(tE + m * KD * kWave, 0, lane, 0.0);
@@ -205,25 +235,7 @@ __device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int 
     stg(xb + 2 * kx, chi0);
     stg(xb + 2 * kx + 1, eta0);
     vel_rays<NMU>(C, chunk, k, fc, chi0, eta0, NMU, ch, Sx);
-    const double dz = ldc(dzt + 2 * (k - 1));  // segment k-1 -> k
-    double jac = 0.0;
-#pragma unroll
-    for (int m = 0; m < NMU; ++m) {
-      const double base = dz * (chp[m] + ch[m]);
-      double e, q, a, bx;
-      seg_coef<double, PM>(base * i2mu[m], 1.0 / base, mu2[m], e, q, a, bx);
-      const double Iup = I[m];
-      I[m] = fmar(e, Iup, fmar(q, Sp[m], a * (Sx[m] - Sp[m])));
-      jac = fmar(wm2[m], I[m], jac);
-      if (PM) {  // c_chi, c_eta of App. A.2 for this ray
-        const double rc = 1.0 / ch[m];
-        stage_put<KD>(tX + m * KD * kWave, k, lane,
-                      -(Sx[m] * rc) * a + dz * (i2mu[m] * (e * (Sp[m] - Iup) - (Sp[m] - Sx[m]) * bx)));
-        stage_put<KD>(tE + m * KD * kWave, k, lane, a * rc);
-      }
-      chp[m] = ch[m];
-      Sp[m] = Sx[m];
-    }
+    const double jac = step(k, (R)ldc(dzt + 2 * (k - 1)));  // segment k-1 -> k
     stg(jm + kx, jac);
     flush_down(k);
     vel_rate_step<NMU>(C, chunk, k, f, fc, NMU, I, wm2, true);
@@ -244,12 +256,12 @@ __device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int 
     const int k = nz - 1;
     const size_t kx = (size_t)k * fp + f;
     vel_rays<NMU>(C, chunk, k, fc, ldg(xb + 2 * kx), ldg(xb + 2 * kx + 1), 0, chp, Sp);
-    const double Bb = ldg(C.Bnu + (size_t)k * nnu + fc);
+    const R Bb = (R)ldg(C.Bnu + (size_t)k * nnu + fc);
     double jp = 0.0;
 #pragma unroll
     for (int m = 0; m < NMU; ++m) {
       I[m] = Bb;
-      jp = fmar(wm2[m], Bb, jp);
+      jp = fmar(wm2[m], (double)Bb, jp);
       if (PM) {  // outgoing rays at the bottom: I prescribed
         stage_put<KD>(tX + m * KD * kWave, k, lane, 0.0);
         stage_put<KD>(tE + m * KD * kWave, k, lane, 0.0);
@@ -263,25 +275,7 @@ __device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int 
   for (int k = nz - 2; k >= 0; --k) {
     const size_t kx = (size_t)k * fp + f;
     vel_rays<NMU>(C, chunk, k, fc, ldg(xb + 2 * kx), ldg(xb + 2 * kx + 1), 0, ch, Sx);
-    const double dz = ldc(dzt + 2 * k);  // segment k -> k+1
-    double jp = 0.0;
-#pragma unroll
-    for (int m = 0; m < NMU; ++m) {
-      const double base = dz * (ch[m] + chp[m]);
-      double e, q, a, bx;
-      seg_coef<double, PM>(base * i2mu[m], 1.0 / base, mu2[m], e, q, a, bx);
-      const double Iup = I[m];
-      I[m] = fmar(e, Iup, fmar(q, Sp[m], a * (Sx[m] - Sp[m])));
-      jp = fmar(wm2[m], I[m], jp);
-      if (PM) {  // a_chi, a_eta of App. A.2 for this ray
-        const double rc = 1.0 / ch[m];
-        stage_put<KD>(tX + m * KD * kWave, k, lane,
-                      -(Sx[m] * rc) * a + dz * (i2mu[m] * (e * (Sp[m] - Iup) - (Sp[m] - Sx[m]) * bx)));
-        stage_put<KD>(tE + m * KD * kWave, k, lane, a * rc);
-      }
-      chp[m] = ch[m];
-      Sp[m] = Sx[m];
-    }
+    const double jp = step(k, (R)ldc(dzt + 2 * k));  // segment k -> k+1
     vel_rate_step<NMU>(C, chunk, k, f, fc, 0, I, wm2, false);
     stage_put<KF>(tJ, k, lane, ldg(jm + kx) + jp);
     if (k % KF == 0) stage_flush<KF>(tJ, C.JT, k, nz, zp, f0, nnu, lane);
@@ -289,7 +283,7 @@ __device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int 
   }
 }
 
-template <bool PM, int NMU>
+template <typename R, bool PM, int NMU>
 __global__ __launch_bounds__(256) void k_formal_vel(const ColDev* __restrict__ cols,
                                                     const Tile* __restrict__ tiles, int ntiles) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -300,19 +294,20 @@ __global__ __launch_bounds__(256) void k_formal_vel(const ColDev* __restrict__ c
   const int chunk = uni(tiles[tid].chunk);
   const ColDev& C = cols[col];
   if (uni(C.st->mode) != (PM ? kModeNewton : kModeF)) return;
+  if (uni(C.st->cur_prec) != (sizeof(R) == sizeof(float) ? NLTE_FP32_FORM : NLTE_FP64)) return;
   extern __shared__ double stage[];  // [waves per block][VelStage doubles]
-  formal_tile_vel<PM, NMU>(C, chunk, lane, stage + wave * VelStage<PM, NMU>::doubles);
+  formal_tile_vel<R, PM, NMU>(C, chunk, lane, stage + wave * VelStage<PM, NMU>::doubles);
 }
 
-template <bool PM>
+template <typename R, bool PM>
 static void launch_formal_vel_mode(int nmu, int wpb, hipStream_t s, const ColDev* cols,
                                    const Tile* tiles, int ntiles) {
   const int blocks = (ntiles + wpb - 1) / wpb;
   switch (nmu) {
-#define NLTE_VEL_CASE(M)                                                                   \
-  case M:                                                                                  \
-    k_formal_vel<PM, M><<<blocks, 64 * wpb, (size_t)wpb * VelStage<PM, M>::doubles * 8, s>>>( \
-        cols, tiles, ntiles);                                                              \
+#define NLTE_VEL_CASE(M)                                                                      \
+  case M:                                                                                     \
+    k_formal_vel<R, PM, M><<<blocks, 64 * wpb, (size_t)wpb * VelStage<PM, M>::doubles * 8, s>>>( \
+        cols, tiles, ntiles);                                                                 \
     break;
     NLTE_VEL_CASE(1) NLTE_VEL_CASE(2) NLTE_VEL_CASE(3) NLTE_VEL_CASE(4)
     NLTE_VEL_CASE(5) NLTE_VEL_CASE(6) NLTE_VEL_CASE(7) NLTE_VEL_CASE(8)
@@ -321,12 +316,19 @@ static void launch_formal_vel_mode(int nmu, int wpb, hipStream_t s, const ColDev
   }
 }
 
-void launch_formal_vel(bool newton, int nmu, int wpb, hipStream_t s, const ColDev* cols,
+void launch_formal_vel(bool fp32, bool newton, int nmu, int wpb, hipStream_t s, const ColDev* cols,
                        const Tile* tiles, int ntiles) {
-  if (newton)
-    launch_formal_vel_mode<true>(nmu, wpb, s, cols, tiles, ntiles);
-  else
-    launch_formal_vel_mode<false>(nmu, wpb, s, cols, tiles, ntiles);
+  if (fp32) {
+    if (newton)
+      launch_formal_vel_mode<float, true>(nmu, wpb, s, cols, tiles, ntiles);
+    else
+      launch_formal_vel_mode<float, false>(nmu, wpb, s, cols, tiles, ntiles);
+  } else {
+    if (newton)
+      launch_formal_vel_mode<double, true>(nmu, wpb, s, cols, tiles, ntiles);
+    else
+      launch_formal_vel_mode<double, false>(nmu, wpb, s, cols, tiles, ntiles);
+  }
 }
 
 // Velocity fields: the same pair sums with the angle integral inside,

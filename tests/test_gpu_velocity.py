@@ -1,4 +1,5 @@
-"""Velocity fields on the device (Sect. 3.5) against the FP64 oracle.
+"""Velocity fields on the device (Sect. 3.5) against the FP64 oracle, in FP64
+and in the FP32 form.
 
 Each ray sees the line profiles Doppler-shifted by the velocity along it, so
 the device builds the opacity ray by ray inside its formal solution, keeps
@@ -157,10 +158,10 @@ def test_mixed_batch_equals_alone(ctx):
     from paper_2406_17234_amd import nlte
     specs = [(PROBLEMS["vel_small"](), nlte.FP64), (S.chromo6(nz=40, nnu=300), nlte.FP64),
              (_tiny_flow(), nlte.FP64), (S.slab3(), nlte.FP32_FORM),
-             (PROBLEMS["vel_8mu"](), nlte.FP64)]
+             (PROBLEMS["vel_8mu"](), nlte.FP64), (PROBLEMS["vel_small"](), nlte.FP32_FORM)]
     cols = [nlte.Column(ctx, p, precision=pr) for p, pr in specs]
     for jv in (nlte.JV_FD, nlte.JV_TANGENT):
-        opts = dict(ftol=1e-10, rtol=1e-4, maxiter=60, jv_method=jv)
+        opts = dict(ftol=1e-6, rtol=1e-4, maxiter=60, jv_method=jv, fp64_fallback=12)
         alone = [c.solve(**opts) for c in cols]
         outs, stats, rc = nlte.solve_batch(ctx, cols, **opts)
         for (n, _, sa, _), o, sb in zip(alone, outs, stats):
@@ -235,11 +236,51 @@ def test_tangent_solve_matches_oracle_root(ctx, method):
     assert maxrel(to_np(n), ref.n) < 1e-10
 
 
+@pytest.mark.parametrize("name", ["vel_1mu", "vel_small", "vel_full"])
+def test_fp32_form_residual(ctx, name):
+    """The FP32 form (recursion in FP32, opacity sums, rates and F in FP64)
+    of velocity columns against the FP64 oracle."""
+    from paper_2406_17234_amd import nlte
+    p = PROBLEMS[name]()
+    tb = O.setup(p)
+    n = perturbed(tb.nstar, seed=15, scale=0.2)
+    ref = O.residual(tb, n)
+    print(f"[case] velocity FP32 residual {name} dims={p.dims}", flush=True)
+    col = nlte.Column(ctx, p, precision=nlte.FP32_FORM)
+    out = col.residual(to_dev(n), want_J=True, want_R=True, want_Jbar=True)
+    big = ref.J > 1e-30 * ref.J.max()
+    assert maxrel(to_np(out["J"])[big], ref.J[big]) < 1e-4
+    R = to_np(out["R"])
+    assert maxrel(R[..., 0], ref.R_lu, floor=1e-300) < 1e-4
+    assert maxrel(R[..., 1], ref.R_ul, floor=1e-300) < 1e-4
+    assert maxrel(to_np(out["Jbar"]), ref.Jbar) < 1e-4
+    assert np.max(np.abs(to_np(out["F"]) - ref.F) / ref.G) < 2e-4
+    col.close()
+
+
+def test_fp32_form_solve_within_1e4(ctx):
+    """FP32-form velocity columns converge to within 1e-4 of the oracle's
+    FP64 root (with the FP64 fallback enabled, as in the batch)."""
+    from paper_2406_17234_amd import nlte
+    ref = _small_root()
+    col = nlte.Column(ctx, PROBLEMS["vel_small"](), precision=nlte.FP32_FORM)
+    n, _, st, rc = col.solve(ftol=1e-6, rtol=1e-3, maxiter=60, fp64_fallback=12)
+    print(st, flush=True)
+    assert rc == 0 and st["status"] == 0
+    assert maxrel(to_np(n), ref.n) < 1e-4
+    full = load_root("chromo6_vel_root")
+    col = nlte.Column(ctx, S.chromo6_vel(), precision=nlte.FP32_FORM)
+    n, _, st, rc = col.solve(ftol=1e-6, rtol=1e-2, maxiter=80, fp64_fallback=12)
+    print(st, flush=True)
+    assert rc == 0 and st["status"] == 0
+    assert maxrel(to_np(n), full) < 1e-4
+
+
 def test_rejected_combinations(ctx):
-    """Velocity columns: no FP32 form, no depth-parallel variant."""
+    """Velocity columns: no depth-parallel variant."""
     from paper_2406_17234_amd import nlte
     p = _tiny_flow()
-    for prec in (nlte.FP32_FORM, nlte.FP64 | nlte.DEPTH_SCAN):
+    for prec in (nlte.FP64 | nlte.DEPTH_SCAN, nlte.FP32_FORM | nlte.DEPTH_SCAN):
         with pytest.raises(nlte.NLTEError) as e:
             nlte.Column(ctx, p, precision=prec)
         assert e.value.status == nlte.NLTE_E_INVALID

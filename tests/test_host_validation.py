@@ -137,11 +137,12 @@ def test_null_arguments_rejected():
 
 
 def test_velocity_field_limits(base):
-    """A velocity field is accepted in FP64 with the sequential formal
-    solution and sized with its per-ray tables; the FP32 form and the
-    depth-parallel variant reject it."""
+    """A velocity field is accepted with the sequential formal solution (FP64
+    or the FP32 form) and sized with its per-ray tables; the depth-parallel
+    variant rejects it."""
     p = copy.deepcopy(base)
     p.atmos.vlos = np.linspace(0.0, 3e5, p.atmos.nz)
     assert nlte.plan_bytes(p) > nlte.plan_bytes(base) + 2 * p.grid.nmu * p.atmos.nz * p.grid.nnu * 8
-    assert _status(p, nlte.FP32_FORM) == nlte.NLTE_E_INVALID
+    assert _status(p, nlte.FP32_FORM) == nlte.NLTE_OK
     assert _status(p, nlte.FP64 | nlte.DEPTH_SCAN) == nlte.NLTE_E_INVALID
+    assert _status(p, nlte.FP32_FORM | nlte.DEPTH_SCAN) == nlte.NLTE_E_INVALID
