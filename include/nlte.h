@@ -201,13 +201,16 @@ typedef struct {
  * (HIP events on the solve's stream around each phase).  The formal-solution
  * launches of one residual call run on up to four streams at once (F mode,
  * Newton mode, and the FP64 ones of fallback columns); formal_ms is the
- * phase's duration, formal_f_ms that of the F-mode launches in the columns'
- * own precision, which run on the solve's stream. */
+ * time until the F-mode ones are done, formal_f_ms that of the F-mode
+ * launches in the columns' own precision, which run on the solve's stream;
+ * depth_ms runs from there until the rate integrals of the F-mode columns
+ * and the Newton-mode launches (formal solutions, rate integrals, pair
+ * sums) are all done. */
 typedef struct {
   int64_t steps;             /* solver steps (one residual per active column)   */
   int64_t formal_launches;   /* depth-recursion (formal-solution) launches      */
-  double formal_ms;          /* duration of the formal-solution phase           */
-  double depth_ms;           /* rate integrals + preconditioner pair sums       */
+  double formal_ms;          /* formal-solution phase of the F-mode columns     */
+  double depth_ms;           /* rate integrals, pair sums, Newton-mode tail     */
   double assemble_ms;        /* residual/preconditioner assembly                */
   double solver_ms;          /* Krylov/Newton step launches                     */
   double opacity_ms;         /* level coefficients + opacity/source function    */

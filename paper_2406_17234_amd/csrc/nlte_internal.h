@@ -301,7 +301,9 @@ struct BatchWork {
 // solution of every tile, rate integrals and preconditioner pair sums,
 // assembly).  ev, if not NULL, holds seven events, all recorded on s:
 // [0] before the coefficients, [1] before the formal-solution launches,
-// [2] after them (all streams joined), [3] after the lane-per-depth work,
+// [2] after the F-mode ones (with side streams: those of the FP64 side
+// stream joined; the Newton-mode stream may still run), [3] after the
+// lane-per-depth work and every side stream,
 // [4] after assembly, [5] left to the caller, [6] after the F-mode
 // formal-solution launches that run on s itself.
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev = nullptr);

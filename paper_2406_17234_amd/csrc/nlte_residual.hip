@@ -854,11 +854,12 @@ __device__ __forceinline__ void rates_shape(const ColDev& C, const RItem& it, in
 // before its first table loads.  The tables follow the evaluation's
 // precision, so that an FP32-form column after its FP64 fallback evaluates
 // the same F as an FP64 column.
-__device__ __forceinline__ void rates_item(const ColDev& C, int b, int k0) {
+__device__ __forceinline__ void rates_item(const ColDev& C, int b, int k0, int only_mode) {
   const int mode = ldc(&C.st->mode), prec = ldc(&C.st->cur_prec);
   const RItem it = ldc_rec(C.ritem + b);
-  if (mode == kModeIdle) return;  // (velocity-field columns list edges only: their line
-                                  // rates come from the formal-solution kernel)
+  // (velocity-field columns list edges only: their line rates come from the
+  // formal-solution kernel)
+  if (mode == kModeIdle || (only_mode >= 0 && mode != only_mode)) return;
   const int k = k0 + threadIdx.x;
   if (k >= C.nz) return;
   if (prec == NLTE_FP32_FORM)
@@ -997,16 +998,17 @@ __device__ __forceinline__ void pair_item(const ColDev& C, int p, int k0) {
 }
 
 // Rate integrals of a step: one item per (column, rate block of a piece, 64
-// depths), lane per depth.
+// depths), lane per depth; only_mode >= 0: the columns in that mode only.
 __global__ __launch_bounds__(64) void k_depthwork(const ColDev* __restrict__ cols,
-                                                  const int4* __restrict__ work, int nwork) {
+                                                  const int4* __restrict__ work, int nwork,
+                                                  int only_mode) {
   // the items of a column are consecutive in the list: keeping them on one
   // XCD lets its transitions share the column's J in that XCD's L2
   const int w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= nwork) return;
   const int4 it = work[w];
   const int col = uni(it.x), idx = uni(it.y), k0 = uni(it.z);
-  rates_item(cols[col], idx, k0);
+  rates_item(cols[col], idx, k0, only_mode);
 }
 
 // Preconditioner pair sums of the columns in Newton mode: one item per
@@ -1302,26 +1304,50 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     }
   }
   if (ev) chk(hipEventRecord(ev[6], s));  // end of the F-mode launches on s
-  if (SS)
-    for (int i = 0; i < 3; ++i) {
-      chk(hipEventRecord(SS->join[i], SS->st[i]));
-      chk(hipStreamWaitEvent(s, SS->join[i], 0));
-    }
-  if (ev) chk(hipEventRecord(ev[2], s));
   // The rate integrals stream V and J of many (column, segment) pairs at
   // once; at full occupancy (32 waves per CU) they ran 20 % slower than with
   // at most 13.  The kernel uses no LDS: the allocation only caps waves per CU
   // (160 KB / 12 KB).
   constexpr size_t kDepthworkLds = 12 * 1024;
-  if (bw.nrate0 > 0)
-    k_depthwork<<<bw.nrate0, 64, kDepthworkLds, s>>>(bw.cols, bw.rate_work, bw.nrate0);
-  if (bw.any_newton && bw.nrate > bw.nrate0)
-    k_pairsum<<<bw.nrate - bw.nrate0, 64, 0, s>>>(bw.cols, bw.rate_work + bw.nrate0,
-                                                   bw.nrate - bw.nrate0);
   bool any_vel = false;
   for (int g = 0; g < bw.ngroup; ++g) any_vel |= bw.groups[g].vel != 0;
-  if (any_vel && bw.any_newton && bw.nrate > bw.nrate0)
-    launch_pairsum_vel(bw.cols, bw.rate_work + bw.nrate0, bw.nrate - bw.nrate0, s);
+  const bool pairs = bw.any_newton && bw.nrate > bw.nrate0;
+  if (SS) {
+    // The F-mode columns' rate integrals start once their formal solutions
+    // are done (s, and sF64 for fallback columns), while the Newton-mode
+    // launches (longer: derivatives) may still run; the Newton-mode columns'
+    // rate integrals and pair sums follow their own formal solutions on
+    // sNewton.  Items of columns in the other mode return at once.
+    chk(hipEventRecord(SS->join[1], SS->st[1]));
+    chk(hipStreamWaitEvent(s, SS->join[1], 0));
+    if (ev) chk(hipEventRecord(ev[2], s));
+    if (bw.nrate0 > 0)
+      k_depthwork<<<bw.nrate0, 64, kDepthworkLds, s>>>(bw.cols, bw.rate_work, bw.nrate0, kModeF);
+    if (bw.any_newton) {
+      chk(hipEventRecord(SS->join[2], SS->st[2]));
+      chk(hipStreamWaitEvent(sNewton, SS->join[2], 0));
+      if (bw.nrate0 > 0)
+        k_depthwork<<<bw.nrate0, 64, 0, sNewton>>>(bw.cols, bw.rate_work, bw.nrate0, kModeNewton);
+      if (pairs)
+        k_pairsum<<<bw.nrate - bw.nrate0, 64, 0, sNewton>>>(bw.cols, bw.rate_work + bw.nrate0,
+                                                             bw.nrate - bw.nrate0);
+      if (any_vel && pairs)
+        launch_pairsum_vel(bw.cols, bw.rate_work + bw.nrate0, bw.nrate - bw.nrate0, sNewton);
+    }
+    for (int i = 0; i < 3; i += 2) {
+      chk(hipEventRecord(SS->join[i], SS->st[i]));
+      chk(hipStreamWaitEvent(s, SS->join[i], 0));
+    }
+  } else {
+    if (ev) chk(hipEventRecord(ev[2], s));
+    if (bw.nrate0 > 0)
+      k_depthwork<<<bw.nrate0, 64, kDepthworkLds, s>>>(bw.cols, bw.rate_work, bw.nrate0, -1);
+    if (pairs)
+      k_pairsum<<<bw.nrate - bw.nrate0, 64, 0, s>>>(bw.cols, bw.rate_work + bw.nrate0,
+                                                     bw.nrate - bw.nrate0);
+    if (any_vel && pairs)
+      launch_pairsum_vel(bw.cols, bw.rate_work + bw.nrate0, bw.nrate - bw.nrate0, s);
+  }
   if (ev) chk(hipEventRecord(ev[3], s));
   {
     const int nsub = (bw.maxnz + kAsmDepths - 1) / kAsmDepths;
