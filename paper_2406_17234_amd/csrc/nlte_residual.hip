@@ -274,7 +274,13 @@ constexpr int kFuseMinTiles = 4096;
 template <typename R, bool PM> struct StageDepths {
   static constexpr int value = PM ? 4 : 8;
 };
-constexpr int kDepthBlock = 4;
+// Depths per operand block of the sweeps: 4 in FP32 (more loads in flight
+// per wait), 2 in FP64, whose larger registers cost occupancy instead
+// (batch6 FP64 F-only 10.15 -> 10.00 ms, solve 1167 -> 1133 ms with 2; the
+// FP32 form is slower with 2: 5.63 -> 5.81 ms).
+template <typename R> struct DepthBlock {
+  static constexpr int value = sizeof(R) == sizeof(float) ? 4 : 2;
+};
 
 template <typename R, bool PM, int NMU>
 __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane, double* tile,
@@ -307,11 +313,11 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
     wm2d[m] = C.wm2[m];
   }
 
-  // Both sweeps take their per-depth operands kDepthBlock depths at a time,
+  // Both sweeps take their per-depth operands DepthBlock depths at a time,
   // loaded one block ahead (depth indices clamped into the column, so every
   // load is unconditional): a wave has that many steps of arithmetic in hand
   // while a block's loads are in flight.
-  constexpr int U = kDepthBlock;
+  constexpr int U = DepthBlock<R>::value;
 
   // ---- sweep 1: ingoing rays, top -> bottom (I- = 0 at the top) ----
   R I[NMU];
