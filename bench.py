@@ -28,11 +28,16 @@ sys.path.insert(0, ROOT)
 
 from paper_2406_17234_amd import synth as S  # noqa: E402
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, non-packed VALU issue
-PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
+# MI355X FP32 vector peak: 157.3 TFLOP/s (256 CUs, 2.4 GHz), i.e. 7.87e13 FMA
+# lane-operations per second.  The issue-rate probes measure what the
+# non-packed FMA that the kernels use reaches of it.
+PEAK_VALU_OPS = 157.3e12 / 2
 # algorithmic work per depth-point: ~10 VALU ops plus half an exp and half a
-# reciprocal (shared by the two rays of an angle), transcendental at 1/4 rate
-OPS_PER_DP = 10.0 + 0.5 * 4 + 0.5 * 4
+# reciprocal (shared by the two rays of an angle), each transcendental
+# counted as the FMA issue slots it costs: 4 unless the issue-rate probes
+# have measured it (main() then replaces this value)
+TRANS_SLOTS = 4.0
+OPS_PER_DP = 10.0 + 0.5 * TRANS_SLOTS + 0.5 * TRANS_SLOTS
 
 # HBM bytes per F-mode k_formal launch (the roofline kernel) from FETCH_SIZE /
 # WRITE_SIZE counter runs of this workload, each scaled by the same counter on
@@ -464,6 +469,25 @@ def copy_calibration(nbytes=256 << 20, reps=3):
     print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}))
 
 
+def issue_rates(ctx, nlte):
+    """The denominators of the VALU roofline, measured: lane operations per
+    second of the FP32 and FP64 FMA, the FP32 exponential and reciprocal on a
+    full device (nlte_issue_rate), the FP32 FMA's rate against the peak used
+    for `peak`, and what an exponential or a reciprocal costs in FP32 FMA
+    issue slots."""
+    ops = {"fma_f32": nlte.PROBE_FMA_F32, "fma_f64": nlte.PROBE_FMA_F64,
+           "exp_f32": nlte.PROBE_EXP_F32, "rcp_f32": nlte.PROBE_RCP_F32}
+    r = {k: ctx.issue_rate(op, 16384) for k, op in ops.items()}
+    out = {k: v for k, v in r.items()}
+    out["unit"] = "lane-ops/s"
+    out["fma_f32_vs_peak"] = r["fma_f32"] / PEAK_VALU_OPS
+    out["exp_slots"] = r["fma_f32"] / r["exp_f32"]
+    out["rcp_slots"] = r["fma_f32"] / r["rcp_f32"]
+    print(f"[bench] issue rates: " + ", ".join(f"{k} {v:.3e}" for k, v in r.items()),
+          file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -518,6 +542,8 @@ def main():
                     help="only run that F-only loop (--runs evaluations) and print its figures: "
                          "a short command for profilers")
     ap.add_argument("--runs", type=int, default=100)
+    ap.add_argument("--issue-rates", type=int, default=1,
+                    help="measure the VALU issue rates behind the roofline's peak (0: skip)")
     ap.add_argument("--velocity", type=int, default=512,
                     help="columns of the velocity-field batch leg (0: skip the velocity leg)")
     ap.add_argument("--velocity-only", action="store_true",
@@ -568,6 +594,11 @@ def main():
     import torch
     from paper_2406_17234_amd import nlte
     ctx = nlte.Context(0)
+    rates = None
+    if args.issue_rates:
+        global OPS_PER_DP
+        rates = issue_rates(ctx, nlte)
+        OPS_PER_DP = 10.0 + 0.5 * rates["exp_slots"] + 0.5 * rates["rcp_slots"]
     t0 = time.perf_counter()
     cols = [nlte.Column(ctx, p, precision=prec) for p in problems]
     torch.cuda.synchronize()
@@ -680,6 +711,8 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if rates:
+        out["roofline"]["issue_rates_measured"] = rates
     def other_solve(label, **kw):
         # the same batch solved with another inner solver or product: one
         # warm-up solve, one timed solve

@@ -487,6 +487,22 @@ int32_t nlte_struct_size(const char *name);
  * Dawson series for |v| < 8, asymptotic series beyond).  For tests. */
 nlte_status nlte_voigt_host(double a, const double *v, int32_t n, double *out);
 
+/* Issue-rate probes (measurement only: the denominators of the depth
+ * recursion's VALU roofline, not part of the method).  Runs `iters`
+ * operations of kind `op` in each of 8 independent chains per lane on a
+ * full device (8 workgroups of 256 lanes per CU) of the context's device,
+ * after one warm-up launch, timed with HIP events on a stream of its own;
+ * *lane_ops_per_s = lanes x iters x 8 / time.  iters: a multiple of 4 in
+ * [4, 2^24].  Allocates and frees a small output buffer.  NLTE_E_INVALID for
+ * an unknown op or iters out of range, NLTE_E_DEVICE for HIP errors. */
+typedef enum {
+  NLTE_PROBE_FMA_F32 = 0, /* v_fma_f32 (non-packed)          */
+  NLTE_PROBE_FMA_F64 = 1, /* v_fma_f64                       */
+  NLTE_PROBE_EXP_F32 = 2, /* v_exp_f32 (base-2 exponential)  */
+  NLTE_PROBE_RCP_F32 = 3  /* v_rcp_f32                       */
+} nlte_probe_op;
+nlte_status nlte_issue_rate(nlte_ctx *ctx, int32_t op, int32_t iters, double *lane_ops_per_s);
+
 #ifdef __cplusplus
 }
 #endif

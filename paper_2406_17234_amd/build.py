@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnlte.so")
 SOURCES = ["nlte_api.hip", "nlte_residual.hip", "nlte_velocity.hip", "nlte_solver.hip",
-           "nlte_server.hip", "nlte_plan.hip", "nlte_tangent.hip"]
+           "nlte_server.hip", "nlte_plan.hip", "nlte_tangent.hip", "nlte_probe.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -20,6 +20,7 @@ NLTE_OK, NLTE_E_INVALID, NLTE_E_NOMEM, NLTE_E_DEVICE = 0, -1, -2, -3
 NLTE_E_NOCONV, NLTE_E_NONFINITE, NLTE_E_BUSY = -4, -5, -6
 DEPTH_SCAN = 0x100  # OR into a column's precision: depth-parallel formal solution
 FP64, FP32_FORM = 0, 1
+PROBE_FMA_F32, PROBE_FMA_F64, PROBE_EXP_F32, PROBE_RCP_F32 = 0, 1, 2, 3
 KRYLOV_GMRES, KRYLOV_BICGSTAB = 0, 1  # nlte_solve_opts.krylov_method
 JV_FD, JV_TANGENT = 0, 1               # nlte_solve_opts.jv_method
 STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "DEVICE", -4: "NOCONV",
@@ -163,6 +164,7 @@ def lib():
         L.nlte_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
         L.nlte_solve_opts_default.restype = None
         L.nlte_voigt_host.argtypes = [C.c_double, _dp, C.c_int32, _dp]
+        L.nlte_issue_rate.argtypes = [vp, C.c_int32, C.c_int32, _dp]
         L.nlte_struct_size.argtypes = [C.c_char_p]
         L.nlte_struct_size.restype = C.c_int32
         L.nlte_plan_create.argtypes = [vp, C.POINTER(vp), C.c_int32, C.POINTER(vp), C.POINTER(vp),
@@ -240,6 +242,12 @@ class Context:
     def profile(self, on: bool = True):
         """Turn kernel timing of solves on/off (clears the accumulators)."""
         _check(lib().nlte_profile_enable(self.h, int(on)))
+
+    def issue_rate(self, op: int, iters: int = 16384) -> float:
+        """Lane operations per second of one vector operation (nlte_issue_rate)."""
+        r = C.c_double()
+        _check(lib().nlte_issue_rate(self.h, op, iters, C.byref(r)))
+        return r.value
 
     def read_profile(self) -> dict:
         p = Profile()
