@@ -44,13 +44,13 @@ OPS_PER_DP = 10.0 + 0.5 * TRANS_SLOTS + 0.5 * TRANS_SLOTS
 # a plain copy kernel; valid only for the kernel source they were taken on
 # (hash of its files).
 TRAFFIC = {
-    "batch6": {"source": "973add010432f075", "bytes_per_launch": 6.1028e+09,
-               "read": 7.0884e+11 / 200, "written": 5.1173e+11 / 200},
+    "batch6": {"source": "5c7cd10173125e2e", "bytes_per_launch": 5.5664e+09,
+               "read": 5.6174e+11 / 192, "written": 5.0700e+11 / 192},
 }
 # the same for the F-mode velocity formal solution of the 512-column velocity
 # batch (mean over the profiled solve's 140 launches)
-TRAFFIC_VEL = {"source": "24dc45070f6817d1", "columns": 512, "bytes_per_launch": 6.366e+09,
-               "read": 5.355e+09, "written": 1.011e+09}
+TRAFFIC_VEL = {"source": "4a06768126913ce6", "columns": 512, "bytes_per_launch": 6.3707e+09,
+               "read": 5.3594e+09, "written": 1.0113e+09}
 KERNEL_SOURCES = ["paper_2406_17234_amd/csrc/nlte_residual.hip",
                   "paper_2406_17234_amd/csrc/nlte_kernels.h",
                   "paper_2406_17234_amd/csrc/nlte_internal.h"]
