@@ -49,8 +49,8 @@ TRAFFIC = {
 }
 # the same for the F-mode velocity formal solution of the 512-column velocity
 # batch (mean over the profiled solve's 140 launches)
-TRAFFIC_VEL = {"source": "4a06768126913ce6", "columns": 512, "bytes_per_launch": 6.3707e+09,
-               "read": 5.3594e+09, "written": 1.0113e+09}
+TRAFFIC_VEL = {"source": "b1ed96cdee71eb89", "columns": 512, "bytes_per_launch": 6.3667e+09,
+               "read": 5.3555e+09, "written": 1.0112e+09}
 KERNEL_SOURCES = ["paper_2406_17234_amd/csrc/nlte_residual.hip",
                   "paper_2406_17234_amd/csrc/nlte_kernels.h",
                   "paper_2406_17234_amd/csrc/nlte_internal.h"]

@@ -790,7 +790,12 @@ static nlte_status plan_column(const nlte_atmos_desc* A, const nlte_atom_desc* M
   // window.  The rate integrals of the s transitions covering a piece run as
   // blocks of up to kRateBlk lines and kRateBlk edges; the pair sums give the
   // piece s^2 entries (t, t') and run as blocks of at most kPairBlk^2 of them
-  const int seg_len = scan ? kSegLenScan : kSegLen;
+  // velocity-field columns take the shortest pieces, since their pair sums
+  // walk every ray at every frequency (512-column velocity batch: 1410 ms
+  // per solve with pieces of 512, 1064 with 96, 989 with 32, 982 with 16,
+  // whose extra entries slow the assembly)
+  constexpr int kSegLenVel = 32;
+  const int seg_len = scan ? kSegLenScan : C.vel ? kSegLenVel : kSegLen;
   std::vector<int> cuts;
   for (int t = 0; t < ntr; ++t) {
     cuts.push_back(tr[t].wlo);

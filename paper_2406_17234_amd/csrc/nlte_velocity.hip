@@ -430,6 +430,131 @@ __device__ void pair_vel(const ColDev& C, const PItem& it, int k) {
       }
 }
 
+// The same sums for a block whose transition lists hold at most one line
+// each (lt, lu: its slot, or -1), taken in factored form: only a line's
+// profile depends on the ray, so for each frequency the ray sums
+//   D1 = sum_r w_r Dchi_r,       D2 = sum_r w_r Dd_r   (Dd = 2 h nu^3/c^2 Deta - Dchi),
+//   X1 = sum_r w_r V_r Dchi_r,   X2 = sum_r w_r V_r Dd_r  (the list's line),
+//   Z1 = sum_r w_r Vt_r Vu_r Dchi_r, Z2 likewise           (line with line)
+// are formed once and every pair (t, u) of the block takes the one that
+// fits it (edges enter with their ray-independent cross-sections), instead
+// of every pair running its own sum over the rays.  Algebraically the sums
+// of pair_vel; rounded in another order.
+__device__ void pair_vel_one_line(const ColDev& C, const PItem& it, int k, int lt, int lu) {
+  const int nz = C.nz, L = C.L, zp = C.zp, nray = C.nray, nmu = C.nmu, nline = C.nline;
+  const int f0 = it.f0, nf = it.f1 - it.f0, nt = it.nt, nu = it.nu;
+  const size_t rs = (size_t)C.nnu * zp;
+  const double *At[kPairBlk], *Au[kPairBlk], *cw[kPairBlk];  // edges' cross-sections at f0
+  double pa[kPairBlk], pb[kPairBlk], g0u[kPairBlk], gEu[kPairBlk];
+  bool edge = false;
+  const double *Vlt = nullptr, *Vlu = nullptr;  // the lines' per-ray V at f0, this depth
+  size_t rlt = 0, rlu = 0;
+#pragma unroll
+  for (int i = 0; i < kPairBlk; ++i) {
+    const int t = it.t[i < nt ? i : 0];
+    const TrDev& T = C.tr[t];
+    const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
+    const double nl = C.eval_n[k * L + uni(T.lo)], nup = C.eval_n[k * L + uni(T.up)];
+    At[i] = C.V + uni(T.voff) + (f0 - wlo);  // (not read for the line)
+    if (t < nline) {
+      if (i == lt) {
+        Vlt = C.VRT + (size_t)nray * uni(T.voff) + (size_t)(f0 - wlo) * nz + k;
+        rlt = (size_t)nz * wl;
+      }
+      pa[i] = nl - uni(T.g) * nup;
+      pb[i] = 0.0;
+    } else {
+      pa[i] = nl;
+      pb[i] = C.rho_bf[k * C.nbf + (t - nline)] * nup;
+      edge |= i < nt;
+    }
+    cw[i] = C.cw + uni(T.cwoff) + (f0 - wlo);
+    const int u = it.u[i < nu ? i : 0];
+    const TrDev& U = C.tr[u];
+    const int ulo = uni(U.wlo), ul = uni(U.whi) - ulo;
+    Au[i] = C.V + uni(U.voff) + (f0 - ulo);
+    if (u < nline) {
+      if (i == lu) {
+        Vlu = C.VRT + (size_t)nray * uni(U.voff) + (size_t)(f0 - ulo) * nz + k;
+        rlu = (size_t)nz * ul;
+      }
+      g0u[i] = uni(U.g);
+      gEu[i] = 0.0;
+    } else {
+      g0u[i] = 0.0;
+      gEu[i] = C.rho_bf[k * C.nbf + (u - nline)];
+      edge |= i < nu;
+    }
+  }
+  const bool same_line = lt >= 0 && lu >= 0 && it.t[lt] == it.u[lu];
+  const double* DX = C.DXR + (size_t)f0 * zp + k;
+  const double* DE = C.DER + (size_t)f0 * zp + k;
+  const double* EB = edge ? C.EbfT + (size_t)f0 * zp + k : DX;  // DX: any valid address
+  double m1[kPairBlk][kPairBlk], m2[kPairBlk][kPairBlk];
+#pragma unroll
+  for (int i = 0; i < kPairBlk; ++i)
+#pragma unroll
+    for (int j = 0; j < kPairBlk; ++j) m1[i][j] = m2[i][j] = 0.0;
+  for (int q = 0; q < nf; ++q) {
+    const size_t oq = (size_t)q * zp;
+    const double E = edge ? ldg(EB + oq) : 0.0;
+    const double gam = ldg(C.gam + f0 + q);
+    double d1 = 0.0, d2 = 0.0, xt1 = 0.0, xt2 = 0.0, xu1 = 0.0, xu2 = 0.0, z1 = 0.0, z2 = 0.0;
+    for (int r = 0; r < nray; ++r) {
+      const double w = C.wm2[r < nmu ? r : r - nmu];
+      const double dx = ldg(DX + r * rs + oq), de = ldg(DE + r * rs + oq);
+      const double wx = w * dx, wd = w * (gam * de - dx);
+      d1 += wx;
+      d2 += wd;
+      const double vt = lt >= 0 ? ldg(Vlt + r * rlt + (size_t)q * nz) : 0.0;
+      const double vu = lu >= 0 ? (same_line ? vt : ldg(Vlu + r * rlu + (size_t)q * nz)) : 0.0;
+      xt1 = fma(vt, wx, xt1);
+      xt2 = fma(vt, wd, xt2);
+      xu1 = fma(vu, wx, xu1);
+      xu2 = fma(vu, wd, xu2);
+      z1 = fma(vt * vu, wx, z1);
+      z2 = fma(vt * vu, wd, z2);
+    }
+#pragma unroll
+    for (int i = 0; i < kPairBlk; ++i) {
+      if (i >= nt) break;
+      const double a0 = cw[i][q] * (pa[i] - pb[i] * E);
+      const double at = i == lt ? 1.0 : ldg(At[i] + q);
+#pragma unroll
+      for (int j = 0; j < kPairBlk; ++j) {
+        if (j >= nu) break;
+        const double gu = g0u[j] + gEu[j] * E;
+        const double au = j == lu ? 1.0 : ldg(Au[j] + q);
+        double s1, s2;
+        if (i == lt && j == lu) {
+          s1 = z1;
+          s2 = z2;
+        } else if (i == lt) {
+          s1 = au * xt1;
+          s2 = au * xt2;
+        } else if (j == lu) {
+          s1 = at * xu1;
+          s2 = at * xu2;
+        } else {
+          s1 = (at * au) * d1;
+          s2 = (at * au) * d2;
+        }
+        m1[i][j] = fma(a0, s1, m1[i][j]);
+        m2[i][j] = fma(a0 * gu, s2, m2[i][j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kPairBlk; ++i)
+#pragma unroll
+    for (int j = 0; j < kPairBlk; ++j)
+      if (i < nt && j < nu) {
+        double* dst = C.M + ((size_t)(it.e0 + i * it.es + j) * nz + k) * 2;
+        stg(dst, m1[i][j]);
+        stg(dst + 1, m2[i][j]);
+      }
+}
+
 // The pair-sum items of velocity-field columns, over the same work list (the
 // other columns' items return at once): a kernel of its own, so that the ray
 // loops do not cost the static kernel registers.
@@ -444,7 +569,22 @@ __global__ __launch_bounds__(64) void k_pairsum_vel(const ColDev* __restrict__ c
   const PItem it = ldc_rec(C.pitem + uni(wi.y));
   const int k = uni(wi.z) + threadIdx.x;
   if (k >= C.nz) return;
-  pair_vel(C, it, k);
+  // the line slots of the two lists (the factored form takes at most one each)
+  int lt = -1, lu = -1, nlt = 0, nlu = 0;
+  for (int i = 0; i < it.nt; ++i)
+    if (it.t[i] < C.nline) {
+      lt = i;
+      ++nlt;
+    }
+  for (int j = 0; j < it.nu; ++j)
+    if (it.u[j] < C.nline) {
+      lu = j;
+      ++nlu;
+    }
+  if (nlt <= 1 && nlu <= 1)
+    pair_vel_one_line(C, it, k, lt, lu);
+  else
+    pair_vel(C, it, k);
 }
 
 void launch_pairsum_vel(const ColDev* cols, const int4* work, int nwork, hipStream_t s) {
