@@ -78,6 +78,18 @@ __device__ __forceinline__ int xcd_item(int b, int nb) {
   return x * q + (x < r ? x : r) + l;
 }
 
+// The same numbering when only the first nlive of a grid's items have work
+// (a count known on the device only): block b gets item xcd_item(b, nlive),
+// or -1 if it has none.  The blocks given an item are exactly those that
+// xcd_item(., nlive) would use, all below any grid of at least nlive blocks.
+__device__ __forceinline__ int xcd_live_item(int b, int nlive) {
+  constexpr int kXcd = 8;
+  const int q = nlive / kXcd, r = nlive % kXcd;
+  const int x = b % kXcd, l = b / kXcd;
+  if (l >= q + (x < r ? 1 : 0)) return -1;
+  return x * q + (x < r ? x : r) + l;
+}
+
 // Evaluation modes of one residual call.
 enum EvalMode : int {
   kModeIdle = 0,    // column takes no part in this step
@@ -295,7 +307,31 @@ struct BatchWork {
   int any_tangent = 0;            // columns may request tangent products
   int single_stream = 0;          // 1: every launch on the caller's stream (no side streams
                                   // are created or used)
+  // Per-step mode lists (optional; NULL: every formal-solution launch walks
+  // its group's whole tile list and waves of other modes return).  At the
+  // start of each residual call the tiles of the sequential static groups are
+  // sorted by the launch that will evaluate them (F or Newton mode, in the
+  // column's current precision), so that each launch starts with the waves
+  // that have work.  gidx [ncol]: each column's group if that group uses the
+  // lists, else -1; mlist: 4 lists of capacity ntiles (F, Newton, and the
+  // FP64 F and Newton launches of an FP32-form group's fallback columns);
+  // mcount: their lengths [kMaxGroups][4], cleared by a fill kernel first.
+  const int* gidx = nullptr;
+  Tile* mlist = nullptr;
+  int* mcount = nullptr;
 };
+
+// The host copy of gidx (per-step mode lists) for the groups in bw and their
+// tile list; the caller copies it to the device.
+inline void set_mode_groups(const BatchWork& bw, const std::vector<Tile>& tiles, int ncol,
+                            std::vector<int>& gidx) {
+  gidx.assign(ncol, -1);
+  for (int g = 0; g < bw.ngroup; ++g) {
+    const TileGroup& G = bw.groups[g];
+    if (G.scan || G.vel) continue;
+    for (int t = G.first; t < G.first + G.count; ++t) gidx[tiles[t].col] = g;
+  }
+}
 
 // Residual launches for a batch (level coefficients and opacity, formal
 // solution of every tile, rate integrals and preconditioner pair sums,

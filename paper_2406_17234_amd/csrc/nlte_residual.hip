@@ -54,10 +54,40 @@ namespace nlte {
 // In the FP32 form, B_nu and E are made in FP32 from T and nu where they are
 // used (one exponential per (k, nu), shared by the rays), unless the caller
 // gave the background emissivity; the FP64 form reads its FP64 tables.
+//
+// With per-step mode lists (ml.mlist non-NULL), each column of a listed group
+// also appends its chunks to the list of the formal-solution launch that
+// will evaluate it (one atomic per column; the order within a list depends
+// on the atomics, which only moves waves between CUs: each tile is evaluated
+// by one wave wherever it runs, so the results are the same bits).
+struct ModeLists {
+  const int* gidx;
+  Tile* mlist;
+  int* mcount;
+  int ntiles;
+  int first[kMaxGroups];  // a group's first tile
+  int fp32[kMaxGroups];   // FP32-form group: fallback columns go to lists 2, 3
+};
+
 __global__ __launch_bounds__(256) void k_coef(const ColDev* __restrict__ cols,
-                                              const int* __restrict__ act) {
-  const ColDev& C = cols[act ? act[blockIdx.x] : blockIdx.x];
-  if (uni(C.st->mode) == kModeIdle) return;
+                                              const int* __restrict__ act, ModeLists ml) {
+  const int c = act ? act[blockIdx.x] : blockIdx.x;
+  const ColDev& C = cols[c];
+  const int mode = uni(C.st->mode);
+  if (mode == kModeIdle) return;
+  if (ml.mlist) {
+    const int g = ml.gidx[c];
+    if (g >= 0) {
+      __shared__ int base;
+      const int li = (mode == kModeNewton ? 1 : 0) +
+                     (ml.fp32[g] && uni(C.st->cur_prec) == NLTE_FP64 ? 2 : 0);
+      const int nch = C.nchunk;
+      if (threadIdx.x == 0) base = atomicAdd(ml.mcount + 4 * g + li, nch);
+      __syncthreads();
+      Tile* dst = ml.mlist + (size_t)li * ml.ntiles + ml.first[g] + base;
+      for (int ch = threadIdx.x; ch < nch; ch += blockDim.x) dst[ch] = Tile{c, ch};
+    }
+  }
   const int nz = C.nz, ntr = C.ntr, nline = C.nline, L = C.L;
   const int per = ntr + 2;
   for (int id = threadIdx.x; id < nz * per; id += blockDim.x) {
@@ -732,14 +762,28 @@ static void launch_formal_scan_mu(int nmu, hipStream_t s, const ColDev* cols, co
 template <typename R, bool PM, int NMU>
 __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
                                                 const Tile* __restrict__ tiles, int ntiles,
-                                                int fused) {
+                                                int fused, const Tile* __restrict__ mlist,
+                                                const int* __restrict__ mcount) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   // the chunks of a column are consecutive tiles: keeping them on one XCD
   // lets them share the column's level coefficients and the table lines
   // their rows have in common in that XCD's L2
-  const int tid = xcd_item(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
-  if (tid >= ntiles) return;
+  int tid;
+  if (mcount) {
+    // this step's list of the launch (the grid covers the whole group; the
+    // live blocks are dealt over the XCDs as xcd_item deals a full grid)
+    const int n = uni(ldc(mcount));
+    const int wpb = blockDim.x >> 6;
+    const int blk = xcd_live_item(blockIdx.x, (n + wpb - 1) / wpb);
+    if (blk < 0) return;
+    tid = blk * wpb + wave;
+    if (tid >= n) return;
+    tiles = mlist;
+  } else {
+    tid = xcd_item(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
+    if (tid >= ntiles) return;
+  }
   const int col = uni(tiles[tid].col);
   const int chunk = uni(tiles[tid].chunk);
   const ColDev& C = cols[col];
@@ -754,12 +798,15 @@ __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
 
 template <typename R, bool PM>
 static void launch_formal_mu(int nmu, int wpb, hipStream_t s, const ColDev* cols,
-                             const Tile* tiles, int ntiles, int fused) {
+                             const Tile* tiles, int ntiles, int fused,
+                             const Tile* mlist = nullptr, const int* mcount = nullptr) {
   const int blocks = (ntiles + wpb - 1) / wpb;
   const size_t lds = (size_t)wpb * (PM ? 3 : 1) * StageDepths<R, PM>::value * kWave * sizeof(double);
   switch (nmu) {
 #define NLTE_FORMAL_CASE(M) \
-  case M: k_formal<R, PM, M><<<blocks, 64 * wpb, lds, s>>>(cols, tiles, ntiles, fused); break;
+  case M: \
+    k_formal<R, PM, M><<<blocks, 64 * wpb, lds, s>>>(cols, tiles, ntiles, fused, mlist, mcount); \
+    break;
     NLTE_FORMAL_CASE(1) NLTE_FORMAL_CASE(2) NLTE_FORMAL_CASE(3) NLTE_FORMAL_CASE(4)
     NLTE_FORMAL_CASE(5) NLTE_FORMAL_CASE(6) NLTE_FORMAL_CASE(7) NLTE_FORMAL_CASE(8)
 #undef NLTE_FORMAL_CASE
@@ -1233,6 +1280,11 @@ hipError_t residual_streams_init() {
   return side_streams(&S);
 }
 
+__global__ __launch_bounds__(256) void k_fill_int(int* __restrict__ p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   // the first failing event or stream call, else the launch status at the end
   hipError_t er = hipSuccess;
@@ -1241,7 +1293,20 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   };
   if (ev) chk(hipEventRecord(ev[0], s));
   const int nblk = bw.act ? bw.nact : bw.ncol;
-  k_coef<<<nblk, 256, 0, s>>>(bw.cols, bw.act);
+  const bool mlists = bw.mlist && bw.mcount && bw.gidx;
+  ModeLists ml{};
+  if (mlists) {
+    ml.gidx = bw.gidx;
+    ml.mlist = bw.mlist;
+    ml.mcount = bw.mcount;
+    ml.ntiles = bw.ntiles;
+    for (int g = 0; g < bw.ngroup; ++g) {
+      ml.first[g] = bw.groups[g].first;
+      ml.fp32[g] = bw.groups[g].prec == NLTE_FP32_FORM;
+    }
+    k_fill_int<<<1, 4 * kMaxGroups, 0, s>>>(bw.mcount, 4 * kMaxGroups, 0);
+  }
+  k_coef<<<nblk, 256, 0, s>>>(bw.cols, bw.act, ml);
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
     if (G.vel) continue;  // the velocity formal solution makes its opacity itself
@@ -1300,13 +1365,22 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
       }
       continue;
     }
+    // this step's lists: [0] F, [1] Newton in the group's precision, [2] F,
+    // [3] Newton in FP64 for an FP32-form group's fallback columns
+    auto lst = [&](int li) -> const Tile* {
+      return mlists ? bw.mlist + (size_t)li * bw.ntiles + G.first : nullptr;
+    };
+    auto cnt = [&](int li) -> const int* { return mlists ? bw.mcount + 4 * g + li : nullptr; };
     if (f32) {
-      launch_formal_mu<float, false>(G.nmu, nb, s, bw.cols, tl, G.count, fused);
-      if (bw.any_newton) launch_formal_mu<float, true>(G.nmu, nb, sNewton, bw.cols, tl, G.count, fused);
+      launch_formal_mu<float, false>(G.nmu, nb, s, bw.cols, tl, G.count, fused, lst(0), cnt(0));
+      if (bw.any_newton)
+        launch_formal_mu<float, true>(G.nmu, nb, sNewton, bw.cols, tl, G.count, fused, lst(1), cnt(1));
     }
     if (!f32 || bw.fallback) {
-      launch_formal_mu<double, false>(G.nmu, nb, dF, bw.cols, tl, G.count, 0);
-      if (bw.any_newton) launch_formal_mu<double, true>(G.nmu, nb, dN, bw.cols, tl, G.count, 0);
+      const int o = f32 ? 2 : 0;
+      launch_formal_mu<double, false>(G.nmu, nb, dF, bw.cols, tl, G.count, 0, lst(o), cnt(o));
+      if (bw.any_newton)
+        launch_formal_mu<double, true>(G.nmu, nb, dN, bw.cols, tl, G.count, 0, lst(o + 1), cnt(o + 1));
     }
   }
   if (ev) chk(hipEventRecord(ev[6], s));  // end of the F-mode launches on s

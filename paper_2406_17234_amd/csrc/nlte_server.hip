@@ -120,6 +120,9 @@ struct nlte_server {
   DevBuf<ColState> d_states;
   DevBuf<const double*> d_n0;
   DevBuf<int> d_done;
+  DevBuf<int> d_gidx;            // per-step mode lists of the formal-solution launches
+  DevBuf<Tile> d_mlist;
+  DevBuf<int> d_mcount;
   ColState* h_states = nullptr;  // pinned
   size_t h_states_cap = 0;
   BatchWork bw;
@@ -178,6 +181,15 @@ hipError_t nlte_server::rebuild() {
     if (hc[c].prec == NLTE_FP64) bw.any64 = 1; else bw.any32 = 1;
   }
   bw.fallback = opts.fp64_fallback > 0 && bw.any32;
+  std::vector<int> gidx;
+  set_mode_groups(bw, tiles, n, gidx);
+  if ((e = d_gidx.fit(n)) != hipSuccess) return e;
+  if ((e = d_mlist.fit(4 * std::max<size_t>(1, tiles.size()))) != hipSuccess) return e;
+  if ((e = d_mcount.fit(4 * kMaxGroups)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(d_gidx.p, gidx.data(), n * sizeof(int), hipMemcpyHostToDevice, stream)) != hipSuccess) return e;
+  bw.gidx = d_gidx.p;
+  bw.mlist = d_mlist.p;
+  bw.mcount = d_mcount.p;
   return hipSuccess;
 }
 

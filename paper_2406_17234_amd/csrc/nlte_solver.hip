@@ -1105,8 +1105,14 @@ struct Batch {
   ColState* states = nullptr;
   int* done = nullptr;
   int* done_host = nullptr;     // pinned
+  int* gidx = nullptr;          // per-step mode lists (BatchWork::gidx, mlist, mcount)
+  Tile* mlist = nullptr;
+  int* mcount = nullptr;
   int ncol = 0, ntiles = 0, maxL = 0, any64 = 0, any32 = 0;
   ~Batch() {
+    if (gidx) hipFree(gidx);
+    if (mlist) hipFree(mlist);
+    if (mcount) hipFree(mcount);
     if (cols) hipFree(cols);
     if (tiles) hipFree(tiles);
     if (rate) hipFree(rate);
@@ -1177,6 +1183,17 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
   if (!set_groups(bw, groups)) return set_err(NLTE_E_INVALID, "too many tile groups");
   for (int c = 0; c < ncol; ++c) bw.maxnz = std::max(bw.maxnz, hc[c].nz);
   bw.fallback = o.fp64_fallback > 0 && b.any32;
+  // per-step mode lists: each formal-solution launch starts with the waves
+  // of the columns it evaluates
+  std::vector<int> gidx;
+  set_mode_groups(bw, tiles, ncol, gidx);
+  HIP_TRY(hipMalloc(&b.gidx, ncol * sizeof(int)));
+  HIP_TRY(hipMalloc(&b.mlist, 4 * std::max<size_t>(1, tiles.size()) * sizeof(Tile)));
+  HIP_TRY(hipMalloc(&b.mcount, 4 * kMaxGroups * sizeof(int)));
+  HIP_TRY(hipMemcpyAsync(b.gidx, gidx.data(), ncol * sizeof(int), hipMemcpyHostToDevice, s));
+  bw.gidx = b.gidx;
+  bw.mlist = b.mlist;
+  bw.mcount = b.mcount;
 
   HIP_TRY(hipMalloc(&b.nout, ncol * sizeof(double*)));
   HIP_TRY(hipMalloc(&b.done, sizeof(int)));
@@ -1341,6 +1358,8 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
       bw.nrate0 = nrate0_l;
       bw.npb = (int)prec_w.size();
       set_groups(bw, groups);  // a subset of the groups checked above
+      set_mode_groups(bw, tiles, ncol, gidx);
+      HIP_TRY(hipMemcpyAsync(b.gidx, gidx.data(), ncol * sizeof(int), hipMemcpyHostToDevice, s));
       bw.maxnz = 0;
       for (int c : live) bw.maxnz = std::max(bw.maxnz, hc[c].nz);
       bw.act = b.act;
