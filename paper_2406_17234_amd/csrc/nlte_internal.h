@@ -262,6 +262,32 @@ struct Tile {
   int chunk;
 };
 
+// The tile of wave `wave` of this block in a formal-solution launch over a
+// group of ntiles tiles: from the launch's per-step list when mcount is set
+// (its first *mcount entries, dealt over the XCDs as a full grid would be),
+// else the group's own list.  The chunks of a column are consecutive either
+// way, so they run on one XCD and share its L2.  False: no tile.
+__device__ __forceinline__ bool pick_tile(const Tile* __restrict__ tiles, int ntiles,
+                                          const Tile* __restrict__ mlist,
+                                          const int* __restrict__ mcount, int wave, Tile& t) {
+  const int wpb = blockDim.x >> 6;
+  int tid;
+  if (mcount) {
+    const int n = __builtin_amdgcn_readfirstlane(ldc(mcount));
+    const int blk = xcd_live_item(blockIdx.x, (n + wpb - 1) / wpb);
+    if (blk < 0) return false;
+    tid = blk * wpb + wave;
+    if (tid >= n) return false;
+    tiles = mlist;
+  } else {
+    tid = xcd_item(blockIdx.x, gridDim.x) * wpb + wave;
+    if (tid >= ntiles) return false;
+  }
+  t.col = __builtin_amdgcn_readfirstlane(tiles[tid].col);
+  t.chunk = __builtin_amdgcn_readfirstlane(tiles[tid].chunk);
+  return true;
+}
+
 
 // Frequency sums over a transition's window (rate integrals, preconditioner
 // pair sums) run in segments of at most this many frequencies, each summed by
@@ -309,7 +335,7 @@ struct BatchWork {
                                   // are created or used)
   // Per-step mode lists (optional; NULL: every formal-solution launch walks
   // its group's whole tile list and waves of other modes return).  At the
-  // start of each residual call the tiles of the sequential static groups are
+  // start of each residual call the tiles of the sequential groups are
   // sorted by the launch that will evaluate them (F or Newton mode, in the
   // column's current precision), so that each launch starts with the waves
   // that have work.  gidx [ncol]: each column's group if that group uses the
@@ -328,7 +354,7 @@ inline void set_mode_groups(const BatchWork& bw, const std::vector<Tile>& tiles,
   gidx.assign(ncol, -1);
   for (int g = 0; g < bw.ngroup; ++g) {
     const TileGroup& G = bw.groups[g];
-    if (G.scan || G.vel) continue;
+    if (G.scan) continue;
     for (int t = G.first; t < G.first + G.count; ++t) gidx[tiles[t].col] = g;
   }
 }
@@ -345,10 +371,12 @@ inline void set_mode_groups(const BatchWork& bw, const std::vector<Tile>& tiles,
 hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev = nullptr);
 // Velocity-field columns (nlte_velocity.hip): the formal-solution launch of
 // one tile group in the FP32 form or FP64 and in F or Newton mode (each wave
-// skips the columns evaluated in the other), and the pair sums over
+// skips the columns evaluated in the other; mlist/mcount: this step's list of
+// the launch, as for k_formal), and the pair sums over
 // the preconditioner items of a batch (other columns' items return at once).
 void launch_formal_vel(bool fp32, bool newton, int nmu, int wpb, hipStream_t s, const ColDev* cols,
-                       const Tile* tiles, int ntiles);
+                       const Tile* tiles, int ntiles, const Tile* mlist = nullptr,
+                       const int* mcount = nullptr);
 void launch_pairsum_vel(const ColDev* cols, const int4* work, int nwork, hipStream_t s);
 // Tangent-linear products (nlte_tangent.hip) of the columns whose state has
 // tan_pending set: J v into F.  launch_residual runs it when bw.any_tangent.

@@ -769,23 +769,9 @@ __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
   // the chunks of a column are consecutive tiles: keeping them on one XCD
   // lets them share the column's level coefficients and the table lines
   // their rows have in common in that XCD's L2
-  int tid;
-  if (mcount) {
-    // this step's list of the launch (the grid covers the whole group; the
-    // live blocks are dealt over the XCDs as xcd_item deals a full grid)
-    const int n = uni(ldc(mcount));
-    const int wpb = blockDim.x >> 6;
-    const int blk = xcd_live_item(blockIdx.x, (n + wpb - 1) / wpb);
-    if (blk < 0) return;
-    tid = blk * wpb + wave;
-    if (tid >= n) return;
-    tiles = mlist;
-  } else {
-    tid = xcd_item(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
-    if (tid >= ntiles) return;
-  }
-  const int col = uni(tiles[tid].col);
-  const int chunk = uni(tiles[tid].chunk);
+  Tile t;
+  if (!pick_tile(tiles, ntiles, mlist, mcount, wave, t)) return;
+  const int col = t.col, chunk = t.chunk;
   const ColDev& C = cols[col];
   const int mode = uni(C.st->mode);
   if (mode != (PM ? kModeNewton : kModeF)) return;
@@ -1343,14 +1329,26 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     // FP64 launches: on s / sNewton for FP64 groups, on sF64 / sN64 for the
     // fallback columns of FP32-form groups
     const hipStream_t dF = f32 ? sF64 : s, dN = f32 ? sN64 : sNewton;
+    // this step's lists (sequential groups): [0] F, [1] Newton in the group's
+    // precision, [2] F, [3] Newton in FP64 for an FP32-form group's fallback
+    // columns
+    const bool gl = mlists && !G.scan;
+    auto lst = [&](int li) -> const Tile* {
+      return gl ? bw.mlist + (size_t)li * bw.ntiles + G.first : nullptr;
+    };
+    auto cnt = [&](int li) -> const int* { return gl ? bw.mcount + 4 * g + li : nullptr; };
+    const int o64 = f32 ? 2 : 0;
     if (G.vel) {  // nlte_velocity.hip; streams as for the other groups
       if (f32) {
-        launch_formal_vel(true, false, G.nmu, nb, s, bw.cols, tl, G.count);
-        if (bw.any_newton) launch_formal_vel(true, true, G.nmu, nb, sNewton, bw.cols, tl, G.count);
+        launch_formal_vel(true, false, G.nmu, nb, s, bw.cols, tl, G.count, lst(0), cnt(0));
+        if (bw.any_newton)
+          launch_formal_vel(true, true, G.nmu, nb, sNewton, bw.cols, tl, G.count, lst(1), cnt(1));
       }
       if (!f32 || bw.fallback) {
-        launch_formal_vel(false, false, G.nmu, nb, dF, bw.cols, tl, G.count);
-        if (bw.any_newton) launch_formal_vel(false, true, G.nmu, nb, dN, bw.cols, tl, G.count);
+        launch_formal_vel(false, false, G.nmu, nb, dF, bw.cols, tl, G.count, lst(o64), cnt(o64));
+        if (bw.any_newton)
+          launch_formal_vel(false, true, G.nmu, nb, dN, bw.cols, tl, G.count, lst(o64 + 1),
+                            cnt(o64 + 1));
       }
       continue;
     }
@@ -1365,22 +1363,16 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
       }
       continue;
     }
-    // this step's lists: [0] F, [1] Newton in the group's precision, [2] F,
-    // [3] Newton in FP64 for an FP32-form group's fallback columns
-    auto lst = [&](int li) -> const Tile* {
-      return mlists ? bw.mlist + (size_t)li * bw.ntiles + G.first : nullptr;
-    };
-    auto cnt = [&](int li) -> const int* { return mlists ? bw.mcount + 4 * g + li : nullptr; };
     if (f32) {
       launch_formal_mu<float, false>(G.nmu, nb, s, bw.cols, tl, G.count, fused, lst(0), cnt(0));
       if (bw.any_newton)
         launch_formal_mu<float, true>(G.nmu, nb, sNewton, bw.cols, tl, G.count, fused, lst(1), cnt(1));
     }
     if (!f32 || bw.fallback) {
-      const int o = f32 ? 2 : 0;
-      launch_formal_mu<double, false>(G.nmu, nb, dF, bw.cols, tl, G.count, 0, lst(o), cnt(o));
+      launch_formal_mu<double, false>(G.nmu, nb, dF, bw.cols, tl, G.count, 0, lst(o64), cnt(o64));
       if (bw.any_newton)
-        launch_formal_mu<double, true>(G.nmu, nb, dN, bw.cols, tl, G.count, 0, lst(o + 1), cnt(o + 1));
+        launch_formal_mu<double, true>(G.nmu, nb, dN, bw.cols, tl, G.count, 0, lst(o64 + 1),
+                                       cnt(o64 + 1));
     }
   }
   if (ev) chk(hipEventRecord(ev[6], s));  // end of the F-mode launches on s

@@ -285,13 +285,14 @@ __device__ __forceinline__ void formal_tile_vel(const ColDev& C, int chunk, int 
 
 template <typename R, bool PM, int NMU>
 __global__ __launch_bounds__(256) void k_formal_vel(const ColDev* __restrict__ cols,
-                                                    const Tile* __restrict__ tiles, int ntiles) {
+                                                    const Tile* __restrict__ tiles, int ntiles,
+                                                    const Tile* __restrict__ mlist,
+                                                    const int* __restrict__ mcount) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int tid = xcd_item(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
-  if (tid >= ntiles) return;
-  const int col = uni(tiles[tid].col);
-  const int chunk = uni(tiles[tid].chunk);
+  Tile t;
+  if (!pick_tile(tiles, ntiles, mlist, mcount, wave, t)) return;
+  const int col = t.col, chunk = t.chunk;
   const ColDev& C = cols[col];
   if (uni(C.st->mode) != (PM ? kModeNewton : kModeF)) return;
   if (uni(C.st->cur_prec) != (sizeof(R) == sizeof(float) ? NLTE_FP32_FORM : NLTE_FP64)) return;
@@ -301,13 +302,14 @@ __global__ __launch_bounds__(256) void k_formal_vel(const ColDev* __restrict__ c
 
 template <typename R, bool PM>
 static void launch_formal_vel_mode(int nmu, int wpb, hipStream_t s, const ColDev* cols,
-                                   const Tile* tiles, int ntiles) {
+                                   const Tile* tiles, int ntiles, const Tile* mlist,
+                                   const int* mcount) {
   const int blocks = (ntiles + wpb - 1) / wpb;
   switch (nmu) {
 #define NLTE_VEL_CASE(M)                                                                      \
   case M:                                                                                     \
     k_formal_vel<R, PM, M><<<blocks, 64 * wpb, (size_t)wpb * VelStage<PM, M>::doubles * 8, s>>>( \
-        cols, tiles, ntiles);                                                                 \
+        cols, tiles, ntiles, mlist, mcount);                                                  \
     break;
     NLTE_VEL_CASE(1) NLTE_VEL_CASE(2) NLTE_VEL_CASE(3) NLTE_VEL_CASE(4)
     NLTE_VEL_CASE(5) NLTE_VEL_CASE(6) NLTE_VEL_CASE(7) NLTE_VEL_CASE(8)
@@ -317,17 +319,17 @@ static void launch_formal_vel_mode(int nmu, int wpb, hipStream_t s, const ColDev
 }
 
 void launch_formal_vel(bool fp32, bool newton, int nmu, int wpb, hipStream_t s, const ColDev* cols,
-                       const Tile* tiles, int ntiles) {
+                       const Tile* tiles, int ntiles, const Tile* mlist, const int* mcount) {
   if (fp32) {
     if (newton)
-      launch_formal_vel_mode<float, true>(nmu, wpb, s, cols, tiles, ntiles);
+      launch_formal_vel_mode<float, true>(nmu, wpb, s, cols, tiles, ntiles, mlist, mcount);
     else
-      launch_formal_vel_mode<float, false>(nmu, wpb, s, cols, tiles, ntiles);
+      launch_formal_vel_mode<float, false>(nmu, wpb, s, cols, tiles, ntiles, mlist, mcount);
   } else {
     if (newton)
-      launch_formal_vel_mode<double, true>(nmu, wpb, s, cols, tiles, ntiles);
+      launch_formal_vel_mode<double, true>(nmu, wpb, s, cols, tiles, ntiles, mlist, mcount);
     else
-      launch_formal_vel_mode<double, false>(nmu, wpb, s, cols, tiles, ntiles);
+      launch_formal_vel_mode<double, false>(nmu, wpb, s, cols, tiles, ntiles, mlist, mcount);
   }
 }
 
