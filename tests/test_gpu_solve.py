@@ -101,6 +101,29 @@ def test_batch_equals_single(ctx):
         assert np.array_equal(to_np(n1), to_np(o))
 
 
+def test_batch_with_every_launch_list_equals_alone(ctx):
+    """Each step sorts the columns' chunks into the lists of the launches
+    that evaluate them (F or Newton mode, in the FP32 form or in FP64 after
+    a fallback).  A batch whose FP32-form columns fall back to FP64 after two
+    Newton iterations, beside FP64 columns, keeps all four lists busy at once
+    and in changing mixes; every column must still get the populations and
+    statistics it gets alone, bit for bit."""
+    from paper_2406_17234_amd import nlte
+    probs = ([S.batch6_column(i) for i in range(6)] +
+             [S.stream_request(j, nz_max=96, nnu_max=500) for j in (0, 1, 5)] +
+             [CASES["slab3"](), CASES["chromo6_small"]()])
+    precs = [nlte.FP32_FORM] * 9 + [nlte.FP64] * 2
+    cols = [nlte.Column(ctx, p, precision=pr) for p, pr in zip(probs, precs)]
+    opts = dict(ftol=1e-8, rtol=1e-3, maxiter=30, max_krylov_total=300, fp64_fallback=2)
+    print("[case] mixed batch, fallback after 2 iterations", flush=True)
+    outs, stats, rc = nlte.solve_batch(ctx, cols, **opts)
+    assert sum(s["precision"] == nlte.FP64 for s in stats[:9]) >= 3, stats
+    for c, o, s in zip(cols, outs, stats):
+        n1, _, s1, _ = c.solve(**opts)
+        assert np.array_equal(to_np(n1), to_np(o))
+        assert s1 == s
+
+
 def test_fp32_form_within_1e4(ctx):
     from paper_2406_17234_amd import nlte
     prob, tb, ref = oracle_root("chromo6", CASES["chromo6"])
