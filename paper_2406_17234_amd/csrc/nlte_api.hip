@@ -52,7 +52,7 @@ struct nlte_column {
   BatchWork bw;               // single-column work lists (col index 0)
   int restart_cap = 0;
   std::vector<double> Blu;    // host copy of line B_lu (profile-averaged J)
-  double* stage_buf = nullptr;
+  bool pooled = false;        // arena (with d at its end) lent by a server's pool: not freed here
 };
 
 namespace nlte {
@@ -923,10 +923,31 @@ static nlte_status plan_column(const nlte_atmos_desc* A, const nlte_atom_desc* M
   return NLTE_OK;
 }
 
+// Bytes of a pooled arena for a column of `plan` arena bytes: the arena,
+// then its device descriptor.
+size_t nlte::pooled_arena_bytes(size_t plan) {
+  return ((plan + 255) / 256) * 256 + ((sizeof(ColDev) + 255) / 256) * 256;
+}
+
+static nlte_status column_create_impl(nlte_ctx* ctx, const nlte_atmos_desc* A,
+                                      const nlte_atom_desc* M, const nlte_grid_desc* G,
+                                      const double* C_up, int32_t prec_arg, hipStream_t stream,
+                                      void* pool_arena, size_t pool_cap, nlte_column** out);
+
 extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* A,
                                           const nlte_atom_desc* M, const nlte_grid_desc* G,
                                           const double* C_up, int32_t prec_arg,
                                           hipStream_t stream, nlte_column** out) {
+  return column_create_impl(ctx, A, M, G, C_up, prec_arg, stream, nullptr, 0, out);
+}
+
+// pool_arena (NULL: the column allocates its own) holds pool_cap bytes, at
+// least pooled_arena_bytes(plan) of them; the column lays itself out at its
+// start, puts its device descriptor after it, and never frees it.
+static nlte_status column_create_impl(nlte_ctx* ctx, const nlte_atmos_desc* A,
+                                      const nlte_atom_desc* M, const nlte_grid_desc* G,
+                                      const double* C_up, int32_t prec_arg, hipStream_t stream,
+                                      void* pool_arena, size_t pool_cap, nlte_column** out) {
   if (!ctx || !out) return set_err(NLTE_E_INVALID, "NULL ctx/out");
   // an error left pending by an unrelated earlier call stays pending for its
   // owner (peeked, not cleared); the setup launches are judged by whether
@@ -957,11 +978,27 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   col->ctx = ctx;
   col->device = ctx->device;
   col->arena_bytes = P.bytes;
-  hipError_t he = hipMalloc(&col->arena, col->arena_bytes);
-  if (he != hipSuccess) {
-    delete col;
-    return set_err(NLTE_E_NOMEM, "hipMalloc(%zu) failed: %s", P.bytes, hipGetErrorString(he));
+  if (pool_arena) {
+    if (pool_cap < pooled_arena_bytes(P.bytes)) {
+      delete col;
+      return set_err(NLTE_E_INVALID, "pooled arena of %zu bytes for a column of %zu", pool_cap,
+                     P.bytes);
+    }
+    col->pooled = true;
+    col->arena = pool_arena;
+  } else {
+    hipError_t he = hipMalloc(&col->arena, col->arena_bytes);
+    if (he != hipSuccess) {
+      delete col;
+      return set_err(NLTE_E_NOMEM, "hipMalloc(%zu) failed: %s", P.bytes, hipGetErrorString(he));
+    }
   }
+  // the arena goes back to a pool or to the device on every failure below
+  auto release = [col]() {
+    if (col->pooled) return;
+    if (col->d) (void)hipFree(col->d);
+    (void)hipFree(col->arena);
+  };
   SetupIn in{};
   TrDev* tr_d;
   int *wbase_d, *lbase_d, *stage_d, *bfptr_d;
@@ -1029,7 +1066,7 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
 #undef UP
   if (e == hipSuccess) e = hipMemsetAsync(C.st, 0, sizeof(ColState), stream);
   if (e != hipSuccess) {
-    (void)hipFree(col->arena);
+    release();
     delete col;
     return set_err(NLTE_E_DEVICE, "upload failed: %s", hipGetErrorString(e));
   }
@@ -1071,12 +1108,16 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
   e = hipPeekAtLastError();
   if (e == pending) e = hipSuccess;  // nothing new from the setup launches
   else (void)hipGetLastError();     // the setup's own launch error, reported below
-  if (e == hipSuccess) e = hipMalloc(&col->d, sizeof(ColDev));
+  if (e == hipSuccess) {
+    if (col->pooled)
+      col->d = reinterpret_cast<ColDev*>(static_cast<char*>(col->arena) + ((P.bytes + 255) / 256) * 256);
+    else
+      e = hipMalloc(&col->d, sizeof(ColDev));
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(col->d, &C, sizeof(ColDev), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
-    if (col->d) (void)hipFree(col->d);
-    (void)hipFree(col->arena);
+    release();
     delete col;
     return set_err(NLTE_E_DEVICE, "column setup failed: %s", hipGetErrorString(e));
   }
@@ -1103,8 +1144,10 @@ extern "C" nlte_status nlte_column_create(nlte_ctx* ctx, const nlte_atmos_desc* 
 extern "C" void nlte_column_destroy(nlte_column* col) {
   if (!col) return;
   (void)hipSetDevice(col->device);
-  if (col->d) (void)hipFree(col->d);
-  if (col->arena) (void)hipFree(col->arena);
+  if (!col->pooled) {
+    if (col->d) (void)hipFree(col->d);
+    if (col->arena) (void)hipFree(col->arena);
+  }
   delete col;
 }
 
@@ -1175,8 +1218,9 @@ nlte_status problem_copy(const nlte_atmos_desc* A, const nlte_atom_desc* M, cons
 size_t problem_bytes(const HostProblem* H) { return H->bytes; }
 
 nlte_status problem_create_column(nlte_ctx* ctx, const HostProblem* H, hipStream_t s,
-                                  nlte_column** out) {
-  return nlte_column_create(ctx, &H->A, &H->M, &H->G, H->C_up.data(), H->precision, s, out);
+                                  void* pool_arena, size_t pool_cap, nlte_column** out) {
+  return column_create_impl(ctx, &H->A, &H->M, &H->G, H->C_up.data(), H->precision, s,
+                            pool_arena, pool_cap, out);
 }
 
 void problem_free(HostProblem* H) { delete H; }

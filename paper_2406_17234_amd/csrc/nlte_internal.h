@@ -406,6 +406,10 @@ inline bool set_groups(BatchWork& bw, const std::vector<TileGroup>& groups) {
   return true;
 }
 
+// Bytes of a server-pooled column arena for a column whose plan takes
+// `plan` bytes (the arena, then the column's device descriptor).
+size_t pooled_arena_bytes(size_t plan);
+
 int build_work_lists(const ColDev* hc, int ncol, std::vector<Tile>& tiles,
                      std::vector<TileGroup>& groups, std::vector<int4>& rate,
                      std::vector<int2>& pblock, int& maxL, const int* sel = nullptr,

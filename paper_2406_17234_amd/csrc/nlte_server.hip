@@ -17,6 +17,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -36,7 +37,7 @@ nlte_status problem_copy(const nlte_atmos_desc* A, const nlte_atom_desc* M, cons
                          const double* C_up, int32_t precision, HostProblem** out);
 size_t problem_bytes(const HostProblem* H);
 nlte_status problem_create_column(nlte_ctx* ctx, const HostProblem* H, hipStream_t s,
-                                  nlte_column** out);
+                                  void* pool_arena, size_t pool_cap, nlte_column** out);
 void problem_free(HostProblem* H);
 }  // namespace nlte
 
@@ -57,6 +58,8 @@ struct Request {
   nlte_server_result res{};
   HostProblem* prob = nullptr;  // problem requests: the description, until destruction
   double* n_out = nullptr;      // problem requests: where the populations go at retirement
+  void* arena = nullptr;        // problem requests: the pooled arena lent to the column
+  size_t arena_cap = 0;
   ~Request() {
     if (prob) problem_free(prob);
   }
@@ -125,13 +128,74 @@ struct nlte_server {
   DevBuf<int> d_mcount;
   ColState* h_states = nullptr;  // pinned
   size_t h_states_cap = 0;
+  // Column arenas of problem requests: a retired column's arena returns to
+  // this pool and the next column that fits it (within 1/16 of its need)
+  // reuses it, so the serving loop does not call hipMalloc and hipFree (the
+  // latter waits for the device) per request.  The arenas lent to columns in
+  // flight plus the pooled ones stay within the budget: pooled arenas are
+  // freed, largest first, before a new one would pass it.
+  std::multimap<size_t, void*> pool;
+  size_t pool_bytes = 0, lent_bytes = 0;
   BatchWork bw;
   std::thread th;
 
   hipError_t rebuild();
   hipError_t admit(std::vector<Request*>& adm);
   void run();
+  nlte_status create_pooled(Request* r, nlte_column** out);
+  void return_arena(Request* r);
+  void release_pool();
 };
+
+// The column of problem request r in an arena from the pool, or in a new one.
+nlte_status nlte_server::create_pooled(Request* r, nlte_column** out) {
+  const size_t need = pooled_arena_bytes(r->bytes);
+  void* a = nullptr;
+  size_t cap = 0;
+  auto it = pool.lower_bound(need);
+  if (it != pool.end() && it->first <= need + need / 16) {
+    cap = it->first;
+    a = it->second;
+    pool_bytes -= cap;
+    pool.erase(it);
+  } else {
+    while (!pool.empty() && lent_bytes + pool_bytes + need > budget) {
+      auto big = std::prev(pool.end());
+      (void)hipFree(big->second);
+      pool_bytes -= big->first;
+      pool.erase(big);
+    }
+    const hipError_t he = hipMalloc(&a, need);
+    if (he != hipSuccess) return set_err(NLTE_E_NOMEM, "hipMalloc(%zu) failed: %s", need, hipGetErrorString(he));
+    cap = need;
+  }
+  const nlte_status cs = problem_create_column(ctx, r->prob, stream, a, cap, out);
+  if (cs != NLTE_OK) {
+    pool.emplace(cap, a);
+    pool_bytes += cap;
+    return cs;
+  }
+  r->arena = a;
+  r->arena_cap = cap;
+  lent_bytes += cap;
+  return NLTE_OK;
+}
+
+// After the column of r has been destroyed (nothing on the device reads it).
+void nlte_server::return_arena(Request* r) {
+  if (!r->arena) return;
+  pool.emplace(r->arena_cap, r->arena);
+  pool_bytes += r->arena_cap;
+  lent_bytes -= r->arena_cap;
+  r->arena = nullptr;
+  r->arena_cap = 0;
+}
+
+void nlte_server::release_pool() {
+  for (auto& kv : pool) (void)hipFree(kv.second);
+  pool.clear();
+  pool_bytes = 0;
+}
 
 hipError_t nlte_server::rebuild() {
   const int n = (int)active.size();
@@ -251,7 +315,7 @@ void nlte_server::run() {
       for (Request* r : adm) {
         if (r->prob && !r->col) {
           nlte_column* c = nullptr;
-          const nlte_status cs = problem_create_column(ctx, r->prob, stream, &c);
+          const nlte_status cs = create_pooled(r, &c);
           if (cs != NLTE_OK) {
             std::lock_guard<std::mutex> lk(mu);
             r->res.stats = nlte_solve_stats{};
@@ -306,6 +370,7 @@ void nlte_server::run() {
       if (r->prob && r->col && state_done(h_states[c])) {
         nlte_column_destroy(r->col);
         r->col = nullptr;
+        return_arena(r);
       }
     }
     const double t = now_ms(t0);
@@ -500,9 +565,12 @@ extern "C" void nlte_server_destroy(nlte_server* S) {
   (void)hipSetDevice(S->device);
   hipStreamSynchronize(S->stream);
   for (auto& kv : S->reqs) {
-    if (kv.second->prob && kv.second->col) nlte_column_destroy(kv.second->col);
-    delete kv.second;
+    Request* r = kv.second;
+    if (r->prob && r->col) nlte_column_destroy(r->col);
+    if (r->arena) (void)hipFree(r->arena);
+    delete r;
   }
+  S->release_pool();
   if (S->h_states) hipHostFree(S->h_states);
   hipStreamDestroy(S->stream);
   hipStreamDestroy(S->copy_stream);
