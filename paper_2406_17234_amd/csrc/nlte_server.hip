@@ -102,6 +102,7 @@ struct nlte_server {
   nlte_solve_opts opts{};
   hipStream_t stream = nullptr;
   hipStream_t copy_stream = nullptr;
+  hipStream_t setup_stream = nullptr;  // column setup of admitted requests, beside the steps
   std::chrono::steady_clock::time_point t0;
 
   std::mutex mu;
@@ -169,7 +170,9 @@ nlte_status nlte_server::create_pooled(Request* r, nlte_column** out) {
     if (he != hipSuccess) return set_err(NLTE_E_NOMEM, "hipMalloc(%zu) failed: %s", need, hipGetErrorString(he));
     cap = need;
   }
-  const nlte_status cs = problem_create_column(ctx, r->prob, stream, a, cap, out);
+  // set up on its own stream (the column's creation waits for it), so that a
+  // block of steps may run meanwhile
+  const nlte_status cs = problem_create_column(ctx, r->prob, setup_stream, a, cap, out);
   if (cs != NLTE_OK) {
     pool.emplace(cap, a);
     pool_bytes += cap;
@@ -284,19 +287,41 @@ void nlte_server::run() {
   if (e == hipSuccess) e = d_done.fit(1);
   if (e == hipSuccess) e = hipMemsetAsync(d_done.p, 0, sizeof(int), stream);
   bool dirty = false;
+  // Requests admitted while the previous block of steps ran: their columns
+  // are made (on setup_stream) and they join the lists before the next block.
+  std::vector<Request*> pending;
   while (e == hipSuccess) {
+    if (!pending.empty() || dirty) {
+      active.insert(active.end(), pending.begin(), pending.end());
+      if ((e = rebuild()) != hipSuccess) break;
+      if ((e = admit(pending)) != hipSuccess) break;
+      pending.clear();
+      dirty = false;
+    }
+    // the next block of steps; the host admits and sets up new requests
+    // while it runs
+    const int n = (int)active.size();
+    const double tb = now_ms(t0);
+    for (int r = 0; r < kSteps && n > 0 && e == hipSuccess; ++r) {
+      e = launch_residual(bw, stream);
+      if (e == hipSuccess) e = solver_step(bw.cols, nullptr, n, d_done.p, stream);
+    }
+    if (n > 0 && e == hipSuccess) e = solver_gather(bw.cols, n, d_states.p, stream);
+    if (n > 0 && e == hipSuccess)
+      e = hipMemcpyAsync(h_states, d_states.p, n * sizeof(ColState), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) break;
     std::vector<Request*> adm;
     {
       std::unique_lock<std::mutex> lk(mu);
-      if (active.empty() && queue.empty()) {
+      if (n == 0 && queue.empty()) {
         cv_idle.notify_all();
         cv.wait(lk, [&] { return stop || !queue.empty(); });
       }
       if (stop) break;
       size_t bytes = (size_t)info.active_bytes;
-      while (!queue.empty() && (int)(active.size() + adm.size()) < max_active) {
+      while (!queue.empty() && (int)(active.size() + pending.size() + adm.size()) < max_active) {
         Request* r = queue.front();
-        const bool empty = active.empty() && adm.empty();
+        const bool empty = active.empty() && pending.empty() && adm.empty();
         if (!empty && bytes + r->bytes > budget) break;
         queue.pop_front();
         r->state = kActive;
@@ -308,51 +333,30 @@ void nlte_server::run() {
       info.peak_active_bytes = std::max(info.peak_active_bytes, info.active_bytes);
       info.queued = (int32_t)queue.size();
     }
-    if (!adm.empty()) {
-      // problem requests: their columns are created now, within the budget
-      std::vector<Request*> ok;
-      ok.reserve(adm.size());
-      for (Request* r : adm) {
-        if (r->prob && !r->col) {
-          nlte_column* c = nullptr;
-          const nlte_status cs = create_pooled(r, &c);
-          if (cs != NLTE_OK) {
-            std::lock_guard<std::mutex> lk(mu);
-            r->res.stats = nlte_solve_stats{};
-            r->res.stats.status = cs;
-            r->res.t_done_ms = now_ms(t0);
-            r->state = kDone;
-            info.active_bytes -= (int64_t)r->bytes;
-            info.completed += 1;
-            cv_idle.notify_all();
-            continue;
-          }
-          r->col = c;
+    // problem requests: their columns are made now, within the budget
+    for (Request* r : adm) {
+      if (r->prob && !r->col) {
+        nlte_column* c = nullptr;
+        const nlte_status cs = create_pooled(r, &c);
+        if (cs != NLTE_OK) {
+          std::lock_guard<std::mutex> lk(mu);
+          r->res.stats = nlte_solve_stats{};
+          r->res.stats.status = cs;
+          r->res.t_done_ms = now_ms(t0);
+          r->state = kDone;
+          info.active_bytes -= (int64_t)r->bytes;
+          info.completed += 1;
+          cv_idle.notify_all();
+          continue;
         }
-        ok.push_back(r);
+        r->col = c;
       }
-      adm.swap(ok);
-      active.insert(active.end(), adm.begin(), adm.end());
-      dirty = !adm.empty() || dirty;
+      pending.push_back(r);
     }
-    if (dirty) {
-      if ((e = rebuild()) != hipSuccess) break;
-      if ((e = admit(adm)) != hipSuccess) break;
-      dirty = false;
-    }
-    const int n = (int)active.size();
-    const double tb = now_ms(t0);
-    for (int r = 0; r < kSteps && e == hipSuccess; ++r) {
-      e = launch_residual(bw, stream);
-      if (e == hipSuccess) e = solver_step(bw.cols, nullptr, n, d_done.p, stream);
-    }
-    if (e == hipSuccess) e = solver_gather(bw.cols, n, d_states.p, stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(h_states, d_states.p, n * sizeof(ColState), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) break;
+    if (n == 0) continue;
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) break;
     // problem requests that finished: populations to the caller's buffer,
-    // then the column (and its device memory) goes
+    // then the column goes and its arena returns to the pool
     bool freed = false;
     for (int c = 0; c < n && e == hipSuccess; ++c) {
       Request* r = active[c];
@@ -436,8 +440,10 @@ extern "C" nlte_status nlte_server_create(nlte_ctx* ctx, size_t hbm_budget, int3
   S->opts = o;
   S->t0 = std::chrono::steady_clock::now();
   if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+      hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&S->setup_stream, hipStreamNonBlocking) != hipSuccess) {
     if (S->stream) hipStreamDestroy(S->stream);
+    if (S->copy_stream) hipStreamDestroy(S->copy_stream);
     delete S;
     return set_err(NLTE_E_DEVICE, "stream creation failed");
   }
@@ -574,5 +580,6 @@ extern "C" void nlte_server_destroy(nlte_server* S) {
   if (S->h_states) hipHostFree(S->h_states);
   hipStreamDestroy(S->stream);
   hipStreamDestroy(S->copy_stream);
+  hipStreamDestroy(S->setup_stream);
   delete S;
 }
