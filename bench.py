@@ -532,7 +532,7 @@ def main():
                          "capacity)")
     ap.add_argument("--serve-budget-gb", type=float, default=96.0)
     ap.add_argument("--serve-max-active", type=int, default=2048)
-    ap.add_argument("--launch", default="eager", choices=["eager", "graph", "graph+tune"],
+    ap.add_argument("--launch", default="eager", choices=["eager", "tune", "graph", "graph+tune"],
                     help="step replay of the timed batch solves (HIP graphs, launch-shape tuner); "
                          "graph replay of the full 4096-column batch is not cleared for use "
                          "(a host-side crash in its second solve is not understood yet)")
@@ -605,7 +605,7 @@ def main():
     setup_s = time.perf_counter() - t0
     print(f"[bench] created {ncol} columns in {setup_s:.1f} s", file=sys.stderr, flush=True)
     dp_col = np.array([p.depth_points() for p in problems], dtype=np.float64)
-    launch = {"eager": 0, "graph": nlte.NLTE_SOLVE_GRAPH,
+    launch = {"eager": 0, "tune": nlte.NLTE_SOLVE_TUNE, "graph": nlte.NLTE_SOLVE_GRAPH,
               "graph+tune": nlte.NLTE_SOLVE_GRAPH | nlte.NLTE_SOLVE_TUNE}[args.launch]
     opts = nlte.default_opts(ftol=ftol, rtol=args.rtol, maxiter=50,
                              max_krylov_total=args.max_krylov_total,

@@ -1235,11 +1235,15 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
     HIP_TRY(hipEventCreate(&G.t1));
   }
   // waves per formal-solution workgroup: one (the four concurrent launches
-  // of a residual call share the device best), or tried 1, 2, 4 on blocks
-  // 1..3 (block 0 holds the first, preconditioned evaluations)
+  // of a residual call share the device best), or tried on blocks 1..6
+  // (block 0 holds the first, preconditioned evaluations) in the order 1,
+  // 2, 4, 4, 2, 1: the cost of a step falls as the batch's Newton phase
+  // settles, and a palindromic order gives each shape the same mean
+  // position, so a linear trend does not favour the shape tried last
   const int wpb_try[3] = {1, 2, 4};
+  const int tune_order[6] = {0, 1, 2, 2, 1, 0};
   double tune_ms[3] = {0.0, 0.0, 0.0};
-  int tune_next = tune ? 0 : 3;
+  int tune_next = tune ? 0 : 6;
   bw.formal_wpb = 1;
   std::vector<hipEvent_t> ev;
   if (prof) {
@@ -1266,9 +1270,9 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
     return hipSuccess;
   };
   while (step < max_steps) {
-    const bool timing = block >= 1 && tune_next < 3;
-    if (timing && bw.formal_wpb != wpb_try[tune_next]) {
-      bw.formal_wpb = wpb_try[tune_next];
+    const bool timing = block >= 1 && tune_next < 6;
+    if (timing && bw.formal_wpb != wpb_try[tune_order[tune_next]]) {
+      bw.formal_wpb = wpb_try[tune_order[tune_next]];
       G.drop();  // captured with another shape
     }
     if (timing) HIP_TRY(hipEventRecord(G.t0, s));
@@ -1302,8 +1306,8 @@ extern "C" nlte_status nlte_solve_batch(nlte_ctx* ctx, nlte_column* const* cols,
     if (timing) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, G.t0, G.t1));
-      tune_ms[tune_next] = ms / check_every;
-      if (++tune_next == 3) {
+      tune_ms[tune_order[tune_next]] += 0.5 * ms / check_every;
+      if (++tune_next == 6) {
         int best = 0;
         for (int i = 1; i < 3; ++i)
           if (tune_ms[i] < tune_ms[best]) best = i;
