@@ -395,8 +395,9 @@ void nlte_plan_destroy(nlte_plan *plan);
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of column solves.
  *
- * A server owns one host thread and one non-blocking HIP stream on the
- * context's device.  Submitted solves wait in a FIFO queue and are admitted
+ * A server owns one host thread and non-blocking HIP streams on the
+ * context's device (one for the steps, one for setting up admitted problem
+ * requests while the steps run).  Submitted solves wait in a FIFO queue and are admitted
  * while the device arenas of the columns in flight stay within hbm_budget
  * bytes and their number within max_active (a column larger than the budget
  * is admitted alone).  Admitted columns advance together, one residual
@@ -442,12 +443,15 @@ nlte_status nlte_server_submit(nlte_server *srv, nlte_column *col, const double 
  * here) and deep-copied, so the caller may free them at once.  The request
  * is admitted when the device bytes of its column (nlte_column_plan_bytes)
  * fit the budget next to the columns in flight; its column is then created
- * (device memory allocated, setup run: part of the request's latency) and
- * solved with the others, and when the solve finishes its populations are
- * copied to n_out_dev ([nz][nlev] device memory owned by the caller, valid
- * until the ticket is polled) and the column is destroyed.  If the column
- * cannot be created, the request finishes with that status.  Sect. 2.1 (the
- * problem), Algorithm 2 (the solve). */
+ * (setup run: part of the request's latency) in device memory from the
+ * server's pool of column arenas (a retired column's arena is reused by a
+ * later column within 1/16 of its size; the arenas lent and pooled stay
+ * within the budget, and the pool is freed with the server) and solved with
+ * the others, and when the solve finishes its populations are copied to
+ * n_out_dev ([nz][nlev] device memory owned by the caller, valid until the
+ * ticket is polled) and the column is destroyed, its arena returning to the
+ * pool.  If the column cannot be created, the request finishes with that
+ * status.  Sect. 2.1 (the problem), Algorithm 2 (the solve). */
 nlte_status nlte_server_submit_problem(nlte_server *srv, const nlte_atmos_desc *atmos,
                                        const nlte_atom_desc *atom, const nlte_grid_desc *grid,
                                        const double *C_up, int32_t precision, double *n_out_dev,
