@@ -192,15 +192,18 @@ __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0
     chi[i] = 0.0;
     et[i] = 0.0;
   }
-  // lines: chi += V c0, et += V c1
-  const int l0 = uni(C.ch_lptr[chunk]), l1 = uni(C.ch_lptr[chunk + 1]);
+  // lines: chi += V c0, et += V c1.  The chunk's transition lists and the
+  // transitions' windows are set up before any evaluation and read through
+  // the scalar cache (ldc): generic loads of them became vector loads whose
+  // waits drained every load and store the wave had in flight.
+  const int l0 = ldc(C.ch_lptr + chunk), l1 = ldc(C.ch_lptr + chunk + 1);
   for (int j = l0; j < l1; ++j) {
-    const int t = uni(C.ch_line[j]);
-    const TrDev& T = C.tr[t];
-    const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
+    const int t = ldc(C.ch_line + j);
+    const TrDev* T = C.tr + t;
+    const int wlo = ldc(&T->wlo), wl = ldc(&T->whi) - wlo;
     const int q = fc - wlo;
     const bool in = q >= 0 && q < wl;
-    const R* vrow = Vt + uni(T.voff) + (in ? q : 0);
+    const R* vrow = Vt + ldc(&T->voff) + (in ? q : 0);
     const double* ct = coef + ((size_t)t * nz + k0) * 2;
     R v[KG];
 #pragma unroll
@@ -223,12 +226,12 @@ __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0
     A1[i] = 0.0;
     A2[i] = 0.0;
   }
-  const int e0 = uni(C.ch_eptr[chunk]), e1 = uni(C.ch_eptr[chunk + 1]);
+  const int e0 = ldc(C.ch_eptr + chunk), e1 = ldc(C.ch_eptr + chunk + 1);
   for (int j = e0; j < e1; ++j) {
-    const int t = uni(C.ch_edge[j]);
-    const TrDev& T = C.tr[t];
-    const int wlo = uni(T.wlo), whi = uni(T.whi);
-    const double al = (fc >= wlo && fc < whi) ? (double)ldg(Vt + uni(T.voff) + (fc - wlo)) : 0.0;
+    const int t = ldc(C.ch_edge + j);
+    const TrDev* T = C.tr + t;
+    const int wlo = ldc(&T->wlo), whi = ldc(&T->whi);
+    const double al = (fc >= wlo && fc < whi) ? (double)ldg(Vt + ldc(&T->voff) + (fc - wlo)) : 0.0;
     const double* ct = coef + ((size_t)t * nz + k0) * 2;
 #pragma unroll
     for (int i = 0; i < KG; ++i) {
