@@ -35,6 +35,8 @@
 //               and the pair sums.
 // Columns with a velocity field run their own formal-solution and pair-sum
 // kernels (nlte_velocity.hip); the other launches are shared.
+#include <type_traits>
+
 #include "nlte_kernels.h"
 
 namespace nlte {
@@ -144,11 +146,22 @@ template <> struct FTab<float> {
 // noise in the finite-difference product (on MI355X an FP64 FMA issues at the
 // rate of a non-packed FP32 one, so this costs no extra issue slots).
 // KG (depths per wave) is a launch shape the plan tuner chooses among 4, 8, 16.
-template <typename R, int KG>
+// FLY (FP32 form only): B_nu(T) and e^{-h nu/kT} made here rather than read
+// from the tables (columns without a caller emissivity).  A compile-time
+// choice, taken once per wave by the callers: as a branch per depth, the
+// table loads of the other side made the compiler wait for every load and
+// store in flight before each exponential.
+template <typename R, int KG, bool FLY>
 __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0, int nz, int nnu,
                                               bool fin, int fc, const R* __restrict__ Vt,
                                               const double* __restrict__ coef, int ntr,
                                               R (&cx)[KG], R (&sx)[KG]);
+
+// Whether a column's opacity in precision R is made with FLY (see above).
+template <typename R>
+__device__ __forceinline__ bool opacity_fly(const ColDev& C) {
+  return sizeof(R) == sizeof(float) && !C.bg_eta;
+}
 
 // nsplit waves share a tile's depth groups (round-robin), so that a launch
 // over few tiles (one large column) still fills the chip; every depth group is
@@ -175,17 +188,24 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
   const R* __restrict__ Vt = FTab<R>::V(C);
   const double* __restrict__ coef = (const double*)C.coef;
   const int ntr = uni(C.ntr);
-  for (int k0 = part * KG; k0 < nz; k0 += nsplit * KG) {
-    R cx[KG], sx[KG];
-    opacity_group<R, KG>(C, chunk, k0, nz, nnu, fin, fc, Vt, coef, ntr, cx, sx);
-  }
+  auto groups = [&](auto fly) {
+    for (int k0 = part * KG; k0 < nz; k0 += nsplit * KG) {
+      R cx[KG], sx[KG];
+      opacity_group<R, KG, decltype(fly)::value>(C, chunk, k0, nz, nnu, fin, fc, Vt, coef, ntr, cx, sx);
+    }
+  };
+  if (opacity_fly<R>(C))
+    groups(std::integral_constant<bool, sizeof(R) == sizeof(float)>{});
+  else
+    groups(std::false_type{});
 }
 
-template <typename R, int KG>
+template <typename R, int KG, bool FLY>
 __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0, int nz, int nnu,
                                               bool fin, int fc, const R* __restrict__ Vt,
                                               const double* __restrict__ coef, int ntr,
                                               R (&cx)[KG], R (&sx)[KG]) {
+  static_assert(!FLY || sizeof(R) == sizeof(float), "B and E on the fly: FP32 form only");
   double chi[KG], et[KG];
 #pragma unroll
   for (int i = 0; i < KG; ++i) {
@@ -251,8 +271,7 @@ __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0
   const int fp = uni(C.fp), tp = sizeof(R) == sizeof(float) ? fp : nnu;
   // FP32 form: B_nu(T) and exp(-h nu / kT) made here in FP32 (n-independent,
   // like the FP32 tables they replace) unless the caller gave the emissivity
-  constexpr bool kOnTheFly = sizeof(R) == sizeof(float);
-  const bool fly = kOnTheFly && !C.bg_eta;
+  constexpr bool fly = FLY;
   const float hnuk = fly ? (float)(kH / kK * ldg(C.nu + fc)) : 0.0f;
   const float gamf = (float)gam;
 #pragma unroll
@@ -403,23 +422,30 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
     const R* __restrict__ Vt = FTab<R>::V(C);
     const double* __restrict__ coef = (const double*)C.coef;
     const int ntr = C.ntr;
-    for (int k0 = 0; k0 < nz; k0 += kFusedDepths) {
-      R gc[kFusedDepths], gs[kFusedDepths], gd[kFusedDepths];
+    auto sweep = [&](auto fly) {
+      for (int k0 = 0; k0 < nz; k0 += kFusedDepths) {
+        R gc[kFusedDepths], gs[kFusedDepths], gd[kFusedDepths];
 #pragma unroll
-      for (int u = 0; u < kFusedDepths; ++u)
-        gd[u] = (R)ldc(dzt + 2 * max(min(k0 + u, nz - 1) - 1, 0));
-      opacity_group<R, kFusedDepths>(C, chunk, k0, nz, nnu, fin, fc, Vt, coef, ntr, gc, gs);
+        for (int u = 0; u < kFusedDepths; ++u)
+          gd[u] = (R)ldc(dzt + 2 * max(min(k0 + u, nz - 1) - 1, 0));
+        opacity_group<R, kFusedDepths, decltype(fly)::value>(C, chunk, k0, nz, nnu, fin, fc, Vt,
+                                                             coef, ntr, gc, gs);
 #pragma unroll
-      for (int u = 0; u < kFusedDepths; ++u) {
-        const int k = k0 + u;
-        if (k == 0) {
-          chi_p = gc[0];
-          S_p = gs[0];
-        } else if (k < nz) {
-          down_step(k, gc[u], gs[u], gd[u]);
+        for (int u = 0; u < kFusedDepths; ++u) {
+          const int k = k0 + u;
+          if (k == 0) {
+            chi_p = gc[0];
+            S_p = gs[0];
+          } else if (k < nz) {
+            down_step(k, gc[u], gs[u], gd[u]);
+          }
         }
       }
-    }
+    };
+    if (opacity_fly<R>(C))
+      sweep(std::integral_constant<bool, sizeof(R) == sizeof(float)>{});
+    else
+      sweep(std::false_type{});
   } else {
     chi_p = ldg(xs + 2 * (size_t)fc);
     S_p = ldg(xs + 2 * (size_t)fc + 1);
