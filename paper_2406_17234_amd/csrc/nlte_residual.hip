@@ -151,11 +151,31 @@ template <> struct FTab<float> {
 // choice, taken once per wave by the callers: as a branch per depth, the
 // table loads of the other side made the compiler wait for every load and
 // store in flight before each exponential.
-template <typename R, int KG, bool FLY>
+//
+// CACHED: the depth-independent inputs of every depth group (gamma = 2 h
+// nu^3 / c^2 and h nu / k of the lane's frequency, and the cross-sections
+// of the chunk's edges, all of them) come from a per-wave copy in LDS made
+// once before the sweep (opacity_cache_fill) instead of a vector load per
+// group and edge, each of which made the wave wait for every load and store
+// it had in flight.  The same values, so the same bits.
+constexpr int kEdgeCache = 6;  // edges a chunk may have to use the LDS copy
+template <typename R>
+struct OpacityCache {
+  static constexpr int kBytes = kWave * 8 + kWave * 4 + kEdgeCache * kWave * (int)sizeof(R);
+  static __device__ __forceinline__ double* gam(char* b) { return reinterpret_cast<double*>(b); }
+  static __device__ __forceinline__ float* hnuk(char* b) {
+    return reinterpret_cast<float*>(b + kWave * 8);
+  }
+  static __device__ __forceinline__ R* al(char* b) {
+    return reinterpret_cast<R*>(b + kWave * 12);
+  }
+};
+
+template <typename R, int KG, bool FLY, bool CACHED>
 __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0, int nz, int nnu,
                                               bool fin, int fc, const R* __restrict__ Vt,
                                               const double* __restrict__ coef, int ntr,
-                                              R (&cx)[KG], R (&sx)[KG]);
+                                              R (&cx)[KG], R (&sx)[KG], char* cache, int lane);
 
 // Whether a column's opacity in precision R is made with FLY (see above).
 template <typename R>
@@ -191,7 +211,8 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
   auto groups = [&](auto fly) {
     for (int k0 = part * KG; k0 < nz; k0 += nsplit * KG) {
       R cx[KG], sx[KG];
-      opacity_group<R, KG, decltype(fly)::value>(C, chunk, k0, nz, nnu, fin, fc, Vt, coef, ntr, cx, sx);
+      opacity_group<R, KG, decltype(fly)::value, false>(C, chunk, k0, nz, nnu, fin, fc, Vt, coef,
+                                                        ntr, cx, sx, nullptr, 0);
     }
   };
   if (opacity_fly<R>(C))
@@ -200,12 +221,13 @@ __global__ __launch_bounds__(256) void k_opacity(const ColDev* __restrict__ cols
     groups(std::false_type{});
 }
 
-template <typename R, int KG, bool FLY>
+template <typename R, int KG, bool FLY, bool CACHED>
 __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0, int nz, int nnu,
                                               bool fin, int fc, const R* __restrict__ Vt,
                                               const double* __restrict__ coef, int ntr,
-                                              R (&cx)[KG], R (&sx)[KG]) {
+                                              R (&cx)[KG], R (&sx)[KG], char* cache, int lane) {
   static_assert(!FLY || sizeof(R) == sizeof(float), "B and E on the fly: FP32 form only");
+  static_assert(!CACHED || FLY, "the LDS copy serves the on-the-fly form");
   double chi[KG], et[KG];
 #pragma unroll
   for (int i = 0; i < KG; ++i) {
@@ -249,9 +271,14 @@ __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0
   const int e0 = ldc(C.ch_eptr + chunk), e1 = ldc(C.ch_eptr + chunk + 1);
   for (int j = e0; j < e1; ++j) {
     const int t = ldc(C.ch_edge + j);
-    const TrDev* T = C.tr + t;
-    const int wlo = ldc(&T->wlo), whi = ldc(&T->whi);
-    const double al = (fc >= wlo && fc < whi) ? (double)ldg(Vt + ldc(&T->voff) + (fc - wlo)) : 0.0;
+    double al;
+    if (CACHED) {
+      al = (double)OpacityCache<R>::al(cache)[(j - e0) * kWave + lane];
+    } else {
+      const TrDev* T = C.tr + t;
+      const int wlo = ldc(&T->wlo), whi = ldc(&T->whi);
+      al = (fc >= wlo && fc < whi) ? (double)ldg(Vt + ldc(&T->voff) + (fc - wlo)) : 0.0;
+    }
     const double* ct = coef + ((size_t)t * nz + k0) * 2;
 #pragma unroll
     for (int i = 0; i < KG; ++i) {
@@ -261,7 +288,7 @@ __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0
     }
   }
   // background, source function
-  const double gam = ldg(C.gam + fc);
+  const double gam = CACHED ? OpacityCache<R>::gam(cache)[lane] : ldg(C.gam + fc);
   const double* cb = coef + ((size_t)ntr * nz + k0) * 2;
   const double* cs = coef + ((size_t)(ntr + 1) * nz + k0) * 2;
   const bool sca = C.has_sca, bf = C.nbf > 0;
@@ -272,7 +299,8 @@ __device__ __forceinline__ void opacity_group(const ColDev& C, int chunk, int k0
   // FP32 form: B_nu(T) and exp(-h nu / kT) made here in FP32 (n-independent,
   // like the FP32 tables they replace) unless the caller gave the emissivity
   constexpr bool fly = FLY;
-  const float hnuk = fly ? (float)(kH / kK * ldg(C.nu + fc)) : 0.0f;
+  const float hnuk = CACHED ? OpacityCache<R>::hnuk(cache)[lane]
+                            : fly ? (float)(kH / kK * ldg(C.nu + fc)) : 0.0f;
   const float gamf = (float)gam;
 #pragma unroll
   for (int i = 0; i < KG; ++i) {
@@ -334,9 +362,30 @@ template <typename R> struct DepthBlock {
   static constexpr int value = sizeof(R) == sizeof(float) ? 4 : 2;
 };
 
+// The LDS copy of OpacityCache for one wave: each lane writes, and later
+// reads, only its own entries, so no barrier is needed.  False (nothing
+// written) if the chunk has more edges than the copy holds.
+template <typename R>
+__device__ __forceinline__ bool opacity_cache_fill(const ColDev& C, int chunk, int fc, int lane,
+                                                   const R* __restrict__ Vt, char* cache) {
+  const int e0 = ldc(C.ch_eptr + chunk), e1 = ldc(C.ch_eptr + chunk + 1);
+  if (e1 - e0 > kEdgeCache) return false;
+  OpacityCache<R>::gam(cache)[lane] = ldg(C.gam + fc);
+  OpacityCache<R>::hnuk(cache)[lane] = (float)(kH / kK * ldg(C.nu + fc));
+  for (int j = e0; j < e1; ++j) {
+    const TrDev* T = C.tr + ldc(C.ch_edge + j);
+    const int wlo = ldc(&T->wlo), whi = ldc(&T->whi);
+    OpacityCache<R>::al(cache)[(j - e0) * kWave + lane] =
+        (fc >= wlo && fc < whi) ? ldg(Vt + ldc(&T->voff) + (fc - wlo)) : (R)0;
+  }
+  return true;
+}
+
+// cache: this wave's LDS for OpacityCache (F-mode launches that make their
+// opacity here), or NULL.
 template <typename R, bool PM, int NMU>
 __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane, double* tile,
-                                            bool fused) {
+                                            bool fused, char* cache) {
   constexpr int KF = StageDepths<R, PM>::value;
   double* tJ = tile;
   double* tX = tile + KF * kWave;
@@ -422,14 +471,14 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
     const R* __restrict__ Vt = FTab<R>::V(C);
     const double* __restrict__ coef = (const double*)C.coef;
     const int ntr = C.ntr;
-    auto sweep = [&](auto fly) {
+    auto sweep = [&](auto fly, auto cached) {
       for (int k0 = 0; k0 < nz; k0 += kFusedDepths) {
         R gc[kFusedDepths], gs[kFusedDepths], gd[kFusedDepths];
 #pragma unroll
         for (int u = 0; u < kFusedDepths; ++u)
           gd[u] = (R)ldc(dzt + 2 * max(min(k0 + u, nz - 1) - 1, 0));
-        opacity_group<R, kFusedDepths, decltype(fly)::value>(C, chunk, k0, nz, nnu, fin, fc, Vt,
-                                                             coef, ntr, gc, gs);
+        opacity_group<R, kFusedDepths, decltype(fly)::value, decltype(cached)::value>(
+            C, chunk, k0, nz, nnu, fin, fc, Vt, coef, ntr, gc, gs, cache, lane);
 #pragma unroll
         for (int u = 0; u < kFusedDepths; ++u) {
           const int k = k0 + u;
@@ -442,10 +491,15 @@ __device__ __forceinline__ void formal_tile(const ColDev& C, int chunk, int lane
         }
       }
     };
-    if (opacity_fly<R>(C))
-      sweep(std::integral_constant<bool, sizeof(R) == sizeof(float)>{});
-    else
-      sweep(std::false_type{});
+    using FlyOk = std::integral_constant<bool, sizeof(R) == sizeof(float)>;
+    if (opacity_fly<R>(C)) {
+      if (FlyOk::value && cache && opacity_cache_fill<R>(C, chunk, fc, lane, Vt, cache))
+        sweep(FlyOk{}, FlyOk{});
+      else
+        sweep(FlyOk{}, std::false_type{});
+    } else {
+      sweep(std::false_type{}, std::false_type{});
+    }
   } else {
     chi_p = ldg(xs + 2 * (size_t)fc);
     S_p = ldg(xs + 2 * (size_t)fc + 1);
@@ -807,8 +861,14 @@ __global__ __launch_bounds__(256) void k_formal(const ColDev* __restrict__ cols,
   if (uni(C.st->cur_prec) != (sizeof(R) == sizeof(float) ? NLTE_FP32_FORM : NLTE_FP64)) return;
   constexpr int KF = StageDepths<R, PM>::value;
   constexpr int NT = PM ? 3 : 1;  // staged outputs: J (and the two derivatives)
-  extern __shared__ double stage[];  // [waves per block][NT * KF * 64]
-  formal_tile<R, PM, NMU>(C, chunk, lane, stage + wave * (NT * KF * kWave), fused != 0);
+  // per wave: the staging tiles, then (F-mode launches that make their
+  // opacity) the OpacityCache copy
+  constexpr bool kCache = !PM && sizeof(R) == sizeof(float);
+  const int per_wave = NT * KF * kWave * 8 + (kCache && fused ? OpacityCache<R>::kBytes : 0);
+  extern __shared__ double stage[];
+  char* mine = reinterpret_cast<char*>(stage) + wave * per_wave;
+  formal_tile<R, PM, NMU>(C, chunk, lane, reinterpret_cast<double*>(mine), fused != 0,
+                          kCache && fused ? mine + NT * KF * kWave * 8 : nullptr);
 }
 
 template <typename R, bool PM>
@@ -816,7 +876,9 @@ static void launch_formal_mu(int nmu, int wpb, hipStream_t s, const ColDev* cols
                              const Tile* tiles, int ntiles, int fused,
                              const Tile* mlist = nullptr, const int* mcount = nullptr) {
   const int blocks = (ntiles + wpb - 1) / wpb;
-  const size_t lds = (size_t)wpb * (PM ? 3 : 1) * StageDepths<R, PM>::value * kWave * sizeof(double);
+  constexpr bool kCache = !PM && sizeof(R) == sizeof(float);
+  const size_t lds = (size_t)wpb * ((PM ? 3 : 1) * StageDepths<R, PM>::value * kWave * sizeof(double) +
+                                    (kCache && fused ? OpacityCache<R>::kBytes : 0));
   switch (nmu) {
 #define NLTE_FORMAL_CASE(M) \
   case M: \
