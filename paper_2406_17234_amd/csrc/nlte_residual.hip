@@ -934,17 +934,20 @@ __device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, in
   for (int i = 0; i < NL; ++i) sl[i] = 0.0;
 #pragma unroll
   for (int i = 0; i < NE; ++i) s1[i] = s2[i] = 0.0;
+  // the rate weights and the edges' cross-sections depend on the frequency
+  // only: scalar loads (ldc), which leave the vector loads of J and V in
+  // flight (as generic loads they waited for every load issued before them)
 #pragma unroll 4
   for (int q = 0; q < nf; ++q) {
     const size_t o = (size_t)q * zp;
     const double j = ldg(J + o);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) sl[i] = fma(cl[i][q] * (double)ldg(vl[i] + (size_t)q * nz), j, sl[i]);
+    for (int i = 0; i < NL; ++i) sl[i] = fma(ldc(cl[i] + q) * (double)ldg(vl[i] + (size_t)q * nz), j, sl[i]);
     if (NE > 0) {
       const double e = (double)ldg(E + o);
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
-        const double x = (ce[i][q] * ae[i][q]) * j;
+        const double x = (ldc(ce[i] + q) * ldc(ae[i] + q)) * j;
         s1[i] += x;
         s2[i] = fma(x, e, s2[i]);
       }
@@ -1076,12 +1079,12 @@ __device__ __forceinline__ void pair_block(const ColDev& C, const PItem& it, int
     const size_t o = (size_t)q * zp;
     const double dx = ldg(DX + o), de = ldg(DE + o);
     const double E = edge ? ldg(EB + o) : 0.0;
-    const double dd = gam[q] * de - dx;
+    const double dd = ldc(gam + q) * de - dx;  // per-frequency operands: scalar loads
     double vt[NT], a[NT];
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
       vt[i] = ldg(ts[i].V + (size_t)q * ts[i].vs);
-      a[i] = cw[i][q] * vt[i] * (pa[i] - pb[i] * E);
+      a[i] = ldc(cw[i] + q) * vt[i] * (pa[i] - pb[i] * E);
     }
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
