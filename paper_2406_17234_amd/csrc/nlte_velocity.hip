@@ -52,23 +52,23 @@ __device__ __forceinline__ void vel_rate_step(const ColDev& C, int chunk, int k,
                                               int r0, const R (&I)[NMU], const double (&wm2)[NMU],
                                               bool first) {
   const int nz = C.nz, nray = C.nray, nnu = C.nnu;
-  const int l0 = uni(C.ch_lptr[chunk]), l1 = uni(C.ch_lptr[chunk + 1]);
+  const int l0 = ldc(C.ch_lptr + chunk), l1 = ldc(C.ch_lptr + chunk + 1);
   double* row = C.RJ + (size_t)k * C.nrseg * 2;
   for (int j = l0; j < l1; ++j) {
-    const int t = uni(C.ch_line[j]);
-    const TrDev& T = C.tr[t];
-    const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
+    const int t = ldc(C.ch_line + j);
+    const TrDev* T = C.tr + t;
+    const int wlo = ldc(&T->wlo), wl = ldc(&T->whi) - wlo;
     const int q = fc - wlo;
     const bool in = f < nnu && q >= 0 && q < wl;
     const size_t rstep = (size_t)nz * wl;
-    const double* vr = C.VR + (size_t)nray * uni(T.voff) + (size_t)r0 * rstep + (size_t)k * wl + (in ? q : 0);
+    const double* vr = C.VR + (size_t)nray * ldc(&T->voff) + (size_t)r0 * rstep + (size_t)k * wl + (in ? q : 0);
     double u = 0.0;
 #pragma unroll
     for (int m = 0; m < NMU; ++m) u = fmar(wm2[m] * ldg(vr + m * rstep), (double)I[m], u);
-    const double x = in ? ldg(C.cw + uni(T.cwoff) + q) * u : 0.0;
+    const double x = in ? ldg(C.cw + ldc(&T->cwoff) + q) * u : 0.0;
     const double tot = wave_sum0(x);
     if ((threadIdx.x & 63) == 0) {
-      double* ent = row + 2 * (uni(T.sfirst) + chunk - wlo / kWave);
+      double* ent = row + 2 * (ldc(&T->sfirst) + chunk - wlo / kWave);
       if (first) {
         stg(ent + 1, tot);
       } else {
@@ -85,12 +85,12 @@ __device__ __forceinline__ void vel_base(const ColDev& C, int chunk, int k, int 
   const int nz = C.nz, ntr = C.ntr;
   const double* __restrict__ coef = (const double*)C.coef;
   double A1 = 0.0, A2 = 0.0;
-  const int e0 = uni(C.ch_eptr[chunk]), e1 = uni(C.ch_eptr[chunk + 1]);
+  const int e0 = ldc(C.ch_eptr + chunk), e1 = ldc(C.ch_eptr + chunk + 1);
   for (int j = e0; j < e1; ++j) {
-    const int t = uni(C.ch_edge[j]);
-    const TrDev& T = C.tr[t];
-    const int wlo = uni(T.wlo), whi = uni(T.whi);
-    const double al = (fc >= wlo && fc < whi) ? ldg(C.V + uni(T.voff) + (fc - wlo)) : 0.0;
+    const int t = ldc(C.ch_edge + j);
+    const TrDev* T = C.tr + t;
+    const int wlo = ldc(&T->wlo), whi = ldc(&T->whi);
+    const double al = (fc >= wlo && fc < whi) ? ldg(C.V + ldc(&T->voff) + (fc - wlo)) : 0.0;
     const double* ct = coef + ((size_t)t * nz + k) * 2;
     A1 = fmar(al, ldc(ct), A1);
     A2 = fmar(al, ldc(ct + 1), A2);
@@ -114,17 +114,17 @@ __device__ __forceinline__ void vel_rays(const ColDev& C, int chunk, int k, int 
   double cl[NMU], el[NMU];
 #pragma unroll
   for (int m = 0; m < NMU; ++m) cl[m] = el[m] = 0.0;
-  const int l0 = uni(C.ch_lptr[chunk]), l1 = uni(C.ch_lptr[chunk + 1]);
+  const int l0 = ldc(C.ch_lptr + chunk), l1 = ldc(C.ch_lptr + chunk + 1);
   for (int j = l0; j < l1; ++j) {
-    const int t = uni(C.ch_line[j]);
-    const TrDev& T = C.tr[t];
-    const int wlo = uni(T.wlo), wl = uni(T.whi) - wlo;
+    const int t = ldc(C.ch_line + j);
+    const TrDev* T = C.tr + t;
+    const int wlo = ldc(&T->wlo), wl = ldc(&T->whi) - wlo;
     const int q = fc - wlo;
     const bool in = q >= 0 && q < wl;
     const double* ct = coef + ((size_t)t * nz + k) * 2;
     const double c0 = ldc(ct), c1 = ldc(ct + 1);
     const size_t rstep = (size_t)nz * wl;
-    const double* vr = C.VR + (size_t)nray * uni(T.voff) + (size_t)r0 * rstep + (size_t)k * wl + (in ? q : 0);
+    const double* vr = C.VR + (size_t)nray * ldc(&T->voff) + (size_t)r0 * rstep + (size_t)k * wl + (in ? q : 0);
     double v[NMU];
 #pragma unroll
     for (int m = 0; m < NMU; ++m) v[m] = ldg(vr + m * rstep);
