@@ -85,31 +85,38 @@ __device__ __forceinline__ void tan_opacity(const ColDev& C, int chunk, int k, i
   const double* nk = C.n + (size_t)k * L;
   const double* vk = C.eval_n + (size_t)k * L;
   double chi = 0.0, et = 0.0, chid = 0.0, etd = 0.0;
-  const int l0 = C.ch_lptr[chunk], l1 = C.ch_lptr[chunk + 1];
+  // the chunk's transition lists, their windows and the depth's level
+  // populations are the same for every lane: scalar loads (ldc), which do
+  // not wait for the wave's vector loads and stores in flight
+  const int l0 = ldc(C.ch_lptr + chunk), l1 = ldc(C.ch_lptr + chunk + 1);
   for (int j = l0; j < l1; ++j) {
-    const TrDev& T = C.tr[C.ch_line[j]];
-    const int wl = T.whi - T.wlo, q = f - T.wlo;
+    const TrDev* T = C.tr + ldc(C.ch_line + j);
+    const int wlo = ldc(&T->wlo), wl = ldc(&T->whi) - wlo, q = f - wlo;
+    const double g = ldc(&T->g), nu = ldc(nk + ldc(&T->up)), vu = ldc(vk + ldc(&T->up));
+    const double nl = ldc(nk + ldc(&T->lo)), vl = ldc(vk + ldc(&T->lo));
     if (q < 0 || q >= wl) continue;
-    const double V = C.V[T.voff + (size_t)k * wl + q];
-    const double c1 = T.g * nk[T.up], c1d = T.g * vk[T.up];
-    chi += V * (nk[T.lo] - c1);
+    const double V = C.V[ldc(&T->voff) + (size_t)k * wl + q];
+    const double c1 = g * nu, c1d = g * vu;
+    chi += V * (nl - c1);
     et += V * c1;
-    chid += V * (vk[T.lo] - c1d);
+    chid += V * (vl - c1d);
     etd += V * c1d;
   }
   double A1 = 0.0, A2 = 0.0, A1d = 0.0, A2d = 0.0;
-  const int e0 = C.ch_eptr[chunk], e1 = C.ch_eptr[chunk + 1];
+  const int e0 = ldc(C.ch_eptr + chunk), e1 = ldc(C.ch_eptr + chunk + 1);
   for (int j = e0; j < e1; ++j) {
-    const int t = C.ch_edge[j];
-    const TrDev& T = C.tr[t];
-    const int q = f - T.wlo;
-    if (q < 0 || q >= T.whi - T.wlo) continue;
-    const double al = C.V[T.voff + q];
-    const double rb = C.rho_bf[(size_t)k * nbf + (t - nline)];
-    A1 += al * nk[T.lo];
-    A2 += al * rb * nk[L - 1];
-    A1d += al * vk[T.lo];
-    A2d += al * rb * vk[L - 1];
+    const int t = ldc(C.ch_edge + j);
+    const TrDev* T = C.tr + t;
+    const int wlo = ldc(&T->wlo), q = f - wlo;
+    const double rb = ldc(C.rho_bf + (size_t)k * nbf + (t - nline));
+    const double nl = ldc(nk + ldc(&T->lo)), vl = ldc(vk + ldc(&T->lo));
+    const double nc = ldc(nk + L - 1), vc = ldc(vk + L - 1);
+    if (q < 0 || q >= ldc(&T->whi) - wlo) continue;
+    const double al = C.V[ldc(&T->voff) + q];
+    A1 += al * nl;
+    A2 += al * rb * nc;
+    A1d += al * vl;
+    A2d += al * rb * vc;
   }
   const size_t kf = (size_t)k * nnu + f;
   const double E = nbf ? C.Ebf[kf] : 0.0;
@@ -235,18 +242,20 @@ __device__ __forceinline__ void tan_base_vel(const ColDev& C, int chunk, int k, 
   const double* nk = C.n + (size_t)k * L;
   const double* vk = C.eval_n + (size_t)k * L;
   double A1 = 0.0, A2 = 0.0, A1d = 0.0, A2d = 0.0;
-  const int e0 = C.ch_eptr[chunk], e1 = C.ch_eptr[chunk + 1];
+  const int e0 = ldc(C.ch_eptr + chunk), e1 = ldc(C.ch_eptr + chunk + 1);
   for (int j = e0; j < e1; ++j) {
-    const int t = C.ch_edge[j];
-    const TrDev& T = C.tr[t];
-    const int q = f - T.wlo;
-    if (q < 0 || q >= T.whi - T.wlo) continue;
-    const double al = C.V[T.voff + q];
-    const double rb = C.rho_bf[(size_t)k * nbf + (t - nline)];
-    A1 += al * nk[T.lo];
-    A2 += al * rb * nk[L - 1];
-    A1d += al * vk[T.lo];
-    A2d += al * rb * vk[L - 1];
+    const int t = ldc(C.ch_edge + j);
+    const TrDev* T = C.tr + t;
+    const int wlo = ldc(&T->wlo), q = f - wlo;
+    const double rb = ldc(C.rho_bf + (size_t)k * nbf + (t - nline));
+    const double nl = ldc(nk + ldc(&T->lo)), vl = ldc(vk + ldc(&T->lo));
+    const double nc = ldc(nk + L - 1), vc = ldc(vk + L - 1);
+    if (q < 0 || q >= ldc(&T->whi) - wlo) continue;
+    const double al = C.V[ldc(&T->voff) + q];
+    A1 += al * nl;
+    A2 += al * rb * nc;
+    A1d += al * vl;
+    A2d += al * rb * vc;
   }
   const size_t kf = (size_t)k * nnu + f;
   const double E = nbf ? C.Ebf[kf] : 0.0;
@@ -274,14 +283,17 @@ __device__ __forceinline__ void tan_rays_vel(const ColDev& C, int chunk, int k, 
     etd[m] = 0.0;
   }
   const int nz = C.nz;
-  const int l0 = C.ch_lptr[chunk], l1 = C.ch_lptr[chunk + 1];
+  const int l0 = ldc(C.ch_lptr + chunk), l1 = ldc(C.ch_lptr + chunk + 1);
   for (int j = l0; j < l1; ++j) {
-    const TrDev& T = C.tr[C.ch_line[j]];
-    const int wl = T.whi - T.wlo, q = f - T.wlo;
+    const TrDev* T = C.tr + ldc(C.ch_line + j);
+    const int wlo = ldc(&T->wlo), wl = ldc(&T->whi) - wlo, q = f - wlo;
+    const double g = ldc(&T->g), nu = ldc(nk + ldc(&T->up)), vu = ldc(vk + ldc(&T->up));
+    const double nl = ldc(nk + ldc(&T->lo)), vl = ldc(vk + ldc(&T->lo));
+    const size_t voff = ldc(&T->voff);
     if (q < 0 || q >= wl) continue;
-    const double c1 = T.g * nk[T.up], c1d = T.g * vk[T.up];
-    const double c0 = nk[T.lo] - c1, c0d = vk[T.lo] - c1d;
-    const double* vr = C.VR + (size_t)C.nray * T.voff + ((size_t)r0 * nz + k) * wl + q;
+    const double c1 = g * nu, c1d = g * vu;
+    const double c0 = nl - c1, c0d = vl - c1d;
+    const double* vr = C.VR + (size_t)C.nray * voff + ((size_t)r0 * nz + k) * wl + q;
 #pragma unroll
     for (int m = 0; m < NMU; ++m) {
       const double V = vr[(size_t)m * nz * wl];
