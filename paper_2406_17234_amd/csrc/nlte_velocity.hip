@@ -399,7 +399,7 @@ __device__ void pair_vel(const ColDev& C, const PItem& it, int k) {
   for (int q = 0; q < nf; ++q) {
     const size_t oq = (size_t)q * zp;
     const double E = edge ? ldg(EB + oq) : 0.0;
-    const double gam = ldg(C.gam + f0 + q);
+    const double gam = ldc(C.gam + f0 + q);  // per-frequency: scalar load
     for (int r = 0; r < nray; ++r) {
       const double w = C.wm2[r < nmu ? r : r - nmu];
       const double dx = ldg(DX + r * rs + oq), de = ldg(DE + r * rs + oq);
@@ -407,7 +407,7 @@ __device__ void pair_vel(const ColDev& C, const PItem& it, int k) {
       double a[kPairBlk];
 #pragma unroll
       for (int i = 0; i < kPairBlk; ++i)
-        a[i] = i < nt ? w * cw[i][q] * ldg(Vt[i] + r * rt[i] + (size_t)q * ft[i]) * (pa[i] - pb[i] * E) : 0.0;
+        a[i] = i < nt ? w * ldc(cw[i] + q) * ldg(Vt[i] + r * rt[i] + (size_t)q * ft[i]) * (pa[i] - pb[i] * E) : 0.0;
 #pragma unroll
       for (int j = 0; j < kPairBlk; ++j) {
         if (j >= nu) break;
@@ -500,7 +500,7 @@ __device__ void pair_vel_one_line(const ColDev& C, const PItem& it, int k, int l
   for (int q = 0; q < nf; ++q) {
     const size_t oq = (size_t)q * zp;
     const double E = edge ? ldg(EB + oq) : 0.0;
-    const double gam = ldg(C.gam + f0 + q);
+    const double gam = ldc(C.gam + f0 + q);  // per-frequency: scalar load
     double d1 = 0.0, d2 = 0.0, xt1 = 0.0, xt2 = 0.0, xu1 = 0.0, xu2 = 0.0, z1 = 0.0, z2 = 0.0;
     for (int r = 0; r < nray; ++r) {
       const double w = C.wm2[r < nmu ? r : r - nmu];
@@ -520,13 +520,13 @@ __device__ void pair_vel_one_line(const ColDev& C, const PItem& it, int k, int l
 #pragma unroll
     for (int i = 0; i < kPairBlk; ++i) {
       if (i >= nt) break;
-      const double a0 = cw[i][q] * (pa[i] - pb[i] * E);
-      const double at = i == lt ? 1.0 : ldg(At[i] + q);
+      const double a0 = ldc(cw[i] + q) * (pa[i] - pb[i] * E);
+      const double at = i == lt ? 1.0 : ldc(At[i] + q);
 #pragma unroll
       for (int j = 0; j < kPairBlk; ++j) {
         if (j >= nu) break;
         const double gu = g0u[j] + gEu[j] * E;
-        const double au = j == lu ? 1.0 : ldg(Au[j] + q);
+        const double au = j == lu ? 1.0 : ldc(Au[j] + q);
         double s1, s2;
         if (i == lt && j == lu) {
           s1 = z1;
