@@ -44,13 +44,13 @@ OPS_PER_DP = 10.0 + 0.5 * TRANS_SLOTS + 0.5 * TRANS_SLOTS
 # a plain copy kernel; valid only for the kernel source they were taken on
 # (hash of its files).
 TRAFFIC = {
-    "batch6": {"source": "790595d1e125ea33", "bytes_per_launch": 5.5639e+09,
-               "read": 5.6184e+11 / 192, "written": 5.0642e+11 / 192},
+    "batch6": {"source": "af133efebb9b6596", "bytes_per_launch": 5.2233e+09,
+               "read": 4.8968e+11 / 192, "written": 5.1318e+11 / 192},
 }
 # the same for the F-mode velocity formal solution of the 512-column velocity
 # batch (mean over the profiled solve's 140 launches)
-TRAFFIC_VEL = {"source": "e5aee45448d71ad2", "columns": 512, "bytes_per_launch": 6.3607e+09,
-               "read": 5.3496e+09, "written": 1.0111e+09}
+TRAFFIC_VEL = {"source": "9f5debcc6ac80876", "columns": 512, "bytes_per_launch": 6.4376e+09,
+               "read": 5.4273e+09, "written": 1.0103e+09}
 KERNEL_SOURCES = ["paper_2406_17234_amd/csrc/nlte_residual.hip",
                   "paper_2406_17234_amd/csrc/nlte_kernels.h",
                   "paper_2406_17234_amd/csrc/nlte_internal.h"]
