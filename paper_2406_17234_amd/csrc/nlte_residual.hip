@@ -905,9 +905,11 @@ static void launch_formal_mu(int nmu, int wpb, hipStream_t s, const ColDev* cols
 // TB: line-table precision (float for FP32-form evaluations).  J stays FP64
 // here: in the FP32 form a J rounded to FP32 before these sums sets a noise
 // floor on F that doubled the share of columns needing the FP64 fallback.
-template <typename TB, int NL, int NE>
+template <typename TB, int NL, int NE, bool SC>
 __device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, int k,
                                             const TB* __restrict__ VTt, const TB* __restrict__ EbfTt) {
+  // wave-uniform per-frequency data: scalar loads (SC) or vector loads
+  auto rd = [](const double* p) { return SC ? ldc(p) : ldg(p); };
   const int nz = C.nz, zp = C.zp, f0 = it.f0, nf = it.f1 - it.f0;
   const TB* vl[NL > 0 ? NL : 1];      // line V at f0, this lane's depth (rows of nz)
   const double* cl[NL > 0 ? NL : 1];  // line rate weights at f0
@@ -935,19 +937,21 @@ __device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, in
 #pragma unroll
   for (int i = 0; i < NE; ++i) s1[i] = s2[i] = 0.0;
   // the rate weights and the edges' cross-sections depend on the frequency
-  // only: scalar loads (ldc), which leave the vector loads of J and V in
-  // flight (as generic loads they waited for every load issued before them)
+  // only.  With SC they are scalar loads (ldc), which leave the vector loads
+  // of J and V in flight (generic loads wait for every load issued before
+  // them): faster where many waves share a CU; a launch of a few hundred
+  // waves (one deep column) is faster with vector loads, which it keeps.
 #pragma unroll 4
   for (int q = 0; q < nf; ++q) {
     const size_t o = (size_t)q * zp;
     const double j = ldg(J + o);
 #pragma unroll
-    for (int i = 0; i < NL; ++i) sl[i] = fma(ldc(cl[i] + q) * (double)ldg(vl[i] + (size_t)q * nz), j, sl[i]);
+    for (int i = 0; i < NL; ++i) sl[i] = fma(rd(cl[i] + q) * (double)ldg(vl[i] + (size_t)q * nz), j, sl[i]);
     if (NE > 0) {
       const double e = (double)ldg(E + o);
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
-        const double x = (ldc(ce[i] + q) * ldc(ae[i] + q)) * j;
+        const double x = (rd(ce[i] + q) * rd(ae[i] + q)) * j;
         s1[i] += x;
         s2[i] = fma(x, e, s2[i]);
       }
@@ -966,12 +970,12 @@ __device__ __forceinline__ void rates_block(const ColDev& C, const RItem& it, in
   }
 }
 
-template <typename TB>
+template <typename TB, bool SC>
 __device__ __forceinline__ void rates_shape(const ColDev& C, const RItem& it, int k,
                                             const TB* __restrict__ VTt, const TB* __restrict__ EbfTt) {
   switch (it.nl * 8 + it.ne) {
 #define RB(L, E) \
-  case L * 8 + E: rates_block<TB, L, E>(C, it, k, VTt, EbfTt); break;
+  case L * 8 + E: rates_block<TB, L, E, SC>(C, it, k, VTt, EbfTt); break;
     RB(0, 1) RB(0, 2) RB(0, 3) RB(0, 4)
     RB(1, 0) RB(1, 1) RB(1, 2) RB(1, 3) RB(1, 4)
     RB(2, 0) RB(2, 1) RB(2, 2) RB(2, 3) RB(2, 4)
@@ -987,6 +991,7 @@ __device__ __forceinline__ void rates_shape(const ColDev& C, const RItem& it, in
 // before its first table loads.  The tables follow the evaluation's
 // precision, so that an FP32-form column after its FP64 fallback evaluates
 // the same F as an FP64 column.
+template <bool SC>
 __device__ __forceinline__ void rates_item(const ColDev& C, int b, int k0, int only_mode) {
   const int mode = ldc(&C.st->mode), prec = ldc(&C.st->cur_prec);
   const RItem it = ldc_rec(C.ritem + b);
@@ -996,9 +1001,9 @@ __device__ __forceinline__ void rates_item(const ColDev& C, int b, int k0, int o
   const int k = k0 + threadIdx.x;
   if (k >= C.nz) return;
   if (prec == NLTE_FP32_FORM)
-    rates_shape<float>(C, it, k, C.VTf, C.EbfTf);
+    rates_shape<float, SC>(C, it, k, C.VTf, C.EbfTf);
   else
-    rates_shape<double>(C, it, k, C.VT, C.EbfT);
+    rates_shape<double, SC>(C, it, k, C.VT, C.EbfT);
 }
 
 // ---------------------------------------------------------------------------
@@ -1132,6 +1137,7 @@ __device__ __forceinline__ void pair_item(const ColDev& C, int p, int k0) {
 
 // Rate integrals of a step: one item per (column, rate block of a piece, 64
 // depths), lane per depth; only_mode >= 0: the columns in that mode only.
+template <bool SC>
 __global__ __launch_bounds__(64) void k_depthwork(const ColDev* __restrict__ cols,
                                                   const int4* __restrict__ work, int nwork,
                                                   int only_mode) {
@@ -1141,7 +1147,21 @@ __global__ __launch_bounds__(64) void k_depthwork(const ColDev* __restrict__ col
   if (w >= nwork) return;
   const int4 it = work[w];
   const int col = uni(it.x), idx = uni(it.y), k0 = uni(it.z);
-  rates_item(cols[col], idx, k0, only_mode);
+  rates_item<SC>(cols[col], idx, k0, only_mode);
+}
+
+// Launches of at least this many rate items (8 waves per CU) read the
+// per-frequency rate data with scalar loads; smaller ones with vector loads.
+// Measured on the 4096-column batch and on one 256-depth column: scalar
+// loads take the batch's F-only residual from 4.76 to 4.55 ms and slow the
+// single column's from 0.441 to 0.463 ms (the same F either way).
+constexpr int kRateScalarMin = 2048;
+
+static void launch_depthwork(const BatchWork& bw, size_t lds, hipStream_t s, int only_mode) {
+  if (bw.nrate0 >= kRateScalarMin)
+    k_depthwork<true><<<bw.nrate0, 64, lds, s>>>(bw.cols, bw.rate_work, bw.nrate0, only_mode);
+  else
+    k_depthwork<false><<<bw.nrate0, 64, lds, s>>>(bw.cols, bw.rate_work, bw.nrate0, only_mode);
 }
 
 // Preconditioner pair sums of the columns in Newton mode: one item per
@@ -1488,12 +1508,12 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
     chk(hipStreamWaitEvent(s, SS->join[1], 0));
     if (ev) chk(hipEventRecord(ev[2], s));
     if (bw.nrate0 > 0)
-      k_depthwork<<<bw.nrate0, 64, kDepthworkLds, s>>>(bw.cols, bw.rate_work, bw.nrate0, kModeF);
+      launch_depthwork(bw, kDepthworkLds, s, kModeF);
     if (bw.any_newton) {
       chk(hipEventRecord(SS->join[2], SS->st[2]));
       chk(hipStreamWaitEvent(sNewton, SS->join[2], 0));
       if (bw.nrate0 > 0)
-        k_depthwork<<<bw.nrate0, 64, 0, sNewton>>>(bw.cols, bw.rate_work, bw.nrate0, kModeNewton);
+        launch_depthwork(bw, 0, sNewton, kModeNewton);
       if (pairs)
         k_pairsum<<<bw.nrate - bw.nrate0, 64, 0, sNewton>>>(bw.cols, bw.rate_work + bw.nrate0,
                                                              bw.nrate - bw.nrate0);
@@ -1507,7 +1527,7 @@ hipError_t launch_residual(const BatchWork& bw, hipStream_t s, hipEvent_t* ev) {
   } else {
     if (ev) chk(hipEventRecord(ev[2], s));
     if (bw.nrate0 > 0)
-      k_depthwork<<<bw.nrate0, 64, kDepthworkLds, s>>>(bw.cols, bw.rate_work, bw.nrate0, -1);
+      launch_depthwork(bw, kDepthworkLds, s, -1);
     if (pairs)
       k_pairsum<<<bw.nrate - bw.nrate0, 64, 0, s>>>(bw.cols, bw.rate_work + bw.nrate0,
                                                      bw.nrate - bw.nrate0);
