@@ -44,8 +44,8 @@ OPS_PER_DP = 10.0 + 0.5 * TRANS_SLOTS + 0.5 * TRANS_SLOTS
 # a plain copy kernel; valid only for the kernel source they were taken on
 # (hash of its files).
 TRAFFIC = {
-    "batch6": {"source": "af133efebb9b6596", "bytes_per_launch": 5.2233e+09,
-               "read": 4.8968e+11 / 192, "written": 5.1318e+11 / 192},
+    "batch6": {"source": "25d629d1e1f31708", "bytes_per_launch": 5.2228e+09,
+               "read": 4.8958e+11 / 192, "written": 5.1320e+11 / 192},
 }
 # the same for the F-mode velocity formal solution of the 512-column velocity
 # batch (mean over the profiled solve's 140 launches)
